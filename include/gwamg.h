@@ -1,0 +1,284 @@
+/*
+ * gwamg.h -- C ABI of the MI355X (gfx950) groundwater AMG-Krylov library.
+ *
+ * Method: Sbai & Larabi, "On Solving Groundwater Flow and Transport Models
+ * with Algebraic Multigrid Preconditioning".  A steady confined flow solve
+ * (finite-difference 7-point M-matrix, CG preconditioned by smoothed-
+ * aggregation AMG), then the steady forward travel-time equation on the
+ * resulting Darcy velocities (Eq. 1, BiCGSTAB preconditioned by AMG), whose
+ * matrix serves several right-hand sides of the dual delineation.
+ *
+ * Conventions for every entry point
+ *   - Pointers marked [device] are HIP device pointers on the current device;
+ *     [host] pointers are ordinary host memory.  The caller owns every buffer
+ *     it passes and keeps it alive until the call returns (queue requests:
+ *     until queue_poll reports the ticket finished).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work of the call is ordered on it.  Calls that must read back sizes or
+ *     convergence flags block until their work is done; the others only
+ *     enqueue.
+ *   - Cell (i,j,k) of an nx x ny x nz grid has flat index i + nx*(j + ny*k).
+ *   - Every function returns a status (GW_OK = 0) and never throws; on error
+ *     gw_last_error() returns a thread-local message.
+ *   - Calls on one amg_hierarchy must not overlap (hierarchies hold their
+ *     solve workspace).  The queue functions are thread safe.
+ */
+#ifndef GWAMG_H
+#define GWAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define GW_OK 0
+#define GW_NOT_CONVERGED 1 /* x holds the last iterate, info is filled      */
+#define GW_BREAKDOWN 2     /* a Krylov scalar became zero or non-finite      */
+#define GW_PENDING 3       /* queue_poll: the request is not finished yet    */
+#define GW_EINVAL (-1)     /* bad size, null pointer, K <= 0 or NaN, unsorted
+                              or non-square CSR, missing/non-positive diagonal */
+#define GW_ENOMEM (-2)     /* device allocation failed / request > budget    */
+#define GW_SINGULAR (-3)   /* zero pivot in the coarsest-level LU            */
+#define GW_EDEVICE (-4)    /* HIP runtime error                              */
+#define GW_EAGAIN (-5)     /* queue full                                     */
+
+enum { GW_SMOOTHER_JACOBI = 0, GW_SMOOTHER_SPAI0 = 1, GW_SMOOTHER_NONE = 2 };
+enum { GW_PRECISION_FP64 = 0, GW_PRECISION_MIXED = 1 };
+
+/* ---- plain data --------------------------------------------------------- */
+
+/* Uniform grid; nz = 1 is a 2D slab of thickness dz. */
+typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } gw_grid;
+
+/* Square CSR matrix, sorted unique columns, diagonal stored. [device] */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t *rowptr; /* n+1 */
+    const int32_t *col;    /* nnz */
+    const double *val;     /* nnz */
+} gw_csr;
+
+/* Point sink in cell (ix,iy,iz): q > 0 pumps q m^3/s out of the aquifer. */
+typedef struct { int32_t ix, iy, iz; double q; } gw_well;
+
+/* Fixed heads on the x = 0 and x = L faces; every other face is no-flow. */
+typedef struct { double h_west, h_east; } gw_bc;
+
+/* Source window [j0,j1) x [k0,k1) on the x = 0 face: its inflow indicator is
+ * the second travel-time right-hand side. */
+typedef struct { int32_t j0, j1, k0, k1; } gw_zone;
+
+/* Smoothed-aggregation parameters.
+ *   eps_strong  strength threshold eps_0 (halved every level)       [0.08]
+ *   smoother    GW_SMOOTHER_*; NONE disables the preconditioner      [SPAI0]
+ *   omega       damping of the Jacobi smoother                       [2/3]
+ *   npre/npost  smoothing sweeps before/after the coarse correction  [2/2]
+ *   n_coarse    a level of at most this many rows is the coarsest    [500]
+ *   max_levels  level cap                                            [20]
+ *   precision   FP64, or MIXED = FP32 hierarchy inside FP64 Krylov   [FP64]
+ *   seed        seed of the MIS-2 hash priorities                    */
+typedef struct {
+    double eps_strong;
+    int32_t smoother;
+    double omega;
+    int32_t npre, npost;
+    int32_t n_coarse, max_levels;
+    int32_t precision;
+    uint64_t seed;
+} amg_params;
+
+/* rtol: stop when ||r||_2 <= rtol ||b||_2.  check_every: iterations between
+ * two reads of the device convergence flag.  flexible: for amg_solve_pcg,
+ * 1 = flexible CG (Polak-Ribiere beta), 0 = standard PCG, -1 = flexible
+ * exactly when the hierarchy is MIXED. */
+typedef struct {
+    double rtol;
+    int32_t maxiter;
+    int32_t check_every;
+    int32_t flexible;
+} amg_solve_params;
+
+typedef struct {
+    int32_t iters;        /* Krylov iterations over all restarts          */
+    int32_t status;       /* GW_OK, GW_NOT_CONVERGED or GW_BREAKDOWN       */
+    int32_t restarts;     /* restarts after a true-residual check failed   */
+    double rel_res;       /* recursive residual / ||b|| at exit            */
+    double rel_res_true;  /* ||b - A x|| / ||b|| in FP64 at exit           */
+    double setup_ms;      /* hierarchy setup time (tt_solve, queue)        */
+    double solve_ms;      /* wall time of this solve                       */
+} amg_solve_info;
+
+typedef struct {
+    int32_t n;            /* rows of A_l                                   */
+    int64_t nnz;          /* nonzeros of A_l                               */
+    int32_t nc;           /* aggregates (rows of A_{l+1}), 0 on coarsest   */
+    int64_t nnz_p;        /* nonzeros of P_l                               */
+    int64_t nnz_s;        /* edges of the strength graph                   */
+    int32_t mis_rounds;   /* MIS-2 rounds                                  */
+    double omega_p;       /* prolongator smoothing weight                  */
+    size_t bytes;         /* device bytes held for this level              */
+} amg_level_info;
+
+typedef struct amg_hierarchy amg_hierarchy;
+typedef struct gw_queue gw_queue;
+
+/* ---- library ------------------------------------------------------------ */
+
+const char *gw_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char *gw_last_error(void);
+/* Release cached device memory held by the library's pool. */
+int gw_trim(void);
+
+/* ---- flow assembly (Benchmarking Examples: 7-point finite differences
+ *      giving an M-matrix) -------------------------------------------------- */
+
+/* Number of nonzeros of the flow matrix of `grid`:
+ * 7n - 2(nx ny + ny nz + nx nz). */
+int64_t fv_nnz(const gw_grid *grid);
+
+/* Assemble A h = b.  Face transmissibility T = (A_f/d) 2 K_a K_b/(K_a+K_b);
+ * fixed-head faces add T_b = (A_f/d) 2 K to the diagonal and T_b h to b;
+ * wells subtract q from b.  K [device] n; wells [host] nwells (<= 64);
+ * rowptr [device] n+1, col/val [device] fv_nnz(grid), b [device] n.
+ * EINVAL for a K that is not positive and finite. */
+int fv_assemble(const gw_grid *grid, const double *K, const gw_bc *bc, const gw_well *wells,
+                int32_t nwells, int32_t *rowptr, int32_t *col, double *val, double *b, void *stream);
+
+/* Darcy face fluxes, positive along +x/+y/+z (the velocity of Eq. 1 times
+ * the face area).  qx [device] (nx+1) ny nz, face i of row (j,k) at
+ * i + (nx+1)(j + ny k); qy [device] nx (ny+1) nz; qz [device] nx ny (nz+1).
+ * Faces on no-flow boundaries are 0. */
+int darcy_flux(const gw_grid *grid, const double *K, const gw_bc *bc, const double *h,
+               double *qx, double *qy, double *qz, void *stream);
+
+/* ---- AMG (Introduction: setup phase, then V-cycle of sparse products with
+ *      a direct solve on the coarsest level) ------------------------------- */
+
+/* Build the hierarchy of A [device].  The hierarchy copies what it needs; A
+ * may be freed when the call returns.  Blocks for the level sizes.
+ * EINVAL: invalid CSR, or coarsening stalled above 2048 rows;
+ * SINGULAR: zero pivot in the coarsest LU. */
+int amg_setup(const gw_csr *A, const amg_params *params, amg_hierarchy **H, void *stream);
+
+/* Apply one V-cycle z = V(r) (the preconditioner).  r, z [device] n. */
+int amg_vcycle(amg_hierarchy *H, const double *r, double *z, void *stream);
+
+/* y = A x with the level-0 operator of H.  x, y [device] n. */
+int amg_spmv(amg_hierarchy *H, const double *x, double *y, void *stream);
+
+/* AMG-preconditioned CG (flow, symmetric), x0 = 0.  b, x [device] n. */
+int amg_solve_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
+                  amg_solve_info *info, void *stream);
+
+/* AMG right-preconditioned BiCGSTAB (nonsymmetric), x0 = 0. */
+int amg_solve_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
+                       amg_solve_info *info, void *stream);
+
+/* Per-level statistics; `out` [host] holds max_levels entries. */
+int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_levels,
+                       int32_t *nlevels, size_t *bytes);
+
+/* Copy level l into caller buffers [device] sized from amg_hierarchy_info:
+ * A_l (rowptr n+1, col/val nnz), the aggregate map agg (n, -1 = removed),
+ * the smoother diagonal M (n), and P_l (rowptr n+1, col/val nnz_p).  Any
+ * pointer may be NULL.  On the coarsest level agg, M and P are not written. */
+int amg_level_export(const amg_hierarchy *H, int32_t level, int32_t *a_rowptr, int32_t *a_col,
+                     double *a_val, int32_t *agg, double *M, int32_t *p_rowptr, int32_t *p_col,
+                     double *p_val, void *stream);
+
+/* Coarsest level: LU factors (row-major nd x nd, unit lower L below the
+ * diagonal), pivot rows (LAPACK getrf order) and the inverse used by the
+ * V-cycle.  [device]; any may be NULL. */
+int amg_coarse_export(const amg_hierarchy *H, double *lu, int32_t *piv, double *inv, void *stream);
+
+void amg_free(amg_hierarchy *H);
+
+/* ---- travel time (Eq. 1) ------------------------------------------------ */
+
+/* Upper bound of the travel-time matrix nonzeros (= fv_nnz). */
+int64_t tt_nnz_bound(const gw_grid *grid);
+
+/* Assemble the first-order upwind matrix of v.grad(tau) = phi:
+ * A_ii = sum of |q| over the inflow faces of cell i, A_ij = -|q| for each
+ * interior inflow face from neighbour j; b_tau = phi V_i; b_c = |q| on the
+ * x = 0 inflow face of cells inside `zone` (NULL = whole face).  Rows with no
+ * inflow become identity rows with zero right-hand sides.  rowptr/col/val
+ * [device] sized n+1 / tt_nnz_bound; b_tau, b_c [device] n.  Returns the
+ * actual nnz and the number of identity rows [host]. */
+int tt_assemble(const gw_grid *grid, const double *qx, const double *qy, const double *qz,
+                double phi, const gw_zone *zone, int32_t *rowptr, int32_t *col, double *val,
+                double *b_tau, double *b_c, int64_t *nnz, int64_t *n_identity, void *stream);
+
+/* Assemble, build one AMG hierarchy, and solve both right-hand sides with
+ * BiCGSTAB on it (the dual-delineation matrix is shared by its equations).
+ * tau, c [device] n; info [host] 2 entries (setup_ms is filled in both). */
+int tt_solve(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+             const gw_zone *zone, const amg_params *params, const amg_solve_params *sp, double *tau,
+             double *c, amg_solve_info info[2], void *stream);
+
+/* ---- kernel timing (HIP events around launches, for roofline reports) --- */
+
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double ms;            /* summed event time                            */
+    double bytes;         /* summed algorithmic HBM bytes                 */
+} gw_kernel_stat;
+
+/* on = 1 starts recording (and clears the table), 0 stops. */
+int gw_prof_enable(int32_t on);
+/* Copy up to max entries [host]; *n receives the number of kernels. */
+int gw_prof_read(gw_kernel_stat *out, int32_t max, int32_t *n);
+
+/* ---- serving: continuous batching of flow + travel-time requests -------- */
+
+typedef struct {
+    gw_grid grid;
+    const double *K;         /* [host] n, read during the request        */
+    gw_bc bc;
+    const gw_well *wells;    /* [host] nwells                            */
+    int32_t nwells;
+    double phi;
+    gw_zone zone;
+    amg_params flow_params;
+    amg_params tt_params;
+    amg_solve_params solve;
+    double *h_out;           /* [host] n or NULL                          */
+    double *tau_out;         /* [host] n or NULL                          */
+    double *c_out;           /* [host] n or NULL                          */
+    double t_arrival;        /* seconds on the queue clock; < 0 = now     */
+} gw_request;
+
+typedef struct {
+    int32_t status;
+    amg_solve_info flow;
+    amg_solve_info tt[2];
+    double t_arrival, t_start, t_done; /* seconds on the queue clock      */
+    size_t bytes_reserved;             /* admission footprint             */
+} gw_result;
+
+/* hbm_budget_bytes: device memory the queue may reserve for requests in
+ * flight; max_slots: requests that may run at once. */
+int queue_create(size_t hbm_budget_bytes, int32_t max_slots, gw_queue **q);
+/* Seconds since the queue was created (the clock of t_arrival). */
+double queue_clock(const gw_queue *q);
+/* Enqueue; EAGAIN when 4096 requests wait; ENOMEM when the request alone
+ * exceeds the budget.  The request is copied; its buffers are not. */
+int queue_submit(gw_queue *q, const gw_request *req, uint64_t *ticket);
+/* GW_PENDING while queued or running; otherwise the final status, with
+ * `res` filled; a finished ticket is forgotten after it is returned. */
+int queue_poll(gw_queue *q, uint64_t ticket, gw_result *res);
+/* Block until every submitted request is finished. */
+int queue_drain(gw_queue *q);
+void queue_destroy(gw_queue *q);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWAMG_H */

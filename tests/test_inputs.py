@@ -1,0 +1,44 @@
+"""Checks of the seeded input generator (CPU only)."""
+import numpy as np
+
+import gwinputs as gi
+
+
+def test_field_is_seeded():
+    a = gi.lognormal_field((16, 12, 8), 4.0, 4, 11)
+    b = gi.lognormal_field((16, 12, 8), 4.0, 4, 11)
+    c = gi.lognormal_field((16, 12, 8), 4.0, 4, 12)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert a.dtype == np.float64 and a.shape == (16 * 12 * 8,) and np.all(a > 0)
+
+
+def test_field_statistics():
+    # Y = ln K - ln(1e-4): zero mean, variance sigma2 and exponential
+    # covariance sigma2 exp(-r / lambda); on a domain much larger than lambda
+    # the single-realisation estimates are within a few sampling errors.
+    s2, lam = 2.0, 4.0
+    K, clip = gi.lognormal_field((512, 512, 1), s2, lam, 5, return_clip=True)
+    y = (np.log(K) - np.log(1e-4)).reshape(512, 512)
+    assert clip < 0.05
+    assert abs(y.mean()) < 0.15
+    assert abs(y.var() - s2) < 0.25 * s2
+    lag = int(lam)
+    cov = np.mean((y[:, :-lag] - y.mean()) * (y[:, lag:] - y.mean()))
+    assert abs(cov - s2 * np.exp(-1.0)) < 0.25 * s2
+
+
+def test_well_layout_rule():
+    g = gi.Grid(128, 128, 64)
+    w = gi.four_well_layout(g)
+    assert [(x.ix, x.iy, x.iz) for x in w] == [(32, 32, 32), (96, 32, 32), (32, 96, 32), (96, 96, 32)]
+    regional = 1e-4 * (10.0 / 128) * (128 * 64)
+    assert np.isclose(sum(x.q for x in w), 0.4 * regional)
+
+
+def test_serve_stream():
+    s = gi.serve_stream(200, 10.0, seed=5)
+    assert len(s) == 200 and s[0].t == 0.0
+    assert all(32 <= a.side <= 192 for a in s)
+    assert {a.sigma2 for a in s} <= {1.0, 2.0, 4.0}
+    assert all(4 <= a.corr_len <= 16 for a in s)
+    assert np.all(np.diff([a.t for a in s]) >= 0)
