@@ -1,0 +1,225 @@
+"""Benchmark of the dual-delineation hot path on one MI355X.
+
+One step = one pass of the whole path over a 1M-cell lognormal aquifer
+(128 x 128 x 64, ln K variance 4, correlation length 8 cells, four pumping
+wells, fixed heads on the x faces), with K already resident in HBM:
+  finite-difference assembly -> AMG setup -> FP64 AMG-PCG to rtol 1e-8
+  -> Darcy fluxes -> upwind travel-time assembly -> AMG setup ->
+  BiCGSTAB for both right-hand sides (travel time and source-zone fraction).
+
+Prints one JSON line (value = passes per second, `solves/s`) with the
+flow time-to-rtol, a roofline entry for the dominant kernel (HIP-event
+timing of each launch inside the timed region, algorithmic bytes per launch)
+and a CPU baseline from the FP64 oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (nx, ny, nz, sigma2, corr_len, seed, precision)
+    "c2": (128, 128, 64, 4.0, 8.0, 11, 0),
+    "c3": (256, 256, 128, 4.0, 8.0, 21, 1),
+    "c3fp64": (256, 256, 128, 4.0, 8.0, 21, 0),
+    "c3s1": (256, 256, 128, 1.0, 8.0, 22, 1),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-prof", action="store_true", help="no per-launch event timing")
+    return ap.parse_args()
+
+
+class Pipeline:
+    def __init__(self, gw, torch, prob, precision):
+        self.gw, self.torch, self.p = gw, torch, prob
+        g = prob.grid
+        self.g = g
+        n, nnz = g.n, gw.fv_nnz(g)
+        d = dict(device="cuda")
+        f64, i32 = torch.float64, torch.int32
+        self.K = torch.from_numpy(prob.K).to(**d)
+        self.rowptr = torch.zeros(n + 1, dtype=i32, **d)
+        self.col = torch.zeros(nnz, dtype=i32, **d)
+        self.val = torch.zeros(nnz, dtype=f64, **d)
+        self.b = torch.zeros(n, dtype=f64, **d)
+        self.h = torch.zeros(n, dtype=f64, **d)
+        self.qx = torch.zeros((g.nx + 1) * g.ny * g.nz, dtype=f64, **d)
+        self.qy = torch.zeros(g.nx * (g.ny + 1) * g.nz, dtype=f64, **d)
+        self.qz = torch.zeros(g.nx * g.ny * (g.nz + 1), dtype=f64, **d)
+        self.tau = torch.zeros(n, dtype=f64, **d)
+        self.c = torch.zeros(n, dtype=f64, **d)
+        self.params = gw.AmgParams(precision=precision)
+        self.sp = gw.SolveParams(rtol=1e-8, maxiter=1000, check_every=4, flexible=-1)
+        self.zone = (0, g.ny, 0, max(1, g.nz // 2))
+        self.ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step(self):
+        gw, p, g = self.gw, self.p, self.g
+        self.ev[0].record()
+        gw.fv_assemble(g, self.K, (p.h_west, p.h_east), p.wells, self.rowptr, self.col, self.val, self.b)
+        H = gw.amg_setup(g.n, self.rowptr, self.col, self.val, self.params)
+        fi = gw.amg_solve_pcg(H, self.b, self.h, self.sp)
+        self.ev[1].record()
+        gw.darcy_flux(g, self.K, (p.h_west, p.h_east), self.h, self.qx, self.qy, self.qz)
+        st, ti = gw.tt_solve(g, self.qx, self.qy, self.qz, p.phi, self.zone, self.params, self.sp,
+                             self.tau, self.c)
+        self.ev[2].record()
+        del H
+        return fi, ti, st
+
+
+def cpu_baseline(prob, precision):
+    """Oracle on a bounded sample of the same workload (single thread)."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    A, b = oracle.fv_assemble(prob)
+    H = oracle.Hierarchy(A, oracle.AmgParams())
+    h, info = oracle.pcg(H, b, rtol=1e-8, flexible=bool(precision))
+    t_flow = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    qx, qy, qz = oracle.darcy_flux(prob, h)
+    g = prob.grid
+    At, bt, bc, _ = oracle.tt_assemble(g, qx, qy, qz, prob.phi, (0, g.ny, 0, max(1, g.nz // 2)))
+    Ht = oracle.Hierarchy(At, oracle.AmgParams())
+    t_tsetup = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    tau, ti = oracle.bicgstab(Ht, bt, rtol=1e-8)
+    t_tsolve = time.perf_counter() - t2
+    total = t_flow + t_tsetup + 2 * t_tsolve
+    return {
+        "value": 1.0 / total,
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("one pass of the same 128x128x64 workload on the FP64 C oracle: assembly, setup, PCG "
+                   f"({info.iters} it), Darcy, travel-time setup and the first of the two BiCGSTAB solves "
+                   f"({ti.iters} it); the second solve is counted at the first one's time "
+                   f"[flow {t_flow:.1f} s, tt setup {t_tsetup:.1f} s, tt solve {t_tsolve:.1f} s]"),
+        "cpu_model": _cpu_model(),
+        "affinity": sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+        "os_cpu_count": os.cpu_count(),
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import gwinputs as gi
+    import paper_2001_05798_amd as gw
+
+    torch.cuda.set_device(0)
+    nx, ny, nz, s2, lam, seed, precision = WORKLOADS[args.workload]
+    prob = gi.heterogeneous_aquifer(nx, ny, nz, s2, lam, seed)
+    print(f"[bench] workload {args.workload}: {nx}x{ny}x{nz} s2={s2} lam={lam} seed={seed} "
+          f"precision={'mixed' if precision else 'fp64'}", file=sys.stderr, flush=True)
+    pipe = Pipeline(gw, torch, prob, precision)
+    for w in range(args.warmup):
+        fi, ti, st = pipe.step()
+        print(f"[bench] warmup {w}: flow iters {fi.iters} tt iters {ti[0].iters}/{ti[1].iters} "
+              f"status {fi.status}/{st}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    if not args.no_prof:
+        gw.prof_enable(True)
+    flow_ms, iters, titers = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        fi, ti, st = pipe.step()
+        iters.append(fi.iters)
+        titers.append((ti[0].iters, ti[1].iters))
+        flow_ms.append(pipe.ev[0].elapsed_time(pipe.ev[1]) if k >= 0 else 0.0)
+        if fi.status != gw.OK or st != gw.OK:
+            print(f"[bench] step {k}: status {fi.status}/{st}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = gw.prof_read() if not args.no_prof else {}
+    if not args.no_prof:
+        gw.prof_enable(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    roof = None
+    cand = {k: v for k, v in stats.items() if v["launches"] > 0 and v["bytes"] > 0 and k not in
+            ("coarse_lu", "spgemm", "setup_misc", "transpose", "mis2", "strength", "aggregate")}
+    if cand:
+        name = max(cand, key=lambda k: cand[k]["ms"])
+        s = cand[name]
+        per_launch_bytes = s["bytes"] / s["launches"]
+        avg_ms = s["ms"] / s["launches"]
+        achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": per_launch_bytes, "avg_launch_us": round(avg_ms * 1e3, 2),
+                "launches": s["launches"]}
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
+               for k, v in stats.items() if v["launches"]}
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(prob, precision)
+
+    out = {
+        "metric": "AMG-PCG time-to-rtol-1e-8 (1M cells, σ²=4); solves/s; p50/p99 latency",
+        "value": round(1e3 / ms_per_step, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32-hierarchy/f64-krylov",
+        "data": "synthetic",
+        "config": {"workload": (f"{nx}x{ny}x{nz} lognormal aquifer (lnK var {s2}, corr len {lam} cells, seed {seed}), "
+                                "4 wells; flow AMG-PCG rtol 1e-8 + Darcy + travel time (2 RHS, BiCGSTAB+AMG)"),
+                   "cells": nx * ny * nz, "parallelism": "single-gpu"},
+        "flow_time_to_rtol_ms": round(statistics.median(flow_ms), 3),
+        "flow_iters": int(statistics.median(iters)),
+        "tt_iters": list(titers[-1]),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,386 @@
+"""Python binding of libgwamg (gfx950 groundwater AMG-Krylov library).
+
+Argument marshalling only: every step runs in the HIP library behind the C
+ABI declared in ``include/gwamg.h``.  Device buffers are PyTorch tensors on
+the current HIP device; the stream is torch's current stream unless one is
+given.  Importing fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import List, Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgwamg.so")
+
+OK, NOT_CONVERGED, BREAKDOWN, PENDING = 0, 1, 2, 3
+EINVAL, ENOMEM, SINGULAR, EDEVICE, EAGAIN = -1, -2, -3, -4, -5
+SMOOTHER_JACOBI, SMOOTHER_SPAI0, SMOOTHER_NONE = 0, 1, 2
+PRECISION_FP64, PRECISION_MIXED = 0, 1
+
+STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", PENDING: "PENDING",
+                EINVAL: "EINVAL", ENOMEM: "ENOMEM", SINGULAR: "SINGULAR", EDEVICE: "EDEVICE",
+                EAGAIN: "EAGAIN"}
+
+
+class GwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# --------------------------------------------------------------- structs --
+class GwGrid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)]
+
+
+class GwCsr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class GwWell(C.Structure):
+    _fields_ = [("ix", C.c_int32), ("iy", C.c_int32), ("iz", C.c_int32), ("q", C.c_double)]
+
+
+class GwBc(C.Structure):
+    _fields_ = [("h_west", C.c_double), ("h_east", C.c_double)]
+
+
+class GwZone(C.Structure):
+    _fields_ = [("j0", C.c_int32), ("j1", C.c_int32), ("k0", C.c_int32), ("k1", C.c_int32)]
+
+
+class AmgParamsC(C.Structure):
+    _fields_ = [("eps_strong", C.c_double), ("smoother", C.c_int32), ("omega", C.c_double),
+                ("npre", C.c_int32), ("npost", C.c_int32), ("n_coarse", C.c_int32),
+                ("max_levels", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64)]
+
+
+class SolveParamsC(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("maxiter", C.c_int32), ("check_every", C.c_int32),
+                ("flexible", C.c_int32)]
+
+
+class SolveInfoC(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("restarts", C.c_int32),
+                ("rel_res", C.c_double), ("rel_res_true", C.c_double), ("setup_ms", C.c_double),
+                ("solve_ms", C.c_double)]
+
+
+class LevelInfoC(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nc", C.c_int32), ("nnz_p", C.c_int64),
+                ("nnz_s", C.c_int64), ("mis_rounds", C.c_int32), ("omega_p", C.c_double),
+                ("bytes", C.c_size_t)]
+
+
+class KernelStatC(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double)]
+
+
+class RequestC(C.Structure):
+    _fields_ = [("grid", GwGrid), ("K", C.c_void_p), ("bc", GwBc), ("wells", C.c_void_p),
+                ("nwells", C.c_int32), ("phi", C.c_double), ("zone", GwZone),
+                ("flow_params", AmgParamsC), ("tt_params", AmgParamsC), ("solve", SolveParamsC),
+                ("h_out", C.c_void_p), ("tau_out", C.c_void_p), ("c_out", C.c_void_p),
+                ("t_arrival", C.c_double)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("flow", SolveInfoC), ("tt", SolveInfoC * 2),
+                ("t_arrival", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("bytes_reserved", C.c_size_t)]
+
+
+# ------------------------------------------------------------------ load --
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_05798_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "gw_version": (C.c_char_p, []),
+        "gw_last_error": (C.c_char_p, []),
+        "gw_trim": (C.c_int, []),
+        "fv_nnz": (i64, [C.POINTER(GwGrid)]),
+        "fv_assemble": (C.c_int, [C.POINTER(GwGrid), vp, C.POINTER(GwBc), vp, i32, vp, vp, vp, vp, vp]),
+        "darcy_flux": (C.c_int, [C.POINTER(GwGrid), vp, C.POINTER(GwBc), vp, vp, vp, vp, vp]),
+        "amg_setup": (C.c_int, [C.POINTER(GwCsr), C.POINTER(AmgParamsC), C.POINTER(vp), vp]),
+        "amg_vcycle": (C.c_int, [vp, vp, vp, vp]),
+        "amg_spmv": (C.c_int, [vp, vp, vp, vp]),
+        "amg_solve_pcg": (C.c_int, [vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "amg_solve_bicgstab": (C.c_int, [vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "amg_hierarchy_info": (C.c_int, [vp, C.POINTER(LevelInfoC), i32, C.POINTER(i32), C.POINTER(C.c_size_t)]),
+        "amg_level_export": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "amg_coarse_export": (C.c_int, [vp, vp, vp, vp, vp]),
+        "amg_free": (None, [vp]),
+        "tt_nnz_bound": (i64, [C.POINTER(GwGrid)]),
+        "tt_assemble": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), vp, vp, vp, vp, vp,
+                                  C.POINTER(i64), C.POINTER(i64), vp]),
+        "tt_solve": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), C.POINTER(AmgParamsC),
+                               C.POINTER(SolveParamsC), vp, vp, C.POINTER(SolveInfoC), vp]),
+        "gw_prof_enable": (C.c_int, [i32]),
+        "gw_prof_read": (C.c_int, [C.POINTER(KernelStatC), i32, C.POINTER(i32)]),
+        "queue_create": (C.c_int, [C.c_size_t, i32, C.POINTER(vp)]),
+        "queue_clock": (f64, [vp]),
+        "queue_submit": (C.c_int, [vp, C.POINTER(RequestC), C.POINTER(C.c_uint64)]),
+        "queue_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ResultC)]),
+        "queue_drain": (C.c_int, [vp]),
+        "queue_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def version() -> str:
+    return _lib.gw_version().decode()
+
+
+def last_error() -> str:
+    return _lib.gw_last_error().decode()
+
+
+def _check(status: int, allow=(OK,)) -> int:
+    if status not in allow:
+        raise GwError(status, last_error())
+    return status
+
+
+# ------------------------------------------------------------- helpers ---
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _expect(t, dtype, n: int, name: str):
+    import torch
+    if t is None:
+        return
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {n}")
+
+
+def grid_c(grid) -> GwGrid:
+    return GwGrid(int(grid.nx), int(grid.ny), int(grid.nz), float(grid.dx), float(grid.dy), float(grid.dz))
+
+
+@dataclasses.dataclass
+class AmgParams:
+    eps_strong: float = 0.08
+    smoother: int = SMOOTHER_SPAI0
+    omega: float = 2.0 / 3.0
+    npre: int = 2
+    npost: int = 2
+    n_coarse: int = 500
+    max_levels: int = 20
+    precision: int = PRECISION_FP64
+    seed: int = 0x5EED
+
+    def c(self) -> AmgParamsC:
+        return AmgParamsC(self.eps_strong, self.smoother, self.omega, self.npre, self.npost,
+                          self.n_coarse, self.max_levels, self.precision, self.seed)
+
+
+@dataclasses.dataclass
+class SolveParams:
+    rtol: float = 1e-8
+    maxiter: int = 1000
+    check_every: int = 4
+    flexible: int = -1
+
+    def c(self) -> SolveParamsC:
+        return SolveParamsC(self.rtol, self.maxiter, self.check_every, self.flexible)
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    iters: int
+    status: int
+    restarts: int
+    rel_res: float
+    rel_res_true: float
+    setup_ms: float
+    solve_ms: float
+
+    @staticmethod
+    def of(c: SolveInfoC) -> "SolveInfo":
+        return SolveInfo(c.iters, c.status, c.restarts, c.rel_res, c.rel_res_true, c.setup_ms, c.solve_ms)
+
+
+# ----------------------------------------------------------- assembly ----
+def fv_nnz(grid) -> int:
+    return int(_lib.fv_nnz(C.byref(grid_c(grid))))
+
+
+def fv_assemble(grid, K, bc: Tuple[float, float], wells: Sequence, rowptr, col, val, b, stream=None) -> None:
+    import torch
+    g = grid_c(grid)
+    n = g.nx * g.ny * g.nz
+    nnz = fv_nnz(grid)
+    _expect(K, torch.float64, n, "K")
+    _expect(rowptr, torch.int32, n + 1, "rowptr")
+    _expect(col, torch.int32, nnz, "col")
+    _expect(val, torch.float64, nnz, "val")
+    _expect(b, torch.float64, n, "b")
+    wl = (GwWell * max(1, len(wells)))(*[GwWell(w.ix, w.iy, w.iz, w.q) for w in wells])
+    _check(_lib.fv_assemble(C.byref(g), _ptr(K), C.byref(GwBc(*bc)), C.addressof(wl), len(wells),
+                            _ptr(rowptr), _ptr(col), _ptr(val), _ptr(b), _stream(stream)))
+
+
+def darcy_flux(grid, K, bc: Tuple[float, float], h, qx, qy, qz, stream=None) -> None:
+    _check(_lib.darcy_flux(C.byref(grid_c(grid)), _ptr(K), C.byref(GwBc(*bc)), _ptr(h), _ptr(qx),
+                           _ptr(qy), _ptr(qz), _stream(stream)))
+
+
+def tt_nnz_bound(grid) -> int:
+    return int(_lib.tt_nnz_bound(C.byref(grid_c(grid))))
+
+
+def tt_assemble(grid, qx, qy, qz, phi: float, zone, rowptr, col, val, b_tau, b_c,
+                stream=None) -> Tuple[int, int]:
+    nnz, nid = C.c_int64(0), C.c_int64(0)
+    z = None if zone is None else C.byref(GwZone(*zone))
+    _check(_lib.tt_assemble(C.byref(grid_c(grid)), _ptr(qx), _ptr(qy), _ptr(qz), float(phi), z,
+                            _ptr(rowptr), _ptr(col), _ptr(val), _ptr(b_tau), _ptr(b_c),
+                            C.byref(nnz), C.byref(nid), _stream(stream)))
+    return int(nnz.value), int(nid.value)
+
+
+def tt_solve(grid, qx, qy, qz, phi: float, zone, params: AmgParams, sp: SolveParams, tau, c,
+             stream=None) -> Tuple[int, List[SolveInfo]]:
+    info = (SolveInfoC * 2)()
+    z = None if zone is None else C.byref(GwZone(*zone))
+    st = _check(_lib.tt_solve(C.byref(grid_c(grid)), _ptr(qx), _ptr(qy), _ptr(qz), float(phi), z,
+                              C.byref(params.c()), C.byref(sp.c()), _ptr(tau), _ptr(c), info,
+                              _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return st, [SolveInfo.of(info[0]), SolveInfo.of(info[1])]
+
+
+# ---------------------------------------------------------------- AMG ----
+@dataclasses.dataclass
+class LevelInfo:
+    n: int
+    nnz: int
+    nc: int
+    nnz_p: int
+    nnz_s: int
+    mis_rounds: int
+    omega_p: float
+    bytes: int
+
+
+class Hierarchy:
+    """Owns an amg_hierarchy handle (freed with amg_free)."""
+
+    def __init__(self, handle: int, n: int):
+        self._h = C.c_void_p(handle)
+        self.n = n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.amg_free(h)
+            self._h = C.c_void_p(0)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> Tuple[List[LevelInfo], int]:
+        arr = (LevelInfoC * 32)()
+        nl, nb = C.c_int32(0), C.c_size_t(0)
+        _check(_lib.amg_hierarchy_info(self._h, arr, 32, C.byref(nl), C.byref(nb)))
+        k = max(1, nl.value)
+        return ([LevelInfo(a.n, a.nnz, a.nc, a.nnz_p, a.nnz_s, a.mis_rounds, a.omega_p, a.bytes)
+                 for a in arr[:k]], int(nb.value))
+
+    @property
+    def nlevels(self) -> int:
+        nl = C.c_int32(0)
+        _check(_lib.amg_hierarchy_info(self._h, None, 0, C.byref(nl), None))
+        return nl.value
+
+
+def amg_setup(n: int, rowptr, col, val, params: AmgParams = AmgParams(), stream=None) -> Hierarchy:
+    nnz = int(col.numel())
+    A = GwCsr(int(n), nnz, _ptr(rowptr), _ptr(col), _ptr(val))
+    h = C.c_void_p(0)
+    _check(_lib.amg_setup(C.byref(A), C.byref(params.c()), C.byref(h), _stream(stream)))
+    return Hierarchy(h.value, int(n))
+
+
+def amg_vcycle(H: Hierarchy, r, z, stream=None) -> None:
+    _check(_lib.amg_vcycle(H.handle, _ptr(r), _ptr(z), _stream(stream)))
+
+
+def amg_spmv(H: Hierarchy, x, y, stream=None) -> None:
+    _check(_lib.amg_spmv(H.handle, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def amg_solve_pcg(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stream=None) -> SolveInfo:
+    info = SolveInfoC()
+    _check(_lib.amg_solve_pcg(H.handle, _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info), _stream(stream)),
+           allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return SolveInfo.of(info)
+
+
+def amg_solve_bicgstab(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stream=None) -> SolveInfo:
+    info = SolveInfoC()
+    _check(_lib.amg_solve_bicgstab(H.handle, _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info),
+                                   _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return SolveInfo.of(info)
+
+
+def amg_level_export(H: Hierarchy, level: int, a_rowptr=None, a_col=None, a_val=None, agg=None, M=None,
+                     p_rowptr=None, p_col=None, p_val=None, stream=None) -> None:
+    _check(_lib.amg_level_export(H.handle, int(level), _ptr(a_rowptr), _ptr(a_col), _ptr(a_val), _ptr(agg),
+                                 _ptr(M), _ptr(p_rowptr), _ptr(p_col), _ptr(p_val), _stream(stream)))
+
+
+def amg_coarse_export(H: Hierarchy, lu=None, piv=None, inv=None, stream=None) -> None:
+    _check(_lib.amg_coarse_export(H.handle, _ptr(lu), _ptr(piv), _ptr(inv), _stream(stream)))
+
+
+# ------------------------------------------------------------ profiling --
+def prof_enable(on: bool) -> None:
+    _check(_lib.gw_prof_enable(1 if on else 0))
+
+
+def prof_read() -> dict:
+    arr = (KernelStatC * 64)()
+    n = C.c_int32(0)
+    _check(_lib.gw_prof_read(arr, 64, C.byref(n)))
+    return {a.name.decode(): {"launches": int(a.launches), "ms": float(a.ms), "bytes": float(a.bytes)}
+            for a in arr[:n.value]}
+
+
+def trim() -> None:
+    _check(_lib.gw_trim())

@@ -1,0 +1,341 @@
+// C ABI entry points (include/gwamg.h): argument checks, hierarchy
+// lifetime, and the host-side sequencing of assembly, setup and solves.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <memory>
+
+#include "gw_internal.h"
+
+using namespace gw;
+
+amg_hierarchy::~amg_hierarchy() { delete ks_host; }
+
+size_t amg_hierarchy::bytes() const {
+    size_t b = lu.bytes() + inv.bytes() + piv.bytes() + kvec.bytes() + partials.bytes() + ks.bytes();
+    for (int l = 0; l < nlev || (l == 0 && !L.empty()); ++l) b += L[l].bytes();
+    return b;
+}
+
+namespace {
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void check_grid(const gw_grid *g) {
+    GW_REQUIRE(g, "null grid");
+    GW_REQUIRE(g->nx > 0 && g->ny > 0 && g->nz > 0, "grid sizes must be positive");
+    GW_REQUIRE((int64_t)g->nx * g->ny * g->nz < ((int64_t)1 << 30), "grid exceeds 2^30 cells");
+    GW_REQUIRE(g->dx > 0 && g->dy > 0 && g->dz > 0 && std::isfinite(g->dx) && std::isfinite(g->dy) &&
+                   std::isfinite(g->dz),
+               "grid spacings must be positive and finite");
+}
+
+int64_t nnz7(const gw_grid *g) {
+    int64_t n = (int64_t)g->nx * g->ny * g->nz;
+    return 7 * n - 2 * ((int64_t)g->nx * g->ny + (int64_t)g->ny * g->nz + (int64_t)g->nx * g->nz);
+}
+
+void check_params(const amg_params *p) {
+    GW_REQUIRE(p, "null amg_params");
+    GW_REQUIRE(p->smoother >= GW_SMOOTHER_JACOBI && p->smoother <= GW_SMOOTHER_NONE, "unknown smoother");
+    GW_REQUIRE(p->precision == GW_PRECISION_FP64 || p->precision == GW_PRECISION_MIXED, "unknown precision");
+    GW_REQUIRE(p->npre >= 0 && p->npost >= 0 && p->npre <= 16 && p->npost <= 16, "sweeps must be in [0, 16]");
+    GW_REQUIRE(p->n_coarse >= 1 && p->max_levels >= 1, "n_coarse and max_levels must be positive");
+    GW_REQUIRE(p->eps_strong >= 0 && std::isfinite(p->eps_strong), "eps_strong must be >= 0");
+    GW_REQUIRE(std::isfinite(p->omega), "omega must be finite");
+}
+
+void finish(hipStream_t s) {
+    GW_HIP(hipStreamSynchronize(s));
+    if (prof_on()) prof_flush();
+}
+
+// Hierarchy of a device CSR (copied), as amg_setup documents.
+amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream_t s) {
+    GW_REQUIRE(A && A->rowptr && A->col && A->val, "amg_setup: null matrix");
+    GW_REQUIRE(A->n > 0 && A->nnz >= A->n && A->nnz < INT32_MAX, "amg_setup: bad matrix size");
+    check_params(prm);
+    std::unique_ptr<amg_hierarchy> H(new amg_hierarchy());
+    int dev = 0;
+    GW_HIP(hipGetDevice(&dev));
+    H->device = dev;
+    H->prm = *prm;
+    H->L.resize(33);
+    Level &L0 = H->L[0];
+    L0.A.alloc(A->n, A->n, A->nnz);
+    copy_bytes(L0.A.rowptr.p, A->rowptr, sizeof(int32_t) * ((size_t)A->n + 1), s);
+    copy_bytes(L0.A.col.p, A->col, sizeof(int32_t) * (size_t)A->nnz, s);
+    copy_bytes(L0.A.val.p, A->val, sizeof(double) * (size_t)A->nnz, s);
+    {
+        DBuf<double> diag(A->n);
+        DBuf<int32_t> bad(1);
+        fill_i32(bad.p, 0, 1, s);
+        launch_csr_check(view(L0.A), diag.p, bad.p, s);
+        int32_t hb = 0;
+        GW_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        if (hb & 1) fail(GW_EINVAL, "amg_setup: CSR structure invalid (row pointers, column range or order)");
+        if (hb & 2) fail(GW_EINVAL, "amg_setup: a diagonal entry is missing or not positive");
+        if (hb & 4) fail(GW_EINVAL, "amg_setup: non-finite matrix value");
+    }
+    if (prm->smoother == GW_SMOOTHER_NONE) {
+        H->nlev = 0;
+        return H.release();
+    }
+    for (int l = 0;; ++l) {
+        bool coarsest = false;
+        build_level(H.get(), l, s, &coarsest);
+        if (coarsest) {
+            build_coarsest(H.get(), l, s);
+            H->nlev = l + 1;
+            break;
+        }
+    }
+    const size_t es = H->mixed() ? 4 : 8;
+    for (int l = 0; l < H->nlev; ++l) {
+        Level &Lv = H->L[l];
+        if (l < H->nlev - 1) {
+            make_smoother(H.get(), l, s);
+            if (H->mixed()) convert_level_fp32(H.get(), l, s);
+        }
+        const size_t n = (size_t)Lv.A.n;
+        Lv.vx.alloc(n * es);
+        Lv.vt.alloc(n * es);
+        if (l > 0) Lv.vb.alloc(n * es);
+    }
+    GW_HIP(hipStreamSynchronize(s));
+    return H.release();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gw_version(void) { return "gwamg 0.1.0 gfx950"; }
+
+int64_t fv_nnz(const gw_grid *grid) {
+    if (!grid || grid->nx <= 0 || grid->ny <= 0 || grid->nz <= 0) return -1;
+    return nnz7(grid);
+}
+
+int64_t tt_nnz_bound(const gw_grid *grid) { return fv_nnz(grid); }
+
+int fv_assemble(const gw_grid *grid, const double *K, const gw_bc *bc, const gw_well *wells, int32_t nwells,
+                int32_t *rowptr, int32_t *col, double *val, double *b, void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(K && bc && rowptr && col && val && b, "fv_assemble: null pointer");
+        GW_REQUIRE(nwells == 0 || wells, "fv_assemble: null wells");
+        GW_REQUIRE(std::isfinite(bc->h_west) && std::isfinite(bc->h_east), "fv_assemble: non-finite head");
+        GW_REQUIRE(nnz7(grid) < INT32_MAX, "fv_assemble: matrix exceeds 2^31 nonzeros");
+        hipStream_t s = as_stream(stream);
+        DBuf<int32_t> bad(1);
+        fill_i32(bad.p, 0, 1, s);
+        launch_fv_assemble(*grid, K, *bc, wells, nwells, rowptr, col, val, b, bad.p, s);
+        int32_t hb = 0;
+        GW_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        finish(s);
+        if (hb) fail(GW_EINVAL, "fv_assemble: conductivity must be positive and finite");
+        return GW_OK;
+    });
+}
+
+int darcy_flux(const gw_grid *grid, const double *K, const gw_bc *bc, const double *h, double *qx, double *qy,
+               double *qz, void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(K && bc && h && qx && qy && qz, "darcy_flux: null pointer");
+        hipStream_t s = as_stream(stream);
+        launch_darcy(*grid, K, *bc, h, qx, qy, qz, s);
+        finish(s);
+        return GW_OK;
+    });
+}
+
+int amg_setup(const gw_csr *A, const amg_params *params, amg_hierarchy **H, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H, "amg_setup: null output");
+        *H = nullptr;
+        hipStream_t s = as_stream(stream);
+        *H = setup_hierarchy(A, params, s);
+        finish(s);
+        return GW_OK;
+    });
+}
+
+int amg_vcycle(amg_hierarchy *H, const double *r, double *z, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H && r && z, "amg_vcycle: null pointer");
+        hipStream_t s = as_stream(stream);
+        vcycle(H, r, z, nullptr, s);
+        finish(s);
+        return GW_OK;
+    });
+}
+
+int amg_spmv(amg_hierarchy *H, const double *x, double *y, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H && x && y, "amg_spmv: null pointer");
+        hipStream_t s = as_stream(stream);
+        spmv_f64(view(H->L[0].A), x, y, s);
+        finish(s);
+        return GW_OK;
+    });
+}
+
+static void check_solve(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp) {
+    GW_REQUIRE(H && b && x && sp, "solve: null pointer");
+    GW_REQUIRE(sp->rtol >= 0 && std::isfinite(sp->rtol), "solve: rtol must be >= 0");
+    GW_REQUIRE(sp->maxiter >= 0, "solve: maxiter must be >= 0");
+}
+
+int amg_solve_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp, amg_solve_info *info,
+                  void *stream) {
+    return guarded([&] {
+        check_solve(H, b, x, sp);
+        hipStream_t s = as_stream(stream);
+        int st = krylov_pcg(H, b, x, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
+int amg_solve_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
+                       amg_solve_info *info, void *stream) {
+    return guarded([&] {
+        check_solve(H, b, x, sp);
+        hipStream_t s = as_stream(stream);
+        int st = krylov_bicgstab(H, b, x, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
+int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_levels, int32_t *nlevels,
+                       size_t *bytes) {
+    return guarded([&] {
+        GW_REQUIRE(H, "amg_hierarchy_info: null hierarchy");
+        const int nl = std::max(H->nlev, 1);
+        if (nlevels) *nlevels = H->nlev;
+        if (bytes) *bytes = H->bytes();
+        for (int l = 0; l < nl && l < max_levels && out; ++l) {
+            const Level &Lv = H->L[l];
+            amg_level_info &o = out[l];
+            o.n = Lv.A.n;
+            o.nnz = Lv.A.nnz;
+            o.nc = Lv.nc;
+            o.nnz_p = Lv.P.nnz;
+            o.nnz_s = Lv.nnz_s;
+            o.mis_rounds = Lv.mis_rounds;
+            o.omega_p = Lv.omega_p;
+            o.bytes = Lv.bytes() + (l == H->nlev - 1 ? H->lu.bytes() + H->inv.bytes() + H->piv.bytes() : 0);
+        }
+        return GW_OK;
+    });
+}
+
+int amg_level_export(const amg_hierarchy *H, int32_t level, int32_t *a_rowptr, int32_t *a_col, double *a_val,
+                     int32_t *agg, double *M, int32_t *p_rowptr, int32_t *p_col, double *p_val, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H, "amg_level_export: null hierarchy");
+        GW_REQUIRE(level >= 0 && level < std::max(H->nlev, 1), "amg_level_export: level out of range");
+        hipStream_t s = as_stream(stream);
+        const Level &Lv = H->L[level];
+        const bool coarsest = level == H->nlev - 1 || H->nlev == 0;
+        if (a_rowptr) copy_bytes(a_rowptr, Lv.A.rowptr.p, Lv.A.rowptr.bytes(), s);
+        if (a_col) copy_bytes(a_col, Lv.A.col.p, Lv.A.col.bytes(), s);
+        if (a_val) copy_bytes(a_val, Lv.A.val.p, Lv.A.val.bytes(), s);
+        if (!coarsest) {
+            if (agg) copy_bytes(agg, Lv.agg.p, Lv.agg.bytes(), s);
+            if (M) copy_bytes(M, Lv.M.p, Lv.M.bytes(), s);
+            if (p_rowptr) copy_bytes(p_rowptr, Lv.P.rowptr.p, Lv.P.rowptr.bytes(), s);
+            if (p_col) copy_bytes(p_col, Lv.P.col.p, Lv.P.col.bytes(), s);
+            if (p_val) copy_bytes(p_val, Lv.P.val.p, Lv.P.val.bytes(), s);
+        }
+        finish(s);
+        return GW_OK;
+    });
+}
+
+int amg_coarse_export(const amg_hierarchy *H, double *lu, int32_t *piv, double *inv, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H && H->nlev > 0, "amg_coarse_export: no coarse level");
+        hipStream_t s = as_stream(stream);
+        if (lu) copy_bytes(lu, H->lu.p, H->lu.bytes(), s);
+        if (piv) copy_bytes(piv, H->piv.p, H->piv.bytes(), s);
+        if (inv) copy_bytes(inv, H->inv.p, H->inv.bytes(), s);
+        finish(s);
+        return GW_OK;
+    });
+}
+
+void amg_free(amg_hierarchy *H) { delete H; }
+
+int tt_assemble(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+                const gw_zone *zone, int32_t *rowptr, int32_t *col, double *val, double *b_tau, double *b_c,
+                int64_t *nnz, int64_t *n_identity, void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(qx && qy && qz && rowptr && col && val && b_tau && b_c, "tt_assemble: null pointer");
+        GW_REQUIRE(std::isfinite(phi) && phi > 0, "tt_assemble: porosity must be positive");
+        hipStream_t s = as_stream(stream);
+        gw_zone z = zone ? *zone : gw_zone{0, grid->ny, 0, grid->nz};
+        const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+        DBuf<int64_t> total(1);
+        DBuf<int32_t> nid(1);
+        fill_i32(nid.p, 0, 1, s);
+        fill_i32(rowptr, 0, 1, s);
+        launch_tt_count(*grid, qx, qy, qz, rowptr + 1, s);
+        scan_inclusive_i32(rowptr + 1, n, total.p, s);
+        launch_tt_fill(*grid, qx, qy, qz, phi, z, rowptr, col, val, b_tau, b_c, nid.p, s);
+        int64_t hn = 0;
+        int32_t hi = 0;
+        GW_HIP(hipMemcpyAsync(&hn, total.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipMemcpyAsync(&hi, nid.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        finish(s);
+        if (nnz) *nnz = hn;
+        if (n_identity) *n_identity = hi;
+        return GW_OK;
+    });
+}
+
+int tt_solve(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+             const gw_zone *zone, const amg_params *params, const amg_solve_params *sp, double *tau, double *c,
+             amg_solve_info info[2], void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(qx && qy && qz && params && sp && tau && c, "tt_solve: null pointer");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+        const double t0 = now_ms();
+        Csr A;
+        A.alloc((int32_t)n, (int32_t)n, nnz7(grid));
+        DBuf<double> bt(n), bc(n);
+        int64_t nnz = 0, nid = 0;
+        int rc = tt_assemble(grid, qx, qy, qz, phi, zone, A.rowptr.p, A.col.p, A.val.p, bt.p, bc.p, &nnz, &nid,
+                             stream);
+        if (rc != GW_OK) fail(rc, gw_last_error());
+        gw_csr view_{(int32_t)n, nnz, A.rowptr.p, A.col.p, A.val.p};
+        std::unique_ptr<amg_hierarchy> H(setup_hierarchy(&view_, params, s));
+        A = Csr();
+        const double setup_ms = now_ms() - t0;
+        amg_solve_info i1{}, i2{};
+        int s1 = krylov_bicgstab(H.get(), bt.p, tau, *sp, &i1, s);
+        int s2 = krylov_bicgstab(H.get(), bc.p, c, *sp, &i2, s);
+        finish(s);
+        i1.setup_ms = i2.setup_ms = setup_ms;
+        if (info) {
+            info[0] = i1;
+            info[1] = i2;
+        }
+        if (s1 == GW_BREAKDOWN || s2 == GW_BREAKDOWN) return GW_BREAKDOWN;
+        if (s1 != GW_OK || s2 != GW_OK) return GW_NOT_CONVERGED;
+        return GW_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,248 @@
+// Internal declarations of the gfx950 groundwater AMG library: error
+// plumbing, the device memory pool, device-resident matrix/level structures
+// and the kernel launchers shared between the .hip translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "gwamg.h"
+
+namespace gw {
+
+// ---------------------------------------------------------------- errors --
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define GW_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            ::gw::fail(GW_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define GW_REQUIRE(cond, msg)                        \
+    do {                                             \
+        if (!(cond)) ::gw::fail(GW_EINVAL, (msg));   \
+    } while (0)
+
+// Run `f` and turn exceptions into a status code + thread-local message.
+template <class F>
+int guarded(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return GW_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return GW_EDEVICE;
+    }
+}
+
+// ------------------------------------------------------------ memory pool --
+// Device allocations are served from per-device free lists of size classes
+// (1/8-octave steps above 4 KiB), so repeated setups and solves do not call
+// hipMalloc.  Thread safe.  gw_trim() returns cached blocks to HIP.
+void *pool_alloc(size_t bytes);
+void pool_free(void *p);
+void pool_trim();
+size_t pool_class_bytes(size_t bytes);
+
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    explicit DBuf(size_t count) { alloc(count); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        p = count ? static_cast<T *>(pool_alloc(count * sizeof(T))) : nullptr;
+    }
+    void release() {
+        if (p) pool_free(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    T *get() const { return p; }
+};
+
+// Pinned host staging for small device->host reads.
+struct Pinned {
+    void *p = nullptr;
+    size_t n = 0;
+    explicit Pinned(size_t bytes);
+    ~Pinned();
+    Pinned(const Pinned &) = delete;
+    Pinned &operator=(const Pinned &) = delete;
+};
+
+// --------------------------------------------------------- kernel timing --
+// When enabled, launches wrapped in a ProfScope are bracketed by HIP events
+// on their stream; durations are summed at the next prof_flush().
+enum KernelId : int {
+    K_FV_ASSEMBLE, K_DARCY, K_TT_ASSEMBLE,
+    K_SETUP_MISC, K_TRANSPOSE, K_STRENGTH, K_MIS2, K_AGGREGATE, K_SPGEMM, K_COARSE_LU,
+    K_SMOOTH_FIRST, K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE,
+    K_KRYLOV_SPMV, K_KRYLOV_UPDATE, K_KRYLOV_DOT, K_TRUE_RESIDUAL,
+    K_COUNT
+};
+const char *kernel_name(int id);
+bool prof_on();
+struct ProfScope {
+    int id;
+    double bytes;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfScope(int id_, double bytes_, hipStream_t s_);
+    ~ProfScope();
+};
+void prof_flush();
+
+// ------------------------------------------------------- device matrices --
+struct Csr {
+    int32_t n = 0, ncols = 0;
+    int64_t nnz = 0;
+    DBuf<int32_t> rowptr, col;
+    DBuf<double> val;
+    DBuf<float> val32;  // FP32 copy (mixed precision levels)
+    void alloc(int32_t n_, int32_t ncols_, int64_t nnz_) {
+        n = n_; ncols = ncols_; nnz = nnz_;
+        rowptr.alloc((size_t)n + 1);
+        col.alloc((size_t)nnz);
+        val.alloc((size_t)nnz);
+    }
+    size_t bytes() const { return rowptr.bytes() + col.bytes() + val.bytes() + val32.bytes(); }
+};
+
+// Read-only view of a CSR on the device.
+struct CsrView {
+    int32_t n, ncols;
+    int64_t nnz;
+    const int32_t *rowptr, *col;
+    const double *val;
+};
+inline CsrView view(const Csr &A) { return {A.n, A.ncols, A.nnz, A.rowptr.p, A.col.p, A.val.p}; }
+
+// ------------------------------------------------------------ hierarchy --
+struct Level {
+    Csr A;           // operator A_l (level 0: copy of the caller's matrix)
+    Csr P, R;        // prolongator n x nc and its transpose (empty on coarsest)
+    DBuf<int32_t> agg;
+    DBuf<double> M;  // smoother diagonal
+    DBuf<float> M32;
+    int32_t nc = 0;
+    int64_t nnz_s = 0;
+    int32_t mis_rounds = 0;
+    double omega_p = 0.0;
+    // V-cycle vectors of this level, element size 8 (FP64) or 4 (mixed):
+    // b (right-hand side), x (iterate) and t (ping-pong / residual)
+    DBuf<char> vb, vx, vt;
+    size_t bytes() const {
+        return A.bytes() + P.bytes() + R.bytes() + agg.bytes() + M.bytes() + M32.bytes() +
+               vb.bytes() + vx.bytes() + vt.bytes();
+    }
+};
+
+// Device-resident Krylov scalars (one block of them per hierarchy).
+struct KScalars {
+    double bnorm, tol;               // ||b||, rtol ||b||
+    double rz, pq, alpha, beta, rr;  // CG
+    double zq;                       // flexible CG: z . q
+    double rho, rho_prev, omega, rv, ts, tt, ss;  // BiCGSTAB
+    double rel_true;
+    int32_t iters, maxiter, done, status, flexible, pending_x;
+    uint32_t counter;                // last-block ticket
+    int32_t pad;
+};
+
+}  // namespace gw
+
+struct amg_hierarchy {
+    amg_params prm{};
+    int device = 0;
+    int nlev = 0;  // number of levels including the coarsest (0 = no preconditioner)
+    std::vector<gw::Level> L;
+    int32_t nd = 0;  // coarsest size
+    gw::DBuf<double> lu, inv;  // row-major LU, column-major inverse
+    gw::DBuf<int32_t> piv;
+    // Krylov workspace
+    gw::DBuf<double> kvec;  // up to 9 vectors of n
+    int kvec_count = 0;
+    gw::DBuf<double> partials;
+    gw::DBuf<gw::KScalars> ks;
+    gw::Pinned *ks_host = nullptr;
+    ~amg_hierarchy();
+    bool mixed() const { return prm.precision == GW_PRECISION_MIXED; }
+    size_t bytes() const;
+};
+
+namespace gw {
+
+// ---------------------------------------------------------- launchers ----
+// All launchers enqueue on `s` and return immediately.
+constexpr int kBlock = 256;
+inline unsigned blocks_for(int64_t n, int per_thread = 1, int block = kBlock) {
+    int64_t b = (n + (int64_t)block * per_thread - 1) / ((int64_t)block * per_thread);
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+// scan.hip / util
+// In place inclusive scan of a[0..n) (int32), total returned in *total (device int64).
+void scan_inclusive_i32(int32_t *a, int64_t n, int64_t *total, hipStream_t s);
+void fill_i32(int32_t *a, int32_t v, int64_t n, hipStream_t s);
+void fill_f64(double *a, double v, int64_t n, hipStream_t s);
+void copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+// assemble.hip
+void launch_fv_assemble(const gw_grid &g, const double *K, const gw_bc &bc, const gw_well *wells,
+                        int nwells, int32_t *rowptr, int32_t *col, double *val, double *b,
+                        int32_t *bad, hipStream_t s);
+void launch_darcy(const gw_grid &g, const double *K, const gw_bc &bc, const double *h, double *qx,
+                  double *qy, double *qz, hipStream_t s);
+void launch_tt_count(const gw_grid &g, const double *qx, const double *qy, const double *qz,
+                     int32_t *rowlen, hipStream_t s);
+void launch_tt_fill(const gw_grid &g, const double *qx, const double *qy, const double *qz,
+                    double phi, const gw_zone &z, const int32_t *rowptr, int32_t *col, double *val,
+                    double *bt, double *bc, int32_t *n_ident, hipStream_t s);
+
+// setup.hip
+void launch_csr_check(const CsrView &A, double *diag, int32_t *bad, hipStream_t s);
+void transpose(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total);
+void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest);
+void build_coarsest(amg_hierarchy *H, int l, hipStream_t s);
+void make_smoother(amg_hierarchy *H, int l, hipStream_t s);
+void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s);
+
+// solve.hip
+void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s);
+void spmv_f64(const CsrView &A, const double *x, double *y, hipStream_t s);
+int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
+               amg_solve_info *info, hipStream_t s);
+int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
+                    amg_solve_info *info, hipStream_t s);
+
+}  // namespace gw

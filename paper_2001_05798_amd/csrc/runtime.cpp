@@ -1,0 +1,274 @@
+// Runtime services of the library: thread-local error messages, the caching
+// device memory pool, pinned staging buffers and event-based kernel timing.
+#include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "gw_internal.h"
+
+namespace gw {
+
+// ------------------------------------------------------------------ errors --
+static thread_local std::string t_last_error;
+
+void set_last_error(const std::string &msg) { t_last_error = msg; }
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+// -------------------------------------------------------------------- pool --
+namespace {
+
+struct BlockInfo {
+    size_t cls;
+    int device;
+};
+
+// Free lists are per (device, host thread, size class): a block freed while
+// kernels of its thread's stream may still read it can only be reused by the
+// same thread, hence on the same stream, in stream order.  Every blocking
+// entry point synchronizes its stream before returning, so a thread never
+// switches streams with such work pending.
+struct Key {
+    int device;
+    int thread;
+    size_t cls;
+    bool operator<(const Key &o) const {
+        if (device != o.device) return device < o.device;
+        if (thread != o.thread) return thread < o.thread;
+        return cls < o.cls;
+    }
+};
+
+int thread_tag() {
+    static std::atomic<int> next{0};
+    static thread_local int tag = next.fetch_add(1);
+    return tag;
+}
+
+struct Pool {
+    std::mutex mu;
+    std::map<Key, std::vector<void *>> free_lists;
+    std::unordered_map<void *, BlockInfo> live;
+    size_t cached = 0, in_use = 0;
+};
+
+Pool &pool() {
+    static Pool *p = new Pool();  // never destroyed: blocks may be freed at exit
+    return *p;
+}
+
+}  // namespace
+
+size_t pool_class_bytes(size_t bytes) {
+    if (bytes <= 4096) return 4096;
+    int e = 63 - __builtin_clzll((unsigned long long)bytes);
+    size_t step = (size_t)1 << (e - 3);
+    return (bytes + step - 1) / step * step;
+}
+
+void *pool_alloc(size_t bytes) {
+    size_t cls = pool_class_bytes(bytes);
+    int dev = 0;
+    GW_HIP(hipGetDevice(&dev));
+    Pool &P = pool();
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        auto it = P.free_lists.find(Key{dev, thread_tag(), cls});
+        if (it != P.free_lists.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            P.cached -= cls;
+            P.in_use += cls;
+            P.live[p] = {cls, dev};
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, cls);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        // give cached blocks back and retry once
+        GW_HIP(hipDeviceSynchronize());
+        pool_trim();
+        e = hipMalloc(&p, cls);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(GW_ENOMEM, "device allocation of " + std::to_string(cls) + " bytes failed");
+        }
+    }
+    std::lock_guard<std::mutex> g(P.mu);
+    P.live[p] = {cls, dev};
+    P.in_use += cls;
+    return p;
+}
+
+void pool_free(void *p) {
+    if (!p) return;
+    Pool &P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    auto it = P.live.find(p);
+    if (it == P.live.end()) return;
+    BlockInfo bi = it->second;
+    P.live.erase(it);
+    P.in_use -= bi.cls;
+    P.cached += bi.cls;
+    P.free_lists[Key{bi.device, thread_tag(), bi.cls}].push_back(p);
+}
+
+void pool_trim() {
+    Pool &P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : P.free_lists) {
+        if (kv.second.empty()) continue;
+        (void)hipSetDevice(kv.first.device);
+        for (void *p : kv.second) (void)hipFree(p);
+        P.cached -= kv.first.cls * kv.second.size();
+        kv.second.clear();
+    }
+    (void)hipSetDevice(cur);
+}
+
+// ------------------------------------------------------------------ pinned --
+Pinned::Pinned(size_t bytes) : n(bytes) {
+    GW_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    std::memset(p, 0, bytes);
+}
+Pinned::~Pinned() {
+    if (p) (void)hipHostFree(p);
+}
+
+// ------------------------------------------------------------------ timing --
+namespace {
+
+struct ProfState {
+    std::mutex mu;
+    bool on = false;
+    struct Pending {
+        int id;
+        double bytes;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+    int64_t launches[K_COUNT] = {};
+    double ms[K_COUNT] = {};
+    double bytes[K_COUNT] = {};
+};
+
+ProfState &prof() {
+    static ProfState *p = new ProfState();
+    return *p;
+}
+
+const char *const kNames[K_COUNT] = {
+    "fv_assemble", "darcy_flux", "tt_assemble",
+    "setup_misc", "transpose", "strength", "mis2", "aggregate", "spgemm", "coarse_lu",
+    "smooth_first", "smooth", "residual", "restrict", "prolong", "coarse_solve",
+    "krylov_spmv", "krylov_update", "krylov_dot", "true_residual"};
+
+hipEvent_t take_event(ProfState &P) {
+    if (!P.spare.empty()) {
+        hipEvent_t e = P.spare.back();
+        P.spare.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    GW_HIP(hipEventCreate(&e));
+    return e;
+}
+
+}  // namespace
+
+const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kNames[id] : "?"; }
+
+bool prof_on() { return prof().on; }
+
+ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_) : id(id_), bytes(bytes_), s(s_) {
+    ProfState &P = prof();
+    if (!P.on) return;
+    std::lock_guard<std::mutex> g(P.mu);
+    e0 = take_event(P);
+    e1 = take_event(P);
+    GW_HIP(hipEventRecord(e0, s));
+}
+
+ProfScope::~ProfScope() {
+    if (!e0) return;
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    if (hipEventRecord(e1, s) != hipSuccess) return;
+    P.pending.push_back({id, bytes, e0, e1});
+}
+
+void prof_flush() {
+    ProfState &P = prof();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (auto &x : P.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(x.e1) == hipSuccess && hipEventElapsedTime(&ms, x.e0, x.e1) == hipSuccess) {
+            P.launches[x.id] += 1;
+            P.ms[x.id] += ms;
+            P.bytes[x.id] += x.bytes;
+        }
+        P.spare.push_back(x.e0);
+        P.spare.push_back(x.e1);
+    }
+    P.pending.clear();
+}
+
+}  // namespace gw
+
+// ------------------------------------------------------------- C entries --
+extern "C" {
+
+const char *gw_last_error(void) { return gw::t_last_error.c_str(); }
+
+int gw_trim(void) {
+    return gw::guarded([&] {
+        GW_HIP(hipDeviceSynchronize());
+        gw::pool_trim();
+        return GW_OK;
+    });
+}
+
+int gw_prof_enable(int32_t on) {
+    return gw::guarded([&] {
+        gw::prof_flush();
+        auto &P = gw::prof();
+        std::lock_guard<std::mutex> g(P.mu);
+        if (on) {
+            std::fill(P.launches, P.launches + gw::K_COUNT, 0);
+            std::fill(P.ms, P.ms + gw::K_COUNT, 0.0);
+            std::fill(P.bytes, P.bytes + gw::K_COUNT, 0.0);
+        }
+        P.on = on != 0;
+        return GW_OK;
+    });
+}
+
+int gw_prof_read(gw_kernel_stat *out, int32_t max, int32_t *n) {
+    return gw::guarded([&] {
+        gw::prof_flush();
+        auto &P = gw::prof();
+        std::lock_guard<std::mutex> g(P.mu);
+        int32_t k = 0;
+        for (int i = 0; i < gw::K_COUNT; ++i) {
+            if (k < max && out) {
+                std::memset(&out[k], 0, sizeof(gw_kernel_stat));
+                std::strncpy(out[k].name, gw::kNames[i], sizeof(out[k].name) - 1);
+                out[k].launches = P.launches[i];
+                out[k].ms = P.ms[i];
+                out[k].bytes = P.bytes[i];
+            }
+            ++k;
+        }
+        if (n) *n = k;
+        return GW_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,935 @@
+// Smoothed-aggregation AMG setup on the device (Introduction: the setup
+// phase builds the grid hierarchy and the transfer operators by nodal
+// aggregation; Results: smoothed aggregation is the coarsening used).
+//
+// Every level is built from deterministic steps, so the hierarchy is
+// bit-reproducible:
+//   strength graph  {i,j} strong <=> a_ij^2 > eps2 a_ii a_jj or a_ji^2 > eps2 a_ii a_jj
+//   MIS-2           synchronous rounds on hash priorities (integer only)
+//   aggregates      roots numbered by index, pass 1 (root neighbours), pass 2
+//   prolongator     P = (I - w D_F^-1 A_F) P_tent, w = (4/3)/Gershgorin bound
+//   Galerkin        A_c = R (A P) with R = P^T, every entry summed in a fixed
+//                   order (AP: ascending k; R(AP): ascending fine row)
+//   coarsest        dense LU with partial pivoting, then its inverse
+// Built with -ffp-contract=off so that a*b+c is never fused.
+#include <algorithm>
+#include <cmath>
+
+#include "gw_device.h"
+#include "gw_internal.h"
+
+namespace gw {
+
+namespace {
+
+constexpr uint32_t ST_OUT = 0, ST_UND = 1, ST_ROOT = 2;
+
+// MurmurHash3 32-bit finalizer (Appleby), host and device.
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+uint32_t level_salt(uint64_t seed, int32_t level) {
+    return fmix32((uint32_t)seed ^ fmix32((uint32_t)(seed >> 32) + 0x9E3779B9u * (uint32_t)(level + 1)));
+}
+
+// Priority key (state rank, hash, index), compared as one uint64; OUT nodes
+// carry 0 (lowest), ROOT outranks UNDECIDED.  Needs i < 2^30.
+__device__ __forceinline__ uint64_t mis_key(uint32_t st, uint32_t salt, int32_t i) {
+    if (st == ST_OUT) return 0ull;
+    return ((uint64_t)st << 62) | ((uint64_t)fmix32((uint32_t)i ^ salt) << 30) | (uint64_t)(uint32_t)i;
+}
+
+// ------------------------------------------------------------ validation --
+// bad bit 1: structure (rowptr, column range/order); bit 2: missing or
+// non-positive diagonal; bit 4: non-finite value.
+__global__ void k_csr_check(CsrView A, double *__restrict__ diag, int32_t *bad, int strict) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i == 0 && (A.rowptr[0] != 0 || (int64_t)A.rowptr[A.n] != A.nnz)) atomicOr(bad, 1);
+    if (i >= A.n) return;
+    int64_t b = A.rowptr[i], e = A.rowptr[i + 1];
+    if (b < 0 || e < b || e > A.nnz) { atomicOr(bad, 1); diag[i] = 0.0; return; }
+    double d = 0.0;
+    bool found = false;
+    int32_t prev = -1;
+    for (int64_t p = b; p < e; ++p) {
+        int32_t c = A.col[p];
+        double v = A.val[p];
+        if (strict) {
+            if (c < 0 || c >= A.ncols || c <= prev) atomicOr(bad, 1);
+            if (!isfinite(v)) atomicOr(bad, 4);
+        }
+        prev = c;
+        if (c == (int32_t)i) { d = v; found = true; }
+    }
+    if (strict && (!found || !(d > 0.0))) atomicOr(bad, 2);
+    diag[i] = d;
+}
+
+// -------------------------------------------------------------- transpose --
+__global__ void k_tr_count(const int32_t *__restrict__ col, int64_t nnz, int32_t *__restrict__ cnt) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[col[p] + 1], 1);
+}
+
+__global__ void k_tr_fill(CsrView A, const int32_t *__restrict__ trow, int32_t *__restrict__ fill,
+                          int32_t *__restrict__ tcol, double *__restrict__ tval, int32_t *__restrict__ rowid) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+        int32_t j = A.col[p];
+        int32_t pos = trow[j] + atomicAdd(&fill[j], 1);
+        tcol[pos] = (int32_t)i;
+        tval[pos] = A.val[p];
+        rowid[pos] = j;
+    }
+}
+
+// Entries of a transposed row arrive in arbitrary order; each entry's final
+// slot is its rank among the (unique) columns of its row.
+__global__ void k_tr_sort(const int32_t *__restrict__ trow, const int32_t *__restrict__ rowid,
+                          const int32_t *__restrict__ tcol, const double *__restrict__ tval, int64_t nnz,
+                          int32_t *__restrict__ ocol, double *__restrict__ oval) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    int32_t j = rowid[e];
+    int32_t key = tcol[e];
+    int32_t b = trow[j], en = trow[j + 1];
+    int32_t rank = 0;
+    for (int32_t u = b; u < en; ++u) rank += tcol[u] < key;
+    ocol[b + rank] = key;
+    oval[b + rank] = tval[e];
+}
+
+// --------------------------------------------------------------- strength --
+// Walk the union of row i of A and row i of A^T (both sorted).
+template <class F>
+__device__ __forceinline__ void union_row(const CsrView &A, const CsrView &T, int32_t i, F &&f) {
+    int32_t pa = A.rowptr[i], ea = A.rowptr[i + 1];
+    int32_t pt = T.rowptr[i], et = T.rowptr[i + 1];
+    while (pa < ea || pt < et) {
+        int32_t ja = pa < ea ? A.col[pa] : INT32_MAX;
+        int32_t jt = pt < et ? T.col[pt] : INT32_MAX;
+        int32_t j = ja < jt ? ja : jt;
+        double aij = 0.0, aji = 0.0;
+        int32_t posa = -1;
+        if (ja == j) { aij = A.val[pa]; posa = pa; ++pa; }
+        if (jt == j) { aji = T.val[pt]; ++pt; }
+        f(j, aij, aji, posa);
+    }
+}
+
+__device__ __forceinline__ bool strong_pair(double aij, double aji, double di, double dj, double eps2) {
+    double dd = di * dj;
+    return (aij * aij > eps2 * dd) || (aji * aji > eps2 * dd);
+}
+
+__global__ void k_strength_count(CsrView A, CsrView T, const double *__restrict__ diag, double eps2,
+                                 int32_t *__restrict__ cnt) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const double di = diag[i];
+    int32_t c = 0;
+    union_row(A, T, (int32_t)i, [&](int32_t j, double aij, double aji, int32_t) {
+        if (j != (int32_t)i && strong_pair(aij, aji, di, diag[j], eps2)) ++c;
+    });
+    cnt[i + 1] = c;
+}
+
+__global__ void k_strength_fill(CsrView A, CsrView T, const double *__restrict__ diag, double eps2,
+                                const int32_t *__restrict__ srow, int32_t *__restrict__ scol,
+                                double *__restrict__ sw, uint8_t *__restrict__ strongA,
+                                double *__restrict__ dF) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const double di = diag[i];
+    int32_t q = srow[i];
+    double lump = di;  // a_ii + weak off-diagonals in ascending column order
+    union_row(A, T, (int32_t)i, [&](int32_t j, double aij, double aji, int32_t posa) {
+        if (j == (int32_t)i) {
+            if (posa >= 0) strongA[posa] = 0;
+            return;
+        }
+        bool s = strong_pair(aij, aji, di, diag[j], eps2);
+        if (posa >= 0) {
+            strongA[posa] = s ? 1 : 0;
+            if (!s) lump = lump + aij;
+        }
+        if (s) {
+            scol[q] = j;
+            double x = fabs(aij), y = fabs(aji);
+            sw[q] = x > y ? x : y;
+            ++q;
+        }
+    });
+    dF[i] = lump;
+}
+
+// ------------------------------------------------------------------ MIS-2 --
+__global__ void k_mis_init(const int32_t *__restrict__ srow, int32_t n, uint32_t *__restrict__ state,
+                           int32_t *und) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t c = 0;
+    if (i < n) {
+        bool kept = srow[i + 1] > srow[i];
+        state[i] = kept ? ST_UND : ST_OUT;
+        c = kept;
+    }
+    c = dev::wave_sum(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(und, c);
+}
+
+// m1_i = max(key_i, max_{j in S(i)} key_j).  Skipped once a previous round
+// left nothing undecided.
+__global__ void k_mis_m1(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
+                         const uint32_t *__restrict__ state, uint32_t salt, uint64_t *__restrict__ m1,
+                         const int32_t *prev_und) {
+    if (*prev_und == 0) return;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t m = mis_key(state[i], salt, (int32_t)i);
+    for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
+        int32_t j = scol[p];
+        uint64_t kj = mis_key(state[j], salt, j);
+        m = kj > m ? kj : m;
+    }
+    m1[i] = m;
+}
+
+// m2_i = max(m1_i, max_j m1_j); UNDECIDED i becomes ROOT if m2_i is its own
+// key, OUT if m2_i belongs to a ROOT.  Counts the nodes left undecided.
+__global__ void k_mis_m2(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
+                         uint32_t *__restrict__ state, uint32_t salt, const uint64_t *__restrict__ m1,
+                         const int32_t *prev_und, int32_t *und) {
+    if (*prev_und == 0) return;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t left = 0;
+    if (i < n && state[i] == ST_UND) {
+        uint64_t m = m1[i];
+        for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
+            uint64_t v = m1[scol[p]];
+            m = v > m ? v : m;
+        }
+        if (m == mis_key(ST_UND, salt, (int32_t)i)) state[i] = ST_ROOT;
+        else if ((m >> 62) == ST_ROOT) state[i] = ST_OUT;
+        else left = 1;
+    }
+    left = dev::wave_sum(left);
+    if ((threadIdx.x & 63) == 0 && left) atomicAdd(und, left);
+}
+
+// ------------------------------------------------------------- aggregates --
+__global__ void k_root_flags(const uint32_t *__restrict__ state, int32_t n, int32_t *__restrict__ flag) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) flag[i + 1] = state[i] == ST_ROOT ? 1 : 0;
+    if (i == 0) flag[0] = 0;
+}
+
+__global__ void k_agg_pass1(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
+                            const uint32_t *__restrict__ state, const int32_t *__restrict__ ids,
+                            int32_t *__restrict__ agg1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t a = -1;
+    if (state[i] == ST_ROOT) {
+        a = ids[i];
+    } else {
+        for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
+            int32_t j = scol[p];
+            if (state[j] == ST_ROOT) { a = ids[j]; break; }
+        }
+    }
+    agg1[i] = a;
+}
+
+__global__ void k_agg_pass2(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol,
+                            const double *__restrict__ sw, int32_t n, const int32_t *__restrict__ agg1,
+                            int32_t *__restrict__ agg) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t a = agg1[i];
+    if (a < 0 && srow[i + 1] > srow[i]) {
+        double best_w = -1.0;
+        int32_t best = -1;
+        for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
+            int32_t c = agg1[scol[p]];
+            if (c < 0) continue;
+            double w = sw[p];
+            if (w > best_w || (w == best_w && c < best)) { best_w = w; best = c; }
+        }
+        a = best;
+    }
+    agg[i] = a;
+}
+
+// ----------------------------------------------------- prolongator weight --
+// rho = max_i (sum_j |a_ij|, ascending j) / a_ii; positive doubles order like
+// their bit patterns, so an integer atomicMax is exact.
+__global__ void k_rho(CsrView A, const double *__restrict__ diag, unsigned long long *rho_bits) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double r = 0.0;
+    if (i < A.n) {
+        double s = 0.0;
+        for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s = s + fabs(A.val[p]);
+        r = s / diag[i];
+    }
+    r = dev::wave_max(r);
+    if ((threadIdx.x & 63) == 0) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(r));
+}
+
+__global__ void k_omega(const unsigned long long *rho_bits, double *omega) {
+    if (threadIdx.x == 0) *omega = (4.0 / 3.0) / __longlong_as_double((long long)*rho_bits);
+}
+
+// ------------------------------------------------------- hashed SpGEMM ----
+// Output row i is the stream, over the A-side entries (k, a) of row i in
+// ascending order, of the B-row entries (J, b): contribution a*b to column J.
+// G lanes own one output row and an LDS hash table; the entries of one B row
+// have distinct columns, so the lanes can add them concurrently while B rows
+// are taken one after another: every output entry is then accumulated left to
+// right in stream order, exactly like a sequential dense accumulator.
+
+struct ARowCsr {
+    const int32_t *rowptr, *col;
+    const double *val;
+    __device__ int32_t begin(int32_t i) const { return rowptr[i]; }
+    __device__ int32_t end(int32_t i) const { return rowptr[i + 1]; }
+    __device__ bool get(int32_t p, int32_t, int32_t &k, double &a) const {
+        k = col[p];
+        a = val[p];
+        return true;
+    }
+};
+
+// Filtered operator A_F: diagonal replaced by the lumped dF, weak
+// off-diagonals dropped.
+struct ARowFiltered {
+    const int32_t *rowptr, *col;
+    const double *val;
+    const uint8_t *strong;
+    const double *dF;
+    __device__ int32_t begin(int32_t i) const { return rowptr[i]; }
+    __device__ int32_t end(int32_t i) const { return rowptr[i + 1]; }
+    __device__ bool get(int32_t p, int32_t i, int32_t &k, double &a) const {
+        k = col[p];
+        if (k != i && !strong[p]) return false;
+        a = (k == i) ? dF[i] : val[p];
+        return true;
+    }
+};
+
+struct BCsr {
+    const int32_t *rowptr, *col;
+    const double *val;
+    __device__ void row(int32_t k, int32_t &base, int32_t &len) const {
+        base = rowptr[k];
+        len = rowptr[k + 1] - base;
+    }
+    __device__ void get(int32_t base, int32_t t, int32_t &J, double &b) const {
+        J = col[base + t];
+        b = val[base + t];
+    }
+};
+
+// Tentative prolongator: row k has the single entry 1 at column agg(k).
+struct BTent {
+    const int32_t *agg;
+    __device__ void row(int32_t k, int32_t &base, int32_t &len) const {
+        base = agg[k];
+        len = base >= 0 ? 1 : 0;
+    }
+    __device__ void get(int32_t base, int32_t, int32_t &J, double &b) const {
+        J = base;
+        b = 1.0;
+    }
+};
+
+struct EpiIdentity {
+    __device__ double operator()(int32_t, int32_t, double s) const { return s; }
+};
+
+// P_iI = [agg(i) == I] - (w / d_i) s_I with d_i = dF_i if positive else a_ii.
+struct EpiSmoothP {
+    const int32_t *agg;
+    const double *dF, *diag;
+    const double *omega;
+    __device__ double operator()(int32_t i, int32_t J, double s) const {
+        double di = dF[i] > 0.0 ? dF[i] : diag[i];
+        double coef = *omega / di;
+        double delta = (agg[i] == J) ? 1.0 : 0.0;
+        return delta - coef * s;
+    }
+};
+
+// Upper bound of the distinct columns of each output row.
+template <class AR, class BR>
+__global__ void k_spgemm_ub(AR ar, BR br, int32_t nrows, int32_t *ub_max) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t u = 0;
+    if (i < nrows) {
+        for (int32_t p = ar.begin((int32_t)i); p < ar.end((int32_t)i); ++p) {
+            int32_t k, base, len;
+            double a;
+            if (!ar.get(p, (int32_t)i, k, a)) continue;
+            br.row(k, base, len);
+            u += len;
+        }
+    }
+    u = dev::wave_max(u);
+    if ((threadIdx.x & 63) == 0) atomicMax(ub_max, u);
+}
+
+__device__ __forceinline__ int32_t hash_slot(int32_t *keys, int hbits, int32_t J, bool &fresh) {
+    const int32_t H = 1 << hbits;
+    uint32_t h = ((uint32_t)J * 2654435761u) >> (32 - hbits);
+    for (int32_t probe = 0; probe < H; ++probe) {
+        int32_t old = atomicCAS(&keys[h], -1, J);
+        if (old == -1) { fresh = true; return (int32_t)h; }
+        if (old == J) { fresh = false; return (int32_t)h; }
+        h = (h + 1) & (uint32_t)(H - 1);
+    }
+    fresh = false;
+    return -1;
+}
+
+template <int G>
+__device__ __forceinline__ int32_t group_sum(int32_t v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, dev::kWave);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int32_t group_max(int32_t v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        int32_t w = __shfl_xor(v, o, dev::kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int G, class AR, class BR>
+__global__ void k_spgemm_sym(AR ar, BR br, int32_t nrows, int hbits, int32_t *__restrict__ cnt,
+                             int32_t *maxd, int32_t *overflow) {
+    extern __shared__ int32_t sm_keys[];
+    const int32_t H = 1 << hbits;
+    const int group = threadIdx.x / G, lane = threadIdx.x % G;
+    const int groups = blockDim.x / G;
+    int32_t *keys = sm_keys + (size_t)group * H;
+    const int64_t row = (int64_t)blockIdx.x * groups + group;
+    const bool active = row < nrows;
+    for (int32_t s = lane; s < H; s += G) keys[s] = -1;
+    __syncthreads();
+    int32_t fresh_count = 0;
+    bool ovf = false;
+    if (active) {
+        const int32_t i = (int32_t)row;
+        for (int32_t p = ar.begin(i); p < ar.end(i); ++p) {
+            int32_t k, base, len;
+            double a;
+            if (!ar.get(p, i, k, a)) continue;
+            br.row(k, base, len);
+            for (int32_t t = lane; t < len; t += G) {
+                int32_t J;
+                double b;
+                br.get(base, t, J, b);
+                bool fresh;
+                if (hash_slot(keys, hbits, J, fresh) < 0) ovf = true;
+                fresh_count += fresh;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    int32_t tot = group_sum<G>(fresh_count);
+    if (active && lane == 0) {
+        cnt[row + 1] = tot;
+        atomicMax(maxd, tot);
+    }
+    if (ovf) atomicOr(overflow, 1);
+}
+
+template <int G, class AR, class BR, class EPI>
+__global__ void k_spgemm_num(AR ar, BR br, int32_t nrows, int hbits, const int32_t *__restrict__ crow,
+                             int32_t *__restrict__ ccol, double *__restrict__ cval, EPI epi,
+                             int32_t *overflow) {
+    extern __shared__ int32_t sm_keys[];
+    const int32_t H = 1 << hbits;
+    const int group = threadIdx.x / G, lane = threadIdx.x % G;
+    const int groups = blockDim.x / G;
+    int32_t *keys = sm_keys + (size_t)group * H;
+    double *vals = reinterpret_cast<double *>(sm_keys + (size_t)groups * H) + (size_t)group * H;
+    const int64_t row = (int64_t)blockIdx.x * groups + group;
+    const bool active = row < nrows;
+    for (int32_t s = lane; s < H; s += G) {
+        keys[s] = -1;
+        vals[s] = 0.0;
+    }
+    __syncthreads();
+    bool ovf = false;
+    if (active) {
+        const int32_t i = (int32_t)row;
+        for (int32_t p = ar.begin(i); p < ar.end(i); ++p) {
+            int32_t k, base, len;
+            double a;
+            if (!ar.get(p, i, k, a)) continue;
+            br.row(k, base, len);
+            for (int32_t t = lane; t < len; t += G) {
+                int32_t J;
+                double b;
+                br.get(base, t, J, b);
+                bool fresh;
+                int32_t h = hash_slot(keys, hbits, J, fresh);
+                if (h < 0) { ovf = true; continue; }
+                vals[h] = vals[h] + a * b;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    if (active) {
+        const int32_t i = (int32_t)row;
+        const int32_t out0 = crow[i];
+        for (int32_t s = lane; s < H; s += G) {
+            int32_t J = keys[s];
+            if (J < 0) continue;
+            int32_t rank = 0;
+            for (int32_t u = 0; u < H; ++u) {
+                int32_t K2 = keys[u];
+                rank += (K2 >= 0 && K2 < J);
+            }
+            ccol[out0 + rank] = J;
+            cval[out0 + rank] = epi(i, J, vals[s]);
+        }
+    }
+    if (ovf) atomicOr(overflow, 1);
+}
+
+// -------------------------------------------------------------- smoother --
+__global__ void k_smoother_diag(CsrView A, const double *__restrict__ diag, int spai0, double omega,
+                                double *__restrict__ M) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double aii = diag[i];
+    if (spai0) {
+        double s = 0.0;
+        for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s = s + A.val[p] * A.val[p];
+        M[i] = aii / s;
+    } else {
+        M[i] = omega / aii;
+    }
+}
+
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
+// ------------------------------------------------------------- coarse LU --
+__global__ void k_csr_to_dense(CsrView A, double *__restrict__ a) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    for (int32_t c = 0; c < A.n; ++c) a[i * A.n + c] = 0.0;
+    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) a[i * A.n + A.col[p]] = A.val[p];
+}
+
+// Right-looking LU with partial pivoting in one workgroup (LAPACK getrf
+// order: the first row holding the largest |a_ik| is the pivot).
+__global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32_t n, int32_t *__restrict__ piv,
+                                                   int32_t *status) {
+    __shared__ double sv[16];
+    __shared__ int32_t si[16];
+    __shared__ int32_t p_sh;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    for (int32_t k = 0; k < n; ++k) {
+        double best = -1.0;
+        int32_t bi = n;
+        for (int32_t i = k + tid; i < n; i += blockDim.x) {
+            double v = fabs(a[(int64_t)i * n + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            double v2 = __shfl_xor(best, o, 64);
+            int32_t i2 = __shfl_xor(bi, o, 64);
+            if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+        }
+        if (lane == 0) { sv[w] = best; si[w] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = sv[0];
+            int32_t ix = si[0];
+            for (int q = 1; q < nw; ++q)
+                if (sv[q] > b || (sv[q] == b && si[q] < ix)) { b = sv[q]; ix = si[q]; }
+            p_sh = (b == 0.0) ? -1 : ix;
+            piv[k] = ix;
+        }
+        __syncthreads();
+        const int32_t p = p_sh;
+        if (p < 0) {
+            if (tid == 0) *status = GW_SINGULAR;
+            return;
+        }
+        if (p != k)
+            for (int32_t j = tid; j < n; j += blockDim.x) {
+                double t = a[(int64_t)k * n + j];
+                a[(int64_t)k * n + j] = a[(int64_t)p * n + j];
+                a[(int64_t)p * n + j] = t;
+            }
+        __syncthreads();
+        const double akk = a[(int64_t)k * n + k];
+        for (int32_t i = k + 1 + tid; i < n; i += blockDim.x) a[(int64_t)i * n + k] = a[(int64_t)i * n + k] / akk;
+        __syncthreads();
+        const int32_t m = n - k - 1;
+        for (int64_t e = tid; e < (int64_t)m * m; e += blockDim.x) {
+            int32_t i = k + 1 + (int32_t)(e / m), j = k + 1 + (int32_t)(e % m);
+            a[(int64_t)i * n + j] = a[(int64_t)i * n + j] - a[(int64_t)i * n + k] * a[(int64_t)k * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+// Column c of the inverse: solve L U x = Perm e_c.  inv is column-major.
+__global__ void k_lu_inverse(const double *__restrict__ lu, const int32_t *__restrict__ piv, int32_t n,
+                             double *__restrict__ inv) {
+    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double *x = inv + (int64_t)c * n;
+    for (int32_t i = 0; i < n; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+    for (int32_t k = 0; k < n; ++k)
+        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
+    for (int32_t i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int32_t j = 0; j < i; ++j) s = s - lu[(int64_t)i * n + j] * x[j];
+        x[i] = s;
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int32_t j = i + 1; j < n; ++j) s = s - lu[(int64_t)i * n + j] * x[j];
+        x[i] = s / lu[(int64_t)i * n + i];
+    }
+}
+
+// ------------------------------------------------------------ host side --
+
+struct Staging {
+    Pinned pin{256};
+    template <class T>
+    T read(const T *d, hipStream_t s) {
+        GW_HIP(hipMemcpyAsync(pin.p, d, sizeof(T), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        T v;
+        std::memcpy(&v, pin.p, sizeof(T));
+        return v;
+    }
+};
+
+int pow2_bits_at_least(int64_t v) {
+    int b = 4;
+    while (b < 30 && ((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+constexpr int kMaxHashBits = 12;  // 4096 slots per output row
+
+// C = (A-side) x (B-side) with fixed summation order; C has `ncols` columns.
+template <class AR, class BR, class EPI>
+void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, int avg_b_len, EPI epi, Csr &C, hipStream_t s,
+            Staging &st) {
+    DBuf<int32_t> ctr(4);  // ub_max, maxd, overflow
+    fill_i32(ctr.p, 0, 4, s);
+    {
+        ProfScope ps(K_SPGEMM, 0, s);
+        hipLaunchKernelGGL((k_spgemm_ub<AR, BR>), dim3(blocks_for(nrows)), dim3(kBlock), 0, s, ar, br, nrows, ctr.p);
+    }
+    int32_t ub = st.read(ctr.p, s);
+    int64_t cap = std::min<int64_t>(ub, ncols);
+    int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
+    C.alloc(nrows, ncols, 0);
+    fill_i32(C.rowptr.p, 0, (int64_t)nrows + 1, s);
+    auto launch = [&](auto kern_sel, int G, size_t bytes_per_slot, int hbits) {
+        const size_t H = (size_t)1 << hbits;
+        int groups = (int)std::min<size_t>(kBlock / G, std::max<size_t>(1, (48 * 1024) / (H * bytes_per_slot)));
+        unsigned grid = (unsigned)((nrows + groups - 1) / groups);
+        if (grid == 0) grid = 1;
+        kern_sel(dim3(grid), dim3(groups * G), groups * H * bytes_per_slot);
+    };
+    const int G = avg_b_len <= 1 ? 1 : (avg_b_len <= 6 ? 4 : (avg_b_len <= 24 ? 16 : 64));
+    {
+        ProfScope ps(K_SPGEMM, 0, s);
+        auto sym = [&](dim3 g, dim3 b, size_t sh) {
+            switch (G) {
+                case 1: hipLaunchKernelGGL((k_spgemm_sym<1, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
+                case 4: hipLaunchKernelGGL((k_spgemm_sym<4, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
+                case 16: hipLaunchKernelGGL((k_spgemm_sym<16, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
+                default: hipLaunchKernelGGL((k_spgemm_sym<64, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
+            }
+        };
+        launch(sym, G, 4, hb);
+        GW_HIP(hipGetLastError());
+    }
+    DBuf<int64_t> total(1);
+    scan_inclusive_i32(C.rowptr.p + 1, nrows, total.p, s);
+    int64_t nnz = st.read(total.p, s);
+    int32_t maxd = st.read(ctr.p + 1, s);
+    int32_t ovf = st.read(ctr.p + 2, s);
+    if (ovf) fail(GW_EINVAL, "amg_setup: a Galerkin row has more than 4096 distinct columns");
+    GW_REQUIRE(nnz < INT32_MAX, "amg_setup: operator exceeds 2^31 nonzeros");
+    C.nnz = nnz;
+    C.col.alloc((size_t)nnz);
+    C.val.alloc((size_t)nnz);
+    int hbn = std::min(pow2_bits_at_least(2 * std::max<int32_t>(maxd, 1)), kMaxHashBits);
+    {
+        ProfScope ps(K_SPGEMM, 0, s);
+        auto num = [&](dim3 g, dim3 b, size_t sh) {
+            switch (G) {
+                case 1: hipLaunchKernelGGL((k_spgemm_num<1, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
+                case 4: hipLaunchKernelGGL((k_spgemm_num<4, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
+                case 16: hipLaunchKernelGGL((k_spgemm_num<16, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
+                default: hipLaunchKernelGGL((k_spgemm_num<64, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
+            }
+        };
+        launch(num, G, 12, hbn);
+        GW_HIP(hipGetLastError());
+    }
+}
+
+void csr_diag(const CsrView &A, double *diag, hipStream_t s) {
+    DBuf<int32_t> bad(1);
+    fill_i32(bad.p, 0, 1, s);
+    hipLaunchKernelGGL(k_csr_check, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag, bad.p, 0);
+    GW_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_csr_check(const CsrView &A, double *diag, int32_t *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_check, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag, bad, 1);
+    GW_HIP(hipGetLastError());
+}
+
+void transpose(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total) {
+    ProfScope ps(K_TRANSPOSE, (double)A.nnz * 36, s);
+    T.alloc(A.ncols, A.n, A.nnz);
+    fill_i32(T.rowptr.p, 0, (int64_t)A.ncols + 1, s);
+    if (A.nnz > 0) {
+        unsigned g = std::min<unsigned>(blocks_for(A.nnz, 4), 65536);
+        hipLaunchKernelGGL(k_tr_count, dim3(g), dim3(kBlock), 0, s, A.col, A.nnz, T.rowptr.p);
+    }
+    scan_inclusive_i32(T.rowptr.p + 1, A.ncols, scratch_total, s);
+    DBuf<int32_t> fill((size_t)A.ncols + 1), rowid((size_t)std::max<int64_t>(A.nnz, 1)),
+        tcol((size_t)std::max<int64_t>(A.nnz, 1));
+    DBuf<double> tval((size_t)std::max<int64_t>(A.nnz, 1));
+    fill_i32(fill.p, 0, A.ncols, s);
+    hipLaunchKernelGGL(k_tr_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, T.rowptr.p, fill.p, tcol.p,
+                       tval.p, rowid.p);
+    if (A.nnz > 0)
+        hipLaunchKernelGGL(k_tr_sort, dim3(blocks_for(A.nnz)), dim3(kBlock), 0, s, T.rowptr.p, rowid.p, tcol.p,
+                           tval.p, A.nnz, T.col.p, T.val.p);
+    GW_HIP(hipGetLastError());
+}
+
+// Build level l+1 from level l, or mark l as the coarsest.  Returns through
+// *is_coarsest whether level l ended the hierarchy.
+void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
+    Staging st;
+    Level &Lv = H->L[l];
+    const int32_t n = Lv.A.n;
+    const amg_params &prm = H->prm;
+    const int maxl = std::max(1, std::min(prm.max_levels, 32));
+    *is_coarsest = false;
+    if (n <= prm.n_coarse || l == maxl - 1) {
+        *is_coarsest = true;
+        return;
+    }
+    GW_REQUIRE(n < (1 << 30), "amg_setup: at most 2^30 rows per level");
+    const CsrView A = view(Lv.A);
+    double eps2 = prm.eps_strong * prm.eps_strong;
+    for (int k = 0; k < l; ++k) eps2 = eps2 * 0.25;
+
+    DBuf<double> diag(n), dF(n), sw;
+    DBuf<int64_t> total(1);
+    csr_diag(A, diag.p, s);
+
+    // strength graph on A and A^T
+    Csr T;
+    transpose(A, T, s, total.p);
+    Csr S;  // pattern only: col + weights in sw
+    S.n = S.ncols = n;
+    S.rowptr.alloc((size_t)n + 1);
+    fill_i32(S.rowptr.p, 0, 1, s);
+    DBuf<uint8_t> strongA((size_t)std::max<int64_t>(A.nnz, 1));
+    {
+        ProfScope ps(K_STRENGTH, (double)A.nnz * 24 + n * 16.0, s);
+        hipLaunchKernelGGL(k_strength_count, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, view(T), diag.p, eps2,
+                           S.rowptr.p);
+        GW_HIP(hipGetLastError());
+    }
+    scan_inclusive_i32(S.rowptr.p + 1, n, total.p, s);
+    S.nnz = st.read(total.p, s);
+    S.col.alloc((size_t)std::max<int64_t>(S.nnz, 1));
+    sw.alloc((size_t)std::max<int64_t>(S.nnz, 1));
+    {
+        ProfScope ps(K_STRENGTH, (double)A.nnz * 25 + n * 24.0 + S.nnz * 12.0, s);
+        hipLaunchKernelGGL(k_strength_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, view(T), diag.p, eps2,
+                           S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p);
+        GW_HIP(hipGetLastError());
+    }
+    T = Csr();
+    Lv.nnz_s = S.nnz;
+
+    // MIS-2 rounds, batched between host checks; a round after the last
+    // decision is a no-op
+    DBuf<uint32_t> state(n);
+    DBuf<uint64_t> m1(n);
+    constexpr int kMaxRounds = 4096, kBatch = 8;
+    DBuf<int32_t> und(kMaxRounds + 1);
+    fill_i32(und.p, 0, kMaxRounds + 1, s);
+    const uint32_t salt = level_salt(prm.seed, l);
+    {
+        ProfScope ps(K_MIS2, n * 8.0, s);
+        hipLaunchKernelGGL(k_mis_init, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, n, state.p, und.p);
+        GW_HIP(hipGetLastError());
+    }
+    int rounds = 0;
+    int32_t left = st.read(und.p, s);
+    while (left > 0) {
+        GW_REQUIRE(rounds + kBatch <= kMaxRounds, "amg_setup: MIS-2 did not terminate");
+        for (int b = 0; b < kBatch; ++b) {
+            int r = rounds + b;
+            ProfScope ps(K_MIS2, (double)S.nnz * 8 + n * 20.0, s);
+            hipLaunchKernelGGL(k_mis_m1, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p,
+                               salt, m1.p, und.p + r);
+            hipLaunchKernelGGL(k_mis_m2, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p,
+                               salt, m1.p, und.p + r, und.p + r + 1);
+        }
+        GW_HIP(hipGetLastError());
+        std::vector<int32_t> h(kBatch);
+        GW_HIP(hipMemcpyAsync(st.pin.p, und.p + rounds + 1, kBatch * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        std::memcpy(h.data(), st.pin.p, kBatch * sizeof(int32_t));
+        int b = 0;
+        while (b < kBatch && h[b] > 0) ++b;
+        if (b < kBatch) {
+            rounds += b + 1;
+            left = 0;
+        } else {
+            rounds += kBatch;
+            left = h[kBatch - 1];
+        }
+    }
+    Lv.mis_rounds = rounds;
+    m1.release();
+
+    // aggregates
+    DBuf<int32_t> ids((size_t)n + 1), agg1(n);
+    Lv.agg.alloc(n);
+    {
+        ProfScope ps(K_AGGREGATE, (double)S.nnz * 16 + n * 24.0, s);
+        hipLaunchKernelGGL(k_root_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, state.p, n, ids.p);
+        scan_inclusive_i32(ids.p + 1, n, total.p, s);
+        hipLaunchKernelGGL(k_agg_pass1, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p,
+                           ids.p, agg1.p);
+        hipLaunchKernelGGL(k_agg_pass2, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, sw.p, n,
+                           agg1.p, Lv.agg.p);
+        GW_HIP(hipGetLastError());
+    }
+    const int64_t nc = st.read(total.p, s);
+    Lv.nc = (int32_t)nc;
+    if (nc == 0 || (double)nc > 0.9 * (double)n) {
+        *is_coarsest = true;
+        Lv.agg.release();
+        Lv.nc = 0;
+        return;
+    }
+
+    // smoothed prolongator
+    DBuf<unsigned long long> rho_bits(1);
+    DBuf<double> omega(1);
+    GW_HIP(hipMemsetAsync(rho_bits.p, 0, sizeof(unsigned long long), s));
+    {
+        ProfScope ps(K_SETUP_MISC, (double)A.nnz * 8 + n * 8.0, s);
+        hipLaunchKernelGGL(k_rho, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, diag.p, rho_bits.p);
+        hipLaunchKernelGGL(k_omega, dim3(1), dim3(64), 0, s, rho_bits.p, omega.p);
+        GW_HIP(hipGetLastError());
+    }
+    ARowFiltered af{A.rowptr, A.col, A.val, strongA.p, dF.p};
+    BTent bt{Lv.agg.p};
+    EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
+    spgemm(af, bt, n, (int32_t)nc, 1, ep, Lv.P, s, st);
+    Lv.omega_p = st.read(omega.p, s);
+
+    // R = P^T, A_c = R (A P)
+    transpose(view(Lv.P), Lv.R, s, total.p);
+    Csr AP;
+    const int pavg = (int)std::max<int64_t>(1, Lv.P.nnz / std::max<int32_t>(n, 1));
+    spgemm(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p}, n, (int32_t)nc,
+           pavg + 1, EpiIdentity{}, AP, s, st);
+    Level &Nx = H->L[l + 1];
+    const int apavg = (int)std::max<int64_t>(1, AP.nnz / std::max<int32_t>(n, 1));
+    spgemm(ARowCsr{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p}, BCsr{AP.rowptr.p, AP.col.p, AP.val.p}, (int32_t)nc,
+           (int32_t)nc, apavg, EpiIdentity{}, Nx.A, s, st);
+    GW_HIP(hipStreamSynchronize(s));
+}
+
+void make_smoother(amg_hierarchy *H, int l, hipStream_t s) {
+    Level &Lv = H->L[l];
+    const CsrView A = view(Lv.A);
+    DBuf<double> diag(A.n);
+    csr_diag(A, diag.p, s);
+    Lv.M.alloc(A.n);
+    ProfScope ps(K_SETUP_MISC, (double)A.nnz * 12 + A.n * 16.0, s);
+    hipLaunchKernelGGL(k_smoother_diag, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag.p,
+                       H->prm.smoother == GW_SMOOTHER_SPAI0 ? 1 : 0, H->prm.omega, Lv.M.p);
+    GW_HIP(hipGetLastError());
+    GW_HIP(hipStreamSynchronize(s));
+}
+
+void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s) {
+    Level &Lv = H->L[l];
+    auto conv = [&](const DBuf<double> &x, DBuf<float> &y) {
+        y.alloc(x.n);
+        if (!x.n) return;
+        unsigned g = std::min<unsigned>(blocks_for((int64_t)x.n, 4), 65536);
+        hipLaunchKernelGGL(k_to_f32, dim3(g), dim3(kBlock), 0, s, x.p, y.p, (int64_t)x.n);
+    };
+    conv(Lv.A.val, Lv.A.val32);
+    if (Lv.P.n) conv(Lv.P.val, Lv.P.val32);
+    if (Lv.R.n) conv(Lv.R.val, Lv.R.val32);
+    if (Lv.M.n) conv(Lv.M, Lv.M32);
+    GW_HIP(hipGetLastError());
+    GW_HIP(hipStreamSynchronize(s));
+}
+
+void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
+    Level &Lv = H->L[l];
+    const int32_t n = Lv.A.n;
+    GW_REQUIRE(n <= 2048, "amg_setup: coarsening stalled at " + std::to_string(n) + " rows (> 2048)");
+    H->nd = n;
+    H->lu.alloc((size_t)n * n);
+    H->inv.alloc((size_t)n * n);
+    H->piv.alloc(n);
+    DBuf<int32_t> status(1);
+    fill_i32(status.p, 0, 1, s);
+    {
+        ProfScope ps(K_COARSE_LU, (double)n * n * 24, s);
+        hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, s, view(Lv.A), H->lu.p);
+        hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(1024), 0, s, H->lu.p, n, H->piv.p, status.p);
+        GW_HIP(hipGetLastError());
+    }
+    Staging st;
+    if (st.read(status.p, s) != 0) fail(GW_SINGULAR, "amg_setup: zero pivot in the coarsest-level LU");
+    {
+        ProfScope ps(K_COARSE_LU, (double)n * n * 16, s);
+        hipLaunchKernelGGL(k_lu_inverse, dim3(blocks_for(n, 1, 64)), dim3(64), 0, s, H->lu.p, H->piv.p, n, H->inv.p);
+        GW_HIP(hipGetLastError());
+    }
+    GW_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace gw

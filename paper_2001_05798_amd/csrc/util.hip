@@ -1,0 +1,120 @@
+// Device-wide inclusive scan of int32 counts (used to turn row lengths into
+// CSR row pointers and flags into ids) and small fill/copy helpers.
+#include "gw_device.h"
+#include "gw_internal.h"
+
+namespace gw {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tile_sums(const int32_t *a, int64_t n, int64_t *bs) {
+    __shared__ int64_t sm[kScanThreads / dev::kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) s += a[i];
+    }
+    s = dev::block_sum(s, sm);
+    if (threadIdx.x == 0) bs[blockIdx.x] = s;
+}
+
+// Exclusive scan of the tile sums in one block; the grand total goes to *total.
+__global__ void __launch_bounds__(1024) k_scan_tile_offsets(int64_t *bs, int64_t nb, int64_t *total) {
+    __shared__ int64_t wsum[1024 / dev::kWave];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t base = 0; base < nb; base += blockDim.x) {
+        int64_t i = base + threadIdx.x;
+        int64_t v = i < nb ? bs[i] : 0;
+        int64_t inc = dev::wave_scan_incl(v);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int64_t off = carry;
+        for (int k = 0; k < w; ++k) off += wsum[k];
+        if (i < nb) bs[i] = off + inc - v;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry = off + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(int32_t *a, int64_t n, const int64_t *bs) {
+    __shared__ int64_t wsum[kScanThreads / dev::kWave];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        s += (i < n) ? a[i] : 0;
+        v[k] = s;
+    }
+    int64_t inc = dev::wave_scan_incl(s);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int64_t off = bs[blockIdx.x];
+    for (int k = 0; k < w; ++k) off += wsum[k];
+    off += inc - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) a[i] = (int32_t)(off + v[k]);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *a, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+__global__ void k_fill_f64(double *a, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+}  // namespace
+
+void scan_inclusive_i32(int32_t *a, int64_t n, int64_t *total, hipStream_t s) {
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_fill_f64, 1, 1, 0, s, reinterpret_cast<double *>(total), 0.0, 1);
+        GW_HIP(hipGetLastError());
+        return;
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    DBuf<int64_t> bs((size_t)nb);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, bs.p);
+    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(1024), 0, s, bs.p, nb, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, bs.p);
+    GW_HIP(hipGetLastError());
+}
+
+void fill_i32(int32_t *a, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = blocks_for(n, 4);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_i32, dim3(g), dim3(kBlock), 0, s, a, v, n);
+    GW_HIP(hipGetLastError());
+}
+
+void fill_f64(double *a, double v, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = blocks_for(n, 4);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_fill_f64, dim3(g), dim3(kBlock), 0, s, a, v, n);
+    GW_HIP(hipGetLastError());
+}
+
+void copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    if (bytes) GW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace gw

@@ -1,0 +1,53 @@
+"""CPU checks of the C ABI: the library loads and exports every function the
+header declares; argument validation happens before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gwamg.h")
+LIB = os.path.join(ROOT, "paper_2001_05798_amd", "libgwamg.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["fv_assemble", "amg_setup", "amg_solve_pcg", "amg_solve_bicgstab", "tt_solve",
+              "queue_submit", "queue_poll", "darcy_flux", "amg_free", "gw_last_error"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_side_validation_without_device():
+    # these calls fail on their arguments before touching HIP
+    lib = ctypes.CDLL(LIB)
+    lib.fv_nnz.restype = ctypes.c_int64
+    lib.gw_last_error.restype = ctypes.c_char_p
+    lib.gw_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.gw_version()
+
+    class Grid(ctypes.Structure):
+        _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                    ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+    assert lib.fv_nnz(ctypes.byref(Grid(550, 500, 10, 1, 1, 1))) == 18_679_000
+    assert lib.fv_nnz(ctypes.byref(Grid(0, 5, 5, 1, 1, 1))) == -1
+    rc = lib.fv_assemble(ctypes.byref(Grid(-1, 2, 2, 1, 1, 1)), None, None, None, 0, None, None, None, None, None)
+    assert rc == -1 and b"grid" in lib.gw_last_error()
+    rc = lib.amg_setup(None, None, None, None)
+    assert rc == -1

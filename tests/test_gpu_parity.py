@@ -1,0 +1,329 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact where the work is integer or a fixed-order floating-point
+definition (assembly, strength/aggregation, prolongator, Galerkin operators,
+coarse LU); within the stated tolerance for Krylov iterates:
+  FP64 path:  ||x - x_oracle|| / ||x_oracle|| <= 1e-8, same algorithm and
+              stopping rule, final true residual <= rtol;
+  mixed path: FP32 hierarchy inside FP64 flexible CG vs the FP64 oracle,
+              <= 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gwinputs as gi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_05798_amd as gw
+    return gw
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gpu_assemble(gw, p):
+    g = p.grid
+    n, nnz = g.n, gw.fv_nnz(g)
+    rowptr = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+    col = torch.zeros(nnz, dtype=torch.int32, device="cuda")
+    val = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    b = torch.zeros(n, dtype=torch.float64, device="cuda")
+    K = dev(p.K)
+    gw.fv_assemble(g, K, (p.h_west, p.h_east), p.wells, rowptr, col, val, b)
+    return K, rowptr, col, val, b
+
+
+def gpu_params(gw, ap, precision=0):
+    return gw.AmgParams(eps_strong=ap.eps_strong, smoother=ap.smoother, omega=ap.omega, npre=ap.npre,
+                        npost=ap.npost, n_coarse=ap.n_coarse, max_levels=ap.max_levels, precision=precision,
+                        seed=ap.seed)
+
+
+ASM_CASES = [
+    ("2d 64x64 homogeneous", lambda: gi.homogeneous_slab()),
+    ("3d 13x7x5 random K, wells", lambda: gi.Problem(gi.Grid(13, 7, 5), gi.random_k(gi.Grid(13, 7, 5), 1),
+                                                     wells=[gi.Well(3, 2, 1, 1e-5), gi.Well(3, 2, 1, 2e-5)])),
+    ("nx=1 column 1x9x6", lambda: gi.Problem(gi.Grid(1, 9, 6), gi.random_k(gi.Grid(1, 9, 6), 2))),
+    ("single cell", lambda: gi.Problem(gi.Grid(1, 1, 1), np.array([3e-4]))),
+    ("3d 33x17x9 lognormal s2=4", lambda: gi.heterogeneous_aquifer(33, 17, 9, 4.0, 4, 7)),
+]
+
+
+@pytest.mark.parametrize("name,make", ASM_CASES, ids=[c[0] for c in ASM_CASES])
+def test_fv_assemble_bitwise(gw, ref, name, make):
+    _say(f"fv_assemble {name}")
+    p = make()
+    A, b = ref.fv_assemble(p)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    assert np.array_equal(host(rowptr), A.rowptr)
+    assert np.array_equal(host(col), A.col)
+    assert np.array_equal(host(val).view(np.uint64), A.val.view(np.uint64))
+    assert np.array_equal(host(bd).view(np.uint64), b.view(np.uint64))
+
+
+def test_fv_assemble_rejects_bad_k(gw):
+    _say("fv_assemble invalid K")
+    p = gi.homogeneous_slab(8, 8)
+    p.K[5] = -1.0
+    with pytest.raises(gw.GwError) as e:
+        gpu_assemble(gw, p)
+    assert e.value.status == gw.EINVAL
+
+
+def test_darcy_bitwise(gw, ref):
+    _say("darcy_flux 20x12x7")
+    p = gi.heterogeneous_aquifer(20, 12, 7, 2.0, 4, 3)
+    g = p.grid
+    h = gi.random_vector(g.n, 9)
+    qx, qy, qz = ref.darcy_flux(p, h)
+    dqx = torch.zeros(len(qx), dtype=torch.float64, device="cuda")
+    dqy = torch.zeros(len(qy), dtype=torch.float64, device="cuda")
+    dqz = torch.zeros(len(qz), dtype=torch.float64, device="cuda")
+    gw.darcy_flux(g, dev(p.K), (p.h_west, p.h_east), dev(h), dqx, dqy, dqz)
+    for a, d in ((qx, dqx), (qy, dqy), (qz, dqz)):
+        assert np.array_equal(host(d).view(np.uint64), a.view(np.uint64))
+
+
+def _compare_hierarchy(gw, ref, H_gpu, H_ref, tag):
+    infos, _ = H_gpu.info()
+    assert H_gpu.nlevels == H_ref.nlevels, tag
+    for l in range(H_ref.nlevels):
+        R = H_ref.level(l)
+        li = infos[l]
+        assert (li.n, li.nnz) == (R.A.n, R.A.nnz), f"{tag} level {l} size"
+        coarsest = l == H_ref.nlevels - 1
+        ar = torch.zeros(li.n + 1, dtype=torch.int32, device="cuda")
+        ac = torch.zeros(max(li.nnz, 1), dtype=torch.int32, device="cuda")
+        av = torch.zeros(max(li.nnz, 1), dtype=torch.float64, device="cuda")
+        if coarsest:
+            gw.amg_level_export(H_gpu, l, ar, ac, av)
+        else:
+            agg = torch.zeros(li.n, dtype=torch.int32, device="cuda")
+            M = torch.zeros(li.n, dtype=torch.float64, device="cuda")
+            pr = torch.zeros(li.n + 1, dtype=torch.int32, device="cuda")
+            pc = torch.zeros(max(li.nnz_p, 1), dtype=torch.int32, device="cuda")
+            pv = torch.zeros(max(li.nnz_p, 1), dtype=torch.float64, device="cuda")
+            gw.amg_level_export(H_gpu, l, ar, ac, av, agg, M, pr, pc, pv)
+            assert li.nc == R.nc and li.mis_rounds == R.mis_rounds and li.nnz_s == R.nnz_s, f"{tag} level {l}"
+            assert np.array_equal(host(agg), R.agg), f"{tag} aggregates level {l}"
+            assert li.omega_p == R.omega_p, f"{tag} omega level {l}"
+            assert np.array_equal(host(pr), R.P.rowptr) and np.array_equal(host(pc)[:li.nnz_p], R.P.col)
+            assert np.array_equal(host(pv)[:li.nnz_p].view(np.uint64), R.P.val.view(np.uint64)), f"{tag} P {l}"
+            assert np.array_equal(host(M).view(np.uint64), R.M.view(np.uint64)), f"{tag} M {l}"
+        assert np.array_equal(host(ar), R.A.rowptr), f"{tag} A rowptr level {l}"
+        assert np.array_equal(host(ac)[:li.nnz], R.A.col), f"{tag} A col level {l}"
+        assert np.array_equal(host(av)[:li.nnz].view(np.uint64), R.A.val.view(np.uint64)), f"{tag} A val {l}"
+    lu_ref, piv_ref = H_ref.coarse_lu()
+    nd = lu_ref.shape[0]
+    lu = torch.zeros(nd * nd, dtype=torch.float64, device="cuda")
+    piv = torch.zeros(nd, dtype=torch.int32, device="cuda")
+    inv = torch.zeros(nd * nd, dtype=torch.float64, device="cuda")
+    gw.amg_coarse_export(H_gpu, lu, piv, inv)
+    assert np.array_equal(host(piv), piv_ref)
+    assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64)), f"{tag} coarse LU"
+    Ac = H_ref.level(H_ref.nlevels - 1).A.dense()
+    Ainv = host(inv).reshape(nd, nd).T  # column-major
+    assert np.allclose(Ainv @ Ac, np.eye(nd), atol=1e-9)
+
+
+HIER_CASES = [
+    ("2d 64x64 jacobi", lambda: gi.homogeneous_slab(), dict(smoother=0, npre=1, npost=1)),
+    ("3d 24x20x12 s2=4", lambda: gi.heterogeneous_aquifer(24, 20, 12, 4.0, 4, 5), dict()),
+    ("3d 37x23x11 s2=1 ragged", lambda: gi.heterogeneous_aquifer(37, 23, 11, 1.0, 3, 8), dict(n_coarse=40)),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", HIER_CASES, ids=[c[0] for c in HIER_CASES])
+def test_flow_hierarchy_bitwise(gw, ref, name, make, kw):
+    _say(f"hierarchy {name}")
+    p = make()
+    ap = ref.AmgParams(**kw)
+    A, b = ref.fv_assemble(p)
+    Hr = ref.Hierarchy(A, ap)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap))
+    _compare_hierarchy(gw, ref, Hg, Hr, name)
+
+
+def test_travel_time_hierarchy_bitwise(gw, ref):
+    _say("hierarchy travel time 24x20x12")
+    import scipy.sparse.linalg as sla
+    p = gi.heterogeneous_aquifer(24, 20, 12, 4.0, 4, 5)
+    A, b = ref.fv_assemble(p)
+    h = sla.spsolve(A.to_scipy().tocsc(), b)
+    qx, qy, qz = ref.darcy_flux(p, h)
+    At, bt, bc, nid = ref.tt_assemble(p.grid, qx, qy, qz, 0.25, zone=(0, 20, 0, 6))
+    g = p.grid
+    n, cap = g.n, gw.tt_nnz_bound(g)
+    rp = torch.zeros(n + 1, dtype=torch.int32, device="cuda")
+    cl = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    vl = torch.zeros(cap, dtype=torch.float64, device="cuda")
+    dbt = torch.zeros(n, dtype=torch.float64, device="cuda")
+    dbc = torch.zeros(n, dtype=torch.float64, device="cuda")
+    nnz, nid_g = gw.tt_assemble(g, dev(qx), dev(qy), dev(qz), 0.25, (0, 20, 0, 6), rp, cl, vl, dbt, dbc)
+    assert nnz == At.nnz and nid_g == nid
+    assert np.array_equal(host(rp), At.rowptr) and np.array_equal(host(cl)[:nnz], At.col)
+    assert np.array_equal(host(vl)[:nnz].view(np.uint64), At.val.view(np.uint64))
+    assert np.array_equal(host(dbt).view(np.uint64), bt.view(np.uint64))
+    assert np.array_equal(host(dbc).view(np.uint64), bc.view(np.uint64))
+    ap = ref.AmgParams(n_coarse=40)
+    Hr = ref.Hierarchy(At, ap)
+    Hg = gw.amg_setup(n, rp, cl[:nnz].contiguous(), vl[:nnz].contiguous(), gpu_params(gw, ap))
+    _compare_hierarchy(gw, ref, Hg, Hr, "travel time")
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_vcycle_parity(gw, ref, precision):
+    _say(f"vcycle precision={precision}")
+    p = gi.heterogeneous_aquifer(30, 22, 14, 4.0, 4, 6)
+    A, b = ref.fv_assemble(p)
+    ap = ref.AmgParams(n_coarse=60)
+    Hr = ref.Hierarchy(A, ap)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap, precision))
+    for seed in (1, 2):
+        r = gi.random_vector(p.grid.n, seed)
+        z_ref = Hr.vcycle(r)
+        z = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+        gw.amg_vcycle(Hg, dev(r), z)
+        err = np.linalg.norm(host(z) - z_ref) / np.linalg.norm(z_ref)
+        assert err < (1e-12 if precision == 0 else 1e-5), err
+    # SpMV with the level-0 operator
+    x = gi.random_vector(p.grid.n, 3)
+    y = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    gw.amg_spmv(Hg, dev(x), y)
+    assert np.allclose(host(y), ref.spmv(A, x), rtol=1e-13, atol=1e-13 * np.abs(ref.spmv(A, x)).max())
+
+
+FLOW_CASES = [
+    ("C1 2d 64x64 jacobi", lambda: gi.homogeneous_slab(), dict(smoother=0, npre=1, npost=1)),
+    ("3d 40x32x16 s2=4 wells", lambda: gi.heterogeneous_aquifer(40, 32, 16, 4.0, 8, 11), dict()),
+    ("3d 29x31x7 s2=2 ragged", lambda: gi.heterogeneous_aquifer(29, 31, 7, 2.0, 4, 12), dict(n_coarse=50)),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", FLOW_CASES, ids=[c[0] for c in FLOW_CASES])
+def test_flow_pcg_parity(gw, ref, name, make, kw):
+    _say(f"pcg {name}")
+    p = make()
+    ap = ref.AmgParams(**kw)
+    fr = ref.solve_flow(p, ap, rtol=1e-8)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap))
+    x = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-8, check_every=3))
+    h = host(x)
+    assert info.status == gw.OK and info.rel_res_true <= 1e-8
+    assert abs(info.iters - fr.info.iters) <= 1, (info.iters, fr.info.iters)
+    err = np.linalg.norm(h - fr.h) / np.linalg.norm(fr.h)
+    assert err <= 1e-8, err
+    if name.startswith("C1"):
+        ex = np.tile(10 * (1 - (np.arange(64) + 0.5) / 64), 64)
+        assert np.linalg.norm(h - ex) / np.linalg.norm(ex) < 1e-6
+
+
+def test_flow_mixed_fcg(gw, ref):
+    _say("mixed fcg 40x32x16")
+    p = gi.heterogeneous_aquifer(40, 32, 16, 4.0, 8, 11)
+    ap = ref.AmgParams()
+    fr = ref.solve_flow(p, ap, rtol=1e-8)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap, gw.PRECISION_MIXED))
+    x = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-8))
+    assert info.status == gw.OK and info.rel_res_true <= 1e-8
+    err = np.linalg.norm(host(x) - fr.h) / np.linalg.norm(fr.h)
+    assert err <= 1e-6, err
+    assert info.iters <= fr.info.iters + 5
+
+
+def test_travel_time_solve_parity(gw, ref):
+    _say("tt_solve 32x24x12")
+    import scipy.sparse.linalg as sla
+    p = gi.heterogeneous_aquifer(32, 24, 12, 4.0, 6, 4)
+    A, b = ref.fv_assemble(p)
+    h = sla.spsolve(A.to_scipy().tocsc(), b)
+    qx, qy, qz = ref.darcy_flux(p, h)
+    zone = (0, 24, 0, 6)
+    ap = ref.AmgParams()
+    tr = ref.solve_travel_time(p.grid, qx, qy, qz, 0.25, ap, rtol=1e-8, zone=zone)
+    tau = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    c = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    st, infos = gw.tt_solve(p.grid, dev(qx), dev(qy), dev(qz), 0.25, zone, gpu_params(gw, ap),
+                            gw.SolveParams(rtol=1e-8), tau, c)
+    assert st == gw.OK
+    for got, want, inf in ((host(tau), tr.tau, infos[0]), (host(c), tr.c, infos[1])):
+        assert inf.rel_res_true <= 1e-8
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-8
+    # and the exact sweep solution within the solve's accuracy
+    tau_ex = ref.tt_sweep(tr.A, tr.b_tau, h)
+    assert np.linalg.norm(host(tau) - tau_ex) / np.linalg.norm(tau_ex) < 1e-6
+
+
+def test_status_codes(gw, ref):
+    _say("status codes")
+    p = gi.heterogeneous_aquifer(16, 12, 8, 1.0, 4, 2)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gw.AmgParams(n_coarse=30))
+    x = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-12, maxiter=1))
+    assert info.status == gw.NOT_CONVERGED and info.iters == 1
+    info = gw.amg_solve_pcg(Hg, torch.zeros_like(bd), x)
+    assert info.status == gw.OK and info.iters == 0 and not host(x).any()
+    bad = bd.clone()
+    bad[3] = float("nan")
+    assert gw.amg_solve_pcg(Hg, bad, x).status == gw.BREAKDOWN
+    assert gw.amg_solve_bicgstab(Hg, bad, x).status == gw.BREAKDOWN
+    info = gw.amg_solve_bicgstab(Hg, bd, x, gw.SolveParams(rtol=1e-12, maxiter=1))
+    assert info.status == gw.NOT_CONVERGED
+    # invalid CSR: unsorted columns
+    c2 = col.clone()
+    c2[0], c2[1] = col[1], col[0]
+    with pytest.raises(gw.GwError) as e:
+        gw.amg_setup(p.grid.n, rowptr, c2, val)
+    assert e.value.status == gw.EINVAL
+
+
+def test_full_size_flow_parity(gw, ref):
+    # the 1M-cell lognormal aquifer (variance 4, correlation length 8, four
+    # wells) in the benchmark's configuration: aggregates of every level bit
+    # for bit, heads within 1e-8 of the oracle's same-algorithm solve
+    _say("full-size 128x128x64 flow parity")
+    p = gi.heterogeneous_aquifer(128, 128, 64, 4.0, 8, 11)
+    ap = ref.AmgParams()
+    fr = ref.solve_flow(p, ap, rtol=1e-8)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap))
+    infos, _ = Hg.info()
+    assert Hg.nlevels == fr.H.nlevels
+    for l in range(fr.H.nlevels - 1):
+        agg = torch.zeros(infos[l].n, dtype=torch.int32, device="cuda")
+        gw.amg_level_export(Hg, l, agg=agg)
+        assert np.array_equal(host(agg), fr.H.level(l).agg), f"level {l}"
+    x = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-8))
+    assert info.status == gw.OK and info.rel_res_true <= 1e-8
+    err = np.linalg.norm(host(x) - fr.h) / np.linalg.norm(fr.h)
+    _say(f"  iters gpu {info.iters} oracle {fr.info.iters} rel err {err:.3e}")
+    assert err <= 1e-8
