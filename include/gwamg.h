@@ -193,7 +193,7 @@ int amg_level_export(const amg_hierarchy *H, int32_t level, int32_t *a_rowptr, i
 
 /* Coarsest level: LU factors (row-major nd x nd, unit lower L below the
  * diagonal), pivot rows (LAPACK getrf order) and the inverse used by the
- * V-cycle.  [device]; any may be NULL. */
+ * V-cycle (row-major nd x nd).  [device]; any may be NULL. */
 int amg_coarse_export(const amg_hierarchy *H, double *lu, int32_t *piv, double *inv, void *stream);
 
 void amg_free(amg_hierarchy *H);

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <memory>
 
 #include "gw_internal.h"
@@ -96,6 +97,17 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
         }
     }
     const size_t es = H->mixed() ? 4 : 8;
+    auto mean = [](const Csr &M) { return M.n ? (double)M.nnz / (double)M.n : 0.0; };
+    for (int l = 0; l < std::max(H->nlev, 1); ++l) {
+        Level &Lv = H->L[l];
+        Lv.A.grp = lane_group_for(mean(Lv.A));
+        Lv.P.grp = lane_group_for(mean(Lv.P));
+        Lv.R.grp = lane_group_for(mean(Lv.R));
+    }
+    if (const char *e = std::getenv("GWAMG_G0")) {
+        int g = std::atoi(e);
+        if (g == 1 || g == 4 || g == 16 || g == 64) H->L[0].A.grp = g;
+    }
     for (int l = 0; l < H->nlev; ++l) {
         Level &Lv = H->L[l];
         if (l < H->nlev - 1) {
@@ -181,7 +193,7 @@ int amg_spmv(amg_hierarchy *H, const double *x, double *y, void *stream) {
     return guarded([&] {
         GW_REQUIRE(H && x && y, "amg_spmv: null pointer");
         hipStream_t s = as_stream(stream);
-        spmv_f64(view(H->L[0].A), x, y, s);
+        spmv_f64(view(H->L[0].A), H->L[0].A.grp, x, y, s);
         finish(s);
         return GW_OK;
     });

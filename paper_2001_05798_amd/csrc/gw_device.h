@@ -57,43 +57,32 @@ __device__ __forceinline__ T block_sum(T v, T *sm) {
     return t;
 }
 
-// Uncached (device-coherent) load of a value written by another workgroup.
-__device__ __forceinline__ double load_coherent(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide sum of NV per-thread values with the "last block finishes"
-// pattern.  Every block stores its NV block sums in partials[b*NV + k] and
-// takes a ticket; the block that draws the last ticket adds all partials in
-// block order (thread t takes blocks t, t+blockDim, ..., then a fixed tree),
-// so the total is identical whichever block arrives last.  Returns true in
-// the last block, where tot[] holds the totals (in every thread).
+// First stage of a grid-wide sum: every block stores its NV block sums in
+// partials[b*NV + k].  A one-block finalize kernel adds them in block order
+// (fixed), so totals do not depend on scheduling.  Two kernels instead of a
+// "last block" ticket: on a multi-XCD part a device-scope fence in every
+// block would write back that XCD's L2 each time, while the kernel boundary
+// makes the partials visible once.
 template <int NV>
-__device__ bool grid_sum_last(double (&v)[NV], double *partials, uint32_t *counter, double (&tot)[NV]) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials) {
     __shared__ double sm[NV][16];
-    __shared__ bool last;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = block_sum(v[k], sm[k]);
         if (threadIdx.x == 0) partials[(size_t)blockIdx.x * NV + k] = s;
     }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+}
+
+// Second stage, one block: tot[k] = sum over nb blocks, same order always.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double *partials, unsigned nb, double (&tot)[NV]) {
+    __shared__ double sm[NV][16];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x)
-            s += load_coherent(&partials[(size_t)b * NV + k]);
+        for (unsigned b = threadIdx.x; b < nb; b += blockDim.x) s += partials[(size_t)b * NV + k];
         tot[k] = block_sum(s, sm[k]);
     }
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
 }
 
 __device__ __forceinline__ bool finite_nz(double v) { return isfinite(v) && v != 0.0; }

@@ -107,6 +107,7 @@ enum KernelId : int {
     K_FV_ASSEMBLE, K_DARCY, K_TT_ASSEMBLE,
     K_SETUP_MISC, K_TRANSPOSE, K_STRENGTH, K_MIS2, K_AGGREGATE, K_SPGEMM, K_COARSE_LU,
     K_SMOOTH_FIRST, K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE,
+    K_SMOOTH_FIRST0, K_SMOOTH0, K_RESIDUAL0, K_RESTRICT0, K_PROLONG0,
     K_KRYLOV_SPMV, K_KRYLOV_UPDATE, K_KRYLOV_DOT, K_TRUE_RESIDUAL,
     K_COUNT
 };
@@ -126,6 +127,7 @@ void prof_flush();
 struct Csr {
     int32_t n = 0, ncols = 0;
     int64_t nnz = 0;
+    int32_t grp = 1;    // lanes per row in the solve-phase products (1, 4, 16, 64)
     DBuf<int32_t> rowptr, col;
     DBuf<double> val;
     DBuf<float> val32;  // FP32 copy (mixed precision levels)
@@ -239,7 +241,9 @@ void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s);
 
 // solve.hip
 void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s);
-void spmv_f64(const CsrView &A, const double *x, double *y, hipStream_t s);
+void spmv_f64(const CsrView &A, int grp, const double *x, double *y, hipStream_t s);
+// Lanes per row for a matrix with this mean row length.
+int lane_group_for(double mean_row_len);
 int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                amg_solve_info *info, hipStream_t s);
 int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,

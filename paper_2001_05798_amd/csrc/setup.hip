@@ -594,25 +594,40 @@ __global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32
     }
 }
 
-// Column c of the inverse: solve L U x = Perm e_c.  inv is column-major.
-__global__ void k_lu_inverse(const double *__restrict__ lu, const int32_t *__restrict__ piv, int32_t n,
-                             double *__restrict__ inv) {
-    int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+// Column c of the inverse: solve L U x = Perm e_c, one wave per column with
+// x in LDS; each substitution step is a wave-wide dot over a row of L or U.
+// The inverse is stored row-major (inv[i*n + c]) for the V-cycle's GEMV.
+constexpr int kMaxDense = 2048;
+__global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu, const int32_t *__restrict__ piv,
+                                                   int32_t n, double *__restrict__ inv) {
+    __shared__ double x[kMaxDense];
+    const int32_t c = blockIdx.x;
+    const int lane = threadIdx.x;
     if (c >= n) return;
-    double *x = inv + (int64_t)c * n;
-    for (int32_t i = 0; i < n; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-    for (int32_t k = 0; k < n; ++k)
-        if (piv[k] != k) { double t = x[k]; x[k] = x[piv[k]]; x[piv[k]] = t; }
-    for (int32_t i = 0; i < n; ++i) {
-        double s = x[i];
-        for (int32_t j = 0; j < i; ++j) s = s - lu[(int64_t)i * n + j] * x[j];
-        x[i] = s;
+    // the permutation moves the single 1 of e_c
+    int32_t pos = c;
+    for (int32_t k = 0; k < n; ++k) {
+        int32_t pk = piv[k];
+        if (pos == k) pos = pk;
+        else if (pos == pk) pos = k;
+    }
+    for (int32_t i = lane; i < n; i += 64) x[i] = (i == pos) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int32_t i = pos + 1; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t j = pos + lane; j < i; j += 64) s += lu[(int64_t)i * n + j] * x[j];
+        s = dev::wave_sum(s);
+        if (lane == 0) x[i] = x[i] - s;
+        __syncthreads();
     }
     for (int32_t i = n - 1; i >= 0; --i) {
-        double s = x[i];
-        for (int32_t j = i + 1; j < n; ++j) s = s - lu[(int64_t)i * n + j] * x[j];
-        x[i] = s / lu[(int64_t)i * n + i];
+        double s = 0.0;
+        for (int32_t j = i + 1 + lane; j < n; j += 64) s += lu[(int64_t)i * n + j] * x[j];
+        s = dev::wave_sum(s);
+        if (lane == 0) x[i] = (x[i] - s) / lu[(int64_t)i * n + i];
+        __syncthreads();
     }
+    for (int32_t i = lane; i < n; i += 64) inv[(int64_t)i * n + c] = x[i];
 }
 
 // ------------------------------------------------------------ host side --
@@ -926,7 +941,7 @@ void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
     if (st.read(status.p, s) != 0) fail(GW_SINGULAR, "amg_setup: zero pivot in the coarsest-level LU");
     {
         ProfScope ps(K_COARSE_LU, (double)n * n * 16, s);
-        hipLaunchKernelGGL(k_lu_inverse, dim3(blocks_for(n, 1, 64)), dim3(64), 0, s, H->lu.p, H->piv.p, n, H->inv.p);
+        hipLaunchKernelGGL(k_lu_inverse, dim3(n), dim3(64), 0, s, H->lu.p, H->piv.p, n, H->inv.p);
         GW_HIP(hipGetLastError());
     }
     GW_HIP(hipStreamSynchronize(s));

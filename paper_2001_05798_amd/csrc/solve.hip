@@ -4,11 +4,13 @@
 // preconditions: CG for the symmetric flow system and BiCGSTAB for the
 // upwind travel-time system (Benchmarking Examples).
 //
-// The Krylov scalars live on the device: every dot product is finished by
-// the last workgroup of its kernel, which also forms alpha/beta/omega and
-// raises the convergence flag; all later kernels read the flag and return at
-// once, so the host only polls it every few iterations.  FP64 throughout the
-// Krylov layer; the hierarchy is FP64 or FP32 (mixed mode).
+// Sparse products use G lanes per row (G picked per matrix from its mean row
+// length), so the lanes of a wave read consecutive CSR entries.  The Krylov
+// scalars live on the device: a product kernel leaves per-block partial sums,
+// a one-block finalize kernel adds them in a fixed order and forms
+// alpha/beta/omega and the convergence flag; every later kernel reads the
+// flag and returns at once, so the host only polls it every few iterations.
+// FP64 throughout the Krylov layer; the hierarchy is FP64 or FP32 (mixed).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -20,93 +22,97 @@ namespace gw {
 
 namespace {
 
-template <class T>
-__device__ __forceinline__ bool is_done(const int32_t *done) {
-    return done && *done;
+// Lanes of a group own one row: strided partial sums, then a butterfly over
+// the group (groups are aligned power-of-two lane ranges of one wave).
+template <int G, class V, class F>
+__device__ __forceinline__ V group_row_sum(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                           const V *__restrict__ val, int64_t i, int lane, F &&xj) {
+    V s = 0;
+    const int32_t e = rowptr[i + 1];
+    for (int32_t p = rowptr[i] + lane; p < e; p += G) s += val[p] * xj(col[p]);
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, dev::kWave);
+    return s;
 }
+
+#define GROUP_ROW(G)                                                              \
+    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;          \
+    const int64_t i = gtid / (G);                                                 \
+    const int lane = (int)(gtid % (G));                                           \
+    if (i >= n) return;
 
 // ------------------------------------------------------------ V-cycle ----
 // Sweep x <- x + M (b - A x); the first two sweeps from x = 0 are fused:
 // x1 = M b, x2 = x1 + M (b - A x1) with x1_j recomputed on the fly.
-template <class V, class Bt, class Yt>
-__global__ void k_smooth_first(int32_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+template <int G, class V, class Bt, class Yt>
+__global__ void k_smooth_first(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                const V *__restrict__ val, const V *__restrict__ M, const Bt *__restrict__ b,
                                Yt *__restrict__ y, int two, const int32_t *done) {
     if (done && *done) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    GROUP_ROW(G)
     const V bi = (V)b[i], mi = M[i];
     V x1 = mi * bi;
     if (two) {
-        V ax = 0;
-        for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            int32_t j = col[p];
-            ax += val[p] * (M[j] * (V)b[j]);
-        }
+        V ax = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return M[j] * (V)b[j]; });
         x1 = x1 + mi * (bi - ax);
     }
-    y[i] = (Yt)x1;
+    if (lane == 0) y[i] = (Yt)x1;
 }
 
-template <class V, class Bt, class Xt, class Yt>
-__global__ void k_smooth(int32_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+template <int G, class V, class Bt, class Xt, class Yt>
+__global__ void k_smooth(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                          const V *__restrict__ val, const V *__restrict__ M, const Bt *__restrict__ b,
                          const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    V ax = 0;
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) ax += val[p] * (V)x[col[p]];
-    y[i] = (Yt)((V)x[i] + M[i] * ((V)b[i] - ax));
+    GROUP_ROW(G)
+    V ax = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)x[j]; });
+    if (lane == 0) y[i] = (Yt)((V)x[i] + M[i] * ((V)b[i] - ax));
 }
 
-template <class V, class Bt, class Xt, class Rt>
-__global__ void k_residual(int32_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+template <int G, class V, class Bt, class Xt, class Rt>
+__global__ void k_residual(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                            const V *__restrict__ val, const Bt *__restrict__ b, const Xt *__restrict__ x,
                            Rt *__restrict__ r, const int32_t *done) {
     if (done && *done) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    V ax = 0;
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) ax += val[p] * (V)x[col[p]];
-    r[i] = (Rt)((V)b[i] - ax);
+    GROUP_ROW(G)
+    V ax = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)x[j]; });
+    if (lane == 0) r[i] = (Rt)((V)b[i] - ax);
 }
 
-template <class V, class Xt, class Yt>
-__global__ void k_spmv(int32_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+template <int G, class V, class Xt, class Yt>
+__global__ void k_spmv(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                        const V *__restrict__ val, const Xt *__restrict__ x, Yt *__restrict__ y,
                        const int32_t *done) {
     if (done && *done) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    V s = 0;
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s += val[p] * (V)x[col[p]];
-    y[i] = (Yt)s;
+    GROUP_ROW(G)
+    V s = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)x[j]; });
+    if (lane == 0) y[i] = (Yt)s;
 }
 
 // x += P x_c
-template <class V, class Xt>
-__global__ void k_prolong(int32_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+template <int G, class V, class Xt>
+__global__ void k_prolong(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                           const V *__restrict__ val, const Xt *__restrict__ xc, Xt *__restrict__ x,
                           const int32_t *done) {
     if (done && *done) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    V s = 0;
-    for (int32_t p = rowptr[i]; p < rowptr[i + 1]; ++p) s += val[p] * (V)xc[col[p]];
-    x[i] = (Xt)((V)x[i] + s);
+    GROUP_ROW(G)
+    V s = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)xc[j]; });
+    if (lane == 0) x[i] = (Xt)((V)x[i] + s);
 }
 
-// Coarsest level: x = A_L^{-1} b with the column-major inverse, in FP64.
+// Coarsest level: x = A_L^{-1} b with the row-major inverse, one wave per
+// row, accumulated in FP64.
 template <class Bt, class Yt>
 __global__ void k_coarse_gemv(int32_t n, const double *__restrict__ inv, const Bt *__restrict__ b,
                               Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / dev::kWave;
+    const int lane = threadIdx.x & (dev::kWave - 1);
     if (i >= n) return;
     double s = 0.0;
-    for (int32_t c = 0; c < n; ++c) s += inv[(int64_t)c * n + i] * (double)b[c];
-    y[i] = (Yt)s;
+    for (int32_t c = lane; c < n; c += dev::kWave) s += inv[i * n + c] * (double)b[c];
+    s = dev::wave_sum(s);
+    if (lane == 0) y[i] = (Yt)s;
 }
 
 template <class X>
@@ -126,13 +132,10 @@ __global__ void k_convert(const Xt *__restrict__ x, Yt *__restrict__ y, int64_t 
 // Bytes one launch of a CSR pass touches (values, columns, row pointers).
 double csr_bytes(int64_t n, int64_t nnz, int vbytes) { return (double)nnz * (vbytes + 4) + 4.0 * (n + 1); }
 
+unsigned grid_rows(int64_t n, int G) { return blocks_for(n * G); }
+
 template <class V>
-struct LevelOps {
-    static const V *aval(const Level &L);
-    static const V *pval(const Level &L);
-    static const V *rval(const Level &L);
-    static const V *mval(const Level &L);
-};
+struct LevelOps;
 template <>
 struct LevelOps<double> {
     static const double *aval(const Level &L) { return L.A.val.p; }
@@ -148,6 +151,15 @@ struct LevelOps<float> {
     static const float *mval(const Level &L) { return L.M32.p; }
 };
 
+// Launch a kernel template instantiated for the matrix's lane-group size.
+#define DISPATCH_G(g, KERNEL, ...)                                            \
+    switch (g) {                                                              \
+        case 1: KERNEL(1, __VA_ARGS__); break;                                \
+        case 4: KERNEL(4, __VA_ARGS__); break;                                \
+        case 16: KERNEL(16, __VA_ARGS__); break;                              \
+        default: KERNEL(64, __VA_ARGS__); break;                              \
+    }
+
 // One V-cycle on level l.  `b` is the right-hand side (type Bt), the result
 // goes to `out` (type Zt) when given, else into one of the level's own
 // buffers, whose address is returned.  V = value type of the hierarchy (also
@@ -155,13 +167,13 @@ struct LevelOps<float> {
 template <class V, class Bt, class Zt>
 void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s) {
     Level &Lv = H->L[l];
-    const int32_t n = Lv.A.n;
-    const unsigned g = blocks_for(n);
+    const int64_t n = Lv.A.n;
     const int vb = (int)sizeof(V);
     if (l == H->nlev - 1) {
         Zt *y = out ? out : reinterpret_cast<Zt *>(Lv.vx.p);
         ProfScope ps(K_COARSE_SOLVE, (double)n * n * 8 + n * (double)(sizeof(Bt) + sizeof(Zt)), s);
-        hipLaunchKernelGGL((k_coarse_gemv<Bt, Zt>), dim3(blocks_for(n, 1, 64)), dim3(64), 0, s, n, H->inv.p, b, y, done);
+        hipLaunchKernelGGL((k_coarse_gemv<Bt, Zt>), dim3(blocks_for(n * dev::kWave)), dim3(kBlock), 0, s,
+                           (int32_t)n, H->inv.p, b, y, done);
         return y;
     }
     const int32_t *ar = Lv.A.rowptr.p, *ac = Lv.A.col.p;
@@ -170,51 +182,64 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     V *x = reinterpret_cast<V *>(Lv.vx.p);
     V *t = reinterpret_cast<V *>(Lv.vt.p);
     const int npre = H->prm.npre, npost = H->prm.npost;
+    const int ga = Lv.A.grp;
 
     // pre-smoothing
     if (npre == 0) {
-        hipLaunchKernelGGL((k_zero<V>), dim3(g), dim3(kBlock), 0, s, x, (int64_t)n, done);
+        hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, done);
     } else {
-        ProfScope ps(K_SMOOTH_FIRST, npre >= 2 ? abytes + n * (double)(sizeof(Bt) + 2 * vb) : n * (double)(sizeof(Bt) + 2 * vb), s);
-        hipLaunchKernelGGL((k_smooth_first<V, Bt, V>), dim3(g), dim3(kBlock), 0, s, n, ar, ac, av, M, b, x,
-                           npre >= 2 ? 1 : 0, done);
+        ProfScope ps(l == 0 ? K_SMOOTH_FIRST0 : K_SMOOTH_FIRST, npre >= 2 ? abytes + n * (double)(sizeof(Bt) + 2 * vb) : n * (double)(sizeof(Bt) + 2 * vb), s);
+#define L_SF(G, ...) hipLaunchKernelGGL((k_smooth_first<G, V, Bt, V>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, ar, ac, av, M, b, x, npre >= 2 ? 1 : 0, done)
+        DISPATCH_G(ga, L_SF, 0)
+#undef L_SF
     }
+#define L_SM(G, XIN, YOUT, YT) hipLaunchKernelGGL((k_smooth<G, V, Bt, V, YT>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, ar, ac, av, M, b, XIN, YOUT, done)
     for (int k = 2; k < npre; ++k) {
-        ProfScope ps(K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 3 * vb), s);
-        hipLaunchKernelGGL((k_smooth<V, Bt, V, V>), dim3(g), dim3(kBlock), 0, s, n, ar, ac, av, M, b, x, t, done);
+        ProfScope ps(l == 0 ? K_SMOOTH0 : K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 3 * vb), s);
+        DISPATCH_G(ga, L_SM, x, t, V)
         std::swap(x, t);
     }
     // residual and restriction
     {
-        ProfScope ps(K_RESIDUAL, abytes + n * (double)(sizeof(Bt) + 2 * vb), s);
-        hipLaunchKernelGGL((k_residual<V, Bt, V, V>), dim3(g), dim3(kBlock), 0, s, n, ar, ac, av, b, x, t, done);
+        ProfScope ps(l == 0 ? K_RESIDUAL0 : K_RESIDUAL, abytes + n * (double)(sizeof(Bt) + 2 * vb), s);
+#define L_RES(G, ...) hipLaunchKernelGGL((k_residual<G, V, Bt, V, V>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, ar, ac, av, b, x, t, done)
+        DISPATCH_G(ga, L_RES, 0)
+#undef L_RES
     }
     Level &Nx = H->L[l + 1];
     V *bc = reinterpret_cast<V *>(Nx.vb.p);
+    const int64_t nc = Lv.nc;
     {
-        ProfScope ps(K_RESTRICT, csr_bytes(Lv.nc, Lv.R.nnz, vb) + (double)(n + Lv.nc) * vb, s);
-        hipLaunchKernelGGL((k_spmv<V, V, V>), dim3(blocks_for(Lv.nc)), dim3(kBlock), 0, s, Lv.nc, Lv.R.rowptr.p,
-                           Lv.R.col.p, LevelOps<V>::rval(Lv), t, bc, done);
+        ProfScope ps(l == 0 ? K_RESTRICT0 : K_RESTRICT, csr_bytes(nc, Lv.R.nnz, vb) + (double)(n + nc) * vb, s);
+        const int32_t *rr = Lv.R.rowptr.p, *rc = Lv.R.col.p;
+        const V *rv = LevelOps<V>::rval(Lv);
+#define L_R(G, ...) hipLaunchKernelGGL((k_spmv<G, V, V, V>), dim3(grid_rows(nc, G)), dim3(kBlock), 0, s, nc, rr, rc, rv, t, bc, done)
+        DISPATCH_G(Lv.R.grp, L_R, 0)
+#undef L_R
     }
     V *xc = static_cast<V *>(vcycle_level<V, V, V>(H, l + 1, bc, (V *)nullptr, done, s));
     {
-        ProfScope ps(K_PROLONG, csr_bytes(n, Lv.P.nnz, vb) + (double)(2 * n + Lv.nc) * vb, s);
-        hipLaunchKernelGGL((k_prolong<V, V>), dim3(g), dim3(kBlock), 0, s, n, Lv.P.rowptr.p, Lv.P.col.p,
-                           LevelOps<V>::pval(Lv), xc, x, done);
+        ProfScope ps(l == 0 ? K_PROLONG0 : K_PROLONG, csr_bytes(n, Lv.P.nnz, vb) + (double)(2 * n + nc) * vb, s);
+        const int32_t *pr = Lv.P.rowptr.p, *pc = Lv.P.col.p;
+        const V *pv = LevelOps<V>::pval(Lv);
+#define L_P(G, ...) hipLaunchKernelGGL((k_prolong<G, V, V>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, pr, pc, pv, xc, x, done)
+        DISPATCH_G(Lv.P.grp, L_P, 0)
+#undef L_P
     }
     // post-smoothing; the last sweep writes the requested output
     for (int k = 0; k < npost; ++k) {
         const bool last = (k == npost - 1);
-        ProfScope ps(K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 3 * vb), s);
+        ProfScope ps(l == 0 ? K_SMOOTH0 : K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 3 * vb), s);
         if (last && out) {
-            hipLaunchKernelGGL((k_smooth<V, Bt, V, Zt>), dim3(g), dim3(kBlock), 0, s, n, ar, ac, av, M, b, x, out, done);
+            DISPATCH_G(ga, L_SM, x, out, Zt)
             return out;
         }
-        hipLaunchKernelGGL((k_smooth<V, Bt, V, V>), dim3(g), dim3(kBlock), 0, s, n, ar, ac, av, M, b, x, t, done);
+        DISPATCH_G(ga, L_SM, x, t, V)
         std::swap(x, t);
     }
+#undef L_SM
     if (out) {
-        hipLaunchKernelGGL((k_convert<V, Zt>), dim3(g), dim3(kBlock), 0, s, x, out, (int64_t)n, done);
+        hipLaunchKernelGGL((k_convert<V, Zt>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, out, n, done);
         return out;
     }
     return x;
@@ -224,111 +249,81 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
 constexpr int kKBlock = 256;
 constexpr int kKMaxBlocks = 2048;
 
-unsigned kgrid(int64_t n) {
-    int64_t b = (n + kKBlock - 1) / kKBlock;
+// Grid of a grouped row loop: rows are visited by (block, group) in a
+// grid-stride loop over at most kKMaxBlocks blocks.
+unsigned kgrid(int64_t n, int G) {
+    int64_t b = (n * G + kKBlock - 1) / kKBlock;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, kKMaxBlocks));
 }
 
-#define GRID_LOOP(i, n) for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+#define GROUP_LOOP(G, i, lane, n)                                                         \
+    const int lane = (int)(threadIdx.x % (G));                                            \
+    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / (G); i < (n);     \
+         i += (int64_t)gridDim.x * blockDim.x / (G))
 
-__device__ __forceinline__ double row_dot(const CsrView &A, int64_t i, const double *__restrict__ x) {
-    double s = 0.0;
-    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s += A.val[p] * x[A.col[p]];
-    return s;
-}
+#define GRID_LOOP(i, n) \
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
-// r = b - A x; first call also forms ||b|| and the tolerance.
+// r = b - A x (and BiCGSTAB's r_hat = r, p = v = 0); partials b.b, r.r
+template <int G>
 __global__ void __launch_bounds__(kKBlock) k_kr_init(CsrView A, const double *__restrict__ b,
                                                      const double *__restrict__ x, double *__restrict__ r,
                                                      double *__restrict__ rh, double *__restrict__ p,
-                                                     double *__restrict__ v, double rtol, int first,
-                                                     double *partials, KScalars *ks) {
+                                                     double *__restrict__ v, double *partials) {
     double acc[2] = {0.0, 0.0};
-    GRID_LOOP(i, A.n) {
-        double ri = b[i] - row_dot(A, i, x);
-        r[i] = ri;
-        if (rh) rh[i] = ri;
-        if (p) p[i] = 0.0;
-        if (v) v[i] = 0.0;
-        acc[0] += b[i] * b[i];
-        acc[1] += ri * ri;
-    }
-    double tot[2];
-    if (dev::grid_sum_last<2>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        if (first) {
-            ks->bnorm = sqrt(tot[0]);
-            ks->tol = rtol * ks->bnorm;
-        }
-        ks->rr = tot[1];
-        ks->done = 0;
-        // BiCGSTAB start: r_hat = r, rho = r_hat.r, rho_prev = alpha = omega = 1
-        ks->rho_prev = 1.0;
-        ks->alpha = 1.0;
-        ks->omega = 1.0;
-        ks->rho = tot[1];
-        ks->beta = tot[1];  // (rho / 1) * (1 / 1)
-        ks->pending_x = 0;
-        if (!dev::finite_nz(tot[1]) && ks->bnorm != 0.0) {
-            ks->status = GW_BREAKDOWN;
-            ks->done = 1;
+    GROUP_LOOP(G, i, lane, A.n) {
+        double ax = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return x[j]; });
+        if (lane == 0) {
+            double ri = b[i] - ax;
+            r[i] = ri;
+            if (rh) rh[i] = ri;
+            if (p) p[i] = 0.0;
+            if (v) v[i] = 0.0;
+            acc[0] += b[i] * b[i];
+            acc[1] += ri * ri;
         }
     }
+    dev::block_partials<2>(acc, partials);
 }
 
-// CG: rz = r.z; beta = rz_new / rz (or Polak-Ribiere -alpha z.q / rz).
-__global__ void __launch_bounds__(kKBlock) k_cg_beta(int64_t n, const double *__restrict__ r,
-                                                     const double *__restrict__ z, const double *__restrict__ q,
-                                                     int first, double *partials, KScalars *ks) {
+// CG: partials r.z and z.q
+__global__ void __launch_bounds__(kKBlock) k_cg_dot(int64_t n, const double *__restrict__ r,
+                                                    const double *__restrict__ z, const double *__restrict__ q,
+                                                    double *partials, const KScalars *ks) {
     if (ks->done) return;
     double acc[2] = {0.0, 0.0};
     GRID_LOOP(i, n) {
         acc[0] += r[i] * z[i];
-        if (!first) acc[1] += z[i] * q[i];
+        acc[1] += z[i] * q[i];
     }
-    double tot[2];
-    if (dev::grid_sum_last<2>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        double rz_new = tot[0];
-        if (first) ks->beta = 0.0;
-        else if (ks->flexible) ks->beta = (-ks->alpha * tot[1]) / ks->rz;
-        else ks->beta = rz_new / ks->rz;
-        ks->rz = rz_new;
-    }
+    dev::block_partials<2>(acc, partials);
 }
 
-// p_new = z + beta p_old;  q = A p_new;  alpha = rz / (p_new . q)
+// p_new = z + beta p_old;  q = A p_new;  partial p_new . q
+template <int G>
 __global__ void __launch_bounds__(kKBlock) k_cg_spmv(CsrView A, const double *__restrict__ z,
                                                      const double *__restrict__ p_old, double *__restrict__ p_new,
-                                                     double *__restrict__ q, double *partials, KScalars *ks) {
+                                                     double *__restrict__ q, double *partials, const KScalars *ks) {
     if (ks->done) return;
     const double beta = ks->beta;
     double acc[1] = {0.0};
-    GRID_LOOP(i, A.n) {
-        double s = 0.0;
-        for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
-            int32_t j = A.col[p];
-            s += A.val[p] * (z[j] + beta * p_old[j]);
-        }
-        double pi = z[i] + beta * p_old[i];
-        p_new[i] = pi;
-        q[i] = s;
-        acc[0] += pi * s;
-    }
-    double tot[1];
-    if (dev::grid_sum_last<1>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        ks->pq = tot[0];
-        if (!dev::finite_nz(tot[0]) || !isfinite(ks->rz)) {
-            ks->status = GW_BREAKDOWN;
-            ks->done = 1;
-        } else {
-            ks->alpha = ks->rz / tot[0];
+    GROUP_LOOP(G, i, lane, A.n) {
+        double s = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane,
+                                            [&](int32_t j) { return z[j] + beta * p_old[j]; });
+        if (lane == 0) {
+            double pi = z[i] + beta * p_old[i];
+            p_new[i] = pi;
+            q[i] = s;
+            acc[0] += pi * s;
         }
     }
+    dev::block_partials<1>(acc, partials);
 }
 
-// x += alpha p;  r -= alpha q;  stop when ||r|| <= rtol ||b||
+// x += alpha p;  r -= alpha q;  partial r.r
 __global__ void __launch_bounds__(kKBlock) k_cg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                        const double *__restrict__ p, const double *__restrict__ q,
-                                                       double *partials, KScalars *ks) {
+                                                       double *partials, const KScalars *ks) {
     if (ks->done) return;
     const double alpha = ks->alpha;
     double acc[1] = {0.0};
@@ -338,60 +333,52 @@ __global__ void __launch_bounds__(kKBlock) k_cg_update(int64_t n, double *__rest
         r[i] = ri;
         acc[0] += ri * ri;
     }
-    double tot[1];
-    if (dev::grid_sum_last<1>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        ks->rr = tot[0];
-        ks->iters += 1;
-        double rn = sqrt(tot[0]);
-        if (!isfinite(rn)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-        else if (rn <= ks->tol) { ks->status = GW_OK; ks->done = 1; }
-        else if (ks->iters >= ks->maxiter) { ks->status = GW_NOT_CONVERGED; ks->done = 1; }
-    }
+    dev::block_partials<1>(acc, partials);
 }
 
-// ||b - A x|| / ||b|| in FP64
+// partial (b - A x).(b - A x)
+template <int G>
 __global__ void __launch_bounds__(kKBlock) k_true_res(CsrView A, const double *__restrict__ b,
-                                                      const double *__restrict__ x, double *partials, KScalars *ks) {
+                                                      const double *__restrict__ x, double *partials) {
     double acc[1] = {0.0};
-    GRID_LOOP(i, A.n) {
-        double ri = b[i] - row_dot(A, i, x);
-        acc[0] += ri * ri;
+    GROUP_LOOP(G, i, lane, A.n) {
+        double ax = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return x[j]; });
+        if (lane == 0) {
+            double ri = b[i] - ax;
+            acc[0] += ri * ri;
+        }
     }
-    double tot[1];
-    if (dev::grid_sum_last<1>(acc, partials, &ks->counter, tot) && threadIdx.x == 0)
-        ks->rel_true = sqrt(tot[0]) / ks->bnorm;
+    dev::block_partials<1>(acc, partials);
 }
 
 // BiCGSTAB: p = r + beta (p - omega v)
 __global__ void __launch_bounds__(kKBlock) k_bcg_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
-                                                   const double *__restrict__ v, KScalars *ks) {
+                                                   const double *__restrict__ v, const KScalars *ks) {
     if (ks->done) return;
     const double beta = ks->beta, omega = ks->omega;
     GRID_LOOP(i, n) p[i] = r[i] + beta * (p[i] - omega * v[i]);
 }
 
-// v = A p_hat;  alpha = rho / (r_hat . v)
+// v = A p_hat;  partial r_hat . v
+template <int G>
 __global__ void __launch_bounds__(kKBlock) k_bcg_v(CsrView A, const double *__restrict__ ph, double *__restrict__ v,
-                                                   const double *__restrict__ rh, double *partials, KScalars *ks) {
+                                                   const double *__restrict__ rh, double *partials, const KScalars *ks) {
     if (ks->done) return;
     double acc[1] = {0.0};
-    GRID_LOOP(i, A.n) {
-        double vi = row_dot(A, i, ph);
-        v[i] = vi;
-        acc[0] += rh[i] * vi;
+    GROUP_LOOP(G, i, lane, A.n) {
+        double vi = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return ph[j]; });
+        if (lane == 0) {
+            v[i] = vi;
+            acc[0] += rh[i] * vi;
+        }
     }
-    double tot[1];
-    if (dev::grid_sum_last<1>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        ks->rv = tot[0];
-        if (!dev::finite_nz(tot[0])) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-        else ks->alpha = ks->rho / tot[0];
-    }
+    dev::block_partials<1>(acc, partials);
 }
 
-// s = r - alpha v; stop (after x += alpha p_hat) when ||s|| <= tol
+// s = r - alpha v;  partial s.s
 __global__ void __launch_bounds__(kKBlock) k_bcg_s(int64_t n, const double *__restrict__ r,
                                                    const double *__restrict__ v, double *__restrict__ sv,
-                                                   double *partials, KScalars *ks) {
+                                                   double *partials, const KScalars *ks) {
     if (ks->done) return;
     const double alpha = ks->alpha;
     double acc[1] = {0.0};
@@ -400,46 +387,33 @@ __global__ void __launch_bounds__(kKBlock) k_bcg_s(int64_t n, const double *__re
         sv[i] = si;
         acc[0] += si * si;
     }
-    double tot[1];
-    if (dev::grid_sum_last<1>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        ks->ss = tot[0];
-        ks->iters += 1;
-        double sn = sqrt(tot[0]);
-        if (!isfinite(sn)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-        else if (sn <= ks->tol) { ks->status = GW_OK; ks->rr = tot[0]; ks->done = 1; ks->pending_x = 1; }
-    }
+    dev::block_partials<1>(acc, partials);
 }
 
-// t = A s_hat;  omega = (t.s) / (t.t)
+// t = A s_hat;  partials t.s, t.t
+template <int G>
 __global__ void __launch_bounds__(kKBlock) k_bcg_t(CsrView A, const double *__restrict__ sh, double *__restrict__ t,
-                                                   const double *__restrict__ sv, double *partials, KScalars *ks) {
+                                                   const double *__restrict__ sv, double *partials, const KScalars *ks) {
     if (ks->done) return;
     double acc[2] = {0.0, 0.0};
-    GRID_LOOP(i, A.n) {
-        double ti = row_dot(A, i, sh);
-        t[i] = ti;
-        acc[0] += ti * sv[i];
-        acc[1] += ti * ti;
-    }
-    double tot[2];
-    if (dev::grid_sum_last<2>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        ks->ts = tot[0];
-        ks->tt = tot[1];
-        if (!dev::finite_nz(tot[1])) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-        else {
-            double om = tot[0] / tot[1];
-            if (!dev::finite_nz(om)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-            else ks->omega = om;
+    GROUP_LOOP(G, i, lane, A.n) {
+        double ti = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return sh[j]; });
+        if (lane == 0) {
+            t[i] = ti;
+            acc[0] += ti * sv[i];
+            acc[1] += ti * ti;
         }
     }
+    dev::block_partials<2>(acc, partials);
 }
 
-// x += alpha p_hat + omega s_hat;  r = s - omega t;  then the next rho and
-// beta.  After an early stop on ||s|| only x += alpha p_hat is applied.
+// x += alpha p_hat + omega s_hat;  r = s - omega t;  partials r.r, r_hat.r.
+// After an early stop on ||s|| only x += alpha p_hat is applied.
 __global__ void __launch_bounds__(kKBlock) k_bcg_xr(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                     const double *__restrict__ ph, const double *__restrict__ sh,
                                                     const double *__restrict__ sv, const double *__restrict__ t,
-                                                    const double *__restrict__ rh, double *partials, KScalars *ks) {
+                                                    const double *__restrict__ rh, double *partials,
+                                                    const KScalars *ks) {
     const int pending = ks->pending_x;
     if (ks->done && !pending) return;
     const double alpha = ks->alpha, omega = ks->omega;
@@ -455,29 +429,126 @@ __global__ void __launch_bounds__(kKBlock) k_bcg_xr(int64_t n, double *__restric
             acc[1] += rh[i] * ri;
         }
     }
-    double tot[2];
-    if (dev::grid_sum_last<2>(acc, partials, &ks->counter, tot) && threadIdx.x == 0) {
-        if (pending) {
-            ks->pending_x = 0;
-            return;
-        }
-        ks->rr = tot[0];
-        double rn = sqrt(tot[0]);
-        if (!isfinite(rn)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-        else if (rn <= ks->tol) { ks->status = GW_OK; ks->done = 1; }
-        else if (ks->iters >= ks->maxiter) { ks->status = GW_NOT_CONVERGED; ks->done = 1; }
-        else {
-            ks->rho_prev = ks->rho;
+    dev::block_partials<2>(acc, partials);
+}
+
+// The scalar step that follows each reduction.
+enum FinOp : int {
+    FIN_INIT_FIRST, FIN_INIT_RESTART, FIN_CG_BETA_FIRST, FIN_CG_BETA, FIN_CG_ALPHA, FIN_CG_CONV,
+    FIN_TRUE_RES, FIN_BCG_ALPHA, FIN_BCG_S, FIN_BCG_OMEGA, FIN_BCG_XR
+};
+
+__global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const double *partials, double rtol,
+                                                      KScalars *ks) {
+    const bool always = op == FIN_INIT_FIRST || op == FIN_INIT_RESTART || op == FIN_TRUE_RES || op == FIN_BCG_XR;
+    if (!always && ks->done) return;
+    if (op == FIN_BCG_XR && ks->done && !ks->pending_x) return;
+    const int nv = (op == FIN_INIT_FIRST || op == FIN_INIT_RESTART || op == FIN_CG_BETA_FIRST ||
+                    op == FIN_CG_BETA || op == FIN_BCG_OMEGA || op == FIN_BCG_XR) ? 2 : 1;
+    double tot[2] = {0.0, 0.0};
+    if (nv == 2) {
+        dev::sum_partials<2>(partials, nb, tot);
+    } else {
+        double t1[1];
+        dev::sum_partials<1>(partials, nb, t1);
+        tot[0] = t1[0];
+    }
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case FIN_INIT_FIRST:
+        case FIN_INIT_RESTART:
+            if (op == FIN_INIT_FIRST) {
+                ks->bnorm = sqrt(tot[0]);
+                ks->tol = rtol * ks->bnorm;
+            }
+            ks->rr = tot[1];
+            ks->done = 0;
+            // BiCGSTAB start: r_hat = r, rho = r_hat.r, rho_prev = alpha = omega = 1
+            ks->rho_prev = 1.0;
+            ks->alpha = 1.0;
+            ks->omega = 1.0;
             ks->rho = tot[1];
-            if (!dev::finite_nz(tot[1])) { ks->status = GW_BREAKDOWN; ks->done = 1; }
-            else ks->beta = (ks->rho / ks->rho_prev) * (ks->alpha / ks->omega);
+            ks->beta = tot[1];
+            ks->pending_x = 0;
+            if (!dev::finite_nz(tot[1]) && ks->bnorm != 0.0) {
+                ks->status = GW_BREAKDOWN;
+                ks->done = 1;
+            }
+            break;
+        case FIN_CG_BETA_FIRST:
+            ks->beta = 0.0;
+            ks->rz = tot[0];
+            break;
+        case FIN_CG_BETA:
+            // Polak-Ribiere: z.(r - r_old) = -alpha z.q since r - r_old = -alpha q
+            ks->beta = ks->flexible ? (-ks->alpha * tot[1]) / ks->rz : tot[0] / ks->rz;
+            ks->rz = tot[0];
+            break;
+        case FIN_CG_ALPHA:
+            ks->pq = tot[0];
+            if (!dev::finite_nz(tot[0]) || !isfinite(ks->rz)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+            else ks->alpha = ks->rz / tot[0];
+            break;
+        case FIN_CG_CONV: {
+            ks->rr = tot[0];
+            ks->iters += 1;
+            double rn = sqrt(tot[0]);
+            if (!isfinite(rn)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+            else if (rn <= ks->tol) { ks->status = GW_OK; ks->done = 1; }
+            else if (ks->iters >= ks->maxiter) { ks->status = GW_NOT_CONVERGED; ks->done = 1; }
+            break;
         }
+        case FIN_TRUE_RES:
+            ks->rel_true = sqrt(tot[0]) / ks->bnorm;
+            break;
+        case FIN_BCG_ALPHA:
+            ks->rv = tot[0];
+            if (!dev::finite_nz(tot[0])) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+            else ks->alpha = ks->rho / tot[0];
+            break;
+        case FIN_BCG_S: {
+            ks->ss = tot[0];
+            ks->iters += 1;
+            double sn = sqrt(tot[0]);
+            if (!isfinite(sn)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+            else if (sn <= ks->tol) { ks->status = GW_OK; ks->rr = tot[0]; ks->done = 1; ks->pending_x = 1; }
+            break;
+        }
+        case FIN_BCG_OMEGA:
+            ks->ts = tot[0];
+            ks->tt = tot[1];
+            if (!dev::finite_nz(tot[1])) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+            else {
+                double om = tot[0] / tot[1];
+                if (!dev::finite_nz(om)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+                else ks->omega = om;
+            }
+            break;
+        case FIN_BCG_XR: {
+            if (ks->pending_x) { ks->pending_x = 0; break; }
+            ks->rr = tot[0];
+            double rn = sqrt(tot[0]);
+            if (!isfinite(rn)) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+            else if (rn <= ks->tol) { ks->status = GW_OK; ks->done = 1; }
+            else if (ks->iters >= ks->maxiter) { ks->status = GW_NOT_CONVERGED; ks->done = 1; }
+            else {
+                ks->rho_prev = ks->rho;
+                ks->rho = tot[1];
+                if (!dev::finite_nz(tot[1])) { ks->status = GW_BREAKDOWN; ks->done = 1; }
+                else ks->beta = (ks->rho / ks->rho_prev) * (ks->alpha / ks->omega);
+            }
+            break;
+        }
+        default: break;
     }
 }
 
+template <int G>
 __global__ void k_spmv_f64(CsrView A, const double *__restrict__ x, double *__restrict__ y) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < A.n) y[i] = row_dot(A, i, x);
+    const int64_t n = A.n;
+    GROUP_ROW(G)
+    double s = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return x[j]; });
+    if (lane == 0) y[i] = s;
 }
 
 void ensure_krylov_workspace(amg_hierarchy *H, int nvec) {
@@ -511,7 +582,61 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// Host-side helper binding the level-0 operator and the scalar block.
+struct Kry {
+    amg_hierarchy *H;
+    CsrView A;
+    int G;
+    int64_t n;
+    unsigned g1, gG;  // grids of element-wise and grouped kernels
+    double *part;
+    KScalars *ks;
+    hipStream_t s;
+    double rtol;
+    double vec, abytes;
+
+    Kry(amg_hierarchy *H_, hipStream_t s_, double rtol_) : H(H_), s(s_), rtol(rtol_) {
+        A = view(H->L[0].A);
+        G = H->L[0].A.grp;
+        n = A.n;
+        g1 = kgrid(n, 1);
+        gG = kgrid(n, G);
+        part = H->partials.p;
+        ks = H->ks.p;
+        vec = 8.0 * n;
+        abytes = csr_bytes(A.n, A.nnz, 8);
+    }
+    void fin(int op, unsigned nb) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kKBlock), 0, s, op, nb, part, rtol, ks);
+    }
+    void init(const double *b, const double *x, double *r, double *rh, double *p, double *v, bool first) {
+        {
+            ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec + (rh ? 3 * vec : 0), s);
+#define L_INIT(GG, ...) hipLaunchKernelGGL((k_kr_init<GG>), dim3(gG), dim3(kKBlock), 0, s, A, b, x, r, rh, p, v, part)
+            DISPATCH_G(G, L_INIT, 0)
+#undef L_INIT
+        }
+        fin(first ? FIN_INIT_FIRST : FIN_INIT_RESTART, gG);
+    }
+    void true_res(const double *b, const double *x) {
+        {
+            ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s);
+#define L_TR(GG, ...) hipLaunchKernelGGL((k_true_res<GG>), dim3(gG), dim3(kKBlock), 0, s, A, b, x, part)
+            DISPATCH_G(G, L_TR, 0)
+#undef L_TR
+        }
+        fin(FIN_TRUE_RES, gG);
+    }
+};
+
 }  // namespace
+
+int lane_group_for(double mean_row_len) {
+    if (mean_row_len <= 3.0) return 1;
+    if (mean_row_len <= 12.0) return 4;
+    if (mean_row_len <= 48.0) return 16;
+    return 64;
+}
 
 void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s) {
     if (H->nlev == 0) {
@@ -526,18 +651,21 @@ void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, h
     GW_HIP(hipGetLastError());
 }
 
-void spmv_f64(const CsrView &A, const double *x, double *y, hipStream_t s) {
+void spmv_f64(const CsrView &A, int grp, const double *x, double *y, hipStream_t s) {
     ProfScope ps(K_KRYLOV_SPMV, csr_bytes(A.n, A.nnz, 8) + 16.0 * A.n, s);
-    hipLaunchKernelGGL(k_spmv_f64, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, x, y);
+    const int64_t n = A.n;
+#define L_SPMV(GG, ...) hipLaunchKernelGGL((k_spmv_f64<GG>), dim3(grid_rows(n, GG)), dim3(kBlock), 0, s, A, x, y)
+    DISPATCH_G(grp, L_SPMV, 0)
+#undef L_SPMV
     GW_HIP(hipGetLastError());
 }
 
 int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp, amg_solve_info *info,
                hipStream_t s) {
     const double t0 = now_ms();
-    const CsrView A = view(H->L[0].A);
-    const int64_t n = A.n;
     ensure_krylov_workspace(H, 5);
+    Kry K(H, s, sp.rtol);
+    const int64_t n = K.n;
     double *r = H->kvec.p, *z = r + n, *pa = z + n, *pb = pa + n, *q = pb + n;
     KScalars k0{};
     k0.maxiter = std::max(0, sp.maxiter);
@@ -545,13 +673,7 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
     k0.status = GW_NOT_CONVERGED;
     write_ks(H, k0, s);
     fill_f64(x, 0.0, n, s);
-    const unsigned g = kgrid(n);
-    const double vec = 8.0 * n, abytes = csr_bytes(A.n, A.nnz, 8);
-    {
-        ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec, s);
-        hipLaunchKernelGGL(k_kr_init, dim3(g), dim3(kKBlock), 0, s, A, b, x, r, (double *)nullptr, pa,
-                           (double *)nullptr, sp.rtol, 1, H->partials.p, H->ks.p);
-    }
+    K.init(b, x, r, nullptr, pa, nullptr, true);
     KScalars k = read_ks(H, s);
     int restarts = 0;
     if (k.bnorm == 0.0) {
@@ -560,30 +682,37 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
     }
     const int check = std::max(1, sp.check_every);
     int32_t *done = &H->ks.p->done;
+    const int G = K.G;
     int parity = 0;
     for (;;) {
         if (!k.done) {
             vcycle(H, r, z, done, s);
             {
-                ProfScope ps(K_KRYLOV_DOT, 2 * vec, s);
-                hipLaunchKernelGGL(k_cg_beta, dim3(g), dim3(kKBlock), 0, s, n, r, z, q, 1, H->partials.p, H->ks.p);
+                ProfScope ps(K_KRYLOV_DOT, 3 * K.vec, s);
+                hipLaunchKernelGGL(k_cg_dot, dim3(K.g1), dim3(kKBlock), 0, s, n, r, z, q, K.part, K.ks);
             }
+            K.fin(FIN_CG_BETA_FIRST, K.g1);
             for (;;) {
                 for (int c = 0; c < check; ++c) {
                     double *po = parity ? pb : pa, *pn = parity ? pa : pb;
                     {
-                        ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec, s);
-                        hipLaunchKernelGGL(k_cg_spmv, dim3(g), dim3(kKBlock), 0, s, A, z, po, pn, q, H->partials.p, H->ks.p);
+                        ProfScope ps(K_KRYLOV_SPMV, K.abytes + 4 * K.vec, s);
+#define L_CGS(GG, ...) hipLaunchKernelGGL((k_cg_spmv<GG>), dim3(K.gG), dim3(kKBlock), 0, s, K.A, z, po, pn, q, K.part, K.ks)
+                        DISPATCH_G(G, L_CGS, 0)
+#undef L_CGS
                     }
+                    K.fin(FIN_CG_ALPHA, K.gG);
                     {
-                        ProfScope ps(K_KRYLOV_UPDATE, 6 * vec, s);
-                        hipLaunchKernelGGL(k_cg_update, dim3(g), dim3(kKBlock), 0, s, n, x, r, pn, q, H->partials.p, H->ks.p);
+                        ProfScope ps(K_KRYLOV_UPDATE, 6 * K.vec, s);
+                        hipLaunchKernelGGL(k_cg_update, dim3(K.g1), dim3(kKBlock), 0, s, n, x, r, pn, q, K.part, K.ks);
                     }
+                    K.fin(FIN_CG_CONV, K.g1);
                     vcycle(H, r, z, done, s);
                     {
-                        ProfScope ps(K_KRYLOV_DOT, 3 * vec, s);
-                        hipLaunchKernelGGL(k_cg_beta, dim3(g), dim3(kKBlock), 0, s, n, r, z, q, 0, H->partials.p, H->ks.p);
+                        ProfScope ps(K_KRYLOV_DOT, 3 * K.vec, s);
+                        hipLaunchKernelGGL(k_cg_dot, dim3(K.g1), dim3(kKBlock), 0, s, n, r, z, q, K.part, K.ks);
                     }
+                    K.fin(FIN_CG_BETA, K.g1);
                     parity ^= 1;
                 }
                 GW_HIP(hipGetLastError());
@@ -591,18 +720,14 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
                 if (k.done) break;
             }
         }
-        {
-            ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s);
-            hipLaunchKernelGGL(k_true_res, dim3(g), dim3(kKBlock), 0, s, A, b, x, H->partials.p, H->ks.p);
-        }
+        K.true_res(b, x);
         k = read_ks(H, s);
         if (k.status == GW_BREAKDOWN) break;
         if (k.rel_true <= sp.rtol) { k.status = GW_OK; break; }
         if (k.iters >= k.maxiter || restarts >= 8) { k.status = GW_NOT_CONVERGED; break; }
         ++restarts;
         parity = 0;
-        hipLaunchKernelGGL(k_kr_init, dim3(g), dim3(kKBlock), 0, s, A, b, x, r, (double *)nullptr, pa,
-                           (double *)nullptr, sp.rtol, 0, H->partials.p, H->ks.p);
+        K.init(b, x, r, nullptr, pa, nullptr, false);
         k = read_ks(H, s);
     }
     if (info) {
@@ -620,9 +745,9 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
 int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                     amg_solve_info *info, hipStream_t s) {
     const double t0 = now_ms();
-    const CsrView A = view(H->L[0].A);
-    const int64_t n = A.n;
     ensure_krylov_workspace(H, 8);
+    Kry K(H, s, sp.rtol);
+    const int64_t n = K.n;
     double *r = H->kvec.p, *rh = r + n, *p = rh + n, *v = p + n, *sv = v + n, *t = sv + n, *ph = t + n,
            *sh = ph + n;
     KScalars k0{};
@@ -630,13 +755,7 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
     k0.status = GW_NOT_CONVERGED;
     write_ks(H, k0, s);
     fill_f64(x, 0.0, n, s);
-    const unsigned g = kgrid(n);
-    const double vec = 8.0 * n, abytes = csr_bytes(A.n, A.nnz, 8);
-    {
-        ProfScope ps(K_KRYLOV_SPMV, abytes + 6 * vec, s);
-        hipLaunchKernelGGL(k_kr_init, dim3(g), dim3(kKBlock), 0, s, A, b, x, r, rh, p, v, sp.rtol, 1, H->partials.p,
-                           H->ks.p);
-    }
+    K.init(b, x, r, rh, p, v, true);
     KScalars k = read_ks(H, s);
     int restarts = 0;
     if (k.bnorm == 0.0) {
@@ -645,47 +764,52 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
     }
     const int check = std::max(1, sp.check_every);
     int32_t *done = &H->ks.p->done;
+    const int G = K.G;
     for (;;) {
         while (!k.done) {
             for (int c = 0; c < check; ++c) {
                 {
-                    ProfScope ps(K_KRYLOV_UPDATE, 4 * vec, s);
-                    hipLaunchKernelGGL(k_bcg_p, dim3(g), dim3(kKBlock), 0, s, n, r, p, v, H->ks.p);
+                    ProfScope ps(K_KRYLOV_UPDATE, 4 * K.vec, s);
+                    hipLaunchKernelGGL(k_bcg_p, dim3(K.g1), dim3(kKBlock), 0, s, n, r, p, v, K.ks);
                 }
                 vcycle(H, p, ph, done, s);
                 {
-                    ProfScope ps(K_KRYLOV_SPMV, abytes + 3 * vec, s);
-                    hipLaunchKernelGGL(k_bcg_v, dim3(g), dim3(kKBlock), 0, s, A, ph, v, rh, H->partials.p, H->ks.p);
+                    ProfScope ps(K_KRYLOV_SPMV, K.abytes + 3 * K.vec, s);
+#define L_BV(GG, ...) hipLaunchKernelGGL((k_bcg_v<GG>), dim3(K.gG), dim3(kKBlock), 0, s, K.A, ph, v, rh, K.part, K.ks)
+                    DISPATCH_G(G, L_BV, 0)
+#undef L_BV
                 }
+                K.fin(FIN_BCG_ALPHA, K.gG);
                 {
-                    ProfScope ps(K_KRYLOV_UPDATE, 3 * vec, s);
-                    hipLaunchKernelGGL(k_bcg_s, dim3(g), dim3(kKBlock), 0, s, n, r, v, sv, H->partials.p, H->ks.p);
+                    ProfScope ps(K_KRYLOV_UPDATE, 3 * K.vec, s);
+                    hipLaunchKernelGGL(k_bcg_s, dim3(K.g1), dim3(kKBlock), 0, s, n, r, v, sv, K.part, K.ks);
                 }
+                K.fin(FIN_BCG_S, K.g1);
                 vcycle(H, sv, sh, done, s);
                 {
-                    ProfScope ps(K_KRYLOV_SPMV, abytes + 3 * vec, s);
-                    hipLaunchKernelGGL(k_bcg_t, dim3(g), dim3(kKBlock), 0, s, A, sh, t, sv, H->partials.p, H->ks.p);
+                    ProfScope ps(K_KRYLOV_SPMV, K.abytes + 3 * K.vec, s);
+#define L_BT(GG, ...) hipLaunchKernelGGL((k_bcg_t<GG>), dim3(K.gG), dim3(kKBlock), 0, s, K.A, sh, t, sv, K.part, K.ks)
+                    DISPATCH_G(G, L_BT, 0)
+#undef L_BT
                 }
+                K.fin(FIN_BCG_OMEGA, K.gG);
                 {
-                    ProfScope ps(K_KRYLOV_UPDATE, 8 * vec, s);
-                    hipLaunchKernelGGL(k_bcg_xr, dim3(g), dim3(kKBlock), 0, s, n, x, r, ph, sh, sv, t, rh, H->partials.p,
-                                       H->ks.p);
+                    ProfScope ps(K_KRYLOV_UPDATE, 8 * K.vec, s);
+                    hipLaunchKernelGGL(k_bcg_xr, dim3(K.g1), dim3(kKBlock), 0, s, n, x, r, ph, sh, sv, t, rh, K.part,
+                                       K.ks);
                 }
+                K.fin(FIN_BCG_XR, K.g1);
             }
             GW_HIP(hipGetLastError());
             k = read_ks(H, s);
         }
-        {
-            ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s);
-            hipLaunchKernelGGL(k_true_res, dim3(g), dim3(kKBlock), 0, s, A, b, x, H->partials.p, H->ks.p);
-        }
+        K.true_res(b, x);
         k = read_ks(H, s);
         if (k.status == GW_BREAKDOWN) break;
         if (k.rel_true <= sp.rtol) { k.status = GW_OK; break; }
         if (k.iters >= k.maxiter || restarts >= 8) { k.status = GW_NOT_CONVERGED; break; }
         ++restarts;
-        hipLaunchKernelGGL(k_kr_init, dim3(g), dim3(kKBlock), 0, s, A, b, x, r, rh, p, v, sp.rtol, 0, H->partials.p,
-                           H->ks.p);
+        K.init(b, x, r, rh, p, v, false);
         k = read_ks(H, s);
     }
     if (info) {

@@ -143,7 +143,7 @@ def _compare_hierarchy(gw, ref, H_gpu, H_ref, tag):
     assert np.array_equal(host(piv), piv_ref)
     assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64)), f"{tag} coarse LU"
     Ac = H_ref.level(H_ref.nlevels - 1).A.dense()
-    Ainv = host(inv).reshape(nd, nd).T  # column-major
+    Ainv = host(inv).reshape(nd, nd)  # row-major
     assert np.allclose(Ainv @ Ac, np.eye(nd), atol=1e-9)
 
 
