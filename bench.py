@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests in the served-stream measurement (0 = skip)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.75,
+                    help="Poisson arrival rate as a fraction of the measured saturation throughput")
     return ap.parse_args()
 
 
@@ -121,6 +126,76 @@ def cpu_baseline(prob, precision):
     }
 
 
+def _make_problem(a):
+    import gwinputs as gi
+    return gi.problem_for_arrival(a)
+
+
+def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
+    """Served stream: cubic grids 32^3..192^3 (uniform side), ln K variance in
+    {1,2,4}, correlation length 4..16 cells, each request a mixed-precision
+    flow solve plus the travel-time pair.  K fields are generated before the
+    clock starts.  First a burst of all requests measures the saturation
+    throughput; then Poisson arrivals at `load` x saturation give latencies."""
+    import concurrent.futures as cf
+    import threading
+
+    import gwinputs as gi
+    arrivals = gi.serve_stream(n_requests, 1.0, seed=seed)
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        probs = list(ex.map(_make_problem, arrivals))
+    ap = gw.AmgParams(precision=gw.PRECISION_MIXED)
+    sp = gw.SolveParams(rtol=1e-8)
+    budget = int(os.environ.get("GWAMG_SERVE_BUDGET", str(96 << 30)))
+
+    def zone(p):
+        return (0, p.grid.ny, 0, max(1, p.grid.nz // 2))
+
+    # saturation: everything at once
+    q = gw.Queue(budget, slots)
+    t0 = q.clock()
+    tick = [q.submit(p, ap, ap, sp, zone=zone(p), want=()) for p in probs]
+    q.drain()
+    makespan = q.clock() - t0
+    res = [q.poll(t)[0] for t in tick]
+    q.close()
+    sat = n_requests / makespan
+    bad = sum(r.status != gw.OK for r in res)
+    # Poisson arrivals at load x saturation
+    rate = load * sat
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    when = np.cumsum(gaps) - gaps[0]
+    q = gw.Queue(budget, slots)
+    base = q.clock()
+    tick = []
+    for k, p in enumerate(probs):
+        t_arr = base + float(when[k])
+        while q.clock() < t_arr:
+            time.sleep(min(0.002, max(0.0, t_arr - q.clock())))
+        tick.append(q.submit(p, ap, ap, sp, zone=zone(p), want=(), t_arrival=t_arr))
+    q.drain()
+    end = q.clock()
+    res2 = [q.poll(t)[0] for t in tick]
+    q.close()
+    lat = np.array([r.latency for r in res2]) * 1e3
+    bad += sum(r.status != gw.OK for r in res2)
+    cells = np.array([p.grid.n for p in probs])
+    return {
+        "requests": n_requests, "slots": slots, "precision": "f32-hierarchy/f64-krylov",
+        "saturation_solves_per_s": round(sat, 3),
+        "offered_load": load, "offered_rate_per_s": round(rate, 3),
+        "achieved_solves_per_s": round(n_requests / (end - base), 3),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                       "p99": round(float(np.percentile(lat, 99)), 2),
+                       "mean": round(float(lat.mean()), 2)},
+        "cells_mean": int(cells.mean()), "cells_max": int(cells.max()),
+        "failed": int(bad),
+        "flow_iters_mean": round(float(np.mean([r.flow.iters for r in res2])), 1),
+        "tt_iters_mean": round(float(np.mean([r.tt[0].iters for r in res2])), 1),
+    }
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -190,6 +265,12 @@ def main():
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
                for k, v in stats.items() if v["launches"]}
 
+    serve = None
+    if args.serve_requests > 0:
+        print(f"[bench] served stream, {args.serve_requests} requests ...", file=sys.stderr, flush=True)
+        serve = serving(gw, args.serve_requests, args.serve_slots, args.serve_load)
+        print(f"[bench] served stream: {serve}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -216,6 +297,7 @@ def main():
         "tt_iters": list(titers[-1]),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serve,
         "kernels": kernels,
     }
     print(json.dumps(out))

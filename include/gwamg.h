@@ -260,6 +260,7 @@ typedef struct {
     amg_solve_info tt[2];
     double t_arrival, t_start, t_done; /* seconds on the queue clock      */
     size_t bytes_reserved;             /* admission footprint             */
+    char error[160];                   /* message when status < 0         */
 } gw_result;
 
 /* hbm_budget_bytes: device memory the queue may reserve for requests in

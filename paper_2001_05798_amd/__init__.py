@@ -93,11 +93,16 @@ class RequestC(C.Structure):
 class ResultC(C.Structure):
     _fields_ = [("status", C.c_int32), ("flow", SolveInfoC), ("tt", SolveInfoC * 2),
                 ("t_arrival", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("bytes_reserved", C.c_size_t)]
+                ("bytes_reserved", C.c_size_t), ("error", C.c_char * 160)]
 
 
 # ------------------------------------------------------------------ load --
 def _load():
+    # PyTorch ships its own HIP runtime under the soname libamdhip64.so.7.
+    # Loading torch first makes the library bind to that same runtime; the
+    # other order would bring a second HIP runtime into the process, and only
+    # one of the two can own the device.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_05798_amd.build`")
     L = C.CDLL(LIB_PATH)
@@ -384,3 +389,82 @@ def prof_read() -> dict:
 
 def trim() -> None:
     _check(_lib.gw_trim())
+
+
+# -------------------------------------------------------------- serving --
+@dataclasses.dataclass
+class Result:
+    status: int
+    flow: SolveInfo
+    tt: List[SolveInfo]
+    t_arrival: float
+    t_start: float
+    t_done: float
+    bytes_reserved: int
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+class Queue:
+    """Continuous-batching queue of flow + travel-time requests.
+
+    Inputs (K, wells) and outputs (h, tau, c) are host numpy arrays that the
+    queue keeps referenced until the ticket's result has been polled.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4):
+        q = C.c_void_p(0)
+        _check(_lib.queue_create(C.c_size_t(int(hbm_budget_bytes)), int(max_slots), C.byref(q)))
+        self._q = q
+        self._keep = {}
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        q = getattr(self, "_q", None)
+        if q is not None and q.value:
+            _lib.queue_destroy(q)
+            self._q = C.c_void_p(0)
+        self._keep = {}
+
+    def clock(self) -> float:
+        return float(_lib.queue_clock(self._q))
+
+    def submit(self, problem, flow_params: AmgParams, tt_params: AmgParams, sp: SolveParams,
+               zone=None, want=("h", "tau", "c"), t_arrival: float = -1.0):
+        import numpy as np
+        g = problem.grid
+        n = g.n
+        K = np.ascontiguousarray(problem.K, dtype=np.float64)
+        wl = (GwWell * max(1, len(problem.wells)))(*[GwWell(w.ix, w.iy, w.iz, w.q) for w in problem.wells])
+        outs = {k: np.zeros(n) for k in want}
+        z = zone if zone is not None else (0, g.ny, 0, g.nz)
+        req = RequestC(grid_c(g), K.ctypes.data, GwBc(problem.h_west, problem.h_east), C.addressof(wl),
+                       len(problem.wells), float(problem.phi), GwZone(*z), flow_params.c(), tt_params.c(),
+                       sp.c(), outs["h"].ctypes.data if "h" in outs else None,
+                       outs["tau"].ctypes.data if "tau" in outs else None,
+                       outs["c"].ctypes.data if "c" in outs else None, float(t_arrival))
+        t = C.c_uint64(0)
+        _check(_lib.queue_submit(self._q, C.byref(req), C.byref(t)))
+        self._keep[t.value] = (K, wl, outs)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else (Result, outputs dict)."""
+        r = ResultC()
+        st = _lib.queue_poll(self._q, C.c_uint64(ticket), C.byref(r))
+        if st == PENDING:
+            return None
+        if st == EINVAL and ticket not in self._keep:
+            raise GwError(st, last_error())
+        K, wl, outs = self._keep.pop(ticket)
+        res = Result(r.status, SolveInfo.of(r.flow), [SolveInfo.of(r.tt[0]), SolveInfo.of(r.tt[1])],
+                     r.t_arrival, r.t_start, r.t_done, int(r.bytes_reserved), r.error.decode(errors="replace"))
+        return res, outs
+
+    def drain(self) -> None:
+        _check(_lib.queue_drain(self._q))

@@ -1,0 +1,114 @@
+"""Serving queue: admission, ordering and results alone vs in a mix.
+
+CPU tests exercise the host-side scheduler (argument checks, HBM-budget
+admission, a request that fails on a host without GPU comes back as a
+finished ticket with EDEVICE instead of hanging).  GPU tests check that a
+request gives the same result alone and inside a concurrent mix.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import gwinputs as gi
+
+try:
+    import paper_2001_05798_amd as gw
+except ImportError:  # library not built
+    gw = None
+
+needs_lib = pytest.mark.skipif(gw is None, reason="library not built")
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def _params():
+    return gw.AmgParams(precision=gw.PRECISION_MIXED), gw.SolveParams(rtol=1e-8)
+
+
+@needs_lib
+def test_queue_argument_checks_cpu():
+    q = gw.Queue(hbm_budget_bytes=1 << 30, max_slots=2)
+    ap, sp = _params()
+    # far larger than the budget: refused at submission
+    big = gi.Problem(gi.Grid(512, 512, 256), np.ones(1))
+    with pytest.raises(gw.GwError) as e:
+        q.submit(big, ap, ap, sp)
+    assert e.value.status == gw.ENOMEM
+    bad = gi.Problem(gi.Grid(8, 8, 8), np.full(512, 1e-4), phi=0.0)
+    with pytest.raises(gw.GwError) as e:
+        q.submit(bad, ap, ap, sp)
+    assert e.value.status == gw.EINVAL
+    with pytest.raises(gw.GwError):
+        q.poll(12345)
+    q.close()
+
+
+@needs_lib
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_queue_without_device_finishes_with_error():
+    q = gw.Queue(hbm_budget_bytes=1 << 30, max_slots=2)
+    ap, sp = _params()
+    p = gi.homogeneous_slab(8, 8)
+    t = q.submit(p, ap, ap, sp)
+    q.drain()
+    res, _ = q.poll(t)
+    assert res.status == gw.EDEVICE
+    assert res.t_done >= res.t_start >= res.t_arrival >= 0
+    q.close()
+
+
+def _serve(problems, slots, budget=64 << 30):
+    ap, sp = _params()
+    q = gw.Queue(hbm_budget_bytes=budget, max_slots=slots)
+    tickets = [q.submit(p, ap, ap, sp, zone=(0, p.grid.ny, 0, max(1, p.grid.nz // 2))) for p in problems]
+    q.drain()
+    out = [q.poll(t) for t in tickets]
+    q.close()
+    return out
+
+
+@pytest.mark.gpu
+def test_alone_equals_in_mix():
+    if gw is None or not _has_gpu():
+        pytest.skip("no GPU")
+    print("[case] serve alone vs mix", flush=True)
+    target = gi.heterogeneous_aquifer(40, 36, 24, 2.0, 6, 101)
+    others = [gi.heterogeneous_aquifer(s, s, s, s2, lam, seed) for s, s2, lam, seed in
+              [(48, 4.0, 8, 7), (32, 1.0, 4, 8), (56, 2.0, 12, 9), (36, 4.0, 16, 10), (44, 1.0, 5, 11)]]
+    (alone_res, alone_out), = _serve([target], slots=1)
+    assert alone_res.status == gw.OK, (alone_res.status, alone_res.error)
+    mix = _serve(others[:3] + [target] + others[3:], slots=4)
+    mix_res, mix_out = mix[3]
+    assert all(r.status == gw.OK for r, _ in mix), [r.status for r, _ in mix]
+    for k in ("h", "tau", "c"):
+        a, b = alone_out[k], mix_out[k]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+        print(f"  {k}: rel diff {rel:.2e} bitwise {np.array_equal(a, b)}", flush=True)
+        assert rel <= 1e-6  # mixed-precision tolerance
+    # requests really overlapped: some started before others finished
+    starts = sorted(r.t_start for r, _ in mix)
+    dones = sorted(r.t_done for r, _ in mix)
+    assert starts[1] < dones[0]
+
+
+@pytest.mark.gpu
+def test_admission_by_budget():
+    if gw is None or not _has_gpu():
+        pytest.skip("no GPU")
+    print("[case] serve admission", flush=True)
+    probs = [gi.heterogeneous_aquifer(48, 48, 48, 2.0, 8, s) for s in range(4)]
+    ap, sp = _params()
+    # room for one request at a time although four slots exist
+    one = 48 ** 3 * 1700 + (64 << 20)
+    res = _serve(probs, slots=4, budget=int(one * 1.5))
+    assert all(r.status == gw.OK for r, _ in res)
+    spans = sorted((r.t_start, r.t_done) for r, _ in res)
+    for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
+        assert s1 >= d0 - 1e-6  # serialized by the budget
