@@ -19,6 +19,7 @@ OK, NOT_CONVERGED, BREAKDOWN, PENDING = 0, 1, 2, 3
 EINVAL, ENOMEM, SINGULAR, EDEVICE, EAGAIN = -1, -2, -3, -4, -5
 SMOOTHER_JACOBI, SMOOTHER_SPAI0, SMOOTHER_NONE = 0, 1, 2
 PRECISION_FP64, PRECISION_MIXED = 0, 1
+TT_EPS_STRONG = 0.25
 
 STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", PENDING: "PENDING",
                 EINVAL: "EINVAL", ENOMEM: "ENOMEM", SINGULAR: "SINGULAR", EDEVICE: "EDEVICE",
@@ -212,6 +213,15 @@ class AmgParams:
     def c(self) -> AmgParamsC:
         return AmgParamsC(self.eps_strong, self.smoother, self.omega, self.npre, self.npost,
                           self.n_coarse, self.max_levels, self.precision, self.seed)
+
+    @classmethod
+    def travel_time(cls, **kw) -> "AmgParams":
+        """Defaults for the advective travel-time system: a larger strength
+        threshold (0.25) keeps aggregates small along streamlines; with the
+        flow default (0.08) BiCGSTAB needs 3x more iterations on 1M cells and
+        breaks down on the larger served grids."""
+        kw.setdefault("eps_strong", TT_EPS_STRONG)
+        return cls(**kw)
 
 
 @dataclasses.dataclass

@@ -305,6 +305,35 @@ def test_status_codes(gw, ref):
     assert e.value.status == gw.EINVAL
 
 
+def test_full_size_travel_time_parity(gw, ref):
+    # travel time on the Darcy velocities of the 1M-cell aquifer, with the
+    # travel-time hierarchy settings the benchmark uses; both sides get the
+    # same fluxes (computed from the oracle's heads) so that no face can flip
+    # its upwind direction between the two
+    _say("full-size 128x128x64 travel-time parity")
+    p = gi.heterogeneous_aquifer(128, 128, 64, 4.0, 8, 11)
+    fr = ref.solve_flow(p, ref.AmgParams(), rtol=1e-8)
+    qx, qy, qz = ref.darcy_flux(p, fr.h)
+    g = p.grid
+    zone = (0, g.ny, 0, g.nz // 2)
+    ap = ref.AmgParams(eps_strong=gw.TT_EPS_STRONG)
+    tr = ref.solve_travel_time(g, qx, qy, qz, p.phi, ap, rtol=1e-8, zone=zone)
+    tau = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    c = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    st, infos = gw.tt_solve(g, dev(qx), dev(qy), dev(qz), p.phi, zone, gpu_params(gw, ap), gw.SolveParams(rtol=1e-8),
+                            tau, c)
+    assert st == gw.OK
+    for name, got, want, inf, oinf in (("tau", host(tau), tr.tau, infos[0], tr.info[0]),
+                                       ("c", host(c), tr.c, infos[1], tr.info[1])):
+        err = np.linalg.norm(got - want) / np.linalg.norm(want)
+        _say(f"  {name}: iters gpu {inf.iters} oracle {oinf.iters} rel err {err:.3e}")
+        assert inf.rel_res_true <= 1e-8 and err <= 1e-8
+    tau_ex = ref.tt_sweep(tr.A, tr.b_tau, fr.h)
+    err_ex = np.linalg.norm(host(tau) - tau_ex) / np.linalg.norm(tau_ex)
+    _say(f"  tau vs exact sweep {err_ex:.2e}")
+    assert err_ex < 1e-6
+
+
 def test_full_size_flow_parity(gw, ref):
     # the 1M-cell lognormal aquifer (variance 4, correlation length 8, four
     # wells) in the benchmark's configuration: aggregates of every level bit

@@ -66,8 +66,9 @@ def test_queue_without_device_finishes_with_error():
 
 def _serve(problems, slots, budget=64 << 30):
     ap, sp = _params()
+    tp = gw.AmgParams.travel_time(precision=gw.PRECISION_MIXED)
     q = gw.Queue(hbm_budget_bytes=budget, max_slots=slots)
-    tickets = [q.submit(p, ap, ap, sp, zone=(0, p.grid.ny, 0, max(1, p.grid.nz // 2))) for p in problems]
+    tickets = [q.submit(p, ap, tp, sp, zone=(0, p.grid.ny, 0, max(1, p.grid.nz // 2))) for p in problems]
     q.drain()
     out = [q.poll(t) for t in tickets]
     q.close()
