@@ -232,6 +232,9 @@ typedef struct {
 
 /* on = 1 starts recording (and clears the table), 0 stops. */
 int gw_prof_enable(int32_t on);
+/* Record only the kernel class `name` (a name gw_prof_read reports), so the
+ * event pairs cost nothing elsewhere; NULL or "" records every class. */
+int gw_prof_select(const char *name);
 /* Copy up to max entries [host]; *n receives the number of kernels. */
 int gw_prof_read(gw_kernel_stat *out, int32_t max, int32_t *n);
 

@@ -131,6 +131,7 @@ def _load():
                                C.POINTER(SolveParamsC), vp, vp, C.POINTER(SolveInfoC), vp]),
         "gw_prof_enable": (C.c_int, [i32]),
         "gw_prof_read": (C.c_int, [C.POINTER(KernelStatC), i32, C.POINTER(i32)]),
+        "gw_prof_select": (C.c_int, [C.c_char_p]),
         "queue_create": (C.c_int, [C.c_size_t, i32, C.POINTER(vp)]),
         "queue_clock": (f64, [vp]),
         "queue_submit": (C.c_int, [vp, C.POINTER(RequestC), C.POINTER(C.c_uint64)]),
@@ -387,6 +388,10 @@ def amg_coarse_export(H: Hierarchy, lu=None, piv=None, inv=None, stream=None) ->
 # ------------------------------------------------------------ profiling --
 def prof_enable(on: bool) -> None:
     _check(_lib.gw_prof_enable(1 if on else 0))
+
+
+def prof_select(name: Optional[str]) -> None:
+    _check(_lib.gw_prof_select(name.encode() if name else None))
 
 
 def prof_read() -> dict:

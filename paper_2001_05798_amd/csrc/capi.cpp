@@ -10,8 +10,6 @@
 
 using namespace gw;
 
-amg_hierarchy::~amg_hierarchy() { delete ks_host; }
-
 size_t amg_hierarchy::bytes() const {
     size_t b = lu.bytes() + inv.bytes() + piv.bytes() + kvec.bytes() + partials.bytes() + ks.bytes();
     for (int l = 0; l < nlev || (l == 0 && !L.empty()); ++l) b += L[l].bytes();

@@ -57,6 +57,21 @@ __device__ __forceinline__ T block_sum(T v, T *sm) {
     return t;
 }
 
+// Block maximum (valid in every thread).  `sm` needs blockDim.x / 64 entries.
+template <class T>
+__device__ __forceinline__ T block_max(T v, T *sm) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    T t = sm[0];
+    for (int i = 1; i < nw; ++i) t = sm[i] > t ? sm[i] : t;
+    __syncthreads();
+    return t;
+}
+
 // First stage of a grid-wide sum: every block stores its NV block sums in
 // partials[b*NV + k].  A one-block finalize kernel adds them in block order
 // (fixed), so totals do not depend on scheduling.  Two kernels instead of a

@@ -90,7 +90,13 @@ struct DBuf {
     T *get() const { return p; }
 };
 
-// Pinned host staging for small device->host reads.
+// 4 KiB of pinned host memory owned by the calling host thread, for the
+// small device<->host copies of sizes and Krylov scalars (allocated once per
+// thread: pinned allocation is far too slow to do per call).
+constexpr size_t kHostStageBytes = 4096;
+void *host_stage();
+
+// Pinned host buffer.
 struct Pinned {
     void *p = nullptr;
     size_t n = 0;
@@ -196,8 +202,6 @@ struct amg_hierarchy {
     int kvec_count = 0;
     gw::DBuf<double> partials;
     gw::DBuf<gw::KScalars> ks;
-    gw::Pinned *ks_host = nullptr;
-    ~amg_hierarchy();
     bool mixed() const { return prm.precision == GW_PRECISION_MIXED; }
     size_t bytes() const;
 };
@@ -214,7 +218,9 @@ inline unsigned blocks_for(int64_t n, int per_thread = 1, int block = kBlock) {
 
 // scan.hip / util
 // In place inclusive scan of a[0..n) (int32), total returned in *total (device int64).
-void scan_inclusive_i32(int32_t *a, int64_t n, int64_t *total, hipStream_t s);
+// When max_out is given, the largest element of a (before the scan) is
+// written there too.
+void scan_inclusive_i32(int32_t *a, int64_t n, int64_t *total, hipStream_t s, int32_t *max_out = nullptr);
 void fill_i32(int32_t *a, int32_t v, int64_t n, hipStream_t s);
 void fill_f64(double *a, double v, int64_t n, hipStream_t s);
 void copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t s);

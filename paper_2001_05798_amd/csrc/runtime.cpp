@@ -133,6 +133,17 @@ void pool_trim() {
 }
 
 // ------------------------------------------------------------------ pinned --
+void *host_stage() {
+    // kept for the life of the process (a thread's block is never returned,
+    // which avoids freeing pinned memory during runtime teardown)
+    static thread_local void *stage = nullptr;
+    if (!stage) {
+        GW_HIP(hipHostMalloc(&stage, kHostStageBytes, hipHostMallocDefault));
+        std::memset(stage, 0, kHostStageBytes);
+    }
+    return stage;
+}
+
 Pinned::Pinned(size_t bytes) : n(bytes) {
     GW_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
     std::memset(p, 0, bytes);
@@ -147,6 +158,7 @@ namespace {
 struct ProfState {
     std::mutex mu;
     bool on = false;
+    int only = -1;  // record one kernel class only (-1: all)
     struct Pending {
         int id;
         double bytes;
@@ -190,7 +202,7 @@ bool prof_on() { return prof().on; }
 
 ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_) : id(id_), bytes(bytes_), s(s_) {
     ProfState &P = prof();
-    if (!P.on) return;
+    if (!P.on || (P.only >= 0 && P.only != id)) return;
     std::lock_guard<std::mutex> g(P.mu);
     e0 = take_event(P);
     e1 = take_event(P);
@@ -248,6 +260,23 @@ int gw_prof_enable(int32_t on) {
         }
         P.on = on != 0;
         return GW_OK;
+    });
+}
+
+int gw_prof_select(const char *name) {
+    return gw::guarded([&] {
+        auto &P = gw::prof();
+        std::lock_guard<std::mutex> g(P.mu);
+        if (!name || !*name) {
+            P.only = -1;
+            return GW_OK;
+        }
+        for (int i = 0; i < gw::K_COUNT; ++i)
+            if (std::strcmp(name, gw::kNames[i]) == 0) {
+                P.only = i;
+                return GW_OK;
+            }
+        gw::fail(GW_EINVAL, std::string("gw_prof_select: unknown kernel ") + name);
     });
 }
 

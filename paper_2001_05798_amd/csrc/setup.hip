@@ -173,6 +173,7 @@ __global__ void k_strength_fill(CsrView A, CsrView T, const double *__restrict__
 // ------------------------------------------------------------------ MIS-2 --
 __global__ void k_mis_init(const int32_t *__restrict__ srow, int32_t n, uint32_t *__restrict__ state,
                            int32_t *und) {
+    __shared__ int32_t sm[kBlock / dev::kWave];
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int32_t c = 0;
     if (i < n) {
@@ -180,8 +181,8 @@ __global__ void k_mis_init(const int32_t *__restrict__ srow, int32_t n, uint32_t
         state[i] = kept ? ST_UND : ST_OUT;
         c = kept;
     }
-    c = dev::wave_sum(c);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(und, c);
+    c = dev::block_sum(c, sm);
+    if (threadIdx.x == 0 && c) atomicAdd(und, c);
 }
 
 // m1_i = max(key_i, max_{j in S(i)} key_j).  Skipped once a previous round
@@ -206,6 +207,7 @@ __global__ void k_mis_m1(const int32_t *__restrict__ srow, const int32_t *__rest
 __global__ void k_mis_m2(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
                          uint32_t *__restrict__ state, uint32_t salt, const uint64_t *__restrict__ m1,
                          const int32_t *prev_und, int32_t *und) {
+    __shared__ int32_t sm[kBlock / dev::kWave];
     if (*prev_und == 0) return;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int32_t left = 0;
@@ -219,8 +221,8 @@ __global__ void k_mis_m2(const int32_t *__restrict__ srow, const int32_t *__rest
         else if ((m >> 62) == ST_ROOT) state[i] = ST_OUT;
         else left = 1;
     }
-    left = dev::wave_sum(left);
-    if ((threadIdx.x & 63) == 0 && left) atomicAdd(und, left);
+    left = dev::block_sum(left, sm);
+    if (threadIdx.x == 0 && left) atomicAdd(und, left);
 }
 
 // ------------------------------------------------------------- aggregates --
@@ -278,8 +280,9 @@ __global__ void k_rho(CsrView A, const double *__restrict__ diag, unsigned long 
         for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s = s + fabs(A.val[p]);
         r = s / diag[i];
     }
-    r = dev::wave_max(r);
-    if ((threadIdx.x & 63) == 0) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(r));
+    __shared__ double sm[kBlock / dev::kWave];
+    r = dev::block_max(r, sm);
+    if (threadIdx.x == 0) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(r));
 }
 
 __global__ void k_omega(const unsigned long long *rho_bits, double *omega) {
@@ -380,8 +383,9 @@ __global__ void k_spgemm_ub(AR ar, BR br, int32_t nrows, int32_t *ub_max) {
             u += len;
         }
     }
-    u = dev::wave_max(u);
-    if ((threadIdx.x & 63) == 0) atomicMax(ub_max, u);
+    __shared__ int32_t sm[kBlock / dev::kWave];
+    u = dev::block_max(u, sm);
+    if (threadIdx.x == 0) atomicMax(ub_max, u);
 }
 
 __device__ __forceinline__ int32_t hash_slot(int32_t *keys, int hbits, int32_t J, bool &fresh) {
@@ -414,97 +418,126 @@ __device__ __forceinline__ int32_t group_max(int32_t v) {
     return v;
 }
 
-template <int G, class AR, class BR>
-__global__ void k_spgemm_sym(AR ar, BR br, int32_t nrows, int hbits, int32_t *__restrict__ cnt,
-                             int32_t *maxd, int32_t *overflow) {
-    extern __shared__ int32_t sm_keys[];
+// Inclusive prefix sum over the G lanes of a group.
+template <int G>
+__device__ __forceinline__ int32_t group_scan_incl(int32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int32_t w = __shfl_up(v, o, G);
+        if (lane >= o) v += w;
+    }
+    return v;
+}
+
+// Both passes of the product in one kernel body.  NUM = false counts the
+// distinct columns of every output row (symbolic pass); NUM = true writes
+// them, sorted, with their values.  A segment of A-side entries is taken one
+// entry per lane, all their B rows are loaded at once into an LDS stage
+// (contribution a*b formed by the loading lane), and then the staged B rows
+// are added into the hash one after another, in stream order.  A segment is
+// the longest run of entries whose contributions fit in the stage; an entry
+// that alone exceeds it is added straight from memory.
+template <int G, bool NUM, class AR, class BR, class EPI>
+__global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t *__restrict__ cnt,
+                         const int32_t *__restrict__ crow, int32_t *__restrict__ ccol, double *__restrict__ cval,
+                         EPI epi, int32_t *maxd, int32_t *overflow) {
+    extern __shared__ double sm_dbl[];
     const int32_t H = 1 << hbits;
     const int group = threadIdx.x / G, lane = threadIdx.x % G;
     const int groups = blockDim.x / G;
-    int32_t *keys = sm_keys + (size_t)group * H;
+    // per group: doubles [vals H | stage S] (NUM only), then ints [keys H | stage S]
+    double *vals = nullptr, *stV = nullptr;
+    int32_t *ibase = NUM ? reinterpret_cast<int32_t *>(sm_dbl + (size_t)groups * (H + S))
+                         : reinterpret_cast<int32_t *>(sm_dbl);
+    int32_t *keys = ibase + (size_t)group * (H + S);
+    int32_t *stJ = keys + H;
+    if (NUM) {
+        vals = sm_dbl + (size_t)group * (H + S);
+        stV = vals + H;
+    }
     const int64_t row = (int64_t)blockIdx.x * groups + group;
     const bool active = row < nrows;
-    for (int32_t s = lane; s < H; s += G) keys[s] = -1;
+    for (int32_t s = lane; s < H; s += G) {
+        keys[s] = -1;
+        if (NUM) vals[s] = 0.0;
+    }
     __syncthreads();
     int32_t fresh_count = 0;
     bool ovf = false;
     if (active) {
         const int32_t i = (int32_t)row;
-        for (int32_t p = ar.begin(i); p < ar.end(i); ++p) {
-            int32_t k, base, len;
-            double a;
-            if (!ar.get(p, i, k, a)) continue;
-            br.row(k, base, len);
-            for (int32_t t = lane; t < len; t += G) {
-                int32_t J;
-                double b;
-                br.get(base, t, J, b);
-                bool fresh;
-                if (hash_slot(keys, hbits, J, fresh) < 0) ovf = true;
-                fresh_count += fresh;
+        const int32_t pend = ar.end(i);
+        int32_t p0 = ar.begin(i);
+        while (p0 < pend) {
+            const int32_t p = p0 + lane;
+            int32_t k = 0, base = 0, len = 0;
+            double a = 0.0;
+            const bool valid = p < pend;
+            if (valid && ar.get(p, i, k, a)) br.row(k, base, len);
+            const int32_t incl = group_scan_incl<G>(len, lane);
+            const int32_t excl = incl - len;
+            const int32_t m = group_max<G>((valid && incl <= S) ? lane + 1 : 0);
+            if (m == 0) {
+                const int32_t b0 = __shfl(base, 0, G), l0 = __shfl(len, 0, G);
+                const double a0 = __shfl(a, 0, G);
+                for (int32_t t = lane; t < l0; t += G) {
+                    int32_t J;
+                    double bv;
+                    br.get(b0, t, J, bv);
+                    bool fresh;
+                    int32_t h = hash_slot(keys, hbits, J, fresh);
+                    if (h < 0) { ovf = true; continue; }
+                    fresh_count += fresh;
+                    if (NUM) vals[h] = vals[h] + a0 * bv;
+                }
+                __builtin_amdgcn_wave_barrier();
+                p0 += 1;
+                continue;
+            }
+            if (lane < m) {
+                for (int32_t t = 0; t < len; ++t) {
+                    int32_t J;
+                    double bv;
+                    br.get(base, t, J, bv);
+                    stJ[excl + t] = J;
+                    if (NUM) stV[excl + t] = a * bv;
+                }
             }
             __builtin_amdgcn_wave_barrier();
+            for (int e = 0; e < m; ++e) {
+                const int32_t off = __shfl(excl, e, G), le = __shfl(len, e, G);
+                for (int32_t t = lane; t < le; t += G) {
+                    bool fresh;
+                    int32_t h = hash_slot(keys, hbits, stJ[off + t], fresh);
+                    if (h < 0) { ovf = true; continue; }
+                    fresh_count += fresh;
+                    if (NUM) vals[h] = vals[h] + stV[off + t];
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            p0 += m;
         }
     }
-    int32_t tot = group_sum<G>(fresh_count);
-    if (active && lane == 0) {
-        cnt[row + 1] = tot;
-        atomicMax(maxd, tot);
-    }
-    if (ovf) atomicOr(overflow, 1);
-}
-
-template <int G, class AR, class BR, class EPI>
-__global__ void k_spgemm_num(AR ar, BR br, int32_t nrows, int hbits, const int32_t *__restrict__ crow,
-                             int32_t *__restrict__ ccol, double *__restrict__ cval, EPI epi,
-                             int32_t *overflow) {
-    extern __shared__ int32_t sm_keys[];
-    const int32_t H = 1 << hbits;
-    const int group = threadIdx.x / G, lane = threadIdx.x % G;
-    const int groups = blockDim.x / G;
-    int32_t *keys = sm_keys + (size_t)group * H;
-    double *vals = reinterpret_cast<double *>(sm_keys + (size_t)groups * H) + (size_t)group * H;
-    const int64_t row = (int64_t)blockIdx.x * groups + group;
-    const bool active = row < nrows;
-    for (int32_t s = lane; s < H; s += G) {
-        keys[s] = -1;
-        vals[s] = 0.0;
-    }
-    __syncthreads();
-    bool ovf = false;
-    if (active) {
-        const int32_t i = (int32_t)row;
-        for (int32_t p = ar.begin(i); p < ar.end(i); ++p) {
-            int32_t k, base, len;
-            double a;
-            if (!ar.get(p, i, k, a)) continue;
-            br.row(k, base, len);
-            for (int32_t t = lane; t < len; t += G) {
-                int32_t J;
-                double b;
-                br.get(base, t, J, b);
-                bool fresh;
-                int32_t h = hash_slot(keys, hbits, J, fresh);
-                if (h < 0) { ovf = true; continue; }
-                vals[h] = vals[h] + a * b;
+    if (!NUM) {
+        // row lengths; the scan over them also yields the largest row
+        int32_t tot = group_sum<G>(fresh_count);
+        if (active && lane == 0) cnt[row + 1] = tot;
+    } else {
+        __syncthreads();
+        if (active) {
+            const int32_t i = (int32_t)row;
+            const int32_t out0 = crow[i];
+            for (int32_t s = lane; s < H; s += G) {
+                int32_t J = keys[s];
+                if (J < 0) continue;
+                int32_t rank = 0;
+                for (int32_t u = 0; u < H; ++u) {
+                    int32_t K2 = keys[u];
+                    rank += (K2 >= 0 && K2 < J);
+                }
+                ccol[out0 + rank] = J;
+                cval[out0 + rank] = epi(i, J, vals[s]);
             }
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-    __syncthreads();
-    if (active) {
-        const int32_t i = (int32_t)row;
-        const int32_t out0 = crow[i];
-        for (int32_t s = lane; s < H; s += G) {
-            int32_t J = keys[s];
-            if (J < 0) continue;
-            int32_t rank = 0;
-            for (int32_t u = 0; u < H; ++u) {
-                int32_t K2 = keys[u];
-                rank += (K2 >= 0 && K2 < J);
-            }
-            ccol[out0 + rank] = J;
-            cval[out0 + rank] = epi(i, J, vals[s]);
         }
     }
     if (ovf) atomicOr(overflow, 1);
@@ -632,8 +665,11 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
 
 // ------------------------------------------------------------ host side --
 
+// Small device->host reads through the thread's pinned stage.
 struct Staging {
-    Pinned pin{256};
+    struct {
+        void *p = host_stage();
+    } pin;
     template <class T>
     T read(const T *d, hipStream_t s) {
         GW_HIP(hipMemcpyAsync(pin.p, d, sizeof(T), hipMemcpyDeviceToHost, s));
@@ -653,11 +689,24 @@ int pow2_bits_at_least(int64_t v) {
 constexpr int kMaxHashBits = 12;  // 4096 slots per output row
 
 // C = (A-side) x (B-side) with fixed summation order; C has `ncols` columns.
+// Lanes per output row: one A-side entry per lane, so a typical row is one
+// staging segment.
+int spgemm_group(double avg_a_len) {
+    if (avg_a_len <= 8.0) return 8;
+    if (avg_a_len <= 16.0) return 16;
+    if (avg_a_len <= 32.0) return 32;
+    return 64;
+}
+
+// C = (A-side) x (B-side) with fixed summation order; C has `ncols` columns.
+// Two host reads: the row bound before the symbolic pass, then nnz, the
+// largest row and the overflow flag together.
 template <class AR, class BR, class EPI>
-void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, int avg_b_len, EPI epi, Csr &C, hipStream_t s,
-            Staging &st) {
-    DBuf<int32_t> ctr(4);  // ub_max, maxd, overflow
-    fill_i32(ctr.p, 0, 4, s);
+void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double avg_b_len, EPI epi, Csr &C,
+            hipStream_t s, Staging &st) {
+    DBuf<int32_t> ctr(8);  // [0] row bound, [1] largest row, [2] overflow, [4..5] nnz (int64)
+    int64_t *total = reinterpret_cast<int64_t *>(ctr.p + 4);
+    fill_i32(ctr.p, 0, 8, s);
     {
         ProfScope ps(K_SPGEMM, 0, s);
         hipLaunchKernelGGL((k_spgemm_ub<AR, BR>), dim3(blocks_for(nrows)), dim3(kBlock), 0, s, ar, br, nrows, ctr.p);
@@ -667,51 +716,67 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, int avg_b_len, EPI epi, 
     int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
     C.alloc(nrows, ncols, 0);
     fill_i32(C.rowptr.p, 0, (int64_t)nrows + 1, s);
-    auto launch = [&](auto kern_sel, int G, size_t bytes_per_slot, int hbits) {
+    const int G = spgemm_group(avg_a_len);
+    // stage: about one and a half average segments, 32..512 contributions
+    // (a larger stage costs resident waves: the numeric pass is LDS-bound)
+    int S = 32;
+    while (S < 512 && S < 1.5 * G * avg_b_len) S *= 2;
+    constexpr size_t kMaxLds = 64 * 1024;
+    auto launch = [&](auto kern, bool num, int hbits) {
         const size_t H = (size_t)1 << hbits;
-        int groups = (int)std::min<size_t>(kBlock / G, std::max<size_t>(1, (48 * 1024) / (H * bytes_per_slot)));
+        const size_t per = num ? 12 : 4;
+        int Sx = S;
+        while (Sx > 32 && (H + Sx) * per > kMaxLds) Sx /= 2;
+        const size_t bytes_group = (H + Sx) * per;
+        int groups = (int)std::min<size_t>(kBlock / G, std::max<size_t>(1, kMaxLds / bytes_group));
         unsigned grid = (unsigned)((nrows + groups - 1) / groups);
         if (grid == 0) grid = 1;
-        kern_sel(dim3(grid), dim3(groups * G), groups * H * bytes_per_slot);
+        kern(dim3(grid), dim3(groups * G), groups * bytes_group, Sx);
     };
-    const int G = avg_b_len <= 1 ? 1 : (avg_b_len <= 6 ? 4 : (avg_b_len <= 24 ? 16 : 64));
+#define SPG_SYM(GG) hipLaunchKernelGGL((k_spgemm<GG, false, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hb, Sx, C.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, epi, ctr.p + 1, ctr.p + 2)
+#define SPG_NUM(GG) hipLaunchKernelGGL((k_spgemm<GG, true, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, Sx, (int32_t *)nullptr, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 1, ctr.p + 2)
     {
         ProfScope ps(K_SPGEMM, 0, s);
-        auto sym = [&](dim3 g, dim3 b, size_t sh) {
+        auto sym = [&](dim3 g, dim3 b, size_t sh, int Sx) {
             switch (G) {
-                case 1: hipLaunchKernelGGL((k_spgemm_sym<1, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
-                case 4: hipLaunchKernelGGL((k_spgemm_sym<4, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
-                case 16: hipLaunchKernelGGL((k_spgemm_sym<16, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
-                default: hipLaunchKernelGGL((k_spgemm_sym<64, AR, BR>), g, b, sh, s, ar, br, nrows, hb, C.rowptr.p, ctr.p + 1, ctr.p + 2); break;
+                case 8: SPG_SYM(8); break;
+                case 16: SPG_SYM(16); break;
+                case 32: SPG_SYM(32); break;
+                default: SPG_SYM(64); break;
             }
         };
-        launch(sym, G, 4, hb);
+        launch(sym, false, hb);
         GW_HIP(hipGetLastError());
     }
-    DBuf<int64_t> total(1);
-    scan_inclusive_i32(C.rowptr.p + 1, nrows, total.p, s);
-    int64_t nnz = st.read(total.p, s);
-    int32_t maxd = st.read(ctr.p + 1, s);
-    int32_t ovf = st.read(ctr.p + 2, s);
-    if (ovf) fail(GW_EINVAL, "amg_setup: a Galerkin row has more than 4096 distinct columns");
+    scan_inclusive_i32(C.rowptr.p + 1, nrows, total, s, ctr.p + 1);
+    int32_t info[8];
+    GW_HIP(hipMemcpyAsync(st.pin.p, ctr.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    GW_HIP(hipStreamSynchronize(s));
+    std::memcpy(info, st.pin.p, sizeof(info));
+    int64_t nnz;
+    std::memcpy(&nnz, &info[4], sizeof(nnz));
+    const int32_t maxd = info[1];
+    if (info[2]) fail(GW_EINVAL, "amg_setup: a Galerkin row has more than 4096 distinct columns");
     GW_REQUIRE(nnz < INT32_MAX, "amg_setup: operator exceeds 2^31 nonzeros");
     C.nnz = nnz;
     C.col.alloc((size_t)nnz);
     C.val.alloc((size_t)nnz);
-    int hbn = std::min(pow2_bits_at_least(2 * std::max<int32_t>(maxd, 1)), kMaxHashBits);
+    const int hbn = std::min(pow2_bits_at_least(2 * std::max<int32_t>(maxd, 1)), kMaxHashBits);
     {
         ProfScope ps(K_SPGEMM, 0, s);
-        auto num = [&](dim3 g, dim3 b, size_t sh) {
+        auto num = [&](dim3 g, dim3 b, size_t sh, int Sx) {
             switch (G) {
-                case 1: hipLaunchKernelGGL((k_spgemm_num<1, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
-                case 4: hipLaunchKernelGGL((k_spgemm_num<4, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
-                case 16: hipLaunchKernelGGL((k_spgemm_num<16, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
-                default: hipLaunchKernelGGL((k_spgemm_num<64, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 2); break;
+                case 8: SPG_NUM(8); break;
+                case 16: SPG_NUM(16); break;
+                case 32: SPG_NUM(32); break;
+                default: SPG_NUM(64); break;
             }
         };
-        launch(num, G, 12, hbn);
+        launch(num, true, hbn);
         GW_HIP(hipGetLastError());
     }
+#undef SPG_SYM
+#undef SPG_NUM
 }
 
 void csr_diag(const CsrView &A, double *diag, hipStream_t s) {
@@ -876,19 +941,21 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     ARowFiltered af{A.rowptr, A.col, A.val, strongA.p, dF.p};
     BTent bt{Lv.agg.p};
     EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
-    spgemm(af, bt, n, (int32_t)nc, 1, ep, Lv.P, s, st);
+    const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
+    spgemm(af, bt, n, (int32_t)nc, arow, 1.0, ep, Lv.P, s, st);
     Lv.omega_p = st.read(omega.p, s);
 
     // R = P^T, A_c = R (A P)
     transpose(view(Lv.P), Lv.R, s, total.p);
     Csr AP;
-    const int pavg = (int)std::max<int64_t>(1, Lv.P.nnz / std::max<int32_t>(n, 1));
-    spgemm(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p}, n, (int32_t)nc,
-           pavg + 1, EpiIdentity{}, AP, s, st);
+    const double pavg = (double)Lv.P.nnz / std::max<int32_t>(n, 1);
+    spgemm(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p}, n, (int32_t)nc, arow,
+           pavg, EpiIdentity{}, AP, s, st);
     Level &Nx = H->L[l + 1];
-    const int apavg = (int)std::max<int64_t>(1, AP.nnz / std::max<int32_t>(n, 1));
+    const double apavg = (double)AP.nnz / std::max<int32_t>(n, 1);
+    const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
     spgemm(ARowCsr{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p}, BCsr{AP.rowptr.p, AP.col.p, AP.val.p}, (int32_t)nc,
-           (int32_t)nc, apavg, EpiIdentity{}, Nx.A, s, st);
+           (int32_t)nc, ravg, apavg, EpiIdentity{}, Nx.A, s, st);
     GW_HIP(hipStreamSynchronize(s));
 }
 

@@ -558,23 +558,24 @@ void ensure_krylov_workspace(amg_hierarchy *H, int nvec) {
         H->kvec_count = nvec;
     }
     if (!H->partials.p) H->partials.alloc((size_t)kKMaxBlocks * 2);
-    if (!H->ks.p) {
-        H->ks.alloc(1);
-        H->ks_host = new Pinned(sizeof(KScalars));
-    }
+    if (!H->ks.p) H->ks.alloc(1);
 }
 
+static_assert(sizeof(KScalars) <= kHostStageBytes, "Krylov scalars must fit the pinned stage");
+
 KScalars read_ks(amg_hierarchy *H, hipStream_t s) {
-    GW_HIP(hipMemcpyAsync(H->ks_host->p, H->ks.p, sizeof(KScalars), hipMemcpyDeviceToHost, s));
+    void *stage = host_stage();
+    GW_HIP(hipMemcpyAsync(stage, H->ks.p, sizeof(KScalars), hipMemcpyDeviceToHost, s));
     GW_HIP(hipStreamSynchronize(s));
     KScalars k;
-    std::memcpy(&k, H->ks_host->p, sizeof(KScalars));
+    std::memcpy(&k, stage, sizeof(KScalars));
     return k;
 }
 
 void write_ks(amg_hierarchy *H, const KScalars &k, hipStream_t s) {
-    std::memcpy(H->ks_host->p, &k, sizeof(KScalars));
-    GW_HIP(hipMemcpyAsync(H->ks.p, H->ks_host->p, sizeof(KScalars), hipMemcpyHostToDevice, s));
+    void *stage = host_stage();
+    std::memcpy(stage, &k, sizeof(KScalars));
+    GW_HIP(hipMemcpyAsync(H->ks.p, stage, sizeof(KScalars), hipMemcpyHostToDevice, s));
     GW_HIP(hipStreamSynchronize(s));
 }
 

@@ -11,22 +11,42 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_tile_sums(const int32_t *a, int64_t n, int64_t *bs) {
+// Per tile: the sum and the largest value (the latter only when bm != null).
+__global__ void __launch_bounds__(kScanThreads) k_scan_tile_sums(const int32_t *a, int64_t n, int64_t *bs,
+                                                                 int32_t *bm) {
     __shared__ int64_t sm[kScanThreads / dev::kWave];
+    __shared__ int32_t smx[kScanThreads / dev::kWave];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     int64_t s = 0;
+    int32_t mx = INT32_MIN;
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (i < n) s += a[i];
+        if (i < n) {
+            s += a[i];
+            mx = a[i] > mx ? a[i] : mx;
+        }
     }
     s = dev::block_sum(s, sm);
-    if (threadIdx.x == 0) bs[blockIdx.x] = s;
+    if (bm) mx = dev::block_max(mx, smx);
+    if (threadIdx.x == 0) {
+        bs[blockIdx.x] = s;
+        if (bm) bm[blockIdx.x] = mx;
+    }
 }
 
-// Exclusive scan of the tile sums in one block; the grand total goes to *total.
-__global__ void __launch_bounds__(1024) k_scan_tile_offsets(int64_t *bs, int64_t nb, int64_t *total) {
+// Exclusive scan of the tile sums in one block; the grand total goes to
+// *total and, when asked, the largest element to *max_out.
+__global__ void __launch_bounds__(1024) k_scan_tile_offsets(int64_t *bs, int64_t nb, int64_t *total,
+                                                            const int32_t *bm, int32_t *max_out) {
     __shared__ int64_t wsum[1024 / dev::kWave];
+    __shared__ int32_t smx[1024 / dev::kWave];
     __shared__ int64_t carry;
+    if (max_out) {
+        int32_t mx = INT32_MIN;
+        for (int64_t i = threadIdx.x; i < nb; i += blockDim.x) mx = bm[i] > mx ? bm[i] : mx;
+        mx = dev::block_max(mx, smx);
+        if (threadIdx.x == 0) *max_out = mx;
+    }
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -83,16 +103,18 @@ __global__ void k_fill_f64(double *a, double v, int64_t n) {
 
 }  // namespace
 
-void scan_inclusive_i32(int32_t *a, int64_t n, int64_t *total, hipStream_t s) {
+void scan_inclusive_i32(int32_t *a, int64_t n, int64_t *total, hipStream_t s, int32_t *max_out) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_fill_f64, 1, 1, 0, s, reinterpret_cast<double *>(total), 0.0, 1);
+        if (max_out) hipLaunchKernelGGL(k_fill_i32, 1, 1, 0, s, max_out, 0, 1);
         GW_HIP(hipGetLastError());
         return;
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     DBuf<int64_t> bs((size_t)nb);
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, bs.p);
-    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(1024), 0, s, bs.p, nb, total);
+    DBuf<int32_t> bm(max_out ? (size_t)nb : 0);
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, bs.p, bm.p);
+    hipLaunchKernelGGL(k_scan_tile_offsets, dim3(1), dim3(1024), 0, s, bs.p, nb, total, bm.p, max_out);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, bs.p);
     GW_HIP(hipGetLastError());
 }
