@@ -27,7 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SETUP_KERNELS = ("coarse_lu", "spgemm", "setup_misc", "transpose", "mis2", "strength", "aggregate")
+SETUP_KERNELS = ("coarse_lu", "spgemm", "setup_misc", "transpose", "mis2", "strength", "aggregate",
+                 "sell_build")
 
 WORKLOADS = {
     # name: (nx, ny, nz, sigma2, corr_len, seed, precision)

@@ -193,3 +193,54 @@ def random_k(grid: Grid, seed: int, lo: float = 1e-6, hi: float = 1e-2) -> np.nd
 def random_vector(n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.standard_normal(n).astype(np.float64)
+
+
+def _csr_from_pairs(n: int, i: np.ndarray, j: np.ndarray, w: np.ndarray, diag: np.ndarray):
+    """CSR (sorted columns) of the symmetric matrix with off-diagonal
+    entries (i, j, w) and (j, i, w) and the given diagonal."""
+    rows = np.concatenate([i, j, np.arange(n)])
+    cols = np.concatenate([j, i, np.arange(n)])
+    vals = np.concatenate([w, w, diag])
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32), vals.astype(np.float64)
+
+
+def random_graph_spd(n: int, deg: int, seed: int):
+    """Symmetric, strictly diagonally dominant M-matrix on a random graph
+    (close to 2*deg neighbours in every row, at arbitrary column distance): an
+    operator with no stencil structure.  Returns (rowptr, col, val)."""
+    rng = np.random.default_rng(seed)
+    i = np.tile(np.arange(n), deg)
+    j = np.concatenate([rng.permutation(n) for _ in range(deg)])
+    i, j = np.minimum(i, j), np.maximum(i, j)
+    keep = i < j
+    i, j = i[keep], j[keep]
+    key = np.unique(i.astype(np.int64) * n + j)
+    i, j = (key // n).astype(np.int64), (key % n).astype(np.int64)
+    w = -rng.uniform(0.5, 1.5, size=len(i))
+    off = np.zeros(n)
+    np.add.at(off, i, -w)
+    np.add.at(off, j, -w)
+    return _csr_from_pairs(n, i, j, w, off + rng.uniform(0.1, 1.0, size=n))
+
+
+def arrow_spd(n: int, seed: int, stride: int = 2, weak: float = 0.01):
+    """1-D chain (a tridiagonal M-matrix) plus weak couplings between row 0
+    and every `stride`-th row: one row far longer than the rest.  Returns
+    (rowptr, col, val)."""
+    rng = np.random.default_rng(seed)
+    ci = np.arange(n - 1)
+    cw = -rng.uniform(0.5, 1.5, size=n - 1)
+    aj = np.arange(stride, n, stride)
+    aj = aj[aj > 1]
+    aw = np.full(len(aj), -weak)
+    i = np.concatenate([ci, np.zeros(len(aj), dtype=np.int64)])
+    j = np.concatenate([ci + 1, aj])
+    w = np.concatenate([cw, aw])
+    off = np.zeros(n)
+    np.add.at(off, i, -w)
+    np.add.at(off, j, -w)
+    return _csr_from_pairs(n, i, j, w, off + rng.uniform(0.1, 1.0, size=n))

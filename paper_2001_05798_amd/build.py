@@ -1,6 +1,6 @@
 """Build libgwamg.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2001_05798_amd.build  (or build() from Python).
+Usage: python paper_2001_05798_amd/build.py  (or build() from Python).
 Setup and assembly sources are compiled with -ffp-contract=off so that the
 hierarchy is bit-reproducible; the solve sources may fuse multiply-adds.
 """
@@ -24,6 +24,7 @@ SOURCES = [
     ("util.hip", False),
     ("assemble.hip", True),
     ("setup.hip", True),
+    ("sell.hip", False),
     ("solve.hip", False),
     ("capi.cpp", False),
     ("serve.cpp", False),

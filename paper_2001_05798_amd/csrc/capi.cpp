@@ -83,6 +83,10 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     }
     if (prm->smoother == GW_SMOOTHER_NONE) {
         H->nlev = 0;
+        H->L[0].A.grp = lane_group_for(A->n ? (double)A->nnz / (double)A->n : 0.0);
+        const char *sell_env = std::getenv("GWAMG_SELL");
+        if (!(sell_env && std::atoi(sell_env) == 0)) build_sell(H.get(), 0, false, s);
+        GW_HIP(hipStreamSynchronize(s));
         return H.release();
     }
     for (int l = 0;; ++l) {
@@ -106,6 +110,10 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
         int g = std::atoi(e);
         if (g == 1 || g == 4 || g == 16 || g == 64) H->L[0].A.grp = g;
     }
+    // Level-0 products (smoother, residual, Krylov) run on the sliced ELL
+    // copy unless GWAMG_SELL=0 keeps them on the CSR kernels.
+    const char *sell_env = std::getenv("GWAMG_SELL");
+    if (!(sell_env && std::atoi(sell_env) == 0)) build_sell(H.get(), 0, H->mixed() && H->nlev > 1, s);
     for (int l = 0; l < H->nlev; ++l) {
         Level &Lv = H->L[l];
         if (l < H->nlev - 1) {
@@ -191,7 +199,7 @@ int amg_spmv(amg_hierarchy *H, const double *x, double *y, void *stream) {
     return guarded([&] {
         GW_REQUIRE(H && x && y, "amg_spmv: null pointer");
         hipStream_t s = as_stream(stream);
-        spmv_f64(view(H->L[0].A), H->L[0].A.grp, x, y, s);
+        spmv_level0(H, x, y, s);
         finish(s);
         return GW_OK;
     });

@@ -111,7 +111,7 @@ struct Pinned {
 // on their stream; durations are summed at the next prof_flush().
 enum KernelId : int {
     K_FV_ASSEMBLE, K_DARCY, K_TT_ASSEMBLE,
-    K_SETUP_MISC, K_TRANSPOSE, K_STRENGTH, K_MIS2, K_AGGREGATE, K_SPGEMM, K_COARSE_LU,
+    K_SETUP_MISC, K_TRANSPOSE, K_STRENGTH, K_MIS2, K_AGGREGATE, K_SPGEMM, K_COARSE_LU, K_SELL_BUILD,
     K_SMOOTH_FIRST, K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE,
     K_SMOOTH_FIRST0, K_SMOOTH0, K_RESIDUAL0, K_RESTRICT0, K_PROLONG0,
     K_KRYLOV_SPMV, K_KRYLOV_UPDATE, K_KRYLOV_DOT, K_TRUE_RESIDUAL,
@@ -155,9 +155,43 @@ struct CsrView {
 };
 inline CsrView view(const Csr &A) { return {A.n, A.ncols, A.nnz, A.rowptr.p, A.col.p, A.val.p}; }
 
+// Sliced ELL copy of an operator for the solve phase: slices of 64 rows (one
+// wave), entries column-major inside a slice so lane l of a wave reads
+// consecutive addresses; short rows are padded with zero values pointing at
+// the row itself.  When the operator has at most 255 distinct offsets
+// (col - row), as stencil matrices do, each column is stored as a one-byte
+// index into a small dictionary of offsets; otherwise as an int32 column.
+constexpr int kSellC = 64;
+constexpr int kSellMaxDict = 255;
+struct Sell {
+    int32_t n = 0, nslices = 0;
+    int64_t nnz_padded = 0;
+    int32_t ndict = 0;           // 0: int32 columns, else dictionary size
+    DBuf<int32_t> soff;          // nslices + 1, entry offset of each slice
+    DBuf<uint8_t> idx;           // dictionary indices (ndict > 0)
+    DBuf<int32_t> col;           // columns (ndict == 0)
+    DBuf<int32_t> dict;          // offsets, ascending
+    DBuf<double> val;
+    DBuf<float> val32;
+    bool built() const { return nslices > 0; }
+    size_t bytes() const {
+        return soff.bytes() + idx.bytes() + col.bytes() + dict.bytes() + val.bytes() + val32.bytes();
+    }
+};
+
+struct SellView {
+    int32_t n, ndict;
+    const int32_t *soff;
+    const uint8_t *idx;
+    const int32_t *col;
+    const int32_t *dict;
+};
+inline SellView view(const Sell &S) { return {S.n, S.ndict, S.soff.p, S.idx.p, S.col.p, S.dict.p}; }
+
 // ------------------------------------------------------------ hierarchy --
 struct Level {
     Csr A;           // operator A_l (level 0: copy of the caller's matrix)
+    Sell As;         // sliced ELL copy of A_l used by the solve phase (level 0)
     Csr P, R;        // prolongator n x nc and its transpose (empty on coarsest)
     DBuf<int32_t> agg;
     DBuf<double> M;  // smoother diagonal
@@ -170,7 +204,7 @@ struct Level {
     // b (right-hand side), x (iterate) and t (ping-pong / residual)
     DBuf<char> vb, vx, vt;
     size_t bytes() const {
-        return A.bytes() + P.bytes() + R.bytes() + agg.bytes() + M.bytes() + M32.bytes() +
+        return A.bytes() + As.bytes() + P.bytes() + R.bytes() + agg.bytes() + M.bytes() + M32.bytes() +
                vb.bytes() + vx.bytes() + vt.bytes();
     }
 };
@@ -244,10 +278,14 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest);
 void build_coarsest(amg_hierarchy *H, int l, hipStream_t s);
 void make_smoother(amg_hierarchy *H, int l, hipStream_t s);
 void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s);
+// Build the sliced ELL copy of level l's operator (values in FP64, plus FP32
+// when `fp32`).
+void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s);
 
 // solve.hip
 void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s);
-void spmv_f64(const CsrView &A, int grp, const double *x, double *y, hipStream_t s);
+// y = A_0 x in FP64 with the level's solve-phase operator.
+void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s);
 // Lanes per row for a matrix with this mean row length.
 int lane_group_for(double mean_row_len);
 int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,

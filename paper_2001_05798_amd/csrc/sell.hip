@@ -1,0 +1,209 @@
+// Sliced ELL layout of the level-0 operator for the solve phase.
+//
+// One slice = 64 consecutive rows = one wave; inside a slice the k-th
+// entries of all 64 rows are stored next to each other, so a wave's load of
+// values or column indices is a single contiguous 512 B (FP64) or 256 B
+// (FP32) run.  A row keeps its CSR entry order; rows shorter than the slice
+// width are padded with a zero value at the row's own column.  Stencil
+// operators have a handful of distinct offsets col - row: those columns are
+// stored as one-byte indices into a sorted offset dictionary (9 B per entry in
+// FP64, 5 B in FP32, instead of 12 / 8 with int32 columns).
+#include <algorithm>
+#include <cstring>
+
+#include "gw_device.h"
+#include "gw_internal.h"
+
+namespace gw {
+
+namespace {
+
+constexpr int kOffsetTable = 4096;  // open-addressing set of offsets (device)
+constexpr int kBlockTable = 512;    // per-block set in LDS
+constexpr int32_t kEmpty = INT32_MIN;
+
+__global__ void k_sell_width(const int32_t *__restrict__ rowptr, int32_t n, int32_t *__restrict__ width) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+    len = dev::wave_max(len);
+    if ((threadIdx.x & (kSellC - 1)) == 0 && row < n) width[row / kSellC + 1] = len * kSellC;
+}
+
+__device__ __forceinline__ uint32_t offset_hash(int32_t d) { return ((uint32_t)d * 2654435761u) >> 16; }
+
+// Insert d into an open-addressing set of `size` slots (power of two); the
+// slot is read before any atomic so repeated offsets cost no contention.
+template <int SCOPE>
+__device__ __forceinline__ bool set_insert(int32_t *table, int size, int32_t d) {
+    uint32_t h = offset_hash(d) & (size - 1);
+    for (int probe = 0; probe < 64; ++probe) {
+        int32_t cur = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, SCOPE);
+        if (cur == d) return true;
+        if (cur == kEmpty) {
+            int32_t old = atomicCAS(&table[h], kEmpty, d);
+            if (old == kEmpty || old == d) return true;
+        }
+        h = (h + 1) & (size - 1);
+    }
+    return false;
+}
+
+// Distinct offsets col - row: each block collects its own in LDS, then adds
+// that short list to the device-wide set.
+__global__ void __launch_bounds__(kBlock) k_offset_set(const int32_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ col, int32_t n, int32_t *table,
+                                                       int32_t *overflow) {
+    __shared__ int32_t lt[kBlockTable];
+    __shared__ int32_t lovf;
+    for (int t = threadIdx.x; t < kBlockTable; t += blockDim.x) lt[t] = kEmpty;
+    if (threadIdx.x == 0) lovf = 0;
+    __syncthreads();
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row < n) {
+        int32_t last = kEmpty;
+        const int32_t e = rowptr[row + 1];
+        for (int32_t p = rowptr[row]; p < e; ++p) {
+            const int32_t d = col[p] - (int32_t)row;
+            if (d == last) continue;
+            last = d;
+            if (!set_insert<__HIP_MEMORY_SCOPE_WORKGROUP>(lt, kBlockTable, d)) lovf = 1;
+        }
+    }
+    __syncthreads();
+    if (lovf) {
+        if (threadIdx.x == 0) atomicOr(overflow, 1);
+        return;
+    }
+    for (int t = threadIdx.x; t < kBlockTable; t += blockDim.x) {
+        const int32_t d = lt[t];
+        if (d != kEmpty && !set_insert<__HIP_MEMORY_SCOPE_AGENT>(table, kOffsetTable, d)) atomicOr(overflow, 1);
+    }
+}
+
+// One block: the set's entries in ascending order into meta[4 + k] and their
+// count into meta[1] (meta[0] is the overflow flag; a count above
+// kSellMaxDict is reported as such and nothing is written).  The padded entry
+// total is copied next to them so one small read returns everything.
+__global__ void __launch_bounds__(1024) k_offset_compact(const int32_t *__restrict__ table, int32_t *meta,
+                                                         const int64_t *__restrict__ total) {
+    __shared__ int32_t keys[kOffsetTable];
+    __shared__ int32_t cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < kOffsetTable; t += blockDim.x) {
+        const int32_t d = table[t];
+        if (d != kEmpty) keys[atomicAdd(&cnt, 1)] = d;
+    }
+    __syncthreads();
+    const int m = cnt;
+    if (threadIdx.x == 0) {
+        meta[1] = m;
+        reinterpret_cast<int64_t *>(meta)[1] = *total;
+    }
+    if (m > kSellMaxDict) return;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        const int32_t d = keys[t];
+        int rank = 0;
+        for (int u = 0; u < m; ++u) rank += keys[u] < d;
+        meta[4 + rank] = d;
+    }
+}
+
+__device__ __forceinline__ int32_t dict_index(const int32_t *dict, int32_t ndict, int32_t d) {
+    int32_t lo = 0, hi = ndict - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (dict[mid] < d) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Thread per row: write the row's entries column-major into its slice.
+__global__ void k_sell_fill(CsrView A, const int32_t *__restrict__ soff, const int32_t *__restrict__ dict,
+                            int32_t ndict, uint8_t *__restrict__ idx, int32_t *__restrict__ cols,
+                            double *__restrict__ val, float *__restrict__ val32) {
+    __shared__ int32_t sdict[kSellMaxDict + 1];
+    for (int t = threadIdx.x; t < ndict; t += blockDim.x) sdict[t] = dict[t];
+    __syncthreads();
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= A.n) return;
+    const int64_t s = row / kSellC;
+    const int l = (int)(row % kSellC);
+    const int32_t off = soff[s], w = (soff[s + 1] - off) / kSellC;
+    const int32_t b = A.rowptr[row], len = A.rowptr[row + 1] - b;
+    const int32_t self = ndict ? dict_index(sdict, ndict, 0) : 0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t e = off + (int64_t)k * kSellC + l;
+        double v = 0.0;
+        int32_t c = (int32_t)row;
+        if (k < len) {
+            v = A.val[b + k];
+            c = A.col[b + k];
+        }
+        if (ndict) idx[e] = (uint8_t)(k < len ? dict_index(sdict, ndict, c - (int32_t)row) : self);
+        else cols[e] = c;
+        val[e] = v;
+        if (val32) val32[e] = (float)v;
+    }
+}
+
+}  // namespace
+
+void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
+    Level &Lv = H->L[l];
+    const CsrView A = view(Lv.A);
+    Sell &S = Lv.As;
+    S = Sell();
+    const int32_t nslices = (A.n + kSellC - 1) / kSellC;
+    // meta: [0] overflow, [1] count, [2..3] padded total (int64), [4..] offsets
+    constexpr int kMeta = 4 + kSellMaxDict;
+    static_assert(kMeta * sizeof(int32_t) <= kHostStageBytes, "offset dictionary must fit the pinned stage");
+    ProfScope ps(K_SELL_BUILD, 0.0, s);
+    DBuf<int32_t> soff((size_t)nslices + 1);
+    DBuf<int64_t> total(1);
+    DBuf<int32_t> table(kOffsetTable);
+    DBuf<int32_t> meta(kMeta);
+    fill_i32(soff.p, 0, 1, s);
+    fill_i32(table.p, kEmpty, kOffsetTable, s);
+    fill_i32(meta.p, 0, kMeta, s);
+    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.n, soff.p);
+    scan_inclusive_i32(soff.p + 1, nslices, total.p, s);
+    hipLaunchKernelGGL(k_offset_set, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.col, A.n, table.p,
+                       meta.p);
+    hipLaunchKernelGGL(k_offset_compact, dim3(1), dim3(1024), 0, s, table.p, meta.p, total.p);
+    GW_HIP(hipGetLastError());
+    int32_t *stage = static_cast<int32_t *>(host_stage());
+    GW_HIP(hipMemcpyAsync(stage, meta.p, sizeof(int32_t) * kMeta, hipMemcpyDeviceToHost, s));
+    GW_HIP(hipStreamSynchronize(s));
+    const bool overflow = stage[0] != 0;
+    const int32_t count = stage[1];
+    int64_t padded = 0;
+    std::memcpy(&padded, stage + 2, sizeof(int64_t));
+    // Rows of very uneven length would pad the copy far beyond the CSR
+    // operator: keep the CSR kernels then (also past int32 entry offsets).
+    if (padded >= INT32_MAX || (double)padded > 1.5 * (double)A.nnz + kSellC) return;
+    bool use_dict = !overflow && count <= kSellMaxDict && count > 0;
+    if (use_dict) use_dict = std::binary_search(stage + 4, stage + 4 + count, 0);
+    S.n = A.n;
+    S.nslices = nslices;
+    S.nnz_padded = padded;
+    S.soff = std::move(soff);
+    const size_t np = (size_t)std::max<int64_t>(padded, 1);
+    if (use_dict) {
+        S.ndict = count;
+        S.dict.alloc((size_t)count);
+        copy_bytes(S.dict.p, meta.p + 4, sizeof(int32_t) * (size_t)count, s);
+        S.idx.alloc(np);
+    } else {
+        S.ndict = 0;
+        S.col.alloc(np);
+    }
+    S.val.alloc(np);
+    if (fp32) S.val32.alloc(np);
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, S.soff.p, S.dict.p, S.ndict,
+                       S.idx.p, S.col.p, S.val.p, S.val32.p);
+    GW_HIP(hipGetLastError());
+}
+
+}  // namespace gw

@@ -4,13 +4,16 @@
 // preconditions: CG for the symmetric flow system and BiCGSTAB for the
 // upwind travel-time system (Benchmarking Examples).
 //
-// Sparse products use G lanes per row (G picked per matrix from its mean row
-// length), so the lanes of a wave read consecutive CSR entries.  The Krylov
-// scalars live on the device: a product kernel leaves per-block partial sums,
-// a one-block finalize kernel adds them in a fixed order and forms
-// alpha/beta/omega and the convergence flag; every later kernel reads the
-// flag and returns at once, so the host only polls it every few iterations.
-// FP64 throughout the Krylov layer; the hierarchy is FP64 or FP32 (mixed).
+// Every product kernel is written once against an operator type: OpSell (the
+// sliced ELL copy of the level-0 operator, one lane per row, dictionary of
+// column offsets in LDS) or OpCsr<G> (G lanes per CSR row, G picked per
+// matrix from its mean row length, so the lanes of a wave read consecutive
+// entries).  The Krylov scalars live on the device: a product kernel leaves
+// per-block partial sums, a one-block finalize kernel adds them in a fixed
+// order and forms alpha/beta/omega and the convergence flag; every later
+// kernel reads the flag and returns at once, so the host only polls it every
+// few iterations.  FP64 throughout the Krylov layer; the hierarchy is FP64 or
+// FP32 (mixed mode).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -22,6 +25,7 @@ namespace gw {
 
 namespace {
 
+// ----------------------------------------------------------- operators ---
 // Lanes of a group own one row: strided partial sums, then a butterfly over
 // the group (groups are aligned power-of-two lane ranges of one wave).
 template <int G, class V, class F>
@@ -35,6 +39,67 @@ __device__ __forceinline__ V group_row_sum(const int32_t *__restrict__ rowptr, c
     return s;
 }
 
+template <int G_, class V>
+struct OpCsr {
+    static constexpr int G = G_;
+    const int32_t *rowptr, *col;
+    const V *val;
+    __device__ __forceinline__ void load(int32_t *) const {}
+    template <class F>
+    __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *, F &&xj) const {
+        return group_row_sum<G, V>(rowptr, col, val, i, lane, xj);
+    }
+};
+
+template <class V>
+struct OpSell {
+    static constexpr int G = 1;
+    SellView S;
+    const V *val;
+    __device__ __forceinline__ void load(int32_t *sd) const {
+        for (int t = threadIdx.x; t < S.ndict; t += blockDim.x) sd[t] = S.dict[t];
+    }
+    // Entries k of row i sit at soff[slice] + k*64 + (i mod 64).  Eight
+    // entries are loaded before their products are summed, so the gathers
+    // of x overlap; the sum still runs in entry order.  Slots past the slice
+    // width re-read the last entry and are replaced by the padding entry
+    // (value 0 at the row's own column) in registers, without branches.
+    template <bool DICT, class F>
+    __device__ __forceinline__ V row_impl(int64_t i, const int32_t *sd, F &&xj) const {
+        const int64_t sl = i / kSellC;
+        const int l = (int)(i - sl * kSellC);
+        const int32_t off = S.soff[sl], w = (S.soff[sl + 1] - off) / kSellC;
+        V acc = 0;
+        for (int32_t k0 = 0; k0 < w; k0 += 8) {
+            V a[8];
+            int32_t c[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int32_t k = min(k0 + u, w - 1);
+                const int64_t e = off + (int64_t)k * kSellC + l;
+                const V av = val[e];
+                const int32_t cv = DICT ? (int32_t)i + sd[S.idx[e]] : S.col[e];
+                const bool in = k0 + u < w;
+                a[u] = in ? av : V(0);
+                c[u] = in ? cv : (int32_t)i;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += a[u] * xj(c[u]);
+        }
+        return acc;
+    }
+    template <class F>
+    __device__ __forceinline__ V row(int64_t i, int, const int32_t *sd, F &&xj) const {
+        return S.ndict ? row_impl<true>(i, sd, xj) : row_impl<false>(i, sd, xj);
+    }
+};
+
+// Block prologue of every product kernel (after its uniform early exit).
+#define OP_PROLOGUE(op)                         \
+    __shared__ int32_t sd_[kSellMaxDict + 1];   \
+    (op).load(sd_);                             \
+    __syncthreads();
+
 #define GROUP_ROW(G)                                                              \
     const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;          \
     const int64_t i = gtid / (G);                                                 \
@@ -44,59 +109,57 @@ __device__ __forceinline__ V group_row_sum(const int32_t *__restrict__ rowptr, c
 // ------------------------------------------------------------ V-cycle ----
 // Sweep x <- x + M (b - A x); the first two sweeps from x = 0 are fused:
 // x1 = M b, x2 = x1 + M (b - A x1) with x1_j recomputed on the fly.
-template <int G, class V, class Bt, class Yt>
-__global__ void k_smooth_first(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                               const V *__restrict__ val, const V *__restrict__ M, const Bt *__restrict__ b,
+template <class OP, class V, class Bt, class Yt>
+__global__ void k_smooth_first(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b,
                                Yt *__restrict__ y, int two, const int32_t *done) {
     if (done && *done) return;
-    GROUP_ROW(G)
+    OP_PROLOGUE(op)
+    GROUP_ROW(OP::G)
     const V bi = (V)b[i], mi = M[i];
     V x1 = mi * bi;
     if (two) {
-        V ax = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return M[j] * (V)b[j]; });
+        V ax = op.row(i, lane, sd_, [&](int32_t j) { return M[j] * (V)b[j]; });
         x1 = x1 + mi * (bi - ax);
     }
     if (lane == 0) y[i] = (Yt)x1;
 }
 
-template <int G, class V, class Bt, class Xt, class Yt>
-__global__ void k_smooth(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                         const V *__restrict__ val, const V *__restrict__ M, const Bt *__restrict__ b,
+template <class OP, class V, class Bt, class Xt, class Yt>
+__global__ void k_smooth(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b,
                          const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
-    GROUP_ROW(G)
-    V ax = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)x[j]; });
+    OP_PROLOGUE(op)
+    GROUP_ROW(OP::G)
+    V ax = op.row(i, lane, sd_, [&](int32_t j) { return (V)x[j]; });
     if (lane == 0) y[i] = (Yt)((V)x[i] + M[i] * ((V)b[i] - ax));
 }
 
-template <int G, class V, class Bt, class Xt, class Rt>
-__global__ void k_residual(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                           const V *__restrict__ val, const Bt *__restrict__ b, const Xt *__restrict__ x,
+template <class OP, class V, class Bt, class Xt, class Rt>
+__global__ void k_residual(int64_t n, OP op, const Bt *__restrict__ b, const Xt *__restrict__ x,
                            Rt *__restrict__ r, const int32_t *done) {
     if (done && *done) return;
-    GROUP_ROW(G)
-    V ax = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)x[j]; });
+    OP_PROLOGUE(op)
+    GROUP_ROW(OP::G)
+    V ax = op.row(i, lane, sd_, [&](int32_t j) { return (V)x[j]; });
     if (lane == 0) r[i] = (Rt)((V)b[i] - ax);
 }
 
-template <int G, class V, class Xt, class Yt>
-__global__ void k_spmv(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                       const V *__restrict__ val, const Xt *__restrict__ x, Yt *__restrict__ y,
-                       const int32_t *done) {
+template <class OP, class V, class Xt, class Yt>
+__global__ void k_spmv(int64_t n, OP op, const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
-    GROUP_ROW(G)
-    V s = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)x[j]; });
+    OP_PROLOGUE(op)
+    GROUP_ROW(OP::G)
+    V s = op.row(i, lane, sd_, [&](int32_t j) { return (V)x[j]; });
     if (lane == 0) y[i] = (Yt)s;
 }
 
 // x += P x_c
-template <int G, class V, class Xt>
-__global__ void k_prolong(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                          const V *__restrict__ val, const Xt *__restrict__ xc, Xt *__restrict__ x,
-                          const int32_t *done) {
+template <class OP, class V, class Xt>
+__global__ void k_prolong(int64_t n, OP op, const Xt *__restrict__ xc, Xt *__restrict__ x, const int32_t *done) {
     if (done && *done) return;
-    GROUP_ROW(G)
-    V s = group_row_sum<G, V>(rowptr, col, val, i, lane, [&](int32_t j) { return (V)xc[j]; });
+    OP_PROLOGUE(op)
+    GROUP_ROW(OP::G)
+    V s = op.row(i, lane, sd_, [&](int32_t j) { return (V)xc[j]; });
     if (lane == 0) x[i] = (Xt)((V)x[i] + s);
 }
 
@@ -129,8 +192,14 @@ __global__ void k_convert(const Xt *__restrict__ x, Yt *__restrict__ y, int64_t 
     if (i < n) y[i] = (Yt)x[i];
 }
 
-// Bytes one launch of a CSR pass touches (values, columns, row pointers).
+// Bytes one pass over an operator touches: values and column information
+// (int32 columns + row pointers for CSR; one-byte offsets or int32 columns,
+// padding included, + slice offsets for sliced ELL).
 double csr_bytes(int64_t n, int64_t nnz, int vbytes) { return (double)nnz * (vbytes + 4) + 4.0 * (n + 1); }
+double op_bytes(const Csr &A, const Sell &S, int vbytes) {
+    if (S.built()) return (double)S.nnz_padded * (vbytes + (S.ndict ? 1 : 4)) + 4.0 * (S.nslices + 1);
+    return csr_bytes(A.n, A.nnz, vbytes);
+}
 
 unsigned grid_rows(int64_t n, int G) { return blocks_for(n * G); }
 
@@ -139,6 +208,7 @@ struct LevelOps;
 template <>
 struct LevelOps<double> {
     static const double *aval(const Level &L) { return L.A.val.p; }
+    static const double *asval(const Level &L) { return L.As.val.p; }
     static const double *pval(const Level &L) { return L.P.val.p; }
     static const double *rval(const Level &L) { return L.R.val.p; }
     static const double *mval(const Level &L) { return L.M.p; }
@@ -146,19 +216,29 @@ struct LevelOps<double> {
 template <>
 struct LevelOps<float> {
     static const float *aval(const Level &L) { return L.A.val32.p; }
+    static const float *asval(const Level &L) { return L.As.val32.p; }
     static const float *pval(const Level &L) { return L.P.val32.p; }
     static const float *rval(const Level &L) { return L.R.val32.p; }
     static const float *mval(const Level &L) { return L.M32.p; }
 };
 
-// Launch a kernel template instantiated for the matrix's lane-group size.
-#define DISPATCH_G(g, KERNEL, ...)                                            \
-    switch (g) {                                                              \
-        case 1: KERNEL(1, __VA_ARGS__); break;                                \
-        case 4: KERNEL(4, __VA_ARGS__); break;                                \
-        case 16: KERNEL(16, __VA_ARGS__); break;                              \
-        default: KERNEL(64, __VA_ARGS__); break;                              \
+// Call f(op) with the operator type of a CSR matrix (its lane group).
+template <class V, class F>
+void with_csr(const Csr &A, const V *val, F &&f) {
+    switch (A.grp) {
+        case 1: f(OpCsr<1, V>{A.rowptr.p, A.col.p, val}); break;
+        case 4: f(OpCsr<4, V>{A.rowptr.p, A.col.p, val}); break;
+        case 16: f(OpCsr<16, V>{A.rowptr.p, A.col.p, val}); break;
+        default: f(OpCsr<64, V>{A.rowptr.p, A.col.p, val}); break;
     }
+}
+
+// Call f(op) with the level's operator: the sliced ELL copy when built.
+template <class V, class F>
+void with_level_op(const Level &Lv, F &&f) {
+    if (Lv.As.built() && LevelOps<V>::asval(Lv)) f(OpSell<V>{view(Lv.As), LevelOps<V>::asval(Lv)});
+    else with_csr<V>(Lv.A, LevelOps<V>::aval(Lv), f);
+}
 
 // One V-cycle on level l.  `b` is the right-hand side (type Bt), the result
 // goes to `out` (type Zt) when given, else into one of the level's own
@@ -176,68 +256,75 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
                            (int32_t)n, H->inv.p, b, y, done);
         return y;
     }
-    const int32_t *ar = Lv.A.rowptr.p, *ac = Lv.A.col.p;
-    const V *av = LevelOps<V>::aval(Lv), *M = LevelOps<V>::mval(Lv);
-    const double abytes = csr_bytes(n, Lv.A.nnz, vb);
+    const V *M = LevelOps<V>::mval(Lv);
+    const double abytes = op_bytes(Lv.A, Lv.As, vb);
     V *x = reinterpret_cast<V *>(Lv.vx.p);
     V *t = reinterpret_cast<V *>(Lv.vt.p);
     const int npre = H->prm.npre, npost = H->prm.npost;
-    const int ga = Lv.A.grp;
 
     // pre-smoothing
     if (npre == 0) {
         hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, done);
     } else {
-        ProfScope ps(l == 0 ? K_SMOOTH_FIRST0 : K_SMOOTH_FIRST, npre >= 2 ? abytes + n * (double)(sizeof(Bt) + 2 * vb) : n * (double)(sizeof(Bt) + 2 * vb), s);
-#define L_SF(G, ...) hipLaunchKernelGGL((k_smooth_first<G, V, Bt, V>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, ar, ac, av, M, b, x, npre >= 2 ? 1 : 0, done)
-        DISPATCH_G(ga, L_SF, 0)
-#undef L_SF
+        ProfScope ps(l == 0 ? K_SMOOTH_FIRST0 : K_SMOOTH_FIRST,
+                     npre >= 2 ? abytes + n * (double)(sizeof(Bt) + 2 * vb) : n * (double)(sizeof(Bt) + 2 * vb), s);
+        with_level_op<V>(Lv, [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_smooth_first<OP, V, Bt, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, M,
+                               b, x, npre >= 2 ? 1 : 0, done);
+        });
     }
-#define L_SM(G, XIN, YOUT, YT) hipLaunchKernelGGL((k_smooth<G, V, Bt, V, YT>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, ar, ac, av, M, b, XIN, YOUT, done)
+    auto sweep = [&](auto *xin, auto *yout) {
+        using YT = std::remove_pointer_t<decltype(yout)>;
+        ProfScope ps(l == 0 ? K_SMOOTH0 : K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 2 * vb + sizeof(YT)), s);
+        with_level_op<V>(Lv, [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_smooth<OP, V, Bt, V, YT>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, M,
+                               b, xin, yout, done);
+        });
+    };
     for (int k = 2; k < npre; ++k) {
-        ProfScope ps(l == 0 ? K_SMOOTH0 : K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 3 * vb), s);
-        DISPATCH_G(ga, L_SM, x, t, V)
+        sweep(x, t);
         std::swap(x, t);
     }
     // residual and restriction
     {
         ProfScope ps(l == 0 ? K_RESIDUAL0 : K_RESIDUAL, abytes + n * (double)(sizeof(Bt) + 2 * vb), s);
-#define L_RES(G, ...) hipLaunchKernelGGL((k_residual<G, V, Bt, V, V>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, ar, ac, av, b, x, t, done)
-        DISPATCH_G(ga, L_RES, 0)
-#undef L_RES
+        with_level_op<V>(Lv, [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_residual<OP, V, Bt, V, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, b,
+                               x, t, done);
+        });
     }
     Level &Nx = H->L[l + 1];
     V *bc = reinterpret_cast<V *>(Nx.vb.p);
     const int64_t nc = Lv.nc;
     {
         ProfScope ps(l == 0 ? K_RESTRICT0 : K_RESTRICT, csr_bytes(nc, Lv.R.nnz, vb) + (double)(n + nc) * vb, s);
-        const int32_t *rr = Lv.R.rowptr.p, *rc = Lv.R.col.p;
-        const V *rv = LevelOps<V>::rval(Lv);
-#define L_R(G, ...) hipLaunchKernelGGL((k_spmv<G, V, V, V>), dim3(grid_rows(nc, G)), dim3(kBlock), 0, s, nc, rr, rc, rv, t, bc, done)
-        DISPATCH_G(Lv.R.grp, L_R, 0)
-#undef L_R
+        with_csr<V>(Lv.R, LevelOps<V>::rval(Lv), [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_spmv<OP, V, V, V>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t, bc,
+                               done);
+        });
     }
     V *xc = static_cast<V *>(vcycle_level<V, V, V>(H, l + 1, bc, (V *)nullptr, done, s));
     {
         ProfScope ps(l == 0 ? K_PROLONG0 : K_PROLONG, csr_bytes(n, Lv.P.nnz, vb) + (double)(2 * n + nc) * vb, s);
-        const int32_t *pr = Lv.P.rowptr.p, *pc = Lv.P.col.p;
-        const V *pv = LevelOps<V>::pval(Lv);
-#define L_P(G, ...) hipLaunchKernelGGL((k_prolong<G, V, V>), dim3(grid_rows(n, G)), dim3(kBlock), 0, s, n, pr, pc, pv, xc, x, done)
-        DISPATCH_G(Lv.P.grp, L_P, 0)
-#undef L_P
+        with_csr<V>(Lv.P, LevelOps<V>::pval(Lv), [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_prolong<OP, V, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, xc, x,
+                               done);
+        });
     }
     // post-smoothing; the last sweep writes the requested output
     for (int k = 0; k < npost; ++k) {
-        const bool last = (k == npost - 1);
-        ProfScope ps(l == 0 ? K_SMOOTH0 : K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 3 * vb), s);
-        if (last && out) {
-            DISPATCH_G(ga, L_SM, x, out, Zt)
+        if (k == npost - 1 && out) {
+            sweep(x, out);
             return out;
         }
-        DISPATCH_G(ga, L_SM, x, t, V)
+        sweep(x, t);
         std::swap(x, t);
     }
-#undef L_SM
     if (out) {
         hipLaunchKernelGGL((k_convert<V, Zt>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, out, n, done);
         return out;
@@ -265,14 +352,15 @@ unsigned kgrid(int64_t n, int G) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
 
 // r = b - A x (and BiCGSTAB's r_hat = r, p = v = 0); partials b.b, r.r
-template <int G>
-__global__ void __launch_bounds__(kKBlock) k_kr_init(CsrView A, const double *__restrict__ b,
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_kr_init(int64_t n, OP op, const double *__restrict__ b,
                                                      const double *__restrict__ x, double *__restrict__ r,
                                                      double *__restrict__ rh, double *__restrict__ p,
                                                      double *__restrict__ v, double *partials) {
+    OP_PROLOGUE(op)
     double acc[2] = {0.0, 0.0};
-    GROUP_LOOP(G, i, lane, A.n) {
-        double ax = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return x[j]; });
+    GROUP_LOOP(OP::G, i, lane, n) {
+        double ax = op.row(i, lane, sd_, [&](int32_t j) { return x[j]; });
         if (lane == 0) {
             double ri = b[i] - ax;
             r[i] = ri;
@@ -300,16 +388,16 @@ __global__ void __launch_bounds__(kKBlock) k_cg_dot(int64_t n, const double *__r
 }
 
 // p_new = z + beta p_old;  q = A p_new;  partial p_new . q
-template <int G>
-__global__ void __launch_bounds__(kKBlock) k_cg_spmv(CsrView A, const double *__restrict__ z,
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_cg_spmv(int64_t n, OP op, const double *__restrict__ z,
                                                      const double *__restrict__ p_old, double *__restrict__ p_new,
                                                      double *__restrict__ q, double *partials, const KScalars *ks) {
     if (ks->done) return;
+    OP_PROLOGUE(op)
     const double beta = ks->beta;
     double acc[1] = {0.0};
-    GROUP_LOOP(G, i, lane, A.n) {
-        double s = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane,
-                                            [&](int32_t j) { return z[j] + beta * p_old[j]; });
+    GROUP_LOOP(OP::G, i, lane, n) {
+        double s = op.row(i, lane, sd_, [&](int32_t j) { return z[j] + beta * p_old[j]; });
         if (lane == 0) {
             double pi = z[i] + beta * p_old[i];
             p_new[i] = pi;
@@ -337,12 +425,13 @@ __global__ void __launch_bounds__(kKBlock) k_cg_update(int64_t n, double *__rest
 }
 
 // partial (b - A x).(b - A x)
-template <int G>
-__global__ void __launch_bounds__(kKBlock) k_true_res(CsrView A, const double *__restrict__ b,
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_true_res(int64_t n, OP op, const double *__restrict__ b,
                                                       const double *__restrict__ x, double *partials) {
+    OP_PROLOGUE(op)
     double acc[1] = {0.0};
-    GROUP_LOOP(G, i, lane, A.n) {
-        double ax = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return x[j]; });
+    GROUP_LOOP(OP::G, i, lane, n) {
+        double ax = op.row(i, lane, sd_, [&](int32_t j) { return x[j]; });
         if (lane == 0) {
             double ri = b[i] - ax;
             acc[0] += ri * ri;
@@ -360,13 +449,15 @@ __global__ void __launch_bounds__(kKBlock) k_bcg_p(int64_t n, const double *__re
 }
 
 // v = A p_hat;  partial r_hat . v
-template <int G>
-__global__ void __launch_bounds__(kKBlock) k_bcg_v(CsrView A, const double *__restrict__ ph, double *__restrict__ v,
-                                                   const double *__restrict__ rh, double *partials, const KScalars *ks) {
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_bcg_v(int64_t n, OP op, const double *__restrict__ ph,
+                                                   double *__restrict__ v, const double *__restrict__ rh,
+                                                   double *partials, const KScalars *ks) {
     if (ks->done) return;
+    OP_PROLOGUE(op)
     double acc[1] = {0.0};
-    GROUP_LOOP(G, i, lane, A.n) {
-        double vi = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return ph[j]; });
+    GROUP_LOOP(OP::G, i, lane, n) {
+        double vi = op.row(i, lane, sd_, [&](int32_t j) { return ph[j]; });
         if (lane == 0) {
             v[i] = vi;
             acc[0] += rh[i] * vi;
@@ -391,13 +482,15 @@ __global__ void __launch_bounds__(kKBlock) k_bcg_s(int64_t n, const double *__re
 }
 
 // t = A s_hat;  partials t.s, t.t
-template <int G>
-__global__ void __launch_bounds__(kKBlock) k_bcg_t(CsrView A, const double *__restrict__ sh, double *__restrict__ t,
-                                                   const double *__restrict__ sv, double *partials, const KScalars *ks) {
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_bcg_t(int64_t n, OP op, const double *__restrict__ sh,
+                                                   double *__restrict__ t, const double *__restrict__ sv,
+                                                   double *partials, const KScalars *ks) {
     if (ks->done) return;
+    OP_PROLOGUE(op)
     double acc[2] = {0.0, 0.0};
-    GROUP_LOOP(G, i, lane, A.n) {
-        double ti = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return sh[j]; });
+    GROUP_LOOP(OP::G, i, lane, n) {
+        double ti = op.row(i, lane, sd_, [&](int32_t j) { return sh[j]; });
         if (lane == 0) {
             t[i] = ti;
             acc[0] += ti * sv[i];
@@ -543,11 +636,11 @@ __global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const
     }
 }
 
-template <int G>
-__global__ void k_spmv_f64(CsrView A, const double *__restrict__ x, double *__restrict__ y) {
-    const int64_t n = A.n;
-    GROUP_ROW(G)
-    double s = group_row_sum<G, double>(A.rowptr, A.col, A.val, i, lane, [&](int32_t j) { return x[j]; });
+template <class OP>
+__global__ void k_spmv_f64(int64_t n, OP op, const double *__restrict__ x, double *__restrict__ y) {
+    OP_PROLOGUE(op)
+    GROUP_ROW(OP::G)
+    double s = op.row(i, lane, sd_, [&](int32_t j) { return x[j]; });
     if (lane == 0) y[i] = s;
 }
 
@@ -586,45 +679,50 @@ double now_ms() {
 // Host-side helper binding the level-0 operator and the scalar block.
 struct Kry {
     amg_hierarchy *H;
-    CsrView A;
+    const Level &L0;
     int G;
     int64_t n;
-    unsigned g1, gG;  // grids of element-wise and grouped kernels
+    unsigned g1, gG;  // grids of element-wise and row-product kernels
     double *part;
     KScalars *ks;
     hipStream_t s;
     double rtol;
     double vec, abytes;
 
-    Kry(amg_hierarchy *H_, hipStream_t s_, double rtol_) : H(H_), s(s_), rtol(rtol_) {
-        A = view(H->L[0].A);
-        G = H->L[0].A.grp;
-        n = A.n;
+    Kry(amg_hierarchy *H_, hipStream_t s_, double rtol_) : H(H_), L0(H_->L[0]), s(s_), rtol(rtol_) {
+        G = L0.As.built() ? 1 : L0.A.grp;
+        n = L0.A.n;
         g1 = kgrid(n, 1);
         gG = kgrid(n, G);
         part = H->partials.p;
         ks = H->ks.p;
         vec = 8.0 * n;
-        abytes = csr_bytes(A.n, A.nnz, 8);
+        abytes = op_bytes(L0.A, L0.As, 8);
     }
-    void fin(int op, unsigned nb) {
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kKBlock), 0, s, op, nb, part, rtol, ks);
+    template <class F>
+    void op(F &&f) const {
+        if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
+        else with_csr<double>(L0.A, L0.A.val.p, f);
+    }
+    void fin(int code, unsigned nb) {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kKBlock), 0, s, code, nb, part, rtol, ks);
     }
     void init(const double *b, const double *x, double *r, double *rh, double *p, double *v, bool first) {
         {
             ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec + (rh ? 3 * vec : 0), s);
-#define L_INIT(GG, ...) hipLaunchKernelGGL((k_kr_init<GG>), dim3(gG), dim3(kKBlock), 0, s, A, b, x, r, rh, p, v, part)
-            DISPATCH_G(G, L_INIT, 0)
-#undef L_INIT
+            op([&](auto o) {
+                hipLaunchKernelGGL((k_kr_init<decltype(o)>), dim3(gG), dim3(kKBlock), 0, s, n, o, b, x, r, rh, p, v,
+                                   part);
+            });
         }
         fin(first ? FIN_INIT_FIRST : FIN_INIT_RESTART, gG);
     }
     void true_res(const double *b, const double *x) {
         {
             ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s);
-#define L_TR(GG, ...) hipLaunchKernelGGL((k_true_res<GG>), dim3(gG), dim3(kKBlock), 0, s, A, b, x, part)
-            DISPATCH_G(G, L_TR, 0)
-#undef L_TR
+            op([&](auto o) {
+                hipLaunchKernelGGL((k_true_res<decltype(o)>), dim3(gG), dim3(kKBlock), 0, s, n, o, b, x, part);
+            });
         }
         fin(FIN_TRUE_RES, gG);
     }
@@ -652,12 +750,16 @@ void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, h
     GW_HIP(hipGetLastError());
 }
 
-void spmv_f64(const CsrView &A, int grp, const double *x, double *y, hipStream_t s) {
-    ProfScope ps(K_KRYLOV_SPMV, csr_bytes(A.n, A.nnz, 8) + 16.0 * A.n, s);
-    const int64_t n = A.n;
-#define L_SPMV(GG, ...) hipLaunchKernelGGL((k_spmv_f64<GG>), dim3(grid_rows(n, GG)), dim3(kBlock), 0, s, A, x, y)
-    DISPATCH_G(grp, L_SPMV, 0)
-#undef L_SPMV
+void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s) {
+    const Level &L0 = H->L[0];
+    const int64_t n = L0.A.n;
+    ProfScope ps(K_KRYLOV_SPMV, op_bytes(L0.A, L0.As, 8) + 16.0 * n, s);
+    auto launch = [&](auto o) {
+        using OP = decltype(o);
+        hipLaunchKernelGGL((k_spmv_f64<OP>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, o, x, y);
+    };
+    if (L0.As.built()) launch(OpSell<double>{view(L0.As), L0.As.val.p});
+    else with_csr<double>(L0.A, L0.A.val.p, launch);
     GW_HIP(hipGetLastError());
 }
 
@@ -683,7 +785,6 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
     }
     const int check = std::max(1, sp.check_every);
     int32_t *done = &H->ks.p->done;
-    const int G = K.G;
     int parity = 0;
     for (;;) {
         if (!k.done) {
@@ -698,9 +799,10 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
                     double *po = parity ? pb : pa, *pn = parity ? pa : pb;
                     {
                         ProfScope ps(K_KRYLOV_SPMV, K.abytes + 4 * K.vec, s);
-#define L_CGS(GG, ...) hipLaunchKernelGGL((k_cg_spmv<GG>), dim3(K.gG), dim3(kKBlock), 0, s, K.A, z, po, pn, q, K.part, K.ks)
-                        DISPATCH_G(G, L_CGS, 0)
-#undef L_CGS
+                        K.op([&](auto o) {
+                            hipLaunchKernelGGL((k_cg_spmv<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, z, po,
+                                               pn, q, K.part, K.ks);
+                        });
                     }
                     K.fin(FIN_CG_ALPHA, K.gG);
                     {
@@ -765,7 +867,6 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
     }
     const int check = std::max(1, sp.check_every);
     int32_t *done = &H->ks.p->done;
-    const int G = K.G;
     for (;;) {
         while (!k.done) {
             for (int c = 0; c < check; ++c) {
@@ -776,9 +877,10 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
                 vcycle(H, p, ph, done, s);
                 {
                     ProfScope ps(K_KRYLOV_SPMV, K.abytes + 3 * K.vec, s);
-#define L_BV(GG, ...) hipLaunchKernelGGL((k_bcg_v<GG>), dim3(K.gG), dim3(kKBlock), 0, s, K.A, ph, v, rh, K.part, K.ks)
-                    DISPATCH_G(G, L_BV, 0)
-#undef L_BV
+                    K.op([&](auto o) {
+                        hipLaunchKernelGGL((k_bcg_v<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, ph, v, rh,
+                                           K.part, K.ks);
+                    });
                 }
                 K.fin(FIN_BCG_ALPHA, K.gG);
                 {
@@ -789,9 +891,10 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
                 vcycle(H, sv, sh, done, s);
                 {
                     ProfScope ps(K_KRYLOV_SPMV, K.abytes + 3 * K.vec, s);
-#define L_BT(GG, ...) hipLaunchKernelGGL((k_bcg_t<GG>), dim3(K.gG), dim3(kKBlock), 0, s, K.A, sh, t, sv, K.part, K.ks)
-                    DISPATCH_G(G, L_BT, 0)
-#undef L_BT
+                    K.op([&](auto o) {
+                        hipLaunchKernelGGL((k_bcg_t<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, sh, t, sv,
+                                           K.part, K.ks);
+                    });
                 }
                 K.fin(FIN_BCG_OMEGA, K.gG);
                 {

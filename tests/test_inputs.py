@@ -42,3 +42,17 @@ def test_serve_stream():
     assert {a.sigma2 for a in s} <= {1.0, 2.0, 4.0}
     assert all(4 <= a.corr_len <= 16 for a in s)
     assert np.all(np.diff([a.t for a in s]) >= 0)
+
+
+def test_general_matrix_generators():
+    import scipy.sparse as sp
+    for rowptr, col, val in (gi.random_graph_spd(500, 4, 1), gi.arrow_spd(300, 2)):
+        n = len(rowptr) - 1
+        A = sp.csr_matrix((val, col, rowptr), shape=(n, n))
+        assert (A - A.T).nnz == 0
+        for i in range(n):
+            c = col[rowptr[i]:rowptr[i + 1]]
+            assert np.all(np.diff(c) > 0) and i in c
+        d = A.diagonal()
+        off = np.asarray(abs(A).sum(axis=1)).ravel() - d
+        assert np.all(d > off)
