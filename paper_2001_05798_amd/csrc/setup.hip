@@ -13,6 +13,7 @@
 //   coarsest        dense LU with partial pivoting, then its inverse
 // Built with -ffp-contract=off so that a*b+c is never fused.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "gw_device.h"
@@ -77,11 +78,16 @@ __global__ void k_tr_count(const int32_t *__restrict__ col, int64_t nnz, int32_t
         atomicAdd(&cnt[col[p] + 1], 1);
 }
 
+// G lanes per row of A (long coarse-level rows would serialize one lane).
+template <int G>
 __global__ void k_tr_fill(CsrView A, const int32_t *__restrict__ trow, int32_t *__restrict__ fill,
                           int32_t *__restrict__ tcol, double *__restrict__ tval, int32_t *__restrict__ rowid) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = gtid / G;
+    const int lane = (int)(gtid % G);
     if (i >= A.n) return;
-    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+    const int32_t e = A.rowptr[i + 1];
+    for (int32_t p = A.rowptr[i] + lane; p < e; p += G) {
         int32_t j = A.col[p];
         int32_t pos = trow[j] + atomicAdd(&fill[j], 1);
         tcol[pos] = (int32_t)i;
@@ -129,29 +135,25 @@ __device__ __forceinline__ bool strong_pair(double aij, double aji, double di, d
     return (aij * aij > eps2 * dd) || (aji * aji > eps2 * dd);
 }
 
-__global__ void k_strength_count(CsrView A, CsrView T, const double *__restrict__ diag, double eps2,
-                                 int32_t *__restrict__ cnt) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+__device__ __forceinline__ int32_t strength_count_row(const CsrView &A, const CsrView &T,
+                                                      const double *__restrict__ diag, double eps2, int32_t i) {
     const double di = diag[i];
     int32_t c = 0;
-    union_row(A, T, (int32_t)i, [&](int32_t j, double aij, double aji, int32_t) {
-        if (j != (int32_t)i && strong_pair(aij, aji, di, diag[j], eps2)) ++c;
+    union_row(A, T, i, [&](int32_t j, double aij, double aji, int32_t) {
+        if (j != i && strong_pair(aij, aji, di, diag[j], eps2)) ++c;
     });
-    cnt[i + 1] = c;
+    return c;
 }
 
-__global__ void k_strength_fill(CsrView A, CsrView T, const double *__restrict__ diag, double eps2,
-                                const int32_t *__restrict__ srow, int32_t *__restrict__ scol,
-                                double *__restrict__ sw, uint8_t *__restrict__ strongA,
-                                double *__restrict__ dF) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+__device__ __forceinline__ void strength_fill_row(const CsrView &A, const CsrView &T, const double *__restrict__ diag,
+                                                  double eps2, int32_t i, const int32_t *__restrict__ srow,
+                                                  int32_t *__restrict__ scol, double *__restrict__ sw,
+                                                  uint8_t *__restrict__ strongA, double *__restrict__ dF) {
     const double di = diag[i];
     int32_t q = srow[i];
     double lump = di;  // a_ii + weak off-diagonals in ascending column order
-    union_row(A, T, (int32_t)i, [&](int32_t j, double aij, double aji, int32_t posa) {
-        if (j == (int32_t)i) {
+    union_row(A, T, i, [&](int32_t j, double aij, double aji, int32_t posa) {
+        if (j == i) {
             if (posa >= 0) strongA[posa] = 0;
             return;
         }
@@ -168,6 +170,159 @@ __global__ void k_strength_fill(CsrView A, CsrView T, const double *__restrict__
         }
     });
     dF[i] = lump;
+}
+
+__global__ void k_strength_count(CsrView A, CsrView T, const double *__restrict__ diag, double eps2,
+                                 int32_t *__restrict__ cnt) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    cnt[i + 1] = strength_count_row(A, T, diag, eps2, (int32_t)i);
+}
+
+__global__ void k_strength_fill(CsrView A, CsrView T, const double *__restrict__ diag, double eps2,
+                                const int32_t *__restrict__ srow, int32_t *__restrict__ scol,
+                                double *__restrict__ sw, uint8_t *__restrict__ strongA,
+                                double *__restrict__ dF) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    strength_fill_row(A, T, diag, eps2, (int32_t)i, srow, scol, sw, strongA, dF);
+}
+
+// Number of entries of the sorted a[0..n) below key.
+__device__ __forceinline__ int32_t lower_bound_i32(const int32_t *__restrict__ a, int32_t n, int32_t key) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int G>
+__device__ __forceinline__ int32_t grp_scan_incl(int32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        int32_t w = __shfl_up(v, o, G);
+        if (lane >= o) v += w;
+    }
+    return v;
+}
+
+// The same strength graph with G lanes per row, for rows of a few dozen
+// entries (coarse levels), where walking the union one entry at a time is a
+// long chain of dependent loads.  The union of row i of A and of A^T is not
+// formed: the lanes take A's entries (a_ji found by binary search in row i
+// of A^T), then the entries of A^T's row whose column A's row lacks (a_ij =
+// 0).  A strong entry's place in the column-ordered union is its count of
+// strong predecessors in its own list plus the strong entries of the other
+// list with a smaller column (exclusive prefix counts kept in LDS).  The
+// lumped diagonal is summed in column order, one lane's value after the
+// other.  Rows longer than the LDS lists take the one-lane walk.
+template <int G, bool FILL>
+__global__ void __launch_bounds__(kBlock) k_strength_grp(CsrView A, CsrView T, const double *__restrict__ diag,
+                                                         double eps2, int32_t *__restrict__ cnt,
+                                                         const int32_t *__restrict__ srow, int32_t *__restrict__ scol,
+                                                         double *__restrict__ sw, uint8_t *__restrict__ strongA,
+                                                         double *__restrict__ dF) {
+    constexpr int CAP = 16 * G;
+    __shared__ int32_t pref[FILL ? (kBlock / G) * 2 * (CAP + 1) : 1];
+    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t row = gtid / G;
+    const int lane = (int)(threadIdx.x % G);
+    if (row >= A.n) return;
+    const int32_t i = (int32_t)row;
+    const int32_t pa = A.rowptr[i], la = A.rowptr[i + 1] - pa;
+    const int32_t pt = T.rowptr[i], lt = T.rowptr[i + 1] - pt;
+    if (la > CAP || lt > CAP) {
+        if (lane == 0) {
+            if (FILL) strength_fill_row(A, T, diag, eps2, i, srow, scol, sw, strongA, dF);
+            else cnt[i + 1] = strength_count_row(A, T, diag, eps2, i);
+        }
+        return;
+    }
+    const double di = diag[i];
+    int32_t *PA = pref + (FILL ? (threadIdx.x / G) * 2 * (CAP + 1) : 0);
+    int32_t *PT = PA + (CAP + 1);
+    // entry a of A's row: column, a_ij, a_ji, strong
+    auto a_entry = [&](int32_t a, int32_t &j, double &aij, double &aji, int32_t &idx) -> bool {
+        j = A.col[pa + a];
+        aij = A.val[pa + a];
+        idx = lower_bound_i32(T.col + pt, lt, j);
+        aji = (idx < lt && T.col[pt + idx] == j) ? T.val[pt + idx] : 0.0;
+        return j != i && strong_pair(aij, aji, di, diag[j], eps2);
+    };
+    // entry u of A^T's row: column, a_ji, strong and absent from A's row
+    auto t_entry = [&](int32_t u, int32_t &j, double &aji, int32_t &idx) -> bool {
+        j = T.col[pt + u];
+        aji = T.val[pt + u];
+        idx = lower_bound_i32(A.col + pa, la, j);
+        const bool only = !(idx < la && A.col[pa + idx] == j);
+        return only && j != i && strong_pair(0.0, aji, di, diag[j], eps2);
+    };
+    int32_t runA = 0, runT = 0;
+    double lump = di;
+    for (int32_t c0 = 0; c0 < la; c0 += G) {
+        const int32_t a = c0 + lane;
+        const bool in = a < la;
+        int32_t j = i, idx = 0;
+        double aij = 0.0, aji = 0.0;
+        const bool st = in && a_entry(a, j, aij, aji, idx);
+        const int32_t sc = st ? 1 : 0;
+        const int32_t incl = grp_scan_incl<G>(sc, lane);
+        if (FILL) {
+            if (in) {
+                strongA[pa + a] = st ? 1 : 0;
+                PA[a] = runA + incl - sc;
+            }
+            const double weak = (in && j != i && !st) ? aij : 0.0;
+            for (int t = 0; t < G; ++t) {
+                const double w = __shfl(weak, t, G);
+                if (c0 + t < la && w != 0.0) lump = lump + w;
+            }
+        }
+        runA += __shfl(incl, G - 1, G);
+    }
+    for (int32_t c0 = 0; c0 < lt; c0 += G) {
+        const int32_t u = c0 + lane;
+        const bool in = u < lt;
+        int32_t j = i, idx = 0;
+        double aji = 0.0;
+        const bool st = in && t_entry(u, j, aji, idx);
+        const int32_t sc = st ? 1 : 0;
+        const int32_t incl = grp_scan_incl<G>(sc, lane);
+        if (FILL && in) PT[u] = runT + incl - sc;
+        runT += __shfl(incl, G - 1, G);
+    }
+    if (!FILL) {
+        if (lane == 0) cnt[i + 1] = runA + runT;
+        return;
+    }
+    if (lane == 0) {
+        PA[la] = runA;
+        PT[lt] = runT;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int32_t q0 = srow[i];
+    for (int32_t a = lane; a < la; a += G) {
+        int32_t j, idx;
+        double aij, aji;
+        if (!a_entry(a, j, aij, aji, idx)) continue;
+        const int32_t pos = PA[a] + PT[idx];
+        scol[q0 + pos] = j;
+        const double x = fabs(aij), y = fabs(aji);
+        sw[q0 + pos] = x > y ? x : y;
+    }
+    for (int32_t u = lane; u < lt; u += G) {
+        int32_t j, idx;
+        double aji;
+        if (!t_entry(u, j, aji, idx)) continue;
+        const int32_t pos = PT[u] + PA[idx];
+        scol[q0 + pos] = j;
+        const double y = fabs(aji);
+        sw[q0 + pos] = 0.0 > y ? 0.0 : y;
+    }
+    if (lane == 0) dF[i] = lump;
 }
 
 // ------------------------------------------------------------------ MIS-2 --
@@ -522,17 +677,41 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
         // row lengths; the scan over them also yields the largest row
         int32_t tot = group_sum<G>(fresh_count);
         if (active && lane == 0) cnt[row + 1] = tot;
-    } else {
-        __syncthreads();
-        if (active) {
-            const int32_t i = (int32_t)row;
-            const int32_t out0 = crow[i];
+    } else if (active) {
+        // Sorted write-out: the occupied slots are packed into the stage
+        // (when the row fits it) so that each entry's rank is counted over
+        // the row's entries only, not over the whole table.
+        __builtin_amdgcn_wave_barrier();
+        const int32_t i = (int32_t)row;
+        const int32_t out0 = crow[i];
+        int32_t mine = 0;
+        for (int32_t s = lane; s < H; s += G) mine += keys[s] >= 0;
+        const int32_t incl = group_scan_incl<G>(mine, lane);
+        const int32_t m = __shfl(incl, G - 1, G);
+        if (m <= S) {
+            int32_t q = incl - mine;
             for (int32_t s = lane; s < H; s += G) {
-                int32_t J = keys[s];
+                const int32_t J = keys[s];
+                if (J < 0) continue;
+                stJ[q] = J;
+                stV[q] = vals[s];
+                ++q;
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int32_t t = lane; t < m; t += G) {
+                const int32_t J = stJ[t];
+                int32_t rank = 0;
+                for (int32_t u = 0; u < m; ++u) rank += stJ[u] < J;
+                ccol[out0 + rank] = J;
+                cval[out0 + rank] = epi(i, J, stV[t]);
+            }
+        } else {
+            for (int32_t s = lane; s < H; s += G) {
+                const int32_t J = keys[s];
                 if (J < 0) continue;
                 int32_t rank = 0;
                 for (int32_t u = 0; u < H; ++u) {
-                    int32_t K2 = keys[u];
+                    const int32_t K2 = keys[u];
                     rank += (K2 >= 0 && K2 < J);
                 }
                 ccol[out0 + rank] = J;
@@ -806,8 +985,18 @@ void transpose(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total) 
         tcol((size_t)std::max<int64_t>(A.nnz, 1));
     DBuf<double> tval((size_t)std::max<int64_t>(A.nnz, 1));
     fill_i32(fill.p, 0, A.ncols, s);
-    hipLaunchKernelGGL(k_tr_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, T.rowptr.p, fill.p, tcol.p,
-                       tval.p, rowid.p);
+    const int G = lane_group_for(A.n ? (double)A.nnz / (double)A.n : 0.0);
+    auto fill_rows = [&](auto gc) {
+        constexpr int GG = decltype(gc)::value;
+        hipLaunchKernelGGL((k_tr_fill<GG>), dim3(blocks_for((int64_t)A.n * GG)), dim3(kBlock), 0, s, A, T.rowptr.p,
+                           fill.p, tcol.p, tval.p, rowid.p);
+    };
+    switch (G) {
+        case 1: fill_rows(std::integral_constant<int, 1>()); break;
+        case 4: fill_rows(std::integral_constant<int, 4>()); break;
+        case 16: fill_rows(std::integral_constant<int, 16>()); break;
+        default: fill_rows(std::integral_constant<int, 64>()); break;
+    }
     if (A.nnz > 0)
         hipLaunchKernelGGL(k_tr_sort, dim3(blocks_for(A.nnz)), dim3(kBlock), 0, s, T.rowptr.p, rowid.p, tcol.p,
                            tval.p, A.nnz, T.col.p, T.val.p);
@@ -844,10 +1033,37 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     S.rowptr.alloc((size_t)n + 1);
     fill_i32(S.rowptr.p, 0, 1, s);
     DBuf<uint8_t> strongA((size_t)std::max<int64_t>(A.nnz, 1));
+    const int Gs = lane_group_for(n ? (double)A.nnz / (double)n : 0.0);
+    auto launch_strength = [&](bool fill) {
+        const CsrView Tv = view(T);
+        auto grp = [&](auto gc) {
+            constexpr int GG = decltype(gc)::value;
+            const dim3 grid(blocks_for((int64_t)n * GG));
+            if (fill)
+                hipLaunchKernelGGL((k_strength_grp<GG, true>), grid, dim3(kBlock), 0, s, A, Tv, diag.p, eps2,
+                                   (int32_t *)nullptr, S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p);
+            else
+                hipLaunchKernelGGL((k_strength_grp<GG, false>), grid, dim3(kBlock), 0, s, A, Tv, diag.p, eps2,
+                                   S.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr,
+                                   (uint8_t *)nullptr, (double *)nullptr);
+        };
+        switch (Gs) {
+            case 1:
+                if (fill)
+                    hipLaunchKernelGGL(k_strength_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, Tv, diag.p, eps2,
+                                       S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p);
+                else
+                    hipLaunchKernelGGL(k_strength_count, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, Tv, diag.p,
+                                       eps2, S.rowptr.p);
+                break;
+            case 4: grp(std::integral_constant<int, 4>()); break;
+            case 16: grp(std::integral_constant<int, 16>()); break;
+            default: grp(std::integral_constant<int, 64>()); break;
+        }
+    };
     {
         ProfScope ps(K_STRENGTH, (double)A.nnz * 24 + n * 16.0, s);
-        hipLaunchKernelGGL(k_strength_count, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, view(T), diag.p, eps2,
-                           S.rowptr.p);
+        launch_strength(false);
         GW_HIP(hipGetLastError());
     }
     scan_inclusive_i32(S.rowptr.p + 1, n, total.p, s);
@@ -856,8 +1072,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     sw.alloc((size_t)std::max<int64_t>(S.nnz, 1));
     {
         ProfScope ps(K_STRENGTH, (double)A.nnz * 25 + n * 24.0 + S.nnz * 12.0, s);
-        hipLaunchKernelGGL(k_strength_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, view(T), diag.p, eps2,
-                           S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p);
+        launch_strength(true);
         GW_HIP(hipGetLastError());
     }
     T = Csr();

@@ -27,13 +27,37 @@ namespace {
 
 // ----------------------------------------------------------- operators ---
 // Lanes of a group own one row: strided partial sums, then a butterfly over
-// the group (groups are aligned power-of-two lane ranges of one wave).
+// the group (groups are aligned power-of-two lane ranges of one wave).  Each
+// lane loads U of its entries before summing their products, so the gathers
+// overlap (U*G slots cover a typical row of a matrix given G lanes: G is
+// picked from the mean row length); slots past the row end take value 0 at
+// the row's first column (a finite x makes them exact zeros; a non-finite x
+// there makes the row non-finite in any case).
 template <int G, class V, class F>
 __device__ __forceinline__ V group_row_sum(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                            const V *__restrict__ val, int64_t i, int lane, F &&xj) {
+    constexpr int U = G == 1 ? 4 : (G == 64 ? 1 : 2);
     V s = 0;
-    const int32_t e = rowptr[i + 1];
-    for (int32_t p = rowptr[i] + lane; p < e; p += G) s += val[p] * xj(col[p]);
+    const int32_t b = rowptr[i], e = rowptr[i + 1];
+    if (b < e) {
+        const int32_t cb = col[b];
+        for (int32_t q = b + lane; q < e; q += U * G) {
+            V a[U];
+            int32_t c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t p = q + u * G;
+                const bool in = p < e;
+                const int32_t pc = in ? p : b;
+                const V av = val[pc];
+                const int32_t cv = col[pc];
+                a[u] = in ? av : V(0);
+                c[u] = in ? cv : cb;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += a[u] * xj(c[u]);
+        }
+    }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, dev::kWave);
     return s;
