@@ -326,55 +326,103 @@ __global__ void __launch_bounds__(kBlock) k_strength_grp(CsrView A, CsrView T, c
 }
 
 // ------------------------------------------------------------------ MIS-2 --
+// Kernels that end in one same-address atomic per block run a capped grid
+// over a row loop: such atomics serialize (about 10 ns each), so a grid of one
+// block per 256 rows of a million-row level would spend tens of microseconds
+// on them alone.
+constexpr unsigned kAtomicBlocks = 1024;
+
 __global__ void k_mis_init(const int32_t *__restrict__ srow, int32_t n, uint32_t *__restrict__ state,
                            int32_t *und) {
     __shared__ int32_t sm[kBlock / dev::kWave];
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int32_t c = 0;
-    if (i < n) {
-        bool kept = srow[i + 1] > srow[i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const bool kept = srow[i + 1] > srow[i];
         state[i] = kept ? ST_UND : ST_OUT;
-        c = kept;
+        c += kept;
     }
     c = dev::block_sum(c, sm);
     if (threadIdx.x == 0 && c) atomicAdd(und, c);
 }
 
-// m1_i = max(key_i, max_{j in S(i)} key_j).  Skipped once a previous round
-// left nothing undecided.
+template <int G, class T>
+__device__ __forceinline__ T grp_max(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, G);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <int G, class T>
+__device__ __forceinline__ T grp_min(T v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, G);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Row of a G-lane group: index, lane, and whether it exists.  Every lane of
+// a block stays to the end (block reductions follow).
+#define GRP_ROW(G, n)                                                            \
+    const int64_t row_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / (G); \
+    const int lane_ = (int)(threadIdx.x % (G));                                  \
+    const bool has_ = row_ < (n);                                                \
+    const int32_t i = has_ ? (int32_t)row_ : 0;
+
+// Rows visited by G-lane groups over the whole (capped) grid.
+#define GRP_LOOP(G, n)                                                                      \
+    const int lane_ = (int)(threadIdx.x % (G));                                             \
+    for (int64_t row_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / (G); row_ < (n); \
+         row_ += (int64_t)gridDim.x * blockDim.x / (G))
+
+// m1_i = max(key_i, max_{j in S(i)} key_j) (a maximum: any lane order).
+// Skipped once a previous round left nothing undecided.
+template <int G>
 __global__ void k_mis_m1(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
                          const uint32_t *__restrict__ state, uint32_t salt, uint64_t *__restrict__ m1,
                          const int32_t *prev_und) {
     if (*prev_und == 0) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t m = mis_key(state[i], salt, (int32_t)i);
-    for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
-        int32_t j = scol[p];
-        uint64_t kj = mis_key(state[j], salt, j);
+    GRP_ROW(G, n)
+    if (!has_) return;
+    uint64_t m = lane_ == 0 ? mis_key(state[i], salt, i) : 0ull;
+    const int32_t e = srow[i + 1];
+    for (int32_t p = srow[i] + lane_; p < e; p += G) {
+        const int32_t j = scol[p];
+        const uint64_t kj = mis_key(state[j], salt, j);
         m = kj > m ? kj : m;
     }
-    m1[i] = m;
+    m = grp_max<G>(m);
+    if (lane_ == 0) m1[i] = m;
 }
 
 // m2_i = max(m1_i, max_j m1_j); UNDECIDED i becomes ROOT if m2_i is its own
 // key, OUT if m2_i belongs to a ROOT.  Counts the nodes left undecided.
+template <int G>
 __global__ void k_mis_m2(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
                          uint32_t *__restrict__ state, uint32_t salt, const uint64_t *__restrict__ m1,
                          const int32_t *prev_und, int32_t *und) {
     __shared__ int32_t sm[kBlock / dev::kWave];
     if (*prev_und == 0) return;
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int32_t left = 0;
-    if (i < n && state[i] == ST_UND) {
-        uint64_t m = m1[i];
-        for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
-            uint64_t v = m1[scol[p]];
+    GRP_LOOP(G, n) {
+        const int32_t i = (int32_t)row_;
+        if (state[i] != ST_UND) continue;
+        uint64_t m = lane_ == 0 ? m1[i] : 0ull;
+        const int32_t e = srow[i + 1];
+        for (int32_t p = srow[i] + lane_; p < e; p += G) {
+            const uint64_t v = m1[scol[p]];
             m = v > m ? v : m;
         }
-        if (m == mis_key(ST_UND, salt, (int32_t)i)) state[i] = ST_ROOT;
-        else if ((m >> 62) == ST_ROOT) state[i] = ST_OUT;
-        else left = 1;
+        m = grp_max<G>(m);
+        if (lane_ == 0) {
+            if (m == mis_key(ST_UND, salt, i)) state[i] = ST_ROOT;
+            else if ((m >> 62) == ST_ROOT) state[i] = ST_OUT;
+            else left += 1;
+        }
     }
     left = dev::block_sum(left, sm);
     if (threadIdx.x == 0 && left) atomicAdd(und, left);
@@ -387,53 +435,88 @@ __global__ void k_root_flags(const uint32_t *__restrict__ state, int32_t n, int3
     if (i == 0) flag[0] = 0;
 }
 
+// Aggregate of i: its own id if ROOT, else that of its first ROOT neighbour
+// in column order (smallest position).
+template <int G>
 __global__ void k_agg_pass1(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
                             const uint32_t *__restrict__ state, const int32_t *__restrict__ ids,
                             int32_t *__restrict__ agg1) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t a = -1;
+    GRP_ROW(G, n)
+    if (!has_) return;
     if (state[i] == ST_ROOT) {
-        a = ids[i];
-    } else {
-        for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
-            int32_t j = scol[p];
-            if (state[j] == ST_ROOT) { a = ids[j]; break; }
+        if (lane_ == 0) agg1[i] = ids[i];
+        return;
+    }
+    const int32_t e = srow[i + 1];
+    int32_t first = INT32_MAX;
+    for (int32_t p = srow[i] + lane_; p < e; p += G) {
+        if (state[scol[p]] == ST_ROOT) {
+            first = p;
+            break;
         }
     }
-    agg1[i] = a;
+    first = grp_min<G>(first);
+    if (lane_ == 0) agg1[i] = first == INT32_MAX ? -1 : ids[scol[first]];
 }
 
+// Unassigned i joins the neighbouring aggregate of largest strength weight,
+// the smallest aggregate id among equal weights.
+template <int G>
 __global__ void k_agg_pass2(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol,
                             const double *__restrict__ sw, int32_t n, const int32_t *__restrict__ agg1,
                             int32_t *__restrict__ agg) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t a = agg1[i];
-    if (a < 0 && srow[i + 1] > srow[i]) {
-        double best_w = -1.0;
-        int32_t best = -1;
-        for (int32_t p = srow[i]; p < srow[i + 1]; ++p) {
-            int32_t c = agg1[scol[p]];
-            if (c < 0) continue;
-            double w = sw[p];
-            if (w > best_w || (w == best_w && c < best)) { best_w = w; best = c; }
-        }
-        a = best;
+    GRP_ROW(G, n)
+    if (!has_) return;
+    const int32_t a = agg1[i];
+    const int32_t b = srow[i], e = srow[i + 1];
+    if (a >= 0 || e == b) {
+        if (lane_ == 0) agg[i] = a;
+        return;
     }
-    agg[i] = a;
+    double best_w = -1.0;
+    int32_t best = -1;
+    for (int32_t p = b + lane_; p < e; p += G) {
+        const int32_t c = agg1[scol[p]];
+        if (c < 0) continue;
+        const double w = sw[p];
+        if (w > best_w || (w == best_w && c < best)) { best_w = w; best = c; }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const double w = __shfl_xor(best_w, o, G);
+        const int32_t c = __shfl_xor(best, o, G);
+        if (w > best_w || (w == best_w && c < best && c >= 0)) { best_w = w; best = c; }
+    }
+    if (lane_ == 0) agg[i] = best;
 }
 
 // ----------------------------------------------------- prolongator weight --
 // rho = max_i (sum_j |a_ij|, ascending j) / a_ii; positive doubles order like
 // their bit patterns, so an integer atomicMax is exact.
+// Sum over row i in column order, lane values taken one after another.
+template <int G, class F>
+__device__ __forceinline__ double grp_ordered_sum(int32_t b, int32_t e, int lane, F &&term) {
+    double s = 0.0;
+    for (int32_t c0 = b; c0 < e; c0 += G) {
+        const int32_t p = c0 + lane;
+        const double v = p < e ? term(p) : 0.0;
+        for (int t = 0; t < G; ++t) {
+            const double w = __shfl(v, t, G);
+            if (c0 + t < e) s = s + w;
+        }
+    }
+    return s;
+}
+
+template <int G>
 __global__ void k_rho(CsrView A, const double *__restrict__ diag, unsigned long long *rho_bits) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double r = 0.0;
-    if (i < A.n) {
-        double s = 0.0;
-        for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s = s + fabs(A.val[p]);
-        r = s / diag[i];
+    GRP_LOOP(G, A.n) {
+        const int32_t i = (int32_t)row_;
+        const double s = grp_ordered_sum<G>(A.rowptr[i], A.rowptr[i + 1], lane_,
+                                            [&](int32_t p) { return fabs(A.val[p]); });
+        const double ri = s / diag[i];
+        r = ri > r ? ri : r;
     }
     __shared__ double sm[kBlock / dev::kWave];
     r = dev::block_max(r, sm);
@@ -527,16 +610,17 @@ struct EpiSmoothP {
 // Upper bound of the distinct columns of each output row.
 template <class AR, class BR>
 __global__ void k_spgemm_ub(AR ar, BR br, int32_t nrows, int32_t *ub_max) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int32_t u = 0;
-    if (i < nrows) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t ui = 0;
         for (int32_t p = ar.begin((int32_t)i); p < ar.end((int32_t)i); ++p) {
             int32_t k, base, len;
             double a;
             if (!ar.get(p, (int32_t)i, k, a)) continue;
             br.row(k, base, len);
-            u += len;
+            ui += len;
         }
+        u = ui > u ? ui : u;
     }
     __shared__ int32_t sm[kBlock / dev::kWave];
     u = dev::block_max(u, sm);
@@ -723,18 +807,32 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
 }
 
 // -------------------------------------------------------------- smoother --
+template <int G>
 __global__ void k_smoother_diag(CsrView A, const double *__restrict__ diag, int spai0, double omega,
                                 double *__restrict__ M) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    double aii = diag[i];
+    GRP_ROW(G, A.n)
+    if (!has_) return;
+    const double aii = diag[i];
     if (spai0) {
-        double s = 0.0;
-        for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) s = s + A.val[p] * A.val[p];
-        M[i] = aii / s;
-    } else {
+        const double s = grp_ordered_sum<G>(A.rowptr[i], A.rowptr[i + 1], lane_,
+                                            [&](int32_t p) { return A.val[p] * A.val[p]; });
+        if (lane_ == 0) M[i] = aii / s;
+    } else if (lane_ == 0) {
         M[i] = omega / aii;
     }
+}
+
+// Diagonal of each row (0 when absent).
+template <int G>
+__global__ void k_diag(CsrView A, double *__restrict__ diag) {
+    GRP_ROW(G, A.n)
+    if (!has_) return;
+    const int32_t e = A.rowptr[i + 1];
+    int32_t at = -1;
+    for (int32_t p = A.rowptr[i] + lane_; p < e; p += G)
+        if (A.col[p] == i) at = p;
+    at = grp_max<G>(at);
+    if (lane_ == 0) diag[i] = at >= 0 ? A.val[at] : 0.0;
 }
 
 __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
@@ -888,7 +986,8 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
     fill_i32(ctr.p, 0, 8, s);
     {
         ProfScope ps(K_SPGEMM, 0, s);
-        hipLaunchKernelGGL((k_spgemm_ub<AR, BR>), dim3(blocks_for(nrows)), dim3(kBlock), 0, s, ar, br, nrows, ctr.p);
+        hipLaunchKernelGGL((k_spgemm_ub<AR, BR>), dim3(std::min(blocks_for(nrows), kAtomicBlocks)), dim3(kBlock), 0, s,
+                           ar, br, nrows, ctr.p);
     }
     int32_t ub = st.read(ctr.p, s);
     int64_t cap = std::min<int64_t>(ub, ncols);
@@ -958,10 +1057,25 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
 #undef SPG_NUM
 }
 
+// Call f with the lane-group width (as an integral constant) for rows of
+// this mean length.
+template <class F>
+void with_group(double mean_len, F &&f) {
+    switch (lane_group_for(mean_len)) {
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 16: f(std::integral_constant<int, 16>()); break;
+        default: f(std::integral_constant<int, 64>()); break;
+    }
+}
+
+double mean_row(int64_t nnz, int64_t n) { return n > 0 ? (double)nnz / (double)n : 0.0; }
+
 void csr_diag(const CsrView &A, double *diag, hipStream_t s) {
-    DBuf<int32_t> bad(1);
-    fill_i32(bad.p, 0, 1, s);
-    hipLaunchKernelGGL(k_csr_check, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag, bad.p, 0);
+    with_group(mean_row(A.nnz, A.n), [&](auto gc) {
+        constexpr int G = decltype(gc)::value;
+        hipLaunchKernelGGL((k_diag<G>), dim3(blocks_for((int64_t)A.n * G)), dim3(kBlock), 0, s, A, diag);
+    });
     GW_HIP(hipGetLastError());
 }
 
@@ -1088,20 +1202,26 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     const uint32_t salt = level_salt(prm.seed, l);
     {
         ProfScope ps(K_MIS2, n * 8.0, s);
-        hipLaunchKernelGGL(k_mis_init, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, n, state.p, und.p);
+        hipLaunchKernelGGL(k_mis_init, dim3(std::min(blocks_for(n), kAtomicBlocks)), dim3(kBlock), 0, s, S.rowptr.p, n,
+                           state.p, und.p);
         GW_HIP(hipGetLastError());
     }
     int rounds = 0;
+    const double srow_mean = mean_row(S.nnz, n);
     int32_t left = st.read(und.p, s);
     while (left > 0) {
         GW_REQUIRE(rounds + kBatch <= kMaxRounds, "amg_setup: MIS-2 did not terminate");
         for (int b = 0; b < kBatch; ++b) {
             int r = rounds + b;
             ProfScope ps(K_MIS2, (double)S.nnz * 8 + n * 20.0, s);
-            hipLaunchKernelGGL(k_mis_m1, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p,
-                               salt, m1.p, und.p + r);
-            hipLaunchKernelGGL(k_mis_m2, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p,
-                               salt, m1.p, und.p + r, und.p + r + 1);
+            with_group(srow_mean, [&](auto gc) {
+                constexpr int G = decltype(gc)::value;
+                const dim3 grid(blocks_for((int64_t)n * G));
+                hipLaunchKernelGGL((k_mis_m1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
+                                   m1.p, und.p + r);
+                hipLaunchKernelGGL((k_mis_m2<G>), dim3(std::min(grid.x, kAtomicBlocks)), dim3(kBlock), 0, s,
+                                   S.rowptr.p, S.col.p, n, state.p, salt, m1.p, und.p + r, und.p + r + 1);
+            });
         }
         GW_HIP(hipGetLastError());
         std::vector<int32_t> h(kBatch);
@@ -1128,10 +1248,14 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         ProfScope ps(K_AGGREGATE, (double)S.nnz * 16 + n * 24.0, s);
         hipLaunchKernelGGL(k_root_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, state.p, n, ids.p);
         scan_inclusive_i32(ids.p + 1, n, total.p, s);
-        hipLaunchKernelGGL(k_agg_pass1, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p,
-                           ids.p, agg1.p);
-        hipLaunchKernelGGL(k_agg_pass2, dim3(blocks_for(n)), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, sw.p, n,
-                           agg1.p, Lv.agg.p);
+        with_group(srow_mean, [&](auto gc) {
+            constexpr int G = decltype(gc)::value;
+            const dim3 grid(blocks_for((int64_t)n * G));
+            hipLaunchKernelGGL((k_agg_pass1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, ids.p,
+                               agg1.p);
+            hipLaunchKernelGGL((k_agg_pass2<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, sw.p, n, agg1.p,
+                               Lv.agg.p);
+        });
         GW_HIP(hipGetLastError());
     }
     const int64_t nc = st.read(total.p, s);
@@ -1146,10 +1270,14 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     // smoothed prolongator
     DBuf<unsigned long long> rho_bits(1);
     DBuf<double> omega(1);
-    GW_HIP(hipMemsetAsync(rho_bits.p, 0, sizeof(unsigned long long), s));
+    fill_i32(reinterpret_cast<int32_t *>(rho_bits.p), 0, 2, s);
     {
         ProfScope ps(K_SETUP_MISC, (double)A.nnz * 8 + n * 8.0, s);
-        hipLaunchKernelGGL(k_rho, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, diag.p, rho_bits.p);
+        with_group(mean_row(A.nnz, n), [&](auto gc) {
+            constexpr int G = decltype(gc)::value;
+            hipLaunchKernelGGL((k_rho<G>), dim3(std::min(blocks_for((int64_t)n * G), kAtomicBlocks)), dim3(kBlock), 0,
+                               s, A, diag.p, rho_bits.p);
+        });
         hipLaunchKernelGGL(k_omega, dim3(1), dim3(64), 0, s, rho_bits.p, omega.p);
         GW_HIP(hipGetLastError());
     }
@@ -1181,10 +1309,12 @@ void make_smoother(amg_hierarchy *H, int l, hipStream_t s) {
     csr_diag(A, diag.p, s);
     Lv.M.alloc(A.n);
     ProfScope ps(K_SETUP_MISC, (double)A.nnz * 12 + A.n * 16.0, s);
-    hipLaunchKernelGGL(k_smoother_diag, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag.p,
-                       H->prm.smoother == GW_SMOOTHER_SPAI0 ? 1 : 0, H->prm.omega, Lv.M.p);
+    with_group(mean_row(A.nnz, A.n), [&](auto gc) {
+        constexpr int G = decltype(gc)::value;
+        hipLaunchKernelGGL((k_smoother_diag<G>), dim3(blocks_for((int64_t)A.n * G)), dim3(kBlock), 0, s, A, diag.p,
+                           H->prm.smoother == GW_SMOOTHER_SPAI0 ? 1 : 0, H->prm.omega, Lv.M.p);
+    });
     GW_HIP(hipGetLastError());
-    GW_HIP(hipStreamSynchronize(s));
 }
 
 void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s) {
@@ -1200,7 +1330,6 @@ void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s) {
     if (Lv.R.n) conv(Lv.R.val, Lv.R.val32);
     if (Lv.M.n) conv(Lv.M, Lv.M32);
     GW_HIP(hipGetLastError());
-    GW_HIP(hipStreamSynchronize(s));
 }
 
 void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
