@@ -607,19 +607,24 @@ struct EpiSmoothP {
     }
 };
 
-// Upper bound of the distinct columns of each output row.
-template <class AR, class BR>
+// Upper bound of the distinct columns of each output row (the sum of the B
+// row lengths), largest over all rows; G lanes per output row.
+template <int G, class AR, class BR>
 __global__ void k_spgemm_ub(AR ar, BR br, int32_t nrows, int32_t *ub_max) {
     int32_t u = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows; i += (int64_t)gridDim.x * blockDim.x) {
+    GRP_LOOP(G, nrows) {
+        const int32_t i = (int32_t)row_;
         int32_t ui = 0;
-        for (int32_t p = ar.begin((int32_t)i); p < ar.end((int32_t)i); ++p) {
+        const int32_t e = ar.end(i);
+        for (int32_t p = ar.begin(i) + lane_; p < e; p += G) {
             int32_t k, base, len;
             double a;
-            if (!ar.get(p, (int32_t)i, k, a)) continue;
+            if (!ar.get(p, i, k, a)) continue;
             br.row(k, base, len);
             ui += len;
         }
+#pragma unroll
+        for (int o = G / 2; o > 0; o >>= 1) ui += __shfl_xor(ui, o, G);
         u = ui > u ? ui : u;
     }
     __shared__ int32_t sm[kBlock / dev::kWave];
@@ -957,6 +962,20 @@ struct Staging {
     }
 };
 
+// Call f with the lane-group width (as an integral constant) for rows of
+// this mean length.
+template <class F>
+void with_group(double mean_len, F &&f) {
+    switch (lane_group_for(mean_len)) {
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 16: f(std::integral_constant<int, 16>()); break;
+        default: f(std::integral_constant<int, 64>()); break;
+    }
+}
+
+double mean_row(int64_t nnz, int64_t n) { return n > 0 ? (double)nnz / (double)n : 0.0; }
+
 int pow2_bits_at_least(int64_t v) {
     int b = 4;
     while (b < 30 && ((int64_t)1 << b) < v) ++b;
@@ -965,7 +984,6 @@ int pow2_bits_at_least(int64_t v) {
 
 constexpr int kMaxHashBits = 12;  // 4096 slots per output row
 
-// C = (A-side) x (B-side) with fixed summation order; C has `ncols` columns.
 // Lanes per output row: one A-side entry per lane, so a typical row is one
 // staging segment.
 int spgemm_group(double avg_a_len) {
@@ -986,8 +1004,12 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
     fill_i32(ctr.p, 0, 8, s);
     {
         ProfScope ps(K_SPGEMM, 0, s);
-        hipLaunchKernelGGL((k_spgemm_ub<AR, BR>), dim3(std::min(blocks_for(nrows), kAtomicBlocks)), dim3(kBlock), 0, s,
-                           ar, br, nrows, ctr.p);
+        // short rows: one lane per row (the row sums are a few loads)
+        with_group(avg_a_len > 12.0 ? avg_a_len : 1.0, [&](auto gc) {
+            constexpr int GU = decltype(gc)::value;
+            hipLaunchKernelGGL((k_spgemm_ub<GU, AR, BR>), dim3(std::min(blocks_for((int64_t)nrows * GU), kAtomicBlocks)),
+                               dim3(kBlock), 0, s, ar, br, nrows, ctr.p);
+        });
     }
     int32_t ub = st.read(ctr.p, s);
     int64_t cap = std::min<int64_t>(ub, ncols);
@@ -1007,6 +1029,7 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
         while (Sx > 32 && (H + Sx) * per > kMaxLds) Sx /= 2;
         const size_t bytes_group = (H + Sx) * per;
         int groups = (int)std::min<size_t>(kBlock / G, std::max<size_t>(1, kMaxLds / bytes_group));
+        if (groups >= dev::kWave / G) groups -= groups % (dev::kWave / G);  // whole waves
         unsigned grid = (unsigned)((nrows + groups - 1) / groups);
         if (grid == 0) grid = 1;
         kern(dim3(grid), dim3(groups * G), groups * bytes_group, Sx);
@@ -1056,20 +1079,6 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
 #undef SPG_SYM
 #undef SPG_NUM
 }
-
-// Call f with the lane-group width (as an integral constant) for rows of
-// this mean length.
-template <class F>
-void with_group(double mean_len, F &&f) {
-    switch (lane_group_for(mean_len)) {
-        case 1: f(std::integral_constant<int, 1>()); break;
-        case 4: f(std::integral_constant<int, 4>()); break;
-        case 16: f(std::integral_constant<int, 16>()); break;
-        default: f(std::integral_constant<int, 64>()); break;
-    }
-}
-
-double mean_row(int64_t nnz, int64_t n) { return n > 0 ? (double)nnz / (double)n : 0.0; }
 
 void csr_diag(const CsrView &A, double *diag, hipStream_t s) {
     with_group(mean_row(A.nnz, A.n), [&](auto gc) {
