@@ -94,12 +94,19 @@ typedef struct {
 /* rtol: stop when ||r||_2 <= rtol ||b||_2.  check_every: iterations between
  * two reads of the device convergence flag.  flexible: for amg_solve_pcg,
  * 1 = flexible CG (Polak-Ribiere beta), 0 = standard PCG, -1 = flexible
- * exactly when the hierarchy is MIXED. */
+ * exactly when the hierarchy is MIXED.  graph: 1 = the check_every
+ * iterations between two flag reads are captured once as a HIP graph (kept
+ * with the hierarchy, freed by amg_free) and replayed with one launch;
+ * 0 = kernels are launched one by one; -1 = graph unless kernel timing
+ * (gw_prof_enable) is on, since launches inside a graph cannot be timed one
+ * by one.  Both modes run the same kernels in the same order: results are
+ * identical. */
 typedef struct {
     double rtol;
     int32_t maxiter;
     int32_t check_every;
     int32_t flexible;
+    int32_t graph;
 } amg_solve_params;
 
 typedef struct {

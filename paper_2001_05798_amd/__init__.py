@@ -63,7 +63,7 @@ class AmgParamsC(C.Structure):
 
 class SolveParamsC(C.Structure):
     _fields_ = [("rtol", C.c_double), ("maxiter", C.c_int32), ("check_every", C.c_int32),
-                ("flexible", C.c_int32)]
+                ("flexible", C.c_int32), ("graph", C.c_int32)]
 
 
 class SolveInfoC(C.Structure):
@@ -231,9 +231,10 @@ class SolveParams:
     maxiter: int = 1000
     check_every: int = 4
     flexible: int = -1
+    graph: int = -1
 
     def c(self) -> SolveParamsC:
-        return SolveParamsC(self.rtol, self.maxiter, self.check_every, self.flexible)
+        return SolveParamsC(self.rtol, self.maxiter, self.check_every, self.flexible, self.graph)
 
 
 @dataclasses.dataclass

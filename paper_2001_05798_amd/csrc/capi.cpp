@@ -10,6 +10,20 @@
 
 using namespace gw;
 
+void amg_hierarchy::drop_graphs() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+}
+
+amg_hierarchy::~amg_hierarchy() {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != device) (void)hipSetDevice(device);
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+    if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+}
+
 size_t amg_hierarchy::bytes() const {
     size_t b = lu.bytes() + inv.bytes() + piv.bytes() + kvec.bytes() + partials.bytes() + ks.bytes();
     for (int l = 0; l < nlev || (l == 0 && !L.empty()); ++l) b += L[l].bytes();
@@ -209,6 +223,7 @@ static void check_solve(amg_hierarchy *H, const double *b, double *x, const amg_
     GW_REQUIRE(H && b && x && sp, "solve: null pointer");
     GW_REQUIRE(sp->rtol >= 0 && std::isfinite(sp->rtol), "solve: rtol must be >= 0");
     GW_REQUIRE(sp->maxiter >= 0, "solve: maxiter must be >= 0");
+    GW_REQUIRE(sp->graph >= -1 && sp->graph <= 1, "solve: graph must be -1, 0 or 1");
 }
 
 int amg_solve_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp, amg_solve_info *info,

@@ -236,8 +236,21 @@ struct amg_hierarchy {
     int kvec_count = 0;
     gw::DBuf<double> partials;
     gw::DBuf<gw::KScalars> ks;
+    // Captured blocks of Krylov iterations (they hold the workspace
+    // addresses: dropped whenever the workspace moves)
+    struct Graph {
+        int kind, check, parity;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap = nullptr;  // capture-only stream
     bool mixed() const { return prm.precision == GW_PRECISION_MIXED; }
     size_t bytes() const;
+    void drop_graphs();
+    amg_hierarchy() = default;
+    amg_hierarchy(const amg_hierarchy &) = delete;
+    amg_hierarchy &operator=(const amg_hierarchy &) = delete;
+    ~amg_hierarchy();
 };
 
 namespace gw {

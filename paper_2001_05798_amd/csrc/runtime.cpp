@@ -203,6 +203,9 @@ bool prof_on() { return prof().on; }
 ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_) : id(id_), bytes(bytes_), s(s_) {
     ProfState &P = prof();
     if (!P.on || (P.only >= 0 && P.only != id)) return;
+    // launches being captured into a graph are not timed one by one
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     std::lock_guard<std::mutex> g(P.mu);
     e0 = take_event(P);
     e1 = take_event(P);

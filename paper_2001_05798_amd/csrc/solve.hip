@@ -671,6 +671,7 @@ __global__ void k_spmv_f64(int64_t n, OP op, const double *__restrict__ x, doubl
 void ensure_krylov_workspace(amg_hierarchy *H, int nvec) {
     const size_t n = (size_t)H->L[0].A.n;
     if (H->kvec_count < nvec) {
+        H->drop_graphs();
         H->kvec.alloc(n * nvec);
         H->kvec_count = nvec;
     }
@@ -699,6 +700,44 @@ void write_ks(amg_hierarchy *H, const KScalars &k, hipStream_t s) {
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+enum BlockKind : int { BLOCK_PCG = 1, BLOCK_BICGSTAB = 2 };
+
+// Enqueue one block of Krylov iterations on s: `emit(stream)` launches its
+// kernels.  With `graph`, the block is captured once per (kind, length,
+// parity) on the hierarchy's capture stream, which runs nothing, and the
+// instantiated graph is launched on s.  Every kernel reads its scalars and
+// the convergence flag from device memory, so a replay after convergence is
+// a run of early exits, exactly as the one-by-one launches are.
+template <class Emit>
+void run_block(amg_hierarchy *H, bool graph, int kind, int check, int parity, hipStream_t s, Emit &&emit) {
+    if (!graph) {
+        emit(s);
+        return;
+    }
+    hipGraphExec_t ex = nullptr;
+    for (const auto &g : H->graphs)
+        if (g.kind == kind && g.check == check && g.parity == parity) ex = g.exec;
+    if (!ex) {
+        if (!H->cap) GW_HIP(hipStreamCreateWithFlags(&H->cap, hipStreamNonBlocking));
+        GW_HIP(hipStreamBeginCapture(H->cap, hipStreamCaptureModeThreadLocal));
+        hipGraph_t g = nullptr;
+        try {
+            emit(H->cap);
+        } catch (...) {
+            if (hipStreamEndCapture(H->cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        GW_HIP(hipStreamEndCapture(H->cap, &g));
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        GW_HIP(e);
+        H->graphs.push_back({kind, check, parity, ex});
+    }
+    GW_HIP(hipGraphLaunch(ex, s));
+}
+
+bool use_graph(const amg_solve_params &sp) { return sp.graph > 0 || (sp.graph < 0 && !prof_on()); }
 
 // Host-side helper binding the level-0 operator and the scalar block.
 struct Kry {
@@ -787,13 +826,15 @@ void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s) {
     GW_HIP(hipGetLastError());
 }
 
-int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp, amg_solve_info *info,
+int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve_params &sp, amg_solve_info *info,
                hipStream_t s) {
     const double t0 = now_ms();
-    ensure_krylov_workspace(H, 5);
+    ensure_krylov_workspace(H, 6);
     Kry K(H, s, sp.rtol);
     const int64_t n = K.n;
-    double *r = H->kvec.p, *z = r + n, *pa = z + n, *pb = pa + n, *q = pb + n;
+    // the iterate lives in the workspace (a captured block then serves any
+    // output buffer) and is copied out at the end
+    double *r = H->kvec.p, *z = r + n, *pa = z + n, *pb = pa + n, *q = pb + n, *x = q + n;
     KScalars k0{};
     k0.maxiter = std::max(0, sp.maxiter);
     k0.flexible = sp.flexible < 0 ? (H->mixed() ? 1 : 0) : (sp.flexible ? 1 : 0);
@@ -804,12 +845,47 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
     KScalars k = read_ks(H, s);
     int restarts = 0;
     if (k.bnorm == 0.0) {
+        fill_f64(x_out, 0.0, n, s);
         if (info) *info = {0, GW_OK, 0, 0.0, 0.0, 0.0, now_ms() - t0};
         return GW_OK;
     }
     const int check = std::max(1, sp.check_every);
+    const bool graph = use_graph(sp);
     int32_t *done = &H->ks.p->done;
     int parity = 0;
+    // check_every iterations: q = A p, alpha, x and r updates with the
+    // convergence test, z = M r, beta
+    auto block = [&](int parity0) {
+        return [&, parity0](hipStream_t cs) {
+            Kry Kc(H, cs, sp.rtol);
+            int par = parity0;
+            for (int c = 0; c < check; ++c) {
+                double *po = par ? pb : pa, *pn = par ? pa : pb;
+                {
+                    ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs);
+                    Kc.op([&](auto o) {
+                        hipLaunchKernelGGL((k_cg_spmv<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, z, po,
+                                           pn, q, Kc.part, Kc.ks);
+                    });
+                }
+                Kc.fin(FIN_CG_ALPHA, Kc.gG);
+                {
+                    ProfScope ps(K_KRYLOV_UPDATE, 6 * Kc.vec, cs);
+                    hipLaunchKernelGGL(k_cg_update, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, x, r, pn, q, Kc.part,
+                                       Kc.ks);
+                }
+                Kc.fin(FIN_CG_CONV, Kc.g1);
+                vcycle(H, r, z, done, cs);
+                {
+                    ProfScope ps(K_KRYLOV_DOT, 3 * Kc.vec, cs);
+                    hipLaunchKernelGGL(k_cg_dot, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, z, q, Kc.part, Kc.ks);
+                }
+                Kc.fin(FIN_CG_BETA, Kc.g1);
+                par ^= 1;
+            }
+            GW_HIP(hipGetLastError());
+        };
+    };
     for (;;) {
         if (!k.done) {
             vcycle(H, r, z, done, s);
@@ -819,30 +895,8 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
             }
             K.fin(FIN_CG_BETA_FIRST, K.g1);
             for (;;) {
-                for (int c = 0; c < check; ++c) {
-                    double *po = parity ? pb : pa, *pn = parity ? pa : pb;
-                    {
-                        ProfScope ps(K_KRYLOV_SPMV, K.abytes + 4 * K.vec, s);
-                        K.op([&](auto o) {
-                            hipLaunchKernelGGL((k_cg_spmv<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, z, po,
-                                               pn, q, K.part, K.ks);
-                        });
-                    }
-                    K.fin(FIN_CG_ALPHA, K.gG);
-                    {
-                        ProfScope ps(K_KRYLOV_UPDATE, 6 * K.vec, s);
-                        hipLaunchKernelGGL(k_cg_update, dim3(K.g1), dim3(kKBlock), 0, s, n, x, r, pn, q, K.part, K.ks);
-                    }
-                    K.fin(FIN_CG_CONV, K.g1);
-                    vcycle(H, r, z, done, s);
-                    {
-                        ProfScope ps(K_KRYLOV_DOT, 3 * K.vec, s);
-                        hipLaunchKernelGGL(k_cg_dot, dim3(K.g1), dim3(kKBlock), 0, s, n, r, z, q, K.part, K.ks);
-                    }
-                    K.fin(FIN_CG_BETA, K.g1);
-                    parity ^= 1;
-                }
-                GW_HIP(hipGetLastError());
+                run_block(H, graph, BLOCK_PCG, check, parity, s, block(parity));
+                parity ^= check & 1;
                 k = read_ks(H, s);
                 if (k.done) break;
             }
@@ -857,6 +911,7 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
         K.init(b, x, r, nullptr, pa, nullptr, false);
         k = read_ks(H, s);
     }
+    copy_bytes(x_out, x, sizeof(double) * (size_t)n, s);
     if (info) {
         info->iters = k.iters;
         info->status = k.status;
@@ -869,14 +924,14 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
     return k.status;
 }
 
-int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
+int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_solve_params &sp,
                     amg_solve_info *info, hipStream_t s) {
     const double t0 = now_ms();
-    ensure_krylov_workspace(H, 8);
+    ensure_krylov_workspace(H, 9);
     Kry K(H, s, sp.rtol);
     const int64_t n = K.n;
     double *r = H->kvec.p, *rh = r + n, *p = rh + n, *v = p + n, *sv = v + n, *t = sv + n, *ph = t + n,
-           *sh = ph + n;
+           *sh = ph + n, *x = sh + n;
     KScalars k0{};
     k0.maxiter = std::max(0, sp.maxiter);
     k0.status = GW_NOT_CONVERGED;
@@ -886,49 +941,56 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
     KScalars k = read_ks(H, s);
     int restarts = 0;
     if (k.bnorm == 0.0) {
+        fill_f64(x_out, 0.0, n, s);
         if (info) *info = {0, GW_OK, 0, 0.0, 0.0, 0.0, now_ms() - t0};
         return GW_OK;
     }
     const int check = std::max(1, sp.check_every);
+    const bool graph = use_graph(sp);
     int32_t *done = &H->ks.p->done;
+    // check_every iterations of right-preconditioned BiCGSTAB
+    auto block = [&](hipStream_t cs) {
+        Kry Kc(H, cs, sp.rtol);
+        for (int c = 0; c < check; ++c) {
+            {
+                ProfScope ps(K_KRYLOV_UPDATE, 4 * Kc.vec, cs);
+                hipLaunchKernelGGL(k_bcg_p, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, p, v, Kc.ks);
+            }
+            vcycle(H, p, ph, done, cs);
+            {
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs);
+                Kc.op([&](auto o) {
+                    hipLaunchKernelGGL((k_bcg_v<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
+                                       Kc.part, Kc.ks);
+                });
+            }
+            Kc.fin(FIN_BCG_ALPHA, Kc.gG);
+            {
+                ProfScope ps(K_KRYLOV_UPDATE, 3 * Kc.vec, cs);
+                hipLaunchKernelGGL(k_bcg_s, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, v, sv, Kc.part, Kc.ks);
+            }
+            Kc.fin(FIN_BCG_S, Kc.g1);
+            vcycle(H, sv, sh, done, cs);
+            {
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs);
+                Kc.op([&](auto o) {
+                    hipLaunchKernelGGL((k_bcg_t<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
+                                       Kc.part, Kc.ks);
+                });
+            }
+            Kc.fin(FIN_BCG_OMEGA, Kc.gG);
+            {
+                ProfScope ps(K_KRYLOV_UPDATE, 8 * Kc.vec, cs);
+                hipLaunchKernelGGL(k_bcg_xr, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, x, r, ph, sh, sv, t, rh, Kc.part,
+                                   Kc.ks);
+            }
+            Kc.fin(FIN_BCG_XR, Kc.g1);
+        }
+        GW_HIP(hipGetLastError());
+    };
     for (;;) {
         while (!k.done) {
-            for (int c = 0; c < check; ++c) {
-                {
-                    ProfScope ps(K_KRYLOV_UPDATE, 4 * K.vec, s);
-                    hipLaunchKernelGGL(k_bcg_p, dim3(K.g1), dim3(kKBlock), 0, s, n, r, p, v, K.ks);
-                }
-                vcycle(H, p, ph, done, s);
-                {
-                    ProfScope ps(K_KRYLOV_SPMV, K.abytes + 3 * K.vec, s);
-                    K.op([&](auto o) {
-                        hipLaunchKernelGGL((k_bcg_v<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, ph, v, rh,
-                                           K.part, K.ks);
-                    });
-                }
-                K.fin(FIN_BCG_ALPHA, K.gG);
-                {
-                    ProfScope ps(K_KRYLOV_UPDATE, 3 * K.vec, s);
-                    hipLaunchKernelGGL(k_bcg_s, dim3(K.g1), dim3(kKBlock), 0, s, n, r, v, sv, K.part, K.ks);
-                }
-                K.fin(FIN_BCG_S, K.g1);
-                vcycle(H, sv, sh, done, s);
-                {
-                    ProfScope ps(K_KRYLOV_SPMV, K.abytes + 3 * K.vec, s);
-                    K.op([&](auto o) {
-                        hipLaunchKernelGGL((k_bcg_t<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, sh, t, sv,
-                                           K.part, K.ks);
-                    });
-                }
-                K.fin(FIN_BCG_OMEGA, K.gG);
-                {
-                    ProfScope ps(K_KRYLOV_UPDATE, 8 * K.vec, s);
-                    hipLaunchKernelGGL(k_bcg_xr, dim3(K.g1), dim3(kKBlock), 0, s, n, x, r, ph, sh, sv, t, rh, K.part,
-                                       K.ks);
-                }
-                K.fin(FIN_BCG_XR, K.g1);
-            }
-            GW_HIP(hipGetLastError());
+            run_block(H, graph, BLOCK_BICGSTAB, check, 0, s, block);
             k = read_ks(H, s);
         }
         K.true_res(b, x);
@@ -940,6 +1002,7 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
         K.init(b, x, r, rh, p, v, false);
         k = read_ks(H, s);
     }
+    copy_bytes(x_out, x, sizeof(double) * (size_t)n, s);
     if (info) {
         info->iters = k.iters;
         info->status = k.status;

@@ -395,3 +395,39 @@ def test_general_sparse_operator(gw, ref, name, make):
         assert info.status == gw.OK and info.rel_res_true <= 1e-8
         err = np.linalg.norm(host(h) - h_ref) / np.linalg.norm(h_ref)
         assert err <= (1e-8 if precision == 0 else 1e-6), (precision, err)
+
+
+@pytest.mark.parametrize("precision,check", [(0, 4), (1, 3)], ids=["fp64-check4", "mixed-check3"])
+def test_graph_replay_matches_eager(gw, ref, precision, check):
+    # the captured iteration blocks must give exactly the one-by-one result,
+    # on every solve that replays them, with eager work and host syncs between
+    _say(f"graph vs eager precision={precision} check={check}")
+    p = gi.heterogeneous_aquifer(36, 28, 12, 4.0, 6, 13)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    ap = ref.AmgParams(n_coarse=50)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap, precision))
+    n = p.grid.n
+    x0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    i0 = gw.amg_solve_pcg(Hg, bd, x0, gw.SolveParams(rtol=1e-8, check_every=check, graph=0))
+    want = host(x0)
+    assert i0.status == gw.OK
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        gw.amg_spmv(Hg, bd, y)  # eager work between the solves
+        torch.cuda.synchronize()
+        x = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+        info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-8, check_every=check, graph=1))
+        assert (info.iters, info.status) == (i0.iters, i0.status), rep
+        assert np.array_equal(host(x).view(np.uint64), want.view(np.uint64)), rep
+    # BiCGSTAB on the same hierarchy (its own captured block)
+    z0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    j0 = gw.amg_solve_bicgstab(Hg, bd, z0, gw.SolveParams(rtol=1e-8, check_every=check, graph=0))
+    for rep in range(2):
+        z = torch.zeros(n, dtype=torch.float64, device="cuda")
+        j = gw.amg_solve_bicgstab(Hg, bd, z, gw.SolveParams(rtol=1e-8, check_every=check, graph=1))
+        assert (j.iters, j.status) == (j0.iters, j0.status), rep
+        assert np.array_equal(host(z).view(np.uint64), host(z0).view(np.uint64)), rep
+    # and the PCG blocks again after the workspace grew for BiCGSTAB
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-8, check_every=check, graph=1))
+    assert np.array_equal(host(x).view(np.uint64), want.view(np.uint64))
