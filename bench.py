@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run a plain 256 MiB device copy (torch copy kernel): its FETCH_SIZE / "
+                         "WRITE_SIZE counters calibrate the HBM traffic counters of the path's kernels")
     ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests in the served-stream measurement (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -96,6 +99,32 @@ class Pipeline:
         self.ev[2].record()
         del H
         return fi, ti, st
+
+
+TRAFFIC_SOURCES = ("paper_2001_05798_amd/csrc/solve.hip", "paper_2001_05798_amd/csrc/sell.hip",
+                   "paper_2001_05798_amd/csrc/gw_device.h", "paper_2001_05798_amd/csrc/gw_internal.h")
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
+    no summary covers it or the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if kv.get("workload") == workload and kv.get("kernel") == kernel:
+                    return int(kv["bytes_per_launch"]) if kv.get("sources_sha256") == digest else None
+    return None
 
 
 def cpu_baseline(prob, precision):
@@ -230,6 +259,13 @@ def main():
     print(f"[bench] workload {args.workload}: {nx}x{ny}x{nz} s2={s2} lam={lam} seed={seed} "
           f"precision={'mixed' if precision else 'fp64'}", file=sys.stderr, flush=True)
     pipe = Pipeline(gw, torch, prob, precision)
+    if args.copy_probe:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # warm-up steps also time every kernel class once, to find the dominant one
     if not args.no_prof:
         gw.prof_select(None)
@@ -289,7 +325,8 @@ def main():
             avg_ms = s["ms"] / s["launches"]
             achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(args.workload, dominant),
                     "bytes_per_launch": per_launch_bytes, "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches": s["launches"],
                     "timing": (f"HIP events around each launch, {args.steps} further steps launched one by one "

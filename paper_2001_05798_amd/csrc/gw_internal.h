@@ -112,8 +112,10 @@ struct Pinned {
 enum KernelId : int {
     K_FV_ASSEMBLE, K_DARCY, K_TT_ASSEMBLE,
     K_SETUP_MISC, K_TRANSPOSE, K_STRENGTH, K_MIS2, K_AGGREGATE, K_SPGEMM, K_COARSE_LU, K_SELL_BUILD,
-    K_SMOOTH_FIRST, K_SMOOTH, K_RESIDUAL, K_RESTRICT, K_PROLONG, K_COARSE_SOLVE,
+    // V-cycle kernels in three classes: level 0, level 1, levels >= 2
     K_SMOOTH_FIRST0, K_SMOOTH0, K_RESIDUAL0, K_RESTRICT0, K_PROLONG0,
+    K_SMOOTH_FIRST1, K_SMOOTH1, K_RESIDUAL1, K_RESTRICT1, K_PROLONG1,
+    K_SMOOTH_FIRSTC, K_SMOOTHC, K_RESIDUALC, K_RESTRICTC, K_PROLONGC, K_COARSE_SOLVE,
     K_KRYLOV_SPMV, K_KRYLOV_UPDATE, K_KRYLOV_DOT, K_TRUE_RESIDUAL,
     K_COUNT
 };

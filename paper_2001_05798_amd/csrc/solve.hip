@@ -227,6 +227,10 @@ double op_bytes(const Csr &A, const Sell &S, int vbytes) {
 
 unsigned grid_rows(int64_t n, int G) { return blocks_for(n * G); }
 
+// Timing class of a V-cycle kernel on level l (ids of level 0, 1 and >= 2
+// are five apart).
+int level_kid(int id0, int l) { return id0 + 5 * (l < 2 ? l : 2); }
+
 template <class V>
 struct LevelOps;
 template <>
@@ -290,7 +294,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     if (npre == 0) {
         hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, done);
     } else {
-        ProfScope ps(l == 0 ? K_SMOOTH_FIRST0 : K_SMOOTH_FIRST,
+        ProfScope ps(level_kid(K_SMOOTH_FIRST0, l),
                      npre >= 2 ? abytes + n * (double)(sizeof(Bt) + 2 * vb) : n * (double)(sizeof(Bt) + 2 * vb), s);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
@@ -300,7 +304,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     }
     auto sweep = [&](auto *xin, auto *yout) {
         using YT = std::remove_pointer_t<decltype(yout)>;
-        ProfScope ps(l == 0 ? K_SMOOTH0 : K_SMOOTH, abytes + n * (double)(sizeof(Bt) + 2 * vb + sizeof(YT)), s);
+        ProfScope ps(level_kid(K_SMOOTH0, l), abytes + n * (double)(sizeof(Bt) + 2 * vb + sizeof(YT)), s);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             hipLaunchKernelGGL((k_smooth<OP, V, Bt, V, YT>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, M,
@@ -313,7 +317,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     }
     // residual and restriction
     {
-        ProfScope ps(l == 0 ? K_RESIDUAL0 : K_RESIDUAL, abytes + n * (double)(sizeof(Bt) + 2 * vb), s);
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + n * (double)(sizeof(Bt) + 2 * vb), s);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             hipLaunchKernelGGL((k_residual<OP, V, Bt, V, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, b,
@@ -324,7 +328,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     V *bc = reinterpret_cast<V *>(Nx.vb.p);
     const int64_t nc = Lv.nc;
     {
-        ProfScope ps(l == 0 ? K_RESTRICT0 : K_RESTRICT, csr_bytes(nc, Lv.R.nnz, vb) + (double)(n + nc) * vb, s);
+        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + (double)(n + nc) * vb, s);
         with_csr<V>(Lv.R, LevelOps<V>::rval(Lv), [&](auto op) {
             using OP = decltype(op);
             hipLaunchKernelGGL((k_spmv<OP, V, V, V>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t, bc,
@@ -333,7 +337,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     }
     V *xc = static_cast<V *>(vcycle_level<V, V, V>(H, l + 1, bc, (V *)nullptr, done, s));
     {
-        ProfScope ps(l == 0 ? K_PROLONG0 : K_PROLONG, csr_bytes(n, Lv.P.nnz, vb) + (double)(2 * n + nc) * vb, s);
+        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, vb) + (double)(2 * n + nc) * vb, s);
         with_csr<V>(Lv.P, LevelOps<V>::pval(Lv), [&](auto op) {
             using OP = decltype(op);
             hipLaunchKernelGGL((k_prolong<OP, V, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, xc, x,
