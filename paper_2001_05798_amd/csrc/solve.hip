@@ -741,7 +741,7 @@ void run_block(amg_hierarchy *H, bool graph, int kind, int check, int parity, hi
     GW_HIP(hipGraphLaunch(ex, s));
 }
 
-bool use_graph(const amg_solve_params &sp) { return sp.graph > 0 || (sp.graph < 0 && !prof_on()); }
+bool use_graph(const amg_solve_params &sp) { return sp.graph > 0; }
 
 // Host-side helper binding the level-0 operator and the scalar block.
 struct Kry {
