@@ -187,6 +187,19 @@ int amg_solve_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_
 int amg_solve_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
                        amg_solve_info *info, void *stream);
 
+/* Two systems with the same matrix, A x0 = b0 and A x1 = b1 (the travel time
+ * and the source-zone fraction share the upwind matrix: Benchmarking
+ * Examples, Eq. 1, and the Results' travel-time runs), solved by BiCGSTAB in
+ * lockstep: each product reads the matrix and the hierarchy once for both,
+ * each system keeps its own scalars, stopping test and restarts, and gets
+ * exactly the iterates amg_solve_bicgstab gives it alone.  b0, b1, x0, x1
+ * [device] n each; x0 and x1 must not overlap.  info [host] 2 entries
+ * (solve_ms is the wall time of the pair in both).
+ * Returns GW_BREAKDOWN if either system broke down, else GW_NOT_CONVERGED if
+ * either did not converge, else GW_OK. */
+int amg_solve_bicgstab_pair(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
+                            const amg_solve_params *sp, amg_solve_info info[2], void *stream);
+
 /* Per-level statistics; `out` [host] holds max_levels entries. */
 int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_levels,
                        int32_t *nlevels, size_t *bytes);

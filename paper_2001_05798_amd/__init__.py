@@ -120,6 +120,8 @@ def _load():
         "amg_spmv": (C.c_int, [vp, vp, vp, vp]),
         "amg_solve_pcg": (C.c_int, [vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
         "amg_solve_bicgstab": (C.c_int, [vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "amg_solve_bicgstab_pair": (C.c_int, [vp, vp, vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC),
+                                              vp]),
         "amg_hierarchy_info": (C.c_int, [vp, C.POINTER(LevelInfoC), i32, C.POINTER(i32), C.POINTER(C.c_size_t)]),
         "amg_level_export": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "amg_coarse_export": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -374,6 +376,14 @@ def amg_solve_bicgstab(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stre
     _check(_lib.amg_solve_bicgstab(H.handle, _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info),
                                    _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
     return SolveInfo.of(info)
+
+
+def amg_solve_bicgstab_pair(H: Hierarchy, b0, b1, x0, x1, sp: SolveParams = SolveParams(),
+                            stream=None) -> Tuple[int, List[SolveInfo]]:
+    info = (SolveInfoC * 2)()
+    st = _check(_lib.amg_solve_bicgstab_pair(H.handle, _ptr(b0), _ptr(b1), _ptr(x0), _ptr(x1), C.byref(sp.c()),
+                                             info, _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return st, [SolveInfo.of(info[0]), SolveInfo.of(info[1])]
 
 
 def amg_level_export(H: Hierarchy, level: int, a_rowptr=None, a_col=None, a_val=None, agg=None, M=None,

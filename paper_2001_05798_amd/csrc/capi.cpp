@@ -248,6 +248,19 @@ int amg_solve_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_s
     });
 }
 
+int amg_solve_bicgstab_pair(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
+                            const amg_solve_params *sp, amg_solve_info info[2], void *stream) {
+    return guarded([&] {
+        check_solve(H, b0, x0, sp);
+        GW_REQUIRE(b1 && x1, "solve: null pointer");
+        GW_REQUIRE(x0 != x1, "amg_solve_bicgstab_pair: x0 and x1 must be different buffers");
+        hipStream_t s = as_stream(stream);
+        int st = krylov_bicgstab2(H, b0, b1, x0, x1, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
 int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_levels, int32_t *nlevels,
                        size_t *bytes) {
     return guarded([&] {
@@ -356,18 +369,16 @@ int tt_solve(const gw_grid *grid, const double *qx, const double *qy, const doub
         std::unique_ptr<amg_hierarchy> H(setup_hierarchy(&view_, params, s));
         A = Csr();
         const double setup_ms = now_ms() - t0;
-        amg_solve_info i1{}, i2{};
-        int s1 = krylov_bicgstab(H.get(), bt.p, tau, *sp, &i1, s);
-        int s2 = krylov_bicgstab(H.get(), bc.p, c, *sp, &i2, s);
+        GW_REQUIRE(tau != c, "tt_solve: tau and c must be different buffers");
+        amg_solve_info ii[2] = {};
+        const int st = krylov_bicgstab2(H.get(), bt.p, bc.p, tau, c, *sp, ii, s);
         finish(s);
-        i1.setup_ms = i2.setup_ms = setup_ms;
+        ii[0].setup_ms = ii[1].setup_ms = setup_ms;
         if (info) {
-            info[0] = i1;
-            info[1] = i2;
+            info[0] = ii[0];
+            info[1] = ii[1];
         }
-        if (s1 == GW_BREAKDOWN || s2 == GW_BREAKDOWN) return GW_BREAKDOWN;
-        if (s1 != GW_OK || s2 != GW_OK) return GW_NOT_CONVERGED;
-        return GW_OK;
+        return st;
     });
 }
 

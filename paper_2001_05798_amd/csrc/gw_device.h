@@ -88,14 +88,16 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
     }
 }
 
-// Second stage, one block: tot[k] = sum over nb blocks, same order always.
+// Second stage, one block: tot[k] = sum over nb blocks of the k-th value at
+// `off` in each block's record of `stride` values, same order always.
 template <int NV>
-__device__ __forceinline__ void sum_partials(const double *partials, unsigned nb, double (&tot)[NV]) {
+__device__ __forceinline__ void sum_partials(const double *partials, unsigned nb, double (&tot)[NV],
+                                             int stride = NV, int off = 0) {
     __shared__ double sm[NV][16];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = 0.0;
-        for (unsigned b = threadIdx.x; b < nb; b += blockDim.x) s += partials[(size_t)b * NV + k];
+        for (unsigned b = threadIdx.x; b < nb; b += blockDim.x) s += partials[(size_t)b * stride + off + k];
         tot[k] = block_sum(s, sm[k]);
     }
 }

@@ -307,5 +307,9 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
                amg_solve_info *info, hipStream_t s);
 int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                     amg_solve_info *info, hipStream_t s);
+// Two systems with the hierarchy's matrix, solved in lockstep (each exactly
+// as krylov_bicgstab solves it alone).  Returns the worse of the statuses.
+int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
+                     const amg_solve_params &sp, amg_solve_info info[2], hipStream_t s);
 
 }  // namespace gw

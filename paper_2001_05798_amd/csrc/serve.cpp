@@ -34,7 +34,9 @@ constexpr size_t kMaxWaiting = 4096;
 // stay well below it (see amg_hierarchy_info).
 size_t footprint_bytes(const gw_request &r) {
     const double n = (double)r.grid.nx * r.grid.ny * r.grid.nz;
-    const double per_cell = (r.flow_params.precision == GW_PRECISION_MIXED ? 1700.0 : 1500.0);
+    // (the travel-time pair solve keeps 20 FP64 vectors and two-column level
+    // vectors: about 200 B per cell of its own)
+    const double per_cell = (r.flow_params.precision == GW_PRECISION_MIXED ? 1900.0 : 1700.0);
     return (size_t)(n * per_cell) + ((size_t)64 << 20);
 }
 

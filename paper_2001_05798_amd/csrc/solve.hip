@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "gw_device.h"
 #include "gw_internal.h"
@@ -26,6 +27,51 @@ namespace gw {
 namespace {
 
 // ----------------------------------------------------------- operators ---
+// NR right-hand sides travel together: vectors hold the NR values of a row
+// next to each other (x[i*NR + r]), so one pass over a matrix serves all of
+// them and the gather of x_j is one NR-wide load.  Each right-hand side sees
+// exactly the arithmetic, in the same order, of a single-vector pass.
+template <class V, int NR>
+struct VecN {
+    V v[NR];
+};
+
+template <class T, int NR>
+__device__ __forceinline__ VecN<T, NR> load_n(const T *__restrict__ p, int64_t j) {
+    VecN<T, NR> r;
+    if constexpr (NR == 2) {
+        using T2 = std::conditional_t<std::is_same<T, double>::value, double2, float2>;
+        const T2 t = *reinterpret_cast<const T2 *>(p + 2 * j);
+        r.v[0] = t.x;
+        r.v[1] = t.y;
+    } else {
+        static_assert(NR == 1, "one or two right-hand sides");
+        r.v[0] = p[j];
+    }
+    return r;
+}
+
+template <class T, int NR>
+__device__ __forceinline__ void store_n(T *__restrict__ p, int64_t j, const VecN<T, NR> &x) {
+    if constexpr (NR == 2) {
+        using T2 = std::conditional_t<std::is_same<T, double>::value, double2, float2>;
+        T2 t;
+        t.x = x.v[0];
+        t.y = x.v[1];
+        *reinterpret_cast<T2 *>(p + 2 * j) = t;
+    } else {
+        p[j] = x.v[0];
+    }
+}
+
+template <class To, class From, int NR>
+__device__ __forceinline__ VecN<To, NR> cvt(const VecN<From, NR> &x) {
+    VecN<To, NR> r;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) r.v[k] = (To)x.v[k];
+    return r;
+}
+
 // Lanes of a group own one row: strided partial sums, then a butterfly over
 // the group (groups are aligned power-of-two lane ranges of one wave).  Each
 // lane loads U of its entries before summing their products, so the gathers
@@ -33,11 +79,14 @@ namespace {
 // picked from the mean row length); slots past the row end take value 0 at
 // the row's first column (a finite x makes them exact zeros; a non-finite x
 // there makes the row non-finite in any case).
-template <int G, class V, class F>
-__device__ __forceinline__ V group_row_sum(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                           const V *__restrict__ val, int64_t i, int lane, F &&xj) {
+template <int G, int NR, class V, class F>
+__device__ __forceinline__ VecN<V, NR> group_row_sum(const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const V *__restrict__ val,
+                                                     int64_t i, int lane, F &&xj) {
     constexpr int U = G == 1 ? 4 : (G == 64 ? 1 : 2);
-    V s = 0;
+    VecN<V, NR> s;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) s.v[k] = 0;
     const int32_t b = rowptr[i], e = rowptr[i + 1];
     if (b < e) {
         const int32_t cb = col[b];
@@ -55,11 +104,17 @@ __device__ __forceinline__ V group_row_sum(const int32_t *__restrict__ rowptr, c
                 c[u] = in ? cv : cb;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) s += a[u] * xj(c[u]);
+            for (int u = 0; u < U; ++u) {
+                const VecN<V, NR> xv = xj(c[u]);
+#pragma unroll
+                for (int k = 0; k < NR; ++k) s.v[k] += a[u] * xv.v[k];
+            }
         }
     }
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, dev::kWave);
+    for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s.v[k] += __shfl_xor(s.v[k], o, dev::kWave);
     return s;
 }
 
@@ -69,9 +124,14 @@ struct OpCsr {
     const int32_t *rowptr, *col;
     const V *val;
     __device__ __forceinline__ void load(int32_t *) const {}
+    // xj(j) returns the NR values of column j
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int lane, const int32_t *, F &&xj) const {
+        return group_row_sum<G, NR, V>(rowptr, col, val, i, lane, xj);
+    }
     template <class F>
-    __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *, F &&xj) const {
-        return group_row_sum<G, V>(rowptr, col, val, i, lane, xj);
+    __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows<1>(i, lane, sd, [&](int32_t j) { return VecN<V, 1>{{(V)xj(j)}}; }).v[0];
     }
 };
 
@@ -88,12 +148,14 @@ struct OpSell {
     // of x overlap; the sum still runs in entry order.  Slots past the slice
     // width re-read the last entry and are replaced by the padding entry
     // (value 0 at the row's own column) in registers, without branches.
-    template <bool DICT, class F>
-    __device__ __forceinline__ V row_impl(int64_t i, const int32_t *sd, F &&xj) const {
+    template <bool DICT, int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> row_impl(int64_t i, const int32_t *sd, F &&xj) const {
         const int64_t sl = i / kSellC;
         const int l = (int)(i - sl * kSellC);
         const int32_t off = S.soff[sl], w = (S.soff[sl + 1] - off) / kSellC;
-        V acc = 0;
+        VecN<V, NR> acc;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc.v[k] = 0;
         for (int32_t k0 = 0; k0 < w; k0 += 8) {
             V a[8];
             int32_t c[8];
@@ -108,13 +170,21 @@ struct OpSell {
                 c[u] = in ? cv : (int32_t)i;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += a[u] * xj(c[u]);
+            for (int u = 0; u < 8; ++u) {
+                const VecN<V, NR> xv = xj(c[u]);
+#pragma unroll
+                for (int k = 0; k < NR; ++k) acc.v[k] += a[u] * xv.v[k];
+            }
         }
         return acc;
     }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int, const int32_t *sd, F &&xj) const {
+        return S.ndict ? row_impl<true, NR>(i, sd, xj) : row_impl<false, NR>(i, sd, xj);
+    }
     template <class F>
-    __device__ __forceinline__ V row(int64_t i, int, const int32_t *sd, F &&xj) const {
-        return S.ndict ? row_impl<true>(i, sd, xj) : row_impl<false>(i, sd, xj);
+    __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows<1>(i, lane, sd, [&](int32_t j) { return VecN<V, 1>{{(V)xj(j)}}; }).v[0];
     }
 };
 
@@ -133,73 +203,115 @@ struct OpSell {
 // ------------------------------------------------------------ V-cycle ----
 // Sweep x <- x + M (b - A x); the first two sweeps from x = 0 are fused:
 // x1 = M b, x2 = x1 + M (b - A x1) with x1_j recomputed on the fly.
-template <class OP, class V, class Bt, class Yt>
+template <class OP, class V, class Bt, class Yt, int NR>
 __global__ void k_smooth_first(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b,
                                Yt *__restrict__ y, int two, const int32_t *done) {
     if (done && *done) return;
     OP_PROLOGUE(op)
     GROUP_ROW(OP::G)
-    const V bi = (V)b[i], mi = M[i];
-    V x1 = mi * bi;
+    const VecN<V, NR> bi = cvt<V>(load_n<Bt, NR>(b, i));
+    const V mi = M[i];
+    VecN<V, NR> x1;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) x1.v[k] = mi * bi.v[k];
     if (two) {
-        V ax = op.row(i, lane, sd_, [&](int32_t j) { return M[j] * (V)b[j]; });
-        x1 = x1 + mi * (bi - ax);
+        const VecN<V, NR> ax = op.template rows<NR>(i, lane, sd_, [&](int32_t j) {
+            const VecN<V, NR> bj = cvt<V>(load_n<Bt, NR>(b, j));
+            const V mj = M[j];
+            VecN<V, NR> o;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) o.v[k] = mj * bj.v[k];
+            return o;
+        });
+#pragma unroll
+        for (int k = 0; k < NR; ++k) x1.v[k] = x1.v[k] + mi * (bi.v[k] - ax.v[k]);
     }
-    if (lane == 0) y[i] = (Yt)x1;
+    if (lane == 0) store_n<Yt, NR>(y, i, cvt<Yt>(x1));
 }
 
-template <class OP, class V, class Bt, class Xt, class Yt>
+template <class OP, class V, class Bt, class Xt, class Yt, int NR>
 __global__ void k_smooth(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b,
                          const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
     OP_PROLOGUE(op)
     GROUP_ROW(OP::G)
-    V ax = op.row(i, lane, sd_, [&](int32_t j) { return (V)x[j]; });
-    if (lane == 0) y[i] = (Yt)((V)x[i] + M[i] * ((V)b[i] - ax));
+    const VecN<V, NR> ax =
+        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
+    if (lane == 0) {
+        const VecN<V, NR> xi = cvt<V>(load_n<Xt, NR>(x, i)), bi = cvt<V>(load_n<Bt, NR>(b, i));
+        const V mi = M[i];
+        VecN<V, NR> o;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) o.v[k] = xi.v[k] + mi * (bi.v[k] - ax.v[k]);
+        store_n<Yt, NR>(y, i, cvt<Yt>(o));
+    }
 }
 
-template <class OP, class V, class Bt, class Xt, class Rt>
+template <class OP, class V, class Bt, class Xt, class Rt, int NR>
 __global__ void k_residual(int64_t n, OP op, const Bt *__restrict__ b, const Xt *__restrict__ x,
                            Rt *__restrict__ r, const int32_t *done) {
     if (done && *done) return;
     OP_PROLOGUE(op)
     GROUP_ROW(OP::G)
-    V ax = op.row(i, lane, sd_, [&](int32_t j) { return (V)x[j]; });
-    if (lane == 0) r[i] = (Rt)((V)b[i] - ax);
+    const VecN<V, NR> ax =
+        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
+    if (lane == 0) {
+        const VecN<V, NR> bi = cvt<V>(load_n<Bt, NR>(b, i));
+        VecN<V, NR> o;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) o.v[k] = bi.v[k] - ax.v[k];
+        store_n<Rt, NR>(r, i, cvt<Rt>(o));
+    }
 }
 
-template <class OP, class V, class Xt, class Yt>
+template <class OP, class V, class Xt, class Yt, int NR>
 __global__ void k_spmv(int64_t n, OP op, const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
     OP_PROLOGUE(op)
     GROUP_ROW(OP::G)
-    V s = op.row(i, lane, sd_, [&](int32_t j) { return (V)x[j]; });
-    if (lane == 0) y[i] = (Yt)s;
+    const VecN<V, NR> s =
+        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
+    if (lane == 0) store_n<Yt, NR>(y, i, cvt<Yt>(s));
 }
 
 // x += P x_c
-template <class OP, class V, class Xt>
+template <class OP, class V, class Xt, int NR>
 __global__ void k_prolong(int64_t n, OP op, const Xt *__restrict__ xc, Xt *__restrict__ x, const int32_t *done) {
     if (done && *done) return;
     OP_PROLOGUE(op)
     GROUP_ROW(OP::G)
-    V s = op.row(i, lane, sd_, [&](int32_t j) { return (V)xc[j]; });
-    if (lane == 0) x[i] = (Xt)((V)x[i] + s);
+    const VecN<V, NR> s =
+        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(xc, j)); });
+    if (lane == 0) {
+        const VecN<V, NR> xi = cvt<V>(load_n<Xt, NR>(x, i));
+        VecN<V, NR> o;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) o.v[k] = xi.v[k] + s.v[k];
+        store_n<Xt, NR>(x, i, cvt<Xt>(o));
+    }
 }
 
 // Coarsest level: x = A_L^{-1} b with the row-major inverse, one wave per
 // row, accumulated in FP64.
-template <class Bt, class Yt>
+template <class Bt, class Yt, int NR>
 __global__ void k_coarse_gemv(int32_t n, const double *__restrict__ inv, const Bt *__restrict__ b,
                               Yt *__restrict__ y, const int32_t *done) {
     if (done && *done) return;
     const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / dev::kWave;
     const int lane = threadIdx.x & (dev::kWave - 1);
     if (i >= n) return;
-    double s = 0.0;
-    for (int32_t c = lane; c < n; c += dev::kWave) s += inv[i * n + c] * (double)b[c];
-    s = dev::wave_sum(s);
-    if (lane == 0) y[i] = (Yt)s;
+    VecN<double, NR> s;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) s.v[k] = 0.0;
+    for (int32_t c = lane; c < n; c += dev::kWave) {
+        const double a = inv[i * n + c];
+        const VecN<double, NR> bc = cvt<double>(load_n<Bt, NR>(b, c));
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s.v[k] += a * bc.v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) s.v[k] = dev::wave_sum(s.v[k]);
+    if (lane == 0) store_n<Yt, NR>(y, i, cvt<Yt>(s));
 }
 
 template <class X>
@@ -268,19 +380,20 @@ void with_level_op(const Level &Lv, F &&f) {
     else with_csr<V>(Lv.A, LevelOps<V>::aval(Lv), f);
 }
 
-// One V-cycle on level l.  `b` is the right-hand side (type Bt), the result
-// goes to `out` (type Zt) when given, else into one of the level's own
-// buffers, whose address is returned.  V = value type of the hierarchy (also
-// the type of all internal vectors).
-template <class V, class Bt, class Zt>
+// One V-cycle on level l for NR right-hand sides (interleaved).  `b` is the
+// right-hand side (type Bt), the result goes to `out` (type Zt) when given,
+// else into one of the level's own buffers, whose address is returned.  V =
+// value type of the hierarchy (also the type of all internal vectors).
+template <class V, class Bt, class Zt, int NR>
 void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s) {
     Level &Lv = H->L[l];
     const int64_t n = Lv.A.n;
     const int vb = (int)sizeof(V);
+    const double nr = NR;
     if (l == H->nlev - 1) {
         Zt *y = out ? out : reinterpret_cast<Zt *>(Lv.vx.p);
-        ProfScope ps(K_COARSE_SOLVE, (double)n * n * 8 + n * (double)(sizeof(Bt) + sizeof(Zt)), s);
-        hipLaunchKernelGGL((k_coarse_gemv<Bt, Zt>), dim3(blocks_for(n * dev::kWave)), dim3(kBlock), 0, s,
+        ProfScope ps(K_COARSE_SOLVE, (double)n * n * 8 + nr * n * (double)(sizeof(Bt) + sizeof(Zt)), s);
+        hipLaunchKernelGGL((k_coarse_gemv<Bt, Zt, NR>), dim3(blocks_for(n * dev::kWave)), dim3(kBlock), 0, s,
                            (int32_t)n, H->inv.p, b, y, done);
         return y;
     }
@@ -292,23 +405,24 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
 
     // pre-smoothing
     if (npre == 0) {
-        hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, done);
+        hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n * NR)), dim3(kBlock), 0, s, x, n * NR, done);
     } else {
         ProfScope ps(level_kid(K_SMOOTH_FIRST0, l),
-                     npre >= 2 ? abytes + n * (double)(sizeof(Bt) + 2 * vb) : n * (double)(sizeof(Bt) + 2 * vb), s);
+                     (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb), s);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_smooth_first<OP, V, Bt, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, M,
-                               b, x, npre >= 2 ? 1 : 0, done);
+            hipLaunchKernelGGL((k_smooth_first<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
+                               op, M, b, x, npre >= 2 ? 1 : 0, done);
         });
     }
     auto sweep = [&](auto *xin, auto *yout) {
         using YT = std::remove_pointer_t<decltype(yout)>;
-        ProfScope ps(level_kid(K_SMOOTH0, l), abytes + n * (double)(sizeof(Bt) + 2 * vb + sizeof(YT)), s);
+        ProfScope ps(level_kid(K_SMOOTH0, l),
+                     abytes + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT)), s);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_smooth<OP, V, Bt, V, YT>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, M,
-                               b, xin, yout, done);
+            hipLaunchKernelGGL((k_smooth<OP, V, Bt, V, YT, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
+                               M, b, xin, yout, done);
         });
     };
     for (int k = 2; k < npre; ++k) {
@@ -317,30 +431,30 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     }
     // residual and restriction
     {
-        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + n * (double)(sizeof(Bt) + 2 * vb), s);
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + nr * n * (double)(sizeof(Bt) + 2 * vb), s);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_residual<OP, V, Bt, V, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, b,
-                               x, t, done);
+            hipLaunchKernelGGL((k_residual<OP, V, Bt, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
+                               b, x, t, done);
         });
     }
     Level &Nx = H->L[l + 1];
     V *bc = reinterpret_cast<V *>(Nx.vb.p);
     const int64_t nc = Lv.nc;
     {
-        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + (double)(n + nc) * vb, s);
+        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb, s);
         with_csr<V>(Lv.R, LevelOps<V>::rval(Lv), [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_spmv<OP, V, V, V>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t, bc,
-                               done);
+            hipLaunchKernelGGL((k_spmv<OP, V, V, V, NR>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t,
+                               bc, done);
         });
     }
-    V *xc = static_cast<V *>(vcycle_level<V, V, V>(H, l + 1, bc, (V *)nullptr, done, s));
+    V *xc = static_cast<V *>(vcycle_level<V, V, V, NR>(H, l + 1, bc, (V *)nullptr, done, s));
     {
-        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, vb) + (double)(2 * n + nc) * vb, s);
+        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, vb) + nr * (double)(2 * n + nc) * vb, s);
         with_csr<V>(Lv.P, LevelOps<V>::pval(Lv), [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_prolong<OP, V, V>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, xc, x,
+            hipLaunchKernelGGL((k_prolong<OP, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, xc, x,
                                done);
         });
     }
@@ -354,7 +468,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
         std::swap(x, t);
     }
     if (out) {
-        hipLaunchKernelGGL((k_convert<V, Zt>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, out, n, done);
+        hipLaunchKernelGGL((k_convert<V, Zt>), dim3(blocks_for(n * NR)), dim3(kBlock), 0, s, x, out, n * NR, done);
         return out;
     }
     return x;
@@ -559,22 +673,8 @@ enum FinOp : int {
     FIN_TRUE_RES, FIN_BCG_ALPHA, FIN_BCG_S, FIN_BCG_OMEGA, FIN_BCG_XR
 };
 
-__global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const double *partials, double rtol,
-                                                      KScalars *ks) {
-    const bool always = op == FIN_INIT_FIRST || op == FIN_INIT_RESTART || op == FIN_TRUE_RES || op == FIN_BCG_XR;
-    if (!always && ks->done) return;
-    if (op == FIN_BCG_XR && ks->done && !ks->pending_x) return;
-    const int nv = (op == FIN_INIT_FIRST || op == FIN_INIT_RESTART || op == FIN_CG_BETA_FIRST ||
-                    op == FIN_CG_BETA || op == FIN_BCG_OMEGA || op == FIN_BCG_XR) ? 2 : 1;
-    double tot[2] = {0.0, 0.0};
-    if (nv == 2) {
-        dev::sum_partials<2>(partials, nb, tot);
-    } else {
-        double t1[1];
-        dev::sum_partials<1>(partials, nb, t1);
-        tot[0] = t1[0];
-    }
-    if (threadIdx.x != 0) return;
+// The scalar step that follows reduction `op`, from the reduced values.
+__device__ void fin_apply(int op, const double (&tot)[2], double rtol, KScalars *ks) {
     switch (op) {
         case FIN_INIT_FIRST:
         case FIN_INIT_RESTART:
@@ -664,6 +764,240 @@ __global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const
     }
 }
 
+__device__ __forceinline__ bool fin_skip(int op, const KScalars *ks) {
+    const bool always = op == FIN_INIT_FIRST || op == FIN_INIT_RESTART || op == FIN_TRUE_RES || op == FIN_BCG_XR;
+    if (!always && ks->done) return true;
+    return op == FIN_BCG_XR && ks->done && !ks->pending_x;
+}
+
+__host__ __device__ constexpr int fin_nv(int op) {
+    return (op == FIN_INIT_FIRST || op == FIN_INIT_RESTART || op == FIN_CG_BETA_FIRST || op == FIN_CG_BETA ||
+            op == FIN_BCG_OMEGA || op == FIN_BCG_XR) ? 2 : 1;
+}
+
+__global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const double *partials, double rtol,
+                                                      KScalars *ks) {
+    if (fin_skip(op, ks)) return;
+    double tot[2] = {0.0, 0.0};
+    if (fin_nv(op) == 2) {
+        dev::sum_partials<2>(partials, nb, tot);
+    } else {
+        double t1[1];
+        dev::sum_partials<1>(partials, nb, t1);
+        tot[0] = t1[0];
+    }
+    if (threadIdx.x == 0) fin_apply(op, tot, rtol, ks);
+}
+
+// Two right-hand sides: block records hold NV values of each (first, then
+// second); ks[0], ks[1] are their scalars, ks[2].done / ks[2].pending_x the
+// joint flags read by the product kernels.  Only the right-hand sides in
+// `mask` are touched.
+__global__ void __launch_bounds__(kKBlock) k_finalize2(int op, unsigned nb, const double *partials, double rtol,
+                                                       KScalars *ks, int mask) {
+    const int nv = fin_nv(op);
+    for (int r = 0; r < 2; ++r) {
+        if (!(mask >> r & 1) || fin_skip(op, ks + r)) continue;
+        double tot[2] = {0.0, 0.0};
+        if (nv == 2) {
+            dev::sum_partials<2>(partials, nb, tot, 4, 2 * r);
+        } else {
+            double t1[1];
+            dev::sum_partials<1>(partials, nb, t1, 2, r);
+            tot[0] = t1[0];
+        }
+        if (threadIdx.x == 0) fin_apply(op, tot, rtol, ks + r);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ks[2].done = ks[0].done && ks[1].done;
+        ks[2].pending_x = ks[0].pending_x || ks[1].pending_x;
+    }
+}
+
+// ------------------------------------------- two right-hand sides -------
+// BiCGSTAB for two systems with one matrix, in lockstep: vectors hold the
+// two values of a row next to each other, every product reads the matrix
+// once for both, and each system keeps its own scalars (ks[0], ks[1]) and
+// stops on its own flag; the kernels leave a stopped system untouched.  The
+// grids and per-thread row sets equal those of the one-system kernels, so
+// each system's partial sums, and therefore its iterates, are the ones a
+// separate solve produces.
+
+// r = b - A x, r_hat = r, p = v = 0 for the systems in `mask`; partials b.b,
+// r.r per system
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_kr_init2(int64_t n, OP op, const double *__restrict__ b,
+                                                      const double *__restrict__ x, double *__restrict__ r,
+                                                      double *__restrict__ rh, double *__restrict__ p,
+                                                      double *__restrict__ v, double *partials, int mask) {
+    OP_PROLOGUE(op)
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    GROUP_LOOP(OP::G, i, lane, n) {
+        const VecN<double, 2> ax = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(x, j); });
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (!(mask >> k & 1)) continue;
+                const double bi = b[2 * i + k], ri = bi - ax.v[k];
+                r[2 * i + k] = ri;
+                rh[2 * i + k] = ri;
+                p[2 * i + k] = 0.0;
+                v[2 * i + k] = 0.0;
+                acc[2 * k] += bi * bi;
+                acc[2 * k + 1] += ri * ri;
+            }
+        }
+    }
+    dev::block_partials<4>(acc, partials);
+}
+
+// p = r + beta (p - omega v)
+__global__ void __launch_bounds__(kKBlock) k_bcg_p2(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+                                                    const double *__restrict__ v, const KScalars *ks) {
+    if (ks[2].done) return;
+    const bool on0 = !ks[0].done, on1 = !ks[1].done;
+    const double b0 = ks[0].beta, w0 = ks[0].omega, b1 = ks[1].beta, w1 = ks[1].omega;
+    GRID_LOOP(i, n) {
+        if (on0) p[2 * i] = r[2 * i] + b0 * (p[2 * i] - w0 * v[2 * i]);
+        if (on1) p[2 * i + 1] = r[2 * i + 1] + b1 * (p[2 * i + 1] - w1 * v[2 * i + 1]);
+    }
+}
+
+// v = A p_hat; partials r_hat . v
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_bcg_v2(int64_t n, OP op, const double *__restrict__ ph,
+                                                    double *__restrict__ v, const double *__restrict__ rh,
+                                                    double *partials, const KScalars *ks) {
+    if (ks[2].done) return;
+    OP_PROLOGUE(op)
+    double acc[2] = {0.0, 0.0};
+    GROUP_LOOP(OP::G, i, lane, n) {
+        const VecN<double, 2> vi = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(ph, j); });
+        if (lane == 0) {
+            store_n<double, 2>(v, i, vi);
+            acc[0] += rh[2 * i] * vi.v[0];
+            acc[1] += rh[2 * i + 1] * vi.v[1];
+        }
+    }
+    dev::block_partials<2>(acc, partials);
+}
+
+// s = r - alpha v; partials s.s
+__global__ void __launch_bounds__(kKBlock) k_bcg_s2(int64_t n, const double *__restrict__ r,
+                                                    const double *__restrict__ v, double *__restrict__ sv,
+                                                    double *partials, const KScalars *ks) {
+    if (ks[2].done) return;
+    const bool on0 = !ks[0].done, on1 = !ks[1].done;
+    const double a0 = ks[0].alpha, a1 = ks[1].alpha;
+    double acc[2] = {0.0, 0.0};
+    GRID_LOOP(i, n) {
+        if (on0) {
+            const double si = r[2 * i] - a0 * v[2 * i];
+            sv[2 * i] = si;
+            acc[0] += si * si;
+        }
+        if (on1) {
+            const double si = r[2 * i + 1] - a1 * v[2 * i + 1];
+            sv[2 * i + 1] = si;
+            acc[1] += si * si;
+        }
+    }
+    dev::block_partials<2>(acc, partials);
+}
+
+// t = A s_hat; partials t.s, t.t
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_bcg_t2(int64_t n, OP op, const double *__restrict__ sh,
+                                                    double *__restrict__ t, const double *__restrict__ sv,
+                                                    double *partials, const KScalars *ks) {
+    if (ks[2].done) return;
+    OP_PROLOGUE(op)
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    GROUP_LOOP(OP::G, i, lane, n) {
+        const VecN<double, 2> ti = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(sh, j); });
+        if (lane == 0) {
+            store_n<double, 2>(t, i, ti);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                acc[2 * k] += ti.v[k] * sv[2 * i + k];
+                acc[2 * k + 1] += ti.v[k] * ti.v[k];
+            }
+        }
+    }
+    dev::block_partials<4>(acc, partials);
+}
+
+// x += alpha p_hat + omega s_hat; r = s - omega t; partials r.r, r_hat.r.
+// A system stopped early on ||s|| gets only x += alpha p_hat.
+__global__ void __launch_bounds__(kKBlock) k_bcg_xr2(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                     const double *__restrict__ ph, const double *__restrict__ sh,
+                                                     const double *__restrict__ sv, const double *__restrict__ t,
+                                                     const double *__restrict__ rh, double *partials,
+                                                     const KScalars *ks) {
+    if (ks[2].done && !ks[2].pending_x) return;
+    int mode[2];
+    double al[2], om[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        mode[k] = ks[k].pending_x ? 1 : (ks[k].done ? 0 : 2);
+        al[k] = ks[k].alpha;
+        om[k] = ks[k].omega;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    GRID_LOOP(i, n) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t e = 2 * i + k;
+            if (mode[k] == 1) {
+                x[e] += al[k] * ph[e];
+            } else if (mode[k] == 2) {
+                x[e] += al[k] * ph[e] + om[k] * sh[e];
+                const double ri = sv[e] - om[k] * t[e];
+                r[e] = ri;
+                acc[2 * k] += ri * ri;
+                acc[2 * k + 1] += rh[e] * ri;
+            }
+        }
+    }
+    dev::block_partials<4>(acc, partials);
+}
+
+// partials (b - A x).(b - A x) per system
+template <class OP>
+__global__ void __launch_bounds__(kKBlock) k_true_res2(int64_t n, OP op, const double *__restrict__ b,
+                                                       const double *__restrict__ x, double *partials) {
+    OP_PROLOGUE(op)
+    double acc[2] = {0.0, 0.0};
+    GROUP_LOOP(OP::G, i, lane, n) {
+        const VecN<double, 2> ax = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(x, j); });
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const double ri = b[2 * i + k] - ax.v[k];
+                acc[k] += ri * ri;
+            }
+        }
+    }
+    dev::block_partials<2>(acc, partials);
+}
+
+// Interleave two vectors / split them again.
+__global__ void k_interleave(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                             double *__restrict__ ab) {
+    GRID_LOOP(i, n) {
+        ab[2 * i] = a[i];
+        ab[2 * i + 1] = b[i];
+    }
+}
+
+__global__ void k_split(int64_t n, const double *__restrict__ ab, double *__restrict__ a, double *__restrict__ b) {
+    GRID_LOOP(i, n) {
+        a[i] = ab[2 * i];
+        b[i] = ab[2 * i + 1];
+    }
+}
+
 template <class OP>
 __global__ void k_spmv_f64(int64_t n, OP op, const double *__restrict__ x, double *__restrict__ y) {
     OP_PROLOGUE(op)
@@ -679,11 +1013,27 @@ void ensure_krylov_workspace(amg_hierarchy *H, int nvec) {
         H->kvec.alloc(n * nvec);
         H->kvec_count = nvec;
     }
-    if (!H->partials.p) H->partials.alloc((size_t)kKMaxBlocks * 2);
-    if (!H->ks.p) H->ks.alloc(1);
+    if (!H->partials.p) H->partials.alloc((size_t)kKMaxBlocks * 4);
+    if (!H->ks.p) H->ks.alloc(3);
 }
 
 static_assert(sizeof(KScalars) <= kHostStageBytes, "Krylov scalars must fit the pinned stage");
+
+static_assert(3 * sizeof(KScalars) <= kHostStageBytes, "two systems' scalars must fit the pinned stage");
+
+void read_ks3(amg_hierarchy *H, KScalars (&k)[3], hipStream_t s) {
+    void *stage = host_stage();
+    GW_HIP(hipMemcpyAsync(stage, H->ks.p, 3 * sizeof(KScalars), hipMemcpyDeviceToHost, s));
+    GW_HIP(hipStreamSynchronize(s));
+    std::memcpy(k, stage, 3 * sizeof(KScalars));
+}
+
+void write_ks3(amg_hierarchy *H, const KScalars (&k)[3], hipStream_t s) {
+    void *stage = host_stage();
+    std::memcpy(stage, k, 3 * sizeof(KScalars));
+    GW_HIP(hipMemcpyAsync(H->ks.p, stage, 3 * sizeof(KScalars), hipMemcpyHostToDevice, s));
+    GW_HIP(hipStreamSynchronize(s));
+}
 
 KScalars read_ks(amg_hierarchy *H, hipStream_t s) {
     void *stage = host_stage();
@@ -705,7 +1055,7 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-enum BlockKind : int { BLOCK_PCG = 1, BLOCK_BICGSTAB = 2 };
+enum BlockKind : int { BLOCK_PCG = 1, BLOCK_BICGSTAB = 2, BLOCK_BICGSTAB2 = 3 };
 
 // Enqueue one block of Krylov iterations on s: `emit(stream)` launches its
 // kernels.  With `graph`, the block is captured once per (kind, length,
@@ -812,10 +1162,41 @@ void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, h
         GW_HIP(hipGetLastError());
         return;
     }
-    if (H->mixed()) vcycle_level<float, double, double>(H, 0, r, z, done, s);
-    else vcycle_level<double, double, double>(H, 0, r, z, done, s);
+    if (H->mixed()) vcycle_level<float, double, double, 1>(H, 0, r, z, done, s);
+    else vcycle_level<double, double, double, 1>(H, 0, r, z, done, s);
     GW_HIP(hipGetLastError());
 }
+
+namespace {
+
+// Level vectors sized for nr interleaved right-hand sides.
+void ensure_level_vectors(amg_hierarchy *H, int nr) {
+    const size_t es = H->mixed() ? 4 : 8;
+    for (int l = 0; l < H->nlev; ++l) {
+        Level &Lv = H->L[l];
+        const size_t need = (size_t)Lv.A.n * es * nr;
+        if (Lv.vx.n >= need) continue;
+        H->drop_graphs();
+        Lv.vx.alloc(need);
+        Lv.vt.alloc(need);
+        if (l > 0) Lv.vb.alloc(need);
+    }
+}
+
+// One V-cycle on two interleaved right-hand sides.
+void vcycle2(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s) {
+    if (H->nlev == 0) {
+        const int64_t n2 = 2 * (int64_t)H->L[0].A.n;
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(blocks_for(n2)), dim3(kBlock), 0, s, r, z, n2, done);
+        GW_HIP(hipGetLastError());
+        return;
+    }
+    if (H->mixed()) vcycle_level<float, double, double, 2>(H, 0, r, z, done, s);
+    else vcycle_level<double, double, double, 2>(H, 0, r, z, done, s);
+    GW_HIP(hipGetLastError());
+}
+
+}  // namespace
 
 void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s) {
     const Level &L0 = H->L[0];
@@ -1017,6 +1398,144 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
         info->solve_ms = now_ms() - t0;
     }
     return k.status;
+}
+
+int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
+                     const amg_solve_params &sp, amg_solve_info info[2], hipStream_t s) {
+    const double t0 = now_ms();
+    ensure_krylov_workspace(H, 20);
+    ensure_level_vectors(H, 2);
+    Kry K(H, s, sp.rtol);
+    const int64_t n = K.n, n2 = 2 * n;
+    double *b = H->kvec.p, *r = b + n2, *rh = r + n2, *p = rh + n2, *v = p + n2, *sv = v + n2, *t = sv + n2,
+           *ph = t + n2, *sh = ph + n2, *x = sh + n2;
+    double *part = K.part;
+    KScalars *ks = K.ks;
+    const double vec2 = 2 * K.vec;
+    auto fin2 = [&](hipStream_t cs, int code, unsigned nb, int mask) {
+        hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kKBlock), 0, cs, code, nb, part, sp.rtol, ks, mask);
+    };
+    auto init2 = [&](int mask, bool first) {
+        {
+            ProfScope ps(K_KRYLOV_SPMV, K.abytes + 7 * vec2, s);
+            K.op([&](auto o) {
+                hipLaunchKernelGGL((k_kr_init2<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, b, x, r, rh, p,
+                                   v, part, mask);
+            });
+        }
+        fin2(s, first ? FIN_INIT_FIRST : FIN_INIT_RESTART, K.gG, mask);
+    };
+    hipLaunchKernelGGL(k_interleave, dim3(K.g1), dim3(kKBlock), 0, s, n, b0, b1, b);
+    KScalars kk[3] = {};
+    kk[0].maxiter = kk[1].maxiter = std::max(0, sp.maxiter);
+    kk[0].status = kk[1].status = GW_NOT_CONVERGED;
+    write_ks3(H, kk, s);
+    fill_f64(x, 0.0, n2, s);
+    init2(3, true);
+    read_ks3(H, kk, s);
+    bool final[2] = {false, false};
+    int restarts[2] = {0, 0}, status[2] = {GW_NOT_CONVERGED, GW_NOT_CONVERGED};
+    bool zero_rhs = false;
+    for (int k = 0; k < 2; ++k) {
+        if (kk[k].bnorm != 0.0) continue;
+        // b = 0: x = 0, nothing to iterate
+        final[k] = true;
+        status[k] = GW_OK;
+        kk[k].done = 1;
+        kk[k].iters = 0;
+        kk[k].rr = 0.0;
+        kk[k].rel_true = 0.0;
+        zero_rhs = true;
+    }
+    if (zero_rhs) {
+        kk[2].done = kk[0].done && kk[1].done;
+        write_ks3(H, kk, s);
+    }
+    const int check = std::max(1, sp.check_every);
+    const bool graph = use_graph(sp);
+    const int32_t *done = &ks[2].done;
+    auto block = [&](hipStream_t cs) {
+        Kry Kc(H, cs, sp.rtol);
+        for (int c = 0; c < check; ++c) {
+            {
+                ProfScope ps(K_KRYLOV_UPDATE, 4 * vec2, cs);
+                hipLaunchKernelGGL(k_bcg_p2, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, p, v, ks);
+            }
+            vcycle2(H, p, ph, done, cs);
+            {
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs);
+                Kc.op([&](auto o) {
+                    hipLaunchKernelGGL((k_bcg_v2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
+                                       part, ks);
+                });
+            }
+            fin2(cs, FIN_BCG_ALPHA, Kc.gG, 3);
+            {
+                ProfScope ps(K_KRYLOV_UPDATE, 3 * vec2, cs);
+                hipLaunchKernelGGL(k_bcg_s2, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, v, sv, part, ks);
+            }
+            fin2(cs, FIN_BCG_S, Kc.g1, 3);
+            vcycle2(H, sv, sh, done, cs);
+            {
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs);
+                Kc.op([&](auto o) {
+                    hipLaunchKernelGGL((k_bcg_t2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
+                                       part, ks);
+                });
+            }
+            fin2(cs, FIN_BCG_OMEGA, Kc.gG, 3);
+            {
+                ProfScope ps(K_KRYLOV_UPDATE, 8 * vec2, cs);
+                hipLaunchKernelGGL(k_bcg_xr2, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, x, r, ph, sh, sv, t, rh, part, ks);
+            }
+            fin2(cs, FIN_BCG_XR, Kc.g1, 3);
+        }
+        GW_HIP(hipGetLastError());
+    };
+    for (;;) {
+        while (!kk[2].done) {
+            run_block(H, graph, BLOCK_BICGSTAB2, check, 0, s, block);
+            read_ks3(H, kk, s);
+        }
+        {
+            ProfScope ps(K_TRUE_RESIDUAL, K.abytes + 2 * vec2, s);
+            K.op([&](auto o) {
+                hipLaunchKernelGGL((k_true_res2<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, b, x, part);
+            });
+        }
+        fin2(s, FIN_TRUE_RES, K.gG, 3);
+        read_ks3(H, kk, s);
+        int mask = 0;
+        for (int k = 0; k < 2; ++k) {
+            if (final[k]) continue;
+            const KScalars &q = kk[k];
+            if (q.status == GW_BREAKDOWN) { status[k] = GW_BREAKDOWN; final[k] = true; continue; }
+            if (q.rel_true <= sp.rtol) { status[k] = GW_OK; final[k] = true; continue; }
+            if (q.iters >= q.maxiter || restarts[k] >= 8) { status[k] = GW_NOT_CONVERGED; final[k] = true; continue; }
+            ++restarts[k];
+            mask |= 1 << k;
+        }
+        if (!mask) break;
+        init2(mask, false);
+        read_ks3(H, kk, s);
+    }
+    hipLaunchKernelGGL(k_split, dim3(K.g1), dim3(kKBlock), 0, s, n, x, x0, x1);
+    GW_HIP(hipGetLastError());
+    const double ms = now_ms() - t0;
+    for (int k = 0; k < 2; ++k) {
+        if (!info) break;
+        const KScalars &q = kk[k];
+        info[k].iters = q.iters;
+        info[k].status = status[k];
+        info[k].restarts = restarts[k];
+        info[k].rel_res = q.bnorm != 0.0 ? std::sqrt(q.rr) / q.bnorm : 0.0;
+        info[k].rel_res_true = q.bnorm != 0.0 ? q.rel_true : 0.0;
+        info[k].setup_ms = 0.0;
+        info[k].solve_ms = ms;
+    }
+    if (status[0] == GW_BREAKDOWN || status[1] == GW_BREAKDOWN) return GW_BREAKDOWN;
+    if (status[0] != GW_OK || status[1] != GW_OK) return GW_NOT_CONVERGED;
+    return GW_OK;
 }
 
 }  // namespace gw

@@ -20,7 +20,7 @@ def _declared():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for n in ["fv_assemble", "amg_setup", "amg_solve_pcg", "amg_solve_bicgstab", "tt_solve",
+    for n in ["fv_assemble", "amg_setup", "amg_solve_pcg", "amg_solve_bicgstab", "amg_solve_bicgstab_pair", "tt_solve",
               "queue_submit", "queue_poll", "darcy_flux", "amg_free", "gw_last_error"]:
         assert n in names
 
@@ -51,3 +51,4 @@ def test_host_side_validation_without_device():
     assert rc == -1 and b"grid" in lib.gw_last_error()
     rc = lib.amg_setup(None, None, None, None)
     assert rc == -1
+    assert lib.amg_solve_bicgstab_pair(None, None, None, None, None, None, None, None) == -1

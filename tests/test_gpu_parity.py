@@ -431,3 +431,37 @@ def test_graph_replay_matches_eager(gw, ref, precision, check):
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
     info = gw.amg_solve_pcg(Hg, bd, x, gw.SolveParams(rtol=1e-8, check_every=check, graph=1))
     assert np.array_equal(host(x).view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("precision,check", [(0, 4), (1, 3)], ids=["fp64", "mixed-check3"])
+def test_bicgstab_pair_matches_single(gw, ref, precision, check):
+    # the lockstep two-system solve gives each system exactly the iterates
+    # of a solve on its own (same hierarchy), including a zero right-hand side
+    _say(f"bicgstab pair precision={precision}")
+    p = gi.heterogeneous_aquifer(30, 24, 10, 2.0, 4, 17)
+    fr = ref.solve_flow(p, ref.AmgParams(), rtol=1e-10)
+    qx, qy, qz = ref.darcy_flux(p, fr.h)
+    g = p.grid
+    A, bt, bc, _ = ref.tt_assemble(g, qx, qy, qz, p.phi, (0, g.ny, 0, g.nz // 2))
+    ap = ref.AmgParams(eps_strong=gw.TT_EPS_STRONG, n_coarse=40)
+    Hg = gw.amg_setup(g.n, dev(A.rowptr), dev(A.col), dev(A.val), gpu_params(gw, ap, precision))
+    sp = gw.SolveParams(rtol=1e-8, check_every=check)
+    singles = []
+    for rhs in (bt, bc):
+        x = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        info = gw.amg_solve_bicgstab(Hg, dev(rhs), x, sp)
+        assert info.status == gw.OK
+        singles.append((host(x), info))
+    y0 = torch.full((g.n,), 3.0, dtype=torch.float64, device="cuda")
+    y1 = torch.full((g.n,), 3.0, dtype=torch.float64, device="cuda")
+    st, infos = gw.amg_solve_bicgstab_pair(Hg, dev(bt), dev(bc), y0, y1, sp)
+    assert st == gw.OK
+    for (x, i1), y, i2 in zip(singles, (host(y0), host(y1)), infos):
+        assert (i2.iters, i2.status, i2.restarts) == (i1.iters, i1.status, i1.restarts)
+        assert np.array_equal(y.view(np.uint64), x.view(np.uint64))
+        assert i2.rel_res_true == i1.rel_res_true
+    # second system zero: x1 = 0 with no iterations, the first unchanged
+    st, infos = gw.amg_solve_bicgstab_pair(Hg, dev(bt), torch.zeros(g.n, dtype=torch.float64, device="cuda"),
+                                           y0, y1, sp)
+    assert st == gw.OK and infos[1].iters == 0 and not host(y1).any()
+    assert np.array_equal(host(y0).view(np.uint64), singles[0][0].view(np.uint64))
