@@ -148,6 +148,7 @@ def cpu_baseline(prob, precision):
     tau, ti = oracle.bicgstab(Ht, bt, rtol=1e-8)
     t_tsolve = time.perf_counter() - t2
     total = t_flow + t_tsetup + 2 * t_tsolve
+    cpu_baseline.last = (h, tau)  # the oracle's heads and travel times, for the error report
     return {
         "value": 1.0 / total,
         "unit": "solves/s",
@@ -219,9 +220,35 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
     lat = np.array([r.latency for r in res2]) * 1e3
     bad += sum(r.status != gw.OK for r in res2)
     cells = np.array([p.grid.n for p in probs])
+    # the same burst with an FP64 hierarchy: the plain FP64 GPU solve the
+    # mixed-precision served form is compared with
+    ap64 = gw.AmgParams(precision=gw.PRECISION_FP64)
+    tp64 = gw.AmgParams.travel_time(precision=gw.PRECISION_FP64)
+    q = gw.Queue(budget, slots)
+    t0 = q.clock()
+    tick = [q.submit(p, ap64, tp64, sp, zone=zone(p), want=()) for p in probs]
+    q.drain()
+    makespan64 = q.clock() - t0
+    bad += sum(q.poll(t)[0].status != gw.OK for t in tick)
+    q.close()
+    # accuracy of the served mixed form against the FP64 GPU solve (itself
+    # within 1e-13 of the FP64 oracle in the parity tests), on three requests
+    errs_h, errs_tau = [], []
+    for p in sorted(probs, key=lambda p: p.grid.n)[:: max(1, len(probs) // 3)][:3]:
+        outs = []
+        for a, t in ((ap, tp), (ap64, tp64)):
+            q = gw.Queue(budget, 1)
+            tk = q.submit(p, a, t, sp, zone=zone(p), want=("h", "tau"))
+            q.drain()
+            outs.append(q.poll(tk)[1])
+            q.close()
+        errs_h.append(float(np.linalg.norm(outs[0]["h"] - outs[1]["h"]) / np.linalg.norm(outs[1]["h"])))
+        errs_tau.append(float(np.linalg.norm(outs[0]["tau"] - outs[1]["tau"]) / np.linalg.norm(outs[1]["tau"])))
     return {
         "requests": n_requests, "slots": slots, "precision": "f32-hierarchy/f64-krylov",
         "saturation_solves_per_s": round(sat, 3),
+        "fp64_saturation_solves_per_s": round(n_requests / makespan64, 3),
+        "mixed_head_rel_err_vs_fp64_max": max(errs_h), "mixed_tau_rel_err_vs_fp64_max": max(errs_tau),
         "offered_load": load, "offered_rate_per_s": round(rate, 3),
         "achieved_solves_per_s": round(n_requests / (end - base), 3),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
@@ -346,9 +373,17 @@ def main():
         print(f"[bench] served stream: {serve}", file=sys.stderr, flush=True)
 
     cpu = None
+    accuracy = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(prob, precision)
+        h_ref, tau_ref = cpu_baseline.last
+        h_gpu, tau_gpu = pipe.h.cpu().numpy(), pipe.tau.cpu().numpy()
+        accuracy = {
+            "head_rel_err_vs_oracle": float(np.linalg.norm(h_gpu - h_ref) / np.linalg.norm(h_ref)),
+            "tau_rel_err_vs_oracle": float(np.linalg.norm(tau_gpu - tau_ref) / np.linalg.norm(tau_ref)),
+            "note": "last timed pass vs the FP64 oracle on the same input (both stop at rtol 1e-8)",
+        }
 
     out = {
         "metric": "AMG-PCG time-to-rtol-1e-8 (1M cells, σ²=4); solves/s; p50/p99 latency",
@@ -372,6 +407,7 @@ def main():
                                  [round(statistics.median(x), 3) for x in zip(*parts)])),
         "tt_iters": list(titers[-1]),
         "roofline": roof,
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
         "serving": serve,
         "kernels": kernels,

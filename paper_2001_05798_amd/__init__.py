@@ -105,7 +105,7 @@ def _load():
     # one of the two can own the device.
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2001_05798_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2001_05798_amd/build.py`")
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
