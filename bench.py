@@ -115,7 +115,10 @@ def measured_traffic(workload: str, kernel: str):
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
+        path = os.path.join(ROOT, f)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as fh:
             h.update(fh.read())
     digest = h.hexdigest()
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):

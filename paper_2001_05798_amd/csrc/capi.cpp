@@ -97,7 +97,7 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     }
     if (prm->smoother == GW_SMOOTHER_NONE) {
         H->nlev = 0;
-        H->L[0].A.grp = lane_group_for(A->n ? (double)A->nnz / (double)A->n : 0.0);
+        H->L[0].A.grp = solve_group_for(A->n ? (double)A->nnz / (double)A->n : 0.0);
         const char *sell_env = std::getenv("GWAMG_SELL");
         if (!(sell_env && std::atoi(sell_env) == 0)) build_sell(H.get(), 0, false, s);
         GW_HIP(hipStreamSynchronize(s));
@@ -116,9 +116,9 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     auto mean = [](const Csr &M) { return M.n ? (double)M.nnz / (double)M.n : 0.0; };
     for (int l = 0; l < std::max(H->nlev, 1); ++l) {
         Level &Lv = H->L[l];
-        Lv.A.grp = lane_group_for(mean(Lv.A));
-        Lv.P.grp = lane_group_for(mean(Lv.P));
-        Lv.R.grp = lane_group_for(mean(Lv.R));
+        Lv.A.grp = solve_group_for(mean(Lv.A));
+        Lv.P.grp = solve_group_for(mean(Lv.P));
+        Lv.R.grp = solve_group_for(mean(Lv.R));
     }
     if (const char *e = std::getenv("GWAMG_G0")) {
         int g = std::atoi(e);

