@@ -748,16 +748,32 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            for (int e = 0; e < m; ++e) {
-                const int32_t off = __shfl(excl, e, G), le = __shfl(len, e, G);
-                for (int32_t t = lane; t < le; t += G) {
-                    bool fresh;
-                    int32_t h = hash_slot(keys, hbits, stJ[off + t], fresh);
-                    if (h < 0) { ovf = true; continue; }
-                    fresh_count += fresh;
-                    if (NUM) vals[h] = vals[h] + stV[off + t];
+            // every staged column finds its slot at once (the slot a key
+            // gets does not depend on the order of insertion that matters
+            // for the sums); the slot then replaces the column in the stage
+            const int32_t tot = __shfl(incl, m - 1, G);
+            for (int32_t c = lane; c < tot; c += G) {
+                bool fresh;
+                int32_t h = hash_slot(keys, hbits, stJ[c], fresh);
+                if (h < 0) {
+                    ovf = true;
+                    h = 0;
                 }
-                __builtin_amdgcn_wave_barrier();
+                fresh_count += fresh;
+                if (NUM) stJ[c] = h;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // the sums, B row after B row in stream order
+            if (NUM) {
+                for (int e = 0; e < m; ++e) {
+                    const int32_t off = G == 64 ? __builtin_amdgcn_readlane(excl, e) : __shfl(excl, e, G);
+                    const int32_t le = G == 64 ? __builtin_amdgcn_readlane(len, e) : __shfl(len, e, G);
+                    for (int32_t t = lane; t < le; t += G) {
+                        const int32_t h = stJ[off + t];
+                        vals[h] = vals[h] + stV[off + t];
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
             p0 += m;
         }
