@@ -979,10 +979,12 @@ struct Staging {
 };
 
 // Call f with the lane-group width (as an integral constant) for rows of
-// this mean length.
+// this mean length; rows of up to 6 entries take one lane each (measured
+// best for the MIS-2 rounds and aggregation passes on strength graphs of ~5
+// entries per row).
 template <class F>
 void with_group(double mean_len, F &&f) {
-    switch (lane_group_for(mean_len)) {
+    switch (lane_group_for(mean_len <= 6.0 ? 1.0 : mean_len)) {
         case 1: f(std::integral_constant<int, 1>()); break;
         case 4: f(std::integral_constant<int, 4>()); break;
         case 16: f(std::integral_constant<int, 16>()); break;
