@@ -122,7 +122,7 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     }
     if (const char *e = std::getenv("GWAMG_G0")) {
         int g = std::atoi(e);
-        if (g == 1 || g == 4 || g == 16 || g == 64) H->L[0].A.grp = g;
+        if (g >= 1 && g <= 64 && (g & (g - 1)) == 0) H->L[0].A.grp = g;
     }
     // Level-0 products (smoother, residual, Krylov) run on the sliced ELL
     // copy unless GWAMG_SELL=0 keeps them on the CSR kernels.

@@ -135,7 +135,7 @@ void prof_flush();
 struct Csr {
     int32_t n = 0, ncols = 0;
     int64_t nnz = 0;
-    int32_t grp = 1;    // lanes per row in the solve-phase products (1, 4, 16, 64)
+    int32_t grp = 1;    // lanes per row in the solve-phase products (a power of two <= 64)
     DBuf<int32_t> rowptr, col;
     DBuf<double> val;
     DBuf<float> val32;  // FP32 copy (mixed precision levels)

@@ -367,8 +367,11 @@ template <class V, class F>
 void with_csr(const Csr &A, const V *val, F &&f) {
     switch (A.grp) {
         case 1: f(OpCsr<1, V>{A.rowptr.p, A.col.p, val}); break;
+        case 2: f(OpCsr<2, V>{A.rowptr.p, A.col.p, val}); break;
         case 4: f(OpCsr<4, V>{A.rowptr.p, A.col.p, val}); break;
+        case 8: f(OpCsr<8, V>{A.rowptr.p, A.col.p, val}); break;
         case 16: f(OpCsr<16, V>{A.rowptr.p, A.col.p, val}); break;
+        case 32: f(OpCsr<32, V>{A.rowptr.p, A.col.p, val}); break;
         default: f(OpCsr<64, V>{A.rowptr.p, A.col.p, val}); break;
     }
 }
@@ -1155,14 +1158,15 @@ int lane_group_for(double mean_row_len) {
 }
 
 // Solve-phase products load 8 entries per lane (4 with 64 lanes) before
-// summing, so a row of up to 6 entries takes one lane, up to 24 four lanes,
-// up to 96 sixteen: measured on the 8.4M-cell pass 215 -> 203 ms against
-// the setup kernels' thresholds with 4/2/2/1 entries per lane.
+// summing: a row gets the fewest lanes G (a power of two) whose 8G slots
+// hold 1.4 times the mean row length, so a typical row is one round and the
+// wave covers as many rows as possible.  Measured against 1/4/16/64 lanes
+// with 4/2/2/1 loads per lane: 8.4M-cell pass 215 -> 172 ms, 1M-cell pass
+// 32.0 -> 30.5 ms (level-1 sweeps of ~33-entry rows 15 -> 11.6 us).
 int solve_group_for(double mean_row_len) {
-    if (mean_row_len <= 6.0) return 1;
-    if (mean_row_len <= 24.0) return 4;
-    if (mean_row_len <= 96.0) return 16;
-    return 64;
+    int g = 1;
+    while (g < 64 && 8.0 * g < 1.4 * mean_row_len) g *= 2;
+    return g;
 }
 
 void vcycle(amg_hierarchy *H, const double *r, double *z, const int32_t *done, hipStream_t s) {
