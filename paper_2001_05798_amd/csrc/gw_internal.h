@@ -231,6 +231,7 @@ struct amg_hierarchy {
     int nlev = 0;  // number of levels including the coarsest (0 = no preconditioner)
     std::vector<gw::Level> L;
     int32_t nd = 0;  // coarsest size
+    int sym_pattern = -1;  // level-0 pattern symmetric: -1 not known yet, 0 no, 1 yes
     gw::DBuf<double> lu, inv;  // row-major LU, column-major inverse
     gw::DBuf<int32_t> piv;
     // Krylov workspace

@@ -112,6 +112,34 @@ __global__ void k_tr_sort(const int32_t *__restrict__ trow, const int32_t *__res
     oval[b + rank] = tval[e];
 }
 
+// A^T on the pattern of A, when that pattern is symmetric: entry (i, j) of
+// A^T is a_ji, found by binary search in row j of A; no counting, atomic
+// fill or sort.  `miss` is set when some (j, i) is absent (the pattern is not
+// symmetric and the result is discarded); one atomic per block at most, on a
+// capped grid.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_sym_transpose(CsrView A, double *__restrict__ tval, int32_t *miss) {
+    int32_t bad = 0;
+    const int lane = (int)(threadIdx.x % G);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; row < A.n;
+         row += (int64_t)gridDim.x * blockDim.x / G) {
+        const int32_t i = (int32_t)row, e = A.rowptr[i + 1];
+        for (int32_t p = A.rowptr[i] + lane; p < e; p += G) {
+            const int32_t j = A.col[p];
+            const int32_t b = A.rowptr[j], len = A.rowptr[j + 1] - b;
+            int32_t lo = 0, hi = len;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (A.col[b + mid] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < len && A.col[b + lo] == i) tval[p] = A.val[b + lo];
+            else bad = 1;
+        }
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(miss, 1);
+}
+
 // --------------------------------------------------------------- strength --
 // Walk the union of row i of A and row i of A^T (both sorted).
 template <class F>
@@ -1166,9 +1194,35 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     DBuf<int64_t> total(1);
     csr_diag(A, diag.p, s);
 
-    // strength graph on A and A^T
+    // strength graph on A and A^T (A^T from A's own pattern when that is
+    // symmetric, as for the flow operator and all its Galerkin products)
     Csr T;
-    transpose(A, T, s, total.p);
+    DBuf<double> tval_sym;
+    CsrView Tv{};
+    bool sym = false;
+    if (H->sym_pattern != 0) {
+        tval_sym.alloc((size_t)std::max<int64_t>(A.nnz, 1));
+        DBuf<int32_t> miss(1);
+        fill_i32(miss.p, 0, 1, s);
+        {
+            ProfScope ps(K_TRANSPOSE, (double)A.nnz * 24, s);
+            with_group(mean_row(A.nnz, n), [&](auto gc) {
+                constexpr int G = decltype(gc)::value;
+                hipLaunchKernelGGL((k_sym_transpose<G>), dim3(std::min(blocks_for((int64_t)n * G), kAtomicBlocks)),
+                                   dim3(kBlock), 0, s, A, tval_sym.p, miss.p);
+            });
+            GW_HIP(hipGetLastError());
+        }
+        sym = st.read(miss.p, s) == 0;
+        H->sym_pattern = sym ? 1 : 0;
+    }
+    if (sym) {
+        Tv = CsrView{n, n, A.nnz, A.rowptr, A.col, tval_sym.p};
+    } else {
+        tval_sym.release();
+        transpose(A, T, s, total.p);
+        Tv = view(T);
+    }
     Csr S;  // pattern only: col + weights in sw
     S.n = S.ncols = n;
     S.rowptr.alloc((size_t)n + 1);
@@ -1176,7 +1230,6 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     DBuf<uint8_t> strongA((size_t)std::max<int64_t>(A.nnz, 1));
     const int Gs = lane_group_for(n ? (double)A.nnz / (double)n : 0.0);
     auto launch_strength = [&](bool fill) {
-        const CsrView Tv = view(T);
         auto grp = [&](auto gc) {
             constexpr int GG = decltype(gc)::value;
             const dim3 grid(blocks_for((int64_t)n * GG));
@@ -1217,6 +1270,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         GW_HIP(hipGetLastError());
     }
     T = Csr();
+    tval_sym.release();
     Lv.nnz_s = S.nnz;
 
     // MIS-2 rounds, batched between host checks; a round after the last
