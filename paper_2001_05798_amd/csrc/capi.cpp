@@ -112,6 +112,15 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
             break;
         }
     }
+    {
+        // the prolongator weights, kept on the device during the build
+        double *stage = static_cast<double *>(host_stage());
+        static_assert(33 * sizeof(double) <= kHostStageBytes, "one weight per level fits the pinned stage");
+        for (int l = 0; l + 1 < H->nlev; ++l)
+            GW_HIP(hipMemcpyAsync(stage + l, H->L[l].omega_dev.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        for (int l = 0; l + 1 < H->nlev; ++l) H->L[l].omega_p = stage[l];
+    }
     const size_t es = H->mixed() ? 4 : 8;
     auto mean = [](const Csr &M) { return M.n ? (double)M.nnz / (double)M.n : 0.0; };
     for (int l = 0; l < std::max(H->nlev, 1); ++l) {

@@ -202,6 +202,7 @@ struct Level {
     int64_t nnz_s = 0;
     int32_t mis_rounds = 0;
     double omega_p = 0.0;
+    DBuf<double> omega_dev;  // omega_P on the device (read back after setup)
     // V-cycle vectors of this level, element size 8 (FP64) or 4 (mixed):
     // b (right-hand side), x (iterate) and t (ping-pong / residual)
     DBuf<char> vb, vx, vt;

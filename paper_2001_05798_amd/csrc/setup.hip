@@ -1061,7 +1061,7 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
     int64_t cap = std::min<int64_t>(ub, ncols);
     int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
     C.alloc(nrows, ncols, 0);
-    fill_i32(C.rowptr.p, 0, (int64_t)nrows + 1, s);
+    fill_i32(C.rowptr.p, 0, 1, s);  // the symbolic pass writes every other row length
     const int G = spgemm_group(avg_a_len);
     // stage: about one and a half average segments, 32..512 contributions
     // (a larger stage costs resident waves: the numeric pass is LDS-bound)
@@ -1350,7 +1350,8 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
 
     // smoothed prolongator
     DBuf<unsigned long long> rho_bits(1);
-    DBuf<double> omega(1);
+    DBuf<double> &omega = Lv.omega_dev;  // read back once the hierarchy is built
+    omega.alloc(1);
     fill_i32(reinterpret_cast<int32_t *>(rho_bits.p), 0, 2, s);
     {
         ProfScope ps(K_SETUP_MISC, (double)A.nnz * 8 + n * 8.0, s);
@@ -1367,7 +1368,6 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
     const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
     spgemm(af, bt, n, (int32_t)nc, arow, 1.0, ep, Lv.P, s, st);
-    Lv.omega_p = st.read(omega.p, s);
 
     // R = P^T, A_c = R (A P)
     transpose(view(Lv.P), Lv.R, s, total.p);
@@ -1380,7 +1380,6 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
     spgemm(ARowCsr{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p}, BCsr{AP.rowptr.p, AP.col.p, AP.val.p}, (int32_t)nc,
            (int32_t)nc, ravg, apavg, EpiIdentity{}, Nx.A, s, st);
-    GW_HIP(hipStreamSynchronize(s));
 }
 
 void make_smoother(amg_hierarchy *H, int l, hipStream_t s) {
