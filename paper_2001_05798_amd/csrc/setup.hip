@@ -353,6 +353,55 @@ __global__ void __launch_bounds__(kBlock) k_strength_grp(CsrView A, CsrView T, c
     if (lane == 0) dF[i] = lump;
 }
 
+// The strength graph when A's pattern is symmetric and tval holds A^T on it
+// (a_ji at the position of a_ij): the union of the two rows is A's row, so
+// each entry is classified where it stands.  Same results as the walk over
+// the union.
+template <int G, bool FILL>
+__global__ void __launch_bounds__(kBlock) k_strength_sym(CsrView A, const double *__restrict__ tval,
+                                                         const double *__restrict__ diag, double eps2,
+                                                         int32_t *__restrict__ cnt, const int32_t *__restrict__ srow,
+                                                         int32_t *__restrict__ scol, double *__restrict__ sw,
+                                                         uint8_t *__restrict__ strongA, double *__restrict__ dF) {
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+    const int lane = (int)(threadIdx.x % G);
+    if (row >= A.n) return;
+    const int32_t i = (int32_t)row;
+    const int32_t pa = A.rowptr[i], la = A.rowptr[i + 1] - pa;
+    const double di = diag[i];
+    const int32_t q0 = FILL ? srow[i] : 0;
+    int32_t run = 0;
+    double lump = di;
+    for (int32_t c0 = 0; c0 < la; c0 += G) {
+        const int32_t a = c0 + lane;
+        const bool in = a < la;
+        const int32_t j = in ? A.col[pa + a] : i;
+        const double aij = in ? A.val[pa + a] : 0.0, aji = in ? tval[pa + a] : 0.0;
+        const bool st = in && j != i && strong_pair(aij, aji, di, diag[j], eps2);
+        const int32_t sc = st ? 1 : 0;
+        const int32_t incl = grp_scan_incl<G>(sc, lane);
+        if (FILL) {
+            if (in) strongA[pa + a] = st ? 1 : 0;
+            if (st) {
+                const int32_t pos = run + incl - sc;
+                scol[q0 + pos] = j;
+                const double x = fabs(aij), y = fabs(aji);
+                sw[q0 + pos] = x > y ? x : y;
+            }
+            const double weak = (in && j != i && !st) ? aij : 0.0;
+            for (int t = 0; t < G; ++t) {
+                const double w = __shfl(weak, t, G);
+                if (c0 + t < la && w != 0.0) lump = lump + w;
+            }
+        }
+        run += __shfl(incl, G - 1, G);
+    }
+    if (lane == 0) {
+        if (FILL) dF[i] = lump;
+        else cnt[i + 1] = run;
+    }
+}
+
 // ------------------------------------------------------------------ MIS-2 --
 // Kernels that end in one same-address atomic per block run a capped grid
 // over a row loop: such atomics serialize (about 10 ns each), so a grid of one
@@ -898,9 +947,11 @@ __global__ void k_csr_to_dense(CsrView A, double *__restrict__ a) {
 }
 
 // Right-looking LU with partial pivoting in one workgroup (LAPACK getrf
-// order: the first row holding the largest |a_ik| is the pivot).
-__global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32_t n, int32_t *__restrict__ piv,
-                                                   int32_t *status) {
+// order: the first row holding the largest |a_ik| is the pivot), on `a`
+// row-major n x n in memory M: global memory, or LDS for small n (the
+// matrix is copied in and out).  Each entry is updated k after k, with no
+// fused multiply-add, exactly as the unblocked algorithm does.
+__device__ __forceinline__ void lu_in_place(double *a, int32_t n, int32_t *__restrict__ piv, int32_t *status) {
     __shared__ double sv[16];
     __shared__ int32_t si[16];
     __shared__ int32_t p_sh;
@@ -944,13 +995,31 @@ __global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32
         const double akk = a[(int64_t)k * n + k];
         for (int32_t i = k + 1 + tid; i < n; i += blockDim.x) a[(int64_t)i * n + k] = a[(int64_t)i * n + k] / akk;
         __syncthreads();
-        const int32_t m = n - k - 1;
-        for (int64_t e = tid; e < (int64_t)m * m; e += blockDim.x) {
-            int32_t i = k + 1 + (int32_t)(e / m), j = k + 1 + (int32_t)(e % m);
-            a[(int64_t)i * n + j] = a[(int64_t)i * n + j] - a[(int64_t)i * n + k] * a[(int64_t)k * n + j];
+        // trailing update: wave per row, lanes along the row
+        for (int32_t i = k + 1 + w; i < n; i += nw) {
+            const double lik = a[(int64_t)i * n + k];
+            for (int32_t j = k + 1 + lane; j < n; j += 64)
+                a[(int64_t)i * n + j] = a[(int64_t)i * n + j] - lik * a[(int64_t)k * n + j];
         }
         __syncthreads();
     }
+}
+
+__global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32_t n, int32_t *__restrict__ piv,
+                                                   int32_t *status) {
+    lu_in_place(a, n, piv, status);
+}
+
+constexpr int kLuLdsMax = 88;  // 88 x 88 doubles = 61952 B of LDS
+
+__global__ void __launch_bounds__(1024) k_dense_lu_lds(double *__restrict__ a, int32_t n,
+                                                       int32_t *__restrict__ piv, int32_t *status) {
+    extern __shared__ double lu_sm[];
+    for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) lu_sm[e] = a[e];
+    __syncthreads();
+    lu_in_place(lu_sm, n, piv, status);
+    __syncthreads();
+    for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) a[e] = lu_sm[e];
 }
 
 // Column c of the inverse: solve L U x = Perm e_c, one wave per column with
@@ -1241,6 +1310,22 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
                                    S.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr,
                                    (uint8_t *)nullptr, (double *)nullptr);
         };
+        if (sym) {
+            // A^T lives on A's own pattern: classify in place
+            auto symk = [&](auto gc) {
+                constexpr int GG = decltype(gc)::value;
+                const dim3 grid(blocks_for((int64_t)n * GG));
+                if (fill)
+                    hipLaunchKernelGGL((k_strength_sym<GG, true>), grid, dim3(kBlock), 0, s, A, tval_sym.p, diag.p,
+                                       eps2, (int32_t *)nullptr, S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p);
+                else
+                    hipLaunchKernelGGL((k_strength_sym<GG, false>), grid, dim3(kBlock), 0, s, A, tval_sym.p, diag.p,
+                                       eps2, S.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                       (double *)nullptr, (uint8_t *)nullptr, (double *)nullptr);
+            };
+            with_group(mean_row(A.nnz, n), symk);
+            return;
+        }
         switch (Gs) {
             case 1:
                 if (fill)
@@ -1425,7 +1510,11 @@ void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
     {
         ProfScope ps(K_COARSE_LU, (double)n * n * 24, s);
         hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, s, view(Lv.A), H->lu.p);
-        hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(1024), 0, s, H->lu.p, n, H->piv.p, status.p);
+        if (n <= kLuLdsMax)
+            hipLaunchKernelGGL(k_dense_lu_lds, dim3(1), dim3(1024), (size_t)n * n * sizeof(double), s, H->lu.p, n,
+                               H->piv.p, status.p);
+        else
+            hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(1024), 0, s, H->lu.p, n, H->piv.p, status.p);
         GW_HIP(hipGetLastError());
     }
     Staging st;
