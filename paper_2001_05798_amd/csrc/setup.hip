@@ -995,11 +995,24 @@ __device__ __forceinline__ void lu_in_place(double *a, int32_t n, int32_t *__res
         const double akk = a[(int64_t)k * n + k];
         for (int32_t i = k + 1 + tid; i < n; i += blockDim.x) a[(int64_t)i * n + k] = a[(int64_t)i * n + k] / akk;
         __syncthreads();
-        // trailing update: wave per row, lanes along the row
-        for (int32_t i = k + 1 + w; i < n; i += nw) {
-            const double lik = a[(int64_t)i * n + k];
-            for (int32_t j = k + 1 + lane; j < n; j += 64)
-                a[(int64_t)i * n + j] = a[(int64_t)i * n + j] - lik * a[(int64_t)k * n + j];
+        // trailing update: a wave takes four rows at a time (independent
+        // updates in flight), lanes along the row
+        for (int32_t i0 = k + 1 + w; i0 < n; i0 += 4 * nw) {
+            double lik[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t i = min(i0 + u * nw, n - 1);
+                lik[u] = a[(int64_t)i * n + k];
+            }
+            for (int32_t j = k + 1 + lane; j < n; j += 64) {
+                const double akj = a[(int64_t)k * n + j];
+                double aij[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) aij[u] = a[(int64_t)min(i0 + u * nw, n - 1) * n + j];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u * nw < n) a[(int64_t)(i0 + u * nw) * n + j] = aij[u] - lik[u] * akj;
+            }
         }
         __syncthreads();
     }
@@ -1012,7 +1025,7 @@ __global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32
 
 constexpr int kLuLdsMax = 88;  // 88 x 88 doubles = 61952 B of LDS
 
-__global__ void __launch_bounds__(1024) k_dense_lu_lds(double *__restrict__ a, int32_t n,
+__global__ void __launch_bounds__(256) k_dense_lu_lds(double *__restrict__ a, int32_t n,
                                                        int32_t *__restrict__ piv, int32_t *status) {
     extern __shared__ double lu_sm[];
     for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) lu_sm[e] = a[e];
@@ -1511,7 +1524,7 @@ void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
         ProfScope ps(K_COARSE_LU, (double)n * n * 24, s);
         hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, s, view(Lv.A), H->lu.p);
         if (n <= kLuLdsMax)
-            hipLaunchKernelGGL(k_dense_lu_lds, dim3(1), dim3(1024), (size_t)n * n * sizeof(double), s, H->lu.p, n,
+            hipLaunchKernelGGL(k_dense_lu_lds, dim3(1), dim3(256), (size_t)n * n * sizeof(double), s, H->lu.p, n,
                                H->piv.p, status.p);
         else
             hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(1024), 0, s, H->lu.p, n, H->piv.p, status.p);
