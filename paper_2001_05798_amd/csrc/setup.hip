@@ -1145,10 +1145,10 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
     C.alloc(nrows, ncols, 0);
     fill_i32(C.rowptr.p, 0, 1, s);  // the symbolic pass writes every other row length
     const int G = spgemm_group(avg_a_len);
-    // stage: about one and a half average segments, 32..512 contributions
-    // (a larger stage costs resident waves: the numeric pass is LDS-bound)
-    int S = 32;
-    while (S < 512 && S < 1.5 * G * avg_b_len) S *= 2;
+    // stage: about one and a half average segments, 32..512 contributions,
+    // rounded to 16 (LDS per row bounds the resident waves: no larger stage
+    // than needed)
+    int S = std::max(32, std::min(512, ((int)(1.5 * G * avg_b_len) + 15) / 16 * 16));
     constexpr size_t kMaxLds = 64 * 1024;
     auto launch = [&](auto kern, bool num, int hbits) {
         const size_t H = (size_t)1 << hbits;
@@ -1190,7 +1190,8 @@ void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double
     C.nnz = nnz;
     C.col.alloc((size_t)nnz);
     C.val.alloc((size_t)nnz);
-    const int hbn = std::min(pow2_bits_at_least(2 * std::max<int32_t>(maxd, 1)), kMaxHashBits);
+    // numeric table: at least 1.5 slots per column of the longest row
+    const int hbn = std::min(pow2_bits_at_least((int64_t)(1.5 * std::max<int32_t>(maxd, 1))), kMaxHashBits);
     {
         ProfScope ps(K_SPGEMM, 0, s);
         auto num = [&](dim3 g, dim3 b, size_t sh, int Sx) {
