@@ -369,6 +369,20 @@ def main():
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
                for k, v in all_stats.items() if v["launches"]}
 
+    # the whole solve phase against the roofline: algorithmic bytes of every
+    # solve-phase launch of one pass (counted in the warm-up, where every
+    # launch is recorded) over the timed flow + travel-time solve time
+    solve_phase = None
+    if all_stats and args.warmup > 0:
+        sbytes = sum(v["bytes"] for k, v in all_stats.items() if k not in SETUP_KERNELS and k not in
+                     ("fv_assemble", "darcy_flux", "tt_assemble")) / args.warmup
+        bd = [statistics.median(x) for x in zip(*parts)]
+        sms = bd[1] + bd[3]
+        solve_phase = {"bytes_per_pass": round(sbytes), "ms": round(sms, 3),
+                       "achieved_GBps": round(sbytes / (sms * 1e-3) / 1e9, 1),
+                       "frac": round(sbytes / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "note": "flow PCG + travel-time pair, host polling and launch gaps included"}
+
     serve = None
     if args.serve_requests > 0:
         print(f"[bench] served stream, {args.serve_requests} requests ...", file=sys.stderr, flush=True)
@@ -410,6 +424,7 @@ def main():
                                  [round(statistics.median(x), 3) for x in zip(*parts)])),
         "tt_iters": list(titers[-1]),
         "roofline": roof,
+        "solve_phase_roofline": solve_phase,
         "accuracy": accuracy,
         "cpu_baseline": cpu,
         "serving": serve,

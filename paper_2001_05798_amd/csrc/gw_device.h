@@ -104,5 +104,19 @@ __device__ __forceinline__ void sum_partials(const double *partials, unsigned nb
 
 __device__ __forceinline__ bool finite_nz(double v) { return isfinite(v) && v != 0.0; }
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+// and each XCD has its own L2.  Renumbered this way, each XCD walks one
+// contiguous range of rows, so the x_j its rows gather (neighbours a row, a
+// line or a plane away) stay in its own L2 instead of being fetched by all
+// eight.  A bijection of [0, gridDim.x); the last gridDim.x mod 8 keep their
+// number.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t full = nb / kXcds * kXcds;
+    if (b >= full) return b;
+    return (b % kXcds) * (full / kXcds) + b / kXcds;
+}
+
 }  // namespace dev
 }  // namespace gw

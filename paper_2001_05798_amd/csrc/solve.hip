@@ -195,7 +195,7 @@ struct OpSell {
     __syncthreads();
 
 #define GROUP_ROW(G)                                                              \
-    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;          \
+    const int64_t gtid = dev::xcd_block() * (int64_t)blockDim.x + threadIdx.x;     \
     const int64_t i = gtid / (G);                                                 \
     const int lane = (int)(gtid % (G));                                           \
     if (i >= n) return;
@@ -490,7 +490,7 @@ unsigned kgrid(int64_t n, int G) {
 
 #define GROUP_LOOP(G, i, lane, n)                                                         \
     const int lane = (int)(threadIdx.x % (G));                                            \
-    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / (G); i < (n);     \
+    for (int64_t i = (dev::xcd_block() * (int64_t)blockDim.x + threadIdx.x) / (G); i < (n); \
          i += (int64_t)gridDim.x * blockDim.x / (G))
 
 #define GRID_LOOP(i, n) \

@@ -465,3 +465,30 @@ def test_bicgstab_pair_matches_single(gw, ref, precision, check):
                                            y0, y1, sp)
     assert st == gw.OK and infos[1].iters == 0 and not host(y1).any()
     assert np.array_equal(host(y0).view(np.uint64), singles[0][0].view(np.uint64))
+
+
+def test_c3_mixed_flow_against_fp64_residual(gw, ref):
+    # the 8.4M-cell configuration in the benchmark's mixed form: the true
+    # residual of the GPU heads, recomputed on the CPU with the oracle's own
+    # matrix in FP64, meets rtol; the FP64 hierarchy gives the same heads
+    # within the mixed-path tolerance
+    _say("C3 256x256x128 mixed FCG vs FP64 residual")
+    p = gi.heterogeneous_aquifer(256, 256, 128, 4.0, 8, 21)
+    n = p.grid.n
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    heads = []
+    for precision in (gw.PRECISION_MIXED, gw.PRECISION_FP64):
+        H = gw.amg_setup(n, rowptr, col, val, gw.AmgParams(precision=precision))
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        info = gw.amg_solve_pcg(H, bd, x, gw.SolveParams(rtol=1e-8))
+        _say(f"  precision {precision}: {info.iters} iterations, status {info.status}")
+        assert info.status == gw.OK and info.rel_res_true <= 1e-8
+        heads.append(host(x))
+        del H
+    A, b = ref.fv_assemble(p)
+    r = b - A.to_scipy() @ heads[0]
+    rel = np.linalg.norm(r) / np.linalg.norm(b)
+    _say(f"  oracle-matrix residual of the mixed heads {rel:.2e}")
+    assert rel <= 1.05e-8
+    err = np.linalg.norm(heads[0] - heads[1]) / np.linalg.norm(heads[1])
+    assert err <= 1e-6, err
