@@ -444,16 +444,16 @@ __device__ __forceinline__ T grp_min(T v) {
 
 // Row of a G-lane group: index, lane, and whether it exists.  Every lane of
 // a block stays to the end (block reductions follow).
-#define GRP_ROW(G, n)                                                            \
-    const int64_t row_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / (G); \
+#define GRP_ROW(G, n)                                                                \
+    const int64_t row_ = (dev::xcd_block() * (int64_t)blockDim.x + threadIdx.x) / (G); \
     const int lane_ = (int)(threadIdx.x % (G));                                  \
     const bool has_ = row_ < (n);                                                \
     const int32_t i = has_ ? (int32_t)row_ : 0;
 
 // Rows visited by G-lane groups over the whole (capped) grid.
-#define GRP_LOOP(G, n)                                                                      \
-    const int lane_ = (int)(threadIdx.x % (G));                                             \
-    for (int64_t row_ = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / (G); row_ < (n); \
+#define GRP_LOOP(G, n)                                                                          \
+    const int lane_ = (int)(threadIdx.x % (G));                                                 \
+    for (int64_t row_ = (dev::xcd_block() * (int64_t)blockDim.x + threadIdx.x) / (G); row_ < (n); \
          row_ += (int64_t)gridDim.x * blockDim.x / (G))
 
 // m1_i = max(key_i, max_{j in S(i)} key_j) (a maximum: any lane order).
@@ -776,7 +776,7 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
         vals = sm_dbl + (size_t)group * (H + S);
         stV = vals + H;
     }
-    const int64_t row = (int64_t)blockIdx.x * groups + group;
+    const int64_t row = dev::xcd_block() * groups + group;  // XCD-contiguous row ranges
     const bool active = row < nrows;
     for (int32_t s = lane; s < H; s += G) {
         keys[s] = -1;
