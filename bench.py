@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="skip the direct upwind-sweep travel-time measurement")
     ap.add_argument("--graph", type=int, default=-1, choices=(-1, 0, 1),
                     help="Krylov blocks as captured HIP graphs: 1 on, 0 or -1 (library default) launched one by one")
     ap.add_argument("--copy-probe", action="store_true",
@@ -383,6 +385,38 @@ def main():
                        "frac": round(sbytes / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "note": "flow PCG + travel-time pair, host polling and launch gaps included"}
 
+    # the direct alternative for the travel-time pair: assemble + one upwind
+    # sweep in flow order on the last pass's velocities (exact solution)
+    direct = None
+    if not args.no_direct:
+        tau_d, c_d = torch.zeros_like(pipe.tau), torch.zeros_like(pipe.c)
+        g = pipe.g
+        for _ in range(2):
+            lev = gw.tt_solve_direct(g, pipe.qx, pipe.qy, pipe.qz, prob.phi, pipe.zone, tau_d, c_d)
+        torch.cuda.synchronize()
+        reps, dms = 5, []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            gw.tt_solve_direct(g, pipe.qx, pipe.qy, pipe.qz, prob.phi, pipe.zone, tau_d, c_d)
+            torch.cuda.synchronize()
+            dms.append(1e3 * (time.perf_counter() - t1))
+        gw.prof_select(None)
+        gw.prof_enable(True)
+        gw.tt_solve_direct(g, pipe.qx, pipe.qy, pipe.qz, prob.phi, pipe.zone, tau_d, c_d)
+        ds = gw.prof_read()
+        gw.prof_enable(False)
+        bd = [statistics.median(x) for x in zip(*parts)]
+        amg_tt = bd[2] + bd[3]
+        dmed = statistics.median(dms)
+        direct = {"ms": round(dmed, 3), "levels": lev,
+                  "kernel_ms": {k: round(ds[k]["ms"], 3) for k in ("tt_assemble", "sweep_lists", "sweep")
+                                if k in ds},
+                  "amg_pair_ms": round(amg_tt, 3), "speedup_vs_amg_pair": round(amg_tt / dmed, 2),
+                  "tau_rel_diff_vs_amg": float(torch.linalg.norm(tau_d - pipe.tau) / torch.linalg.norm(tau_d)),
+                  "c_rel_diff_vs_amg": float(torch.linalg.norm(c_d - pipe.c) / torch.linalg.norm(c_d)),
+                  "note": "tt_solve_direct (assemble + upwind sweep, 2 RHS), median of 5 calls; not in the timed step"}
+        print(f"[bench] direct travel time: {direct}", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve_requests > 0:
         print(f"[bench] served stream, {args.serve_requests} requests ...", file=sys.stderr, flush=True)
@@ -425,6 +459,7 @@ def main():
         "tt_iters": list(titers[-1]),
         "roofline": roof,
         "solve_phase_roofline": solve_phase,
+        "tt_direct": direct,
         "accuracy": accuracy,
         "cpu_baseline": cpu,
         "serving": serve,

@@ -242,6 +242,28 @@ int tt_solve(const gw_grid *grid, const double *qx, const double *qy, const doub
              const gw_zone *zone, const amg_params *params, const amg_solve_params *sp, double *tau,
              double *c, amg_solve_info info[2], void *stream);
 
+/* Exact direct solve of an upwind system (Eq. 1 discretised as tt_assemble
+ * does, or the reversed-flow system of the backward travel time).  Each
+ * off-diagonal entry (i, j) of such a matrix couples cell i to an inflow
+ * neighbour j, and water enters a cell only from cells of higher head, so
+ * the matrix is triangular in the order of decreasing head; the paper's
+ * Results prefer a direct method for the transport systems, and this one
+ * costs a single pass.  Cells are solved level by level in a topological
+ * order of the inflow graph (a cell as soon as all its inflow neighbours
+ * are), each as forward substitution does it: x_i = (b_i - sum_j a_ij x_j) /
+ * a_ii with the off-diagonal terms subtracted in the row's column order.
+ * A [device] square CSR with ascending columns and a positive diagonal;
+ * b, x [device] nrhs blocks of n values each (system k in [k n, (k+1) n)),
+ * 1 <= nrhs <= 64; n_levels [host] or NULL receives the number of levels.
+ * EINVAL for a malformed matrix; BREAKDOWN when the inflow graph has a cycle
+ * (then only the cells upstream of no cycle are written). */
+int tt_sweep(const gw_csr *A, int32_t nrhs, const double *b, double *x, int32_t *n_levels, void *stream);
+
+/* tt_assemble followed by tt_sweep on both right-hand sides: the direct
+ * counterpart of tt_solve.  tau, c [device] n; n_levels as in tt_sweep. */
+int tt_solve_direct(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+                    const gw_zone *zone, double *tau, double *c, int32_t *n_levels, void *stream);
+
 /* ---- kernel timing (HIP events around launches, for roofline reports) --- */
 
 typedef struct {

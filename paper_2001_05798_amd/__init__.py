@@ -131,6 +131,9 @@ def _load():
                                   C.POINTER(i64), C.POINTER(i64), vp]),
         "tt_solve": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), C.POINTER(AmgParamsC),
                                C.POINTER(SolveParamsC), vp, vp, C.POINTER(SolveInfoC), vp]),
+        "tt_sweep": (C.c_int, [C.POINTER(GwCsr), i32, vp, vp, C.POINTER(i32), vp]),
+        "tt_solve_direct": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), vp, vp,
+                                      C.POINTER(i32), vp]),
         "gw_prof_enable": (C.c_int, [i32]),
         "gw_prof_read": (C.c_int, [C.POINTER(KernelStatC), i32, C.POINTER(i32)]),
         "gw_prof_select": (C.c_int, [C.c_char_p]),
@@ -303,6 +306,31 @@ def tt_solve(grid, qx, qy, qz, phi: float, zone, params: AmgParams, sp: SolvePar
     return st, [SolveInfo.of(info[0]), SolveInfo.of(info[1])]
 
 
+def tt_sweep(n: int, rowptr, col, val, b, x, nrhs: int = 1, stream=None) -> int:
+    """Exact solve of an upwind system for nrhs right-hand sides (b, x hold
+    nrhs blocks of n values).  Returns the number of dependency levels."""
+    import torch
+    nnz = int(col.numel())
+    for t, name, dt, m in ((rowptr, "rowptr", torch.int32, n + 1), (col, "col", torch.int32, nnz),
+                           (val, "val", torch.float64, nnz), (b, "b", torch.float64, n * nrhs),
+                           (x, "x", torch.float64, n * nrhs)):
+        _expect(t, dt, m, name)
+    A = GwCsr(int(n), nnz, _ptr(rowptr), _ptr(col), _ptr(val))
+    lev = C.c_int32(0)
+    _check(_lib.tt_sweep(C.byref(A), int(nrhs), _ptr(b), _ptr(x), C.byref(lev), _stream(stream)))
+    return int(lev.value)
+
+
+def tt_solve_direct(grid, qx, qy, qz, phi: float, zone, tau, c, stream=None) -> int:
+    """Assemble the travel-time system and solve both right-hand sides by
+    the upwind sweep.  Returns the number of dependency levels."""
+    z = None if zone is None else C.byref(GwZone(*zone))
+    lev = C.c_int32(0)
+    _check(_lib.tt_solve_direct(C.byref(grid_c(grid)), _ptr(qx), _ptr(qy), _ptr(qz), float(phi), z,
+                                _ptr(tau), _ptr(c), C.byref(lev), _stream(stream)))
+    return int(lev.value)
+
+
 # ---------------------------------------------------------------- AMG ----
 @dataclasses.dataclass
 class LevelInfo:
@@ -322,11 +350,14 @@ class Hierarchy:
     def __init__(self, handle: int, n: int):
         self._h = C.c_void_p(handle)
         self.n = n
+        # held by the object: module globals may already be cleared when a
+        # hierarchy is collected at interpreter exit
+        self._free = _lib.amg_free
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.amg_free(h)
+            self._free(h)
             self._h = C.c_void_p(0)
 
     @property
@@ -446,6 +477,7 @@ class Queue:
         _check(_lib.queue_create(C.c_size_t(int(hbm_budget_bytes)), int(max_slots), C.byref(q)))
         self._q = q
         self._keep = {}
+        self._destroy = _lib.queue_destroy
 
     def __del__(self):
         self.close()
@@ -453,7 +485,7 @@ class Queue:
     def close(self):
         q = getattr(self, "_q", None)
         if q is not None and q.value:
-            _lib.queue_destroy(q)
+            self._destroy(q)
             self._q = C.c_void_p(0)
         self._keep = {}
 

@@ -26,6 +26,7 @@ SOURCES = [
     ("setup.hip", True),
     ("sell.hip", False),
     ("solve.hip", False),
+    ("sweep.hip", True),
     ("capi.cpp", False),
     ("serve.cpp", False),
 ]

@@ -391,4 +391,61 @@ int tt_solve(const gw_grid *grid, const double *qx, const double *qy, const doub
     });
 }
 
+int tt_sweep(const gw_csr *A, int32_t nrhs, const double *b, double *x, int32_t *n_levels, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(A && A->rowptr && A->col && A->val && b && x, "tt_sweep: null pointer");
+        GW_REQUIRE(A->n > 0 && A->nnz >= A->n && A->nnz < INT32_MAX, "tt_sweep: bad matrix size");
+        GW_REQUIRE(nrhs >= 1 && nrhs <= 64, "tt_sweep: nrhs must be in [1, 64]");
+        GW_REQUIRE(b != x, "tt_sweep: b and x must be different buffers");
+        hipStream_t s = as_stream(stream);
+        const CsrView V{A->n, A->n, A->nnz, A->rowptr, A->col, A->val};
+        {
+            DBuf<double> diag(A->n);
+            DBuf<int32_t> bad(1);
+            fill_i32(bad.p, 0, 1, s);
+            launch_csr_check(V, diag.p, bad.p, s);
+            int32_t *stage = static_cast<int32_t *>(host_stage());
+            GW_HIP(hipMemcpyAsync(stage, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            GW_HIP(hipStreamSynchronize(s));
+            const int32_t hb = stage[0];
+            if (hb & 1) fail(GW_EINVAL, "tt_sweep: CSR structure invalid (row pointers, column range or order)");
+            if (hb & 2) fail(GW_EINVAL, "tt_sweep: a diagonal entry is missing or not positive");
+            if (hb & 4) fail(GW_EINVAL, "tt_sweep: non-finite matrix value");
+        }
+        int32_t lev = 0;
+        const int64_t solved = upwind_sweep(V, nrhs, b, x, &lev, s);
+        finish(s);
+        if (n_levels) *n_levels = lev;
+        if (solved != A->n) fail(GW_BREAKDOWN, "tt_sweep: the inflow graph has a cycle (not an upwind matrix)");
+        return GW_OK;
+    });
+}
+
+int tt_solve_direct(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+                    const gw_zone *zone, double *tau, double *c, int32_t *n_levels, void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(qx && qy && qz && tau && c, "tt_solve_direct: null pointer");
+        GW_REQUIRE(tau != c, "tt_solve_direct: tau and c must be different buffers");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+        Csr A;
+        A.alloc((int32_t)n, (int32_t)n, nnz7(grid));
+        DBuf<double> b2((size_t)n * 2), x2((size_t)n * 2);
+        int64_t nnz = 0, nid = 0;
+        int rc = tt_assemble(grid, qx, qy, qz, phi, zone, A.rowptr.p, A.col.p, A.val.p, b2.p, b2.p + n, &nnz, &nid,
+                             stream);
+        if (rc != GW_OK) fail(rc, gw_last_error());
+        const CsrView V{(int32_t)n, (int32_t)n, nnz, A.rowptr.p, A.col.p, A.val.p};
+        int32_t lev = 0;
+        const int64_t solved = upwind_sweep(V, 2, b2.p, x2.p, &lev, s);
+        copy_bytes(tau, x2.p, sizeof(double) * (size_t)n, s);
+        copy_bytes(c, x2.p + n, sizeof(double) * (size_t)n, s);
+        finish(s);
+        if (n_levels) *n_levels = lev;
+        if (solved != n) fail(GW_BREAKDOWN, "tt_solve_direct: the inflow graph has a cycle");
+        return GW_OK;
+    });
+}
+
 }  // extern "C"

@@ -117,6 +117,8 @@ enum KernelId : int {
     K_SMOOTH_FIRST1, K_SMOOTH1, K_RESIDUAL1, K_RESTRICT1, K_PROLONG1,
     K_SMOOTH_FIRSTC, K_SMOOTHC, K_RESIDUALC, K_RESTRICTC, K_PROLONGC, K_COARSE_SOLVE,
     K_KRYLOV_SPMV, K_KRYLOV_UPDATE, K_KRYLOV_DOT, K_TRUE_RESIDUAL,
+    // direct upwind sweep: dependency lists, then the sweep itself
+    K_SWEEP_LISTS, K_SWEEP,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -315,5 +317,13 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solv
 // as krylov_bicgstab solves it alone).  Returns the worse of the statuses.
 int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
                      const amg_solve_params &sp, amg_solve_info info[2], hipStream_t s);
+
+// sweep.hip
+// Exact solve of a system whose rows couple each cell to its inflow
+// neighbours only, by levels of a topological order of the inflow graph.
+// b, x: nrhs blocks of A.n values.  Returns the number of cells solved (below
+// A.n when the inflow graph has a cycle) and the number of levels.
+int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
+                     hipStream_t s);
 
 }  // namespace gw

@@ -182,7 +182,8 @@ const char *const kNames[K_COUNT] = {
     "smooth_first_l0", "smooth_l0", "residual_l0", "restrict_l0", "prolong_l0",
     "smooth_first_l1", "smooth_l1", "residual_l1", "restrict_l1", "prolong_l1",
     "smooth_first_lc", "smooth_lc", "residual_lc", "restrict_lc", "prolong_lc", "coarse_solve",
-    "krylov_spmv", "krylov_update", "krylov_dot", "true_residual"};
+    "krylov_spmv", "krylov_update", "krylov_dot", "true_residual",
+    "sweep_lists", "sweep"};
 
 hipEvent_t take_event(ProfState &P) {
     if (!P.spare.empty()) {

@@ -1,0 +1,259 @@
+// Direct solution of the upwind travel-time system by one sweep in flow
+// order.  Each row of the advective upwind matrix couples cell i only to its
+// inflow neighbours, and water flows from higher to lower head (Darcy's law),
+// so the system is triangular in the order of decreasing head: every cell can
+// be solved exactly as soon as its inflow neighbours are (the Results find a
+// direct method best for the transport equations; Eq. 1 for the system).
+//
+// The sweep is level-synchronous (Kahn's topological order): a frontier of
+// cells whose inflow neighbours are all solved is solved at once, each cell
+// then counts down its downstream neighbours, and those reaching zero form
+// the next frontier.  Frontiers are small (about a thousand cells on a 1M-cell
+// field, over more than a thousand levels), so the sweep runs in one
+// workgroup, with a barrier between levels instead of a kernel launch.  A cell
+// is solved with the operations of the sequential sweep in decreasing-head
+// order, in the same order: the result equals it bit for bit.
+#include <algorithm>
+
+#include "gw_device.h"
+#include "gw_internal.h"
+
+namespace gw {
+
+namespace {
+
+// Inflow count of each row (off-diagonal entries) and, per column, the number
+// of rows it feeds.
+__global__ void k_sw_count(CsrView A, int32_t *__restrict__ indeg, int32_t *__restrict__ dcnt) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int32_t c = 0;
+    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+        const int32_t j = A.col[p];
+        if (j == (int32_t)i) continue;
+        ++c;
+        atomicAdd(&dcnt[j + 1], 1);
+    }
+    indeg[i] = c;
+}
+
+// Downstream lists: for each column j, the rows i with an entry (i, j).
+__global__ void k_sw_fill(CsrView A, const int32_t *__restrict__ drow, int32_t *__restrict__ dfill,
+                          int32_t *__restrict__ dcol) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+        const int32_t j = A.col[p];
+        if (j == (int32_t)i) continue;
+        dcol[drow[j] + atomicAdd(&dfill[j], 1)] = (int32_t)i;
+    }
+}
+
+__global__ void k_sw_flag(int64_t n, const int32_t *__restrict__ indeg, int32_t *__restrict__ flag) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = indeg[i] == 0 ? 1 : 0;
+}
+
+// Cells without inflow, in ascending order: the first frontier.
+__global__ void k_sw_first(int64_t n, const int32_t *__restrict__ flag, int32_t *__restrict__ q) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t before = i > 0 ? flag[i - 1] : 0;  // inclusive scan of the flags
+    if (flag[i] != before) q[before] = (int32_t)i;
+}
+
+constexpr int kSweepThreads = 1024;
+constexpr int kQueueLds = 6144;  // frontier entries kept in LDS per buffer
+constexpr int kRowFast = 7;      // rows and downstream lists up to this length (a 7-point stencil): one batch of loads
+
+// x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii for the nrhs systems, with the
+// off-diagonal terms subtracted in the row's order.
+__device__ __forceinline__ void solve_row_slow(const CsrView &A, int32_t i, int32_t p0, int32_t p1, int32_t nrhs,
+                                               const double *__restrict__ b, double *x) {
+    const int64_t n = A.n;
+    for (int32_t k = 0; k < nrhs; ++k) {
+        double s = b[k * n + i], d = 0.0;
+        for (int32_t p = p0; p < p1; ++p) {
+            const int32_t j = A.col[p];
+            if (j == i) d = A.val[p];
+            else s = s - A.val[p] * x[k * n + j];
+        }
+        x[k * n + i] = s / d;
+    }
+}
+
+// The same for a row of at most kRowFast entries whose column indices and
+// values are already in registers (padding entries repeat the last one): the
+// inflow values of two systems at a time are fetched in one batch of
+// independent loads before the ordered arithmetic.
+__device__ __forceinline__ void solve_row_fast(int64_t n, int32_t i, const int32_t (&cj)[kRowFast],
+                                               const double (&cv)[kRowFast], int32_t len, int32_t nrhs,
+                                               const double *__restrict__ b, double *x) {
+    // the diagonal entry, and which entries are inflow terms (selects, not
+    // branches: a term outside the row is computed and dropped)
+    double d = 0.0;
+    bool use[kRowFast];
+#pragma unroll
+    for (int e = 0; e < kRowFast; ++e) {
+        const bool in_row = e < len;
+        d = (in_row && cj[e] == i) ? cv[e] : d;
+        use[e] = in_row && cj[e] != i;
+    }
+    int32_t k = 0;
+    for (; k + 1 < nrhs; k += 2) {
+        const double *x0 = x + k * n, *x1 = x0 + n;
+        double s0 = b[k * n + i], s1 = b[(k + 1) * n + i];
+        double v0[kRowFast], v1[kRowFast];
+#pragma unroll
+        for (int e = 0; e < kRowFast; ++e) {
+            v0[e] = x0[cj[e]];
+            v1[e] = x1[cj[e]];
+        }
+#pragma unroll
+        for (int e = 0; e < kRowFast; ++e) {
+            const double t0 = s0 - cv[e] * v0[e], t1 = s1 - cv[e] * v1[e];
+            s0 = use[e] ? t0 : s0;
+            s1 = use[e] ? t1 : s1;
+        }
+        x[k * n + i] = s0 / d;
+        x[(k + 1) * n + i] = s1 / d;
+    }
+    if (k < nrhs) {
+        const double *x0 = x + k * n;
+        double s0 = b[k * n + i];
+        double v0[kRowFast];
+#pragma unroll
+        for (int e = 0; e < kRowFast; ++e) v0[e] = x0[cj[e]];
+#pragma unroll
+        for (int e = 0; e < kRowFast; ++e) {
+            const double t0 = s0 - cv[e] * v0[e];
+            s0 = use[e] ? t0 : s0;
+        }
+        x[k * n + i] = s0 / d;
+    }
+}
+
+// The whole sweep in one workgroup.  x, b: nrhs systems of n values each;
+// out[0] holds the size of the first frontier (in qg0) on entry, the number
+// of cells solved on exit, and out[1] the number of levels.
+//
+// Every level solves its frontier and counts down the downstream cells; those
+// reaching zero are appended to the next frontier, whose first kQueueLds
+// entries live in LDS and the rest in qg0/qg1.  One barrier per level: the
+// append counters rotate over three slots, so a counter is cleared two levels
+// after it was last read and one level before it is next used.  The loop
+// ends with an empty frontier: all cells solved, or the rest lies downstream
+// of a cycle of the inflow graph (then fewer than n cells are counted).
+__global__ void __launch_bounds__(kSweepThreads) k_sweep(CsrView A, int32_t *__restrict__ indeg,
+                                                         const int32_t *__restrict__ drow,
+                                                         const int32_t *__restrict__ dcol, int32_t nrhs,
+                                                         const double *__restrict__ b, double *x, int32_t *qg0,
+                                                         int32_t *qg1, int64_t *out) {
+    __shared__ int32_t lq[2][kQueueLds];
+    __shared__ int32_t cnt[3];
+    const int64_t n = A.n;
+    const int32_t first = (int32_t)out[0];
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    for (int32_t t = threadIdx.x; t < first && t < kQueueLds; t += blockDim.x) lq[0][t] = qg0[t];
+    __syncthreads();
+    int32_t size = first, lev = 0;
+    int64_t total = 0;
+    while (size > 0) {
+        const int cb = lev & 1, nb = cb ^ 1;
+        const int32_t *gcur = cb ? qg1 : qg0;
+        int32_t *gnxt = cb ? qg0 : qg1;
+        int32_t *app = &cnt[lev % 3];
+        if (threadIdx.x == 0) cnt[(lev + 1) % 3] = 0;
+        for (int32_t t = threadIdx.x; t < size; t += blockDim.x) {
+            const int32_t i = t < kQueueLds ? lq[cb][t] : gcur[t];
+            const int32_t p0 = A.rowptr[i], p1 = A.rowptr[i + 1];
+            const int32_t d0 = drow[i], d1 = drow[i + 1];
+            const int32_t len = p1 - p0, dl = d1 - d0;
+            if (len > 0 && len <= kRowFast && dl <= kRowFast) {
+                // one batch: the row, the downstream cells; then the count-downs
+                // (a padding lane decrements this thread's own spare counter)
+                // and the inflow values, all in flight together
+                int32_t cj[kRowFast], dj[kRowFast], last[kRowFast];
+                double cv[kRowFast];
+#pragma unroll
+                for (int e = 0; e < kRowFast; ++e) {
+                    const int32_t p = p0 + (e < len ? e : len - 1);
+                    cj[e] = A.col[p];
+                    cv[e] = A.val[p];
+                    dj[e] = dcol[dl > 0 ? d0 + (e < dl ? e : dl - 1) : 0];
+                }
+                const int64_t spare = n + threadIdx.x;
+#pragma unroll
+                for (int e = 0; e < kRowFast; ++e) last[e] = atomicSub(&indeg[e < dl ? (int64_t)dj[e] : spare], 1);
+                solve_row_fast(n, i, cj, cv, len, nrhs, b, x);
+#pragma unroll
+                for (int e = 0; e < kRowFast; ++e) {
+                    if (e < dl && last[e] == 1) {
+                        const int32_t pos = atomicAdd(app, 1);
+                        if (pos < kQueueLds) lq[nb][pos] = dj[e];
+                        else gnxt[pos] = dj[e];
+                    }
+                }
+            } else {
+                solve_row_slow(A, i, p0, p1, nrhs, b, x);
+                for (int32_t q = d0; q < d1; ++q) {
+                    const int32_t k2 = dcol[q];
+                    if (atomicSub(&indeg[k2], 1) == 1) {
+                        const int32_t pos = atomicAdd(app, 1);
+                        if (pos < kQueueLds) lq[nb][pos] = k2;
+                        else gnxt[pos] = k2;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        total += size;
+        size = *app;
+        ++lev;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = total;
+        out[1] = lev;
+    }
+}
+
+}  // namespace
+
+int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
+                     hipStream_t s) {
+    const int64_t n = A.n;
+    // indeg: one count-down per cell, then one spare counter per sweep thread
+    DBuf<int32_t> indeg((size_t)n + kSweepThreads), drow((size_t)n + 1), dfill(n), flag(n), q0(n), q1(n);
+    DBuf<int32_t> dcol((size_t)std::max<int64_t>(A.nnz - n, 1));
+    DBuf<int64_t> total(1), out(2);
+    {
+        // rows read twice (count, fill), lists written, frontier flags
+        ProfScope ps(K_SWEEP_LISTS, 2.0 * ((double)(n + 1) * 4 + (double)A.nnz * 4) + (double)A.nnz * 8 + n * 24.0,
+                     s);
+        fill_i32(drow.p, 0, n + 1, s);
+        fill_i32(dfill.p, 0, n, s);
+        fill_i32(indeg.p + n, INT32_MAX, kSweepThreads, s);
+        hipLaunchKernelGGL(k_sw_count, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, indeg.p, drow.p);
+        scan_inclusive_i32(drow.p + 1, n, total.p, s);
+        hipLaunchKernelGGL(k_sw_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, drow.p, dfill.p, dcol.p);
+        hipLaunchKernelGGL(k_sw_flag, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, indeg.p, flag.p);
+        scan_inclusive_i32(flag.p, n, out.p, s);
+        hipLaunchKernelGGL(k_sw_first, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, flag.p, q0.p);
+        GW_HIP(hipGetLastError());
+    }
+    {
+        // the operator, the right-hand sides and the solution once each
+        ProfScope ps(K_SWEEP, (double)(n + 1) * 4 + (double)A.nnz * 12 + (double)n * nrhs * 16, s);
+        hipLaunchKernelGGL(k_sweep, dim3(1), dim3(kSweepThreads), 0, s, A, indeg.p, drow.p, dcol.p, nrhs, b, x,
+                           q0.p, q1.p, out.p);
+        GW_HIP(hipGetLastError());
+    }
+    int64_t *stage = static_cast<int64_t *>(host_stage());
+    GW_HIP(hipMemcpyAsync(stage, out.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GW_HIP(hipStreamSynchronize(s));
+    if (levels) *levels = (int32_t)stage[1];
+    return stage[0];
+}
+
+}  // namespace gw

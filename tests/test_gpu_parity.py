@@ -332,6 +332,13 @@ def test_full_size_travel_time_parity(gw, ref):
     err_ex = np.linalg.norm(host(tau) - tau_ex) / np.linalg.norm(tau_ex)
     _say(f"  tau vs exact sweep {err_ex:.2e}")
     assert err_ex < 1e-6
+    # the direct sweep reproduces the oracle's exact solution bit for bit
+    c_ex = ref.tt_sweep(tr.A, tr.b_c, fr.h)
+    tau_d = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    c_d = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+    lev = gw.tt_solve_direct(g, dev(qx), dev(qy), dev(qz), p.phi, zone, tau_d, c_d)
+    _say(f"  direct sweep: {lev} levels")
+    assert np.array_equal(host(tau_d), tau_ex) and np.array_equal(host(c_d), c_ex)
 
 
 def test_full_size_flow_parity(gw, ref):
