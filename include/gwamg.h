@@ -264,6 +264,24 @@ int tt_sweep(const gw_csr *A, int32_t nrhs, const double *b, double *x, int32_t 
 int tt_solve_direct(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
                     const gw_zone *zone, double *tau, double *c, int32_t *n_levels, void *stream);
 
+/* The full dual delineation (Introduction: N_i + N_p + 2 steady advection
+ * equations; Eq. 1 and its reversed-flow form), each field exact by the
+ * sweep.  Forward, on q: the travel time tau_f, then one indicator per
+ * source, i.e. each zone of the x = 0 face (right-hand side: the inflow
+ * through that face) and each injection well (q < 0).  Backward, on -q: the
+ * travel time tau_b to an outlet, then the capture indicator of each
+ * production well (q > 0).  A well bounds the system in which water crosses
+ * it inwards: it adds |q| to its cell's diagonal (a cell without face inflow
+ * becoming a regular row with b_tau = phi V) and gives its indicator the
+ * right-hand side |q| at that cell; wells are applied in list order.
+ * zones [host] nzones; wells [host] nwells <= 64; out [device]
+ * (2 + nzones + n_injection + n_production) blocks of n values, in the order
+ * above (forward blocks first); n_levels [host] 2 entries or NULL.  At most
+ * 64 fields per direction.  BREAKDOWN if a system is not an upwind one. */
+int tt_delineate(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+                 const gw_zone *zones, int32_t nzones, const gw_well *wells, int32_t nwells, double *out,
+                 int32_t n_levels[2], void *stream);
+
 /* ---- kernel timing (HIP events around launches, for roofline reports) --- */
 
 typedef struct {

@@ -5,7 +5,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 the HIP path and the oracle share no code, headers or helpers.
 
 The arithmetic lives in ``gwref.c`` (plain loops, FP64, compiled with
-``-ffp-contract=off``); this module only marshals numpy arrays through ctypes.
+``-ffp-contract=off``); this module marshals numpy arrays through ctypes, and
+adds the well terms and indicator right-hand sides of the dual delineation
+(a handful of additions, in plain numpy, at the end of this file).
 """
 from __future__ import annotations
 
@@ -400,3 +402,71 @@ def solve_travel_time(grid, qx, qy, qz, phi: float, params: AmgParams = AmgParam
     tau, i1 = bicgstab(H, bt, rtol, maxiter)
     c, i2 = bicgstab(H, bc, rtol, maxiter)
     return TravelTimeResult(A, bt, bc, tau, c, [i1, i2], nid, H)
+
+
+# --------------------------------------------------------------------------
+# Dual delineation: the full set of steady advection problems
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Delineation:
+    forward: np.ndarray    # [1 + n_sources, n]: tau_f, then one indicator per source
+    backward: np.ndarray   # [1 + n_production, n]: tau_b, then one capture indicator per well
+    A_forward: Csr
+    A_backward: Csr
+    rhs_forward: List[np.ndarray]
+    rhs_backward: List[np.ndarray]
+
+
+def _well_terms(grid, A: Csr, bt: np.ndarray, phi: float, wells) -> List[np.ndarray]:
+    """Wells that bound this system, in list order: each adds its rate |q| to
+    the outflow balance of its cell (the diagonal) and gives an indicator
+    right-hand side |q| at that cell.  A cell without face inflow was
+    assembled as an identity row; its first well turns it into a regular row
+    (diagonal 0 + |q|, b_tau = phi V).  A and bt are modified in place."""
+    phi_v = phi * ((grid.dx * grid.dy) * grid.dz)
+    rhs = []
+    for w in wells:
+        c = w.ix + grid.nx * (w.iy + grid.ny * w.iz)
+        lo, hi = int(A.rowptr[c]), int(A.rowptr[c + 1])
+        p = lo + int(np.nonzero(A.col[lo:hi] == c)[0][0])
+        if bt[c] == 0.0:
+            A.val[p] = 0.0
+            bt[c] = phi_v
+        A.val[p] = A.val[p] + abs(w.q)
+        b = np.zeros(grid.n)
+        b[c] = abs(w.q)
+        rhs.append(b)
+    return rhs
+
+
+def dual_delineation(grid, qx, qy, qz, phi: float, h: np.ndarray, zones: Sequence[Sequence[int]],
+                     wells: Sequence) -> Delineation:
+    """The steady advection problems of the dual delineation (Introduction;
+    Eq. 1 and its reversed-flow counterpart), each solved exactly by the sweep.
+
+    Forward, on the flow field q: the travel time tau_f (zero where water
+    enters) and one indicator per source: each zone (j0, j1, k0, k1) of the
+    x = 0 face, whose right-hand side is the inflow through that face, then
+    each injection well (q < 0).  Backward, on the reversed field -q: the
+    travel time tau_b to an outlet (life expectancy, zero where water leaves)
+    and the capture indicator of each production well (q > 0).  A well is a
+    boundary of the system in which water crosses it inwards: injection wells
+    of the forward one, production wells of the backward one.
+    """
+    inj = [w for w in wells if w.q < 0]
+    prod = [w for w in wells if w.q > 0]
+    Af, btf, _, _ = tt_assemble(grid, qx, qy, qz, phi)
+    west = qx.reshape(grid.nz, grid.ny, grid.nx + 1)[:, :, 0]
+    west_in = np.where(west > 0.0, west, 0.0)
+    rhs_f = [btf]
+    for (j0, j1, k0, k1) in zones:
+        b = np.zeros((grid.nz, grid.ny, grid.nx))
+        b[k0:k1, j0:j1, 0] = west_in[k0:k1, j0:j1]
+        rhs_f.append(b.reshape(-1))
+    rhs_f += _well_terms(grid, Af, btf, phi, inj)
+    Ab, btb, _, _ = tt_assemble(grid, -qx, -qy, -qz, phi)
+    rhs_b = [btb] + _well_terms(grid, Ab, btb, phi, prod)
+    fwd = np.stack([tt_sweep(Af, b, h) for b in rhs_f])
+    bwd = np.stack([tt_sweep(Ab, b, -h) for b in rhs_b])
+    return Delineation(fwd, bwd, Af, Ab, rhs_f, rhs_b)

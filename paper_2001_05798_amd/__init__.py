@@ -134,6 +134,8 @@ def _load():
         "tt_sweep": (C.c_int, [C.POINTER(GwCsr), i32, vp, vp, C.POINTER(i32), vp]),
         "tt_solve_direct": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), vp, vp,
                                       C.POINTER(i32), vp]),
+        "tt_delineate": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, vp, i32, vp, i32, vp, C.POINTER(i32),
+                                   vp]),
         "gw_prof_enable": (C.c_int, [i32]),
         "gw_prof_read": (C.c_int, [C.POINTER(KernelStatC), i32, C.POINTER(i32)]),
         "gw_prof_select": (C.c_int, [C.c_char_p]),
@@ -331,6 +333,28 @@ def tt_solve_direct(grid, qx, qy, qz, phi: float, zone, tau, c, stream=None) -> 
     return int(lev.value)
 
 
+def delineation_fields(zones: Sequence, wells: Sequence) -> Tuple[int, int]:
+    """Number of forward and backward fields tt_delineate writes."""
+    return (1 + len(zones) + sum(w.q < 0 for w in wells), 1 + sum(w.q > 0 for w in wells))
+
+
+def tt_delineate(grid, qx, qy, qz, phi: float, zones: Sequence, wells: Sequence, out,
+                 stream=None) -> Tuple[int, int]:
+    """The dual delineation's fields by the upwind sweep into out (forward
+    fields, then backward ones; see delineation_fields).  Returns the number
+    of dependency levels of the forward and backward systems."""
+    import torch
+    g = grid_c(grid)
+    nf, nb = delineation_fields(zones, wells)
+    _expect(out, torch.float64, (nf + nb) * g.nx * g.ny * g.nz, "out")
+    zl = (GwZone * max(1, len(zones)))(*[GwZone(*z) for z in zones])
+    wl = (GwWell * max(1, len(wells)))(*[GwWell(w.ix, w.iy, w.iz, w.q) for w in wells])
+    lev = (C.c_int32 * 2)()
+    _check(_lib.tt_delineate(C.byref(g), _ptr(qx), _ptr(qy), _ptr(qz), float(phi), C.addressof(zl), len(zones),
+                             C.addressof(wl), len(wells), _ptr(out), lev, _stream(stream)))
+    return int(lev[0]), int(lev[1])
+
+
 # ---------------------------------------------------------------- AMG ----
 @dataclasses.dataclass
 class LevelInfo:
@@ -358,7 +382,7 @@ class Hierarchy:
         h = getattr(self, "_h", None)
         if h is not None and h.value:
             self._free(h)
-            self._h = C.c_void_p(0)
+            self._h = None
 
     @property
     def handle(self):
@@ -486,7 +510,7 @@ class Queue:
         q = getattr(self, "_q", None)
         if q is not None and q.value:
             self._destroy(q)
-            self._q = C.c_void_p(0)
+            self._q = None
         self._keep = {}
 
     def clock(self) -> float:

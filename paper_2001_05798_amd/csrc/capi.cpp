@@ -448,4 +448,46 @@ int tt_solve_direct(const gw_grid *grid, const double *qx, const double *qy, con
     });
 }
 
+int tt_delineate(const gw_grid *grid, const double *qx, const double *qy, const double *qz, double phi,
+                 const gw_zone *zones, int32_t nzones, const gw_well *wells, int32_t nwells, double *out,
+                 int32_t n_levels[2], void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(qx && qy && qz && out, "tt_delineate: null pointer");
+        GW_REQUIRE(std::isfinite(phi) && phi > 0, "tt_delineate: porosity must be positive");
+        GW_REQUIRE(nzones >= 0 && (nzones == 0 || zones), "tt_delineate: bad zone list");
+        GW_REQUIRE(nwells >= 0 && nwells <= 64 && (nwells == 0 || wells), "tt_delineate: at most 64 wells");
+        int32_t n_inj = 0, n_prod = 0;
+        for (int32_t z = 0; z < nzones; ++z) {
+            const gw_zone &Z = zones[z];
+            GW_REQUIRE(Z.j0 >= 0 && Z.j0 <= Z.j1 && Z.j1 <= grid->ny && Z.k0 >= 0 && Z.k0 <= Z.k1 &&
+                           Z.k1 <= grid->nz,
+                       "tt_delineate: zone outside the x = 0 face");
+        }
+        for (int32_t k = 0; k < nwells; ++k) {
+            const gw_well &w = wells[k];
+            GW_REQUIRE(w.ix >= 0 && w.ix < grid->nx && w.iy >= 0 && w.iy < grid->ny && w.iz >= 0 &&
+                           w.iz < grid->nz && std::isfinite(w.q),
+                       "tt_delineate: well outside the grid or rate not finite");
+            n_inj += w.q < 0;
+            n_prod += w.q > 0;
+        }
+        GW_REQUIRE(1 + nzones + n_inj <= 64 && 1 + n_prod <= 64, "tt_delineate: at most 64 fields per direction");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+        Csr A;
+        A.alloc((int32_t)n, (int32_t)n, nnz7(grid));
+        int32_t lev[2] = {0, 0};
+        int64_t solved[2] = {0, 0};
+        delineate(*grid, qx, qy, qz, phi, zones, nzones, wells, nwells, A, out, lev, solved, s);
+        finish(s);
+        if (n_levels) {
+            n_levels[0] = lev[0];
+            n_levels[1] = lev[1];
+        }
+        if (solved[0] != n || solved[1] != n) fail(GW_BREAKDOWN, "tt_delineate: the inflow graph has a cycle");
+        return GW_OK;
+    });
+}
+
 }  // extern "C"

@@ -325,5 +325,12 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
 // A.n when the inflow graph has a cycle) and the number of levels.
 int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
                      hipStream_t s);
+// The forward and backward systems of the dual delineation, assembled into A
+// (capacity: the 7-point bound) and swept into out: forward blocks (tau_f,
+// one per zone, one per injection well), then backward blocks (tau_b, one per
+// production well).  levels/solved per direction.
+void delineate(const gw_grid &g, const double *qx, const double *qy, const double *qz, double phi,
+               const gw_zone *zones, int32_t nzones, const gw_well *wells, int32_t nwells, Csr &A, double *out,
+               int32_t levels[2], int64_t solved[2], hipStream_t s);
 
 }  // namespace gw

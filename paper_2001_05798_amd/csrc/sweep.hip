@@ -218,6 +218,63 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(CsrView A, int32_t *__r
     }
 }
 
+
+// ---------------------------------------------------- dual delineation --
+
+constexpr int kMaxSweepWells = 64;
+
+// A CSR whose values the well terms modify in place.
+struct CsrViewMut {
+    int32_t n;
+    const int32_t *rowptr, *col;
+    double *val;
+};
+
+__global__ void k_negate(const double *__restrict__ a, double *__restrict__ out, int64_t m) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) out[i] = -a[i];
+}
+
+// Indicator right-hand side of one zone of the x = 0 face: the inflow through
+// the face, for the face cells inside the zone (the other entries are zero
+// already).  One thread per cell of the face.
+__global__ void k_zone_rhs(int32_t nx, int32_t ny, int32_t nz, const double *__restrict__ qx, gw_zone z,
+                           double *__restrict__ b) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ny * nz) return;
+    const int32_t j = (int32_t)(t % ny), k = (int32_t)(t / ny);
+    if (j < z.j0 || j >= z.j1 || k < z.k0 || k >= z.k1) return;
+    const double q = qx[(int64_t)(nx + 1) * (j + (int64_t)ny * k)];
+    b[(int64_t)nx * (j + (int64_t)ny * k)] = q > 0.0 ? q : 0.0;
+}
+
+struct WellTerms {
+    int32_t n;
+    int64_t cell[kMaxSweepWells];
+    double rate[kMaxSweepWells];   // |q|
+    int32_t block[kMaxSweepWells]; // right-hand side that receives |q| at the cell
+};
+
+// Wells that bound the system, in list order (one thread: repeated additions
+// on one cell are ordered): each adds |q| to its cell's diagonal; a cell that
+// was assembled as an identity row (b_tau = 0) first becomes a regular row
+// with diagonal 0 and b_tau = phi V.
+__global__ void k_well_terms(CsrViewMut A, double *bt, double phi_v, WellTerms w, double *rhs) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const int64_t n = A.n;
+    for (int32_t k = 0; k < w.n; ++k) {
+        const int64_t c = w.cell[k];
+        int32_t p = A.rowptr[c];
+        while (p + 1 < A.rowptr[c + 1] && A.col[p] != (int32_t)c) ++p;
+        if (bt[c] == 0.0) {
+            A.val[p] = 0.0;
+            bt[c] = phi_v;
+        }
+        A.val[p] = A.val[p] + w.rate[k];
+        rhs[w.block[k] * n + c] = w.rate[k];
+    }
+}
+
 }  // namespace
 
 int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
@@ -254,6 +311,72 @@ int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x,
     GW_HIP(hipStreamSynchronize(s));
     if (levels) *levels = (int32_t)stage[1];
     return stage[0];
+}
+
+void delineate(const gw_grid &g, const double *qx, const double *qy, const double *qz, double phi,
+               const gw_zone *zones, int32_t nzones, const gw_well *wells, int32_t nwells, Csr &A, double *out,
+               int32_t levels[2], int64_t solved[2], hipStream_t s) {
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const double phi_v = phi * ((g.dx * g.dy) * g.dz);
+    WellTerms inj{}, prod{};
+    int32_t n_inj = 0, n_prod = 0;
+    for (int32_t k = 0; k < nwells; ++k) {
+        const gw_well &w = wells[k];
+        const int64_t c = w.ix + (int64_t)g.nx * (w.iy + (int64_t)g.ny * w.iz);
+        if (w.q < 0) {
+            inj.cell[inj.n] = c;
+            inj.rate[inj.n] = -w.q;
+            inj.block[inj.n] = 1 + nzones + n_inj++;
+            ++inj.n;
+        } else if (w.q > 0) {
+            prod.cell[prod.n] = c;
+            prod.rate[prod.n] = w.q;
+            prod.block[prod.n] = 1 + n_prod++;
+            ++prod.n;
+        }
+    }
+    const int32_t nf = 1 + nzones + n_inj, nb = 1 + n_prod;
+    const int64_t fluxes[3] = {(int64_t)(g.nx + 1) * g.ny * g.nz, (int64_t)g.nx * (g.ny + 1) * g.nz,
+                               (int64_t)g.nx * g.ny * (g.nz + 1)};
+    DBuf<double> rhs((size_t)n * std::max(nf, nb)), scratch(n);
+    DBuf<int64_t> nnz(1);
+    DBuf<int32_t> nid(1);
+    for (int dir = 0; dir < 2; ++dir) {
+        const double *q[3] = {qx, qy, qz};
+        DBuf<double> rq[3];
+        if (dir == 1) {
+            for (int a = 0; a < 3; ++a) {
+                rq[a].alloc((size_t)fluxes[a]);
+                hipLaunchKernelGGL(k_negate, dim3(blocks_for(fluxes[a])), dim3(kBlock), 0, s, q[a], rq[a].p,
+                                   fluxes[a]);
+                q[a] = rq[a].p;
+            }
+        }
+        const int32_t nr = dir == 0 ? nf : nb;
+        fill_f64(rhs.p + n, 0.0, n * (nr - 1), s);
+        fill_i32(nid.p, 0, 1, s);
+        fill_i32(A.rowptr.p, 0, 1, s);
+        const gw_zone all{0, g.ny, 0, g.nz};
+        launch_tt_count(g, q[0], q[1], q[2], A.rowptr.p + 1, s);
+        scan_inclusive_i32(A.rowptr.p + 1, n, nnz.p, s);
+        launch_tt_fill(g, q[0], q[1], q[2], phi, all, A.rowptr.p, A.col.p, A.val.p, rhs.p, scratch.p, nid.p, s);
+        if (dir == 0) {
+            for (int32_t z = 0; z < nzones; ++z)
+                hipLaunchKernelGGL(k_zone_rhs, dim3(blocks_for((int64_t)g.ny * g.nz)), dim3(kBlock), 0, s, g.nx,
+                                   g.ny, g.nz, q[0], zones[z], rhs.p + (1 + z) * n);
+        }
+        const WellTerms &wt = dir == 0 ? inj : prod;
+        if (wt.n) {
+            const CsrViewMut M{(int32_t)n, A.rowptr.p, A.col.p, A.val.p};
+            hipLaunchKernelGGL(k_well_terms, dim3(1), dim3(64), 0, s, M, rhs.p, phi_v, wt, rhs.p);
+        }
+        GW_HIP(hipGetLastError());
+        int64_t *stage = static_cast<int64_t *>(host_stage());
+        GW_HIP(hipMemcpyAsync(stage, nnz.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        const CsrView V{(int32_t)n, (int32_t)n, stage[0], A.rowptr.p, A.col.p, A.val.p};
+        solved[dir] = upwind_sweep(V, nr, rhs.p, out + (dir == 0 ? 0 : nf * n), &levels[dir], s);
+    }
 }
 
 }  // namespace gw

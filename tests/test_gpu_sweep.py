@@ -148,3 +148,57 @@ def test_sweep_large_synthetic_heads(gw, ref):
     lev = gw.tt_solve_direct(g, dev(qx), dev(qy), dev(qz), p.phi, (0, g.ny, 0, g.nz // 2), tau, c)
     _say(f"  levels {lev}")
     assert np.array_equal(host(tau), want_t) and np.array_equal(host(c), want_c)
+
+
+def _wells_problem():
+    g = gi.Grid(24, 18, 6)
+    K = gi.lognormal_field((24, 18, 6), 2.0, 4.0, 31)
+    wells = [gi.Well(16, 5, 2, 2e-4), gi.Well(8, 12, 3, -1.5e-4), gi.Well(19, 13, 1, 1e-4),
+             gi.Well(19, 13, 1, 5e-5), gi.Well(3, 3, 0, 0.0)]
+    return gi.Problem(g, K, wells=wells)
+
+
+DELINEATION_CASES = [
+    ("24x18x6 zones + injection + 2 wells in one cell", _wells_problem,
+     [(0, 9, 0, 6), (9, 18, 0, 3), (9, 18, 3, 6)]),
+    ("32x24x12 lognormal, four pumping wells, no zones", lambda: gi.heterogeneous_aquifer(32, 24, 12, 4.0, 6, 4),
+     []),
+    ("2d 64x64 homogeneous, one zone", lambda: gi.homogeneous_slab(), [(0, 64, 0, 1)]),
+]
+
+
+@pytest.mark.parametrize("name,make,zones", DELINEATION_CASES, ids=[c[0] for c in DELINEATION_CASES])
+def test_delineation_bitwise(gw, ref, name, make, zones):
+    _say(f"tt_delineate {name}")
+    p = make()
+    g = p.grid
+    h = _heads(ref, p)
+    qx, qy, qz = ref.darcy_flux(p, h)
+    d = ref.dual_delineation(g, qx, qy, qz, p.phi, h, zones, p.wells)
+    nf, nb = gw.delineation_fields(zones, p.wells)
+    assert (nf, nb) == (d.forward.shape[0], d.backward.shape[0])
+    out = torch.full(((nf + nb) * g.n,), np.nan, dtype=torch.float64, device="cuda")
+    lf, lb = gw.tt_delineate(g, dev(qx), dev(qy), dev(qz), p.phi, zones, p.wells, out)
+    _say(f"  levels forward {lf} backward {lb}")
+    got = host(out).reshape(nf + nb, g.n)
+    for k in range(nf):
+        assert np.array_equal(got[k], d.forward[k]), ("forward", k)
+    for k in range(nb):
+        assert np.array_equal(got[nf + k], d.backward[k]), ("backward", k)
+
+
+def test_delineation_rejects_bad_input(gw):
+    _say("tt_delineate bad input")
+    g = gi.Grid(6, 5, 4)
+    q = [torch.zeros(m, dtype=torch.float64, device="cuda") for m in (7 * 5 * 4, 6 * 6 * 4, 6 * 5 * 5)]
+    out = torch.zeros(2 * g.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(gw.GwError) as e:
+        gw.tt_delineate(g, *q, 0.25, [(0, 9, 0, 1)], [], torch.zeros(3 * g.n, dtype=torch.float64, device="cuda"))
+    assert e.value.status == gw.EINVAL
+    with pytest.raises(gw.GwError) as e:
+        gw.tt_delineate(g, *q, 0.25, [], [gi.Well(6, 0, 0, 1.0)], torch.zeros(3 * g.n, dtype=torch.float64,
+                                                                                 device="cuda"))
+    assert e.value.status == gw.EINVAL
+    # no flow at all: every row is an identity row, every field is zero
+    gw.tt_delineate(g, *q, 0.25, [], [], out)
+    assert not host(out).any()
