@@ -405,6 +405,18 @@ def main():
         gw.tt_solve_direct(g, pipe.qx, pipe.qy, pipe.qz, prob.phi, pipe.zone, tau_d, c_d)
         ds = gw.prof_read()
         gw.prof_enable(False)
+        # the full dual delineation of this field: forward travel time and the
+        # source zone's indicator, backward travel time and one capture field
+        # per pumping well
+        nf, nb = gw.delineation_fields([pipe.zone], prob.wells)
+        dout = torch.empty((nf + nb) * g.n, dtype=torch.float64, device="cuda")
+        gw.tt_delineate(g, pipe.qx, pipe.qy, pipe.qz, prob.phi, [pipe.zone], prob.wells, dout)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dlev = gw.tt_delineate(g, pipe.qx, pipe.qy, pipe.qz, prob.phi, [pipe.zone], prob.wells, dout)
+        torch.cuda.synchronize()
+        deli_ms = 1e3 * (time.perf_counter() - t1)
+        del dout
         bd = [statistics.median(x) for x in zip(*parts)]
         amg_tt = bd[2] + bd[3]
         dmed = statistics.median(dms)
@@ -414,6 +426,7 @@ def main():
                   "amg_pair_ms": round(amg_tt, 3), "speedup_vs_amg_pair": round(amg_tt / dmed, 2),
                   "tau_rel_diff_vs_amg": float(torch.linalg.norm(tau_d - pipe.tau) / torch.linalg.norm(tau_d)),
                   "c_rel_diff_vs_amg": float(torch.linalg.norm(c_d - pipe.c) / torch.linalg.norm(c_d)),
+                  "delineation": {"fields": [nf, nb], "levels": list(dlev), "ms": round(deli_ms, 3)},
                   "note": "tt_solve_direct (assemble + upwind sweep, 2 RHS), median of 5 calls; not in the timed step"}
         print(f"[bench] direct travel time: {direct}", file=sys.stderr, flush=True)
 

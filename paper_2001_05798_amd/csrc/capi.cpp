@@ -438,7 +438,7 @@ int tt_solve_direct(const gw_grid *grid, const double *qx, const double *qy, con
         if (rc != GW_OK) fail(rc, gw_last_error());
         const CsrView V{(int32_t)n, (int32_t)n, nnz, A.rowptr.p, A.col.p, A.val.p};
         int32_t lev = 0;
-        const int64_t solved = upwind_sweep(V, 2, b2.p, x2.p, &lev, s);
+        const int64_t solved = grid_sweep(*grid, V, 2, b2.p, x2.p, &lev, s);
         copy_bytes(tau, x2.p, sizeof(double) * (size_t)n, s);
         copy_bytes(c, x2.p + n, sizeof(double) * (size_t)n, s);
         finish(s);

@@ -325,6 +325,10 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
 // A.n when the inflow graph has a cycle) and the number of levels.
 int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
                      hipStream_t s);
+// The same for an upwind matrix on the 7-point grid g (rows of at most the
+// six face neighbours), through one 64-byte record per row.
+int64_t grid_sweep(const gw_grid &g, const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
+                   hipStream_t s);
 // The forward and backward systems of the dual delineation, assembled into A
 // (capacity: the 7-point bound) and swept into out: forward blocks (tau_f,
 // one per zone, one per injection well), then backward blocks (tau_b, one per

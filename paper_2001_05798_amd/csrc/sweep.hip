@@ -275,6 +275,176 @@ __global__ void k_well_terms(CsrViewMut A, double *bt, double phi_v, WellTerms w
     }
 }
 
+// ------------------------------------------------- sweep on a 7-point grid --
+// On a grid the neighbours of a cell are fixed offsets, so a row is stored as
+// one 64-byte record: the matrix entries of the six faces (zero where the face
+// brings no inflow), the diagonal, and two 6-bit masks: the faces with
+// inflow (the row's off-diagonal entries) and the faces with outflow (the
+// cells downstream).  The right-hand sides and solutions of a cell are
+// interleaved, so one load returns a neighbour's values of two systems.  A
+// sweep step then reads one record line, one value pair per inflow face, and
+// counts down the outflow faces: about a third of the memory requests of the
+// general sweep.
+
+struct alignas(64) GridRow {
+    double v[6];  // faces -z, -y, -x, +x, +y, +z: ascending column order
+    double diag;
+    int32_t in_mask, out_mask;
+};
+
+struct FaceOffsets {
+    int64_t d[6];
+};
+
+__device__ __forceinline__ FaceOffsets face_offsets(int32_t nx, int32_t ny) {
+    const int64_t sxy = (int64_t)nx * ny;
+    return {{-sxy, -(int64_t)nx, -1, 1, nx, sxy}};
+}
+
+// Records from an assembled upwind CSR (columns ascending): the face of an
+// entry is found from the cell coordinates, so grids with a dimension of one
+// cell (where two offsets coincide) are handled too.
+__global__ void k_grid_rows(CsrView A, int32_t nx, int32_t ny, GridRow *__restrict__ rows,
+                            int32_t *__restrict__ indeg) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= A.n) return;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int32_t i = (int32_t)(c % nx), j = (int32_t)((c / nx) % ny), k = (int32_t)(c / sxy);
+    GridRow r;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) r.v[f] = 0.0;
+    r.diag = 0.0;
+    r.in_mask = 0;
+    r.out_mask = 0;
+    for (int32_t p = A.rowptr[c]; p < A.rowptr[c + 1]; ++p) {
+        const int64_t col = A.col[p];
+        if (col == c) {
+            r.diag = A.val[p];
+            continue;
+        }
+        const int32_t ci = (int32_t)(col % nx), cj = (int32_t)((col / nx) % ny), ck = (int32_t)(col / sxy);
+        int f;
+        if (ck != k) f = ck < k ? 0 : 5;
+        else if (cj != j) f = cj < j ? 1 : 4;
+        else f = ci < i ? 2 : 3;
+        r.v[f] = A.val[p];
+        r.in_mask |= 1 << f;
+    }
+    rows[c] = r;
+    indeg[c] = __popc(r.in_mask);
+}
+
+// Outflow faces: face f of cell c feeds its neighbour when the neighbour's
+// opposite face (5 - f) is an inflow face.
+__global__ void k_grid_out(int64_t n, int32_t nx, int32_t ny, GridRow *__restrict__ rows) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int64_t sxy = (int64_t)nx * ny;
+    const int32_t nz = (int32_t)(n / sxy);
+    const int32_t i = (int32_t)(c % nx), j = (int32_t)((c / nx) % ny), k = (int32_t)(c / sxy);
+    const bool has[6] = {k > 0, j > 0, i > 0, i < nx - 1, j < ny - 1, k < nz - 1};
+    const FaceOffsets o = face_offsets(nx, ny);
+    int32_t m = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+        if (has[f] && ((rows[c + o.d[f]].in_mask >> (5 - f)) & 1)) m |= 1 << f;
+    rows[c].out_mask = m;
+}
+
+// Right-hand sides from nrhs blocks of n values to nrp interleaved values per
+// cell (the padding system is zero), and solutions back.
+__global__ void k_interleave_rhs(int64_t n, int32_t nrhs, int32_t nrp, const double *__restrict__ b,
+                                 double *__restrict__ bi) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n * nrp) return;
+    const int64_t c = t / nrp;
+    const int32_t k = (int32_t)(t % nrp);
+    bi[t] = k < nrhs ? b[k * n + c] : 0.0;
+}
+
+__global__ void k_split_sol(int64_t n, int32_t nrhs, int32_t nrp, const double *__restrict__ xi,
+                            double *__restrict__ x) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= n * nrhs) return;
+    const int32_t k = (int32_t)(t / n);
+    const int64_t c = t % n;
+    x[t] = xi[c * nrp + k];
+}
+
+// The level-synchronous sweep of k_sweep on grid records; nrp (even) systems
+// interleaved per cell, solved two at a time with the same record.
+__global__ void __launch_bounds__(kSweepThreads) k_sweep_grid(int64_t n, int32_t nx, int32_t ny,
+                                                              const GridRow *__restrict__ rows,
+                                                              int32_t *__restrict__ indeg, int32_t nrp,
+                                                              const double *__restrict__ bi, double *xi,
+                                                              int32_t *qg0, int32_t *qg1, int64_t *out) {
+    __shared__ int32_t lq[2][kQueueLds];
+    __shared__ int32_t cnt[3];
+    const FaceOffsets o = face_offsets(nx, ny);
+    const int32_t first = (int32_t)out[0];
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    for (int32_t t = threadIdx.x; t < first && t < kQueueLds; t += blockDim.x) lq[0][t] = qg0[t];
+    __syncthreads();
+    int32_t size = first, lev = 0;
+    int64_t total = 0;
+    while (size > 0) {
+        const int cb = lev & 1, nb = cb ^ 1;
+        const int32_t *gcur = cb ? qg1 : qg0;
+        int32_t *gnxt = cb ? qg0 : qg1;
+        int32_t *app = &cnt[lev % 3];
+        if (threadIdx.x == 0) cnt[(lev + 1) % 3] = 0;
+        for (int32_t t = threadIdx.x; t < size; t += blockDim.x) {
+            const int64_t c = t < kQueueLds ? lq[cb][t] : gcur[t];
+            const GridRow r = rows[c];
+            // count-downs first: they do not wait for the solve.  All six are
+            // issued unconditionally, a face without outflow decrementing this
+            // thread's spare counter, so that none waits for another.
+            const int64_t spare = n + threadIdx.x;
+            int32_t last[6];
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+                last[f] = atomicSub(&indeg[(r.out_mask >> f) & 1 ? c + o.d[f] : spare], 1);
+            for (int32_t k = 0; k < nrp; k += 2) {
+                const double2 bb = *reinterpret_cast<const double2 *>(bi + c * nrp + k);
+                // only the inflow faces are fetched (masked lanes issue no request)
+                double2 xv[6];
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    xv[f] = make_double2(0.0, 0.0);
+                    if ((r.in_mask >> f) & 1) xv[f] = *reinterpret_cast<const double2 *>(xi + (c + o.d[f]) * nrp + k);
+                }
+                double s0 = bb.x, s1 = bb.y;
+#pragma unroll
+                for (int f = 0; f < 6; ++f) {
+                    const double t0 = s0 - r.v[f] * xv[f].x, t1 = s1 - r.v[f] * xv[f].y;
+                    const bool use = (r.in_mask >> f) & 1;
+                    s0 = use ? t0 : s0;
+                    s1 = use ? t1 : s1;
+                }
+                *reinterpret_cast<double2 *>(xi + c * nrp + k) = make_double2(s0 / r.diag, s1 / r.diag);
+            }
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                if (((r.out_mask >> f) & 1) && last[f] == 1) {
+                    const int32_t pos = atomicAdd(app, 1);
+                    const int32_t d = (int32_t)(c + o.d[f]);
+                    if (pos < kQueueLds) lq[nb][pos] = d;
+                    else gnxt[pos] = d;
+                }
+            }
+        }
+        __syncthreads();
+        total += size;
+        size = *app;
+        ++lev;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = total;
+        out[1] = lev;
+    }
+}
+
 }  // namespace
 
 int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
@@ -306,6 +476,44 @@ int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x,
                            q0.p, q1.p, out.p);
         GW_HIP(hipGetLastError());
     }
+    int64_t *stage = static_cast<int64_t *>(host_stage());
+    GW_HIP(hipMemcpyAsync(stage, out.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GW_HIP(hipStreamSynchronize(s));
+    if (levels) *levels = (int32_t)stage[1];
+    return stage[0];
+}
+
+int64_t grid_sweep(const gw_grid &g, const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
+                   hipStream_t s) {
+    const int64_t n = A.n;
+    const int32_t nrp = (nrhs + 1) & ~1;
+    DBuf<GridRow> rows(n);
+    // count-downs of the cells, then one spare counter per sweep thread
+    DBuf<int32_t> indeg((size_t)n + kSweepThreads), flag(n), q0(n), q1(n);
+    DBuf<double> bi((size_t)n * nrp), xi((size_t)n * nrp);
+    DBuf<int64_t> out(2);
+    {
+        // CSR read once, records written and read back, frontier flags
+        ProfScope ps(K_SWEEP_LISTS, (double)(n + 1) * 4 + (double)A.nnz * 12 + n * (64.0 * 3 + 16),
+                     s);
+        fill_i32(indeg.p + n, INT32_MAX, kSweepThreads, s);
+        hipLaunchKernelGGL(k_grid_rows, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, g.nx, g.ny, rows.p, indeg.p);
+        hipLaunchKernelGGL(k_grid_out, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, g.nx, g.ny, rows.p);
+        hipLaunchKernelGGL(k_sw_flag, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, indeg.p, flag.p);
+        scan_inclusive_i32(flag.p, n, out.p, s);
+        hipLaunchKernelGGL(k_sw_first, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, flag.p, q0.p);
+        hipLaunchKernelGGL(k_interleave_rhs, dim3(blocks_for(n * nrp)), dim3(kBlock), 0, s, n, nrhs, nrp, b,
+                           bi.p);
+        GW_HIP(hipGetLastError());
+    }
+    {
+        ProfScope ps(K_SWEEP, (double)n * (64.0 + 16.0 * nrp), s);
+        hipLaunchKernelGGL(k_sweep_grid, dim3(1), dim3(kSweepThreads), 0, s, n, g.nx, g.ny, rows.p, indeg.p, nrp,
+                           bi.p, xi.p, q0.p, q1.p, out.p);
+        GW_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_split_sol, dim3(blocks_for(n * nrhs)), dim3(kBlock), 0, s, n, nrhs, nrp, xi.p, x);
+    GW_HIP(hipGetLastError());
     int64_t *stage = static_cast<int64_t *>(host_stage());
     GW_HIP(hipMemcpyAsync(stage, out.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     GW_HIP(hipStreamSynchronize(s));
@@ -375,7 +583,7 @@ void delineate(const gw_grid &g, const double *qx, const double *qy, const doubl
         GW_HIP(hipMemcpyAsync(stage, nnz.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         GW_HIP(hipStreamSynchronize(s));
         const CsrView V{(int32_t)n, (int32_t)n, stage[0], A.rowptr.p, A.col.p, A.val.p};
-        solved[dir] = upwind_sweep(V, nr, rhs.p, out + (dir == 0 ? 0 : nf * n), &levels[dir], s);
+        solved[dir] = grid_sweep(g, V, nr, rhs.p, out + (dir == 0 ? 0 : nf * n), &levels[dir], s);
     }
 }
 
