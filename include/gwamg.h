@@ -219,6 +219,42 @@ int amg_coarse_export(const amg_hierarchy *H, double *lu, int32_t *piv, double *
 
 void amg_free(amg_hierarchy *H);
 
+/* ---- transient flow (Eq. 2) -------------------------------------------- */
+
+/* PCG on (A + diag(shift)) x = b, preconditioned by the V-cycle of H built
+ * for A: the setup of the conductance matrix kept for the fully implicit
+ * time steps of Eq. 2, whose matrix adds S_i V_i / dt to the diagonal.  The
+ * Discussion after Eq. 2 keeps it while S_i V_i / dt < delta C_ii for all i.
+ * shift, b, x [device] n.  Launched one kernel at a time (graph ignored). */
+int amg_solve_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b, double *x,
+                          const amg_solve_params *sp, amg_solve_info *info, void *stream);
+
+typedef struct {
+    int32_t status;       /* of the step's solve                          */
+    int32_t iters;
+    int32_t reused;       /* 1: setup of C kept (criterion met); 2: setup
+                             of C + S/dt of an earlier step with the same
+                             dt; 0: built for this step                    */
+    double ratio;         /* max_i S_i V_i / (dt C_ii)                     */
+    double rel_res_true;
+    double setup_ms;      /* setups done in this step (step 0: that of C)  */
+    double solve_ms;
+} gw_step_info;
+
+/* Fully implicit steps of Eq. 2 from h0: (C + S/dt_k) h^{k+1} =
+ * b + (S/dt_k) h^k, with C and b assembled as fv_assemble does (fixed-head
+ * faces and wells held constant) and S_i = Ss_i V_i.  The hierarchy of C
+ * serves every step with max_i S_i V_i / (dt_k C_ii) < delta (shifted PCG);
+ * other steps build a hierarchy of C + S/dt_k, kept while dt does not
+ * change.  K, Ss, h0 [device] n; dt [host] nsteps; h [device] n receives
+ * the last heads; h_steps [device] nsteps x n or NULL receives every step;
+ * info [host] nsteps or NULL.  Returns the worst step status (stops at a
+ * breakdown). */
+int flow_transient(const gw_grid *grid, const double *K, const gw_bc *bc, const gw_well *wells, int32_t nwells,
+                   const double *Ss, const double *h0, const double *dt, int32_t nsteps, double delta,
+                   const amg_params *params, const amg_solve_params *sp, double *h, double *h_steps,
+                   gw_step_info *info, void *stream);
+
 /* ---- travel time (Eq. 1) ------------------------------------------------ */
 
 /* Upper bound of the travel-time matrix nonzeros (= fv_nnz). */

@@ -72,6 +72,11 @@ class SolveInfoC(C.Structure):
                 ("solve_ms", C.c_double)]
 
 
+class StepInfoC(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("reused", C.c_int32), ("ratio", C.c_double),
+                ("rel_res_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
 class LevelInfoC(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nc", C.c_int32), ("nnz_p", C.c_int64),
                 ("nnz_s", C.c_int64), ("mis_rounds", C.c_int32), ("omega_p", C.c_double),
@@ -134,6 +139,10 @@ def _load():
         "tt_sweep": (C.c_int, [C.POINTER(GwCsr), i32, vp, vp, C.POINTER(i32), vp]),
         "tt_solve_direct": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), vp, vp,
                                       C.POINTER(i32), vp]),
+        "amg_solve_pcg_shifted": (C.c_int, [vp, vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "flow_transient": (C.c_int, [C.POINTER(GwGrid), vp, C.POINTER(GwBc), vp, i32, vp, vp, C.POINTER(f64), i32,
+                                     f64, C.POINTER(AmgParamsC), C.POINTER(SolveParamsC), vp, vp,
+                                     C.POINTER(StepInfoC), vp]),
         "tt_delineate": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, vp, i32, vp, i32, vp, C.POINTER(i32),
                                    vp]),
         "gw_prof_enable": (C.c_int, [i32]),
@@ -257,6 +266,17 @@ class SolveInfo:
     @staticmethod
     def of(c: SolveInfoC) -> "SolveInfo":
         return SolveInfo(c.iters, c.status, c.restarts, c.rel_res, c.rel_res_true, c.setup_ms, c.solve_ms)
+
+
+@dataclasses.dataclass
+class StepInfo:
+    status: int
+    iters: int
+    reused: int      # 1 setup of C kept, 2 setup of an earlier equal step, 0 built
+    ratio: float     # max_i S_i V_i / (dt C_ii)
+    rel_res_true: float
+    setup_ms: float
+    solve_ms: float
 
 
 # ----------------------------------------------------------- assembly ----
@@ -424,6 +444,38 @@ def amg_solve_pcg(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stream=No
     _check(_lib.amg_solve_pcg(H.handle, _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info), _stream(stream)),
            allow=(OK, NOT_CONVERGED, BREAKDOWN))
     return SolveInfo.of(info)
+
+
+def amg_solve_pcg_shifted(H: Hierarchy, shift, b, x, sp: SolveParams = SolveParams(), stream=None) -> SolveInfo:
+    """PCG on (A + diag(shift)) x = b with the hierarchy of A as preconditioner."""
+    info = SolveInfoC()
+    _check(_lib.amg_solve_pcg_shifted(H.handle, _ptr(shift), _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info),
+                                      _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return SolveInfo.of(info)
+
+
+def flow_transient(grid, K, bc: Tuple[float, float], wells: Sequence, Ss, h0, dts: Sequence[float], h,
+                   delta: float = 0.01, params: "AmgParams" = None, sp: SolveParams = SolveParams(),
+                   h_steps=None, stream=None) -> Tuple[int, List[StepInfo]]:
+    """Fully implicit steps of Eq. 2 with setup reuse; see flow_transient in
+    the C header.  Returns the worst status and one StepInfo per step."""
+    import torch
+    g = grid_c(grid)
+    n = g.nx * g.ny * g.nz
+    for t, name in ((K, "K"), (Ss, "Ss"), (h0, "h0"), (h, "h")):
+        _expect(t, torch.float64, n, name)
+    if h_steps is not None:
+        _expect(h_steps, torch.float64, n * len(dts), "h_steps")
+    params = params if params is not None else AmgParams()
+    wl = (GwWell * max(1, len(wells)))(*[GwWell(w.ix, w.iy, w.iz, w.q) for w in wells])
+    dt = (C.c_double * len(dts))(*[float(x) for x in dts])
+    info = (StepInfoC * len(dts))()
+    st = _check(_lib.flow_transient(C.byref(g), _ptr(K), C.byref(GwBc(*bc)), C.addressof(wl), len(wells), _ptr(Ss),
+                                    _ptr(h0), dt, len(dts), float(delta), C.byref(params.c()), C.byref(sp.c()),
+                                    _ptr(h), _ptr(h_steps), info, _stream(stream)),
+                allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return st, [StepInfo(i.status, i.iters, i.reused, i.ratio, i.rel_res_true, i.setup_ms, i.solve_ms)
+                for i in info]
 
 
 def amg_solve_bicgstab(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stream=None) -> SolveInfo:

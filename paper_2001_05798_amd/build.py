@@ -27,6 +27,7 @@ SOURCES = [
     ("sell.hip", False),
     ("solve.hip", False),
     ("sweep.hip", True),
+    ("transient.hip", True),
     ("capi.cpp", False),
     ("serve.cpp", False),
 ]

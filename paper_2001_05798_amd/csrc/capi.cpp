@@ -152,6 +152,70 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     return H.release();
 }
 
+// Steps of Eq. 2 from h0: the hierarchy of C serves every step whose
+// storage term passes the reuse criterion (shifted PCG); otherwise a
+// hierarchy of C + S/dt is built, and kept while dt does not change.
+int transient_run(const gw_grid &g, const Csr &C, const double *b, const double *Ss, const double *h0,
+                  const double *dt, int32_t nsteps, double delta, const amg_params &prm, const amg_solve_params &sp,
+                  double *h, double *h_steps, gw_step_info *info, hipStream_t s) {
+    const int64_t n = C.n;
+    const double vol = (g.dx * g.dy) * g.dz;
+    const CsrView Cv = view(C);
+    DBuf<double> shift(n), rhs(n), hcur(n), At_val((size_t)C.nnz);
+    copy_bytes(hcur.p, h0, sizeof(double) * (size_t)n, s);
+    auto setup = [&](const double *val) {
+        const gw_csr A{(int32_t)n, C.nnz, C.rowptr.p, C.col.p, val};
+        return std::unique_ptr<amg_hierarchy>(setup_hierarchy(&A, &prm, s));
+    };
+    double t0 = now_ms();
+    std::unique_ptr<amg_hierarchy> HC = setup(C.val.p);  // hierarchy of C, kept for every step
+    const double setup_c = now_ms() - t0;
+    std::unique_ptr<amg_hierarchy> HT;                  // hierarchy of C + S/dt for the last rebuilt dt
+    double dt_cached = 0.0;
+    int worst = GW_OK;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        gw_step_info st{};
+        st.setup_ms = k == 0 ? setup_c : 0.0;
+        storage_shift(n, Ss, vol, dt[k], shift.p, s);
+        st.ratio = shift_ratio(Cv, shift.p, s);
+        storage_rhs(n, b, shift.p, hcur.p, rhs.p, s);
+        amg_solve_info si{};
+        int rc;
+        if (st.ratio < delta) {
+            st.reused = 1;
+            rc = krylov_pcg_shifted(HC.get(), shift.p, rhs.p, hcur.p, sp, &si, s);
+        } else {
+            if (!HT || dt[k] != dt_cached) {
+                HT.reset();
+                add_diagonal(Cv, shift.p, At_val.p, s);
+                t0 = now_ms();
+                HT = setup(At_val.p);
+                st.setup_ms += now_ms() - t0;
+                dt_cached = dt[k];
+                st.reused = 0;
+            } else {
+                st.reused = 2;
+            }
+            rc = krylov_pcg(HT.get(), rhs.p, hcur.p, sp, &si, s);
+        }
+        st.status = rc;
+        st.iters = si.iters;
+        st.rel_res_true = si.rel_res_true;
+        st.solve_ms = si.solve_ms;
+        if (h_steps) copy_bytes(h_steps + k * n, hcur.p, sizeof(double) * (size_t)n, s);
+        if (info) info[k] = st;
+        if (rc == GW_BREAKDOWN) {
+            worst = rc;
+            break;
+        }
+        if (rc != GW_OK) worst = rc;
+    }
+    copy_bytes(h, hcur.p, sizeof(double) * (size_t)n, s);
+    GW_HIP(hipStreamSynchronize(s));
+    return worst;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -487,6 +551,52 @@ int tt_delineate(const gw_grid *grid, const double *qx, const double *qy, const 
         }
         if (solved[0] != n || solved[1] != n) fail(GW_BREAKDOWN, "tt_delineate: the inflow graph has a cycle");
         return GW_OK;
+    });
+}
+
+int amg_solve_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b, double *x,
+                          const amg_solve_params *sp, amg_solve_info *info, void *stream) {
+    return guarded([&] {
+        check_solve(H, b, x, sp);
+        GW_REQUIRE(shift, "amg_solve_pcg_shifted: null shift");
+        hipStream_t s = as_stream(stream);
+        int st = krylov_pcg_shifted(H, shift, b, x, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
+int flow_transient(const gw_grid *grid, const double *K, const gw_bc *bc, const gw_well *wells, int32_t nwells,
+                   const double *Ss, const double *h0, const double *dt, int32_t nsteps, double delta,
+                   const amg_params *params, const amg_solve_params *sp, double *h, double *h_steps,
+                   gw_step_info *info, void *stream) {
+    return guarded([&] {
+        check_grid(grid);
+        GW_REQUIRE(K && bc && Ss && h0 && dt && params && sp && h, "flow_transient: null pointer");
+        GW_REQUIRE(nwells == 0 || wells, "flow_transient: null wells");
+        GW_REQUIRE(nsteps >= 1, "flow_transient: nsteps must be >= 1");
+        GW_REQUIRE(std::isfinite(delta) && delta >= 0, "flow_transient: delta must be >= 0");
+        for (int32_t k = 0; k < nsteps; ++k)
+            GW_REQUIRE(std::isfinite(dt[k]) && dt[k] > 0, "flow_transient: time steps must be positive");
+        GW_REQUIRE(params->smoother != GW_SMOOTHER_NONE, "flow_transient: needs an AMG smoother");
+        check_params(params);
+        GW_REQUIRE(sp->rtol >= 0 && sp->maxiter >= 0, "flow_transient: bad solve parameters");
+        GW_REQUIRE(nnz7(grid) < INT32_MAX, "flow_transient: matrix exceeds 2^31 nonzeros");
+        hipStream_t s = as_stream(stream);
+        const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+        Csr C;
+        C.alloc((int32_t)n, (int32_t)n, nnz7(grid));
+        DBuf<double> b(n);
+        DBuf<int32_t> bad(1);
+        fill_i32(bad.p, 0, 1, s);
+        launch_fv_assemble(*grid, K, *bc, wells, nwells, C.rowptr.p, C.col.p, C.val.p, b.p, bad.p, s);
+        int32_t *stage = static_cast<int32_t *>(host_stage());
+        GW_HIP(hipMemcpyAsync(stage, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        if (stage[0]) fail(GW_EINVAL, "flow_transient: conductivity must be positive and finite");
+        const int st = transient_run(*grid, C, b.p, Ss, h0, dt, nsteps, delta, *params, *sp, h, h_steps, info, s);
+        finish(s);
+        return st;
     });
 }
 

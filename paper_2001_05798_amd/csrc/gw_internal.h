@@ -311,12 +311,25 @@ int lane_group_for(double mean_row_len);
 int solve_group_for(double mean_row_len);
 int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                amg_solve_info *info, hipStream_t s);
+// PCG on A + diag(shift), preconditioned by the hierarchy of A.
+int krylov_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b, double *x, const amg_solve_params &sp,
+                       amg_solve_info *info, hipStream_t s);
 int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                     amg_solve_info *info, hipStream_t s);
 // Two systems with the hierarchy's matrix, solved in lockstep (each exactly
 // as krylov_bicgstab solves it alone).  Returns the worse of the statuses.
 int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
                      const amg_solve_params &sp, amg_solve_info info[2], hipStream_t s);
+
+// transient.hip (Eq. 2)
+// shift = S_i V_i / dt with vol = V_i.
+void storage_shift(int64_t n, const double *Ss, double vol, double dt, double *shift, hipStream_t s);
+// max_i shift_i / C_ii (blocks for the host read).
+double shift_ratio(const CsrView &C, const double *shift, hipStream_t s);
+// rhs = b + shift h.
+void storage_rhs(int64_t n, const double *b, const double *shift, const double *h, double *rhs, hipStream_t s);
+// val = values of C + diag(shift) (same pattern as C).
+void add_diagonal(const CsrView &C, const double *shift, double *val, hipStream_t s);
 
 // sweep.hip
 // Exact solve of a system whose rows couple each cell to its inflow

@@ -188,6 +188,29 @@ struct OpSell {
     }
 };
 
+// A + diag(d): the level-0 operator with a diagonal added, for the storage
+// term S/dt of Eq. 2 when the hierarchy of the conductance matrix is kept.
+template <class B>
+struct OpShift {
+    static constexpr int G = B::G;
+    B base;
+    const double *d;
+    __device__ __forceinline__ void load(int32_t *sd) const { base.load(sd); }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<double, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        VecN<double, NR> s = base.template rows<NR>(i, lane, sd, xj);
+        const VecN<double, NR> xi = xj((int32_t)i);
+        const double di = d[i];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s.v[k] += di * xi.v[k];
+        return s;
+    }
+    template <class F>
+    __device__ __forceinline__ double row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows<1>(i, lane, sd, [&](int32_t j) { return VecN<double, 1>{{(double)xj(j)}}; }).v[0];
+    }
+};
+
 // Block prologue of every product kernel (after its uniform early exit).
 #define OP_PROLOGUE(op)                         \
     __shared__ int32_t sd_[kSellMaxDict + 1];   \
@@ -1108,6 +1131,7 @@ struct Kry {
     hipStream_t s;
     double rtol;
     double vec, abytes;
+    const double *shift = nullptr;  // diagonal added to A (OpShift), or none
 
     Kry(amg_hierarchy *H_, hipStream_t s_, double rtol_) : H(H_), L0(H_->L[0]), s(s_), rtol(rtol_) {
         G = L0.As.built() ? 1 : L0.A.grp;
@@ -1119,28 +1143,35 @@ struct Kry {
         vec = 8.0 * n;
         abytes = op_bytes(L0.A, L0.As, 8);
     }
-    template <class F>
+    template <bool SHIFT = false, class F>
     void op(F &&f) const {
-        if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
-        else with_csr<double>(L0.A, L0.A.val.p, f);
+        if constexpr (SHIFT) {
+            if (L0.As.built()) f(OpShift<OpSell<double>>{OpSell<double>{view(L0.As), L0.As.val.p}, shift});
+            else with_csr<double>(L0.A, L0.A.val.p, [&](auto o) { f(OpShift<decltype(o)>{o, shift}); });
+        } else {
+            if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
+            else with_csr<double>(L0.A, L0.A.val.p, f);
+        }
     }
     void fin(int code, unsigned nb) {
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kKBlock), 0, s, code, nb, part, rtol, ks);
     }
+    template <bool SHIFT = false>
     void init(const double *b, const double *x, double *r, double *rh, double *p, double *v, bool first) {
         {
             ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec + (rh ? 3 * vec : 0), s);
-            op([&](auto o) {
+            op<SHIFT>([&](auto o) {
                 hipLaunchKernelGGL((k_kr_init<decltype(o)>), dim3(gG), dim3(kKBlock), 0, s, n, o, b, x, r, rh, p, v,
                                    part);
             });
         }
         fin(first ? FIN_INIT_FIRST : FIN_INIT_RESTART, gG);
     }
+    template <bool SHIFT = false>
     void true_res(const double *b, const double *x) {
         {
             ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s);
-            op([&](auto o) {
+            op<SHIFT>([&](auto o) {
                 hipLaunchKernelGGL((k_true_res<decltype(o)>), dim3(gG), dim3(kKBlock), 0, s, n, o, b, x, part);
             });
         }
@@ -1226,11 +1257,18 @@ void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s) {
     GW_HIP(hipGetLastError());
 }
 
-int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve_params &sp, amg_solve_info *info,
-               hipStream_t s) {
+namespace {
+
+// PCG on A (SHIFT false) or on A + diag(shift) with the hierarchy of A as the
+// preconditioner (SHIFT true; launched one by one: a captured graph would
+// keep the shift pointer of its first call).
+template <bool SHIFT>
+int pcg_impl(amg_hierarchy *H, const double *shift, const double *b, double *x_out, const amg_solve_params &sp,
+             amg_solve_info *info, hipStream_t s) {
     const double t0 = now_ms();
     ensure_krylov_workspace(H, 6);
     Kry K(H, s, sp.rtol);
+    K.shift = shift;
     const int64_t n = K.n;
     // the iterate lives in the workspace (a captured block then serves any
     // output buffer) and is copied out at the end
@@ -1241,7 +1279,7 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve
     k0.status = GW_NOT_CONVERGED;
     write_ks(H, k0, s);
     fill_f64(x, 0.0, n, s);
-    K.init(b, x, r, nullptr, pa, nullptr, true);
+    K.template init<SHIFT>(b, x, r, nullptr, pa, nullptr, true);
     KScalars k = read_ks(H, s);
     int restarts = 0;
     if (k.bnorm == 0.0) {
@@ -1250,7 +1288,7 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve
         return GW_OK;
     }
     const int check = std::max(1, sp.check_every);
-    const bool graph = use_graph(sp);
+    const bool graph = !SHIFT && use_graph(sp);
     int32_t *done = &H->ks.p->done;
     int parity = 0;
     // check_every iterations: q = A p, alpha, x and r updates with the
@@ -1258,12 +1296,13 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve
     auto block = [&](int parity0) {
         return [&, parity0](hipStream_t cs) {
             Kry Kc(H, cs, sp.rtol);
+            Kc.shift = shift;
             int par = parity0;
             for (int c = 0; c < check; ++c) {
                 double *po = par ? pb : pa, *pn = par ? pa : pb;
                 {
                     ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs);
-                    Kc.op([&](auto o) {
+                    Kc.template op<SHIFT>([&](auto o) {
                         hipLaunchKernelGGL((k_cg_spmv<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, z, po,
                                            pn, q, Kc.part, Kc.ks);
                     });
@@ -1301,14 +1340,14 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve
                 if (k.done) break;
             }
         }
-        K.true_res(b, x);
+        K.template true_res<SHIFT>(b, x);
         k = read_ks(H, s);
         if (k.status == GW_BREAKDOWN) break;
         if (k.rel_true <= sp.rtol) { k.status = GW_OK; break; }
         if (k.iters >= k.maxiter || restarts >= 8) { k.status = GW_NOT_CONVERGED; break; }
         ++restarts;
         parity = 0;
-        K.init(b, x, r, nullptr, pa, nullptr, false);
+        K.template init<SHIFT>(b, x, r, nullptr, pa, nullptr, false);
         k = read_ks(H, s);
     }
     copy_bytes(x_out, x, sizeof(double) * (size_t)n, s);
@@ -1322,6 +1361,18 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve
         info->solve_ms = now_ms() - t0;
     }
     return k.status;
+}
+
+}  // namespace
+
+int krylov_pcg(amg_hierarchy *H, const double *b, double *x_out, const amg_solve_params &sp, amg_solve_info *info,
+               hipStream_t s) {
+    return pcg_impl<false>(H, nullptr, b, x_out, sp, info, s);
+}
+
+int krylov_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b, double *x_out,
+                       const amg_solve_params &sp, amg_solve_info *info, hipStream_t s) {
+    return pcg_impl<true>(H, shift, b, x_out, sp, info, s);
 }
 
 int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_solve_params &sp,
