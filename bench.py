@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--no-transient", action="store_true", help="skip the transient-flow measurement")
     ap.add_argument("--no-direct", action="store_true",
                     help="skip the direct upwind-sweep travel-time measurement")
     ap.add_argument("--graph", type=int, default=-1, choices=(-1, 0, 1),
@@ -430,6 +431,32 @@ def main():
                   "note": "tt_solve_direct (assemble + upwind sweep, 2 RHS), median of 5 calls; not in the timed step"}
         print(f"[bench] direct travel time: {direct}", file=sys.stderr, flush=True)
 
+    # transient flow (Eq. 2) on the same aquifer: four implicit steps of
+    # growing length, with the setup of C kept (reuse criterion met) and,
+    # for comparison, with a setup per step (delta = 0)
+    transient = None
+    if not args.no_transient:
+        g = pipe.g
+        Ss = torch.full((g.n,), 1e-5, dtype=torch.float64, device="cuda")
+        h0 = torch.zeros(g.n, dtype=torch.float64, device="cuda")
+        ht = torch.empty_like(h0)
+        dts = [36000.0 * 1.5 ** k for k in range(4)]
+        bc = (prob.h_west, prob.h_east)
+        res = {}
+        for name, delta in (("kept", 0.01), ("rebuilt", 0.0)):
+            gw.flow_transient(g, pipe.K, bc, prob.wells, Ss, h0, dts, ht, delta=delta, sp=pipe.sp)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st, info = gw.flow_transient(g, pipe.K, bc, prob.wells, Ss, h0, dts, ht, delta=delta, sp=pipe.sp)
+            torch.cuda.synchronize()
+            res[name] = {"ms": round(1e3 * (time.perf_counter() - t1), 3), "status": st,
+                         "setups": sum(1 for i in info if i.reused == 0) + int(any(i.reused == 1 for i in info)),
+                         "iters": [i.iters for i in info], "max_ratio": max(i.ratio for i in info)}
+        transient = {"steps": len(dts), "dt_s": dts, "Ss": 1e-5, **res,
+                     "note": "flow_transient, 4 steps from h = 0; 'kept' reuses the setup of C "
+                             "(ratio < 0.01), 'rebuilt' builds one for every step"}
+        print(f"[bench] transient: {transient}", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve_requests > 0:
         print(f"[bench] served stream, {args.serve_requests} requests ...", file=sys.stderr, flush=True)
@@ -473,6 +500,7 @@ def main():
         "roofline": roof,
         "solve_phase_roofline": solve_phase,
         "tt_direct": direct,
+        "transient": transient,
         "accuracy": accuracy,
         "cpu_baseline": cpu,
         "serving": serve,

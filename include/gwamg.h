@@ -232,12 +232,13 @@ int amg_solve_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b
 typedef struct {
     int32_t status;       /* of the step's solve                          */
     int32_t iters;
-    int32_t reused;       /* 1: setup of C kept (criterion met); 2: setup
-                             of C + S/dt of an earlier step with the same
-                             dt; 0: built for this step                    */
+    int32_t reused;       /* 1: setup of C (built once, at the first step
+                             that meets the criterion); 2: setup of C + S/dt
+                             of an earlier step with the same dt; 0: built
+                             for this step                                 */
     double ratio;         /* max_i S_i V_i / (dt C_ii)                     */
     double rel_res_true;
-    double setup_ms;      /* setups done in this step (step 0: that of C)  */
+    double setup_ms;      /* setup done in this step (C's at its first use) */
     double solve_ms;
 } gw_step_info;
 

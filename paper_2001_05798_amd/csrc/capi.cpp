@@ -167,15 +167,13 @@ int transient_run(const gw_grid &g, const Csr &C, const double *b, const double 
         const gw_csr A{(int32_t)n, C.nnz, C.rowptr.p, C.col.p, val};
         return std::unique_ptr<amg_hierarchy>(setup_hierarchy(&A, &prm, s));
     };
-    double t0 = now_ms();
-    std::unique_ptr<amg_hierarchy> HC = setup(C.val.p);  // hierarchy of C, kept for every step
-    const double setup_c = now_ms() - t0;
-    std::unique_ptr<amg_hierarchy> HT;                  // hierarchy of C + S/dt for the last rebuilt dt
+    double t0 = 0.0;
+    std::unique_ptr<amg_hierarchy> HC;  // hierarchy of C, built at the first step that may keep it
+    std::unique_ptr<amg_hierarchy> HT;  // hierarchy of C + S/dt for the last rebuilt dt
     double dt_cached = 0.0;
     int worst = GW_OK;
     for (int32_t k = 0; k < nsteps; ++k) {
         gw_step_info st{};
-        st.setup_ms = k == 0 ? setup_c : 0.0;
         storage_shift(n, Ss, vol, dt[k], shift.p, s);
         st.ratio = shift_ratio(Cv, shift.p, s);
         storage_rhs(n, b, shift.p, hcur.p, rhs.p, s);
@@ -183,6 +181,11 @@ int transient_run(const gw_grid &g, const Csr &C, const double *b, const double 
         int rc;
         if (st.ratio < delta) {
             st.reused = 1;
+            if (!HC) {
+                t0 = now_ms();
+                HC = setup(C.val.p);
+                st.setup_ms = now_ms() - t0;
+            }
             rc = krylov_pcg_shifted(HC.get(), shift.p, rhs.p, hcur.p, sp, &si, s);
         } else {
             if (!HT || dt[k] != dt_cached) {
@@ -190,7 +193,7 @@ int transient_run(const gw_grid &g, const Csr &C, const double *b, const double 
                 add_diagonal(Cv, shift.p, At_val.p, s);
                 t0 = now_ms();
                 HT = setup(At_val.p);
-                st.setup_ms += now_ms() - t0;
+                st.setup_ms = now_ms() - t0;
                 dt_cached = dt[k];
                 st.reused = 0;
             } else {
