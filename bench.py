@@ -36,6 +36,10 @@ WORKLOADS = {
     "c3": (256, 256, 128, 4.0, 8.0, 21, 1),
     "c3fp64": (256, 256, 128, 4.0, 8.0, 21, 0),
     "c3s1": (256, 256, 128, 1.0, 8.0, 22, 1),
+    # the paper's 3D model size (550 x 500 x 10 blocks of 20 m, four
+    # doublets): lognormal variance 10, and its homogeneous case
+    "paper": (550, 500, 10, 10.0, 10.0, 31, 0),
+    "paper-homog": (550, 500, 10, 0.0, 10.0, 31, 0),
 }
 
 
@@ -290,7 +294,10 @@ def main():
 
     torch.cuda.set_device(0)
     nx, ny, nz, s2, lam, seed, precision = WORKLOADS[args.workload]
-    prob = gi.heterogeneous_aquifer(nx, ny, nz, s2, lam, seed)
+    if args.workload.startswith("paper"):
+        prob = gi.paper_like_aquifer(s2, lam, seed, nz)
+    else:
+        prob = gi.heterogeneous_aquifer(nx, ny, nz, s2, lam, seed)
     print(f"[bench] workload {args.workload}: {nx}x{ny}x{nz} s2={s2} lam={lam} seed={seed} "
           f"precision={'mixed' if precision else 'fp64'}", file=sys.stderr, flush=True)
     pipe = Pipeline(gw, torch, prob, precision, args.graph)
@@ -489,8 +496,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == 0 else "f32-hierarchy/f64-krylov",
         "data": "synthetic",
-        "config": {"workload": (f"{nx}x{ny}x{nz} lognormal aquifer (lnK var {s2}, corr len {lam} cells, seed {seed}), "
-                                "4 wells; flow AMG-PCG rtol 1e-8 + Darcy + travel time (2 RHS, BiCGSTAB+AMG)"),
+        "config": {"workload": ((f"{nx}x{ny}x{nz} lognormal aquifer (lnK var {s2}, corr len {lam} cells, seed {seed}), "
+                                 "4 wells" if not args.workload.startswith("paper") else
+                                 f"{nx}x{ny}x{nz} paper-size aquifer, 20 m blocks ("
+                                 + (f"lnK var {s2}, corr len {lam} cells, seed {seed}" if s2 else "homogeneous")
+                                 + "), four doublets screened over 5 layers")
+                                + "; flow AMG-PCG rtol 1e-8 + Darcy + travel time (2 RHS, BiCGSTAB+AMG)"),
                    "cells": nx * ny * nz, "parallelism": "single-gpu"},
         "flow_time_to_rtol_ms": round(statistics.median(flow_ms), 3),
         "flow_iters": int(statistics.median(iters)),

@@ -25,13 +25,15 @@ import numpy as np
 
 __all__ = [
     "Grid", "Well", "Problem", "lognormal_field", "four_well_layout",
-    "homogeneous_slab", "heterogeneous_aquifer", "serve_stream",
+    "homogeneous_slab", "heterogeneous_aquifer", "serve_stream", "doublet_layout",
+    "paper_like_aquifer",
 ]
 
 K_GEO_DEFAULT = 1.0e-4   # geometric-mean conductivity [m/s]
 H_WEST_DEFAULT = 10.0    # fixed head on the x = 0 face [m]
 H_EAST_DEFAULT = 0.0     # fixed head on the x = L face [m]
 PHI_DEFAULT = 0.25       # porosity used in the travel-time equation
+K_PAPER = 6.38e-5        # K_mean of the paper's benchmark models [m/s]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -151,6 +153,40 @@ def heterogeneous_aquifer(nx: int, ny: int, nz: int, sigma2: float,
     w = four_well_layout(g) if wells else []
     return Problem(g, K, wells=w,
                    label=f"lognormal {nx}x{ny}x{nz} s2={sigma2} lam={corr_len} seed={seed}")
+
+
+def doublet_layout(grid: Grid, rate: float, n_screen: int = 5) -> List[Well]:
+    """Four injection/production doublets (the paper's geothermal model has
+    four, at positions it does not give).  Injectors at (3nx/10 | 7nx/10,
+    ny/4 | 3ny/4) are screened over the lowest ``n_screen`` layers, their
+    producers nx/10 cells downstream over the top ``n_screen`` layers; each
+    well moves ``rate`` m^3/s, split evenly over its screened cells (q < 0
+    injects)."""
+    ns = max(1, min(n_screen, grid.nz))
+    q = rate / ns
+    wells = []
+    for y in (grid.ny // 4, (3 * grid.ny) // 4):
+        for x in ((3 * grid.nx) // 10, (7 * grid.nx) // 10):
+            xp = min(grid.nx - 1, x + max(1, grid.nx // 10))
+            wells += [Well(x, y, k, -q) for k in range(ns)]
+            wells += [Well(xp, y, grid.nz - 1 - k, q) for k in range(ns)]
+    return wells
+
+
+def paper_like_aquifer(sigma2: float = 10.0, corr_len: float = 10.0, seed: int = 31, nz: int = 10,
+                       rate: float = 0.02) -> Problem:
+    """Stand-in for the paper's geothermal model (Benchmarking Examples):
+    550 x 500 blocks of 20 m in every direction, ``nz`` layers (10: the 3D
+    extension, 2.75M blocks; 1: the 2D model), K_mean = 6.38e-5 m/s taken as
+    the geometric mean of a lognormal field of variance ``sigma2`` (10 in the
+    paper; 0 gives its homogeneous case), four doublets with partially
+    penetrating wells (``doublet_layout``).  The paper's boundaries are all
+    no-flow, which leaves the flow matrix singular; fixed heads on the two
+    x faces stand in for them."""
+    g = Grid(550, 500, nz, 20.0, 20.0, 20.0)
+    K = lognormal_field((g.nx, g.ny, g.nz), sigma2, corr_len, seed, k_geo=K_PAPER)
+    return Problem(g, K, wells=doublet_layout(g, rate),
+                   label=f"paper-like 550x500x{nz} s2={sigma2} lam={corr_len} seed={seed}")
 
 
 @dataclasses.dataclass(frozen=True)

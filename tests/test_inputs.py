@@ -56,3 +56,20 @@ def test_general_matrix_generators():
         d = A.diagonal()
         off = np.asarray(abs(A).sum(axis=1)).ravel() - d
         assert np.all(d > off)
+
+
+def test_paper_like_layout():
+    # the paper's 3D model size (Benchmarking Examples; Results, Table 1):
+    # 550 x 500 x 10 blocks of 20 m, four doublets whose injectors are
+    # screened over the five lower layers and producers over the five top ones
+    g = gi.Grid(550, 500, 10, 20.0, 20.0, 20.0)
+    w = gi.doublet_layout(g, 0.02)
+    assert len(w) == 40 and abs(sum(x.q for x in w)) < 1e-15
+    inj = [x for x in w if x.q < 0]
+    prod = [x for x in w if x.q > 0]
+    assert sorted({x.iz for x in inj}) == [0, 1, 2, 3, 4] and sorted({x.iz for x in prod}) == [5, 6, 7, 8, 9]
+    assert len({(x.ix, x.iy) for x in inj}) == 4 and len({(x.ix, x.iy) for x in prod}) == 4
+    p = gi.paper_like_aquifer(sigma2=0.0)
+    assert p.grid == g and np.all(p.K == gi.K_PAPER)
+    w2 = gi.doublet_layout(gi.Grid(550, 500, 1, 20.0, 20.0, 20.0), 0.02)
+    assert len(w2) == 8 and all(x.iz == 0 for x in w2)
