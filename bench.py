@@ -254,6 +254,27 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
             q.close()
         errs_h.append(float(np.linalg.norm(outs[0]["h"] - outs[1]["h"]) / np.linalg.norm(outs[1]["h"])))
         errs_tau.append(float(np.linalg.norm(outs[0]["tau"] - outs[1]["tau"]) / np.linalg.norm(outs[1]["tau"])))
+    # a sensitivity study on well rates: 12 requests on one 128^3 aquifer
+    # that differ only in their pumping rates, with and without the setup
+    # cache (one hierarchy per slot kept, so the requests after the first
+    # round skip the flow setup)
+    aq = gi.heterogeneous_aquifer(128, 128, 128, 2.0, 8, 77)
+    study = [gi.Problem(aq.grid, aq.K, aq.h_west, aq.h_east,
+                        [gi.Well(w.ix, w.iy, w.iz, w.q * (0.5 + 0.1 * k)) for w in aq.wells], aq.phi)
+             for k in range(12)]
+    rates = {}
+    for cache in (0, 1):
+        q = gw.Queue(budget, slots)
+        q.set_setup_cache(slots if cache else 0)
+        t0 = q.clock()
+        tick = [q.submit(p, ap, tp, sp, zone=zone(p), want=()) for p in study]
+        q.drain()
+        span = q.clock() - t0
+        rr = [q.poll(t)[0] for t in tick]
+        q.close()
+        bad += sum(r.status != gw.OK for r in rr)
+        rates["cache" if cache else "no_cache"] = {"solves_per_s": round(len(study) / span, 3),
+                                                   "setups_reused": sum(r.setup_reused for r in rr)}
     return {
         "requests": n_requests, "slots": slots, "precision": "f32-hierarchy/f64-krylov",
         "saturation_solves_per_s": round(sat, 3),
@@ -265,6 +286,7 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
                        "p99": round(float(np.percentile(lat, 99)), 2),
                        "mean": round(float(lat.mean()), 2)},
         "cells_mean": int(cells.mean()), "cells_max": int(cells.max()),
+        "well_rate_study": {"requests": len(study), "cells": aq.grid.n, **rates},
         "failed": int(bad),
         "flow_iters_mean": round(float(np.mean([r.flow.iters for r in res2])), 1),
         "tt_iters_mean": round(float(np.mean([r.tt[0].iters for r in res2])), 1),

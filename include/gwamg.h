@@ -362,6 +362,7 @@ typedef struct {
     double t_arrival, t_start, t_done; /* seconds on the queue clock      */
     size_t bytes_reserved;             /* admission footprint             */
     char error[160];                   /* message when status < 0         */
+    int32_t setup_reused;              /* 1: flow hierarchy from the cache */
 } gw_result;
 
 /* hbm_budget_bytes: device memory the queue may reserve for requests in
@@ -377,6 +378,18 @@ int queue_submit(gw_queue *q, const gw_request *req, uint64_t *ticket);
 int queue_poll(gw_queue *q, uint64_t ticket, gw_result *res);
 /* Block until every submitted request is finished. */
 int queue_drain(gw_queue *q);
+
+/* Keep up to max_entries flow hierarchies after their requests (0, the
+ * default, frees each one at the end of its request).  A request whose
+ * conductance field, grid, boundary heads and flow AMG parameters equal a
+ * cached one's takes that hierarchy instead of a new setup: wells change
+ * only the right-hand side, so the matrix, and the hierarchy built from it,
+ * are the same (the Discussion's setup caching, applied across requests such
+ * as a sensitivity analysis on well rates).  The match compares two 64-bit
+ * hashes of those inputs.  A cached hierarchy serves one request at a time;
+ * cached bytes count against the HBM budget and the least recently used
+ * idle entry is freed when a waiting request does not fit. */
+int queue_set_setup_cache(gw_queue *q, int32_t max_entries);
 void queue_destroy(gw_queue *q);
 
 #ifdef __cplusplus

@@ -99,7 +99,7 @@ class RequestC(C.Structure):
 class ResultC(C.Structure):
     _fields_ = [("status", C.c_int32), ("flow", SolveInfoC), ("tt", SolveInfoC * 2),
                 ("t_arrival", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("bytes_reserved", C.c_size_t), ("error", C.c_char * 160)]
+                ("bytes_reserved", C.c_size_t), ("error", C.c_char * 160), ("setup_reused", C.c_int32)]
 
 
 # ------------------------------------------------------------------ load --
@@ -153,6 +153,7 @@ def _load():
         "queue_submit": (C.c_int, [vp, C.POINTER(RequestC), C.POINTER(C.c_uint64)]),
         "queue_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ResultC)]),
         "queue_drain": (C.c_int, [vp]),
+        "queue_set_setup_cache": (C.c_int, [vp, i32]),
         "queue_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -535,6 +536,7 @@ class Result:
     t_done: float
     bytes_reserved: int
     error: str = ""
+    setup_reused: int = 0   # 1: the flow hierarchy came from the setup cache
 
     @property
     def latency(self) -> float:
@@ -597,8 +599,14 @@ class Queue:
             raise GwError(st, last_error())
         K, wl, outs = self._keep.pop(ticket)
         res = Result(r.status, SolveInfo.of(r.flow), [SolveInfo.of(r.tt[0]), SolveInfo.of(r.tt[1])],
-                     r.t_arrival, r.t_start, r.t_done, int(r.bytes_reserved), r.error.decode(errors="replace"))
+                     r.t_arrival, r.t_start, r.t_done, int(r.bytes_reserved), r.error.decode(errors="replace"),
+                     int(r.setup_reused))
         return res, outs
 
     def drain(self) -> None:
         _check(_lib.queue_drain(self._q))
+
+    def set_setup_cache(self, max_entries: int) -> None:
+        """Keep up to max_entries flow hierarchies for later requests with the
+        same conductance field, grid, heads and AMG parameters (0: off)."""
+        _check(_lib.queue_set_setup_cache(self._q, int(max_entries)))

@@ -9,11 +9,17 @@
 // overlap on the device; a request that arrives while others run joins as
 // soon as a slot and memory free up.  Hierarchies stay resident for the
 // duration of a request: the travel-time hierarchy serves both right-hand
-// sides.
+// sides.  With the setup cache on (queue_set_setup_cache), the flow
+// hierarchy outlives its request: a later request with the same conductance
+// field, grid, boundary heads and AMG parameters takes it instead of a new
+// setup, since wells change only the right-hand side (the Discussion's
+// setup caching, here across requests such as the runs of a sensitivity
+// analysis on well rates).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -40,6 +46,63 @@ size_t footprint_bytes(const gw_request &r) {
     return (size_t)(n * per_cell) + ((size_t)64 << 20);
 }
 
+// Two independent 64-bit hashes of the bytes (words mixed by multiply and
+// xor-shift), with everything else that determines the flow matrix.
+void mix(uint64_t &h, uint64_t w) {
+    h ^= w + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 31;
+}
+
+struct SetupKey {
+    uint64_t h[2];
+    bool operator==(const SetupKey &o) const { return h[0] == o.h[0] && h[1] == o.h[1]; }
+};
+
+SetupKey setup_key(const gw_request &r) {
+    SetupKey k{{0x243F6A8885A308D3ull, 0x13198A2E03707344ull}};
+    auto word = [&](uint64_t w) {
+        mix(k.h[0], w);
+        mix(k.h[1], w ^ 0xA4093822299F31D0ull);
+    };
+    auto dbl = [&](double d) {
+        uint64_t w;
+        std::memcpy(&w, &d, 8);
+        word(w);
+    };
+    const gw_grid &g = r.grid;
+    word((uint64_t)g.nx);
+    word((uint64_t)g.ny);
+    word((uint64_t)g.nz);
+    dbl(g.dx);
+    dbl(g.dy);
+    dbl(g.dz);
+    dbl(r.bc.h_west);
+    dbl(r.bc.h_east);
+    const amg_params &p = r.flow_params;
+    dbl(p.eps_strong);
+    word((uint64_t)p.smoother);
+    dbl(p.omega);
+    word((uint64_t)p.npre);
+    word((uint64_t)p.npost);
+    word((uint64_t)p.n_coarse);
+    word((uint64_t)p.max_levels);
+    word((uint64_t)p.precision);
+    word((uint64_t)p.seed);
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    const uint64_t *K = reinterpret_cast<const uint64_t *>(r.K);
+    for (int64_t i = 0; i < n; ++i) word(K[i]);
+    return k;
+}
+
+struct CachedSetup {
+    SetupKey key;
+    amg_hierarchy *H = nullptr;
+    size_t bytes = 0;
+    bool in_use = false;
+    uint64_t last_use = 0;
+};
+
 struct Job {
     uint64_t ticket;
     gw_request req;
@@ -63,10 +126,30 @@ struct gw_queue {
     int device = 0;
     Clock::time_point t0;
     std::vector<std::thread> workers;
+    // flow hierarchies kept after their request (bytes counted in `reserved`)
+    std::vector<CachedSetup> cache;
+    int cache_max = 0;
+    uint64_t use_clock = 0;
 
     double clock() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void worker();
     int run(Job &job, hipStream_t s, gw_result &res);
+    // With mu held: drop the least recently used idle entry; false if none.
+    bool evict_one() {
+        int best = -1;
+        for (int i = 0; i < (int)cache.size(); ++i)
+            if (!cache[i].in_use && (best < 0 || cache[i].last_use < cache[best].last_use)) best = i;
+        if (best < 0) return false;
+        amg_free(cache[best].H);
+        reserved -= cache[best].bytes;
+        cache.erase(cache.begin() + best);
+        return true;
+    }
+    bool can_evict() const {
+        for (const auto &c : cache)
+            if (!c.in_use) return true;
+        return false;
+    }
 };
 
 namespace {
@@ -96,14 +179,60 @@ int gw_queue::run(Job &job, hipStream_t s, gw_result &res) {
                          d.val.p, d.b.p, s);
     if (st != GW_OK) return st;
     amg_hierarchy *H = nullptr;
-    gw_csr A{(int32_t)n, nnz, d.rowptr.p, d.col.p, d.val.p};
     const double ts = std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count();
-    st = amg_setup(&A, &r.flow_params, &H, s);
-    if (st != GW_OK) return st;
+    SetupKey key{};
+    bool caching = false;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        caching = cache_max > 0;
+    }
+    if (caching) {
+        key = setup_key(r);
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto &c : cache)
+            if (!c.in_use && c.key == key) {
+                c.in_use = true;
+                H = c.H;
+                res.setup_reused = 1;
+                break;
+            }
+    }
+    if (!H) {
+        gw_csr A{(int32_t)n, nnz, d.rowptr.p, d.col.p, d.val.p};
+        st = amg_setup(&A, &r.flow_params, &H, s);
+        if (st != GW_OK) return st;
+    }
     const double setup_ms =
         std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count() - ts;
     st = amg_solve_pcg(H, d.b.p, d.h.p, &r.solve, &res.flow, s);
-    amg_free(H);
+    GW_HIP(hipStreamSynchronize(s));
+    {
+        // hand the hierarchy back to the cache, or keep a new one there
+        std::lock_guard<std::mutex> lk(mu);
+        bool kept = false;
+        for (auto &c : cache)
+            if (c.H == H) {
+                c.in_use = false;
+                c.last_use = ++use_clock;
+                kept = true;
+            }
+        if (!kept && caching && cache_max > 0 && st >= 0) {
+            while ((int)cache.size() >= cache_max && evict_one()) {
+            }
+            if ((int)cache.size() < cache_max) {
+                CachedSetup c;
+                c.key = key;
+                c.H = H;
+                int32_t nl = 0;
+                (void)amg_hierarchy_info(H, nullptr, 0, &nl, &c.bytes);
+                c.last_use = ++use_clock;
+                reserved += c.bytes;
+                cache.push_back(c);
+                kept = true;
+            }
+        }
+        if (!kept) amg_free(H);
+    }
     res.flow.setup_ms = setup_ms;
     d.val.release();
     d.col.release();
@@ -136,9 +265,13 @@ void gw_queue::worker() {
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] {
-                return stop || (!waiting.empty() && reserved + waiting.front().bytes <= budget);
+                return stop || (!waiting.empty() && (reserved + waiting.front().bytes <= budget || can_evict()));
             });
             if (stop) break;
+            // cached setups give way to a request that does not fit beside them
+            while (reserved + waiting.front().bytes > budget && evict_one()) {
+            }
+            if (reserved + waiting.front().bytes > budget) continue;
             job = std::move(waiting.front());
             waiting.pop_front();
             reserved += job.bytes;
@@ -249,6 +382,21 @@ int queue_drain(gw_queue *q) {
     });
 }
 
+int queue_set_setup_cache(gw_queue *q, int32_t max_entries) {
+    return gw::guarded([&] {
+        GW_REQUIRE(q, "queue_set_setup_cache: null queue");
+        GW_REQUIRE(max_entries >= 0 && max_entries <= 64, "queue_set_setup_cache: max_entries must be in [0, 64]");
+        {
+            std::lock_guard<std::mutex> lk(q->mu);
+            q->cache_max = max_entries;
+            while ((int)q->cache.size() > max_entries && q->evict_one()) {
+            }
+        }
+        q->cv_work.notify_all();
+        return GW_OK;
+    });
+}
+
 void queue_destroy(gw_queue *q) {
     if (!q) return;
     {
@@ -259,6 +407,7 @@ void queue_destroy(gw_queue *q) {
     }
     q->cv_work.notify_all();
     for (auto &t : q->workers) t.join();
+    for (auto &c : q->cache) amg_free(c.H);
     delete q;
 }
 

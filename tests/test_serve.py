@@ -113,3 +113,58 @@ def test_admission_by_budget():
     spans = sorted((r.t_start, r.t_done) for r, _ in res)
     for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
         assert s1 >= d0 - 1e-6  # serialized by the budget
+
+
+@needs_lib
+def test_setup_cache_argument_checks_cpu():
+    q = gw.Queue(hbm_budget_bytes=1 << 30, max_slots=1)
+    for bad in (-1, 65):
+        with pytest.raises(gw.GwError) as e:
+            q.set_setup_cache(bad)
+        assert e.value.status == gw.EINVAL
+    q.set_setup_cache(4)
+    q.set_setup_cache(0)
+    q.close()
+
+
+def _with_wells(p, scale):
+    return gi.Problem(p.grid, p.K, p.h_west, p.h_east, [gi.Well(w.ix, w.iy, w.iz, w.q * scale) for w in p.wells],
+                      p.phi, p.label)
+
+
+def _serve_seq(problems, cache, budget=64 << 30):
+    ap, sp = _params()
+    tp = gw.AmgParams.travel_time(precision=gw.PRECISION_MIXED)
+    q = gw.Queue(hbm_budget_bytes=budget, max_slots=1)
+    q.set_setup_cache(cache)
+    out = []
+    for p in problems:  # one at a time, so the cache state is known
+        t = q.submit(p, ap, tp, sp, zone=(0, p.grid.ny, 0, max(1, p.grid.nz // 2)))
+        q.drain()
+        out.append(q.poll(t))
+    q.close()
+    return out
+
+
+@pytest.mark.gpu
+def test_setup_cache_reuse_on_well_rates():
+    if gw is None or not _has_gpu():
+        pytest.skip("no GPU")
+    print("[case] serve setup cache", flush=True)
+    base = gi.heterogeneous_aquifer(40, 36, 24, 2.0, 6, 101)
+    other = gi.heterogeneous_aquifer(40, 36, 24, 2.0, 6, 102)
+    p1, p2 = _with_wells(base, 1.0), _with_wells(base, 0.5)
+    res = _serve_seq([p1, p2, other, p2], cache=2)
+    assert all(r.status == gw.OK for r, _ in res), [(r.status, r.error) for r, _ in res]
+    assert [r.setup_reused for r, _ in res] == [0, 1, 0, 1]
+    # the cached hierarchy is the one a new setup would build: same results bit for bit
+    (fresh, fresh_out), = _serve_seq([p2], cache=0)
+    assert fresh.setup_reused == 0
+    for k in ("h", "tau", "c"):
+        assert np.array_equal(res[1][1][k], fresh_out[k]), k
+        assert np.array_equal(res[3][1][k], fresh_out[k]), k
+    # a budget with room for one request: the cached setup gives way
+    one = 40 * 36 * 24 * 1900 + (64 << 20)
+    res = _serve_seq([p1, other, p2], cache=4, budget=int(one * 1.02))
+    assert all(r.status == gw.OK for r, _ in res)
+    assert [r.setup_reused for r, _ in res] == [0, 0, 0]
