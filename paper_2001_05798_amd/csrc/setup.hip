@@ -477,17 +477,17 @@ __global__ void k_mis_m1(const int32_t *__restrict__ srow, const int32_t *__rest
 }
 
 // m2_i = max(m1_i, max_j m1_j); UNDECIDED i becomes ROOT if m2_i is its own
-// key, OUT if m2_i belongs to a ROOT.  Counts the nodes left undecided.
+// key, OUT if m2_i belongs to a ROOT.  Sets *und to 1 when a node is left
+// undecided (one plain store per wave that has one: the next round and the
+// host only ask whether any is left).
 template <int G>
 __global__ void k_mis_m2(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
                          uint32_t *__restrict__ state, uint32_t salt, const uint64_t *__restrict__ m1,
                          const int32_t *prev_und, int32_t *und) {
-    __shared__ int32_t sm[kBlock / dev::kWave];
     if (*prev_und == 0) return;
-    int32_t left = 0;
-    GRP_LOOP(G, n) {
-        const int32_t i = (int32_t)row_;
-        if (state[i] != ST_UND) continue;
+    GRP_ROW(G, n)
+    bool left = false;
+    if (has_ && state[i] == ST_UND) {
         uint64_t m = lane_ == 0 ? m1[i] : 0ull;
         const int32_t e = srow[i + 1];
         for (int32_t p = srow[i] + lane_; p < e; p += G) {
@@ -498,11 +498,10 @@ __global__ void k_mis_m2(const int32_t *__restrict__ srow, const int32_t *__rest
         if (lane_ == 0) {
             if (m == mis_key(ST_UND, salt, i)) state[i] = ST_ROOT;
             else if ((m >> 62) == ST_ROOT) state[i] = ST_OUT;
-            else left += 1;
+            else left = true;
         }
     }
-    left = dev::block_sum(left, sm);
-    if (threadIdx.x == 0 && left) atomicAdd(und, left);
+    if (__any(left) && (threadIdx.x & (dev::kWave - 1)) == 0) *und = 1;
 }
 
 // ------------------------------------------------------------- aggregates --
@@ -1399,8 +1398,8 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
                 const dim3 grid(blocks_for((int64_t)n * G));
                 hipLaunchKernelGGL((k_mis_m1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
                                    m1.p, und.p + r);
-                hipLaunchKernelGGL((k_mis_m2<G>), dim3(std::min(grid.x, kAtomicBlocks)), dim3(kBlock), 0, s,
-                                   S.rowptr.p, S.col.p, n, state.p, salt, m1.p, und.p + r, und.p + r + 1);
+                hipLaunchKernelGGL((k_mis_m2<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
+                                   m1.p, und.p + r, und.p + r + 1);
             });
         }
         GW_HIP(hipGetLastError());
