@@ -148,6 +148,11 @@ def test_sweep_large_synthetic_heads(gw, ref):
     lev = gw.tt_solve_direct(g, dev(qx), dev(qy), dev(qz), p.phi, (0, g.ny, 0, g.nz // 2), tau, c)
     _say(f"  levels {lev}")
     assert np.array_equal(host(tau), want_t) and np.array_equal(host(c), want_c)
+    # the general CSR sweep on the same system: its frontiers (up to 11k cells)
+    # overflow the LDS queues into HBM
+    got, lev2 = _gpu_sweep(gw, At, [bt, bc])
+    assert lev2 == lev
+    assert np.array_equal(got[0], want_t) and np.array_equal(got[1], want_c)
 
 
 def _wells_problem():
