@@ -1120,93 +1120,145 @@ int spgemm_group(double avg_a_len) {
     return 64;
 }
 
-// C = (A-side) x (B-side) with fixed summation order; C has `ncols` columns.
-// Two host reads: the row bound before the symbolic pass, then nnz, the
-// largest row and the overflow flag together.
-template <class AR, class BR, class EPI>
-void spgemm(AR ar, BR br, int32_t nrows, int32_t ncols, double avg_a_len, double avg_b_len, EPI epi, Csr &C,
-            hipStream_t s, Staging &st) {
-    DBuf<int32_t> ctr(8);  // [0] row bound, [1] largest row, [2] overflow, [4..5] nnz (int64)
-    int64_t *total = reinterpret_cast<int64_t *>(ctr.p + 4);
-    fill_i32(ctr.p, 0, 8, s);
-    {
-        ProfScope ps(K_SPGEMM, 0, s);
-        // short rows: one lane per row (the row sums are a few loads)
-        with_group(avg_a_len > 12.0 ? avg_a_len : 1.0, [&](auto gc) {
-            constexpr int GU = decltype(gc)::value;
-            hipLaunchKernelGGL((k_spgemm_ub<GU, AR, BR>), dim3(std::min(blocks_for((int64_t)nrows * GU), kAtomicBlocks)),
-                               dim3(kBlock), 0, s, ar, br, nrows, ctr.p);
-        });
-    }
-    int32_t ub = st.read(ctr.p, s);
-    int64_t cap = std::min<int64_t>(ub, ncols);
-    int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
-    C.alloc(nrows, ncols, 0);
-    fill_i32(C.rowptr.p, 0, 1, s);  // the symbolic pass writes every other row length
+// C = (A-side) x (B-side) with fixed summation order; C has `ncols` columns,
+// in three phases so that the host reads of a level can be merged: the row
+// bound (spgemm_bound, launched early; its value is read together with
+// other sizes), the symbolic pass (row lengths, nnz, largest row and
+// overflow into `blk`), and the numeric pass once those are on the host.
+// blk: [0] row bound, [1] largest row, [2] overflow, [4..5] nnz (int64).
+template <class AR, class BR>
+void spgemm_bound(AR ar, BR br, int32_t nrows, double avg_a_len, int32_t *blk, hipStream_t s) {
+    fill_i32(blk, 0, 1, s);
+    ProfScope ps(K_SPGEMM, 0, s);
+    // short rows: one lane per row (the row sums are a few loads)
+    with_group(avg_a_len > 12.0 ? avg_a_len : 1.0, [&](auto gc) {
+        constexpr int GU = decltype(gc)::value;
+        hipLaunchKernelGGL((k_spgemm_ub<GU, AR, BR>), dim3(std::min(blocks_for((int64_t)nrows * GU), kAtomicBlocks)),
+                           dim3(kBlock), 0, s, ar, br, nrows, blk);
+    });
+    GW_HIP(hipGetLastError());
+}
+
+struct SpgShape {
+    int G, S;
+};
+
+// Lanes per output row and the staging length.
+inline SpgShape spg_shape(double avg_a_len, double avg_b_len) {
     const int G = spgemm_group(avg_a_len);
     // stage: about one and a half average segments, 32..512 contributions,
     // rounded to 16 (LDS per row bounds the resident waves: no larger stage
     // than needed)
-    int S = std::max(32, std::min(512, ((int)(1.5 * G * avg_b_len) + 15) / 16 * 16));
+    const int S = std::max(32, std::min(512, ((int)(1.5 * G * avg_b_len) + 15) / 16 * 16));
+    return {G, S};
+}
+
+// Launch shape: groups per block, grid, LDS bytes, stage length.
+template <class K>
+void spg_launch(const SpgShape &sh, int32_t nrows, bool num, int hbits, K &&kern) {
     constexpr size_t kMaxLds = 64 * 1024;
-    auto launch = [&](auto kern, bool num, int hbits) {
-        const size_t H = (size_t)1 << hbits;
-        const size_t per = num ? 12 : 4;
-        int Sx = S;
-        while (Sx > 32 && (H + Sx) * per > kMaxLds) Sx /= 2;
-        const size_t bytes_group = (H + Sx) * per;
-        int groups = (int)std::min<size_t>(kBlock / G, std::max<size_t>(1, kMaxLds / bytes_group));
-        if (groups >= dev::kWave / G) groups -= groups % (dev::kWave / G);  // whole waves
-        unsigned grid = (unsigned)((nrows + groups - 1) / groups);
-        if (grid == 0) grid = 1;
-        kern(dim3(grid), dim3(groups * G), groups * bytes_group, Sx);
-    };
-#define SPG_SYM(GG) hipLaunchKernelGGL((k_spgemm<GG, false, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hb, Sx, C.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, epi, ctr.p + 1, ctr.p + 2)
-#define SPG_NUM(GG) hipLaunchKernelGGL((k_spgemm<GG, true, AR, BR, EPI>), g, b, sh, s, ar, br, nrows, hbn, Sx, (int32_t *)nullptr, C.rowptr.p, C.col.p, C.val.p, epi, ctr.p + 1, ctr.p + 2)
+    const int G = sh.G;
+    const size_t H = (size_t)1 << hbits;
+    const size_t per = num ? 12 : 4;
+    int Sx = sh.S;
+    while (Sx > 32 && (H + Sx) * per > kMaxLds) Sx /= 2;
+    const size_t bytes_group = (H + Sx) * per;
+    int groups = (int)std::min<size_t>(kBlock / G, std::max<size_t>(1, kMaxLds / bytes_group));
+    if (groups >= dev::kWave / G) groups -= groups % (dev::kWave / G);  // whole waves
+    unsigned grid = (unsigned)((nrows + groups - 1) / groups);
+    if (grid == 0) grid = 1;
+    kern(dim3(grid), dim3(groups * G), groups * bytes_group, Sx);
+}
+
+template <class AR, class BR, class EPI>
+void spgemm_symbolic(AR ar, BR br, EPI epi, int32_t nrows, int32_t ncols, double avg_a_len, double avg_b_len,
+                     int32_t ub, Csr &C, int32_t *blk, hipStream_t s) {
+    const int64_t cap = std::min<int64_t>(ub, ncols);
+    const int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
+    C.alloc(nrows, ncols, 0);
+    fill_i32(C.rowptr.p, 0, 1, s);  // the symbolic pass writes every other row length
+    fill_i32(blk + 1, 0, 5, s);
+    const SpgShape sh = spg_shape(avg_a_len, avg_b_len);
+#define SPG_SYM(GG)                                                                                           \
+    hipLaunchKernelGGL((k_spgemm<GG, false, AR, BR, EPI>), g, b, shm, s, ar, br, nrows, hb, Sx, C.rowptr.p, \
+                       (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, epi, blk + 1, blk + 2)
     {
         ProfScope ps(K_SPGEMM, 0, s);
-        auto sym = [&](dim3 g, dim3 b, size_t sh, int Sx) {
-            switch (G) {
+        spg_launch(sh, nrows, false, hb, [&](dim3 g, dim3 b, size_t shm, int Sx) {
+            switch (sh.G) {
                 case 8: SPG_SYM(8); break;
                 case 16: SPG_SYM(16); break;
                 case 32: SPG_SYM(32); break;
                 default: SPG_SYM(64); break;
             }
-        };
-        launch(sym, false, hb);
+        });
         GW_HIP(hipGetLastError());
     }
-    scan_inclusive_i32(C.rowptr.p + 1, nrows, total, s, ctr.p + 1);
-    int32_t info[8];
-    GW_HIP(hipMemcpyAsync(st.pin.p, ctr.p, sizeof(info), hipMemcpyDeviceToHost, s));
-    GW_HIP(hipStreamSynchronize(s));
-    std::memcpy(info, st.pin.p, sizeof(info));
+#undef SPG_SYM
+    scan_inclusive_i32(C.rowptr.p + 1, nrows, reinterpret_cast<int64_t *>(blk + 4), s, blk + 1);
+}
+
+// hblk: the host copy of blk after the symbolic pass.
+template <class AR, class BR, class EPI>
+void spgemm_numeric(AR ar, BR br, EPI epi, int32_t nrows, double avg_a_len, double avg_b_len, const int32_t *hblk,
+                    Csr &C, int32_t *blk, hipStream_t s) {
     int64_t nnz;
-    std::memcpy(&nnz, &info[4], sizeof(nnz));
-    const int32_t maxd = info[1];
-    if (info[2]) fail(GW_EINVAL, "amg_setup: a Galerkin row has more than 4096 distinct columns");
+    std::memcpy(&nnz, &hblk[4], sizeof(nnz));
+    const int32_t maxd = hblk[1];
+    if (hblk[2]) fail(GW_EINVAL, "amg_setup: a Galerkin row has more than 4096 distinct columns");
     GW_REQUIRE(nnz < INT32_MAX, "amg_setup: operator exceeds 2^31 nonzeros");
     C.nnz = nnz;
     C.col.alloc((size_t)nnz);
     C.val.alloc((size_t)nnz);
     // numeric table: at least 1.5 slots per column of the longest row
     const int hbn = std::min(pow2_bits_at_least((int64_t)(1.5 * std::max<int32_t>(maxd, 1))), kMaxHashBits);
+    const SpgShape sh = spg_shape(avg_a_len, avg_b_len);
+#define SPG_NUM(GG)                                                                                        \
+    hipLaunchKernelGGL((k_spgemm<GG, true, AR, BR, EPI>), g, b, shm, s, ar, br, nrows, hbn, Sx,          \
+                       (int32_t *)nullptr, C.rowptr.p, C.col.p, C.val.p, epi, blk + 1, blk + 2)
     {
         ProfScope ps(K_SPGEMM, 0, s);
-        auto num = [&](dim3 g, dim3 b, size_t sh, int Sx) {
-            switch (G) {
+        spg_launch(sh, nrows, true, hbn, [&](dim3 g, dim3 b, size_t shm, int Sx) {
+            switch (sh.G) {
                 case 8: SPG_NUM(8); break;
                 case 16: SPG_NUM(16); break;
                 case 32: SPG_NUM(32); break;
                 default: SPG_NUM(64); break;
             }
-        };
-        launch(num, true, hbn);
+        });
         GW_HIP(hipGetLastError());
     }
-#undef SPG_SYM
 #undef SPG_NUM
 }
+
+// Device words of one level read back together at a few host reads.
+//   [0..1] strength-graph nnz, [4..5] aggregates, [8..15] P, [16..23] AP,
+//   [24..31] A_c (each an spgemm blk).
+constexpr int kLevelWords = 32;
+struct LevelReads {
+    DBuf<int32_t> d;
+    int32_t h[kLevelWords] = {};
+    explicit LevelReads(hipStream_t s) : d(kLevelWords) { fill_i32(d.p, 0, kLevelWords, s); }
+    int32_t *blk(int k) { return d.p + 8 + 8 * k; }  // 0: P, 1: AP, 2: A_c
+    const int32_t *hblk(int k) const { return h + 8 + 8 * k; }
+    int64_t *total(int word) { return reinterpret_cast<int64_t *>(d.p + word); }
+    int64_t h64(int word) const {
+        int64_t v;
+        std::memcpy(&v, h + word, sizeof(v));
+        return v;
+    }
+    // Copy the words (and `extra_bytes` from `extra` behind them) to the host
+    // in one synchronisation.
+    void sync(hipStream_t s, const void *extra = nullptr, size_t extra_bytes = 0, void *extra_out = nullptr) {
+        char *stage = static_cast<char *>(host_stage());
+        static_assert(kLevelWords * sizeof(int32_t) + 64 <= kHostStageBytes, "level words fit the pinned stage");
+        GW_HIP(hipMemcpyAsync(stage, d.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        if (extra_bytes) GW_HIP(hipMemcpyAsync(stage + sizeof(h), extra, extra_bytes, hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        std::memcpy(h, stage, sizeof(h));
+        if (extra_bytes) std::memcpy(extra_out, stage + sizeof(h), extra_bytes);
+    }
+};
 
 void csr_diag(const CsrView &A, double *diag, hipStream_t s) {
     with_group(mean_row(A.nnz, A.n), [&](auto gc) {
@@ -1353,29 +1405,31 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             default: grp(std::integral_constant<int, 64>()); break;
         }
     };
+    LevelReads rd(s);
     {
         ProfScope ps(K_STRENGTH, (double)A.nnz * 24 + n * 16.0, s);
         launch_strength(false);
         GW_HIP(hipGetLastError());
     }
-    scan_inclusive_i32(S.rowptr.p + 1, n, total.p, s);
-    S.nnz = st.read(total.p, s);
-    S.col.alloc((size_t)std::max<int64_t>(S.nnz, 1));
-    sw.alloc((size_t)std::max<int64_t>(S.nnz, 1));
+    // the graph's size is read later, with the MIS-2 flags: its arrays take
+    // the bound (A's off-diagonal pattern, and that of A^T when not symmetric)
+    scan_inclusive_i32(S.rowptr.p + 1, n, rd.total(0), s);
+    const int64_t s_cap = std::max<int64_t>(sym ? A.nnz : A.nnz + T.nnz, 1);
+    S.col.alloc((size_t)s_cap);
+    sw.alloc((size_t)s_cap);
     {
-        ProfScope ps(K_STRENGTH, (double)A.nnz * 25 + n * 24.0 + S.nnz * 12.0, s);
+        ProfScope ps(K_STRENGTH, (double)A.nnz * 25 + n * 24.0, s);
         launch_strength(true);
         GW_HIP(hipGetLastError());
     }
-    T = Csr();
-    tval_sym.release();
-    Lv.nnz_s = S.nnz;
 
-    // MIS-2 rounds, batched between host checks; a round after the last
-    // decision is a no-op
+    // MIS-2 rounds, batched between host reads; a round after the last
+    // decision is a no-op.  After each batch the aggregates and the row bound
+    // of the prolongator product are formed from the states reached, and read
+    // back with the round flags: they are final when the rounds have ended.
     DBuf<uint32_t> state(n);
     DBuf<uint64_t> m1(n);
-    constexpr int kMaxRounds = 4096, kBatch = 8;
+    constexpr int kMaxRounds = 4096, kBatch = 12;
     DBuf<int32_t> und(kMaxRounds + 1);
     fill_i32(und.p, 0, kMaxRounds + 1, s);
     const uint32_t salt = level_salt(prm.seed, l);
@@ -1385,14 +1439,20 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
                            state.p, und.p);
         GW_HIP(hipGetLastError());
     }
+    // lanes per row from A's off-diagonal row length (the graph's own size is
+    // not on the host yet; it is a subset of those entries)
+    const double srow_mean = mean_row(A.nnz - n, n);
+    DBuf<int32_t> ids((size_t)n + 1), agg1(n);
+    Lv.agg.alloc(n);
+    ARowFiltered af{A.rowptr, A.col, A.val, strongA.p, dF.p};
+    BTent bt{Lv.agg.p};
+    const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
     int rounds = 0;
-    const double srow_mean = mean_row(S.nnz, n);
-    int32_t left = st.read(und.p, s);
-    while (left > 0) {
+    for (;;) {
         GW_REQUIRE(rounds + kBatch <= kMaxRounds, "amg_setup: MIS-2 did not terminate");
         for (int b = 0; b < kBatch; ++b) {
             int r = rounds + b;
-            ProfScope ps(K_MIS2, (double)S.nnz * 8 + n * 20.0, s);
+            ProfScope ps(K_MIS2, (double)A.nnz * 8 + n * 20.0, s);
             with_group(srow_mean, [&](auto gc) {
                 constexpr int G = decltype(gc)::value;
                 const dim3 grid(blocks_for((int64_t)n * G));
@@ -1403,41 +1463,39 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             });
         }
         GW_HIP(hipGetLastError());
-        std::vector<int32_t> h(kBatch);
-        GW_HIP(hipMemcpyAsync(st.pin.p, und.p + rounds + 1, kBatch * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        GW_HIP(hipStreamSynchronize(s));
-        std::memcpy(h.data(), st.pin.p, kBatch * sizeof(int32_t));
+        {
+            ProfScope ps(K_AGGREGATE, (double)A.nnz * 16 + n * 24.0, s);
+            hipLaunchKernelGGL(k_root_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, state.p, n, ids.p);
+            scan_inclusive_i32(ids.p + 1, n, rd.total(4), s);
+            with_group(srow_mean, [&](auto gc) {
+                constexpr int G = decltype(gc)::value;
+                const dim3 grid(blocks_for((int64_t)n * G));
+                hipLaunchKernelGGL((k_agg_pass1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, ids.p,
+                                   agg1.p);
+                hipLaunchKernelGGL((k_agg_pass2<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, sw.p, n, agg1.p,
+                                   Lv.agg.p);
+            });
+            GW_HIP(hipGetLastError());
+        }
+        spgemm_bound(af, bt, n, arow, rd.blk(0), s);
+        int32_t flags[kBatch + 1];
+        rd.sync(s, und.p + rounds, sizeof(flags), flags);
+        if (flags[0] == 0) break;  // nothing was undecided before this batch
         int b = 0;
-        while (b < kBatch && h[b] > 0) ++b;
+        while (b < kBatch && flags[1 + b] > 0) ++b;
         if (b < kBatch) {
             rounds += b + 1;
-            left = 0;
-        } else {
-            rounds += kBatch;
-            left = h[kBatch - 1];
+            break;
         }
+        rounds += kBatch;
     }
     Lv.mis_rounds = rounds;
     m1.release();
-
-    // aggregates
-    DBuf<int32_t> ids((size_t)n + 1), agg1(n);
-    Lv.agg.alloc(n);
-    {
-        ProfScope ps(K_AGGREGATE, (double)S.nnz * 16 + n * 24.0, s);
-        hipLaunchKernelGGL(k_root_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, state.p, n, ids.p);
-        scan_inclusive_i32(ids.p + 1, n, total.p, s);
-        with_group(srow_mean, [&](auto gc) {
-            constexpr int G = decltype(gc)::value;
-            const dim3 grid(blocks_for((int64_t)n * G));
-            hipLaunchKernelGGL((k_agg_pass1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, ids.p,
-                               agg1.p);
-            hipLaunchKernelGGL((k_agg_pass2<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, sw.p, n, agg1.p,
-                               Lv.agg.p);
-        });
-        GW_HIP(hipGetLastError());
-    }
-    const int64_t nc = st.read(total.p, s);
+    S.nnz = rd.h64(0);
+    Lv.nnz_s = S.nnz;
+    T = Csr();
+    tval_sym.release();
+    const int64_t nc = rd.h64(4);
     Lv.nc = (int32_t)nc;
     if (nc == 0 || (double)nc > 0.9 * (double)n) {
         *is_coarsest = true;
@@ -1461,23 +1519,34 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         hipLaunchKernelGGL(k_omega, dim3(1), dim3(64), 0, s, rho_bits.p, omega.p);
         GW_HIP(hipGetLastError());
     }
-    ARowFiltered af{A.rowptr, A.col, A.val, strongA.p, dF.p};
-    BTent bt{Lv.agg.p};
     EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
-    const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
-    spgemm(af, bt, n, (int32_t)nc, arow, 1.0, ep, Lv.P, s, st);
+    // P: symbolic pass, then the row bound of A P (it needs only P's row
+    // pointers), one read for both
+    spgemm_symbolic(af, bt, ep, n, (int32_t)nc, arow, 1.0, rd.hblk(0)[0], Lv.P, rd.blk(0), s);
+    spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s);
+    rd.sync(s);
+    spgemm_numeric(af, bt, ep, n, arow, 1.0, rd.hblk(0), Lv.P, rd.blk(0), s);
 
-    // R = P^T, A_c = R (A P)
+    // R = P^T, A_c = R (A P): the symbolic pass of A P, then the row bound of
+    // R (A P), one read for both
     transpose(view(Lv.P), Lv.R, s, total.p);
     Csr AP;
     const double pavg = (double)Lv.P.nnz / std::max<int32_t>(n, 1);
-    spgemm(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p}, n, (int32_t)nc, arow,
-           pavg, EpiIdentity{}, AP, s, st);
+    const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
+    const ARowCsr a_side{A.rowptr, A.col, A.val};
+    const BCsr p_side{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p};
+    spgemm_symbolic(a_side, p_side, EpiIdentity{}, n, (int32_t)nc, arow, pavg, rd.hblk(1)[0], AP, rd.blk(1), s);
+    const ARowCsr r_side{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p};
+    spgemm_bound(r_side, BCsr{AP.rowptr.p, nullptr, nullptr}, (int32_t)nc, ravg, rd.blk(2), s);
+    rd.sync(s);
+    spgemm_numeric(a_side, p_side, EpiIdentity{}, n, arow, pavg, rd.hblk(1), AP, rd.blk(1), s);
     Level &Nx = H->L[l + 1];
     const double apavg = (double)AP.nnz / std::max<int32_t>(n, 1);
-    const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
-    spgemm(ARowCsr{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p}, BCsr{AP.rowptr.p, AP.col.p, AP.val.p}, (int32_t)nc,
-           (int32_t)nc, ravg, apavg, EpiIdentity{}, Nx.A, s, st);
+    const BCsr ap_side{AP.rowptr.p, AP.col.p, AP.val.p};
+    spgemm_symbolic(r_side, ap_side, EpiIdentity{}, (int32_t)nc, (int32_t)nc, ravg, apavg, rd.hblk(2)[0], Nx.A,
+                    rd.blk(2), s);
+    rd.sync(s);
+    spgemm_numeric(r_side, ap_side, EpiIdentity{}, (int32_t)nc, ravg, apavg, rd.hblk(2), Nx.A, rd.blk(2), s);
 }
 
 void make_smoother(amg_hierarchy *H, int l, hipStream_t s) {
