@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "libgwref.so")
 
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 EINVAL, SINGULAR = -1, -3
-JACOBI, SPAI0, NONE = 0, 1, 2
+JACOBI, SPAI0, NONE, ILU0 = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -94,6 +94,8 @@ def _declare(L):
     L.ref_hier_level_sizes.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+    L.ref_hier_level_ilu.restype = C.c_int
+    L.ref_hier_level_ilu.argtypes = [C.c_void_p, C.c_int, C.c_void_p]
     L.ref_hier_level_copy.restype = None
     L.ref_hier_level_copy.argtypes = [C.c_void_p, C.c_int] + [C.c_void_p] * 9
     L.ref_hier_coarse_copy.restype = None
@@ -285,6 +287,14 @@ class Hierarchy:
     @property
     def nlevels(self) -> int:
         return int(_L().ref_hier_nlevels(self._h))
+
+    def level_ilu(self, l: int) -> np.ndarray:
+        """ILU(0) factors of level l on its matrix's pattern (smoother ILU0)."""
+        lv = self.level(l)
+        out = np.zeros(lv.A.nnz)
+        if _L().ref_hier_level_ilu(self._h, l, _p(out)) != OK:
+            raise ValueError("no ILU(0) factors on this level")
+        return out
 
     def level(self, l: int) -> Level:
         L = _L()

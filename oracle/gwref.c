@@ -42,6 +42,7 @@
 #define SM_JACOBI 0
 #define SM_SPAI0 1
 #define SM_NONE 2
+#define SM_ILU0 3
 
 #define ST_OUT 0u
 #define ST_UNDECIDED 1u
@@ -59,7 +60,7 @@ typedef struct {
 
 typedef struct {
     double eps_strong;   /* epsilon_0 of the strength test                */
-    int32_t smoother;    /* SM_JACOBI | SM_SPAI0 | SM_NONE                */
+    int32_t smoother;    /* SM_JACOBI | SM_SPAI0 | SM_NONE | SM_ILU0      */
     double omega;        /* Jacobi damping                                 */
     int32_t npre, npost; /* smoothing sweeps                               */
     int32_t n_coarse;    /* stop coarsening at or below this size          */
@@ -74,6 +75,10 @@ typedef struct {
     int32_t *state;     /* final MIS-2 state                               */
     int32_t nc;         /* number of aggregates                            */
     double *M;          /* smoother diagonal                               */
+    double *ilu;        /* ILU(0) factors on A's pattern (SM_ILU0): L below
+                           the diagonal (unit diagonal implied), U on and
+                           above it                                        */
+    int32_t *dpos;      /* position of each row's diagonal entry           */
     double omega_p;     /* prolongator smoothing weight                    */
     int64_t nnz_s;      /* strength-graph edges                            */
     int32_t mis_rounds;
@@ -782,6 +787,55 @@ static void smoother_diag(const rcsr *A, const ref_params *prm, double *M) {
     }
 }
 
+/* ILU(0): the incomplete LU factorization on A's own pattern (Results: the
+ * relaxation used throughout).  Row by row in ascending order, and in each
+ * row over its lower entries k in ascending column order: l_ik = a_ik / u_kk,
+ * then a_ij = a_ij - l_ik u_kj for every later entry j of row i that row k
+ * also holds.  Returns REF_SINGULAR for a zero pivot. */
+static int ilu0(const rcsr *A, double *ilu, int32_t *dpos) {
+    memcpy(ilu, A->val, (size_t)A->nnz * sizeof(double));
+    for (int32_t i = 0; i < A->n; ++i) {
+        dpos[i] = -1;
+        for (int32_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
+            if (A->col[p] == i) dpos[i] = p;
+        if (dpos[i] < 0) return REF_SINGULAR;
+    }
+    for (int32_t i = 0; i < A->n; ++i) {
+        const int32_t e = A->rowptr[i + 1];
+        for (int32_t p = A->rowptr[i]; p < e && A->col[p] < i; ++p) {
+            const int32_t k = A->col[p];
+            const double ukk = ilu[dpos[k]];
+            if (ukk == 0.0) return REF_SINGULAR;
+            const double lik = ilu[p] / ukk;
+            ilu[p] = lik;
+            int32_t r = dpos[k] + 1;
+            const int32_t ek = A->rowptr[k + 1];
+            for (int32_t q = p + 1; q < e; ++q) {
+                const int32_t j = A->col[q];
+                while (r < ek && A->col[r] < j) ++r;
+                if (r < ek && A->col[r] == j) ilu[q] = ilu[q] - lik * ilu[r];
+            }
+        }
+        if (ilu[dpos[i]] == 0.0) return REF_SINGULAR;
+    }
+    return REF_OK;
+}
+
+/* t <- (LU)^{-1} t in place: forward substitution with the unit lower factor,
+ * then backward substitution with U, each row's terms in column order. */
+static void ilu_solve(const rcsr *A, const double *ilu, const int32_t *dpos, double *t) {
+    for (int32_t i = 0; i < A->n; ++i) {
+        double s = t[i];
+        for (int32_t p = A->rowptr[i]; p < dpos[i]; ++p) s = s - ilu[p] * t[A->col[p]];
+        t[i] = s;
+    }
+    for (int32_t i = A->n - 1; i >= 0; --i) {
+        double s = t[i];
+        for (int32_t p = dpos[i] + 1; p < A->rowptr[i + 1]; ++p) s = s - ilu[p] * t[A->col[p]];
+        t[i] = s / ilu[dpos[i]];
+    }
+}
+
 static void copy_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, rcsr *A) {
     csr_alloc(A, n, n, rowptr[n]);
     memcpy(A->rowptr, rowptr, ((size_t)n + 1) * sizeof(int32_t));
@@ -844,7 +898,18 @@ ref_hier *ref_amg_setup(int32_t n, const int32_t *rowptr, const int32_t *col, co
             break;
         }
         L->M = (double *)xcalloc((size_t)nl, sizeof(double));
-        smoother_diag(&L->A, prm, L->M);
+        if (prm->smoother == SM_ILU0) {
+            L->ilu = (double *)xcalloc((size_t)L->A.nnz, sizeof(double));
+            L->dpos = (int32_t *)xcalloc((size_t)nl, sizeof(int32_t));
+            if (ilu0(&L->A, L->ilu, L->dpos) != REF_OK) {
+                free(strongA);
+                *status = REF_SINGULAR;
+                H->nlevels = l + 1;
+                break;
+            }
+        } else {
+            smoother_diag(&L->A, prm, L->M);
+        }
         L->omega_p = smooth_prolongator(&L->A, strongA, L->agg, L->nc, &L->P);
         free(strongA);
         transpose(&L->P, &L->R);
@@ -865,6 +930,8 @@ void ref_amg_free(ref_hier *H) {
     if (!H) return;
     for (int l = 0; l < REF_MAX_LEVELS; ++l) {
         ref_level *L = &H->L[l];
+        free(L->ilu);
+        free(L->dpos);
         csr_free(&L->A); csr_free(&L->P); csr_free(&L->R);
         free(L->agg); free(L->state); free(L->M);
         for (int t = 0; t < 3; ++t) free(H->work[l][t]);
@@ -882,6 +949,14 @@ void ref_hier_level_sizes(const ref_hier *H, int l, int32_t *n, int64_t *nnz, in
     *n = L->A.n; *nnz = L->A.nnz; *nc = L->nc; *nnz_p = L->P.nnz;
     *omega_p = L->omega_p; *rounds = L->mis_rounds; *nnz_s = L->nnz_s;
 }
+/* ILU(0) factors of level l (A's pattern), when the smoother is SM_ILU0. */
+int ref_hier_level_ilu(const ref_hier *H, int l, double *ilu) {
+    const ref_level *L = &H->L[l];
+    if (!L->ilu) return REF_EINVAL;
+    memcpy(ilu, L->ilu, (size_t)L->A.nnz * sizeof(double));
+    return REF_OK;
+}
+
 void ref_hier_level_copy(const ref_hier *H, int l, int32_t *a_rowptr, int32_t *a_col, double *a_val,
                          int32_t *agg, int32_t *state, double *M, int32_t *p_rowptr, int32_t *p_col,
                          double *p_val) {
@@ -915,7 +990,14 @@ static void smooth_sweeps(const ref_level *L, const double *b, double *x, double
     int32_t n = L->A.n;
     for (int s = 0; s < sweeps; ++s) {
         spmv(&L->A, x, t);
-        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + L->M[i] * (b[i] - t[i]);
+        if (L->ilu) {
+            /* x <- x + (LU)^{-1} (b - A x) */
+            for (int32_t i = 0; i < n; ++i) t[i] = b[i] - t[i];
+            ilu_solve(&L->A, L->ilu, L->dpos, t);
+            for (int32_t i = 0; i < n; ++i) x[i] = x[i] + t[i];
+        } else {
+            for (int32_t i = 0; i < n; ++i) x[i] = x[i] + L->M[i] * (b[i] - t[i]);
+        }
     }
 }
 
