@@ -45,7 +45,7 @@ extern "C" {
 #define GW_EDEVICE (-4)    /* HIP runtime error                              */
 #define GW_EAGAIN (-5)     /* queue full                                     */
 
-enum { GW_SMOOTHER_JACOBI = 0, GW_SMOOTHER_SPAI0 = 1, GW_SMOOTHER_NONE = 2 };
+enum { GW_SMOOTHER_JACOBI = 0, GW_SMOOTHER_SPAI0 = 1, GW_SMOOTHER_NONE = 2, GW_SMOOTHER_ILU0 = 3 };
 enum { GW_PRECISION_FP64 = 0, GW_PRECISION_MIXED = 1 };
 
 /* ---- plain data --------------------------------------------------------- */
@@ -74,7 +74,10 @@ typedef struct { int32_t j0, j1, k0, k1; } gw_zone;
 
 /* Smoothed-aggregation parameters.
  *   eps_strong  strength threshold eps_0 (halved every level)       [0.08]
- *   smoother    GW_SMOOTHER_*; NONE disables the preconditioner      [SPAI0]
+ *   smoother    GW_SMOOTHER_*; NONE disables the preconditioner; ILU0 [SPAI0]
+ *               is the paper's relaxation (incomplete LU on each level's
+ *               pattern, applied by level-scheduled substitutions: a
+ *               baseline, FP64 only, pair solves run one system at a time)
  *   omega       damping of the Jacobi smoother                       [2/3]
  *   npre/npost  smoothing sweeps before/after the coarse correction  [2/2]
  *   n_coarse    a level of at most this many rows is the coarsest    [500]
@@ -216,6 +219,11 @@ int amg_level_export(const amg_hierarchy *H, int32_t level, int32_t *a_rowptr, i
  * diagonal), pivot rows (LAPACK getrf order) and the inverse used by the
  * V-cycle (row-major nd x nd).  [device]; any may be NULL. */
 int amg_coarse_export(const amg_hierarchy *H, double *lu, int32_t *piv, double *inv, void *stream);
+
+/* ILU(0) factors of level l (smoother GW_SMOOTHER_ILU0), on A_l's pattern:
+ * L below the diagonal (unit diagonal implied), U on and above it.
+ * lu [device] nnz of A_l.  EINVAL for a level without them. */
+int amg_ilu_export(const amg_hierarchy *H, int32_t level, double *lu, void *stream);
 
 void amg_free(amg_hierarchy *H);
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgwamg.so")
 
 OK, NOT_CONVERGED, BREAKDOWN, PENDING = 0, 1, 2, 3
 EINVAL, ENOMEM, SINGULAR, EDEVICE, EAGAIN = -1, -2, -3, -4, -5
-SMOOTHER_JACOBI, SMOOTHER_SPAI0, SMOOTHER_NONE = 0, 1, 2
+SMOOTHER_JACOBI, SMOOTHER_SPAI0, SMOOTHER_NONE, SMOOTHER_ILU0 = 0, 1, 2, 3
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 TT_EPS_STRONG = 0.25
 
@@ -130,6 +130,7 @@ def _load():
         "amg_hierarchy_info": (C.c_int, [vp, C.POINTER(LevelInfoC), i32, C.POINTER(i32), C.POINTER(C.c_size_t)]),
         "amg_level_export": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "amg_coarse_export": (C.c_int, [vp, vp, vp, vp, vp]),
+        "amg_ilu_export": (C.c_int, [vp, i32, vp, vp]),
         "amg_free": (None, [vp]),
         "tt_nnz_bound": (i64, [C.POINTER(GwGrid)]),
         "tt_assemble": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), vp, vp, vp, vp, vp,
@@ -498,6 +499,10 @@ def amg_level_export(H: Hierarchy, level: int, a_rowptr=None, a_col=None, a_val=
                      p_rowptr=None, p_col=None, p_val=None, stream=None) -> None:
     _check(_lib.amg_level_export(H.handle, int(level), _ptr(a_rowptr), _ptr(a_col), _ptr(a_val), _ptr(agg),
                                  _ptr(M), _ptr(p_rowptr), _ptr(p_col), _ptr(p_val), _stream(stream)))
+
+
+def amg_ilu_export(H: Hierarchy, level: int, lu, stream=None) -> None:
+    _check(_lib.amg_ilu_export(H.handle, int(level), _ptr(lu), _stream(stream)))
 
 
 def amg_coarse_export(H: Hierarchy, lu=None, piv=None, inv=None, stream=None) -> None:

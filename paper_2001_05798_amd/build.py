@@ -28,6 +28,7 @@ SOURCES = [
     ("solve.hip", False),
     ("sweep.hip", True),
     ("transient.hip", True),
+    ("ilu.hip", True),
     ("capi.cpp", False),
     ("serve.cpp", False),
 ]

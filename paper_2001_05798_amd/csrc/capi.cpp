@@ -54,8 +54,10 @@ int64_t nnz7(const gw_grid *g) {
 
 void check_params(const amg_params *p) {
     GW_REQUIRE(p, "null amg_params");
-    GW_REQUIRE(p->smoother >= GW_SMOOTHER_JACOBI && p->smoother <= GW_SMOOTHER_NONE, "unknown smoother");
+    GW_REQUIRE(p->smoother >= GW_SMOOTHER_JACOBI && p->smoother <= GW_SMOOTHER_ILU0, "unknown smoother");
     GW_REQUIRE(p->precision == GW_PRECISION_FP64 || p->precision == GW_PRECISION_MIXED, "unknown precision");
+    GW_REQUIRE(!(p->smoother == GW_SMOOTHER_ILU0 && p->precision == GW_PRECISION_MIXED),
+               "the ILU(0) smoother needs the FP64 hierarchy");
     GW_REQUIRE(p->npre >= 0 && p->npost >= 0 && p->npre <= 16 && p->npost <= 16, "sweeps must be in [0, 16]");
     GW_REQUIRE(p->n_coarse >= 1 && p->max_levels >= 1, "n_coarse and max_levels must be positive");
     GW_REQUIRE(p->eps_strong >= 0 && std::isfinite(p->eps_strong), "eps_strong must be >= 0");
@@ -140,8 +142,12 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     for (int l = 0; l < H->nlev; ++l) {
         Level &Lv = H->L[l];
         if (l < H->nlev - 1) {
-            make_smoother(H.get(), l, s);
-            if (H->mixed()) convert_level_fp32(H.get(), l, s);
+            if (prm->smoother == GW_SMOOTHER_ILU0) {
+                build_ilu0(H.get(), l, s);
+            } else {
+                make_smoother(H.get(), l, s);
+                if (H->mixed()) convert_level_fp32(H.get(), l, s);
+            }
         }
         const size_t n = (size_t)Lv.A.n;
         Lv.vx.alloc(n * es);
@@ -390,6 +396,17 @@ int amg_coarse_export(const amg_hierarchy *H, double *lu, int32_t *piv, double *
         if (lu) copy_bytes(lu, H->lu.p, H->lu.bytes(), s);
         if (piv) copy_bytes(piv, H->piv.p, H->piv.bytes(), s);
         if (inv) copy_bytes(inv, H->inv.p, H->inv.bytes(), s);
+        finish(s);
+        return GW_OK;
+    });
+}
+
+int amg_ilu_export(const amg_hierarchy *H, int32_t level, double *lu, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H && lu, "amg_ilu_export: null pointer");
+        GW_REQUIRE(level >= 0 && level < H->nlev && H->L[level].ilu, "amg_ilu_export: level has no ILU(0) factors");
+        hipStream_t s = as_stream(stream);
+        copy_bytes(lu, H->L[level].ilu->lu.p, H->L[level].ilu->lu.bytes(), s);
         finish(s);
         return GW_OK;
     });

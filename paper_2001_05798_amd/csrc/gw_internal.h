@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <utility>
+#include <memory>
 #include <vector>
 
 #include "gwamg.h"
@@ -193,6 +194,31 @@ struct SellView {
 inline SellView view(const Sell &S) { return {S.n, S.ndict, S.soff.p, S.idx.p, S.col.p, S.dict.p}; }
 
 // ------------------------------------------------------------ hierarchy --
+// Level-synchronous schedule of a triangular (more generally acyclic) system
+// M x = b: per row its count of off-diagonal dependencies, the rows that
+// depend on it, and the rows with none; plus the work copies a run mutates.
+struct TriPlan {
+    Csr M;                       // the system, diagonal stored (unit for L)
+    DBuf<int32_t> indeg0, drow, dcol, q0;
+    DBuf<int64_t> first;         // size of the first frontier (device)
+    DBuf<int32_t> indeg, qa, qb; // per-run copies
+    DBuf<int64_t> out;
+    size_t bytes() const {
+        return M.bytes() + indeg0.bytes() + drow.bytes() + dcol.bytes() + q0.bytes() + indeg.bytes() + qa.bytes() +
+               qb.bytes();
+    }
+};
+
+// ILU(0) smoother of a level: the factors on A's pattern, the two triangles
+// as systems for the substitutions, and the vectors of one smoothing step.
+struct IluData {
+    DBuf<double> lu;
+    DBuf<int32_t> dpos;
+    TriPlan lo, up;
+    DBuf<double> r, y, z;
+    size_t bytes() const { return lu.bytes() + dpos.bytes() + lo.bytes() + up.bytes() + r.bytes() * 3; }
+};
+
 struct Level {
     Csr A;           // operator A_l (level 0: copy of the caller's matrix)
     Sell As;         // sliced ELL copy of A_l used by the solve phase (level 0)
@@ -208,9 +234,10 @@ struct Level {
     // V-cycle vectors of this level, element size 8 (FP64) or 4 (mixed):
     // b (right-hand side), x (iterate) and t (ping-pong / residual)
     DBuf<char> vb, vx, vt;
+    std::unique_ptr<IluData> ilu;  // ILU(0) smoother (else the diagonal M)
     size_t bytes() const {
         return A.bytes() + As.bytes() + P.bytes() + R.bytes() + agg.bytes() + M.bytes() + M32.bytes() +
-               vb.bytes() + vx.bytes() + vt.bytes();
+               vb.bytes() + vx.bytes() + vt.bytes() + (ilu ? ilu->bytes() : 0);
     }
 };
 
@@ -338,6 +365,14 @@ void add_diagonal(const CsrView &C, const double *shift, double *val, hipStream_
 // A.n when the inflow graph has a cycle) and the number of levels.
 int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,
                      hipStream_t s);
+// Schedule of an acyclic system (built once), and one solve with it on one
+// right-hand side; skipped when *done is set.  The run does not read back.
+void sweep_plan(TriPlan &P, hipStream_t s);
+void sweep_run(TriPlan &P, const double *b, double *x, const int32_t *done, hipStream_t s);
+// ILU(0) smoother of level l (ilu.hip); EINVAL-style failure on a zero pivot.
+void build_ilu0(amg_hierarchy *H, int l, hipStream_t s);
+// z = (LU)^{-1} r with the level's factors.
+void ilu_apply(IluData &I, const double *r, double *z, const int32_t *done, hipStream_t s);
 // The same for an upwind matrix on the 7-point grid g (rows of at most the
 // six face neighbours), through one 64-byte record per row.
 int64_t grid_sweep(const gw_grid &g, const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,

@@ -344,6 +344,13 @@ __global__ void k_zero(X *x, int64_t n, const int32_t *done) {
     if (i < n) x[i] = (X)0;
 }
 
+// y = x + z (ILU(0) smoothing step; y may be x)
+__global__ void k_add(const double *x, const double *__restrict__ z, double *y, int64_t n, const int32_t *done) {
+    if (done && *done) return;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i] + z[i];
+}
+
 template <class Xt, class Yt>
 __global__ void k_convert(const Xt *__restrict__ x, Yt *__restrict__ y, int64_t n, const int32_t *done) {
     if (done && *done) return;
@@ -411,6 +418,75 @@ void with_level_op(const Level &Lv, F &&f) {
 // else into one of the level's own buffers, whose address is returned.  V =
 // value type of the hierarchy (also the type of all internal vectors).
 template <class V, class Bt, class Zt, int NR>
+void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s);
+
+// A level with the ILU(0) smoother (FP64, one right-hand side): each sweep is
+// x <- x + (LU)^{-1} (b - A x), the first from x = 0 being x = (LU)^{-1} b.
+template <class Zt>
+void *vcycle_level_ilu(amg_hierarchy *H, int l, const double *b, Zt *out, const int32_t *done, hipStream_t s) {
+    Level &Lv = H->L[l];
+    IluData &I = *Lv.ilu;
+    const int64_t n = Lv.A.n;
+    double *x = reinterpret_cast<double *>(Lv.vx.p);
+    double *t = reinterpret_cast<double *>(Lv.vt.p);
+    const int npre = H->prm.npre, npost = H->prm.npost;
+    const double abytes = op_bytes(Lv.A, Lv.As, 8);
+    auto residual = [&](const double *xin, double *r) {
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + n * 24.0, s);
+        with_level_op<double>(Lv, [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_residual<OP, double, double, double, double, 1>), dim3(grid_rows(n, OP::G)),
+                               dim3(kBlock), 0, s, n, op, b, xin, r, done);
+        });
+    };
+    auto step = [&](double *xio, double *dst) {  // dst = x + (LU)^{-1}(b - A x)
+        residual(xio, I.r.p);
+        ilu_apply(I, I.r.p, I.z.p, done, s);
+        hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(kBlock), 0, s, xio, I.z.p, dst, n, done);
+    };
+    if (npre == 0) {
+        hipLaunchKernelGGL((k_zero<double>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, n, done);
+    } else {
+        ilu_apply(I, b, x, done, s);
+        for (int k = 1; k < npre; ++k) step(x, x);
+    }
+    residual(x, t);
+    Level &Nx = H->L[l + 1];
+    double *bc = reinterpret_cast<double *>(Nx.vb.p);
+    const int64_t nc = Lv.nc;
+    {
+        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, 8) + (double)(n + nc) * 8, s);
+        with_csr<double>(Lv.R, Lv.R.val.p, [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_spmv<OP, double, double, double, 1>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0,
+                               s, nc, op, t, bc, done);
+        });
+    }
+    double *xc = static_cast<double *>(vcycle_level<double, double, double, 1>(H, l + 1, bc, (double *)nullptr,
+                                                                               done, s));
+    {
+        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, 8) + (double)(2 * n + nc) * 8, s);
+        with_csr<double>(Lv.P, Lv.P.val.p, [&](auto op) {
+            using OP = decltype(op);
+            hipLaunchKernelGGL((k_prolong<OP, double, double, 1>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
+                               op, xc, x, done);
+        });
+    }
+    for (int k = 0; k < npost; ++k) {
+        if (k == npost - 1 && out && std::is_same_v<Zt, double>) {
+            step(x, reinterpret_cast<double *>(out));
+            return out;
+        }
+        step(x, x);
+    }
+    if (out) {
+        hipLaunchKernelGGL((k_convert<double, Zt>), dim3(blocks_for(n)), dim3(kBlock), 0, s, x, out, n, done);
+        return out;
+    }
+    return x;
+}
+
+template <class V, class Bt, class Zt, int NR>
 void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s) {
     Level &Lv = H->L[l];
     const int64_t n = Lv.A.n;
@@ -428,6 +504,9 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     V *x = reinterpret_cast<V *>(Lv.vx.p);
     V *t = reinterpret_cast<V *>(Lv.vt.p);
     const int npre = H->prm.npre, npost = H->prm.npost;
+    if constexpr (std::is_same_v<V, double> && std::is_same_v<Bt, double> && NR == 1) {
+        if (Lv.ilu) return vcycle_level_ilu<Zt>(H, l, b, out, done, s);
+    }
 
     // pre-smoothing
     if (npre == 0) {
@@ -1468,6 +1547,12 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
 
 int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
                      const amg_solve_params &sp, amg_solve_info info[2], hipStream_t s) {
+    if (H->prm.smoother == GW_SMOOTHER_ILU0) {
+        // the substitution sweeps take one right-hand side: one system at a time
+        const int s0 = krylov_bicgstab(H, b0, x0, sp, &info[0], s);
+        const int s1 = krylov_bicgstab(H, b1, x1, sp, &info[1], s);
+        return std::max(s0, s1);
+    }
     const double t0 = now_ms();
     ensure_krylov_workspace(H, 20);
     ensure_level_vectors(H, 2);

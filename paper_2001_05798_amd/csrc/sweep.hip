@@ -63,6 +63,18 @@ __global__ void k_sw_first(int64_t n, const int32_t *__restrict__ flag, int32_t 
 }
 
 constexpr int kSweepThreads = 1024;
+
+// Work copies for one run of a stored schedule: the count-downs (and the
+// spare counters behind them), the first frontier and its size.
+__global__ void k_sweep_prep(int64_t n, const int32_t *__restrict__ indeg0, const int32_t *__restrict__ q0,
+                             const int64_t *__restrict__ first, int32_t *__restrict__ indeg, int32_t *__restrict__ qa,
+                             int64_t *out, const int32_t *done) {
+    if (done && *done) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n + kSweepThreads) indeg[i] = indeg0[i];
+    if (i < *first) qa[i] = q0[i];
+    if (i == 0) out[0] = *first;
+}
 constexpr int kQueueLds = 6144;  // frontier entries kept in LDS per buffer
 constexpr int kRowFast = 7;      // rows and downstream lists up to this length (a 7-point stencil): one batch of loads
 
@@ -148,7 +160,8 @@ __global__ void __launch_bounds__(kSweepThreads) k_sweep(CsrView A, int32_t *__r
                                                          const int32_t *__restrict__ drow,
                                                          const int32_t *__restrict__ dcol, int32_t nrhs,
                                                          const double *__restrict__ b, double *x, int32_t *qg0,
-                                                         int32_t *qg1, int64_t *out) {
+                                                         int32_t *qg1, int64_t *out, const int32_t *done) {
+    if (done && *done) return;
     __shared__ int32_t lq[2][kQueueLds];
     __shared__ int32_t cnt[3];
     const int64_t n = A.n;
@@ -473,7 +486,7 @@ int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x,
         // the operator, the right-hand sides and the solution once each
         ProfScope ps(K_SWEEP, (double)(n + 1) * 4 + (double)A.nnz * 12 + (double)n * nrhs * 16, s);
         hipLaunchKernelGGL(k_sweep, dim3(1), dim3(kSweepThreads), 0, s, A, indeg.p, drow.p, dcol.p, nrhs, b, x,
-                           q0.p, q1.p, out.p);
+                           q0.p, q1.p, out.p, (const int32_t *)nullptr);
         GW_HIP(hipGetLastError());
     }
     int64_t *stage = static_cast<int64_t *>(host_stage());
@@ -481,6 +494,44 @@ int64_t upwind_sweep(const CsrView &A, int32_t nrhs, const double *b, double *x,
     GW_HIP(hipStreamSynchronize(s));
     if (levels) *levels = (int32_t)stage[1];
     return stage[0];
+}
+
+void sweep_plan(TriPlan &P, hipStream_t s) {
+    const CsrView A = view(P.M);
+    const int64_t n = A.n;
+    P.indeg0.alloc((size_t)n + kSweepThreads);
+    P.drow.alloc((size_t)n + 1);
+    P.dcol.alloc((size_t)std::max<int64_t>(A.nnz - n, 1));
+    P.q0.alloc((size_t)std::max<int64_t>(n, 1));
+    P.first.alloc(1);
+    P.indeg.alloc((size_t)n + kSweepThreads);
+    P.qa.alloc((size_t)std::max<int64_t>(n, 1));
+    P.qb.alloc((size_t)std::max<int64_t>(n, 1));
+    P.out.alloc(2);
+    DBuf<int32_t> dfill(n), flag(n);
+    DBuf<int64_t> total(1);
+    ProfScope ps(K_SWEEP_LISTS, 2.0 * ((double)(n + 1) * 4 + (double)A.nnz * 4) + (double)A.nnz * 8 + n * 24.0, s);
+    fill_i32(P.drow.p, 0, n + 1, s);
+    fill_i32(dfill.p, 0, n, s);
+    fill_i32(P.indeg0.p + n, INT32_MAX, kSweepThreads, s);
+    hipLaunchKernelGGL(k_sw_count, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, P.indeg0.p, P.drow.p);
+    scan_inclusive_i32(P.drow.p + 1, n, total.p, s);
+    hipLaunchKernelGGL(k_sw_fill, dim3(blocks_for(n)), dim3(kBlock), 0, s, A, P.drow.p, dfill.p, P.dcol.p);
+    hipLaunchKernelGGL(k_sw_flag, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, P.indeg0.p, flag.p);
+    scan_inclusive_i32(flag.p, n, P.first.p, s);
+    hipLaunchKernelGGL(k_sw_first, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, flag.p, P.q0.p);
+    GW_HIP(hipGetLastError());
+}
+
+void sweep_run(TriPlan &P, const double *b, double *x, const int32_t *done, hipStream_t s) {
+    const CsrView A = view(P.M);
+    const int64_t n = A.n;
+    ProfScope ps(K_SWEEP, (double)(n + 1) * 4 + (double)A.nnz * 12 + (double)n * 16, s);
+    hipLaunchKernelGGL(k_sweep_prep, dim3(blocks_for(n + kSweepThreads)), dim3(kBlock), 0, s, n, P.indeg0.p, P.q0.p,
+                       P.first.p, P.indeg.p, P.qa.p, P.out.p, done);
+    hipLaunchKernelGGL(k_sweep, dim3(1), dim3(kSweepThreads), 0, s, A, P.indeg.p, P.drow.p, P.dcol.p, 1, b, x, P.qa.p,
+                       P.qb.p, P.out.p, done);
+    GW_HIP(hipGetLastError());
 }
 
 int64_t grid_sweep(const gw_grid &g, const CsrView &A, int32_t nrhs, const double *b, double *x, int32_t *levels,

@@ -21,7 +21,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ["fv_assemble", "amg_setup", "amg_solve_pcg", "amg_solve_bicgstab", "amg_solve_bicgstab_pair", "tt_solve",
-              "tt_sweep", "tt_solve_direct", "tt_delineate", "amg_solve_pcg_shifted", "flow_transient",
+              "tt_sweep", "tt_solve_direct", "tt_delineate", "amg_solve_pcg_shifted", "flow_transient", "amg_ilu_export",
               "queue_submit", "queue_poll", "darcy_flux", "amg_free", "gw_last_error"]:
         assert n in names
 
