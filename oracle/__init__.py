@@ -26,6 +26,8 @@ _LIB = os.path.join(_HERE, "libgwref.so")
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 EINVAL, SINGULAR = -1, -3
 JACOBI, SPAI0, NONE, ILU0 = 0, 1, 2, 3
+SA, RS = 0, 1
+CF_UND, CF_C, CF_F = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -54,7 +56,7 @@ def _L():
 class _Params(C.Structure):
     _fields_ = [("eps_strong", C.c_double), ("smoother", C.c_int32), ("omega", C.c_double),
                 ("npre", C.c_int32), ("npost", C.c_int32), ("n_coarse", C.c_int32),
-                ("max_levels", C.c_int32), ("seed", C.c_uint64)]
+                ("max_levels", C.c_int32), ("seed", C.c_uint64), ("coarsening", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -151,10 +153,11 @@ class AmgParams:
     n_coarse: int = 500
     max_levels: int = 20
     seed: int = 0x5EED
+    coarsening: int = 0  # SA, or RS (Ruge-Stueben: eps_strong is then its theta)
 
     def _c(self) -> _Params:
         return _Params(self.eps_strong, self.smoother, self.omega, self.npre, self.npost,
-                       self.n_coarse, self.max_levels, self.seed)
+                       self.n_coarse, self.max_levels, self.seed, self.coarsening)
 
 
 @dataclasses.dataclass

@@ -65,8 +65,12 @@ typedef struct {
     int32_t npre, npost; /* smoothing sweeps                               */
     int32_t n_coarse;    /* stop coarsening at or below this size          */
     int32_t max_levels;
-    uint64_t seed;       /* MIS-2 hash seed                                */
+    uint64_t seed;       /* MIS-2 / PMIS hash seed                         */
+    int32_t coarsening;  /* CO_SA | CO_RS                                  */
 } ref_params;
+
+#define CO_SA 0
+#define CO_RS 1
 
 typedef struct {
     rcsr A;
@@ -836,6 +840,139 @@ static void ilu_solve(const rcsr *A, const double *ilu, const int32_t *dpos, dou
     }
 }
 
+/* ---------------------------------------------------------------------- */
+/* Ruge-Stueben coarsening (the paper's other AMG variant): classical       */
+/* strength, a PMIS C/F splitting and direct interpolation.                 */
+/* ---------------------------------------------------------------------- */
+
+/* S_i = { j != i : -a_ij >= theta * max_{k != i} (-a_ik) }, the points i
+ * depends on strongly (empty when row i has no negative off-diagonal). */
+static void strength_rs(const rcsr *A, double theta, rcsr *S) {
+    int32_t n = A->n;
+    int64_t cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        cnt = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            double mx = 0.0;
+            for (int32_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
+                if (A->col[p] != i && -A->val[p] > mx) mx = -A->val[p];
+            if (pass == 1) S->rowptr[i] = (int32_t)cnt;
+            if (mx > 0.0)
+                for (int32_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p)
+                    if (A->col[p] != i && -A->val[p] >= theta * mx) {
+                        if (pass == 1) { S->col[cnt] = A->col[p]; S->val[cnt] = 1.0; }
+                        ++cnt;
+                    }
+        }
+        if (pass == 0) csr_alloc(S, n, n, cnt);
+    }
+    S->rowptr[n] = (int32_t)cnt;
+}
+
+#define CF_UND 0
+#define CF_C 1
+#define CF_F 2
+
+/* Weight of point i: the number of points that depend on it strongly, plus
+ * a hash fraction in [0, 1) (24 bits of fmix32(i ^ salt)); ties by index. */
+static int pmis_beats(double wi, int32_t i, double wj, int32_t j) { return wi > wj || (wi == wj && i > j); }
+
+/* PMIS: a point with no dependents is F; then in rounds, an undecided point
+ * whose weight beats every undecided neighbour of the symmetrised strength
+ * graph becomes C, and an undecided point that depends strongly on a C point
+ * becomes F.  Returns the number of rounds. */
+static int32_t pmis(const rcsr *S, const rcsr *St, uint64_t seed, int32_t level, int32_t *cf) {
+    int32_t n = S->n;
+    uint32_t salt = level_salt(seed, level);
+    double *w = (double *)xcalloc((size_t)n, sizeof(double));
+    int32_t *newc = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t dep = St->rowptr[i + 1] - St->rowptr[i];
+        w[i] = (double)dep + (double)(fmix32((uint32_t)i ^ salt) >> 8) * (1.0 / 16777216.0);
+        cf[i] = dep == 0 ? CF_F : CF_UND;
+    }
+    int32_t rounds = 0;
+    for (;;) {
+        int any = 0;
+        for (int32_t i = 0; i < n; ++i) any |= cf[i] == CF_UND;
+        if (!any) break;
+        ++rounds;
+        for (int32_t i = 0; i < n; ++i) {
+            newc[i] = 0;
+            if (cf[i] != CF_UND) continue;
+            int best = 1;
+            for (int32_t p = S->rowptr[i]; p < S->rowptr[i + 1] && best; ++p) {
+                int32_t j = S->col[p];
+                if (cf[j] == CF_UND && !pmis_beats(w[i], i, w[j], j)) best = 0;
+            }
+            for (int32_t p = St->rowptr[i]; p < St->rowptr[i + 1] && best; ++p) {
+                int32_t j = St->col[p];
+                if (cf[j] == CF_UND && !pmis_beats(w[i], i, w[j], j)) best = 0;
+            }
+            newc[i] = best;
+        }
+        for (int32_t i = 0; i < n; ++i)
+            if (newc[i]) cf[i] = CF_C;
+        for (int32_t i = 0; i < n; ++i) {
+            if (cf[i] != CF_UND) continue;
+            for (int32_t p = S->rowptr[i]; p < S->rowptr[i + 1]; ++p)
+                if (cf[S->col[p]] == CF_C) { cf[i] = CF_F; break; }
+        }
+    }
+    free(w);
+    free(newc);
+    return rounds;
+}
+
+/* Direct interpolation.  C points are numbered in ascending order; a C
+ * point's row of P is 1 at its own number.  For an F point i with strong C
+ * neighbours C_i: d = a_ii + (positive off-diagonals, lumped), alpha =
+ * (sum of negative off-diagonals) / (sum of a_ij over C_i), and
+ * P_ij = -(alpha * a_ij) / d for j in C_i (all sums in column order).  An F
+ * point without strong C neighbours has an empty row. */
+static int32_t interp_direct(const rcsr *A, const rcsr *S, const int32_t *cf, int32_t *cidx, rcsr *P) {
+    int32_t n = A->n, nc = 0;
+    for (int32_t i = 0; i < n; ++i) cidx[i] = cf[i] == CF_C ? nc++ : -1;
+    int64_t cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        cnt = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (pass == 1) P->rowptr[i] = (int32_t)cnt;
+            if (cf[i] == CF_C) {
+                if (pass == 1) { P->col[cnt] = cidx[i]; P->val[cnt] = 1.0; }
+                ++cnt;
+                continue;
+            }
+            double d = 0.0, neg = 0.0, sc = 0.0;
+            int32_t q = S->rowptr[i];
+            for (int32_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+                int32_t j = A->col[p];
+                double a = A->val[p];
+                if (j == i) { d = d + a; continue; }
+                if (a > 0.0) { d = d + a; continue; }
+                neg = neg + a;
+                while (q < S->rowptr[i + 1] && S->col[q] < j) ++q;
+                if (q < S->rowptr[i + 1] && S->col[q] == j && cf[j] == CF_C) sc = sc + a;
+            }
+            if (sc == 0.0) continue;
+            double alpha = neg / sc;
+            q = S->rowptr[i];
+            for (int32_t p = A->rowptr[i]; p < A->rowptr[i + 1]; ++p) {
+                int32_t j = A->col[p];
+                if (j == i || A->val[p] > 0.0) continue;
+                while (q < S->rowptr[i + 1] && S->col[q] < j) ++q;
+                if (q < S->rowptr[i + 1] && S->col[q] == j && cf[j] == CF_C) {
+                    if (pass == 1) { P->col[cnt] = cidx[j]; P->val[cnt] = -(alpha * A->val[p]) / d; }
+                    ++cnt;
+                }
+            }
+        }
+        if (pass == 0) csr_alloc(P, n, nc, cnt);
+    }
+    P->rowptr[n] = (int32_t)cnt;
+    return nc;
+}
+
 static void copy_csr(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val, rcsr *A) {
     csr_alloc(A, n, n, rowptr[n]);
     memcpy(A->rowptr, rowptr, ((size_t)n + 1) * sizeof(int32_t));
@@ -877,6 +1014,42 @@ ref_hier *ref_amg_setup(int32_t n, const int32_t *rowptr, const int32_t *col, co
         ref_level *L = &H->L[l];
         int32_t nl = L->A.n;
         if (nl <= prm->n_coarse || l == maxl - 1) { make_coarsest(H, l, status); break; }
+        if (prm->coarsening == CO_RS) {
+            rcsr S, St;
+            strength_rs(&L->A, prm->eps_strong, &S);
+            transpose(&S, &St);
+            L->nnz_s = S.nnz;
+            int32_t *cf = (int32_t *)xcalloc((size_t)nl, sizeof(int32_t));
+            L->mis_rounds = pmis(&S, &St, prm->seed, l, cf);
+            L->agg = (int32_t *)xcalloc((size_t)nl, sizeof(int32_t));
+            L->state = (int32_t *)xcalloc((size_t)nl, sizeof(int32_t));
+            for (int32_t i = 0; i < nl; ++i) L->state[i] = cf[i];
+            L->nc = interp_direct(&L->A, &S, cf, L->agg, &L->P);
+            free(cf);
+            csr_free(&S);
+            csr_free(&St);
+            if (L->nc == 0 || (double)L->nc > 0.9 * (double)nl) {
+                csr_free(&L->P);
+                memset(&L->P, 0, sizeof(L->P));
+                make_coarsest(H, l, status);
+                break;
+            }
+            L->M = (double *)xcalloc((size_t)nl, sizeof(double));
+            if (prm->smoother == SM_ILU0) {
+                L->ilu = (double *)xcalloc((size_t)L->A.nnz, sizeof(double));
+                L->dpos = (int32_t *)xcalloc((size_t)nl, sizeof(int32_t));
+                if (ilu0(&L->A, L->ilu, L->dpos) != REF_OK) { *status = REF_SINGULAR; H->nlevels = l + 1; break; }
+            } else {
+                smoother_diag(&L->A, prm, L->M);
+            }
+            L->omega_p = 0.0;
+            transpose(&L->P, &L->R);
+            rcsr AP;
+            spgemm(&L->A, &L->P, &AP);
+            spgemm(&L->R, &AP, &H->L[l + 1].A);
+            csr_free(&AP);
+            continue;
+        }
         rcsr At;
         transpose(&L->A, &At);
         uint8_t *strongA = (uint8_t *)xcalloc((size_t)L->A.nnz, 1);
