@@ -47,6 +47,7 @@ extern "C" {
 
 enum { GW_SMOOTHER_JACOBI = 0, GW_SMOOTHER_SPAI0 = 1, GW_SMOOTHER_NONE = 2, GW_SMOOTHER_ILU0 = 3 };
 enum { GW_PRECISION_FP64 = 0, GW_PRECISION_MIXED = 1 };
+enum { GW_COARSEN_SA = 0, GW_COARSEN_RS = 1 };
 
 /* ---- plain data --------------------------------------------------------- */
 
@@ -72,8 +73,8 @@ typedef struct { double h_west, h_east; } gw_bc;
  * the second travel-time right-hand side. */
 typedef struct { int32_t j0, j1, k0, k1; } gw_zone;
 
-/* Smoothed-aggregation parameters.
- *   eps_strong  strength threshold eps_0 (halved every level)       [0.08]
+/* AMG parameters.
+ *   eps_strong  strength threshold eps_0 (halved every level under SA) [0.08]
  *   smoother    GW_SMOOTHER_*; NONE disables the preconditioner; ILU0 [SPAI0]
  *               is the paper's relaxation (incomplete LU on each level's
  *               pattern, applied by level-scheduled substitutions: a
@@ -83,7 +84,19 @@ typedef struct { int32_t j0, j1, k0, k1; } gw_zone;
  *   n_coarse    a level of at most this many rows is the coarsest    [500]
  *   max_levels  level cap                                            [20]
  *   precision   FP64, or MIXED = FP32 hierarchy inside FP64 Krylov   [FP64]
- *   seed        seed of the MIS-2 hash priorities                    */
+ *   seed        seed of the MIS-2 hash priorities (of the PMIS weights
+ *               under RS)
+ *   coarsening  GW_COARSEN_SA: smoothed aggregation on MIS-2 aggregates [SA]
+ *               (Figs. 1 and 3, CG/AMG/SA); GW_COARSEN_RS: classical
+ *               Ruge-Stueben (the figures' other AMG, CG/AMG/RS, kept as
+ *               a baseline): strong set S_i = { j : -a_ij >= eps_strong
+ *               max_k -a_ik } with eps_strong kept on every level, a PMIS
+ *               C/F splitting (weight: number of dependents plus a 24-bit
+ *               hash fraction, ties by index; a point with no dependents
+ *               is F) and direct interpolation from the strong C neighbours
+ *               (positive off-diagonals lumped into the diagonal); the
+ *               level's aggregate array then holds each C point's coarse
+ *               index and -1 for F points, and omega_P is 0 */
 typedef struct {
     double eps_strong;
     int32_t smoother;
@@ -92,6 +105,7 @@ typedef struct {
     int32_t n_coarse, max_levels;
     int32_t precision;
     uint64_t seed;
+    int32_t coarsening;
 } amg_params;
 
 /* rtol: stop when ||r||_2 <= rtol ||b||_2.  check_every: iterations between

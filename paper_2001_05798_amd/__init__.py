@@ -19,6 +19,7 @@ OK, NOT_CONVERGED, BREAKDOWN, PENDING = 0, 1, 2, 3
 EINVAL, ENOMEM, SINGULAR, EDEVICE, EAGAIN = -1, -2, -3, -4, -5
 SMOOTHER_JACOBI, SMOOTHER_SPAI0, SMOOTHER_NONE, SMOOTHER_ILU0 = 0, 1, 2, 3
 PRECISION_FP64, PRECISION_MIXED = 0, 1
+COARSEN_SA, COARSEN_RS = 0, 1
 TT_EPS_STRONG = 0.25
 
 STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", PENDING: "PENDING",
@@ -58,7 +59,8 @@ class GwZone(C.Structure):
 class AmgParamsC(C.Structure):
     _fields_ = [("eps_strong", C.c_double), ("smoother", C.c_int32), ("omega", C.c_double),
                 ("npre", C.c_int32), ("npost", C.c_int32), ("n_coarse", C.c_int32),
-                ("max_levels", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64)]
+                ("max_levels", C.c_int32), ("precision", C.c_int32), ("seed", C.c_uint64),
+                ("coarsening", C.c_int32)]
 
 
 class SolveParamsC(C.Structure):
@@ -228,10 +230,11 @@ class AmgParams:
     max_levels: int = 20
     precision: int = PRECISION_FP64
     seed: int = 0x5EED
+    coarsening: int = COARSEN_SA
 
     def c(self) -> AmgParamsC:
         return AmgParamsC(self.eps_strong, self.smoother, self.omega, self.npre, self.npost,
-                          self.n_coarse, self.max_levels, self.precision, self.seed)
+                          self.n_coarse, self.max_levels, self.precision, self.seed, self.coarsening)
 
     @classmethod
     def travel_time(cls, **kw) -> "AmgParams":

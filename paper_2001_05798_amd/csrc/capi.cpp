@@ -56,6 +56,7 @@ void check_params(const amg_params *p) {
     GW_REQUIRE(p, "null amg_params");
     GW_REQUIRE(p->smoother >= GW_SMOOTHER_JACOBI && p->smoother <= GW_SMOOTHER_ILU0, "unknown smoother");
     GW_REQUIRE(p->precision == GW_PRECISION_FP64 || p->precision == GW_PRECISION_MIXED, "unknown precision");
+    GW_REQUIRE(p->coarsening == GW_COARSEN_SA || p->coarsening == GW_COARSEN_RS, "unknown coarsening");
     GW_REQUIRE(!(p->smoother == GW_SMOOTHER_ILU0 && p->precision == GW_PRECISION_MIXED),
                "the ILU(0) smoother needs the FP64 hierarchy");
     GW_REQUIRE(p->npre >= 0 && p->npost >= 0 && p->npre <= 16 && p->npost <= 16, "sweeps must be in [0, 16]");

@@ -89,6 +89,7 @@ SetupKey setup_key(const gw_request &r) {
     word((uint64_t)p.max_levels);
     word((uint64_t)p.precision);
     word((uint64_t)p.seed);
+    word((uint64_t)p.coarsening);
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     const uint64_t *K = reinterpret_cast<const uint64_t *>(r.K);
     for (int64_t i = 0; i < n; ++i) word(K[i]);

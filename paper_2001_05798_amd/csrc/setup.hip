@@ -1070,6 +1070,177 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
     for (int32_t i = lane; i < n; i += 64) inv[(int64_t)i * n + c] = x[i];
 }
 
+// ----------------------------------------------------------- Ruge-Stueben --
+// The classical coarsening the paper's figures compare with smoothed
+// aggregation: strength on the size of the negative couplings, a PMIS C/F
+// splitting and direct interpolation.  One thread per row throughout: level
+// 0 has seven entries a row and the Galerkin levels a few dozen.
+constexpr int32_t CF_UND = 0, CF_C = 1, CF_F = 2;
+
+// Strong set of row i: the j != i with -a_ij >= theta max_{k != i}(-a_ik),
+// empty when no off-diagonal is negative.  The counting pass writes cnt[i+1];
+// the filling pass writes the columns in A's order and marks each entry of
+// A in `strong`.
+template <bool FILL>
+__global__ void k_rs_strength(CsrView A, double theta, int32_t *__restrict__ cnt, const int32_t *__restrict__ srow,
+                              int32_t *__restrict__ scol, uint8_t *__restrict__ strong) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    const int32_t b = A.rowptr[i], e = A.rowptr[i + 1];
+    double mx = 0.0;
+    for (int32_t p = b; p < e; ++p)
+        if (A.col[p] != (int32_t)i && -A.val[p] > mx) mx = -A.val[p];
+    const double cut = theta * mx;
+    int32_t c = 0;
+    for (int32_t p = b; p < e; ++p) {
+        const bool st = mx > 0.0 && A.col[p] != (int32_t)i && -A.val[p] >= cut;
+        if (FILL) {
+            strong[p] = st ? 1 : 0;
+            if (st) scol[srow[i] + c] = A.col[p];
+        }
+        c += st;
+    }
+    if (!FILL) cnt[i + 1] = c;
+}
+
+// Weight of i: its number of dependents (the length of its row of S^T) plus
+// a hash fraction in [0, 1) from the top 24 bits of fmix32(i ^ salt), exact
+// in a double.  Points nothing depends on start as F.
+__global__ void k_pmis_init(const int32_t *__restrict__ trow, int32_t n, uint32_t salt, double *__restrict__ w,
+                            int32_t *__restrict__ cf, int32_t *und) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool left = false;
+    if (i < n) {
+        const int32_t dep = trow[i + 1] - trow[i];
+        w[i] = (double)dep + (double)(fmix32((uint32_t)i ^ salt) >> 8) * (1.0 / 16777216.0);
+        cf[i] = dep == 0 ? CF_F : CF_UND;
+        left = dep != 0;
+    }
+    if (__any(left) && (threadIdx.x & (dev::kWave - 1)) == 0) *und = 1;
+}
+
+__device__ __forceinline__ bool pmis_beats(double wi, int32_t i, double wj, int32_t j) {
+    return wi > wj || (wi == wj && i > j);
+}
+
+// First half of a round: an undecided point whose weight beats that of every
+// undecided neighbour in S and in S^T is a new C point.
+__global__ void k_pmis_c(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol,
+                         const int32_t *__restrict__ trow, const int32_t *__restrict__ tcol, int32_t n,
+                         const double *__restrict__ w, const int32_t *__restrict__ cf, int32_t *__restrict__ newc) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t best = 0;
+    if (cf[i] == CF_UND) {
+        best = 1;
+        const double wi = w[i];
+        for (int32_t p = srow[i]; p < srow[i + 1] && best; ++p) {
+            const int32_t j = scol[p];
+            if (cf[j] == CF_UND && !pmis_beats(wi, (int32_t)i, w[j], j)) best = 0;
+        }
+        for (int32_t p = trow[i]; p < trow[i + 1] && best; ++p) {
+            const int32_t j = tcol[p];
+            if (cf[j] == CF_UND && !pmis_beats(wi, (int32_t)i, w[j], j)) best = 0;
+        }
+    }
+    newc[i] = best;
+}
+
+// Second half: new C points take C; an undecided point that depends on a C
+// point (old or new) takes F.  Each thread writes only its own point and
+// tests its neighbours for C, a state no write of this pass creates or
+// removes (new C points are read from newc), so the result does not depend
+// on the order of the writes.  *und_next records whether any point is left.
+__global__ void k_pmis_f(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
+                         const int32_t *__restrict__ newc, int32_t *cf, int32_t *und_next) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool left = false;
+    if (i < n && cf[i] == CF_UND) {
+        if (newc[i]) {
+            cf[i] = CF_C;
+        } else {
+            bool f = false;
+            for (int32_t p = srow[i]; p < srow[i + 1] && !f; ++p) {
+                const int32_t j = scol[p];
+                f = newc[j] != 0 || cf[j] == CF_C;
+            }
+            if (f) cf[i] = CF_F;
+            else left = true;
+        }
+    }
+    if (__any(left) && (threadIdx.x & (dev::kWave - 1)) == 0) *und_next = 1;
+}
+
+__global__ void k_c_flags(const int32_t *__restrict__ cf, int32_t n, int32_t *__restrict__ flag) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) flag[i + 1] = cf[i] == CF_C ? 1 : 0;
+    if (i == 0) flag[0] = 0;
+}
+
+// Coarse index of each C point (its rank among the C points), -1 for F.
+__global__ void k_c_index(const int32_t *__restrict__ cf, const int32_t *__restrict__ rank, int32_t n,
+                          int32_t *__restrict__ cidx) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) cidx[i] = cf[i] == CF_C ? rank[i] : -1;
+}
+
+// Direct interpolation.  A C point's row is 1 at its coarse index.  For an F
+// point: d = a_ii plus the positive off-diagonals (lumped), neg = the sum of
+// the other off-diagonals, sc = the sum of a_ij over the strong C
+// neighbours, all in column order; then alpha = neg / sc and
+// P_ij = -(alpha a_ij) / d on those neighbours (coarse indices ascend with
+// j).  No strong C neighbour (sc = 0) leaves the row empty.
+template <bool FILL>
+__global__ void k_rs_interp(CsrView A, const uint8_t *__restrict__ strong, const int32_t *__restrict__ cf,
+                            const int32_t *__restrict__ cidx, int32_t *__restrict__ cnt,
+                            const int32_t *__restrict__ prow, int32_t *__restrict__ pcol,
+                            double *__restrict__ pval) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    if (cf[i] == CF_C) {
+        if (FILL) {
+            pcol[prow[i]] = cidx[i];
+            pval[prow[i]] = 1.0;
+        } else {
+            cnt[i + 1] = 1;
+        }
+        return;
+    }
+    const int32_t b = A.rowptr[i], e = A.rowptr[i + 1];
+    double d = 0.0, neg = 0.0, sc = 0.0;
+    int32_t m = 0;
+    for (int32_t p = b; p < e; ++p) {
+        const int32_t j = A.col[p];
+        const double a = A.val[p];
+        if (j == (int32_t)i || a > 0.0) {
+            d = d + a;
+            continue;
+        }
+        neg = neg + a;
+        if (strong[p] && cf[j] == CF_C) {
+            sc = sc + a;
+            ++m;
+        }
+    }
+    if (sc == 0.0) m = 0;
+    if (!FILL) {
+        cnt[i + 1] = m;
+        return;
+    }
+    if (m == 0) return;
+    const double alpha = neg / sc;
+    int32_t q = prow[i];
+    for (int32_t p = b; p < e; ++p) {
+        const int32_t j = A.col[p];
+        if (j == (int32_t)i || A.val[p] > 0.0) continue;
+        if (strong[p] && cf[j] == CF_C) {
+            pcol[q] = cidx[j];
+            pval[q] = -(alpha * A.val[p]) / d;
+            ++q;
+        }
+    }
+}
+
 // ------------------------------------------------------------ host side --
 
 // Small device->host reads through the thread's pinned stage.
@@ -1306,6 +1477,157 @@ void transpose(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total) 
     GW_HIP(hipGetLastError());
 }
 
+namespace {
+
+// R = P^T and A_{l+1} = R (A P) for a level whose P is built; the row bound
+// of A P must already be in rd (blk 1).  The symbolic pass of A P and the row
+// bound of R (A P) share one read.
+void galerkin(amg_hierarchy *H, int l, int64_t nc, LevelReads &rd, hipStream_t s) {
+    Level &Lv = H->L[l];
+    const CsrView A = view(Lv.A);
+    const int32_t n = A.n;
+    DBuf<int64_t> total(1);
+    transpose(view(Lv.P), Lv.R, s, total.p);
+    Csr AP;
+    const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
+    const double pavg = (double)Lv.P.nnz / std::max<int32_t>(n, 1);
+    const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
+    const ARowCsr a_side{A.rowptr, A.col, A.val};
+    const BCsr p_side{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p};
+    spgemm_symbolic(a_side, p_side, EpiIdentity{}, n, (int32_t)nc, arow, pavg, rd.hblk(1)[0], AP, rd.blk(1), s);
+    const ARowCsr r_side{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p};
+    spgemm_bound(r_side, BCsr{AP.rowptr.p, nullptr, nullptr}, (int32_t)nc, ravg, rd.blk(2), s);
+    rd.sync(s);
+    spgemm_numeric(a_side, p_side, EpiIdentity{}, n, arow, pavg, rd.hblk(1), AP, rd.blk(1), s);
+    Level &Nx = H->L[l + 1];
+    const double apavg = (double)AP.nnz / std::max<int32_t>(n, 1);
+    const BCsr ap_side{AP.rowptr.p, AP.col.p, AP.val.p};
+    spgemm_symbolic(r_side, ap_side, EpiIdentity{}, (int32_t)nc, (int32_t)nc, ravg, apavg, rd.hblk(2)[0], Nx.A,
+                    rd.blk(2), s);
+    rd.sync(s);
+    spgemm_numeric(r_side, ap_side, EpiIdentity{}, (int32_t)nc, ravg, apavg, rd.hblk(2), Nx.A, rd.blk(2), s);
+}
+
+// Ruge-Stueben level: strength with the threshold kept on every level, PMIS
+// rounds batched between host reads (as the MIS-2 rounds), coarse indices,
+// direct interpolation, then the Galerkin product.
+void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
+    Level &Lv = H->L[l];
+    const CsrView A = view(Lv.A);
+    const int32_t n = A.n;
+    const amg_params &prm = H->prm;
+    const unsigned nb = blocks_for(n);
+    LevelReads rd(s);
+
+    Csr S, St;
+    S.n = S.ncols = n;
+    S.rowptr.alloc((size_t)n + 1);
+    fill_i32(S.rowptr.p, 0, 1, s);
+    S.col.alloc((size_t)std::max<int64_t>(A.nnz, 1));  // a subset of A's off-diagonal entries
+    DBuf<uint8_t> strong((size_t)std::max<int64_t>(A.nnz, 1));
+    {
+        ProfScope ps(K_STRENGTH, (double)A.nnz * 25 + n * 8.0, s);
+        hipLaunchKernelGGL((k_rs_strength<false>), dim3(nb), dim3(kBlock), 0, s, A, prm.eps_strong, S.rowptr.p,
+                           (const int32_t *)nullptr, (int32_t *)nullptr, (uint8_t *)nullptr);
+        scan_inclusive_i32(S.rowptr.p + 1, n, rd.total(0), s);
+        hipLaunchKernelGGL((k_rs_strength<true>), dim3(nb), dim3(kBlock), 0, s, A, prm.eps_strong,
+                           (int32_t *)nullptr, S.rowptr.p, S.col.p, strong.p);
+        GW_HIP(hipGetLastError());
+    }
+    rd.sync(s);
+    S.nnz = rd.h64(0);
+    Lv.nnz_s = S.nnz;
+    S.val.alloc((size_t)std::max<int64_t>(S.nnz, 1));
+    fill_f64(S.val.p, 1.0, S.nnz, s);
+    DBuf<int64_t> total(1);
+    transpose(view(S), St, s, total.p);
+
+    // PMIS rounds; und[r] = some point was undecided before round r
+    DBuf<double> w(n);
+    DBuf<int32_t> cf(n), newc(n);
+    constexpr int kMaxRounds = 4096, kBatch = 12;
+    DBuf<int32_t> und(kMaxRounds + 1);
+    fill_i32(und.p, 0, kMaxRounds + 1, s);
+    {
+        ProfScope ps(K_MIS2, n * 20.0, s);
+        hipLaunchKernelGGL(k_pmis_init, dim3(nb), dim3(kBlock), 0, s, St.rowptr.p, n, level_salt(prm.seed, l), w.p,
+                           cf.p, und.p);
+        GW_HIP(hipGetLastError());
+    }
+    int rounds = 0;
+    for (;;) {
+        GW_REQUIRE(rounds + kBatch <= kMaxRounds, "amg_setup: PMIS did not terminate");
+        for (int b = 0; b < kBatch; ++b) {
+            const int r = rounds + b;
+            ProfScope ps(K_MIS2, (double)S.nnz * 16 + n * 24.0, s);
+            hipLaunchKernelGGL(k_pmis_c, dim3(nb), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, St.rowptr.p, St.col.p, n,
+                               w.p, cf.p, newc.p);
+            hipLaunchKernelGGL(k_pmis_f, dim3(nb), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, newc.p, cf.p,
+                               und.p + r + 1);
+        }
+        GW_HIP(hipGetLastError());
+        int32_t flags[kBatch + 1];
+        rd.sync(s, und.p + rounds, sizeof(flags), flags);
+        if (flags[0] == 0) break;  // nothing was undecided before this batch
+        int b = 0;
+        while (b < kBatch && flags[1 + b] > 0) ++b;
+        if (b < kBatch) {
+            rounds += b + 1;
+            break;
+        }
+        rounds += kBatch;
+    }
+    Lv.mis_rounds = rounds;
+    St = Csr();
+    w.release();
+
+    // coarse indices, the rows of P, and the row bound of A P, one read
+    DBuf<int32_t> rank((size_t)n + 1);
+    Lv.agg.alloc(n);
+    Csr &P = Lv.P;
+    P.n = n;
+    P.rowptr.alloc((size_t)n + 1);
+    fill_i32(P.rowptr.p, 0, 1, s);
+    {
+        ProfScope ps(K_AGGREGATE, (double)A.nnz * 13 + n * 20.0, s);
+        hipLaunchKernelGGL(k_c_flags, dim3(nb), dim3(kBlock), 0, s, cf.p, n, rank.p);
+        scan_inclusive_i32(rank.p + 1, n, rd.total(4), s);
+        hipLaunchKernelGGL(k_c_index, dim3(nb), dim3(kBlock), 0, s, cf.p, rank.p, n, Lv.agg.p);
+        hipLaunchKernelGGL((k_rs_interp<false>), dim3(nb), dim3(kBlock), 0, s, A, strong.p, cf.p, Lv.agg.p,
+                           P.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr);
+        scan_inclusive_i32(P.rowptr.p + 1, n, rd.total(2), s);
+        GW_HIP(hipGetLastError());
+    }
+    const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
+    spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s);
+    rd.sync(s);
+    const int64_t nc = rd.h64(4);
+    Lv.nc = (int32_t)nc;
+    if (nc == 0 || (double)nc > 0.9 * (double)n) {
+        *is_coarsest = true;
+        Lv.agg.release();
+        Lv.P = Csr();
+        Lv.nc = 0;
+        return;
+    }
+    P.ncols = (int32_t)nc;
+    P.nnz = rd.h64(2);
+    P.col.alloc((size_t)std::max<int64_t>(P.nnz, 1));
+    P.val.alloc((size_t)std::max<int64_t>(P.nnz, 1));
+    {
+        ProfScope ps(K_SETUP_MISC, (double)A.nnz * 13 + P.nnz * 12.0 + n * 12.0, s);
+        hipLaunchKernelGGL((k_rs_interp<true>), dim3(nb), dim3(kBlock), 0, s, A, strong.p, cf.p, Lv.agg.p,
+                           (int32_t *)nullptr, P.rowptr.p, P.col.p, P.val.p);
+        GW_HIP(hipGetLastError());
+    }
+    // no prolongator smoothing: omega_P is 0
+    Lv.omega_dev.alloc(1);
+    fill_f64(Lv.omega_dev.p, 0.0, 1, s);
+    galerkin(H, l, nc, rd, s);
+}
+
+}  // namespace
+
 // Build level l+1 from level l, or mark l as the coarsest.  Returns through
 // *is_coarsest whether level l ended the hierarchy.
 void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
@@ -1320,6 +1642,10 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         return;
     }
     GW_REQUIRE(n < (1 << 30), "amg_setup: at most 2^30 rows per level");
+    if (prm.coarsening == GW_COARSEN_RS) {
+        build_level_rs(H, l, s, is_coarsest);
+        return;
+    }
     const CsrView A = view(Lv.A);
     double eps2 = prm.eps_strong * prm.eps_strong;
     for (int k = 0; k < l; ++k) eps2 = eps2 * 0.25;
@@ -1527,26 +1853,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     rd.sync(s);
     spgemm_numeric(af, bt, ep, n, arow, 1.0, rd.hblk(0), Lv.P, rd.blk(0), s);
 
-    // R = P^T, A_c = R (A P): the symbolic pass of A P, then the row bound of
-    // R (A P), one read for both
-    transpose(view(Lv.P), Lv.R, s, total.p);
-    Csr AP;
-    const double pavg = (double)Lv.P.nnz / std::max<int32_t>(n, 1);
-    const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
-    const ARowCsr a_side{A.rowptr, A.col, A.val};
-    const BCsr p_side{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p};
-    spgemm_symbolic(a_side, p_side, EpiIdentity{}, n, (int32_t)nc, arow, pavg, rd.hblk(1)[0], AP, rd.blk(1), s);
-    const ARowCsr r_side{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p};
-    spgemm_bound(r_side, BCsr{AP.rowptr.p, nullptr, nullptr}, (int32_t)nc, ravg, rd.blk(2), s);
-    rd.sync(s);
-    spgemm_numeric(a_side, p_side, EpiIdentity{}, n, arow, pavg, rd.hblk(1), AP, rd.blk(1), s);
-    Level &Nx = H->L[l + 1];
-    const double apavg = (double)AP.nnz / std::max<int32_t>(n, 1);
-    const BCsr ap_side{AP.rowptr.p, AP.col.p, AP.val.p};
-    spgemm_symbolic(r_side, ap_side, EpiIdentity{}, (int32_t)nc, (int32_t)nc, ravg, apavg, rd.hblk(2)[0], Nx.A,
-                    rd.blk(2), s);
-    rd.sync(s);
-    spgemm_numeric(r_side, ap_side, EpiIdentity{}, (int32_t)nc, ravg, apavg, rd.hblk(2), Nx.A, rd.blk(2), s);
+    galerkin(H, l, nc, rd, s);
 }
 
 void make_smoother(amg_hierarchy *H, int l, hipStream_t s) {

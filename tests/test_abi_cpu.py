@@ -61,3 +61,51 @@ def test_host_side_validation_without_device():
                             None, 0, None, 0, None, None, None) == -1
     assert lib.tt_solve_direct(ctypes.byref(Grid(0, 2, 2, 1, 1, 1)), None, None, None, ctypes.c_double(0.25),
                                None, None, None, None, None) == -1
+
+
+def _c_layout(struct, field):
+    # sizeof and offsetof as the C compiler sees the header
+    import subprocess
+    import tempfile
+    src = (f'#include <stdio.h>\n#include <stddef.h>\n#include "gwamg.h"\n'
+           f'int main(void) {{ printf("%zu %zu", sizeof({struct}), offsetof({struct}, {field})); return 0; }}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), int(out[1])
+
+
+def test_amg_params_layout_and_validation():
+    # amg_params as the header lays it out (coarsening last), checked by the
+    # library before any device work
+    lib = ctypes.CDLL(LIB)
+    lib.gw_last_error.restype = ctypes.c_char_p
+
+    class Csr(ctypes.Structure):
+        _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                    ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+    class Params(ctypes.Structure):
+        _fields_ = [("eps_strong", ctypes.c_double), ("smoother", ctypes.c_int32), ("omega", ctypes.c_double),
+                    ("npre", ctypes.c_int32), ("npost", ctypes.c_int32), ("n_coarse", ctypes.c_int32),
+                    ("max_levels", ctypes.c_int32), ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                    ("coarsening", ctypes.c_int32)]
+
+    import paper_2001_05798_amd as gw
+    size, off = _c_layout("amg_params", "coarsening")
+    assert ctypes.sizeof(gw.AmgParamsC) == ctypes.sizeof(Params) == size
+    assert gw.AmgParamsC.coarsening.offset == Params.coarsening.offset == off
+    buf = (ctypes.c_int64 * 8)()
+    a = ctypes.addressof(buf)
+    A = Csr(2, 2, a, a, a)
+    h = ctypes.c_void_p()
+    for coarsening, ok in ((2, False), (-1, False)):
+        prm = Params(0.25, 1, 2.0 / 3.0, 2, 2, 500, 20, 0, 0x5EED, coarsening)
+        assert lib.amg_setup(ctypes.byref(A), ctypes.byref(prm), ctypes.byref(h), None) == -1
+        assert b"coarsening" in lib.gw_last_error()
+    prm = Params(0.25, 3, 2.0 / 3.0, 2, 2, 500, 20, 1, 0x5EED, 1)   # ILU0 with the FP32 hierarchy
+    assert lib.amg_setup(ctypes.byref(A), ctypes.byref(prm), ctypes.byref(h), None) == -1
+    assert b"ILU(0)" in lib.gw_last_error()
