@@ -80,14 +80,12 @@ __device__ __forceinline__ VecN<To, NR> cvt(const VecN<From, NR> &x) {
 // the row's first column (a finite x makes them exact zeros; a non-finite x
 // there makes the row non-finite in any case).
 template <int G, int NR, class V, class F>
-__device__ __forceinline__ VecN<V, NR> group_row_sum(const int32_t *__restrict__ rowptr,
-                                                     const int32_t *__restrict__ col, const V *__restrict__ val,
-                                                     int64_t i, int lane, F &&xj) {
+__device__ __forceinline__ VecN<V, NR> group_row_sum(int32_t b, int32_t e, const int32_t *__restrict__ col,
+                                                     const V *__restrict__ val, int lane, F &&xj) {
     constexpr int U = G == 64 ? 4 : 8;
     VecN<V, NR> s;
 #pragma unroll
     for (int k = 0; k < NR; ++k) s.v[k] = 0;
-    const int32_t b = rowptr[i], e = rowptr[i + 1];
     if (b < e) {
         const int32_t cb = col[b];
         for (int32_t q = b + lane; q < e; q += U * G) {
@@ -118,16 +116,33 @@ __device__ __forceinline__ VecN<V, NR> group_row_sum(const int32_t *__restrict__
     return s;
 }
 
+// An operator's head(i) loads what locates row i (its CSR range, or its
+// slice's range in the sliced copy); kernels issue it before the block
+// prologue and their `done` test so that those latencies overlap.
 template <int G_, class V>
 struct OpCsr {
     static constexpr int G = G_;
+    static constexpr bool kShared = false;  // no block prologue
+    struct Head {
+        int32_t b, e;
+        // An empty asm that reads the head: where a kernel returns early,
+        // it keeps the head's loads above the return (otherwise the
+        // compiler sinks them below the `done` test).
+        __device__ __forceinline__ void keep() const { asm volatile("" ::"v"(b), "v"(e)); }
+    };
     const int32_t *rowptr, *col;
     const V *val;
     __device__ __forceinline__ void load(int32_t *) const {}
+    __device__ __forceinline__ Head head(int64_t i) const { return Head{rowptr[i], rowptr[i + 1]}; }
     // xj(j) returns the NR values of column j
     template <int NR, class F>
-    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int lane, const int32_t *, F &&xj) const {
-        return group_row_sum<G, NR, V>(rowptr, col, val, i, lane, xj);
+    __device__ __forceinline__ VecN<V, NR> rows_at(const Head &h, int64_t, int lane, const int32_t *,
+                                                   F &&xj) const {
+        return group_row_sum<G, NR, V>(h.b, h.e, col, val, lane, xj);
+    }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows_at<NR>(head(i), i, lane, sd, xj);
     }
     template <class F>
     __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
@@ -138,10 +153,20 @@ struct OpCsr {
 template <class V>
 struct OpSell {
     static constexpr int G = 1;
+    static constexpr bool kShared = true;  // the offset dictionary in LDS
+    struct Head {
+        int32_t off, w;
+        __device__ __forceinline__ void keep() const { asm volatile("" ::"v"(off), "v"(w)); }
+    };
     SellView S;
     const V *val;
     __device__ __forceinline__ void load(int32_t *sd) const {
         for (int t = threadIdx.x; t < S.ndict; t += blockDim.x) sd[t] = S.dict[t];
+    }
+    __device__ __forceinline__ Head head(int64_t i) const {
+        const int64_t sl = i / kSellC;
+        const int32_t off = S.soff[sl];
+        return Head{off, (S.soff[sl + 1] - off) / kSellC};
     }
     // Entries k of row i sit at soff[slice] + k*64 + (i mod 64).  Eight
     // entries are loaded before their products are summed, so the gathers
@@ -149,10 +174,9 @@ struct OpSell {
     // width re-read the last entry and are replaced by the padding entry
     // (value 0 at the row's own column) in registers, without branches.
     template <bool DICT, int NR, class F>
-    __device__ __forceinline__ VecN<V, NR> row_impl(int64_t i, const int32_t *sd, F &&xj) const {
-        const int64_t sl = i / kSellC;
-        const int l = (int)(i - sl * kSellC);
-        const int32_t off = S.soff[sl], w = (S.soff[sl + 1] - off) / kSellC;
+    __device__ __forceinline__ VecN<V, NR> row_impl(const Head &h, int64_t i, const int32_t *sd, F &&xj) const {
+        const int l = (int)(i % kSellC);
+        const int32_t off = h.off, w = h.w;
         VecN<V, NR> acc;
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc.v[k] = 0;
@@ -179,8 +203,13 @@ struct OpSell {
         return acc;
     }
     template <int NR, class F>
-    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int, const int32_t *sd, F &&xj) const {
-        return S.ndict ? row_impl<true, NR>(i, sd, xj) : row_impl<false, NR>(i, sd, xj);
+    __device__ __forceinline__ VecN<V, NR> rows_at(const Head &h, int64_t i, int, const int32_t *sd,
+                                                   F &&xj) const {
+        return S.ndict ? row_impl<true, NR>(h, i, sd, xj) : row_impl<false, NR>(h, i, sd, xj);
+    }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows_at<NR>(head(i), i, lane, sd, xj);
     }
     template <class F>
     __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
@@ -193,17 +222,25 @@ struct OpSell {
 template <class B>
 struct OpShift {
     static constexpr int G = B::G;
+    static constexpr bool kShared = B::kShared;
+    using Head = typename B::Head;
     B base;
     const double *d;
     __device__ __forceinline__ void load(int32_t *sd) const { base.load(sd); }
+    __device__ __forceinline__ Head head(int64_t i) const { return base.head(i); }
     template <int NR, class F>
-    __device__ __forceinline__ VecN<double, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
-        VecN<double, NR> s = base.template rows<NR>(i, lane, sd, xj);
+    __device__ __forceinline__ VecN<double, NR> rows_at(const Head &h, int64_t i, int lane, const int32_t *sd,
+                                                        F &&xj) const {
+        VecN<double, NR> s = base.template rows_at<NR>(h, i, lane, sd, xj);
         const VecN<double, NR> xi = xj((int32_t)i);
         const double di = d[i];
 #pragma unroll
         for (int k = 0; k < NR; ++k) s.v[k] += di * xi.v[k];
         return s;
+    }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<double, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows_at<NR>(head(i), i, lane, sd, xj);
     }
     template <class F>
     __device__ __forceinline__ double row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
@@ -223,22 +260,49 @@ struct OpShift {
     const int lane = (int)(gtid % (G));                                           \
     if (i >= n) return;
 
+// Read in place of a null `done` flag (a select, not a branch, so the flag's
+// load joins the first batch of loads).
+__device__ const int32_t kNotDone = 0;
+
+// Prologue of a V-cycle kernel (blocks of kBlock threads, G lanes per row,
+// n >= 1): the `done` flag, the row's head and the statements `...` (loads
+// of the row's own vector entries, through `i`) are issued together, rows
+// past the end reading row n-1; then the dictionary (sliced operators only);
+// then the flag is tested.  A small level's kernel thus waits for one round
+// of loads where a test first would wait for three in a row.
+#define VROW_PROLOGUE(OP, op, ...)                                                \
+    const int64_t gtid = dev::xcd_block() * (int64_t)kBlock + threadIdx.x;         \
+    const int64_t row_ = gtid / OP::G;                                            \
+    const int lane = (int)(gtid % OP::G);                                         \
+    const bool live_ = row_ < n;                                                  \
+    const int32_t stop_ = *(done ? done : &kNotDone);                             \
+    const int64_t i = live_ ? row_ : n - 1;                                       \
+    const typename OP::Head h_ = (op).head(i);                                    \
+    __VA_ARGS__                                                                   \
+    __shared__ int32_t sd_[OP::kShared ? kSellMaxDict + 1 : 1];                   \
+    if constexpr (OP::kShared) {                                                  \
+        (op).load(sd_);                                                           \
+        __syncthreads();                                                          \
+    }                                                                             \
+    if (stop_ || !live_) {                                                        \
+        h_.keep();                                                                \
+        return;                                                                   \
+    }
+
 // ------------------------------------------------------------ V-cycle ----
 // Sweep x <- x + M (b - A x); the first two sweeps from x = 0 are fused:
 // x1 = M b, x2 = x1 + M (b - A x1) with x1_j recomputed on the fly.
 template <class OP, class V, class Bt, class Yt, int NR>
 __global__ void k_smooth_first(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b,
                                Yt *__restrict__ y, int two, const int32_t *done) {
-    if (done && *done) return;
-    OP_PROLOGUE(op)
-    GROUP_ROW(OP::G)
-    const VecN<V, NR> bi = cvt<V>(load_n<Bt, NR>(b, i));
-    const V mi = M[i];
+    VecN<V, NR> bi{};
+    V mi = 0;
+    VROW_PROLOGUE(OP, op, bi = cvt<V>(load_n<Bt, NR>(b, i)); mi = M[i];)
     VecN<V, NR> x1;
 #pragma unroll
     for (int k = 0; k < NR; ++k) x1.v[k] = mi * bi.v[k];
     if (two) {
-        const VecN<V, NR> ax = op.template rows<NR>(i, lane, sd_, [&](int32_t j) {
+        const VecN<V, NR> ax = op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) {
             const VecN<V, NR> bj = cvt<V>(load_n<Bt, NR>(b, j));
             const V mj = M[j];
             VecN<V, NR> o;
@@ -255,14 +319,12 @@ __global__ void k_smooth_first(int64_t n, OP op, const V *__restrict__ M, const 
 template <class OP, class V, class Bt, class Xt, class Yt, int NR>
 __global__ void k_smooth(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b,
                          const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
-    if (done && *done) return;
-    OP_PROLOGUE(op)
-    GROUP_ROW(OP::G)
+    VecN<V, NR> xi{}, bi{};
+    V mi = 0;
+    VROW_PROLOGUE(OP, op, xi = cvt<V>(load_n<Xt, NR>(x, i)); bi = cvt<V>(load_n<Bt, NR>(b, i)); mi = M[i];)
     const VecN<V, NR> ax =
-        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
+        op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
     if (lane == 0) {
-        const VecN<V, NR> xi = cvt<V>(load_n<Xt, NR>(x, i)), bi = cvt<V>(load_n<Bt, NR>(b, i));
-        const V mi = M[i];
         VecN<V, NR> o;
 #pragma unroll
         for (int k = 0; k < NR; ++k) o.v[k] = xi.v[k] + mi * (bi.v[k] - ax.v[k]);
@@ -273,13 +335,11 @@ __global__ void k_smooth(int64_t n, OP op, const V *__restrict__ M, const Bt *__
 template <class OP, class V, class Bt, class Xt, class Rt, int NR>
 __global__ void k_residual(int64_t n, OP op, const Bt *__restrict__ b, const Xt *__restrict__ x,
                            Rt *__restrict__ r, const int32_t *done) {
-    if (done && *done) return;
-    OP_PROLOGUE(op)
-    GROUP_ROW(OP::G)
+    VecN<V, NR> bi{};
+    VROW_PROLOGUE(OP, op, bi = cvt<V>(load_n<Bt, NR>(b, i));)
     const VecN<V, NR> ax =
-        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
+        op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
     if (lane == 0) {
-        const VecN<V, NR> bi = cvt<V>(load_n<Bt, NR>(b, i));
         VecN<V, NR> o;
 #pragma unroll
         for (int k = 0; k < NR; ++k) o.v[k] = bi.v[k] - ax.v[k];
@@ -289,24 +349,20 @@ __global__ void k_residual(int64_t n, OP op, const Bt *__restrict__ b, const Xt 
 
 template <class OP, class V, class Xt, class Yt, int NR>
 __global__ void k_spmv(int64_t n, OP op, const Xt *__restrict__ x, Yt *__restrict__ y, const int32_t *done) {
-    if (done && *done) return;
-    OP_PROLOGUE(op)
-    GROUP_ROW(OP::G)
+    VROW_PROLOGUE(OP, op, )
     const VecN<V, NR> s =
-        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
+        op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(x, j)); });
     if (lane == 0) store_n<Yt, NR>(y, i, cvt<Yt>(s));
 }
 
 // x += P x_c
 template <class OP, class V, class Xt, int NR>
 __global__ void k_prolong(int64_t n, OP op, const Xt *__restrict__ xc, Xt *__restrict__ x, const int32_t *done) {
-    if (done && *done) return;
-    OP_PROLOGUE(op)
-    GROUP_ROW(OP::G)
+    VecN<V, NR> xi{};
+    VROW_PROLOGUE(OP, op, xi = cvt<V>(load_n<Xt, NR>(x, i));)
     const VecN<V, NR> s =
-        op.template rows<NR>(i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(xc, j)); });
+        op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) { return cvt<V>(load_n<Xt, NR>(xc, j)); });
     if (lane == 0) {
-        const VecN<V, NR> xi = cvt<V>(load_n<Xt, NR>(x, i));
         VecN<V, NR> o;
 #pragma unroll
         for (int k = 0; k < NR; ++k) o.v[k] = xi.v[k] + s.v[k];
