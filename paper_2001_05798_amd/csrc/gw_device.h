@@ -102,6 +102,51 @@ __device__ __forceinline__ void sum_partials(const double *partials, unsigned nb
     }
 }
 
+// sum_partials for several values at once (nb >= 1), with every block record this
+// thread reads loaded before any is added (records b = threadIdx.x +
+// u*blockDim.x, u < MAXU, then the rest in a loop), so the loads take one
+// round of latency instead of one per record: tot[k] = the sum of value
+// off[k] of the nb records, added in exactly the order of sum_partials.
+template <int NV, int MAXU = 8>
+__device__ __forceinline__ void sum_partials_batched(const double *partials, unsigned nb, int stride,
+                                                     const int (&off)[NV], double (&tot)[NV]) {
+    __shared__ double sm[NV][16];
+    double s[NV], t[MAXU][NV];
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u) {
+        const unsigned b = threadIdx.x + u * blockDim.x;
+        const unsigned bb = b < nb ? b : 0;  // nb >= 1; unused, but no branch
+#pragma unroll
+        for (int k = 0; k < NV; ++k) t[u][k] = partials[(size_t)bb * stride + off[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = 0.0;
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u)
+        if (threadIdx.x + u * blockDim.x < nb)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) s[k] += t[u][k];
+    for (unsigned b = threadIdx.x + MAXU * blockDim.x; b < nb; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] += partials[(size_t)b * stride + off[k]];
+    // block sums in block_sum's order, one pair of barriers for all values
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = wave_sum(s[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sm[k][w] = s[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = sm[k][0];
+        for (int i = 1; i < nw; ++i) a += sm[k][i];
+        tot[k] = a;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ bool finite_nz(double v) { return isfinite(v) && v != 0.0; }
 
 // Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8),

@@ -248,11 +248,14 @@ struct OpShift {
     }
 };
 
-// Block prologue of every product kernel (after its uniform early exit).
-#define OP_PROLOGUE(op)                         \
-    __shared__ int32_t sd_[kSellMaxDict + 1];   \
-    (op).load(sd_);                             \
-    __syncthreads();
+// Block prologue of every product kernel: the offset dictionary of a sliced
+// operator into LDS (nothing for CSR operators).
+#define OP_PROLOGUE(op)                                                   \
+    __shared__ int32_t sd_[kSellMaxDict + 1];                             \
+    if constexpr (std::decay_t<decltype(op)>::kShared) {                  \
+        (op).load(sd_);                                                   \
+        __syncthreads();                                                  \
+    }
 
 #define GROUP_ROW(G)                                                              \
     const int64_t gtid = dev::xcd_block() * (int64_t)blockDim.x + threadIdx.x;     \
@@ -372,21 +375,40 @@ __global__ void k_prolong(int64_t n, OP op, const Xt *__restrict__ xc, Xt *__res
 
 // Coarsest level: x = A_L^{-1} b with the row-major inverse, one wave per
 // row, accumulated in FP64.
+// The first kCoarseU columns of a lane are loaded with the done flag, before
+// any is used (a coarsest level of up to kCoarseU*64 rows takes one round of
+// loads); the products are added in column order all the same.
+constexpr int kCoarseU = 8;
+
 template <class Bt, class Yt, int NR>
 __global__ void k_coarse_gemv(int32_t n, const double *__restrict__ inv, const Bt *__restrict__ b,
                               Yt *__restrict__ y, const int32_t *done) {
-    if (done && *done) return;
+    const int32_t stop = *(done ? done : &kNotDone);
     const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / dev::kWave;
     const int lane = threadIdx.x & (dev::kWave - 1);
-    if (i >= n) return;
+    const int64_t ir = i < n ? i : n - 1;
+    double a[kCoarseU];
+    VecN<double, NR> bc[kCoarseU];
+#pragma unroll
+    for (int u = 0; u < kCoarseU; ++u) {
+        const int32_t c = min(lane + u * dev::kWave, n - 1);
+        a[u] = inv[ir * n + c];
+        bc[u] = cvt<double>(load_n<Bt, NR>(b, c));
+    }
+    if (stop || i >= n) return;
     VecN<double, NR> s;
 #pragma unroll
     for (int k = 0; k < NR; ++k) s.v[k] = 0.0;
-    for (int32_t c = lane; c < n; c += dev::kWave) {
-        const double a = inv[i * n + c];
-        const VecN<double, NR> bc = cvt<double>(load_n<Bt, NR>(b, c));
 #pragma unroll
-        for (int k = 0; k < NR; ++k) s.v[k] += a * bc.v[k];
+    for (int u = 0; u < kCoarseU; ++u)
+        if (lane + u * dev::kWave < n)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) s.v[k] += a[u] * bc[u].v[k];
+    for (int32_t c = lane + kCoarseU * dev::kWave; c < n; c += dev::kWave) {
+        const double av = inv[i * n + c];
+        const VecN<double, NR> bv = cvt<double>(load_n<Bt, NR>(b, c));
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s.v[k] += av * bv.v[k];
     }
 #pragma unroll
     for (int k = 0; k < NR; ++k) s.v[k] = dev::wave_sum(s.v[k]);
@@ -695,8 +717,8 @@ template <class OP>
 __global__ void __launch_bounds__(kKBlock) k_cg_spmv(int64_t n, OP op, const double *__restrict__ z,
                                                      const double *__restrict__ p_old, double *__restrict__ p_new,
                                                      double *__restrict__ q, double *partials, const KScalars *ks) {
-    if (ks->done) return;
     OP_PROLOGUE(op)
+    if (ks->done) return;
     const double beta = ks->beta;
     double acc[1] = {0.0};
     GROUP_LOOP(OP::G, i, lane, n) {
@@ -756,8 +778,8 @@ template <class OP>
 __global__ void __launch_bounds__(kKBlock) k_bcg_v(int64_t n, OP op, const double *__restrict__ ph,
                                                    double *__restrict__ v, const double *__restrict__ rh,
                                                    double *partials, const KScalars *ks) {
-    if (ks->done) return;
     OP_PROLOGUE(op)
+    if (ks->done) return;
     double acc[1] = {0.0};
     GROUP_LOOP(OP::G, i, lane, n) {
         double vi = op.row(i, lane, sd_, [&](int32_t j) { return ph[j]; });
@@ -789,8 +811,8 @@ template <class OP>
 __global__ void __launch_bounds__(kKBlock) k_bcg_t(int64_t n, OP op, const double *__restrict__ sh,
                                                    double *__restrict__ t, const double *__restrict__ sv,
                                                    double *partials, const KScalars *ks) {
-    if (ks->done) return;
     OP_PROLOGUE(op)
+    if (ks->done) return;
     double acc[2] = {0.0, 0.0};
     GROUP_LOOP(OP::G, i, lane, n) {
         double ti = op.row(i, lane, sd_, [&](int32_t j) { return sh[j]; });
@@ -936,18 +958,21 @@ __host__ __device__ constexpr int fin_nv(int op) {
             op == FIN_BCG_OMEGA || op == FIN_BCG_XR) ? 2 : 1;
 }
 
+// The partials are loaded before the skip test reads the scalars, so both
+// latencies overlap.
 __global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const double *partials, double rtol,
                                                       KScalars *ks) {
-    if (fin_skip(op, ks)) return;
     double tot[2] = {0.0, 0.0};
     if (fin_nv(op) == 2) {
-        dev::sum_partials<2>(partials, nb, tot);
+        const int off[2] = {0, 1};
+        dev::sum_partials_batched<2>(partials, nb, 2, off, tot);
     } else {
+        const int off[1] = {0};
         double t1[1];
-        dev::sum_partials<1>(partials, nb, t1);
+        dev::sum_partials_batched<1>(partials, nb, 1, off, t1);
         tot[0] = t1[0];
     }
-    if (threadIdx.x == 0) fin_apply(op, tot, rtol, ks);
+    if (threadIdx.x == 0 && !fin_skip(op, ks)) fin_apply(op, tot, rtol, ks);
 }
 
 // Two right-hand sides: block records hold NV values of each (first, then
@@ -956,20 +981,23 @@ __global__ void __launch_bounds__(kKBlock) k_finalize(int op, unsigned nb, const
 // `mask` are touched.
 __global__ void __launch_bounds__(kKBlock) k_finalize2(int op, unsigned nb, const double *partials, double rtol,
                                                        KScalars *ks, int mask) {
-    const int nv = fin_nv(op);
-    for (int r = 0; r < 2; ++r) {
-        if (!(mask >> r & 1) || fin_skip(op, ks + r)) continue;
-        double tot[2] = {0.0, 0.0};
-        if (nv == 2) {
-            dev::sum_partials<2>(partials, nb, tot, 4, 2 * r);
-        } else {
-            double t1[1];
-            dev::sum_partials<1>(partials, nb, t1, 2, r);
-            tot[0] = t1[0];
-        }
-        if (threadIdx.x == 0) fin_apply(op, tot, rtol, ks + r);
-        __syncthreads();
+    // both systems' sums in one pass over the records (each added in the
+    // order of a one-system finalize)
+    double tot[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    if (fin_nv(op) == 2) {
+        const int off[4] = {0, 1, 2, 3};
+        double t[4];
+        dev::sum_partials_batched<4>(partials, nb, 4, off, t);
+        tot[0][0] = t[0], tot[0][1] = t[1], tot[1][0] = t[2], tot[1][1] = t[3];
+    } else {
+        const int off[2] = {0, 1};
+        double t[2];
+        dev::sum_partials_batched<2>(partials, nb, 2, off, t);
+        tot[0][0] = t[0], tot[1][0] = t[1];
     }
+    if (threadIdx.x == 0)
+        for (int r = 0; r < 2; ++r)
+            if ((mask >> r & 1) && !fin_skip(op, ks + r)) fin_apply(op, tot[r], rtol, ks + r);
     if (threadIdx.x == 0) {
         ks[2].done = ks[0].done && ks[1].done;
         ks[2].pending_x = ks[0].pending_x || ks[1].pending_x;
@@ -1030,8 +1058,8 @@ template <class OP>
 __global__ void __launch_bounds__(kKBlock) k_bcg_v2(int64_t n, OP op, const double *__restrict__ ph,
                                                     double *__restrict__ v, const double *__restrict__ rh,
                                                     double *partials, const KScalars *ks) {
-    if (ks[2].done) return;
     OP_PROLOGUE(op)
+    if (ks[2].done) return;
     double acc[2] = {0.0, 0.0};
     GROUP_LOOP(OP::G, i, lane, n) {
         const VecN<double, 2> vi = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(ph, j); });
@@ -1072,8 +1100,8 @@ template <class OP>
 __global__ void __launch_bounds__(kKBlock) k_bcg_t2(int64_t n, OP op, const double *__restrict__ sh,
                                                     double *__restrict__ t, const double *__restrict__ sv,
                                                     double *partials, const KScalars *ks) {
-    if (ks[2].done) return;
     OP_PROLOGUE(op)
+    if (ks[2].done) return;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     GROUP_LOOP(OP::G, i, lane, n) {
         const VecN<double, 2> ti = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(sh, j); });
