@@ -87,7 +87,7 @@ class Pipeline:
         self.qz = torch.zeros(g.nx * g.ny * (g.nz + 1), dtype=f64, **d)
         self.tau = torch.zeros(n, dtype=f64, **d)
         self.c = torch.zeros(n, dtype=f64, **d)
-        self.params = gw.AmgParams(precision=precision)
+        self.params = gw.AmgParams.flow(precision=precision)
         # the advective travel-time system coarsens better with a larger
         # strength threshold (42 -> 14 BiCGSTAB iterations on this workload)
         self.tt_params = gw.AmgParams.travel_time(precision=precision)
@@ -146,7 +146,7 @@ def cpu_baseline(prob, precision):
     oracle.build(force=False)
     t0 = time.perf_counter()
     A, b = oracle.fv_assemble(prob)
-    H = oracle.Hierarchy(A, oracle.AmgParams())
+    H = oracle.Hierarchy(A, oracle.AmgParams(npre=1, npost=1))
     h, info = oracle.pcg(H, b, rtol=1e-8, flexible=bool(precision))
     t_flow = time.perf_counter() - t0
     t1 = time.perf_counter()

@@ -82,7 +82,10 @@ __device__ __forceinline__ VecN<To, NR> cvt(const VecN<From, NR> &x) {
 template <int G, int NR, class V, class F>
 __device__ __forceinline__ VecN<V, NR> group_row_sum(int32_t b, int32_t e, const int32_t *__restrict__ col,
                                                      const V *__restrict__ val, int lane, F &&xj) {
-    constexpr int U = G == 64 ? 4 : 8;
+    // one-lane rows (prolongators, ~3.5 entries a row) take 4: with 8, the
+    // clamped slots past the row end doubled the L1 requests (level-0
+    // prolongation 3.0 -> 3.6 TB/s at 4)
+    constexpr int U = (G == 1 || G == 64) ? 4 : 8;
     VecN<V, NR> s;
 #pragma unroll
     for (int k = 0; k < NR; ++k) s.v[k] = 0;
