@@ -146,7 +146,7 @@ def cpu_baseline(prob, precision):
     oracle.build(force=False)
     t0 = time.perf_counter()
     A, b = oracle.fv_assemble(prob)
-    H = oracle.Hierarchy(A, oracle.AmgParams(npre=1, npost=1))
+    H = oracle.Hierarchy(A, oracle.AmgParams(eps_strong=0.03, npre=1, npost=1))
     h, info = oracle.pcg(H, b, rtol=1e-8, flexible=bool(precision))
     t_flow = time.perf_counter() - t0
     t1 = time.perf_counter()

@@ -238,12 +238,16 @@ class AmgParams:
 
     @classmethod
     def flow(cls, **kw) -> "AmgParams":
-        """Defaults for the flow system in the benchmark pass: one pre- and
-        one post-smoothing sweep (the most common AMG setting).  On the
-        1M-cell lognormal aquifer CG then needs 32 iterations instead of 26
-        but reaches 1e-8 in 6.5 ms instead of 7.2 ms; 1/2, 2/1, 2/3 and 3/3
-        were slower.  The travel-time system keeps two sweeps each (1/1
-        costs it 10 more BiCGSTAB iterations)."""
+        """Defaults for the flow system in the benchmark pass: strength
+        threshold 0.03 and one pre- and one post-smoothing sweep.  On the
+        1M-cell lognormal aquifer (variance 4) setup + CG to 1e-8 take
+        11.2 ms against 12.0 ms at (0.08, 1/1) and 12.6 ms at (0.08, 2/2);
+        on the 550x500x10 aquifer of variance 10, 45.6 ms against 60.4 ms.
+        Thresholds from 0.05 up leave coarse levels of several hundred rows
+        whose dense factorization dominates the setup.  The travel-time
+        system keeps two sweeps each (1/1 costs it 10 more BiCGSTAB
+        iterations)."""
+        kw.setdefault("eps_strong", 0.03)
         kw.setdefault("npre", 1)
         kw.setdefault("npost", 1)
         return cls(**kw)

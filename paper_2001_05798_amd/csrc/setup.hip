@@ -1022,16 +1022,155 @@ __global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32
     lu_in_place(a, n, piv, status);
 }
 
-constexpr int kLuLdsMax = 88;  // 88 x 88 doubles = 61952 B of LDS
+constexpr int kLuLdsSmall = 88;  // up to 88 x 88 (61952 B): 256 threads, more: 1024
 
-__global__ void __launch_bounds__(256) k_dense_lu_lds(double *__restrict__ a, int32_t n,
-                                                       int32_t *__restrict__ piv, int32_t *status) {
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_dense_lu_lds(double *__restrict__ a, int32_t n,
+                                                         int32_t *__restrict__ piv, int32_t *status) {
     extern __shared__ double lu_sm[];
     for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) lu_sm[e] = a[e];
     __syncthreads();
     lu_in_place(lu_sm, n, piv, status);
     __syncthreads();
     for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) a[e] = lu_sm[e];
+}
+
+// Blocked form of the same factorization for matrices past the LDS limit:
+// panels of nb columns.  The panel kernel factors columns [k0, k0+nb) over
+// rows [k0, n) in LDS (pivot search, swap inside the panel, scaling, and the
+// updates of the panel's later columns); the update kernel then applies the
+// panel's row swaps to every other column, solves the panel rows of the
+// later columns with the panel's unit lower triangle (U12), and subtracts
+// L21 U12 from the trailing matrix.  Every entry receives the updates of
+// steps k in increasing k, each a product then a difference, and every
+// pivot is chosen from the same column values, so the factors and pivots
+// equal those of the unblocked loop bit for bit.
+__global__ void __launch_bounds__(1024) k_lu_panel(double *__restrict__ a, int32_t n, int32_t k0, int32_t nb,
+                                                   int32_t *__restrict__ piv, int32_t *status) {
+    extern __shared__ double pan[];  // rows k0..n-1, nb columns, row-major
+    __shared__ double sv[16];
+    __shared__ int32_t si[16];
+    __shared__ int32_t p_sh;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+    const int32_t m = n - k0;  // panel rows
+    if (*status != 0) return;   // an earlier panel met a zero pivot
+    for (int32_t e = tid; e < m * nb; e += blockDim.x) {
+        const int32_t r = e / nb, c = e - r * nb;
+        pan[e] = a[(int64_t)(k0 + r) * n + k0 + c];
+    }
+    __syncthreads();
+    for (int32_t kk = 0; kk < nb; ++kk) {
+        double best = -1.0;
+        int32_t bi = m;
+        for (int32_t r = kk + tid; r < m; r += blockDim.x) {
+            const double v = fabs(pan[r * nb + kk]);
+            if (v > best) { best = v; bi = r; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(best, o, 64);
+            const int32_t i2 = __shfl_xor(bi, o, 64);
+            if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+        }
+        if (lane == 0) { sv[w] = best; si[w] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = sv[0];
+            int32_t ix = si[0];
+            for (int q = 1; q < nw; ++q)
+                if (sv[q] > b || (sv[q] == b && si[q] < ix)) { b = sv[q]; ix = si[q]; }
+            p_sh = (b == 0.0) ? -1 : ix;
+            piv[k0 + kk] = k0 + ix;
+        }
+        __syncthreads();
+        const int32_t p = p_sh;
+        if (p < 0) {
+            if (tid == 0) *status = GW_SINGULAR;
+            return;
+        }
+        if (p != kk)
+            for (int32_t c = tid; c < nb; c += blockDim.x) {
+                const double t = pan[kk * nb + c];
+                pan[kk * nb + c] = pan[p * nb + c];
+                pan[p * nb + c] = t;
+            }
+        __syncthreads();
+        const double akk = pan[kk * nb + kk];
+        for (int32_t r = kk + 1 + tid; r < m; r += blockDim.x) pan[r * nb + kk] = pan[r * nb + kk] / akk;
+        __syncthreads();
+        const int32_t wc = nb - kk - 1;  // later panel columns
+        if (wc > 0)
+            for (int32_t e = tid; e < (m - kk - 1) * wc; e += blockDim.x) {
+                const int32_t r = kk + 1 + e / wc, c = kk + 1 + e % wc;
+                pan[r * nb + c] = pan[r * nb + c] - pan[r * nb + kk] * pan[kk * nb + c];
+            }
+        __syncthreads();
+    }
+    for (int32_t e = tid; e < m * nb; e += blockDim.x) {
+        const int32_t r = e / nb, c = e - r * nb;
+        a[(int64_t)(k0 + r) * n + k0 + c] = pan[e];
+    }
+}
+
+// The panel's swaps (in pivot order) on every column outside the panel, and
+// for the later columns their panel rows: U12 = L11^-1 A12 by forward
+// substitution (k increasing).  One lane per column, 64 columns a
+// workgroup; L11 and the column's panel rows sit in LDS during the solve.
+constexpr int kLuPanelMax = 64;
+__global__ void __launch_bounds__(64) k_lu_swap_u12(double *__restrict__ a, int32_t n, int32_t k0, int32_t w,
+                                                    const int32_t *__restrict__ piv, const int32_t *status) {
+    __shared__ double l11[kLuPanelMax * kLuPanelMax];
+    __shared__ double u[kLuPanelMax * 64];
+    if (*status != 0) return;
+    const int lane = threadIdx.x;
+    const int32_t jb = blockIdx.x * 64 + lane;  // among the n - w columns outside the panel
+    const bool live = jb < n - w;
+    const int32_t j = jb < k0 ? jb : jb + w;
+    for (int32_t e = lane; e < w * w; e += 64) l11[e] = a[(int64_t)(k0 + e / w) * n + k0 + e % w];
+    if (live)
+        for (int32_t kk = 0; kk < w; ++kk) {
+            const int32_t p = piv[k0 + kk];
+            if (p != k0 + kk) {
+                const double t = a[(int64_t)(k0 + kk) * n + j];
+                a[(int64_t)(k0 + kk) * n + j] = a[(int64_t)p * n + j];
+                a[(int64_t)p * n + j] = t;
+            }
+        }
+    __syncthreads();
+    if (!live || j < k0) return;
+    for (int32_t kk = 0; kk < w; ++kk) u[kk * 64 + lane] = a[(int64_t)(k0 + kk) * n + j];
+    for (int32_t kk = 1; kk < w; ++kk) {
+        double v = u[kk * 64 + lane];
+        for (int32_t q = 0; q < kk; ++q) v = v - l11[kk * w + q] * u[q * 64 + lane];
+        u[kk * 64 + lane] = v;
+    }
+    for (int32_t kk = 1; kk < w; ++kk) a[(int64_t)(k0 + kk) * n + j] = u[kk * 64 + lane];
+}
+
+// Trailing update a_ij -= sum_q l_iq u_qj over the panel (q increasing), one
+// thread per entry, consecutive threads along a row; the row's l_iq and the
+// column's u_qj are loaded eight at a time before they are used.
+__global__ void k_lu_trail(double *__restrict__ a, int32_t n, int32_t k0, int32_t w, const int32_t *status) {
+    if (*status != 0) return;
+    const int32_t t0 = k0 + w, nt = n - t0;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nt * nt) return;
+    const int32_t i = t0 + (int32_t)(e / nt), j = t0 + (int32_t)(e % nt);
+    const double *li = a + (int64_t)i * n + k0;
+    double v = a[(int64_t)i * n + j];
+    for (int32_t q0 = 0; q0 < w; q0 += 8) {
+        double l[8], uq[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int32_t q = min(q0 + r, w - 1);
+            l[r] = li[q];
+            uq[r] = a[(int64_t)(k0 + q) * n + j];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (q0 + r < w) v = v - l[r] * uq[r];
+    }
+    a[(int64_t)i * n + j] = v;
 }
 
 // Column c of the inverse: solve L U x = Perm e_c, one wave per column with
@@ -1886,6 +2025,16 @@ void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s) {
     GW_HIP(hipGetLastError());
 }
 
+// Dynamic LDS a workgroup of the LU may use for the matrix: the device's
+// per-block limit (160 KB on gfx950, i.e. n <= 142) less the LU's own
+// shared words.
+static size_t lu_lds_bytes() {
+    int dev = 0, v = 0;
+    GW_HIP(hipGetDevice(&dev));
+    GW_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    return v > 1024 ? (size_t)(v - 1024) : 0;
+}
+
 void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
     Level &Lv = H->L[l];
     const int32_t n = Lv.A.n;
@@ -1899,11 +2048,34 @@ void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
     {
         ProfScope ps(K_COARSE_LU, (double)n * n * 24, s);
         hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, s, view(Lv.A), H->lu.p);
-        if (n <= kLuLdsMax)
-            hipLaunchKernelGGL(k_dense_lu_lds, dim3(1), dim3(256), (size_t)n * n * sizeof(double), s, H->lu.p, n,
-                               H->piv.p, status.p);
-        else
-            hipLaunchKernelGGL(k_dense_lu, dim3(1), dim3(1024), 0, s, H->lu.p, n, H->piv.p, status.p);
+        const size_t lds = (size_t)n * n * sizeof(double);
+        if (n <= kLuLdsSmall) {
+            hipLaunchKernelGGL(k_dense_lu_lds<256>, dim3(1), dim3(256), lds, s, H->lu.p, n, H->piv.p, status.p);
+        } else if (lds <= lu_lds_bytes()) {
+            // past 64 KB of dynamic LDS the kernel has to ask for it
+            GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dense_lu_lds<1024>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(k_dense_lu_lds<1024>, dim3(1), dim3(1024), lds, s, H->lu.p, n, H->piv.p, status.p);
+        } else {
+            // panels as wide as the LDS holds (n x nb doubles), at most 64
+            int32_t nb = kLuPanelMax;
+            while (nb > 1 && (size_t)n * nb * sizeof(double) > lu_lds_bytes()) nb /= 2;
+            const size_t plds = (size_t)n * nb * sizeof(double);
+            if (plds > 65536)
+                GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lu_panel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));
+            for (int32_t k0 = 0; k0 < n; k0 += nb) {
+                const int32_t w = std::min(nb, n - k0), nt = n - k0 - w;
+                hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(1024), (size_t)(n - k0) * w * sizeof(double), s,
+                                   H->lu.p, n, k0, w, H->piv.p, status.p);
+                if (n - w > 0)
+                    hipLaunchKernelGGL(k_lu_swap_u12, dim3((n - w + 63) / 64), dim3(64), 0, s, H->lu.p, n, k0, w,
+                                       H->piv.p, status.p);
+                if (nt > 0)
+                    hipLaunchKernelGGL(k_lu_trail, dim3(blocks_for((int64_t)nt * nt)), dim3(kBlock), 0, s, H->lu.p,
+                                       n, k0, w, status.p);
+            }
+        }
         GW_HIP(hipGetLastError());
     }
     Staging st;

@@ -151,6 +151,11 @@ HIER_CASES = [
     ("2d 64x64 jacobi", lambda: gi.homogeneous_slab(), dict(smoother=0, npre=1, npost=1)),
     ("3d 24x20x12 s2=4", lambda: gi.heterogeneous_aquifer(24, 20, 12, 4.0, 4, 5), dict()),
     ("3d 37x23x11 s2=1 ragged", lambda: gi.heterogeneous_aquifer(37, 23, 11, 1.0, 3, 8), dict(n_coarse=40)),
+    # coarsest levels of 109 and 141 rows (LU in LDS with 1024 threads, the
+    # second at the 160 KB limit) and of 412 rows (LU in global memory)
+    ("3d 30x22x14 coarsest 109", lambda: gi.heterogeneous_aquifer(30, 22, 14, 4.0, 4, 5), dict()),
+    ("3d 36x30x12 coarsest 141", lambda: gi.heterogeneous_aquifer(36, 30, 12, 4.0, 4, 5), dict()),
+    ("3d 36x30x12 coarsest 412", lambda: gi.heterogeneous_aquifer(36, 30, 12, 4.0, 4, 5), dict(eps_strong=0.15)),
 ]
 
 
@@ -161,13 +166,25 @@ def test_flow_hierarchy_bitwise(gw, ref, name, make, kw):
     ap = ref.AmgParams(**kw)
     A, b = ref.fv_assemble(p)
     Hr = ref.Hierarchy(A, ap)
+    if "coarsest" in name:  # the case is there for its coarsest size
+        assert Hr.level(Hr.nlevels - 1).A.n == int(name.split("coarsest ")[1])
     K, rowptr, col, val, bd = gpu_assemble(gw, p)
     Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap))
     _compare_hierarchy(gw, ref, Hg, Hr, name)
 
 
-def test_travel_time_hierarchy_bitwise(gw, ref):
-    _say("hierarchy travel time 24x20x12")
+TT_HIER_CASES = [
+    ("coarse 42", dict(n_coarse=40)),
+    # a coarsest level of 729 and of 1320 rows: blocked LU (panels of 16 and
+    # 8 columns in LDS), with 15 and 27 row interchanges
+    ("coarsest 729", dict(n_coarse=1500)),
+    ("coarsest 1320", dict(n_coarse=1500, eps_strong=0.25)),
+]
+
+
+@pytest.mark.parametrize("name,kw", TT_HIER_CASES, ids=[c[0] for c in TT_HIER_CASES])
+def test_travel_time_hierarchy_bitwise(gw, ref, name, kw):
+    _say(f"hierarchy travel time 24x20x12 {name}")
     import scipy.sparse.linalg as sla
     p = gi.heterogeneous_aquifer(24, 20, 12, 4.0, 4, 5)
     A, b = ref.fv_assemble(p)
@@ -187,10 +204,12 @@ def test_travel_time_hierarchy_bitwise(gw, ref):
     assert np.array_equal(host(vl)[:nnz].view(np.uint64), At.val.view(np.uint64))
     assert np.array_equal(host(dbt).view(np.uint64), bt.view(np.uint64))
     assert np.array_equal(host(dbc).view(np.uint64), bc.view(np.uint64))
-    ap = ref.AmgParams(n_coarse=40)
+    ap = ref.AmgParams(**kw)
     Hr = ref.Hierarchy(At, ap)
+    if name.startswith("coarsest"):
+        assert Hr.level(Hr.nlevels - 1).A.n == int(name.split()[1])
     Hg = gw.amg_setup(n, rp, cl[:nnz].contiguous(), vl[:nnz].contiguous(), gpu_params(gw, ap))
-    _compare_hierarchy(gw, ref, Hg, Hr, "travel time")
+    _compare_hierarchy(gw, ref, Hg, Hr, "travel time " + name)
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
