@@ -193,7 +193,7 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
     arrivals = gi.serve_stream(n_requests, 1.0, seed=seed)
     with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
         probs = list(ex.map(_make_problem, arrivals))
-    ap = gw.AmgParams(precision=gw.PRECISION_MIXED)
+    ap = gw.AmgParams.flow(precision=gw.PRECISION_MIXED)
     tp = gw.AmgParams.travel_time(precision=gw.PRECISION_MIXED)
     sp = gw.SolveParams(rtol=1e-8)
     budget = int(os.environ.get("GWAMG_SERVE_BUDGET", str(96 << 30)))
@@ -233,7 +233,7 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
     cells = np.array([p.grid.n for p in probs])
     # the same burst with an FP64 hierarchy: the plain FP64 GPU solve the
     # mixed-precision served form is compared with
-    ap64 = gw.AmgParams(precision=gw.PRECISION_FP64)
+    ap64 = gw.AmgParams.flow(precision=gw.PRECISION_FP64)
     tp64 = gw.AmgParams.travel_time(precision=gw.PRECISION_FP64)
     q = gw.Queue(budget, slots)
     t0 = q.clock()
@@ -469,8 +469,8 @@ def main():
     if not args.no_ilu:
         g = pipe.g
         res = {}
-        variants = (("spai0", gw.AmgParams()), ("ilu0", gw.AmgParams(smoother=gw.SMOOTHER_ILU0)),
-                    ("rs_spai0", gw.AmgParams(coarsening=gw.COARSEN_RS, eps_strong=0.25)))
+        variants = (("spai0", gw.AmgParams.flow()), ("ilu0", gw.AmgParams.flow(smoother=gw.SMOOTHER_ILU0)),
+                    ("rs_spai0", gw.AmgParams.flow(coarsening=gw.COARSEN_RS, eps_strong=0.25)))
         for name, prm in variants:
             for rep in range(1 if prm.smoother == gw.SMOOTHER_ILU0 else 2):
                 torch.cuda.synchronize()
