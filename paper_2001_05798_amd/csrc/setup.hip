@@ -1685,7 +1685,7 @@ void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     // PMIS rounds; und[r] = some point was undecided before round r
     DBuf<double> w(n);
     DBuf<int32_t> cf(n), newc(n);
-    constexpr int kMaxRounds = 4096, kBatch = 12;
+    constexpr int kMaxRounds = 4096, kBatch = 12, kLate = 4;
     DBuf<int32_t> und(kMaxRounds + 1);
     fill_i32(und.p, 0, kMaxRounds + 1, s);
     {
@@ -1696,8 +1696,12 @@ void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     }
     int rounds = 0;
     for (;;) {
-        GW_REQUIRE(rounds + kBatch <= kMaxRounds, "amg_setup: PMIS did not terminate");
-        for (int b = 0; b < kBatch; ++b) {
+        // a first batch of kBatch rounds covers most levels; later ones
+        // take kLate, so a level needing a few more rounds launches few
+        // no-op rounds
+        const int batch = rounds == 0 ? kBatch : kLate;
+        GW_REQUIRE(rounds + batch <= kMaxRounds, "amg_setup: PMIS did not terminate");
+        for (int b = 0; b < batch; ++b) {
             const int r = rounds + b;
             ProfScope ps(K_MIS2, (double)S.nnz * 16 + n * 24.0, s);
             hipLaunchKernelGGL(k_pmis_c, dim3(nb), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, St.rowptr.p, St.col.p, n,
@@ -1707,15 +1711,15 @@ void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         }
         GW_HIP(hipGetLastError());
         int32_t flags[kBatch + 1];
-        rd.sync(s, und.p + rounds, sizeof(flags), flags);
+        rd.sync(s, und.p + rounds, sizeof(int32_t) * (batch + 1), flags);
         if (flags[0] == 0) break;  // nothing was undecided before this batch
         int b = 0;
-        while (b < kBatch && flags[1 + b] > 0) ++b;
-        if (b < kBatch) {
+        while (b < batch && flags[1 + b] > 0) ++b;
+        if (b < batch) {
             rounds += b + 1;
             break;
         }
-        rounds += kBatch;
+        rounds += batch;
     }
     Lv.mis_rounds = rounds;
     St = Csr();
@@ -1895,7 +1899,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     // back with the round flags: they are final when the rounds have ended.
     DBuf<uint32_t> state(n);
     DBuf<uint64_t> m1(n);
-    constexpr int kMaxRounds = 4096, kBatch = 12;
+    constexpr int kMaxRounds = 4096, kBatch = 12, kLate = 4;
     DBuf<int32_t> und(kMaxRounds + 1);
     fill_i32(und.p, 0, kMaxRounds + 1, s);
     const uint32_t salt = level_salt(prm.seed, l);
@@ -1915,8 +1919,12 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
     int rounds = 0;
     for (;;) {
-        GW_REQUIRE(rounds + kBatch <= kMaxRounds, "amg_setup: MIS-2 did not terminate");
-        for (int b = 0; b < kBatch; ++b) {
+        // a first batch of kBatch rounds covers most levels; later ones
+        // take kLate, so a level needing a few more rounds launches few
+        // no-op rounds
+        const int batch = rounds == 0 ? kBatch : kLate;
+        GW_REQUIRE(rounds + batch <= kMaxRounds, "amg_setup: MIS-2 did not terminate");
+        for (int b = 0; b < batch; ++b) {
             int r = rounds + b;
             ProfScope ps(K_MIS2, (double)A.nnz * 8 + n * 20.0, s);
             with_group(srow_mean, [&](auto gc) {
@@ -1945,15 +1953,15 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         }
         spgemm_bound(af, bt, n, arow, rd.blk(0), s);
         int32_t flags[kBatch + 1];
-        rd.sync(s, und.p + rounds, sizeof(flags), flags);
+        rd.sync(s, und.p + rounds, sizeof(int32_t) * (batch + 1), flags);
         if (flags[0] == 0) break;  // nothing was undecided before this batch
         int b = 0;
-        while (b < kBatch && flags[1 + b] > 0) ++b;
-        if (b < kBatch) {
+        while (b < batch && flags[1 + b] > 0) ++b;
+        if (b < batch) {
             rounds += b + 1;
             break;
         }
-        rounds += kBatch;
+        rounds += batch;
     }
     Lv.mis_rounds = rounds;
     m1.release();
