@@ -855,9 +855,11 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
         }
     }
     if (!NUM) {
-        // row lengths; the scan over them also yields the largest row
+        // row lengths (and the leading zero); the scan over them also
+        // yields the largest row
         int32_t tot = group_sum<G>(fresh_count);
         if (active && lane == 0) cnt[row + 1] = tot;
+        if (row == 0 && lane == 0) cnt[0] = 0;
     } else if (active) {
         // Sorted write-out: the occupied slots are packed into the stage
         // (when the row fits it) so that each entry's rank is counted over
@@ -1439,7 +1441,7 @@ int spgemm_group(double avg_a_len) {
 // blk: [0] row bound, [1] largest row, [2] overflow, [4..5] nnz (int64).
 template <class AR, class BR>
 void spgemm_bound(AR ar, BR br, int32_t nrows, double avg_a_len, int32_t *blk, hipStream_t s) {
-    fill_i32(blk, 0, 1, s);
+    fill_i32(blk, 0, 6, s);  // the bound, and the words the symbolic pass that follows accumulates into
     ProfScope ps(K_SPGEMM, 0, s);
     // short rows: one lane per row (the row sums are a few loads)
     with_group(avg_a_len > 12.0 ? avg_a_len : 1.0, [&](auto gc) {
@@ -1486,9 +1488,7 @@ void spgemm_symbolic(AR ar, BR br, EPI epi, int32_t nrows, int32_t ncols, double
                      int32_t ub, Csr &C, int32_t *blk, hipStream_t s) {
     const int64_t cap = std::min<int64_t>(ub, ncols);
     const int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
-    C.alloc(nrows, ncols, 0);
-    fill_i32(C.rowptr.p, 0, 1, s);  // the symbolic pass writes every other row length
-    fill_i32(blk + 1, 0, 5, s);
+    C.alloc(nrows, ncols, 0);  // blk[1..5] were cleared by the product's spgemm_bound
     const SpgShape sh = spg_shape(avg_a_len, avg_b_len);
 #define SPG_SYM(GG)                                                                                           \
     hipLaunchKernelGGL((k_spgemm<GG, false, AR, BR, EPI>), g, b, shm, s, ar, br, nrows, hb, Sx, C.rowptr.p, \
@@ -1543,13 +1543,23 @@ void spgemm_numeric(AR ar, BR br, EPI epi, int32_t nrows, double avg_a_len, doub
 }
 
 // Device words of one level read back together at a few host reads.
-//   [0..1] strength-graph nnz, [4..5] aggregates, [8..15] P, [16..23] AP,
-//   [24..31] A_c (each an spgemm blk).
+//   [0..1] strength-graph nnz, [2] pattern-symmetry misses (SA) or [2..3]
+//   P nnz (RS), [4..5] aggregates / coarse points, [6..7] the spectral
+//   bound's bits (SA), [8..15] P, [16..23] AP, [24..31] A_c (each an spgemm
+//   blk).
 constexpr int kLevelWords = 32;
+constexpr int kMaxMisRounds = 4096;
 struct LevelReads {
     DBuf<int32_t> d;
     int32_t h[kLevelWords] = {};
-    explicit LevelReads(hipStream_t s) : d(kLevelWords) { fill_i32(d.p, 0, kLevelWords, s); }
+    // the read words, then the per-round "undecided left" flags of the
+    // MIS-2 / PMIS rounds, cleared by one launch
+    explicit LevelReads(hipStream_t s) : d(kLevelWords + kMaxMisRounds + 1) {
+        fill_i32(d.p, 0, kLevelWords + kMaxMisRounds + 1, s);
+    }
+    int32_t *und() { return d.p + kLevelWords; }
+    int32_t *miss() { return d.p + 2; }  // pattern-symmetry misses (smoothed aggregation)
+    unsigned long long *rho() { return reinterpret_cast<unsigned long long *>(d.p + 6); }  // words 6..7
     int32_t *blk(int k) { return d.p + 8 + 8 * k; }  // 0: P, 1: AP, 2: A_c
     const int32_t *hblk(int k) const { return h + 8 + 8 * k; }
     int64_t *total(int word) { return reinterpret_cast<int64_t *>(d.p + word); }
@@ -1685,13 +1695,12 @@ void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     // PMIS rounds; und[r] = some point was undecided before round r
     DBuf<double> w(n);
     DBuf<int32_t> cf(n), newc(n);
-    constexpr int kMaxRounds = 4096, kBatch = 12, kLate = 4;
-    DBuf<int32_t> und(kMaxRounds + 1);
-    fill_i32(und.p, 0, kMaxRounds + 1, s);
+    constexpr int kMaxRounds = kMaxMisRounds, kBatch = 12, kLate = 4;
+    int32_t *und = rd.und();
     {
         ProfScope ps(K_MIS2, n * 20.0, s);
         hipLaunchKernelGGL(k_pmis_init, dim3(nb), dim3(kBlock), 0, s, St.rowptr.p, n, level_salt(prm.seed, l), w.p,
-                           cf.p, und.p);
+                           cf.p, und);
         GW_HIP(hipGetLastError());
     }
     int rounds = 0;
@@ -1707,11 +1716,11 @@ void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             hipLaunchKernelGGL(k_pmis_c, dim3(nb), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, St.rowptr.p, St.col.p, n,
                                w.p, cf.p, newc.p);
             hipLaunchKernelGGL(k_pmis_f, dim3(nb), dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, newc.p, cf.p,
-                               und.p + r + 1);
+                               und + r + 1);
         }
         GW_HIP(hipGetLastError());
         int32_t flags[kBatch + 1];
-        rd.sync(s, und.p + rounds, sizeof(int32_t) * (batch + 1), flags);
+        rd.sync(s, und + rounds, sizeof(int32_t) * (batch + 1), flags);
         if (flags[0] == 0) break;  // nothing was undecided before this batch
         int b = 0;
         while (b < batch && flags[1 + b] > 0) ++b;
@@ -1797,6 +1806,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     DBuf<double> diag(n), dF(n), sw;
     DBuf<int64_t> total(1);
     csr_diag(A, diag.p, s);
+    LevelReads rd(s);
 
     // strength graph on A and A^T (A^T from A's own pattern when that is
     // symmetric, as for the flow operator and all its Galerkin products)
@@ -1806,18 +1816,17 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     bool sym = false;
     if (H->sym_pattern != 0) {
         tval_sym.alloc((size_t)std::max<int64_t>(A.nnz, 1));
-        DBuf<int32_t> miss(1);
-        fill_i32(miss.p, 0, 1, s);
+        int32_t *miss = rd.miss();
         {
             ProfScope ps(K_TRANSPOSE, (double)A.nnz * 24, s);
             with_group(mean_row(A.nnz, n), [&](auto gc) {
                 constexpr int G = decltype(gc)::value;
                 hipLaunchKernelGGL((k_sym_transpose<G>), dim3(std::min(blocks_for((int64_t)n * G), kAtomicBlocks)),
-                                   dim3(kBlock), 0, s, A, tval_sym.p, miss.p);
+                                   dim3(kBlock), 0, s, A, tval_sym.p, miss);
             });
             GW_HIP(hipGetLastError());
         }
-        sym = st.read(miss.p, s) == 0;
+        sym = st.read(miss, s) == 0;
         H->sym_pattern = sym ? 1 : 0;
     }
     if (sym) {
@@ -1875,7 +1884,6 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             default: grp(std::integral_constant<int, 64>()); break;
         }
     };
-    LevelReads rd(s);
     {
         ProfScope ps(K_STRENGTH, (double)A.nnz * 24 + n * 16.0, s);
         launch_strength(false);
@@ -1899,14 +1907,13 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     // back with the round flags: they are final when the rounds have ended.
     DBuf<uint32_t> state(n);
     DBuf<uint64_t> m1(n);
-    constexpr int kMaxRounds = 4096, kBatch = 12, kLate = 4;
-    DBuf<int32_t> und(kMaxRounds + 1);
-    fill_i32(und.p, 0, kMaxRounds + 1, s);
+    constexpr int kMaxRounds = kMaxMisRounds, kBatch = 12, kLate = 4;
+    int32_t *und = rd.und();
     const uint32_t salt = level_salt(prm.seed, l);
     {
         ProfScope ps(K_MIS2, n * 8.0, s);
         hipLaunchKernelGGL(k_mis_init, dim3(std::min(blocks_for(n), kAtomicBlocks)), dim3(kBlock), 0, s, S.rowptr.p, n,
-                           state.p, und.p);
+                           state.p, und);
         GW_HIP(hipGetLastError());
     }
     // lanes per row from A's off-diagonal row length (the graph's own size is
@@ -1931,9 +1938,9 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
                 constexpr int G = decltype(gc)::value;
                 const dim3 grid(blocks_for((int64_t)n * G));
                 hipLaunchKernelGGL((k_mis_m1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
-                                   m1.p, und.p + r);
+                                   m1.p, und + r);
                 hipLaunchKernelGGL((k_mis_m2<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
-                                   m1.p, und.p + r, und.p + r + 1);
+                                   m1.p, und + r, und + r + 1);
             });
         }
         GW_HIP(hipGetLastError());
@@ -1953,7 +1960,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         }
         spgemm_bound(af, bt, n, arow, rd.blk(0), s);
         int32_t flags[kBatch + 1];
-        rd.sync(s, und.p + rounds, sizeof(int32_t) * (batch + 1), flags);
+        rd.sync(s, und + rounds, sizeof(int32_t) * (batch + 1), flags);
         if (flags[0] == 0) break;  // nothing was undecided before this batch
         int b = 0;
         while (b < batch && flags[1 + b] > 0) ++b;
@@ -1979,18 +1986,17 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     }
 
     // smoothed prolongator
-    DBuf<unsigned long long> rho_bits(1);
+    unsigned long long *rho_bits = rd.rho();
     DBuf<double> &omega = Lv.omega_dev;  // read back once the hierarchy is built
     omega.alloc(1);
-    fill_i32(reinterpret_cast<int32_t *>(rho_bits.p), 0, 2, s);
     {
         ProfScope ps(K_SETUP_MISC, (double)A.nnz * 8 + n * 8.0, s);
         with_group(mean_row(A.nnz, n), [&](auto gc) {
             constexpr int G = decltype(gc)::value;
             hipLaunchKernelGGL((k_rho<G>), dim3(std::min(blocks_for((int64_t)n * G), kAtomicBlocks)), dim3(kBlock), 0,
-                               s, A, diag.p, rho_bits.p);
+                               s, A, diag.p, rho_bits);
         });
-        hipLaunchKernelGGL(k_omega, dim3(1), dim3(64), 0, s, rho_bits.p, omega.p);
+        hipLaunchKernelGGL(k_omega, dim3(1), dim3(64), 0, s, rho_bits, omega.p);
         GW_HIP(hipGetLastError());
     }
     EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
