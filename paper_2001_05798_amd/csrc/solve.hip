@@ -1255,6 +1255,32 @@ enum BlockKind : int { BLOCK_PCG = 1, BLOCK_BICGSTAB = 2, BLOCK_BICGSTAB2 = 3 };
 // instantiated graph is launched on s.  Every kernel reads its scalars and
 // the convergence flag from device memory, so a replay after convergence is
 // a run of early exits, exactly as the one-by-one launches are.
+// Iterations to enqueue before the next convergence poll: check_every, or
+// fewer once the residual's rate of decrease over the last block predicts
+// convergence sooner, so that few iterations run as early exits after it
+// (each still launches its kernels).  Graph replays keep their captured
+// check_every.  Only the launching changes: the iterates are the same.
+struct PollPlan {
+    int check;
+    bool graph;
+    double rn_prev = -1.0;
+    int it_prev = 0;
+    int predict(double rn, double goal, int iters) const {
+        if (graph || rn_prev <= 0.0 || iters <= it_prev || !(rn < rn_prev) || !(rn > goal) || !(goal > 0.0))
+            return check;
+        const double rate = std::pow(rn / rn_prev, 1.0 / (iters - it_prev));
+        const double need = std::log(goal / rn) / std::log(rate);
+        if (!std::isfinite(need)) return check;
+        return std::max(1, std::min(check, (int)std::ceil(need)));
+    }
+    int next(double rn, double goal, int iters) {
+        const int c = predict(rn, goal, iters);
+        rn_prev = rn;
+        it_prev = iters;
+        return c;
+    }
+};
+
 template <class Emit>
 void run_block(amg_hierarchy *H, bool graph, int kind, int check, int parity, hipStream_t s, Emit &&emit) {
     if (!graph) {
@@ -1457,6 +1483,7 @@ int pcg_impl(amg_hierarchy *H, const double *shift, const double *b, double *x_o
     const bool graph = !SHIFT && use_graph(sp);
     int32_t *done = &H->ks.p->done;
     int parity = 0;
+    int cnt = check;  // iterations in the next block
     // check_every iterations: q = A p, alpha, x and r updates with the
     // convergence test, z = M r, beta
     auto block = [&](int parity0) {
@@ -1464,7 +1491,7 @@ int pcg_impl(amg_hierarchy *H, const double *shift, const double *b, double *x_o
             Kry Kc(H, cs, sp.rtol);
             Kc.shift = shift;
             int par = parity0;
-            for (int c = 0; c < check; ++c) {
+            for (int c = 0; c < cnt; ++c) {
                 double *po = par ? pb : pa, *pn = par ? pa : pb;
                 {
                     ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs);
@@ -1499,11 +1526,14 @@ int pcg_impl(amg_hierarchy *H, const double *shift, const double *b, double *x_o
                 hipLaunchKernelGGL(k_cg_dot, dim3(K.g1), dim3(kKBlock), 0, s, n, r, z, q, K.part, K.ks);
             }
             K.fin(FIN_CG_BETA_FIRST, K.g1);
+            PollPlan plan{check, graph};
+            cnt = check;
             for (;;) {
                 run_block(H, graph, BLOCK_PCG, check, parity, s, block(parity));
-                parity ^= check & 1;
+                parity ^= cnt & 1;
                 k = read_ks(H, s);
                 if (k.done) break;
+                cnt = plan.next(std::sqrt(k.rr), k.tol, k.iters);
             }
         }
         K.template true_res<SHIFT>(b, x);
@@ -1565,10 +1595,11 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
     const int check = std::max(1, sp.check_every);
     const bool graph = use_graph(sp);
     int32_t *done = &H->ks.p->done;
-    // check_every iterations of right-preconditioned BiCGSTAB
+    int cnt = check;  // iterations in the next block
+    // cnt iterations of right-preconditioned BiCGSTAB
     auto block = [&](hipStream_t cs) {
         Kry Kc(H, cs, sp.rtol);
-        for (int c = 0; c < check; ++c) {
+        for (int c = 0; c < cnt; ++c) {
             {
                 ProfScope ps(K_KRYLOV_UPDATE, 4 * Kc.vec, cs);
                 hipLaunchKernelGGL(k_bcg_p, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, p, v, Kc.ks);
@@ -1606,9 +1637,12 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
         GW_HIP(hipGetLastError());
     };
     for (;;) {
+        PollPlan plan{check, graph};
+        cnt = check;
         while (!k.done) {
             run_block(H, graph, BLOCK_BICGSTAB, check, 0, s, block);
             k = read_ks(H, s);
+            cnt = plan.next(std::sqrt(k.rr), k.tol, k.iters);
         }
         K.true_res(b, x);
         k = read_ks(H, s);
@@ -1692,9 +1726,10 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
     const int check = std::max(1, sp.check_every);
     const bool graph = use_graph(sp);
     const int32_t *done = &ks[2].done;
+    int cnt = check;  // iterations in the next block
     auto block = [&](hipStream_t cs) {
         Kry Kc(H, cs, sp.rtol);
-        for (int c = 0; c < check; ++c) {
+        for (int c = 0; c < cnt; ++c) {
             {
                 ProfScope ps(K_KRYLOV_UPDATE, 4 * vec2, cs);
                 hipLaunchKernelGGL(k_bcg_p2, dim3(Kc.g1), dim3(kKBlock), 0, cs, n, r, p, v, ks);
@@ -1731,9 +1766,19 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
         GW_HIP(hipGetLastError());
     };
     for (;;) {
+        // the block ends when the slower of the running systems is predicted
+        // to converge
+        PollPlan plan[2] = {{check, graph}, {check, graph}};
+        cnt = check;
         while (!kk[2].done) {
             run_block(H, graph, BLOCK_BICGSTAB2, check, 0, s, block);
             read_ks3(H, kk, s);
+            int c2 = 1;
+            for (int q = 0; q < 2; ++q) {
+                const int cq = plan[q].next(std::sqrt(kk[q].rr), kk[q].tol, kk[q].iters);
+                if (!kk[q].done) c2 = std::max(c2, cq);
+            }
+            cnt = c2;
         }
         {
             ProfScope ps(K_TRUE_RESIDUAL, K.abytes + 2 * vec2, s);
