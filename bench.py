@@ -408,7 +408,8 @@ def main():
                     "traffic": measured_traffic(args.workload, dominant),
                     "bytes_per_launch": per_launch_bytes, "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches": s["launches"],
-                    "timing": (f"HIP events around each launch, in {args.steps} further steps "
+                    "timing": (f"start and end events taken by each launch of the class itself "
+                               f"(hipExtLaunchKernelGGL), in {args.steps} further steps "
                                f"({ms_per_step_events:.2f} ms/step with the events)")}
     # per-class table from the warm-up steps (every launch bracketed there)
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),

@@ -3,6 +3,7 @@
 // and the kernel launchers shared between the .hip translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -124,14 +125,28 @@ enum KernelId : int {
 };
 const char *kernel_name(int id);
 bool prof_on();
+// Times the work enqueued on s during its lifetime with a pair of events
+// (when profiling is on and the class is selected).  With ext = true the
+// scope holds exactly one launch, made through GW_LAUNCH_TIMED, and the
+// events are taken by that dispatch itself (kernel start and end), without
+// the barrier packets of two hipEventRecord calls (about 3 us per launch).
 struct ProfScope {
     int id;
     double bytes;
     hipStream_t s;
+    bool ext;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    ProfScope(int id_, double bytes_, hipStream_t s_);
+    ProfScope(int id_, double bytes_, hipStream_t s_, bool ext_ = false);
     ~ProfScope();
 };
+
+#define GW_LAUNCH_TIMED(ps, kernel, grid, block, shm, stream, ...)                                          \
+    do {                                                                                                    \
+        if ((ps).e0 && (ps).ext)                                                                            \
+            hipExtLaunchKernelGGL(kernel, grid, block, shm, stream, (ps).e0, (ps).e1, 0u, __VA_ARGS__);     \
+        else                                                                                                \
+            hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__);                              \
+    } while (0)
 void prof_flush();
 
 // ------------------------------------------------------- device matrices --

@@ -202,7 +202,7 @@ const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kNames[id] 
 
 bool prof_on() { return prof().on; }
 
-ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_) : id(id_), bytes(bytes_), s(s_) {
+ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_, bool ext_) : id(id_), bytes(bytes_), s(s_), ext(ext_) {
     ProfState &P = prof();
     if (!P.on || (P.only >= 0 && P.only != id)) return;
     // launches being captured into a graph are not timed one by one
@@ -211,14 +211,14 @@ ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_) : id(id_), bytes(by
     std::lock_guard<std::mutex> g(P.mu);
     e0 = take_event(P);
     e1 = take_event(P);
-    GW_HIP(hipEventRecord(e0, s));
+    if (!ext) GW_HIP(hipEventRecord(e0, s));
 }
 
 ProfScope::~ProfScope() {
     if (!e0) return;
     ProfState &P = prof();
     std::lock_guard<std::mutex> g(P.mu);
-    if (hipEventRecord(e1, s) != hipSuccess) return;
+    if (!ext && hipEventRecord(e1, s) != hipSuccess) return;
     P.pending.push_back({id, bytes, e0, e1});
 }
 

@@ -513,10 +513,10 @@ void *vcycle_level_ilu(amg_hierarchy *H, int l, const double *b, Zt *out, const 
     const int npre = H->prm.npre, npost = H->prm.npost;
     const double abytes = op_bytes(Lv.A, Lv.As, 8);
     auto residual = [&](const double *xin, double *r) {
-        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + n * 24.0, s);
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + n * 24.0, s, true);
         with_level_op<double>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_residual<OP, double, double, double, double, 1>), dim3(grid_rows(n, OP::G)),
+            GW_LAUNCH_TIMED(ps, (k_residual<OP, double, double, double, double, 1>), dim3(grid_rows(n, OP::G)),
                                dim3(kBlock), 0, s, n, op, b, xin, r, done);
         });
     };
@@ -536,20 +536,20 @@ void *vcycle_level_ilu(amg_hierarchy *H, int l, const double *b, Zt *out, const 
     double *bc = reinterpret_cast<double *>(Nx.vb.p);
     const int64_t nc = Lv.nc;
     {
-        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, 8) + (double)(n + nc) * 8, s);
+        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, 8) + (double)(n + nc) * 8, s, true);
         with_csr<double>(Lv.R, Lv.R.val.p, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_spmv<OP, double, double, double, 1>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0,
+            GW_LAUNCH_TIMED(ps, (k_spmv<OP, double, double, double, 1>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0,
                                s, nc, op, t, bc, done);
         });
     }
     double *xc = static_cast<double *>(vcycle_level<double, double, double, 1>(H, l + 1, bc, (double *)nullptr,
                                                                                done, s));
     {
-        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, 8) + (double)(2 * n + nc) * 8, s);
+        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, 8) + (double)(2 * n + nc) * 8, s, true);
         with_csr<double>(Lv.P, Lv.P.val.p, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_prolong<OP, double, double, 1>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
+            GW_LAUNCH_TIMED(ps, (k_prolong<OP, double, double, 1>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
                                op, xc, x, done);
         });
     }
@@ -594,20 +594,20 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
         hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n * NR)), dim3(kBlock), 0, s, x, n * NR, done);
     } else {
         ProfScope ps(level_kid(K_SMOOTH_FIRST0, l),
-                     (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb), s);
+                     (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb), s, true);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_smooth_first<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
+            GW_LAUNCH_TIMED(ps, (k_smooth_first<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
                                op, M, b, x, npre >= 2 ? 1 : 0, done);
         });
     }
     auto sweep = [&](auto *xin, auto *yout) {
         using YT = std::remove_pointer_t<decltype(yout)>;
         ProfScope ps(level_kid(K_SMOOTH0, l),
-                     abytes + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT)), s);
+                     abytes + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT)), s, true);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_smooth<OP, V, Bt, V, YT, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
+            GW_LAUNCH_TIMED(ps, (k_smooth<OP, V, Bt, V, YT, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
                                M, b, xin, yout, done);
         });
     };
@@ -617,10 +617,10 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     }
     // residual and restriction
     {
-        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + nr * n * (double)(sizeof(Bt) + 2 * vb), s);
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + nr * n * (double)(sizeof(Bt) + 2 * vb), s, true);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_residual<OP, V, Bt, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
+            GW_LAUNCH_TIMED(ps, (k_residual<OP, V, Bt, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
                                b, x, t, done);
         });
     }
@@ -628,19 +628,19 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     V *bc = reinterpret_cast<V *>(Nx.vb.p);
     const int64_t nc = Lv.nc;
     {
-        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb, s);
+        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb, s, true);
         with_csr<V>(Lv.R, LevelOps<V>::rval(Lv), [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_spmv<OP, V, V, V, NR>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t,
+            GW_LAUNCH_TIMED(ps, (k_spmv<OP, V, V, V, NR>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t,
                                bc, done);
         });
     }
     V *xc = static_cast<V *>(vcycle_level<V, V, V, NR>(H, l + 1, bc, (V *)nullptr, done, s));
     {
-        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, vb) + nr * (double)(2 * n + nc) * vb, s);
+        ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, vb) + nr * (double)(2 * n + nc) * vb, s, true);
         with_csr<V>(Lv.P, LevelOps<V>::pval(Lv), [&](auto op) {
             using OP = decltype(op);
-            hipLaunchKernelGGL((k_prolong<OP, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, xc, x,
+            GW_LAUNCH_TIMED(ps, (k_prolong<OP, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op, xc, x,
                                done);
         });
     }
@@ -1494,9 +1494,9 @@ int pcg_impl(amg_hierarchy *H, const double *shift, const double *b, double *x_o
             for (int c = 0; c < cnt; ++c) {
                 double *po = par ? pb : pa, *pn = par ? pa : pb;
                 {
-                    ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs);
+                    ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs, true);
                     Kc.template op<SHIFT>([&](auto o) {
-                        hipLaunchKernelGGL((k_cg_spmv<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, z, po,
+                        GW_LAUNCH_TIMED(ps, (k_cg_spmv<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, z, po,
                                            pn, q, Kc.part, Kc.ks);
                     });
                 }
@@ -1606,9 +1606,9 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
             }
             vcycle(H, p, ph, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs, true);
                 Kc.op([&](auto o) {
-                    hipLaunchKernelGGL((k_bcg_v<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
+                    GW_LAUNCH_TIMED(ps, (k_bcg_v<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
                                        Kc.part, Kc.ks);
                 });
             }
@@ -1620,9 +1620,9 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
             Kc.fin(FIN_BCG_S, Kc.g1);
             vcycle(H, sv, sh, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs, true);
                 Kc.op([&](auto o) {
-                    hipLaunchKernelGGL((k_bcg_t<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
+                    GW_LAUNCH_TIMED(ps, (k_bcg_t<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
                                        Kc.part, Kc.ks);
                 });
             }
@@ -1736,9 +1736,9 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
             }
             vcycle2(H, p, ph, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs, true);
                 Kc.op([&](auto o) {
-                    hipLaunchKernelGGL((k_bcg_v2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
+                    GW_LAUNCH_TIMED(ps, (k_bcg_v2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
                                        part, ks);
                 });
             }
@@ -1750,9 +1750,9 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
             fin2(cs, FIN_BCG_S, Kc.g1, 3);
             vcycle2(H, sv, sh, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs, true);
                 Kc.op([&](auto o) {
-                    hipLaunchKernelGGL((k_bcg_t2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
+                    GW_LAUNCH_TIMED(ps, (k_bcg_t2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
                                        part, ks);
                 });
             }
