@@ -106,11 +106,12 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
         GW_HIP(hipStreamSynchronize(s));
         return H.release();
     }
+    CoarseJob coarse;  // after H: waits for the side stream before H is freed
     for (int l = 0;; ++l) {
         bool coarsest = false;
         build_level(H.get(), l, s, &coarsest);
         if (coarsest) {
-            build_coarsest(H.get(), l, s);
+            start_coarsest(H.get(), l, s, coarse);
             H->nlev = l + 1;
             break;
         }
@@ -155,6 +156,7 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
         Lv.vt.alloc(n * es);
         if (l > 0) Lv.vb.alloc(n * es);
     }
+    finish_coarsest(coarse, s);
     GW_HIP(hipStreamSynchronize(s));
     return H.release();
 }

@@ -98,6 +98,10 @@ struct DBuf {
 constexpr size_t kHostStageBytes = 4096;
 void *host_stage();
 
+// A second stream of the calling host thread on the current device, for work
+// that overlaps the caller's stream (ordered against it by events).
+hipStream_t side_stream();
+
 // Pinned host buffer.
 struct Pinned {
     void *p = nullptr;
@@ -336,7 +340,23 @@ void launch_tt_fill(const gw_grid &g, const double *qx, const double *qy, const 
 void launch_csr_check(const CsrView &A, double *diag, int32_t *bad, hipStream_t s);
 void transpose(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total);
 void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest);
-void build_coarsest(amg_hierarchy *H, int l, hipStream_t s);
+// The coarsest level's dense LU and its inverse.  start_coarsest enqueues
+// them on the thread's side stream, after the work already on s, so that
+// they overlap the rest of the setup; finish_coarsest makes s wait for them
+// and reports a zero pivot.  The job's destructor waits for the side stream,
+// so the hierarchy's buffers outlive its kernels on every path, errors
+// included (declare the job after the hierarchy it fills).
+struct CoarseJob {
+    hipStream_t side = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+    DBuf<int32_t> status;
+    CoarseJob() = default;
+    CoarseJob(const CoarseJob &) = delete;
+    CoarseJob &operator=(const CoarseJob &) = delete;
+    ~CoarseJob();
+};
+void start_coarsest(amg_hierarchy *H, int l, hipStream_t s, CoarseJob &job);
+void finish_coarsest(CoarseJob &job, hipStream_t s);
 void make_smoother(amg_hierarchy *H, int l, hipStream_t s);
 void convert_level_fp32(amg_hierarchy *H, int l, hipStream_t s);
 // Build the sliced ELL copy of level l's operator (values in FP64, plus FP32

@@ -144,6 +144,21 @@ void *host_stage() {
     return stage;
 }
 
+hipStream_t side_stream() {
+    // one per (host thread, device), created on first use and kept for the
+    // life of the process; non-blocking, so that it is ordered against the
+    // caller's stream by events only, and at the default priority
+    static thread_local std::map<int, hipStream_t> streams;
+    int dev = 0;
+    GW_HIP(hipGetDevice(&dev));
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    GW_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams[dev] = st;
+    return st;
+}
+
 Pinned::Pinned(size_t bytes) : n(bytes) {
     GW_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
     std::memset(p, 0, bytes);

@@ -1181,11 +1181,11 @@ __global__ void k_lu_trail(double *__restrict__ a, int32_t n, int32_t k0, int32_
 // The inverse is stored row-major (inv[i*n + c]) for the V-cycle's GEMV.
 constexpr int kMaxDense = 2048;
 __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu, const int32_t *__restrict__ piv,
-                                                   int32_t n, double *__restrict__ inv) {
+                                                   int32_t n, double *__restrict__ inv, const int32_t *status) {
     __shared__ double x[kMaxDense];
     const int32_t c = blockIdx.x;
     const int lane = threadIdx.x;
-    if (c >= n) return;
+    if (c >= n || *status != 0) return;
     // the permutation moves the single 1 of e_c
     int32_t pos = c;
     for (int32_t k = 0; k < n; ++k) {
@@ -2050,7 +2050,13 @@ static size_t lu_lds_bytes() {
     return v > 1024 ? (size_t)(v - 1024) : 0;
 }
 
-void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
+CoarseJob::~CoarseJob() {
+    if (side) (void)hipStreamSynchronize(side);
+    if (ready) (void)hipEventDestroy(ready);
+    if (done) (void)hipEventDestroy(done);
+}
+
+void start_coarsest(amg_hierarchy *H, int l, hipStream_t s, CoarseJob &job) {
     Level &Lv = H->L[l];
     const int32_t n = Lv.A.n;
     GW_REQUIRE(n <= 2048, "amg_setup: coarsening stalled at " + std::to_string(n) + " rows (> 2048)");
@@ -2058,19 +2064,26 @@ void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
     H->lu.alloc((size_t)n * n);
     H->inv.alloc((size_t)n * n);
     H->piv.alloc(n);
-    DBuf<int32_t> status(1);
-    fill_i32(status.p, 0, 1, s);
+    job.status.alloc(1);
+    GW_HIP(hipEventCreateWithFlags(&job.ready, hipEventDisableTiming));
+    GW_HIP(hipEventCreateWithFlags(&job.done, hipEventDisableTiming));
+    fill_i32(job.status.p, 0, 1, s);
+    GW_HIP(hipEventRecord(job.ready, s));
+    const hipStream_t q = side_stream();
+    GW_HIP(hipStreamWaitEvent(q, job.ready, 0));
+    job.side = q;
+    int32_t *status = job.status.p;
     {
-        ProfScope ps(K_COARSE_LU, (double)n * n * 24, s);
-        hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, s, view(Lv.A), H->lu.p);
+        ProfScope ps(K_COARSE_LU, (double)n * n * 24, q);
+        hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, q, view(Lv.A), H->lu.p);
         const size_t lds = (size_t)n * n * sizeof(double);
         if (n <= kLuLdsSmall) {
-            hipLaunchKernelGGL(k_dense_lu_lds<256>, dim3(1), dim3(256), lds, s, H->lu.p, n, H->piv.p, status.p);
+            hipLaunchKernelGGL(k_dense_lu_lds<256>, dim3(1), dim3(256), lds, q, H->lu.p, n, H->piv.p, status);
         } else if (lds <= lu_lds_bytes()) {
             // past 64 KB of dynamic LDS the kernel has to ask for it
             GW_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dense_lu_lds<512>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL(k_dense_lu_lds<512>, dim3(1), dim3(512), lds, s, H->lu.p, n, H->piv.p, status.p);
+            hipLaunchKernelGGL(k_dense_lu_lds<512>, dim3(1), dim3(512), lds, q, H->lu.p, n, H->piv.p, status);
         } else {
             // panels as wide as the LDS holds (n x nb doubles), at most 64
             int32_t nb = kLuPanelMax;
@@ -2081,26 +2094,31 @@ void build_coarsest(amg_hierarchy *H, int l, hipStream_t s) {
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));
             for (int32_t k0 = 0; k0 < n; k0 += nb) {
                 const int32_t w = std::min(nb, n - k0), nt = n - k0 - w;
-                hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(512), (size_t)(n - k0) * w * sizeof(double), s,
-                                   H->lu.p, n, k0, w, H->piv.p, status.p);
+                hipLaunchKernelGGL(k_lu_panel, dim3(1), dim3(512), (size_t)(n - k0) * w * sizeof(double), q,
+                                   H->lu.p, n, k0, w, H->piv.p, status);
                 if (n - w > 0)
-                    hipLaunchKernelGGL(k_lu_swap_u12, dim3((n - w + 63) / 64), dim3(64), 0, s, H->lu.p, n, k0, w,
-                                       H->piv.p, status.p);
+                    hipLaunchKernelGGL(k_lu_swap_u12, dim3((n - w + 63) / 64), dim3(64), 0, q, H->lu.p, n, k0, w,
+                                       H->piv.p, status);
                 if (nt > 0)
-                    hipLaunchKernelGGL(k_lu_trail, dim3(blocks_for((int64_t)nt * nt)), dim3(kBlock), 0, s, H->lu.p,
-                                       n, k0, w, status.p);
+                    hipLaunchKernelGGL(k_lu_trail, dim3(blocks_for((int64_t)nt * nt)), dim3(kBlock), 0, q, H->lu.p,
+                                       n, k0, w, status);
             }
         }
         GW_HIP(hipGetLastError());
     }
-    Staging st;
-    if (st.read(status.p, s) != 0) fail(GW_SINGULAR, "amg_setup: zero pivot in the coarsest-level LU");
     {
-        ProfScope ps(K_COARSE_LU, (double)n * n * 16, s);
-        hipLaunchKernelGGL(k_lu_inverse, dim3(n), dim3(64), 0, s, H->lu.p, H->piv.p, n, H->inv.p);
+        // skipped after a zero pivot (the pivots past it were never written)
+        ProfScope ps(K_COARSE_LU, (double)n * n * 16, q);
+        hipLaunchKernelGGL(k_lu_inverse, dim3(n), dim3(64), 0, q, H->lu.p, H->piv.p, n, H->inv.p, status);
         GW_HIP(hipGetLastError());
     }
-    GW_HIP(hipStreamSynchronize(s));
+    GW_HIP(hipEventRecord(job.done, q));
+}
+
+void finish_coarsest(CoarseJob &job, hipStream_t s) {
+    GW_HIP(hipStreamWaitEvent(s, job.done, 0));
+    Staging st;
+    if (st.read(job.status.p, s) != 0) fail(GW_SINGULAR, "amg_setup: zero pivot in the coarsest-level LU");
 }
 
 }  // namespace gw
