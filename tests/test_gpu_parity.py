@@ -518,3 +518,26 @@ def test_c3_mixed_flow_against_fp64_residual(gw, ref):
     assert rel <= 1.05e-8
     err = np.linalg.norm(heads[0] - heads[1]) / np.linalg.norm(heads[1])
     assert err <= 1e-6, err
+
+
+def test_setup_reports_zero_pivot_in_coarsest_lu(gw, ref):
+    # [[1, 1], [1, 1]] is its own coarsest level and elimination leaves a zero
+    # second pivot: both sides report it as singular (the LU runs beside the
+    # rest of the setup, and the status is read before amg_setup returns);
+    # the library stays usable, and [[2, 1], [1, 2]] then factors bit for bit
+    _say("zero pivot in the coarsest LU")
+    rp, cl = np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32)
+    A = ref.Csr(rowptr=rp, col=cl, val=np.ones(4))
+    with pytest.raises(ArithmeticError):
+        ref.Hierarchy(A, ref.AmgParams())
+    with pytest.raises(gw.GwError) as e:
+        gw.amg_setup(2, dev(rp), dev(cl), dev(A.val))
+    assert e.value.status == gw.SINGULAR
+    B = ref.Csr(rowptr=rp, col=cl, val=np.array([2.0, 1.0, 1.0, 2.0]))
+    lu_ref, piv_ref = ref.Hierarchy(B, ref.AmgParams()).coarse_lu()
+    Hg = gw.amg_setup(2, dev(rp), dev(cl), dev(B.val))
+    lu = torch.zeros(4, dtype=torch.float64, device="cuda")
+    piv = torch.zeros(2, dtype=torch.int32, device="cuda")
+    gw.amg_coarse_export(Hg, lu, piv)
+    assert np.array_equal(host(piv), piv_ref)
+    assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64))
