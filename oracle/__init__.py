@@ -106,6 +106,9 @@ def _declare(L):
     L.ref_vcycle.argtypes = [C.c_void_p, _f64p, _f64p]
     L.ref_pcg.restype = C.c_int
     L.ref_pcg.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32, C.c_int, C.POINTER(_Info)]
+    L.ref_pcg_dirs.restype = C.c_int
+    L.ref_pcg_dirs.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32, C.c_int, C.POINTER(_Info),
+                               C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]
     L.ref_bicgstab.restype = C.c_int
     L.ref_bicgstab.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double, C.c_int32, C.POINTER(_Info)]
     L.ref_mis2_keys.restype = None
@@ -347,6 +350,19 @@ def pcg(H: Hierarchy, b: np.ndarray, rtol: float = 1e-8, maxiter: int = 1000,
     _L().ref_pcg(H._h, np.ascontiguousarray(b, dtype=np.float64), x, rtol, maxiter,
                  1 if flexible else 0, C.byref(info))
     return x, SolveInfo(info.iters, info.status, info.restarts, info.rel_res, info.rel_res_true)
+
+
+def pcg_directions(H: Hierarchy, b: np.ndarray, rtol: float = 1e-8, maxiter: int = 1000,
+                   flexible: bool = False, max_dirs: int = 64):
+    """pcg() that also returns its search directions p_0, p_1, ... (rows)."""
+    n = H.A.n
+    x = np.zeros(n)
+    dirs = np.zeros((max_dirs, n))
+    nd = C.c_int32(0)
+    info = _Info()
+    _L().ref_pcg_dirs(H._h, np.ascontiguousarray(b, dtype=np.float64), x, rtol, maxiter,
+                      1 if flexible else 0, C.byref(info), _p(dirs), max_dirs, C.byref(nd))
+    return x, SolveInfo(info.iters, info.status, info.restarts, info.rel_res, info.rel_res_true), dirs[:nd.value]
 
 
 def bicgstab(H: Hierarchy, b: np.ndarray, rtol: float = 1e-8,

@@ -1217,9 +1217,13 @@ typedef struct {
 
 static int finite_nz(double v) { return isfinite(v) && v != 0.0; }
 
-/* PCG (flex = 0) or flexible CG with the Polak-Ribiere beta (flex = 1). */
-int ref_pcg(ref_hier *H, const double *b, double *x, double rtol, int32_t maxiter, int flex,
-            ref_info *info) {
+/* PCG (flex = 0) or flexible CG with the Polak-Ribiere beta (flex = 1).
+ * When dirs is not null, the search directions p_0, p_1, ... of the first
+ * cycle (before any restart) are copied into dirs[k*n .. k*n+n-1], at most
+ * max_dirs of them, and their count is stored in *ndirs (a test hook: the
+ * iteration itself is the same with or without it). */
+static int pcg_run(ref_hier *H, const double *b, double *x, double rtol, int32_t maxiter, int flex,
+                   ref_info *info, double *dirs, int32_t max_dirs, int32_t *ndirs) {
     const rcsr *A = &H->L[0].A;
     int32_t n = A->n;
     memset(info, 0, sizeof(*info));
@@ -1238,6 +1242,8 @@ int ref_pcg(ref_hier *H, const double *b, double *x, double rtol, int32_t maxite
         for (int32_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
         ref_vcycle(H, r, z);
         for (int32_t i = 0; i < n; ++i) p[i] = z[i];
+        if (dirs && info->restarts == 0 && *ndirs < max_dirs)
+            memcpy(dirs + (size_t)(*ndirs)++ * (size_t)n, p, (size_t)n * sizeof(double));
         double rz = dot(n, r, z);
         int inner = REF_NOT_CONVERGED;
         while (info->iters < maxiter) {
@@ -1264,6 +1270,8 @@ int ref_pcg(ref_hier *H, const double *b, double *x, double rtol, int32_t maxite
             }
             rz = rz_new;
             for (int32_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+            if (dirs && info->restarts == 0 && *ndirs < max_dirs)
+                memcpy(dirs + (size_t)(*ndirs)++ * (size_t)n, p, (size_t)n * sizeof(double));
         }
         spmv(A, x, q);
         for (int32_t i = 0; i < n; ++i) q[i] = b[i] - q[i];
@@ -1276,6 +1284,18 @@ int ref_pcg(ref_hier *H, const double *b, double *x, double rtol, int32_t maxite
     info->status = status;
     free(r); free(z); free(p); free(q); free(rold);
     return status;
+}
+
+int ref_pcg(ref_hier *H, const double *b, double *x, double rtol, int32_t maxiter, int flex,
+            ref_info *info) {
+    return pcg_run(H, b, x, rtol, maxiter, flex, info, NULL, 0, NULL);
+}
+
+/* ref_pcg that also records the search directions (test hook, see pcg_run). */
+int ref_pcg_dirs(ref_hier *H, const double *b, double *x, double rtol, int32_t maxiter, int flex,
+                 ref_info *info, double *dirs, int32_t max_dirs, int32_t *ndirs) {
+    *ndirs = 0;
+    return pcg_run(H, b, x, rtol, maxiter, flex, info, dirs, max_dirs, ndirs);
 }
 
 /* Right-preconditioned BiCGSTAB (van der Vorst 1992).
