@@ -331,12 +331,23 @@ def test_full_size_travel_time_parity(gw, ref):
     # its upwind direction between the two
     _say("full-size 128x128x64 travel-time parity")
     p = gi.heterogeneous_aquifer(128, 128, 64, 4.0, 8, 11)
-    fr = ref.solve_flow(p, ref.AmgParams(), rtol=1e-8)
+    # heads from the benchmark's flow settings (threshold 0.03, one sweep each way)
+    fr = ref.solve_flow(p, ref.AmgParams(eps_strong=0.03, npre=1, npost=1), rtol=1e-8)
     qx, qy, qz = ref.darcy_flux(p, fr.h)
     g = p.grid
     zone = (0, g.ny, 0, g.nz // 2)
-    ap = ref.AmgParams(eps_strong=gw.TT_EPS_STRONG)
+    tp = gw.AmgParams.travel_time()
+    ap = ref.AmgParams(eps_strong=tp.eps_strong, npre=tp.npre, npost=tp.npost)
     tr = ref.solve_travel_time(g, qx, qy, qz, p.phi, ap, rtol=1e-8, zone=zone)
+    # the travel-time hierarchy of those settings: aggregates of every level bit for bit
+    Hg = gw.amg_setup(g.n, dev(tr.A.rowptr), dev(tr.A.col), dev(tr.A.val), gpu_params(gw, ap))
+    infos, _ = Hg.info()
+    assert Hg.nlevels == tr.H.nlevels
+    for l in range(tr.H.nlevels - 1):
+        agg = torch.zeros(infos[l].n, dtype=torch.int32, device="cuda")
+        gw.amg_level_export(Hg, l, agg=agg)
+        assert np.array_equal(host(agg), tr.H.level(l).agg), f"level {l}"
+    del Hg
     tau = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     c = torch.zeros(g.n, dtype=torch.float64, device="cuda")
     st, infos = gw.tt_solve(g, dev(qx), dev(qy), dev(qz), p.phi, zone, gpu_params(gw, ap), gw.SolveParams(rtol=1e-8),
@@ -360,13 +371,24 @@ def test_full_size_travel_time_parity(gw, ref):
     assert np.array_equal(host(tau_d), tau_ex) and np.array_equal(host(c_d), c_ex)
 
 
-def test_full_size_flow_parity(gw, ref):
+FULL_FLOW_PARAMS = [
+    ("library defaults 0.08 2/2", dict()),
+    ("benchmark flow 0.03 1/1", dict(eps_strong=0.03, npre=1, npost=1)),
+]
+
+
+@pytest.mark.parametrize("name,kw", FULL_FLOW_PARAMS, ids=[c[0] for c in FULL_FLOW_PARAMS])
+def test_full_size_flow_parity(gw, ref, name, kw):
     # the 1M-cell lognormal aquifer (variance 4, correlation length 8, four
-    # wells) in the benchmark's configuration: aggregates of every level bit
-    # for bit, heads within 1e-8 of the oracle's same-algorithm solve
-    _say("full-size 128x128x64 flow parity")
+    # wells), at the library defaults and at the flow settings the benchmark
+    # times (AmgParams.flow()): aggregates of every level bit for bit, heads
+    # within 1e-8 of the oracle's same-algorithm solve
+    _say(f"full-size 128x128x64 flow parity, {name}")
+    bench = gw.AmgParams.flow()
+    if kw:
+        assert (kw["eps_strong"], kw["npre"], kw["npost"]) == (bench.eps_strong, bench.npre, bench.npost)
     p = gi.heterogeneous_aquifer(128, 128, 64, 4.0, 8, 11)
-    ap = ref.AmgParams()
+    ap = ref.AmgParams(**kw)
     fr = ref.solve_flow(p, ap, rtol=1e-8)
     K, rowptr, col, val, bd = gpu_assemble(gw, p)
     Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap))
@@ -493,18 +515,21 @@ def test_bicgstab_pair_matches_single(gw, ref, precision, check):
     assert np.array_equal(host(y0).view(np.uint64), singles[0][0].view(np.uint64))
 
 
-def test_c3_mixed_flow_against_fp64_residual(gw, ref):
-    # the 8.4M-cell configuration in the benchmark's mixed form: the true
-    # residual of the GPU heads, recomputed on the CPU with the oracle's own
-    # matrix in FP64, meets rtol; the FP64 hierarchy gives the same heads
-    # within the mixed-path tolerance
-    _say("C3 256x256x128 mixed FCG vs FP64 residual")
+def test_c3_mixed_flow_against_oracle(gw, ref):
+    # the 8.4M-cell configuration as the benchmark times it (strength
+    # threshold 0.05, two pre- and post-sweeps, FP32 hierarchy inside FP64
+    # flexible CG): heads within 1e-6 of the oracle's FP64 flexible-CG solve
+    # at the same settings, the true residual of the GPU heads recomputed
+    # with the oracle's own matrix meets rtol, and the FP64 hierarchy gives
+    # the same heads within the mixed-path tolerance
+    _say("C3 256x256x128 mixed FCG vs the oracle (0.05, 2/2)")
     p = gi.heterogeneous_aquifer(256, 256, 128, 4.0, 8, 21)
     n = p.grid.n
+    kw = dict(eps_strong=0.05, npre=2, npost=2)
     K, rowptr, col, val, bd = gpu_assemble(gw, p)
     heads = []
     for precision in (gw.PRECISION_MIXED, gw.PRECISION_FP64):
-        H = gw.amg_setup(n, rowptr, col, val, gw.AmgParams(precision=precision))
+        H = gw.amg_setup(n, rowptr, col, val, gw.AmgParams(precision=precision, **kw))
         x = torch.zeros(n, dtype=torch.float64, device="cuda")
         info = gw.amg_solve_pcg(H, bd, x, gw.SolveParams(rtol=1e-8))
         _say(f"  precision {precision}: {info.iters} iterations, status {info.status}")
@@ -518,6 +543,13 @@ def test_c3_mixed_flow_against_fp64_residual(gw, ref):
     assert rel <= 1.05e-8
     err = np.linalg.norm(heads[0] - heads[1]) / np.linalg.norm(heads[1])
     assert err <= 1e-6, err
+    Hr = ref.Hierarchy(A, ref.AmgParams(**kw))
+    h_ref, info_ref = ref.pcg(Hr, b, rtol=1e-8, flexible=True)
+    assert info_ref.status == ref.OK
+    for name, h in (("mixed", heads[0]), ("fp64", heads[1])):
+        e = np.linalg.norm(h - h_ref) / np.linalg.norm(h_ref)
+        _say(f"  {name} heads vs oracle (FCG, {info_ref.iters} iterations): {e:.2e}")
+        assert e <= 1e-6, (name, e)
 
 
 def test_setup_reports_zero_pivot_in_coarsest_lu(gw, ref):
@@ -541,3 +573,27 @@ def test_setup_reports_zero_pivot_in_coarsest_lu(gw, ref):
     gw.amg_coarse_export(Hg, lu, piv)
     assert np.array_equal(host(piv), piv_ref)
     assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64))
+
+
+def test_breakdown_when_rhat_v_vanishes(gw, ref):
+    # identity preconditioner on A = [[1, -3], [1, 1]], b = (1, 1): r_hat = r
+    # = p = b and v = A b = (-2, 2), so r_hat.v = 0 exactly at the first
+    # BiCGSTAB step and p.A p = 0 at the first CG step: both sides report
+    # BREAKDOWN with no iteration taken.  (The skew matrix [[0, 1], [-1, 0]]
+    # has the same zero but no positive diagonal: EINVAL on both sides.)
+    _say("breakdown r_hat.v = 0")
+    rp, cl = np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32)
+    val = np.array([1.0, -3.0, 1.0, 1.0])
+    b = np.array([1.0, 1.0])
+    Hr = ref.Hierarchy(ref.Csr(rp, cl, val), ref.AmgParams(smoother=ref.NONE))
+    assert ref.bicgstab(Hr, b)[1].status == ref.BREAKDOWN
+    assert ref.pcg(Hr, b)[1].status == ref.BREAKDOWN
+    Hg = gw.amg_setup(2, dev(rp), dev(cl), dev(val), gw.AmgParams(smoother=gw.SMOOTHER_NONE))
+    for solve in (gw.amg_solve_bicgstab, gw.amg_solve_pcg):
+        x = torch.full((2,), 5.0, dtype=torch.float64, device="cuda")
+        info = solve(Hg, dev(b), x, gw.SolveParams(rtol=1e-8))
+        assert info.status == gw.BREAKDOWN and info.iters == 0, (solve.__name__, info)
+    with pytest.raises(gw.GwError) as e:
+        gw.amg_setup(2, dev(rp), dev(cl), dev(np.array([0.0, 1.0, -1.0, 0.0])),
+                     gw.AmgParams(smoother=gw.SMOOTHER_NONE))
+    assert e.value.status == gw.EINVAL

@@ -3,7 +3,8 @@
 CPU tests exercise the host-side scheduler (argument checks, HBM-budget
 admission, a request that fails on a host without GPU comes back as a
 finished ticket with EDEVICE instead of hanging).  GPU tests check that a
-request gives the same result alone and inside a concurrent mix.
+request gives the same result alone and inside a concurrent mix, and that
+the served result matches the oracle.
 """
 import time
 
@@ -75,17 +76,27 @@ def _serve(problems, slots, budget=64 << 30):
     return out
 
 
-@pytest.mark.gpu
-def test_alone_equals_in_mix():
+def _target():
+    return gi.heterogeneous_aquifer(40, 36, 24, 2.0, 6, 101)
+
+
+@pytest.fixture(scope="module")
+def mix_run():
+    """The target request inside a concurrent 4-slot mix of six requests."""
     if gw is None or not _has_gpu():
         pytest.skip("no GPU")
-    print("[case] serve alone vs mix", flush=True)
-    target = gi.heterogeneous_aquifer(40, 36, 24, 2.0, 6, 101)
     others = [gi.heterogeneous_aquifer(s, s, s, s2, lam, seed) for s, s2, lam, seed in
               [(48, 4.0, 8, 7), (32, 1.0, 4, 8), (56, 2.0, 12, 9), (36, 4.0, 16, 10), (44, 1.0, 5, 11)]]
+    return _serve(others[:3] + [_target()] + others[3:], slots=4)
+
+
+@pytest.mark.gpu
+def test_alone_equals_in_mix(mix_run):
+    print("[case] serve alone vs mix", flush=True)
+    target = _target()
     (alone_res, alone_out), = _serve([target], slots=1)
     assert alone_res.status == gw.OK, (alone_res.status, alone_res.error)
-    mix = _serve(others[:3] + [target] + others[3:], slots=4)
+    mix = mix_run
     mix_res, mix_out = mix[3]
     assert all(r.status == gw.OK for r, _ in mix), [r.status for r, _ in mix]
     for k in ("h", "tau", "c"):
@@ -97,6 +108,32 @@ def test_alone_equals_in_mix():
     starts = sorted(r.t_start for r, _ in mix)
     dones = sorted(r.t_done for r, _ in mix)
     assert starts[1] < dones[0]
+
+
+@pytest.mark.gpu
+def test_served_result_matches_oracle(mix_run, ref):
+    # the request served inside the mix against the FP64 oracle end to end:
+    # flow by flexible CG on the same hierarchy settings, Darcy fluxes from
+    # the oracle's own heads, then the travel-time pair by BiCGSTAB with the
+    # travel-time settings; h, tau and c within the mixed-path tolerance
+    print("[case] served request vs oracle", flush=True)
+    p = _target()
+    g = p.grid
+    res, out = mix_run[3]
+    assert res.status == gw.OK
+    ap = gw.AmgParams()
+    tp = gw.AmgParams.travel_time()
+    fr = ref.solve_flow(p, ref.AmgParams(eps_strong=ap.eps_strong, npre=ap.npre, npost=ap.npost),
+                        rtol=1e-8, flexible=True)
+    qx, qy, qz = ref.darcy_flux(p, fr.h)
+    tr = ref.solve_travel_time(g, qx, qy, qz, p.phi,
+                               ref.AmgParams(eps_strong=tp.eps_strong, npre=tp.npre, npost=tp.npost),
+                               rtol=1e-8, zone=(0, g.ny, 0, max(1, g.nz // 2)))
+    assert fr.info.status == ref.OK and all(i.status == ref.OK for i in tr.info)
+    for k, want in (("h", fr.h), ("tau", tr.tau), ("c", tr.c)):
+        rel = np.linalg.norm(out[k] - want) / np.linalg.norm(want)
+        print(f"  {k}: rel err vs oracle {rel:.2e}", flush=True)
+        assert rel <= 1e-6, (k, rel)
 
 
 @pytest.mark.gpu
