@@ -73,18 +73,18 @@ __device__ __forceinline__ T block_max(T v, T *sm) {
 }
 
 // First stage of a grid-wide sum: every block stores its NV block sums in
-// partials[b*NV + k].  A one-block finalize kernel adds them in block order
+// partials[b*NV + k], b = `block` (the block's index in its grid).  A one-block finalize kernel adds them in block order
 // (fixed), so totals do not depend on scheduling.  Two kernels instead of a
 // "last block" ticket: on a multi-XCD part a device-scope fence in every
 // block would write back that XCD's L2 each time, while the kernel boundary
 // makes the partials visible once.
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials, int64_t block) {
     __shared__ double sm[NV][16];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = block_sum(v[k], sm[k]);
-        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * NV + k] = s;
+        if (threadIdx.x == 0) partials[(size_t)block * NV + k] = s;
     }
 }
 

@@ -373,6 +373,18 @@ int lane_group_for(double mean_row_len);
 int solve_group_for(double mean_row_len);
 int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp,
                amg_solve_info *info, hipStream_t s);
+// Krylov workspace of a hierarchy: nvec n-vectors, block partials, scalars
+// (grown on demand); V-cycle level vectors for nr interleaved right-hand
+// sides.
+void ensure_krylov_workspace(amg_hierarchy *H, int nvec);
+void ensure_level_vectors(amg_hierarchy *H, int nr);
+// Blocks of a Krylov reduction (each leaves its partial sums).
+constexpr int kKrylovMaxBlocks = 2048;
+// krylov_pcg in a workspace the caller provides: `vec` six n-vectors, `part`
+// kKrylovMaxBlocks x 4 doubles, `ks` one scalar record (all device memory);
+// nothing is allocated, kernels are launched one by one.
+int krylov_pcg_in(amg_hierarchy *H, double *vec, double *part, KScalars *ks, const double *b, double *x,
+                  const amg_solve_params &sp, amg_solve_info *info, hipStream_t s);
 // PCG on A + diag(shift), preconditioned by the hierarchy of A.
 int krylov_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b, double *x, const amg_solve_params &sp,
                        amg_solve_info *info, hipStream_t s);
