@@ -200,6 +200,27 @@ int amg_spmv(amg_hierarchy *H, const double *x, double *y, void *stream);
 int amg_solve_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
                   amg_solve_info *info, void *stream);
 
+/* amg_solve_pcg for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, the same kernels and results bit for bit, but the Krylov
+ * workspace (six n-vectors, block partials, the scalar record) is a
+ * statically sized array of device memory (6 x 8 x GW_NOALLOC_MAX_ROWS
+ * bytes + 64 KiB, ~48 MiB) that the HIP runtime places on a device with
+ * the code object holding it, at this entry point's first call there, and
+ * keeps until the process ends; the scalars travel through a host variable
+ * instead of a pinned stage.  The call allocates nothing: no hipMalloc,
+ * hipFree, pinned or pool allocation, no graph.  H
+ * must come from amg_setup (which allocated the hierarchy); b, x [device] n,
+ * caller-owned.  EINVAL when n > GW_NOALLOC_MAX_ROWS, when sp->graph > 0
+ * (graph objects are allocations) or while kernel timing is on
+ * (gw_prof_enable creates events).  Every call on one device shares that
+ * device's array, and each call initialises everything it reads there:
+ * calls that overlap on one device (other host threads, other streams) race
+ * on it and must be serialised by the caller. */
+#define GW_NOALLOC_MAX_ROWS 1048576
+int amg_solve_pcg_noalloc(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
+                          amg_solve_info *info, void *stream);
+
 /* AMG right-preconditioned BiCGSTAB (nonsymmetric), x0 = 0. */
 int amg_solve_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
                        amg_solve_info *info, void *stream);

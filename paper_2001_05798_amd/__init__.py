@@ -21,6 +21,7 @@ SMOOTHER_JACOBI, SMOOTHER_SPAI0, SMOOTHER_NONE, SMOOTHER_ILU0 = 0, 1, 2, 3
 PRECISION_FP64, PRECISION_MIXED = 0, 1
 COARSEN_SA, COARSEN_RS = 0, 1
 TT_EPS_STRONG = 0.25
+NOALLOC_MAX_ROWS = 1048576  # GW_NOALLOC_MAX_ROWS
 
 STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", PENDING: "PENDING",
                 EINVAL: "EINVAL", ENOMEM: "ENOMEM", SINGULAR: "SINGULAR", EDEVICE: "EDEVICE",
@@ -143,6 +144,7 @@ def _load():
         "tt_solve_direct": (C.c_int, [C.POINTER(GwGrid), vp, vp, vp, f64, C.POINTER(GwZone), vp, vp,
                                       C.POINTER(i32), vp]),
         "amg_solve_pcg_shifted": (C.c_int, [vp, vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "amg_solve_pcg_noalloc": (C.c_int, [vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
         "flow_transient": (C.c_int, [C.POINTER(GwGrid), vp, C.POINTER(GwBc), vp, i32, vp, vp, C.POINTER(f64), i32,
                                      f64, C.POINTER(AmgParamsC), C.POINTER(SolveParamsC), vp, vp,
                                      C.POINTER(StepInfoC), vp]),
@@ -464,6 +466,15 @@ def amg_solve_pcg(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stream=No
     info = SolveInfoC()
     _check(_lib.amg_solve_pcg(H.handle, _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info), _stream(stream)),
            allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return SolveInfo.of(info)
+
+
+def amg_solve_pcg_noalloc(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), stream=None) -> SolveInfo:
+    """amg_solve_pcg with the library's static workspace: allocates nothing
+    (n <= NOALLOC_MAX_ROWS; calls on one device must not overlap)."""
+    info = SolveInfoC()
+    _check(_lib.amg_solve_pcg_noalloc(H.handle, _ptr(b), _ptr(x), C.byref(sp.c()), C.byref(info),
+                                      _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
     return SolveInfo.of(info)
 
 

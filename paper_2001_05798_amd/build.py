@@ -26,6 +26,7 @@ SOURCES = [
     ("setup.hip", True),
     ("sell.hip", False),
     ("solve.hip", False),
+    ("noalloc.hip", False),
     ("sweep.hip", True),
     ("transient.hip", True),
     ("ilu.hip", True),

@@ -304,7 +304,7 @@ int amg_spmv(amg_hierarchy *H, const double *x, double *y, void *stream) {
     });
 }
 
-static void check_solve(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp) {
+void check_solve(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp) {
     GW_REQUIRE(H && b && x && sp, "solve: null pointer");
     GW_REQUIRE(sp->rtol >= 0 && std::isfinite(sp->rtol), "solve: rtol must be >= 0");
     GW_REQUIRE(sp->maxiter >= 0, "solve: maxiter must be >= 0");
@@ -317,6 +317,19 @@ int amg_solve_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_
         check_solve(H, b, x, sp);
         hipStream_t s = as_stream(stream);
         int st = krylov_pcg(H, b, x, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
+int amg_solve_pcg_noalloc(amg_hierarchy *H, const double *b, double *x, const amg_solve_params *sp,
+                          amg_solve_info *info, void *stream) {
+    return guarded([&] {
+        check_solve(H, b, x, sp);
+        GW_REQUIRE(sp->graph <= 0, "amg_solve_pcg_noalloc: graph replay allocates graph objects; pass graph <= 0");
+        GW_REQUIRE(!prof_on(), "amg_solve_pcg_noalloc: kernel timing is on (it creates events)");
+        hipStream_t s = as_stream(stream);
+        int st = pcg_noalloc(H, b, x, *sp, info, s);
         finish(s);
         return st;
     });

@@ -385,6 +385,9 @@ constexpr int kKrylovMaxBlocks = 2048;
 // nothing is allocated, kernels are launched one by one.
 int krylov_pcg_in(amg_hierarchy *H, double *vec, double *part, KScalars *ks, const double *b, double *x,
                   const amg_solve_params &sp, amg_solve_info *info, hipStream_t s);
+// amg_solve_pcg_noalloc's solve in the library's static workspace array.
+int pcg_noalloc(amg_hierarchy *H, const double *b, double *x, const amg_solve_params &sp, amg_solve_info *info,
+                hipStream_t s);
 // PCG on A + diag(shift), preconditioned by the hierarchy of A.
 int krylov_pcg_shifted(amg_hierarchy *H, const double *shift, const double *b, double *x, const amg_solve_params &sp,
                        amg_solve_info *info, hipStream_t s);

@@ -21,7 +21,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ["fv_assemble", "amg_setup", "amg_solve_pcg", "amg_solve_bicgstab", "amg_solve_bicgstab_pair", "tt_solve",
-              "tt_sweep", "tt_solve_direct", "tt_delineate", "amg_solve_pcg_shifted", "flow_transient", "amg_ilu_export",
+              "tt_sweep", "tt_solve_direct", "tt_delineate", "amg_solve_pcg_shifted", "flow_transient", "amg_ilu_export", "amg_solve_pcg_noalloc",
               "queue_submit", "queue_poll", "darcy_flux", "amg_free", "gw_last_error"]:
         assert n in names
 
@@ -55,6 +55,7 @@ def test_host_side_validation_without_device():
     assert lib.amg_solve_bicgstab_pair(None, None, None, None, None, None, None, None) == -1
     assert lib.tt_sweep(None, 1, None, None, None, None) == -1
     assert lib.amg_solve_pcg_shifted(None, None, None, None, None, None, None) == -1
+    assert lib.amg_solve_pcg_noalloc(None, None, None, None, None, None) == -1
     assert lib.flow_transient(ctypes.byref(Grid(0, 4, 4, 1, 1, 1)), None, None, None, 0, None, None, None, 1,
                               ctypes.c_double(0.01), None, None, None, None, None, None) == -1
     assert lib.tt_delineate(ctypes.byref(Grid(4, 4, 4, 1, 1, 1)), None, None, None, ctypes.c_double(0.25),
