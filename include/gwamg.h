@@ -238,6 +238,28 @@ int amg_solve_bicgstab(amg_hierarchy *H, const double *b, double *x, const amg_s
 int amg_solve_bicgstab_pair(amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1,
                             const amg_solve_params *sp, amg_solve_info info[2], void *stream);
 
+/* Shared launches for many solves (the Discussion's setups kept for many
+ * solves; the serving loop's batches): nsys independent systems, each with
+ * its own hierarchy H[j] (all distinct, from amg_setup, with the same
+ * precision and the same pre- and post-sweep counts, both >= 1, and a
+ * diagonal smoother), solved together so that every kernel step is one
+ * launch for all of them per operator type instead of one per system.  Each
+ * launch runs every system's kernel on the grid it would have alone, so each
+ * system gets exactly the iterates, iteration count, stopping decision and
+ * restarts of amg_solve_pcg / amg_solve_bicgstab_pair on its own (bit for
+ * bit); a system that has converged skips the remaining launches.  H, b, x,
+ * b0, b1, x0, x1 [host] arrays of nsys pointers; the vectors they point to
+ * [device] n_j each.  info [host] nsys entries (the pair: 2 nsys, systems
+ * 2j and 2j+1 of hierarchy j); solve_ms is the batch's wall time.  graph = 1
+ * replays each block of check_every iterations of the whole batch as one
+ * captured HIP graph.  nsys in [1, 256].  Returns the worst status
+ * (BREAKDOWN, then NOT_CONVERGED); EINVAL for mismatched hierarchies. */
+int amg_solve_pcg_batch(amg_hierarchy *const *H, const double *const *b, double *const *x, int32_t nsys,
+                        const amg_solve_params *sp, amg_solve_info *info, void *stream);
+int amg_solve_bicgstab_pair_batch(amg_hierarchy *const *H, const double *const *b0, const double *const *b1,
+                                  double *const *x0, double *const *x1, int32_t nsys, const amg_solve_params *sp,
+                                  amg_solve_info *info, void *stream);
+
 /* Per-level statistics; `out` [host] holds max_levels entries. */
 int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_levels,
                        int32_t *nlevels, size_t *bytes);
@@ -368,7 +390,11 @@ typedef struct {
     char name[32];
     int64_t launches;
     double ms;            /* summed event time                            */
-    double bytes;         /* summed algorithmic HBM bytes                 */
+    double bytes;         /* summed algorithmic HBM bytes, operators in the
+                             format the kernel reads (sliced copy or CSR)  */
+    double bytes_csr;     /* the same with every operator pass counted as a
+                             CSR pass: nnz (value + 4-byte column)
+                             + 4 (n + 1)                                   */
 } gw_kernel_stat;
 
 /* on = 1 starts recording (and clears the table), 0 stops. */
@@ -406,6 +432,11 @@ typedef struct {
     size_t bytes_reserved;             /* admission footprint             */
     char error[160];                   /* message when status < 0         */
     int32_t setup_reused;              /* 1: flow hierarchy from the cache */
+    size_t bytes_used;                 /* device bytes the request held at its
+                                          larger phase (flow: K, CSR, vectors,
+                                          hierarchy; travel time: K, h, fluxes,
+                                          CSR, vectors, hierarchy); setup
+                                          temporaries not included         */
 } gw_result;
 
 /* hbm_budget_bytes: device memory the queue may reserve for requests in
@@ -433,6 +464,19 @@ int queue_drain(gw_queue *q);
  * cached bytes count against the HBM budget and the least recently used
  * idle entry is freed when a waiting request does not fit. */
 int queue_set_setup_cache(gw_queue *q, int32_t max_entries);
+/* Shared launches for the solves of the running requests (the default,
+ * max_batch = 16, window_us = 0): a request's flow solve and its
+ * travel-time pair go to the queue's solver thread, which runs every waiting
+ * solve of the same kind and parameters (up to max_batch) as one batch of
+ * amg_solve_pcg_batch / amg_solve_bicgstab_pair_batch; each result is bit
+ * for bit the one of a solve of its own.  With window_us > 0 a batch waits
+ * up to that long for the solves of other running requests to join it (it
+ * starts as soon as every running request has one waiting).  max_batch = 1:
+ * each request solves on its own slot stream.  EINVAL for max_batch outside
+ * [1, 256] or window_us outside [0, 1e7]. */
+int queue_set_batch(gw_queue *q, int32_t max_batch, double window_us);
+/* Batches the solver thread ran and the solves they held, since creation. */
+int queue_stats(const gw_queue *q, uint64_t *batches, uint64_t *batched_solves);
 void queue_destroy(gw_queue *q);
 
 #ifdef __cplusplus

@@ -88,7 +88,7 @@ class LevelInfoC(C.Structure):
 
 class KernelStatC(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double),
-                ("bytes", C.c_double)]
+                ("bytes", C.c_double), ("bytes_csr", C.c_double)]
 
 
 class RequestC(C.Structure):
@@ -102,7 +102,8 @@ class RequestC(C.Structure):
 class ResultC(C.Structure):
     _fields_ = [("status", C.c_int32), ("flow", SolveInfoC), ("tt", SolveInfoC * 2),
                 ("t_arrival", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
-                ("bytes_reserved", C.c_size_t), ("error", C.c_char * 160), ("setup_reused", C.c_int32)]
+                ("bytes_reserved", C.c_size_t), ("error", C.c_char * 160), ("setup_reused", C.c_int32),
+                ("bytes_used", C.c_size_t)]
 
 
 # ------------------------------------------------------------------ load --
@@ -145,6 +146,9 @@ def _load():
                                       C.POINTER(i32), vp]),
         "amg_solve_pcg_shifted": (C.c_int, [vp, vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
         "amg_solve_pcg_noalloc": (C.c_int, [vp, vp, vp, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "amg_solve_pcg_batch": (C.c_int, [vp, vp, vp, C.c_int32, C.POINTER(SolveParamsC), C.POINTER(SolveInfoC), vp]),
+        "amg_solve_bicgstab_pair_batch": (C.c_int, [vp, vp, vp, vp, vp, C.c_int32, C.POINTER(SolveParamsC),
+                                                    C.POINTER(SolveInfoC), vp]),
         "flow_transient": (C.c_int, [C.POINTER(GwGrid), vp, C.POINTER(GwBc), vp, i32, vp, vp, C.POINTER(f64), i32,
                                      f64, C.POINTER(AmgParamsC), C.POINTER(SolveParamsC), vp, vp,
                                      C.POINTER(StepInfoC), vp]),
@@ -159,6 +163,8 @@ def _load():
         "queue_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ResultC)]),
         "queue_drain": (C.c_int, [vp]),
         "queue_set_setup_cache": (C.c_int, [vp, i32]),
+        "queue_set_batch": (C.c_int, [vp, i32, f64]),
+        "queue_stats": (C.c_int, [vp, vp, vp]),
         "queue_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -478,6 +484,43 @@ def amg_solve_pcg_noalloc(H: Hierarchy, b, x, sp: SolveParams = SolveParams(), s
     return SolveInfo.of(info)
 
 
+def _ptr_array(items, conv):
+    arr = (C.c_void_p * len(items))()
+    for k, it in enumerate(items):
+        arr[k] = conv(it)
+    return arr
+
+
+def amg_solve_pcg_batch(Hs: Sequence[Hierarchy], bs, xs, sp: SolveParams = SolveParams(),
+                        stream=None) -> List[SolveInfo]:
+    """PCG on several hierarchies at once, one launch per kernel step for all
+    (each system's iterates equal amg_solve_pcg's)."""
+    n = len(Hs)
+    if not (len(bs) == len(xs) == n):
+        raise ValueError("one b and one x per hierarchy")
+    info = (SolveInfoC * n)()
+    _check(_lib.amg_solve_pcg_batch(_ptr_array(Hs, lambda h: h.handle), _ptr_array(bs, _ptr),
+                                    _ptr_array(xs, _ptr), n, C.byref(sp.c()), info, _stream(stream)),
+           allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return [SolveInfo.of(i) for i in info]
+
+
+def amg_solve_bicgstab_pair_batch(Hs: Sequence[Hierarchy], b0s, b1s, x0s, x1s, sp: SolveParams = SolveParams(),
+                                  stream=None) -> Tuple[int, List[Tuple[SolveInfo, SolveInfo]]]:
+    """The BiCGSTAB pair on several hierarchies at once (each pair's iterates
+    equal amg_solve_bicgstab_pair's).  Returns the worst status and one
+    (info0, info1) per hierarchy."""
+    n = len(Hs)
+    if not (len(b0s) == len(b1s) == len(x0s) == len(x1s) == n):
+        raise ValueError("two right-hand sides and two solutions per hierarchy")
+    info = (SolveInfoC * (2 * n))()
+    st = _lib.amg_solve_bicgstab_pair_batch(_ptr_array(Hs, lambda h: h.handle), _ptr_array(b0s, _ptr),
+                                            _ptr_array(b1s, _ptr), _ptr_array(x0s, _ptr), _ptr_array(x1s, _ptr), n,
+                                            C.byref(sp.c()), info, _stream(stream))
+    _check(st, allow=(OK, NOT_CONVERGED, BREAKDOWN))
+    return st, [(SolveInfo.of(info[2 * k]), SolveInfo.of(info[2 * k + 1])) for k in range(n)]
+
+
 def amg_solve_pcg_shifted(H: Hierarchy, shift, b, x, sp: SolveParams = SolveParams(), stream=None) -> SolveInfo:
     """PCG on (A + diag(shift)) x = b with the hierarchy of A as preconditioner."""
     info = SolveInfoC()
@@ -552,7 +595,8 @@ def prof_read() -> dict:
     arr = (KernelStatC * 64)()
     n = C.c_int32(0)
     _check(_lib.gw_prof_read(arr, 64, C.byref(n)))
-    return {a.name.decode(): {"launches": int(a.launches), "ms": float(a.ms), "bytes": float(a.bytes)}
+    return {a.name.decode(): {"launches": int(a.launches), "ms": float(a.ms), "bytes": float(a.bytes),
+                              "bytes_csr": float(a.bytes_csr)}
             for a in arr[:n.value]}
 
 
@@ -572,6 +616,7 @@ class Result:
     bytes_reserved: int
     error: str = ""
     setup_reused: int = 0   # 1: the flow hierarchy came from the setup cache
+    bytes_used: int = 0     # device bytes held at the request's larger phase
 
     @property
     def latency(self) -> float:
@@ -635,11 +680,23 @@ class Queue:
         K, wl, outs = self._keep.pop(ticket)
         res = Result(r.status, SolveInfo.of(r.flow), [SolveInfo.of(r.tt[0]), SolveInfo.of(r.tt[1])],
                      r.t_arrival, r.t_start, r.t_done, int(r.bytes_reserved), r.error.decode(errors="replace"),
-                     int(r.setup_reused))
+                     int(r.setup_reused), int(r.bytes_used))
         return res, outs
 
     def drain(self) -> None:
         _check(_lib.queue_drain(self._q))
+
+    def set_batch(self, max_batch: int, window_us: float = 0.0) -> None:
+        """Solves of the running requests share launches in batches of up to
+        max_batch (1: each request solves on its own stream); a batch waits
+        up to window_us for other running requests' solves to join."""
+        _check(_lib.queue_set_batch(self._q, int(max_batch), float(window_us)))
+
+    def stats(self) -> Tuple[int, int]:
+        """(batches run by the solver thread, solves they held)."""
+        a, b = C.c_uint64(0), C.c_uint64(0)
+        _check(_lib.queue_stats(self._q, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
 
     def set_setup_cache(self, max_entries: int) -> None:
         """Keep up to max_entries flow hierarchies for later requests with the

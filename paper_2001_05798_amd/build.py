@@ -27,6 +27,7 @@ SOURCES = [
     ("sell.hip", False),
     ("solve.hip", False),
     ("noalloc.hip", False),
+    ("batch.hip", False),
     ("sweep.hip", True),
     ("transient.hip", True),
     ("ilu.hip", True),

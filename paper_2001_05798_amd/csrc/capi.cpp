@@ -359,6 +359,37 @@ int amg_solve_bicgstab_pair(amg_hierarchy *H, const double *b0, const double *b1
     });
 }
 
+int amg_solve_pcg_batch(amg_hierarchy *const *H, const double *const *b, double *const *x, int32_t nsys,
+                        const amg_solve_params *sp, amg_solve_info *info, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H && b && x && sp, "amg_solve_pcg_batch: null pointer");
+        GW_REQUIRE(nsys >= 1 && nsys <= 256, "amg_solve_pcg_batch: nsys must be in [1, 256]");
+        for (int32_t j = 0; j < nsys; ++j) check_solve(H[j], b[j], x[j], sp);
+        hipStream_t s = as_stream(stream);
+        int st = krylov_pcg_batch(H, b, x, nsys, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
+int amg_solve_bicgstab_pair_batch(amg_hierarchy *const *H, const double *const *b0, const double *const *b1,
+                                  double *const *x0, double *const *x1, int32_t nsys, const amg_solve_params *sp,
+                                  amg_solve_info *info, void *stream) {
+    return guarded([&] {
+        GW_REQUIRE(H && b0 && b1 && x0 && x1 && sp, "amg_solve_bicgstab_pair_batch: null pointer");
+        GW_REQUIRE(nsys >= 1 && nsys <= 256, "amg_solve_bicgstab_pair_batch: nsys must be in [1, 256]");
+        for (int32_t j = 0; j < nsys; ++j) {
+            check_solve(H[j], b0[j], x0[j], sp);
+            GW_REQUIRE(b1[j] && x1[j], "amg_solve_bicgstab_pair_batch: null pointer");
+            GW_REQUIRE(x0[j] != x1[j], "amg_solve_bicgstab_pair_batch: x0 and x1 must be different buffers");
+        }
+        hipStream_t s = as_stream(stream);
+        int st = krylov_bicgstab2_batch(H, b0, b1, x0, x1, nsys, *sp, info, s);
+        finish(s);
+        return st;
+    });
+}
+
 int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_levels, int32_t *nlevels,
                        size_t *bytes) {
     return guarded([&] {

@@ -101,6 +101,11 @@ void *host_stage();
 // A second stream of the calling host thread on the current device, for work
 // that overlaps the caller's stream (ordered against it by events).
 hipStream_t side_stream();
+// For a host thread that ends (a serving worker): synchronize and destroy
+// its side streams, free its pinned stage and the pool blocks cached on its
+// free lists.
+void release_thread_resources();
+void pool_release_thread();
 
 // Pinned host buffer.
 struct Pinned {
@@ -134,13 +139,17 @@ bool prof_on();
 // scope holds exactly one launch, made through GW_LAUNCH_TIMED, and the
 // events are taken by that dispatch itself (kernel start and end), without
 // the barrier packets of two hipEventRecord calls (about 3 us per launch).
+// `bytes` counts the launch's operators in the format it reads (sliced copy
+// or CSR); `cbytes` the same launch with every operator pass counted as a
+// CSR pass (nnz (value + 4-byte column) + 4 (n + 1)), the accounting of the
+// plain formula; negative: the same as `bytes`.
 struct ProfScope {
     int id;
-    double bytes;
+    double bytes, cbytes;
     hipStream_t s;
     bool ext;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    ProfScope(int id_, double bytes_, hipStream_t s_, bool ext_ = false);
+    ProfScope(int id_, double bytes_, hipStream_t s_, bool ext_ = false, double cbytes_ = -1.0);
     ~ProfScope();
 };
 
@@ -378,6 +387,13 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
 // sides.
 void ensure_krylov_workspace(amg_hierarchy *H, int nvec);
 void ensure_level_vectors(amg_hierarchy *H, int nr);
+// batch.hip: several independent systems in shared launches, each with the
+// iterates of its own solve (info: nsys entries; the pair: 2 nsys).
+int krylov_pcg_batch(amg_hierarchy *const *H, const double *const *b, double *const *x, int32_t nsys,
+                     const amg_solve_params &sp, amg_solve_info *info, hipStream_t s);
+int krylov_bicgstab2_batch(amg_hierarchy *const *H, const double *const *b0, const double *const *b1,
+                           double *const *x0, double *const *x1, int32_t nsys, const amg_solve_params &sp,
+                           amg_solve_info *info, hipStream_t s);
 // Blocks of a Krylov reduction (each leaves its partial sums).
 constexpr int kKrylovMaxBlocks = 2048;
 // krylov_pcg in a workspace the caller provides: `vec` six n-vectors, `part`

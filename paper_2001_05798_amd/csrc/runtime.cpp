@@ -132,11 +132,45 @@ void pool_trim() {
     (void)hipSetDevice(cur);
 }
 
+void pool_release_thread() {
+    // blocks this thread freed and nobody took since: no stream of this
+    // thread uses them any more once the thread's work is synchronized
+    Pool &P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    const int me = thread_tag();
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : P.free_lists) {
+        if (kv.first.thread != me || kv.second.empty()) continue;
+        (void)hipSetDevice(kv.first.device);
+        for (void *p : kv.second) (void)hipFree(p);
+        P.cached -= kv.first.cls * kv.second.size();
+        kv.second.clear();
+    }
+    (void)hipSetDevice(cur);
+}
+
 // ------------------------------------------------------------------ pinned --
-void *host_stage() {
-    // kept for the life of the process (a thread's block is never returned,
-    // which avoids freeing pinned memory during runtime teardown)
+namespace {
+
+void *&thread_stage() {
     static thread_local void *stage = nullptr;
+    return stage;
+}
+
+std::map<int, hipStream_t> &thread_side_streams() {
+    static thread_local std::map<int, hipStream_t> streams;
+    return streams;
+}
+
+}  // namespace
+
+void *host_stage() {
+    // one per host thread, kept until the thread calls
+    // release_thread_resources (threads that never do keep it for the life
+    // of the process, which avoids freeing pinned memory during runtime
+    // teardown)
+    void *&stage = thread_stage();
     if (!stage) {
         GW_HIP(hipHostMalloc(&stage, kHostStageBytes, hipHostMallocDefault));
         std::memset(stage, 0, kHostStageBytes);
@@ -145,10 +179,10 @@ void *host_stage() {
 }
 
 hipStream_t side_stream() {
-    // one per (host thread, device), created on first use and kept for the
-    // life of the process; non-blocking, so that it is ordered against the
-    // caller's stream by events only, and at the default priority
-    static thread_local std::map<int, hipStream_t> streams;
+    // one per (host thread, device), created on first use; non-blocking, so
+    // that it is ordered against the caller's stream by events only, and at
+    // the default priority
+    auto &streams = thread_side_streams();
     int dev = 0;
     GW_HIP(hipGetDevice(&dev));
     auto it = streams.find(dev);
@@ -157,6 +191,25 @@ hipStream_t side_stream() {
     GW_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     streams[dev] = st;
     return st;
+}
+
+void release_thread_resources() {
+    auto &streams = thread_side_streams();
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : streams) {
+        (void)hipSetDevice(kv.first);
+        (void)hipStreamSynchronize(kv.second);
+        (void)hipStreamDestroy(kv.second);
+    }
+    streams.clear();
+    (void)hipSetDevice(cur);
+    void *&stage = thread_stage();
+    if (stage) {
+        (void)hipHostFree(stage);
+        stage = nullptr;
+    }
+    pool_release_thread();
 }
 
 Pinned::Pinned(size_t bytes) : n(bytes) {
@@ -176,7 +229,7 @@ struct ProfState {
     int only = -1;  // record one kernel class only (-1: all)
     struct Pending {
         int id;
-        double bytes;
+        double bytes, cbytes;
         hipEvent_t e0, e1;
     };
     std::vector<Pending> pending;
@@ -184,6 +237,7 @@ struct ProfState {
     int64_t launches[K_COUNT] = {};
     double ms[K_COUNT] = {};
     double bytes[K_COUNT] = {};
+    double cbytes[K_COUNT] = {};
 };
 
 ProfState &prof() {
@@ -217,7 +271,8 @@ const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kNames[id] 
 
 bool prof_on() { return prof().on; }
 
-ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_, bool ext_) : id(id_), bytes(bytes_), s(s_), ext(ext_) {
+ProfScope::ProfScope(int id_, double bytes_, hipStream_t s_, bool ext_, double cbytes_)
+    : id(id_), bytes(bytes_), cbytes(cbytes_ < 0.0 ? bytes_ : cbytes_), s(s_), ext(ext_) {
     ProfState &P = prof();
     if (!P.on || (P.only >= 0 && P.only != id)) return;
     // launches being captured into a graph are not timed one by one
@@ -234,7 +289,7 @@ ProfScope::~ProfScope() {
     ProfState &P = prof();
     std::lock_guard<std::mutex> g(P.mu);
     if (!ext && hipEventRecord(e1, s) != hipSuccess) return;
-    P.pending.push_back({id, bytes, e0, e1});
+    P.pending.push_back({id, bytes, cbytes, e0, e1});
 }
 
 void prof_flush() {
@@ -246,6 +301,7 @@ void prof_flush() {
             P.launches[x.id] += 1;
             P.ms[x.id] += ms;
             P.bytes[x.id] += x.bytes;
+            P.cbytes[x.id] += x.cbytes;
         }
         P.spare.push_back(x.e0);
         P.spare.push_back(x.e1);
@@ -277,6 +333,7 @@ int gw_prof_enable(int32_t on) {
             std::fill(P.launches, P.launches + gw::K_COUNT, 0);
             std::fill(P.ms, P.ms + gw::K_COUNT, 0.0);
             std::fill(P.bytes, P.bytes + gw::K_COUNT, 0.0);
+            std::fill(P.cbytes, P.cbytes + gw::K_COUNT, 0.0);
         }
         P.on = on != 0;
         return GW_OK;
@@ -313,6 +370,7 @@ int gw_prof_read(gw_kernel_stat *out, int32_t max, int32_t *n) {
                 out[k].launches = P.launches[i];
                 out[k].ms = P.ms[i];
                 out[k].bytes = P.bytes[i];
+                out[k].bytes_csr = P.cbytes[i];
             }
             ++k;
         }

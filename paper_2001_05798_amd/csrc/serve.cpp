@@ -9,7 +9,17 @@
 // overlap on the device; a request that arrives while others run joins as
 // soon as a slot and memory free up.  Hierarchies stay resident for the
 // duration of a request: the travel-time hierarchy serves both right-hand
-// sides.  With the setup cache on (queue_set_setup_cache), the flow
+// sides.
+//
+// Solves share launches: a slot that reaches a solve (after its setup on
+// its own stream) hands it to the queue's solver thread, which takes every
+// solve of the same kind waiting at that moment (flow CG, or travel-time
+// pairs, with the same precision, sweeps and stopping parameters) and runs
+// them as one batch, one launch per kernel step for all of them
+// (amg_solve_pcg_batch / amg_solve_bicgstab_pair_batch); solves arriving
+// while a batch runs form the next one.  Each system's iterates are those of
+// its solve alone, bit for bit, so a result does not depend on the mix it
+// was served in.  With the setup cache on (queue_set_setup_cache), the flow
 // hierarchy outlives its request: a later request with the same conductance
 // field, grid, boundary heads and AMG parameters takes it instead of a new
 // setup, since wells change only the right-hand side (the Discussion's
@@ -96,13 +106,57 @@ SetupKey setup_key(const gw_request &r) {
     return k;
 }
 
+// The inputs that determine the flow matrix, kept with a cached hierarchy:
+// a hash match is confirmed by comparing them in full.
+struct SetupInputs {
+    gw_grid grid;
+    gw_bc bc;
+    amg_params params;
+    std::vector<double> K;
+    bool same(const gw_request &r) const {
+        const int64_t n = (int64_t)r.grid.nx * r.grid.ny * r.grid.nz;
+        return std::memcmp(&grid, &r.grid, sizeof(gw_grid)) == 0 && std::memcmp(&bc, &r.bc, sizeof(gw_bc)) == 0 &&
+               std::memcmp(&params, &r.flow_params, sizeof(amg_params)) == 0 && (int64_t)K.size() == n &&
+               std::memcmp(K.data(), r.K, sizeof(double) * (size_t)n) == 0;
+    }
+};
+
 struct CachedSetup {
     SetupKey key;
+    std::shared_ptr<SetupInputs> inputs;
     amg_hierarchy *H = nullptr;
     size_t bytes = 0;
     bool in_use = false;
     uint64_t last_use = 0;
 };
+
+// A solve handed to the solver thread: kind 0 = flow (CG), 1 = travel-time
+// pair (BiCGSTAB on two right-hand sides).
+struct SolveTask {
+    int kind = 0;
+    amg_hierarchy *H = nullptr;
+    const double *b0 = nullptr, *b1 = nullptr;
+    double *x0 = nullptr, *x1 = nullptr;
+    amg_solve_params sp{};
+    amg_solve_info info[2] = {};
+    int status = GW_OK;
+    bool done = false;
+    char error[160] = {};
+};
+
+// Solves that may share launches: same kind, hierarchy precision and sweep
+// counts, and stopping parameters.
+bool same_batch(const SolveTask &a, const SolveTask &b) {
+    return a.kind == b.kind && a.H->prm.precision == b.H->prm.precision && a.H->prm.npre == b.H->prm.npre &&
+           a.H->prm.npost == b.H->prm.npost && a.sp.rtol == b.sp.rtol && a.sp.maxiter == b.sp.maxiter &&
+           a.sp.check_every == b.sp.check_every && a.sp.flexible == b.sp.flexible && a.sp.graph == b.sp.graph;
+}
+
+// A hierarchy the shared-launch solvers take (a diagonal smoother with at
+// least one sweep each way).
+bool batchable(const amg_hierarchy *H) {
+    return H->nlev >= 1 && H->prm.smoother != GW_SMOOTHER_ILU0 && H->prm.npre >= 1 && H->prm.npost >= 1;
+}
 
 struct Job {
     uint64_t ticket;
@@ -131,9 +185,19 @@ struct gw_queue {
     std::vector<CachedSetup> cache;
     int cache_max = 0;
     uint64_t use_clock = 0;
+    // solves waiting for the solver thread, and its batches
+    std::deque<SolveTask *> solves;
+    std::condition_variable cv_solve, cv_solved;
+    int max_batch = 16;    // 1: every slot solves on its own stream
+    double window_s = 0.0;  // how long a batch waits for more solves to join
+    bool stop_solver = false;
+    std::thread solver;
+    uint64_t n_batches = 0, n_batched = 0;
 
     double clock() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void worker();
+    void solver_loop();
+    int solve(SolveTask &t, hipStream_t s);
     int run(Job &job, hipStream_t s, gw_result &res);
     // With mu held: drop the least recently used idle entry; false if none.
     bool evict_one() {
@@ -191,7 +255,7 @@ int gw_queue::run(Job &job, hipStream_t s, gw_result &res) {
         key = setup_key(r);
         std::lock_guard<std::mutex> lk(mu);
         for (auto &c : cache)
-            if (!c.in_use && c.key == key) {
+            if (!c.in_use && c.key == key && c.inputs->same(r)) {
                 c.in_use = true;
                 H = c.H;
                 res.setup_reused = 1;
@@ -205,8 +269,24 @@ int gw_queue::run(Job &job, hipStream_t s, gw_result &res) {
     }
     const double setup_ms =
         std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count() - ts;
-    st = amg_solve_pcg(H, d.b.p, d.h.p, &r.solve, &res.flow, s);
-    GW_HIP(hipStreamSynchronize(s));
+    size_t flow_h_bytes = 0;
+    {
+        SolveTask t;
+        t.kind = 0;
+        t.H = H;
+        t.b0 = d.b.p;
+        t.x0 = d.h.p;
+        t.sp = r.solve;
+        try {
+            st = solve(t, s);
+        } catch (...) {
+            st = GW_EDEVICE;
+        }
+        res.flow = t.info[0];
+        if (st < 0) gw::set_last_error(t.error);
+        int32_t nl = 0;
+        (void)amg_hierarchy_info(H, nullptr, 0, &nl, &flow_h_bytes);
+    }
     {
         // hand the hierarchy back to the cache, or keep a new one there
         std::lock_guard<std::mutex> lk(mu);
@@ -223,9 +303,13 @@ int gw_queue::run(Job &job, hipStream_t s, gw_result &res) {
             if ((int)cache.size() < cache_max) {
                 CachedSetup c;
                 c.key = key;
+                c.inputs = std::make_shared<SetupInputs>();
+                c.inputs->grid = r.grid;
+                c.inputs->bc = r.bc;
+                c.inputs->params = r.flow_params;
+                c.inputs->K.assign(r.K, r.K + n);
                 c.H = H;
-                int32_t nl = 0;
-                (void)amg_hierarchy_info(H, nullptr, 0, &nl, &c.bytes);
+                c.bytes = flow_h_bytes;
                 c.last_use = ++use_clock;
                 reserved += c.bytes;
                 cache.push_back(c);
@@ -235,6 +319,9 @@ int gw_queue::run(Job &job, hipStream_t s, gw_result &res) {
         if (!kept) amg_free(H);
     }
     res.flow.setup_ms = setup_ms;
+    // device bytes held while the flow system was solved
+    const size_t flow_phase = d.K.bytes() + d.b.bytes() + d.h.bytes() + d.rowptr.bytes() + d.col.bytes() +
+                              d.val.bytes() + (res.setup_reused ? 0 : flow_h_bytes);
     d.val.release();
     d.col.release();
     d.rowptr.release();
@@ -249,13 +336,177 @@ int gw_queue::run(Job &job, hipStream_t s, gw_result &res) {
     if (r.h_out) GW_HIP(hipMemcpyAsync(r.h_out, d.h.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     d.tau.alloc(n);
     d.c.alloc(n);
-    st = tt_solve(&g, d.qx.p, d.qy.p, d.qz.p, r.phi, &r.zone, &r.tt_params, &r.solve, d.tau.p, d.c.p, res.tt, s);
+    // travel time (Eq. 1): the upwind matrix and its two right-hand sides, one
+    // hierarchy, then the pair solve
+    const double tt0 = std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count();
+    gw::DBuf<int32_t> trp((size_t)n + 1), tcol((size_t)nnz);
+    gw::DBuf<double> tval((size_t)nnz), bt(n), bc(n);
+    int64_t tnnz = 0, nid = 0;
+    st = tt_assemble(&g, d.qx.p, d.qy.p, d.qz.p, r.phi, &r.zone, trp.p, tcol.p, tval.p, bt.p, bc.p, &tnnz, &nid, s);
+    if (st != GW_OK) return st;
+    amg_hierarchy *Ht = nullptr;
+    {
+        gw_csr At{(int32_t)n, tnnz, trp.p, tcol.p, tval.p};
+        st = amg_setup(&At, &r.tt_params, &Ht, s);
+        if (st != GW_OK) return st;
+    }
+    std::unique_ptr<amg_hierarchy, void (*)(amg_hierarchy *)> Ht_owner(Ht, amg_free);
+    const size_t tt_csr_bytes = trp.bytes() + tcol.bytes() + tval.bytes();
+    trp.release();
+    tcol.release();
+    tval.release();
+    const double tt_setup_ms =
+        std::chrono::duration<double, std::milli>(Clock::now().time_since_epoch()).count() - tt0;
+    SolveTask t;
+    t.kind = 1;
+    t.H = Ht;
+    t.b0 = bt.p;
+    t.b1 = bc.p;
+    t.x0 = d.tau.p;
+    t.x1 = d.c.p;
+    t.sp = r.solve;
+    try {
+        st = solve(t, s);
+    } catch (...) {
+        st = GW_EDEVICE;
+    }
+    if (st < 0) gw::set_last_error(t.error);
+    res.tt[0] = t.info[0];
+    res.tt[1] = t.info[1];
+    res.tt[0].setup_ms = res.tt[1].setup_ms = tt_setup_ms;
+    size_t tt_h_bytes = 0;
+    {
+        int32_t nl = 0;
+        (void)amg_hierarchy_info(Ht, nullptr, 0, &nl, &tt_h_bytes);
+    }
+    // device bytes held during the travel-time setup and solve (the CSR is
+    // released after the setup, but counted: both live during it)
+    const size_t tt_phase = d.K.bytes() + d.h.bytes() + d.qx.bytes() + d.qy.bytes() + d.qz.bytes() +
+                            d.tau.bytes() + d.c.bytes() + bt.bytes() + bc.bytes() + tt_csr_bytes + tt_h_bytes;
+    res.bytes_used = std::max(flow_phase, tt_phase);
     if (st < 0) return st;
     if (r.tau_out) GW_HIP(hipMemcpyAsync(r.tau_out, d.tau.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     if (r.c_out) GW_HIP(hipMemcpyAsync(r.c_out, d.c.p, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     GW_HIP(hipStreamSynchronize(s));
     if (flow_status != GW_OK) return flow_status;
     return st;
+}
+
+// A solve of a slot: handed to the solver thread (shared launches with the
+// other slots' solves), or run on the slot's own stream when batching is off
+// or the hierarchy is not one the shared-launch solvers take.  The inputs
+// are complete on the device when it is called (every entry point before it
+// synchronized the slot's stream), and so are the outputs when it returns.
+int gw_queue::solve(SolveTask &t, hipStream_t s) {
+    bool batch = false;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        batch = max_batch > 1 && batchable(t.H);
+    }
+    if (!batch) {
+        const int st = t.kind == 0 ? amg_solve_pcg(t.H, t.b0, t.x0, &t.sp, &t.info[0], s)
+                                   : amg_solve_bicgstab_pair(t.H, t.b0, t.b1, t.x0, t.x1, &t.sp, t.info, s);
+        if (st < 0) std::strncpy(t.error, gw_last_error(), sizeof(t.error) - 1);
+        return st;
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    solves.push_back(&t);
+    cv_solve.notify_one();
+    cv_solved.wait(lk, [&] { return t.done; });
+    return t.status;
+}
+
+// The solver thread: takes the oldest waiting solve and every other waiting
+// solve that may share its launches (up to max_batch), runs them as one
+// batch on its own stream, and wakes their slots.
+void gw_queue::solver_loop() {
+    hipStream_t s = nullptr;
+    for (;;) {
+        std::vector<SolveTask *> take;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_solve.wait(lk, [&] { return stop_solver || !solves.empty(); });
+            if (solves.empty()) break;  // stop_solver, nothing left
+            const int cap = std::max(1, max_batch);
+            if (window_s > 0.0) {
+                // let solves of other running requests join, up to the window
+                const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                                      std::chrono::duration<double>(window_s));
+                cv_solve.wait_until(lk, until, [&] { return stop_solver || (int)solves.size() >= cap ||
+                                                            (int)solves.size() >= running; });
+            }
+            SolveTask *first = solves.front();
+            for (auto it = solves.begin(); it != solves.end() && (int)take.size() < cap;) {
+                if (same_batch(**it, *first)) {
+                    take.push_back(*it);
+                    it = solves.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            ++n_batches;
+            n_batched += take.size();
+        }
+        const int nsys = (int)take.size();
+        std::vector<amg_solve_info> info((size_t)nsys * 2);
+        std::vector<int> status(nsys, GW_OK);
+        const int st = gw::guarded([&] {
+            if (!s) {
+                GW_HIP(hipSetDevice(device));
+                GW_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            }
+            std::vector<amg_hierarchy *> H(nsys);
+            std::vector<const double *> b0(nsys), b1(nsys);
+            std::vector<double *> x0(nsys), x1(nsys);
+            for (int j = 0; j < nsys; ++j) {
+                H[j] = take[j]->H;
+                b0[j] = take[j]->b0;
+                b1[j] = take[j]->b1;
+                x0[j] = take[j]->x0;
+                x1[j] = take[j]->x1;
+            }
+            const amg_solve_params &sp = take[0]->sp;
+            if (take[0]->kind == 0) {
+                gw::krylov_pcg_batch(H.data(), b0.data(), x0.data(), nsys, sp, info.data(), s);
+                for (int j = 0; j < nsys; ++j) status[j] = info[j].status;
+            } else {
+                gw::krylov_bicgstab2_batch(H.data(), b0.data(), b1.data(), x0.data(), x1.data(), nsys, sp,
+                                           info.data(), s);
+                for (int j = 0; j < nsys; ++j) {
+                    const int s0 = info[2 * j].status, s1 = info[2 * j + 1].status;
+                    status[j] = (s0 == GW_BREAKDOWN || s1 == GW_BREAKDOWN) ? GW_BREAKDOWN
+                                : (s0 != GW_OK || s1 != GW_OK)           ? GW_NOT_CONVERGED
+                                                                         : GW_OK;
+                }
+            }
+            return GW_OK;
+        });
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (int j = 0; j < nsys; ++j) {
+                SolveTask &t = *take[j];
+                if (st < 0) {
+                    t.status = st;
+                    std::strncpy(t.error, gw_last_error(), sizeof(t.error) - 1);
+                } else {
+                    t.status = status[j];
+                    if (t.kind == 0) {
+                        t.info[0] = info[j];
+                    } else {
+                        t.info[0] = info[2 * j];
+                        t.info[1] = info[2 * j + 1];
+                    }
+                }
+                t.done = true;
+            }
+        }
+        cv_solved.notify_all();
+    }
+    if (s) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    gw::release_thread_resources();
 }
 
 void gw_queue::worker() {
@@ -304,7 +555,11 @@ void gw_queue::worker() {
         cv_work.notify_all();
         cv_done.notify_all();
     }
-    if (have_stream) (void)hipStreamDestroy(s);
+    if (have_stream) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    gw::release_thread_resources();
 }
 
 extern "C" {
@@ -323,6 +578,7 @@ int queue_create(size_t hbm_budget_bytes, int32_t max_slots, gw_queue **q) {
         (void)hipGetLastError();
         Q->device = dev;
         for (int i = 0; i < max_slots; ++i) Q->workers.emplace_back([p = Q.get()] { p->worker(); });
+        Q->solver = std::thread([p = Q.get()] { p->solver_loop(); });
         *q = Q.release();
         return GW_OK;
     });
@@ -408,8 +664,40 @@ void queue_destroy(gw_queue *q) {
     }
     q->cv_work.notify_all();
     for (auto &t : q->workers) t.join();
+    {
+        // the slots are gone, so no solve waits any more
+        std::lock_guard<std::mutex> lk(q->mu);
+        q->stop_solver = true;
+    }
+    q->cv_solve.notify_all();
+    if (q->solver.joinable()) q->solver.join();
     for (auto &c : q->cache) amg_free(c.H);
     delete q;
+}
+
+int queue_set_batch(gw_queue *q, int32_t max_batch, double window_us) {
+    return gw::guarded([&] {
+        GW_REQUIRE(q, "queue_set_batch: null queue");
+        GW_REQUIRE(max_batch >= 1 && max_batch <= 256, "queue_set_batch: max_batch must be in [1, 256]");
+        GW_REQUIRE(window_us >= 0.0 && window_us <= 1e7, "queue_set_batch: window_us must be in [0, 1e7]");
+        {
+            std::lock_guard<std::mutex> lk(q->mu);
+            q->max_batch = max_batch;
+            q->window_s = window_us * 1e-6;
+        }
+        q->cv_solve.notify_all();
+        return GW_OK;
+    });
+}
+
+int queue_stats(const gw_queue *q, uint64_t *batches, uint64_t *batched_solves) {
+    return gw::guarded([&] {
+        GW_REQUIRE(q, "queue_stats: null queue");
+        std::lock_guard<std::mutex> lk(const_cast<gw_queue *>(q)->mu);
+        if (batches) *batches = q->n_batches;
+        if (batched_solves) *batched_solves = q->n_batched;
+        return GW_OK;
+    });
 }
 
 }  // extern "C"

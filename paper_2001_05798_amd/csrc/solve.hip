@@ -172,7 +172,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
         return y;
     }
     const V *M = LevelOps<V>::mval(Lv);
-    const double abytes = op_bytes(Lv.A, Lv.As, vb);
+    const double abytes = op_bytes(Lv.A, Lv.As, vb), cabytes = csr_bytes(n, Lv.A.nnz, vb);
     V *x = reinterpret_cast<V *>(Lv.vx.p);
     V *t = reinterpret_cast<V *>(Lv.vt.p);
     const int npre = H->prm.npre, npost = H->prm.npost;
@@ -184,8 +184,9 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     if (npre == 0) {
         hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n * NR)), dim3(kBlock), 0, s, x, n * NR, done);
     } else {
-        ProfScope ps(level_kid(K_SMOOTH_FIRST0, l),
-                     (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb), s, true);
+        const double vec = n * (double)vb + nr * n * (double)(sizeof(Bt) + vb);
+        ProfScope ps(level_kid(K_SMOOTH_FIRST0, l), (npre >= 2 ? abytes : 0.0) + vec, s, true,
+                     (npre >= 2 ? cabytes : 0.0) + vec);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             GW_LAUNCH_TIMED(ps, (k_smooth_first<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
@@ -194,8 +195,8 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     }
     auto sweep = [&](auto *xin, auto *yout) {
         using YT = std::remove_pointer_t<decltype(yout)>;
-        ProfScope ps(level_kid(K_SMOOTH0, l),
-                     abytes + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT)), s, true);
+        const double vec = n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT));
+        ProfScope ps(level_kid(K_SMOOTH0, l), abytes + vec, s, true, cabytes + vec);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             GW_LAUNCH_TIMED(ps, (k_smooth<OP, V, Bt, V, YT, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
@@ -211,7 +212,8 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     const int64_t nc = Lv.nc;
     // residual and restriction
     {
-        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + nr * n * (double)(sizeof(Bt) + 2 * vb), s, true);
+        const double vec = nr * n * (double)(sizeof(Bt) + 2 * vb);
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + vec, s, true, cabytes + vec);
         with_level_op<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             GW_LAUNCH_TIMED(ps, (k_residual<OP, V, Bt, V, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, op,
@@ -508,7 +510,7 @@ struct Kry {
     KScalars *ks;
     hipStream_t s;
     double rtol;
-    double vec, abytes;
+    double vec, abytes, cabytes;
     const double *shift = nullptr;  // diagonal added to A (OpShift), or none
 
     Kry(amg_hierarchy *H_, hipStream_t s_, double rtol_) : Kry(H_, hier_work(H_), s_, rtol_) {}
@@ -521,6 +523,7 @@ struct Kry {
         ks = W.ks;
         vec = 8.0 * n;
         abytes = op_bytes(L0.A, L0.As, 8);
+        cabytes = csr_bytes(n, L0.A.nnz, 8);
     }
     template <bool SHIFT = false, class F>
     void op(F &&f) const {
@@ -538,7 +541,7 @@ struct Kry {
     template <bool SHIFT = false>
     void init(const double *b, const double *x, double *r, double *rh, double *p, double *v, bool first) {
         {
-            ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec + (rh ? 3 * vec : 0), s);
+            ProfScope ps(K_KRYLOV_SPMV, abytes + 4 * vec + (rh ? 3 * vec : 0), s, false, cabytes + 4 * vec + (rh ? 3 * vec : 0));
             op<SHIFT>([&](auto o) {
                 hipLaunchKernelGGL((k_kr_init<decltype(o)>), dim3(gG), dim3(kKBlock), 0, s, n, o, b, x, r, rh, p, v,
                                    part);
@@ -549,7 +552,7 @@ struct Kry {
     template <bool SHIFT = false>
     void true_res(const double *b, const double *x) {
         {
-            ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s);
+            ProfScope ps(K_TRUE_RESIDUAL, abytes + 2 * vec, s, false, cabytes + 2 * vec);
             op<SHIFT>([&](auto o) {
                 hipLaunchKernelGGL((k_true_res<decltype(o)>), dim3(gG), dim3(kKBlock), 0, s, n, o, b, x, part);
             });
@@ -638,7 +641,7 @@ void vcycle2(amg_hierarchy *H, const double *r, double *z, const int32_t *done, 
 void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s) {
     const Level &L0 = H->L[0];
     const int64_t n = L0.A.n;
-    ProfScope ps(K_KRYLOV_SPMV, op_bytes(L0.A, L0.As, 8) + 16.0 * n, s);
+    ProfScope ps(K_KRYLOV_SPMV, op_bytes(L0.A, L0.As, 8) + 16.0 * n, s, false, csr_bytes(n, L0.A.nnz, 8) + 16.0 * n);
     auto launch = [&](auto o) {
         using OP = decltype(o);
         hipLaunchKernelGGL((k_spmv_f64<OP>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, o, x, y);
@@ -694,7 +697,7 @@ int pcg_impl(amg_hierarchy *H, const KWork &W, const double *shift, const double
             for (int c = 0; c < cnt; ++c) {
                 double *po = par ? pb : pa, *pn = par ? pa : pb;
                 {
-                    ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs, true);
+                    ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 4 * Kc.vec, cs, true, Kc.cabytes + 4 * Kc.vec);
                     Kc.template op<SHIFT>([&](auto o) {
                         GW_LAUNCH_TIMED(ps, (k_cg_spmv<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, z, po,
                                            pn, q, Kc.part, Kc.ks);
@@ -819,7 +822,7 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
             }
             vcycle(H, p, ph, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs, true);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs, true, Kc.cabytes + 3 * Kc.vec);
                 Kc.op([&](auto o) {
                     GW_LAUNCH_TIMED(ps, (k_bcg_v<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
                                        Kc.part, Kc.ks);
@@ -833,7 +836,7 @@ int krylov_bicgstab(amg_hierarchy *H, const double *b, double *x_out, const amg_
             Kc.fin(FIN_BCG_S, Kc.g1);
             vcycle(H, sv, sh, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs, true);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * Kc.vec, cs, true, Kc.cabytes + 3 * Kc.vec);
                 Kc.op([&](auto o) {
                     GW_LAUNCH_TIMED(ps, (k_bcg_t<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
                                        Kc.part, Kc.ks);
@@ -902,7 +905,7 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
     };
     auto init2 = [&](int mask, bool first) {
         {
-            ProfScope ps(K_KRYLOV_SPMV, K.abytes + 7 * vec2, s);
+            ProfScope ps(K_KRYLOV_SPMV, K.abytes + 7 * vec2, s, false, K.cabytes + 7 * vec2);
             K.op([&](auto o) {
                 hipLaunchKernelGGL((k_kr_init2<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, b, x, r, rh, p,
                                    v, part, mask);
@@ -949,7 +952,7 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
             }
             vcycle2(H, p, ph, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs, true);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs, true, Kc.cabytes + 3 * vec2);
                 Kc.op([&](auto o) {
                     GW_LAUNCH_TIMED(ps, (k_bcg_v2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, ph, v, rh,
                                        part, ks);
@@ -963,7 +966,7 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
             fin2(cs, FIN_BCG_S, Kc.g1, 3);
             vcycle2(H, sv, sh, done, cs);
             {
-                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs, true);
+                ProfScope ps(K_KRYLOV_SPMV, Kc.abytes + 3 * vec2, cs, true, Kc.cabytes + 3 * vec2);
                 Kc.op([&](auto o) {
                     GW_LAUNCH_TIMED(ps, (k_bcg_t2<decltype(o)>), dim3(Kc.gG), dim3(kKBlock), 0, cs, n, o, sh, t, sv,
                                        part, ks);
@@ -994,7 +997,7 @@ int krylov_bicgstab2(amg_hierarchy *H, const double *b0, const double *b1, doubl
             cnt = c2;
         }
         {
-            ProfScope ps(K_TRUE_RESIDUAL, K.abytes + 2 * vec2, s);
+            ProfScope ps(K_TRUE_RESIDUAL, K.abytes + 2 * vec2, s, false, K.cabytes + 2 * vec2);
             K.op([&](auto o) {
                 hipLaunchKernelGGL((k_true_res2<decltype(o)>), dim3(K.gG), dim3(kKBlock), 0, s, n, o, b, x, part);
             });

@@ -22,6 +22,7 @@ def test_header_declares_the_boundary():
     names = _declared()
     for n in ["fv_assemble", "amg_setup", "amg_solve_pcg", "amg_solve_bicgstab", "amg_solve_bicgstab_pair", "tt_solve",
               "tt_sweep", "tt_solve_direct", "tt_delineate", "amg_solve_pcg_shifted", "flow_transient", "amg_ilu_export", "amg_solve_pcg_noalloc",
+              "amg_solve_pcg_batch", "amg_solve_bicgstab_pair_batch",
               "queue_submit", "queue_poll", "darcy_flux", "amg_free", "gw_last_error"]:
         assert n in names
 
@@ -56,6 +57,8 @@ def test_host_side_validation_without_device():
     assert lib.tt_sweep(None, 1, None, None, None, None) == -1
     assert lib.amg_solve_pcg_shifted(None, None, None, None, None, None, None) == -1
     assert lib.amg_solve_pcg_noalloc(None, None, None, None, None, None) == -1
+    assert lib.amg_solve_pcg_batch(None, None, None, 1, None, None, None) == -1
+    assert lib.amg_solve_bicgstab_pair_batch(None, None, None, None, None, 1, None, None, None) == -1
     assert lib.flow_transient(ctypes.byref(Grid(0, 4, 4, 1, 1, 1)), None, None, None, 0, None, None, None, 1,
                               ctypes.c_double(0.01), None, None, None, None, None, None) == -1
     assert lib.tt_delineate(ctypes.byref(Grid(4, 4, 4, 1, 1, 1)), None, None, None, ctypes.c_double(0.25),

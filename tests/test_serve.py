@@ -65,13 +65,17 @@ def test_queue_without_device_finishes_with_error():
     q.close()
 
 
-def _serve(problems, slots, budget=64 << 30):
+def _serve(problems, slots, budget=64 << 30, batch=None, window_us=0.0, stats=None):
     ap, sp = _params()
     tp = gw.AmgParams.travel_time(precision=gw.PRECISION_MIXED)
     q = gw.Queue(hbm_budget_bytes=budget, max_slots=slots)
+    if batch is not None:
+        q.set_batch(batch, window_us)
     tickets = [q.submit(p, ap, tp, sp, zone=(0, p.grid.ny, 0, max(1, p.grid.nz // 2))) for p in problems]
     q.drain()
     out = [q.poll(t) for t in tickets]
+    if stats is not None:
+        stats.extend(q.stats())
     q.close()
     return out
 
@@ -108,6 +112,33 @@ def test_alone_equals_in_mix(mix_run):
     starts = sorted(r.t_start for r, _ in mix)
     dones = sorted(r.t_done for r, _ in mix)
     assert starts[1] < dones[0]
+    for r, _ in mix:
+        assert 0 < r.bytes_used <= r.bytes_reserved, (r.bytes_used, r.bytes_reserved)
+
+
+@pytest.mark.gpu
+def test_shared_launches_equal_own_streams():
+    # the same mix served with shared launches (every running request's solve
+    # waits up to 0.5 s for the others, so solves of one phase share a batch)
+    # and with each request solving on its own stream: results bit for bit
+    # equal; the footprint a request held stays within its admission bytes
+    if gw is None or not _has_gpu():
+        pytest.skip("no GPU")
+    print("[case] serve shared launches vs own streams", flush=True)
+    probs = [gi.heterogeneous_aquifer(s, s - 4, s - 8, s2, lam, seed) for s, s2, lam, seed in
+             [(40, 2.0, 6, 61), (32, 4.0, 4, 62), (48, 1.0, 8, 63), (36, 2.0, 5, 64)]]
+    st = []
+    shared = _serve(probs, slots=4, batch=16, window_us=5e5, stats=st)
+    own = _serve(probs, slots=4, batch=1)
+    batches, solves = st
+    print(f"  {batches} batches held {solves} solves", flush=True)
+    assert solves == 2 * len(probs) and batches < solves
+    for (ra, oa), (rb, ob) in zip(shared, own):
+        assert ra.status == gw.OK and rb.status == gw.OK, (ra.error, rb.error)
+        for k in ("h", "tau", "c"):
+            assert np.array_equal(oa[k].view(np.uint64), ob[k].view(np.uint64)), k
+        assert (ra.flow.iters, ra.tt[0].iters, ra.tt[1].iters) == (rb.flow.iters, rb.tt[0].iters, rb.tt[1].iters)
+        assert 0 < ra.bytes_used <= ra.bytes_reserved, (ra.bytes_used, ra.bytes_reserved)
 
 
 @pytest.mark.gpu
@@ -150,6 +181,19 @@ def test_admission_by_budget():
     spans = sorted((r.t_start, r.t_done) for r, _ in res)
     for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
         assert s1 >= d0 - 1e-6  # serialized by the budget
+
+
+@needs_lib
+def test_batch_argument_checks_cpu():
+    q = gw.Queue(hbm_budget_bytes=1 << 30, max_slots=1)
+    for bad in ((0, 0.0), (257, 0.0), (4, -1.0)):
+        with pytest.raises(gw.GwError) as e:
+            q.set_batch(*bad)
+        assert e.value.status == gw.EINVAL
+    q.set_batch(1)
+    q.set_batch(8, 100.0)
+    assert q.stats() == (0, 0)
+    q.close()
 
 
 @needs_lib
