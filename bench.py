@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-prof", action="store_true", help="no per-launch event timing")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 8.4M-cell mixed roofline leg of the default (1M-cell) run")
     ap.add_argument("--no-transient", action="store_true", help="skip the transient-flow measurement")
     ap.add_argument("--no-ilu", action="store_true", help="skip the ILU(0)-smoother and Ruge-Stueben baselines")
     ap.add_argument("--no-direct", action="store_true",
@@ -60,11 +62,13 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run a plain 256 MiB device copy (torch copy kernel): its FETCH_SIZE / "
                          "WRITE_SIZE counters calibrate the HBM traffic counters of the path's kernels")
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the served-stream measurement (0 = skip)")
+    ap.add_argument("--serve-small", type=int, default=200,
+                    help="requests in the small-grid (32^3..64^3) served stream (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=4)
-    ap.add_argument("--serve-load", type=float, default=0.75,
-                    help="Poisson arrival rate as a fraction of the measured saturation throughput")
+    ap.add_argument("--serve-loads", default="0.5,0.75,0.9",
+                    help="Poisson arrival rates as fractions of the measured saturation throughput")
     return ap.parse_args()
 
 
@@ -152,40 +156,141 @@ def measured_traffic(workload: str, kernel: str):
     return None
 
 
+def _pinned(fn):
+    """Run fn() with the calling thread pinned to one core (no new process);
+    returns (result, the core)."""
+    old = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+    core = min(old) if old else None
+    if old:
+        os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        if old:
+            os.sched_setaffinity(0, old)
+
+
 def cpu_baseline(prob, precision, fp):
-    """Oracle on a bounded sample of the same workload (single thread), with
-    the flow hierarchy parameters `fp` of the GPU pass."""
+    """Oracle on a bounded sample of the same workload, on one pinned core,
+    with the flow hierarchy parameters `fp` of the GPU pass: every stage of
+    one pass timed (both travel-time solves included), plus the 64 x 64
+    homogeneous slab's setup and solve."""
+    import gwinputs as gi
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    A, b = oracle.fv_assemble(prob)
-    H = oracle.Hierarchy(A, oracle.AmgParams(eps_strong=fp.eps_strong, npre=fp.npre, npost=fp.npost))
-    h, info = oracle.pcg(H, b, rtol=1e-8, flexible=bool(precision))
-    t_flow = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    qx, qy, qz = oracle.darcy_flux(prob, h)
-    g = prob.grid
-    At, bt, bc, _ = oracle.tt_assemble(g, qx, qy, qz, prob.phi, (0, g.ny, 0, max(1, g.nz // 2)))
-    Ht = oracle.Hierarchy(At, oracle.AmgParams(eps_strong=0.25))
-    t_tsetup = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    tau, ti = oracle.bicgstab(Ht, bt, rtol=1e-8)
-    t_tsolve = time.perf_counter() - t2
-    total = t_flow + t_tsetup + 2 * t_tsolve
+
+    def run():
+        t = {}
+        t0 = time.perf_counter()
+        A, b = oracle.fv_assemble(prob)
+        t["assemble"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        H = oracle.Hierarchy(A, oracle.AmgParams(eps_strong=fp.eps_strong, npre=fp.npre, npost=fp.npost))
+        t["flow_setup"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        h, info = oracle.pcg(H, b, rtol=1e-8, flexible=bool(precision))
+        t["flow_solve"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        qx, qy, qz = oracle.darcy_flux(prob, h)
+        g = prob.grid
+        At, bt, bc, _ = oracle.tt_assemble(g, qx, qy, qz, prob.phi, (0, g.ny, 0, max(1, g.nz // 2)))
+        t["darcy_tt_assemble"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Ht = oracle.Hierarchy(At, oracle.AmgParams(eps_strong=0.25))
+        t["tt_setup"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        tau, ti = oracle.bicgstab(Ht, bt, rtol=1e-8)
+        t["tt_solve_tau"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        c, ci = oracle.bicgstab(Ht, bc, rtol=1e-8)
+        t["tt_solve_c"] = time.perf_counter() - t0
+        # the 64 x 64 homogeneous slab (Jacobi 2/3, one sweep each way)
+        slab = gi.homogeneous_slab()
+        A1, b1 = oracle.fv_assemble(slab)
+        t0 = time.perf_counter()
+        H1 = oracle.Hierarchy(A1, oracle.AmgParams(smoother=oracle.JACOBI, npre=1, npost=1))
+        t["slab_setup"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, i1 = oracle.pcg(H1, b1, rtol=1e-8)
+        t["slab_solve"] = time.perf_counter() - t0
+        return t, h, tau, info, ti, ci, i1
+
+    (t, h, tau, info, ti, ci, i1), core = _pinned(run)
+    total = sum(v for k, v in t.items() if not k.startswith("slab"))
     cpu_baseline.last = (h, tau)  # the oracle's heads and travel times, for the error report
     return {
         "value": 1.0 / total,
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": ("one pass of the same 128x128x64 workload on the FP64 C oracle: assembly, setup, PCG "
-                   f"({info.iters} it), Darcy, travel-time setup and the first of the two BiCGSTAB solves "
-                   f"({ti.iters} it); the second solve is counted at the first one's time "
-                   f"[flow {t_flow:.1f} s, tt setup {t_tsetup:.1f} s, tt solve {t_tsolve:.1f} s]"),
+        "sample": ("one whole pass of the same 128x128x64 workload on the FP64 C oracle, every stage timed: "
+                   f"assembly, flow setup, PCG ({info.iters} it), Darcy + travel-time assembly, travel-time "
+                   f"setup, BiCGSTAB for tau ({ti.iters} it) and for the zone fraction ({ci.iters} it)"),
+        "seconds": {k: round(v, 3) for k, v in t.items()},
+        "slab_64x64_iters": i1.iters,
         "cpu_model": _cpu_model(),
-        "affinity": sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+        "affinity": [core] if core is not None else None,
         "os_cpu_count": os.cpu_count(),
     }
+
+
+def roofline_entry(s, kernel, traffic):
+    """Roofline of one kernel class from its event-timed launches: `achieved`
+    by the plain formula (each operator pass counted as CSR: nnz (value +
+    4-byte column) + 4 (n + 1), vectors as read and written), beside the
+    bytes of the format the kernel reads and the counter-measured traffic."""
+    n = s["launches"]
+    avg_ms = s["ms"] / n
+    csr_b = s.get("bytes_csr", s["bytes"]) / n
+    fmt_b = s["bytes"] / n
+    gbs = lambda b: b / (avg_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "kernel": kernel, "achieved": round(gbs(csr_b), 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(gbs(csr_b) / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "bytes_per_launch": csr_b, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": n,
+           "format_bytes": {"bytes_per_launch": fmt_b, "achieved": round(gbs(fmt_b), 1),
+                            "frac": round(gbs(fmt_b) / HBM_PEAK_GBS, 4)},
+           "counter": None}
+    if traffic:
+        out["counter"] = {"bytes_per_launch": traffic, "achieved": round(gbs(traffic), 1),
+                          "frac": round(gbs(traffic) / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def c3_leg(gw, torch, steps: int):
+    """The 8.4M-cell mixed workload (its working set is far beyond the 256 MB
+    Infinity Cache, so the kernels meet HBM): a few passes with every launch
+    timed to find its dominant class, then passes with events on that class."""
+    import gwinputs as gi
+    nx, ny, nz, s2, lam, seed, precision = WORKLOADS["c3"]
+    prob = gi.heterogeneous_aquifer(nx, ny, nz, s2, lam, seed)
+    pipe = Pipeline(gw, torch, prob, precision, flow_kw=FLOW_PARAMS["c3"])
+    pipe.step()
+    gw.prof_select(None)
+    gw.prof_enable(True)
+    pipe.step()
+    st = gw.prof_read()
+    gw.prof_enable(False)
+    cand = {k: v for k, v in st.items() if v["launches"] > 0 and v["bytes"] > 0 and k not in SETUP_KERNELS}
+    dom = max(cand, key=lambda k: cand[k]["bytes"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    gw.prof_select(dom)
+    gw.prof_enable(True)
+    for _ in range(steps):
+        pipe.step()
+    s = gw.prof_read()[dom]
+    gw.prof_enable(False)
+    gw.prof_select(None)
+    out = roofline_entry(s, dom, measured_traffic("c3", dom))
+    out["workload"] = f"{nx}x{ny}x{nz} lognormal aquifer (lnK var {s2}, seed {seed}), FP32 hierarchy, FP64 Krylov"
+    out["ms_per_pass"] = round(ms, 3)
+    del pipe
+    torch.cuda.empty_cache()
+    return out
 
 
 def _make_problem(a):
@@ -193,68 +298,108 @@ def _make_problem(a):
     return gi.problem_for_arrival(a)
 
 
-def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
-    """Served stream: cubic grids 32^3..192^3 (uniform side), ln K variance in
-    {1,2,4}, correlation length 4..16 cells, each request a mixed-precision
-    flow solve plus the travel-time pair.  K fields are generated before the
-    clock starts.  First a burst of all requests measures the saturation
-    throughput; then Poisson arrivals at `load` x saturation give latencies."""
-    import concurrent.futures as cf
-    import threading
+def _zone(p):
+    return (0, p.grid.ny, 0, max(1, p.grid.nz // 2))
 
-    import gwinputs as gi
-    arrivals = gi.serve_stream(n_requests, 1.0, seed=seed)
-    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
-        probs = list(ex.map(_make_problem, arrivals))
-    ap = gw.AmgParams.flow(precision=gw.PRECISION_MIXED)
-    tp = gw.AmgParams.travel_time(precision=gw.PRECISION_MIXED)
-    sp = gw.SolveParams(rtol=1e-8)
-    budget = int(os.environ.get("GWAMG_SERVE_BUDGET", str(96 << 30)))
 
-    def zone(p):
-        return (0, p.grid.ny, 0, max(1, p.grid.nz // 2))
-
-    # saturation: everything at once
+def _burst(gw, probs, ap, tp, sp, budget, slots, batch):
+    """All requests at once: solves/s at saturation, the results, and the
+    solver thread's (batches, solves) counts."""
     q = gw.Queue(budget, slots)
+    q.set_batch(batch)
     t0 = q.clock()
-    tick = [q.submit(p, ap, tp, sp, zone=zone(p), want=()) for p in probs]
+    tick = [q.submit(p, ap, tp, sp, zone=_zone(p), want=()) for p in probs]
     q.drain()
-    makespan = q.clock() - t0
+    span = q.clock() - t0
     res = [q.poll(t)[0] for t in tick]
+    st = q.stats()
     q.close()
-    sat = n_requests / makespan
-    bad = sum(r.status != gw.OK for r in res)
-    # Poisson arrivals at load x saturation
-    rate = load * sat
-    rng = np.random.default_rng(seed + 1)
-    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    return len(probs) / span, res, st
+
+
+def _poisson(gw, probs, ap, tp, sp, budget, slots, batch, rate, seed):
+    """Poisson arrivals at `rate`: latencies (ms), the achieved rate and the results."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(probs))
     when = np.cumsum(gaps) - gaps[0]
     q = gw.Queue(budget, slots)
+    q.set_batch(batch)
     base = q.clock()
     tick = []
     for k, p in enumerate(probs):
         t_arr = base + float(when[k])
         while q.clock() < t_arr:
             time.sleep(min(0.002, max(0.0, t_arr - q.clock())))
-        tick.append(q.submit(p, ap, tp, sp, zone=zone(p), want=(), t_arrival=t_arr))
+        tick.append(q.submit(p, ap, tp, sp, zone=_zone(p), want=(), t_arrival=t_arr))
     q.drain()
     end = q.clock()
-    res2 = [q.poll(t)[0] for t in tick]
+    res = [q.poll(t)[0] for t in tick]
     q.close()
-    lat = np.array([r.latency for r in res2]) * 1e3
-    bad += sum(r.status != gw.OK for r in res2)
-    cells = np.array([p.grid.n for p in probs])
-    # the same burst with an FP64 hierarchy: the plain FP64 GPU solve the
-    # mixed-precision served form is compared with
+    lat = np.array([r.latency for r in res]) * 1e3
+    return lat, len(probs) / (end - base), res
+
+
+def _lat(lat):
+    return {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2),
+            "mean": round(float(lat.mean()), 2), "n": int(lat.size)}
+
+
+def serving(gw, n_requests: int, slots: int, loads, n_small: int, seed: int = 5):
+    """Served streams of dual-delineation requests, each a mixed-precision
+    flow solve plus the travel-time pair; K fields are generated before any
+    clock starts.  The specified stream: cubic grids 32^3..192^3 (uniform
+    side), ln K variance in {1,2,4}, correlation length 4..16 cells; its
+    saturation throughput with the solves sharing launches (the default),
+    with each request solving on its own stream, and with FP64 hierarchies;
+    then Poisson arrivals at each of `loads` x saturation for p50/p99.  A
+    stream of small requests (32^3..64^3, where launches dominate) measures
+    the shared launches' gain the same way."""
+    import concurrent.futures as cf
+
+    import gwinputs as gi
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        probs = list(ex.map(_make_problem, gi.serve_stream(n_requests, 1.0, seed=seed)))
+        small = list(ex.map(_make_problem, gi.serve_stream(n_small, 1.0, seed=seed + 2, side_min=32,
+                                                           side_max=64))) if n_small else []
+    ap = gw.AmgParams.flow(precision=gw.PRECISION_MIXED)
+    tp = gw.AmgParams.travel_time(precision=gw.PRECISION_MIXED)
+    sp = gw.SolveParams(rtol=1e-8)
+    budget = int(os.environ.get("GWAMG_SERVE_BUDGET", str(96 << 30)))
+    bad = 0
+    shared = 16
+
+    sat, res, stats = _burst(gw, probs, ap, tp, sp, budget, slots, shared)
+    bad += sum(r.status != gw.OK for r in res)
+    over = [r for r in res if r.bytes_used > r.bytes_reserved]
+    sat_own, res_own, _ = _burst(gw, probs, ap, tp, sp, budget, slots, 1)
+    bad += sum(r.status != gw.OK for r in res_own)
     ap64 = gw.AmgParams.flow(precision=gw.PRECISION_FP64)
     tp64 = gw.AmgParams.travel_time(precision=gw.PRECISION_FP64)
-    q = gw.Queue(budget, slots)
-    t0 = q.clock()
-    tick = [q.submit(p, ap64, tp64, sp, zone=zone(p), want=()) for p in probs]
-    q.drain()
-    makespan64 = q.clock() - t0
-    bad += sum(q.poll(t)[0].status != gw.OK for t in tick)
-    q.close()
+    sat64, res64, _ = _burst(gw, probs, ap64, tp64, sp, budget, slots, shared)
+    bad += sum(r.status != gw.OK for r in res64)
+    per_load = {}
+    last = None
+    for k, load in enumerate(loads):
+        lat, achieved, rr = _poisson(gw, probs, ap, tp, sp, budget, slots, shared, load * sat, seed + 10 + k)
+        bad += sum(r.status != gw.OK for r in rr)
+        per_load[str(load)] = {"offered_rate_per_s": round(load * sat, 3), "achieved_solves_per_s": round(achieved, 3),
+                               "latency_ms": _lat(lat)}
+        last = rr
+    small_out = None
+    if small:
+        s_sat, s_res, s_stats = _burst(gw, small, ap, tp, sp, budget, slots, shared)
+        s_own, s_res_own, _ = _burst(gw, small, ap, tp, sp, budget, slots, 1)
+        bad += sum(r.status != gw.OK for r in s_res + s_res_own)
+        lat_s, ach_s, rr = _poisson(gw, small, ap, tp, sp, budget, slots, shared, 0.75 * s_sat, seed + 20)
+        lat_o, ach_o, rr2 = _poisson(gw, small, ap, tp, sp, budget, slots, 1, 0.75 * s_sat, seed + 20)
+        bad += sum(r.status != gw.OK for r in rr + rr2)
+        cs = np.array([p.grid.n for p in small])
+        small_out = {"requests": len(small), "cells_mean": int(cs.mean()), "cells_max": int(cs.max()),
+                     "saturation_solves_per_s": {"shared_launches": round(s_sat, 3), "own_streams": round(s_own, 3)},
+                     "solver_batches": {"batches": s_stats[0], "solves": s_stats[1]},
+                     "at_0.75_of_shared_saturation": {
+                         "shared_launches": {"achieved_solves_per_s": round(ach_s, 3), "latency_ms": _lat(lat_s)},
+                         "own_streams": {"achieved_solves_per_s": round(ach_o, 3), "latency_ms": _lat(lat_o)}}}
     # accuracy of the served mixed form against the FP64 GPU solve (itself
     # within 1e-13 of the FP64 oracle in the parity tests), on three requests
     errs_h, errs_tau = [], []
@@ -262,7 +407,7 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
         outs = []
         for a, t in ((ap, tp), (ap64, tp64)):
             q = gw.Queue(budget, 1)
-            tk = q.submit(p, a, t, sp, zone=zone(p), want=("h", "tau"))
+            tk = q.submit(p, a, t, sp, zone=_zone(p), want=("h", "tau"))
             q.drain()
             outs.append(q.poll(tk)[1])
             q.close()
@@ -281,7 +426,7 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
         q = gw.Queue(budget, slots)
         q.set_setup_cache(slots if cache else 0)
         t0 = q.clock()
-        tick = [q.submit(p, ap, tp, sp, zone=zone(p), want=()) for p in study]
+        tick = [q.submit(p, ap, tp, sp, zone=_zone(p), want=()) for p in study]
         q.drain()
         span = q.clock() - t0
         rr = [q.poll(t)[0] for t in tick]
@@ -289,21 +434,23 @@ def serving(gw, n_requests: int, slots: int, load: float, seed: int = 5):
         bad += sum(r.status != gw.OK for r in rr)
         rates["cache" if cache else "no_cache"] = {"solves_per_s": round(len(study) / span, 3),
                                                    "setups_reused": sum(r.setup_reused for r in rr)}
+    cells = np.array([p.grid.n for p in probs])
     return {
         "requests": n_requests, "slots": slots, "precision": "f32-hierarchy/f64-krylov",
         "saturation_solves_per_s": round(sat, 3),
-        "fp64_saturation_solves_per_s": round(n_requests / makespan64, 3),
+        "own_streams_saturation_solves_per_s": round(sat_own, 3),
+        "fp64_saturation_solves_per_s": round(sat64, 3),
+        "solver_batches": {"batches": stats[0], "solves": stats[1]},
         "mixed_head_rel_err_vs_fp64_max": max(errs_h), "mixed_tau_rel_err_vs_fp64_max": max(errs_tau),
-        "offered_load": load, "offered_rate_per_s": round(rate, 3),
-        "achieved_solves_per_s": round(n_requests / (end - base), 3),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
-                       "p99": round(float(np.percentile(lat, 99)), 2),
-                       "mean": round(float(lat.mean()), 2)},
+        "poisson": per_load,
         "cells_mean": int(cells.mean()), "cells_max": int(cells.max()),
+        "footprint_exceeded": len(over),
+        "bytes_used_over_reserved_max": round(max(r.bytes_used / r.bytes_reserved for r in res), 3),
+        "small_stream": small_out,
         "well_rate_study": {"requests": len(study), "cells": aq.grid.n, **rates},
         "failed": int(bad),
-        "flow_iters_mean": round(float(np.mean([r.flow.iters for r in res2])), 1),
-        "tt_iters_mean": round(float(np.mean([r.tt[0].iters for r in res2])), 1),
+        "flow_iters_mean": round(float(np.mean([r.flow.iters for r in last or res])), 1),
+        "tt_iters_mean": round(float(np.mean([r.tt[0].iters for r in last or res])), 1),
     }
 
 
@@ -402,20 +549,15 @@ def main():
         ms_per_step_events = 1e3 * elapsed_ev / args.steps
         s = stats.get(dominant, {})
         if s.get("launches"):
-            per_launch_bytes = s["bytes"] / s["launches"]
-            avg_ms = s["ms"] / s["launches"]
-            achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(args.workload, dominant),
-                    "bytes_per_launch": per_launch_bytes, "avg_launch_us": round(avg_ms * 1e3, 2),
-                    "launches": s["launches"],
-                    "timing": (f"start and end events taken by each launch of the class itself "
-                               f"(hipExtLaunchKernelGGL), in {args.steps} further steps "
-                               f"({ms_per_step_events:.2f} ms/step with the events)")}
+            roof = roofline_entry(s, dominant, measured_traffic(args.workload, dominant))
+            roof["timing"] = (f"start and end events taken by each launch of the class itself "
+                              f"(hipExtLaunchKernelGGL), in {args.steps} further steps "
+                              f"({ms_per_step_events:.2f} ms/step with the events)")
     # per-class table from the last warm-up step (every launch timed there)
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None}
+                   "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None,
+                   "GBps_csr": round(v["bytes_csr"] / (v["ms"] * 1e-3) / 1e9, 1)
+                   if v["ms"] > 0 and v["bytes_csr"] > 0 else None}
                for k, v in all_stats.items() if v["launches"]}
 
     # the whole solve phase against the roofline: algorithmic bytes of every
@@ -537,10 +679,17 @@ def main():
                              "(ratio < 0.01), 'rebuilt' builds one for every step"}
         print(f"[bench] transient: {transient}", file=sys.stderr, flush=True)
 
+    c3 = None
+    if args.workload == "c2" and not args.no_c3:
+        print("[bench] 8.4M-cell mixed roofline leg ...", file=sys.stderr, flush=True)
+        c3 = c3_leg(gw, torch, 3)
+        print(f"[bench] c3 leg: {c3}", file=sys.stderr, flush=True)
+
     serve = None
     if args.serve_requests > 0:
         print(f"[bench] served stream, {args.serve_requests} requests ...", file=sys.stderr, flush=True)
-        serve = serving(gw, args.serve_requests, args.serve_slots, args.serve_load)
+        serve = serving(gw, args.serve_requests, args.serve_slots,
+                        [float(x) for x in args.serve_loads.split(",") if x], args.serve_small)
         print(f"[bench] served stream: {serve}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -582,6 +731,7 @@ def main():
                                  [round(statistics.median(x), 3) for x in zip(*parts)])),
         "tt_iters": list(titers[-1]),
         "roofline": roof,
+        "roofline_c3_mixed": c3,
         "solve_phase_roofline": solve_phase,
         "tt_direct": direct,
         "transient": transient,

@@ -204,6 +204,11 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
     hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, S.soff.p, S.dict.p, S.ndict,
                        S.idx.p, S.col.p, S.val.p, S.val32.p);
     GW_HIP(hipGetLastError());
+    // the widths (row pointers), the offset set (row pointers and columns),
+    // the fill (the CSR read, the copy written)
+    ps.bytes = 4.0 * (A.n + 1) * 3 + 4.0 * (double)A.nnz + 12.0 * (double)A.nnz +
+               (double)padded * (8 + (S.ndict ? 1 : 4) + (fp32 ? 4 : 0)) + 4.0 * (nslices + 1);
+    ps.cbytes = ps.bytes;
 }
 
 }  // namespace gw

@@ -1439,10 +1439,14 @@ int spgemm_group(double avg_a_len) {
 // other sizes), the symbolic pass (row lengths, nnz, largest row and
 // overflow into `blk`), and the numeric pass once those are on the host.
 // blk: [0] row bound, [1] largest row, [2] overflow, [4..5] nnz (int64).
+// Each pass is timed with its algorithmic bytes (every array it reads or
+// writes touched once): `bytes` for the row bound; for the symbolic and
+// numeric passes `in_bytes` covers the A- and B-side rows they read, and the
+// pass adds what it writes (C's row pointers; its columns and values).
 template <class AR, class BR>
-void spgemm_bound(AR ar, BR br, int32_t nrows, double avg_a_len, int32_t *blk, hipStream_t s) {
+void spgemm_bound(AR ar, BR br, int32_t nrows, double avg_a_len, int32_t *blk, hipStream_t s, double bytes) {
     fill_i32(blk, 0, 6, s);  // the bound, and the words the symbolic pass that follows accumulates into
-    ProfScope ps(K_SPGEMM, 0, s);
+    ProfScope ps(K_SPGEMM, bytes, s);
     // short rows: one lane per row (the row sums are a few loads)
     with_group(avg_a_len > 12.0 ? avg_a_len : 1.0, [&](auto gc) {
         constexpr int GU = decltype(gc)::value;
@@ -1485,7 +1489,7 @@ void spg_launch(const SpgShape &sh, int32_t nrows, bool num, int hbits, K &&kern
 
 template <class AR, class BR, class EPI>
 void spgemm_symbolic(AR ar, BR br, EPI epi, int32_t nrows, int32_t ncols, double avg_a_len, double avg_b_len,
-                     int32_t ub, Csr &C, int32_t *blk, hipStream_t s) {
+                     int32_t ub, Csr &C, int32_t *blk, hipStream_t s, double in_bytes) {
     const int64_t cap = std::min<int64_t>(ub, ncols);
     const int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
     C.alloc(nrows, ncols, 0);  // blk[1..5] were cleared by the product's spgemm_bound
@@ -1494,7 +1498,7 @@ void spgemm_symbolic(AR ar, BR br, EPI epi, int32_t nrows, int32_t ncols, double
     hipLaunchKernelGGL((k_spgemm<GG, false, AR, BR, EPI>), g, b, shm, s, ar, br, nrows, hb, Sx, C.rowptr.p, \
                        (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, epi, blk + 1, blk + 2)
     {
-        ProfScope ps(K_SPGEMM, 0, s);
+        ProfScope ps(K_SPGEMM, in_bytes + 4.0 * (nrows + 1), s);
         spg_launch(sh, nrows, false, hb, [&](dim3 g, dim3 b, size_t shm, int Sx) {
             switch (sh.G) {
                 case 8: SPG_SYM(8); break;
@@ -1512,7 +1516,7 @@ void spgemm_symbolic(AR ar, BR br, EPI epi, int32_t nrows, int32_t ncols, double
 // hblk: the host copy of blk after the symbolic pass.
 template <class AR, class BR, class EPI>
 void spgemm_numeric(AR ar, BR br, EPI epi, int32_t nrows, double avg_a_len, double avg_b_len, const int32_t *hblk,
-                    Csr &C, int32_t *blk, hipStream_t s) {
+                    Csr &C, int32_t *blk, hipStream_t s, double in_bytes) {
     int64_t nnz;
     std::memcpy(&nnz, &hblk[4], sizeof(nnz));
     const int32_t maxd = hblk[1];
@@ -1528,7 +1532,7 @@ void spgemm_numeric(AR ar, BR br, EPI epi, int32_t nrows, double avg_a_len, doub
     hipLaunchKernelGGL((k_spgemm<GG, true, AR, BR, EPI>), g, b, shm, s, ar, br, nrows, hbn, Sx,          \
                        (int32_t *)nullptr, C.rowptr.p, C.col.p, C.val.p, epi, blk + 1, blk + 2)
     {
-        ProfScope ps(K_SPGEMM, 0, s);
+        ProfScope ps(K_SPGEMM, in_bytes + 4.0 * (nrows + 1) + 12.0 * (double)nnz, s);
         spg_launch(sh, nrows, true, hbn, [&](dim3 g, dim3 b, size_t shm, int Sx) {
             switch (sh.G) {
                 case 8: SPG_NUM(8); break;
@@ -1644,18 +1648,26 @@ void galerkin(amg_hierarchy *H, int l, int64_t nc, LevelReads &rd, hipStream_t s
     const double ravg = (double)Lv.R.nnz / std::max<int64_t>(nc, 1);
     const ARowCsr a_side{A.rowptr, A.col, A.val};
     const BCsr p_side{Lv.P.rowptr.p, Lv.P.col.p, Lv.P.val.p};
-    spgemm_symbolic(a_side, p_side, EpiIdentity{}, n, (int32_t)nc, arow, pavg, rd.hblk(1)[0], AP, rd.blk(1), s);
+    // rows read by a pass: row pointers, then columns (symbolic) or columns
+    // and values (numeric)
+    auto rows = [](int64_t nr, int64_t nz, double per) { return 4.0 * (nr + 1) + per * (double)nz; };
+    const int64_t np = Lv.P.nnz, nr_ = Lv.R.nnz;
+    spgemm_symbolic(a_side, p_side, EpiIdentity{}, n, (int32_t)nc, arow, pavg, rd.hblk(1)[0], AP, rd.blk(1), s,
+                    rows(n, A.nnz, 4) + rows(n, np, 4));
     const ARowCsr r_side{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p};
-    spgemm_bound(r_side, BCsr{AP.rowptr.p, nullptr, nullptr}, (int32_t)nc, ravg, rd.blk(2), s);
+    spgemm_bound(r_side, BCsr{AP.rowptr.p, nullptr, nullptr}, (int32_t)nc, ravg, rd.blk(2), s,
+                 rows(nc, nr_, 4) + 4.0 * (n + 1));
     rd.sync(s);
-    spgemm_numeric(a_side, p_side, EpiIdentity{}, n, arow, pavg, rd.hblk(1), AP, rd.blk(1), s);
+    spgemm_numeric(a_side, p_side, EpiIdentity{}, n, arow, pavg, rd.hblk(1), AP, rd.blk(1), s,
+                   rows(n, A.nnz, 12) + rows(n, np, 12));
     Level &Nx = H->L[l + 1];
     const double apavg = (double)AP.nnz / std::max<int32_t>(n, 1);
     const BCsr ap_side{AP.rowptr.p, AP.col.p, AP.val.p};
     spgemm_symbolic(r_side, ap_side, EpiIdentity{}, (int32_t)nc, (int32_t)nc, ravg, apavg, rd.hblk(2)[0], Nx.A,
-                    rd.blk(2), s);
+                    rd.blk(2), s, rows(nc, nr_, 4) + rows(n, AP.nnz, 4));
     rd.sync(s);
-    spgemm_numeric(r_side, ap_side, EpiIdentity{}, (int32_t)nc, ravg, apavg, rd.hblk(2), Nx.A, rd.blk(2), s);
+    spgemm_numeric(r_side, ap_side, EpiIdentity{}, (int32_t)nc, ravg, apavg, rd.hblk(2), Nx.A, rd.blk(2), s,
+                   rows(nc, nr_, 12) + rows(n, AP.nnz, 12));
 }
 
 // Ruge-Stueben level: strength with the threshold kept on every level, PMIS
@@ -1752,7 +1764,8 @@ void build_level_rs(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         GW_HIP(hipGetLastError());
     }
     const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
-    spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s);
+    spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s,
+                 4.0 * (n + 1) + 4.0 * (double)A.nnz + 4.0 * (n + 1));
     rd.sync(s);
     const int64_t nc = rd.h64(4);
     Lv.nc = (int32_t)nc;
@@ -1958,7 +1971,8 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             });
             GW_HIP(hipGetLastError());
         }
-        spgemm_bound(af, bt, n, arow, rd.blk(0), s);
+        // filtered rows: columns and strong flags; tentative P: the aggregate map
+        spgemm_bound(af, bt, n, arow, rd.blk(0), s, 4.0 * (n + 1) + 5.0 * (double)A.nnz + 4.0 * n);
         int32_t flags[kBatch + 1];
         rd.sync(s, und + rounds, sizeof(int32_t) * (batch + 1), flags);
         if (flags[0] == 0) break;  // nothing was undecided before this batch
@@ -2002,10 +2016,14 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
     // P: symbolic pass, then the row bound of A P (it needs only P's row
     // pointers), one read for both
-    spgemm_symbolic(af, bt, ep, n, (int32_t)nc, arow, 1.0, rd.hblk(0)[0], Lv.P, rd.blk(0), s);
-    spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s);
+    spgemm_symbolic(af, bt, ep, n, (int32_t)nc, arow, 1.0, rd.hblk(0)[0], Lv.P, rd.blk(0), s,
+                    4.0 * (n + 1) + 5.0 * (double)A.nnz + 4.0 * n);
+    spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s,
+                 4.0 * (n + 1) + 4.0 * (double)A.nnz + 4.0 * (n + 1));
     rd.sync(s);
-    spgemm_numeric(af, bt, ep, n, arow, 1.0, rd.hblk(0), Lv.P, rd.blk(0), s);
+    // numeric: values too, the aggregate map, the lumped and the smoothing diagonals
+    spgemm_numeric(af, bt, ep, n, arow, 1.0, rd.hblk(0), Lv.P, rd.blk(0), s,
+                   4.0 * (n + 1) + 13.0 * (double)A.nnz + 4.0 * n + 16.0 * n);
 
     galerkin(H, l, nc, rd, s);
 }
