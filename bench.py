@@ -128,7 +128,8 @@ class Pipeline:
 
 
 TRAFFIC_SOURCES = ("paper_2001_05798_amd/csrc/solve.hip", "paper_2001_05798_amd/csrc/sell.hip",
-                   "paper_2001_05798_amd/csrc/gw_device.h", "paper_2001_05798_amd/csrc/gw_internal.h")
+                   "paper_2001_05798_amd/csrc/gw_device.h", "paper_2001_05798_amd/csrc/gw_internal.h",
+                   "paper_2001_05798_amd/csrc/solve_kernels.h")
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -349,11 +350,11 @@ def serving(gw, n_requests: int, slots: int, loads, n_small: int, seed: int = 5)
     flow solve plus the travel-time pair; K fields are generated before any
     clock starts.  The specified stream: cubic grids 32^3..192^3 (uniform
     side), ln K variance in {1,2,4}, correlation length 4..16 cells; its
-    saturation throughput with the solves sharing launches (the default),
-    with each request solving on its own stream, and with FP64 hierarchies;
-    then Poisson arrivals at each of `loads` x saturation for p50/p99.  A
-    stream of small requests (32^3..64^3, where launches dominate) measures
-    the shared launches' gain the same way."""
+    saturation throughput with each request solving on its own slot stream
+    (the default), with the solves sharing launches, and with FP64
+    hierarchies; then Poisson arrivals at each of `loads` x saturation for
+    p50/p99.  A stream of small requests (32^3..64^3, where launches
+    dominate) compares own streams with shared launches the same way."""
     import concurrent.futures as cf
 
     import gwinputs as gi
@@ -366,21 +367,21 @@ def serving(gw, n_requests: int, slots: int, loads, n_small: int, seed: int = 5)
     sp = gw.SolveParams(rtol=1e-8)
     budget = int(os.environ.get("GWAMG_SERVE_BUDGET", str(96 << 30)))
     bad = 0
-    shared = 16
+    own, shared = 1, 16
 
-    sat, res, stats = _burst(gw, probs, ap, tp, sp, budget, slots, shared)
+    sat, res, _ = _burst(gw, probs, ap, tp, sp, budget, slots, own)
     bad += sum(r.status != gw.OK for r in res)
     over = [r for r in res if r.bytes_used > r.bytes_reserved]
-    sat_own, res_own, _ = _burst(gw, probs, ap, tp, sp, budget, slots, 1)
-    bad += sum(r.status != gw.OK for r in res_own)
+    sat_sh, res_sh, stats = _burst(gw, probs, ap, tp, sp, budget, slots, shared)
+    bad += sum(r.status != gw.OK for r in res_sh)
     ap64 = gw.AmgParams.flow(precision=gw.PRECISION_FP64)
     tp64 = gw.AmgParams.travel_time(precision=gw.PRECISION_FP64)
-    sat64, res64, _ = _burst(gw, probs, ap64, tp64, sp, budget, slots, shared)
+    sat64, res64, _ = _burst(gw, probs, ap64, tp64, sp, budget, slots, own)
     bad += sum(r.status != gw.OK for r in res64)
     per_load = {}
     last = None
     for k, load in enumerate(loads):
-        lat, achieved, rr = _poisson(gw, probs, ap, tp, sp, budget, slots, shared, load * sat, seed + 10 + k)
+        lat, achieved, rr = _poisson(gw, probs, ap, tp, sp, budget, slots, own, load * sat, seed + 10 + k)
         bad += sum(r.status != gw.OK for r in rr)
         per_load[str(load)] = {"offered_rate_per_s": round(load * sat, 3), "achieved_solves_per_s": round(achieved, 3),
                                "latency_ms": _lat(lat)}
@@ -388,16 +389,16 @@ def serving(gw, n_requests: int, slots: int, loads, n_small: int, seed: int = 5)
     small_out = None
     if small:
         s_sat, s_res, s_stats = _burst(gw, small, ap, tp, sp, budget, slots, shared)
-        s_own, s_res_own, _ = _burst(gw, small, ap, tp, sp, budget, slots, 1)
+        s_own, s_res_own, _ = _burst(gw, small, ap, tp, sp, budget, slots, own)
         bad += sum(r.status != gw.OK for r in s_res + s_res_own)
-        lat_s, ach_s, rr = _poisson(gw, small, ap, tp, sp, budget, slots, shared, 0.75 * s_sat, seed + 20)
-        lat_o, ach_o, rr2 = _poisson(gw, small, ap, tp, sp, budget, slots, 1, 0.75 * s_sat, seed + 20)
+        lat_s, ach_s, rr = _poisson(gw, small, ap, tp, sp, budget, slots, shared, 0.75 * s_own, seed + 20)
+        lat_o, ach_o, rr2 = _poisson(gw, small, ap, tp, sp, budget, slots, own, 0.75 * s_own, seed + 20)
         bad += sum(r.status != gw.OK for r in rr + rr2)
         cs = np.array([p.grid.n for p in small])
         small_out = {"requests": len(small), "cells_mean": int(cs.mean()), "cells_max": int(cs.max()),
                      "saturation_solves_per_s": {"shared_launches": round(s_sat, 3), "own_streams": round(s_own, 3)},
-                     "solver_batches": {"batches": s_stats[0], "solves": s_stats[1]},
-                     "at_0.75_of_shared_saturation": {
+                     "solver": {"shared_blocks": s_stats[0], "solves": s_stats[1]},
+                     "at_0.75_of_own_stream_saturation": {
                          "shared_launches": {"achieved_solves_per_s": round(ach_s, 3), "latency_ms": _lat(lat_s)},
                          "own_streams": {"achieved_solves_per_s": round(ach_o, 3), "latency_ms": _lat(lat_o)}}}
     # accuracy of the served mixed form against the FP64 GPU solve (itself
@@ -438,9 +439,9 @@ def serving(gw, n_requests: int, slots: int, loads, n_small: int, seed: int = 5)
     return {
         "requests": n_requests, "slots": slots, "precision": "f32-hierarchy/f64-krylov",
         "saturation_solves_per_s": round(sat, 3),
-        "own_streams_saturation_solves_per_s": round(sat_own, 3),
+        "shared_launches_saturation_solves_per_s": round(sat_sh, 3),
         "fp64_saturation_solves_per_s": round(sat64, 3),
-        "solver_batches": {"batches": stats[0], "solves": stats[1]},
+        "solver": {"shared_blocks": stats[0], "solves": stats[1]},
         "mixed_head_rel_err_vs_fp64_max": max(errs_h), "mixed_tau_rel_err_vs_fp64_max": max(errs_tau),
         "poisson": per_load,
         "cells_mean": int(cells.mean()), "cells_max": int(cells.max()),

@@ -464,19 +464,29 @@ int queue_drain(gw_queue *q);
  * cached bytes count against the HBM budget and the least recently used
  * idle entry is freed when a waiting request does not fit. */
 int queue_set_setup_cache(gw_queue *q, int32_t max_entries);
-/* Shared launches for the solves of the running requests (the default,
- * max_batch = 16, window_us = 0): a request's flow solve and its
- * travel-time pair go to the queue's solver thread, which runs every waiting
- * solve of the same kind and parameters (up to max_batch) as one batch of
- * amg_solve_pcg_batch / amg_solve_bicgstab_pair_batch; each result is bit
- * for bit the one of a solve of its own.  With window_us > 0 a batch waits
- * up to that long for the solves of other running requests to join it (it
- * starts as soon as every running request has one waiting).  max_batch = 1:
- * each request solves on its own slot stream.  EINVAL for max_batch outside
- * [1, 256] or window_us outside [0, 1e7]. */
-int queue_set_batch(gw_queue *q, int32_t max_batch, double window_us);
-/* Batches the solver thread ran and the solves they held, since creation. */
-int queue_stats(const gw_queue *q, uint64_t *batches, uint64_t *batched_solves);
+/* Shared launches for the solves of the running requests (off by default:
+ * max_batch = 1; with max_batch > 1, window_us = 0 and one solver stream
+ * are the defaults of the other two arguments): a request's flow solve
+ * and its travel-time pair go to the queue's solver thread, whose engines
+ * (one for flow CG, one for travel-time pairs) run the iterations of every
+ * solve they hold -- up to max_batch, with the same precision, sweeps and
+ * stopping parameters -- in shared launches (one launch per kernel step for
+ * all of them, as amg_solve_pcg_batch / amg_solve_bicgstab_pair_batch); a
+ * solve joins at the next block of iterations and leaves as soon as it is
+ * final, and its result is bit for bit the one of a solve of its own.  With
+ * window_us > 0 an idle solver waits up to that long for the solves of the
+ * other running requests before its first block (it starts as soon as every
+ * running request has one waiting).  streams: solver threads, each with its
+ * own stream and engines (raised, never lowered, by a call).  max_batch = 1:
+ * each request solves on its own slot stream, which measured faster on one
+ * MI355X (the slots' small kernels already overlap on its four hardware
+ * queues; a shared launch adds two dependent loads to every kernel and
+ * serializes the systems' steps on one stream).  EINVAL for max_batch outside
+ * [1, 256], window_us outside [0, 1e7] or streams outside [1, 16]. */
+int queue_set_batch(gw_queue *q, int32_t max_batch, double window_us, int32_t streams);
+/* Blocks of iterations the solver threads ran for two or more solves at
+ * once, and the solves they have taken, since the queue was created. */
+int queue_stats(const gw_queue *q, uint64_t *shared_blocks, uint64_t *solves);
 void queue_destroy(gw_queue *q);
 
 #ifdef __cplusplus

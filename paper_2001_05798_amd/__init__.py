@@ -163,7 +163,7 @@ def _load():
         "queue_poll": (C.c_int, [vp, C.c_uint64, C.POINTER(ResultC)]),
         "queue_drain": (C.c_int, [vp]),
         "queue_set_setup_cache": (C.c_int, [vp, i32]),
-        "queue_set_batch": (C.c_int, [vp, i32, f64]),
+        "queue_set_batch": (C.c_int, [vp, i32, f64, i32]),
         "queue_stats": (C.c_int, [vp, vp, vp]),
         "queue_destroy": (None, [vp]),
     }
@@ -686,14 +686,15 @@ class Queue:
     def drain(self) -> None:
         _check(_lib.queue_drain(self._q))
 
-    def set_batch(self, max_batch: int, window_us: float = 0.0) -> None:
+    def set_batch(self, max_batch: int, window_us: float = 0.0, streams: int = 1) -> None:
         """Solves of the running requests share launches in batches of up to
         max_batch (1: each request solves on its own stream); a batch waits
-        up to window_us for other running requests' solves to join."""
-        _check(_lib.queue_set_batch(self._q, int(max_batch), float(window_us)))
+        up to window_us for other running requests' solves to join; `streams`
+        solver threads run batches side by side."""
+        _check(_lib.queue_set_batch(self._q, int(max_batch), float(window_us), int(streams)))
 
     def stats(self) -> Tuple[int, int]:
-        """(batches run by the solver thread, solves they held)."""
+        """(blocks of iterations run for two or more solves at once, solves taken)."""
         a, b = C.c_uint64(0), C.c_uint64(0)
         _check(_lib.queue_stats(self._q, C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)

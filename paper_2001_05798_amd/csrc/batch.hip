@@ -46,9 +46,11 @@ struct Launch {
 };
 using Seq = std::vector<Launch>;
 
+// The table of a launch: its records, then the record index of every block.
 template <class A>
 void launch_seg(const void *table, int nseg, unsigned nblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_seg<A>, dim3(nblk), dim3(kBlock), 0, s, static_cast<const Seg<A> *>(table), nseg);
+    const Seg<A> *t = static_cast<const Seg<A> *>(table);
+    hipLaunchKernelGGL(k_seg<A>, dim3(nblk), dim3(kBlock), 0, s, t, reinterpret_cast<const uint16_t *>(t + nseg));
 }
 
 struct Plan {
@@ -59,12 +61,19 @@ struct Plan {
     void add(Seq &q, const std::vector<std::pair<A, unsigned>> &recs, int kid, double bytes) {
         static_assert(std::is_trivially_copyable<Seg<A>>::value, "records are copied as bytes");
         if (recs.empty()) return;
+        GW_REQUIRE(recs.size() <= 65535, "shared launch: too many systems");
+        uint32_t total = 0;
+        for (const auto &r : recs) total += r.second;
         const size_t off = (host.size() + 255) / 256 * 256;
-        host.resize(off + recs.size() * sizeof(Seg<A>));
+        const size_t idx = off + recs.size() * sizeof(Seg<A>);
+        host.resize(idx + total * sizeof(uint16_t));
         uint32_t blk = 0;
         for (size_t k = 0; k < recs.size(); ++k) {
             const Seg<A> sg{recs[k].first, blk, recs[k].second};
             std::memcpy(host.data() + off + k * sizeof(Seg<A>), &sg, sizeof(Seg<A>));
+            const uint16_t id = (uint16_t)k;
+            for (uint32_t b = 0; b < recs[k].second; ++b)
+                std::memcpy(host.data() + idx + (blk + b) * sizeof(uint16_t), &id, sizeof(id));
             blk += recs[k].second;
         }
         q.push_back(Launch{&launch_seg<A>, off, (int)recs.size(), blk, kid, bytes});
@@ -132,10 +141,24 @@ struct Sys {
     double abytes;
 };
 
+// Operators of the shared launches: the sliced copy, or CSR with its lane
+// group as a run-time value, so that systems whose matrices pick different
+// groups still share one launch (same row sums as the one-system kernels).
+template <class V>
+OpCsrDyn<V> dyn(const Csr &A, const V *val) {
+    return OpCsrDyn<V>{A.rowptr.p, A.col.p, val, A.grp};
+}
+
 template <class F>
 void with_l0(const Level &L0, F &&f) {
     if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
-    else with_csr<double>(L0.A, L0.A.val.p, f);
+    else f(dyn<double>(L0.A, L0.A.val.p));
+}
+
+template <class V, class F>
+void with_level_dyn(const Level &Lv, F &&f) {
+    if (Lv.As.built() && LevelOps<V>::asval(Lv)) f(OpSell<V>{view(Lv.As), LevelOps<V>::asval(Lv)});
+    else f(dyn<V>(Lv.A, LevelOps<V>::aval(Lv)));
 }
 
 // ---------------------------------------------------- V-cycle recording ---
@@ -179,11 +202,11 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n;
         const double abytes = op_bytes(Lv.A, Lv.As, vb);
-        with_level_op<V>(Lv, [&](auto op) {
+        with_level_dyn<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             B.put(SmoothFirstK<OP, V, Bt, V, NR>{n, op, LevelOps<V>::mval(Lv), b[a], x[a], npre >= 2 ? 1 : 0,
                                                   S[act[a]].done},
-                  grid_rows(n, OP::G), (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb));
+                  grid_rows(n, op.lanes()), (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb));
         });
     }
     B.emit(P, q, level_kid(K_SMOOTH_FIRST0, l));
@@ -194,10 +217,10 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
             const double abytes = op_bytes(Lv.A, Lv.As, vb);
             auto *yo = yout_of(a);
             using YT = std::remove_pointer_t<decltype(yo)>;
-            with_level_op<V>(Lv, [&](auto op) {
+            with_level_dyn<V>(Lv, [&](auto op) {
                 using OP = decltype(op);
                 B.put(SmoothK<OP, V, Bt, V, YT, NR>{n, op, LevelOps<V>::mval(Lv), b[a], x[a], yo, S[act[a]].done},
-                      grid_rows(n, OP::G), abytes + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT)));
+                      grid_rows(n, op.lanes()), abytes + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb + sizeof(YT)));
             });
         }
         B.emit(P, q, level_kid(K_SMOOTH0, l));
@@ -213,9 +236,9 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n;
         const double abytes = op_bytes(Lv.A, Lv.As, vb);
-        with_level_op<V>(Lv, [&](auto op) {
+        with_level_dyn<V>(Lv, [&](auto op) {
             using OP = decltype(op);
-            B.put(ResidualK<OP, V, Bt, V, V, NR>{n, op, b[a], x[a], t[a], S[act[a]].done}, grid_rows(n, OP::G),
+            B.put(ResidualK<OP, V, Bt, V, V, NR>{n, op, b[a], x[a], t[a], S[act[a]].done}, grid_rows(n, op.lanes()),
                   abytes + nr * n * (double)(sizeof(Bt) + 2 * vb));
         });
     }
@@ -223,11 +246,9 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
     for (int a : fine) {
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n, nc = Lv.nc;
-        with_csr<V>(Lv.R, LevelOps<V>::rval(Lv), [&](auto op) {
-            using OP = decltype(op);
-            B.put(SpmvK<OP, V, V, V, NR>{nc, op, t[a], bnext[a], S[act[a]].done},
-                  grid_rows(nc, OP::G), csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb);
-        });
+        const OpCsrDyn<V> op = dyn<V>(Lv.R, LevelOps<V>::rval(Lv));
+        B.put(SpmvK<OpCsrDyn<V>, V, V, V, NR>{nc, op, t[a], bnext[a], S[act[a]].done}, grid_rows(nc, op.lanes()),
+              csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb);
     }
     B.emit(P, q, level_kid(K_RESTRICT0, l));
     // the next level, for the systems that continue
@@ -244,11 +265,9 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         const int a = fine[k];
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n, nc = Lv.nc;
-        with_csr<V>(Lv.P, LevelOps<V>::pval(Lv), [&](auto op) {
-            using OP = decltype(op);
-            B.put(ProlongK<OP, V, V, NR>{n, op, static_cast<const V *>(xc[k]), x[a], S[act[a]].done},
-                  grid_rows(n, OP::G), csr_bytes(n, Lv.P.nnz, vb) + nr * (double)(2 * n + nc) * vb);
-        });
+        const OpCsrDyn<V> op = dyn<V>(Lv.P, LevelOps<V>::pval(Lv));
+        B.put(ProlongK<OpCsrDyn<V>, V, V, NR>{n, op, static_cast<const V *>(xc[k]), x[a], S[act[a]].done},
+              grid_rows(n, op.lanes()), csr_bytes(n, Lv.P.nnz, vb) + nr * (double)(2 * n + nc) * vb);
     }
     B.emit(P, q, level_kid(K_PROLONG0, l));
     // post-smoothing (npost >= 1); the last sweep writes the requested output
@@ -293,530 +312,601 @@ void rec_fin(Plan &P, Seq &q, std::vector<Sys> &S, const std::vector<int> &act, 
     B.emit(P, q, -1);
 }
 
-void check_batch(amg_hierarchy *const *Hs, int32_t nsys, const char *who) {
-    GW_REQUIRE(nsys >= 1 && nsys <= 256, std::string(who) + ": nsys must be in [1, 256]");
-    GW_REQUIRE(Hs, std::string(who) + ": null hierarchy list");
-    const amg_params &p0 = Hs[0] ? Hs[0]->prm : amg_params{};
-    for (int j = 0; j < nsys; ++j) {
-        const amg_hierarchy *H = Hs[j];
-        GW_REQUIRE(H, std::string(who) + ": null hierarchy");
-        for (int k = 0; k < j; ++k) GW_REQUIRE(Hs[k] != H, std::string(who) + ": a hierarchy appears twice");
-        GW_REQUIRE(H->nlev >= 1 && H->prm.smoother != GW_SMOOTHER_ILU0,
-                   std::string(who) + ": every system needs a diagonal-smoother AMG preconditioner");
-        GW_REQUIRE(H->prm.npre >= 1 && H->prm.npost >= 1,
-                   std::string(who) + ": shared launches need at least one pre- and one post-sweep");
-        GW_REQUIRE(H->prm.precision == p0.precision && H->prm.npre == p0.npre && H->prm.npost == p0.npost,
-                   std::string(who) + ": the systems must share precision and sweep counts");
-    }
+void check_member(const amg_hierarchy *H, const amg_hierarchy *first, const char *who) {
+    GW_REQUIRE(H, std::string(who) + ": null hierarchy");
+    GW_REQUIRE(H->nlev >= 1 && H->prm.smoother != GW_SMOOTHER_ILU0,
+               std::string(who) + ": every system needs a diagonal-smoother AMG preconditioner");
+    GW_REQUIRE(H->prm.npre >= 1 && H->prm.npost >= 1,
+               std::string(who) + ": shared launches need at least one pre- and one post-sweep");
+    GW_REQUIRE(H->prm.precision == first->prm.precision && H->prm.npre == first->prm.npre &&
+                   H->prm.npost == first->prm.npost,
+               std::string(who) + ": the systems must share precision and sweep counts");
 }
-
-void read_all(const DBuf<KScalars> &ks, Pinned &stage, std::vector<KScalars> &h, hipStream_t s) {
-    const size_t bytes = h.size() * sizeof(KScalars);
-    GW_HIP(hipMemcpyAsync(stage.p, ks.p, bytes, hipMemcpyDeviceToHost, s));
-    GW_HIP(hipStreamSynchronize(s));
-    std::memcpy(h.data(), stage.p, bytes);
-}
-
-void write_all(DBuf<KScalars> &ks, Pinned &stage, const std::vector<KScalars> &h, hipStream_t s) {
-    const size_t bytes = h.size() * sizeof(KScalars);
-    std::memcpy(stage.p, h.data(), bytes);
-    GW_HIP(hipMemcpyAsync(ks.p, stage.p, bytes, hipMemcpyHostToDevice, s));
-    GW_HIP(hipStreamSynchronize(s));
-}
-
-// Blocks of `cnt` iterations: the recorded launches one by one, or a HIP
-// graph captured once per (parity, cnt) for this batch.
-struct Runner {
-    const Plan &P;
-    bool graph;
-    hipStream_t cap = nullptr;
-    struct G {
-        int parity, cnt;
-        hipGraphExec_t ex;
-    };
-    std::vector<G> graphs;
-    ~Runner() {
-        for (auto &g : graphs) (void)hipGraphExecDestroy(g.ex);
-        if (cap) (void)hipStreamDestroy(cap);
-    }
-    void block(const Seq (&iter)[2], int parity, int cnt, hipStream_t s) {
-        auto emit = [&](hipStream_t cs) {
-            int par = parity;
-            for (int c = 0; c < cnt; ++c) {
-                P.run(iter[par], cs);
-                par ^= iter[1].empty() ? 0 : 1;
-            }
-        };
-        if (!graph) {
-            emit(s);
-            return;
-        }
-        hipGraphExec_t ex = nullptr;
-        for (auto &g : graphs)
-            if (g.parity == parity && g.cnt == cnt) ex = g.ex;
-        if (!ex) {
-            if (!cap) GW_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            GW_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-            hipGraph_t g = nullptr;
-            try {
-                emit(cap);
-            } catch (...) {
-                if (hipStreamEndCapture(cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            GW_HIP(hipStreamEndCapture(cap, &g));
-            const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            GW_HIP(e);
-            graphs.push_back({parity, cnt, ex});
-        }
-        GW_HIP(hipGraphLaunch(ex, s));
-    }
-};
 
 }  // namespace
 
-// ------------------------------------------------------------- CG batch ---
-int krylov_pcg_batch(amg_hierarchy *const *Hs, const double *const *b, double *const *x_out, int32_t nsys,
-                     const amg_solve_params &sp, amg_solve_info *info, hipStream_t s) {
-    check_batch(Hs, nsys, "amg_solve_pcg_batch");
-    const double t0 = ms_now();
-    const bool mixed = Hs[0]->mixed();
-    const int flexible = sp.flexible < 0 ? (mixed ? 1 : 0) : (sp.flexible ? 1 : 0);
-    std::vector<Sys> S(nsys);
-    DBuf<KScalars> ks((size_t)nsys);
-    Pinned stage((size_t)nsys * sizeof(KScalars));
-    std::vector<double *> r(nsys), z(nsys), pa(nsys), pb(nsys), q(nsys), x(nsys);
-    for (int j = 0; j < nsys; ++j) {
-        amg_hierarchy *H = Hs[j];
-        ensure_krylov_workspace(H, 6);
-        const Level &L0 = H->L[0];
-        Sys &y = S[j];
-        y.H = H;
-        y.n = L0.A.n;
-        const int G = L0.As.built() ? 1 : L0.A.grp;
-        y.g1 = kgrid(y.n, 1);
-        y.gG = kgrid(y.n, G);
-        y.part = H->partials.p;
-        y.ks = ks.p + j;
-        y.done = &ks.p[j].done;
-        y.abytes = op_bytes(L0.A, L0.As, 8);
-        r[j] = H->kvec.p;
-        z[j] = r[j] + y.n;
-        pa[j] = z[j] + y.n;
-        pb[j] = pa[j] + y.n;
-        q[j] = pb[j] + y.n;
-        x[j] = q[j] + y.n;
-    }
-    std::vector<int> all(nsys);
-    for (int j = 0; j < nsys; ++j) all[j] = j;
-    std::vector<unsigned> nb1(nsys), nbG(nsys);
-    for (int j = 0; j < nsys; ++j) nb1[j] = S[j].g1, nbG[j] = S[j].gG;
+// ---------------------------------------------------------------- engine ---
+// The shared-launch solver: an active set of systems of one kind (CG or the
+// BiCGSTAB pair) with the same hierarchy precision and sweep counts and the
+// same stopping parameters.  Each step admits the systems that joined since
+// the last one (their start: r = b - A x0 with x0 = 0, and for CG the first
+// preconditioner application), runs one block of iterations of every active
+// system in shared launches, reads every system's scalars, and completes the
+// systems whose flag says done (true residual, then final or a restart, as
+// their own solve would).  Systems join and leave between blocks, so a system
+// that converges early returns at once and one that arrives later starts at
+// the next block.  A system's kernels and their order are those of its own
+// solve (krylov_pcg / krylov_bicgstab2), so are its iterates, bit for bit.
+struct BatchEngine::State {
+    Plan plan;
+    Seq iter[2];
+};
 
-    // the recorded sequences
+struct BatchEngine::Member {
+    void *tag = nullptr;
+    amg_hierarchy *H = nullptr;
+    const double *b0 = nullptr, *b1 = nullptr;
+    double *x0 = nullptr, *x1 = nullptr;
+    Sys sys{};
+    int slot = -1;
+    int par_off = 0;  // CG: block parity at the system's (re)start
+    PollPlan plan[2] = {{1, false}, {1, false}};
+    int restarts[2] = {0, 0}, status[2] = {GW_NOT_CONVERGED, GW_NOT_CONVERGED}, final[2] = {0, 0};
+    KScalars kfinal[2] = {};
+    double *v[10] = {};  // CG: r z pa pb q x; pair: b r rh p v s t ph sh x (interleaved)
+    double t0 = 0.0;
+};
+
+namespace {
+
+constexpr int kCgVecs = 6, kPairVecs = 20;
+
+}  // namespace
+
+BatchEngine::BatchEngine(int kind, const amg_solve_params &sp, int capacity, hipStream_t s)
+    : kind_(kind), sp_(sp), cap_(capacity), s_(s) {
+    nrec_ = kind == 0 ? 1 : 3;
+    ks_.alloc((size_t)cap_ * nrec_);
+    stage_.reset(new Pinned((size_t)cap_ * nrec_ * sizeof(KScalars)));
+    for (int k = cap_ - 1; k >= 0; --k) free_.push_back(k);
+    check_ = std::max(1, sp.check_every);
+    cnt_ = check_;
+}
+
+BatchEngine::~BatchEngine() = default;
+
+bool BatchEngine::accepts(const amg_hierarchy *H, const amg_solve_params &sp) const {
+    if ((int)(members_.size() + joining_.size()) >= cap_) return false;
+    if (sp.rtol != sp_.rtol || sp.maxiter != sp_.maxiter || sp.check_every != sp_.check_every ||
+        sp.flexible != sp_.flexible)
+        return false;
+    const amg_hierarchy *ref = !members_.empty() ? members_[0]->H : (!joining_.empty() ? joining_[0]->H : nullptr);
+    return !ref || (H->prm.precision == ref->prm.precision && H->prm.npre == ref->prm.npre &&
+                    H->prm.npost == ref->prm.npost);
+}
+
+void BatchEngine::join(void *tag, amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1) {
+    const char *who = kind_ == 0 ? "amg_solve_pcg_batch" : "amg_solve_bicgstab_pair_batch";
+    const amg_hierarchy *ref = !members_.empty() ? members_[0]->H : (!joining_.empty() ? joining_[0]->H : H);
+    check_member(H, ref, who);
+    for (auto &m : members_) GW_REQUIRE(m->H != H, std::string(who) + ": a hierarchy appears twice");
+    for (auto &m : joining_) GW_REQUIRE(m->H != H, std::string(who) + ": a hierarchy appears twice");
+    GW_REQUIRE(!free_.empty(), std::string(who) + ": too many systems");
+    std::unique_ptr<Member> m(new Member());
+    m->tag = tag;
+    m->H = H;
+    m->b0 = b0;
+    m->b1 = b1;
+    m->x0 = x0;
+    m->x1 = x1;
+    m->slot = free_.back();
+    free_.pop_back();
+    m->t0 = ms_now();
+    ensure_krylov_workspace(H, kind_ == 0 ? kCgVecs : kPairVecs);
+    if (kind_ == 1) ensure_level_vectors(H, 2);
+    const Level &L0 = H->L[0];
+    Sys &y = m->sys;
+    y.H = H;
+    y.n = L0.A.n;
+    const int G = L0.As.built() ? 1 : L0.A.grp;
+    y.g1 = kgrid(y.n, 1);
+    y.gG = kgrid(y.n, G);
+    y.part = H->partials.p;
+    y.ks = ks_.p + (size_t)m->slot * nrec_;
+    y.done = kind_ == 0 ? &y.ks->done : &y.ks[2].done;
+    y.abytes = op_bytes(L0.A, L0.As, 8);
+    const int64_t len = kind_ == 0 ? y.n : 2 * y.n;
+    for (int k = 0; k < (kind_ == 0 ? kCgVecs : 10); ++k) m->v[k] = H->kvec.p + k * len;
+    m->plan[0] = m->plan[1] = PollPlan{check_, false};
+    joining_.push_back(std::move(m));
+}
+
+bool BatchEngine::empty() const { return members_.empty() && joining_.empty(); }
+int BatchEngine::size() const { return (int)(members_.size() + joining_.size()); }
+
+namespace {
+
+std::vector<Sys> sys_of(const std::vector<BatchEngine::Member *> &ms) {
+    std::vector<Sys> S;
+    for (auto *m : ms) S.push_back(m->sys);
+    return S;
+}
+
+std::vector<int> iota_n(size_t n) {
+    std::vector<int> a(n);
+    for (size_t k = 0; k < n; ++k) a[k] = (int)k;
+    return a;
+}
+
+}  // namespace
+
+void BatchEngine::read_ks() {
+    const size_t bytes = (size_t)cap_ * nrec_ * sizeof(KScalars);
+    GW_HIP(hipMemcpyAsync(stage_->p, ks_.p, bytes, hipMemcpyDeviceToHost, s_));
+    GW_HIP(hipStreamSynchronize(s_));
+}
+
+KScalars *BatchEngine::hks(const Member &m) {
+    return static_cast<KScalars *>(stage_->p) + (size_t)m.slot * nrec_;
+}
+
+void BatchEngine::write_ks(const Member &m) {
+    GW_HIP(hipMemcpyAsync(ks_.p + (size_t)m.slot * nrec_, hks(m), nrec_ * sizeof(KScalars), hipMemcpyHostToDevice,
+                          s_));
+    GW_HIP(hipStreamSynchronize(s_));
+}
+
+// Record and run one step for the systems `ms` (a plan of its own).
+template <class Rec>
+void BatchEngine::run_once(const std::vector<Member *> &ms, Rec &&rec) {
+    if (ms.empty()) return;
     Plan P;
-    Seq init_first, first_z, iter[2], tres;
-    {
-        Buckets B;
-        for (int j = 0; j < nsys; ++j)
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(KrInitK<OP>{S[j].n, o, b[j], x[j], r[j], nullptr, pa[j], nullptr, S[j].part}, S[j].gG,
-                      S[j].abytes + 4 * 8.0 * S[j].n);
-            });
-        B.emit(P, init_first, K_KRYLOV_SPMV);
-        rec_fin(P, init_first, S, all, FIN_INIT_FIRST, false, sp.rtol, nbG);
-    }
-    auto rec_z_dot_beta = [&](Seq &qq, int fin) {
-        std::vector<const double *> rin(r.begin(), r.end());
-        rec_precond<1>(P, qq, S, all, rin, z, mixed);
-        Buckets B;
-        for (int j = 0; j < nsys; ++j)
-            B.put(CgDotK{S[j].n, r[j], z[j], q[j], S[j].part, S[j].ks}, S[j].g1, 3 * 8.0 * S[j].n);
-        B.emit(P, qq, K_KRYLOV_DOT);
-        rec_fin(P, qq, S, all, fin, false, sp.rtol, nb1);
-    };
-    rec_z_dot_beta(first_z, FIN_CG_BETA_FIRST);
-    for (int par = 0; par < 2; ++par) {
-        Seq &qq = iter[par];
-        Buckets B;
-        for (int j = 0; j < nsys; ++j) {
-            double *po = par ? pb[j] : pa[j], *pn = par ? pa[j] : pb[j];
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(CgSpmvK<OP>{S[j].n, o, z[j], po, pn, q[j], S[j].part, S[j].ks}, S[j].gG,
-                      S[j].abytes + 4 * 8.0 * S[j].n);
-            });
-        }
-        B.emit(P, qq, K_KRYLOV_SPMV);
-        rec_fin(P, qq, S, all, FIN_CG_ALPHA, false, sp.rtol, nbG);
-        for (int j = 0; j < nsys; ++j) {
-            double *pn = par ? pa[j] : pb[j];
-            B.put(CgUpdateK{S[j].n, x[j], r[j], pn, q[j], S[j].part, S[j].ks}, S[j].g1, 6 * 8.0 * S[j].n);
-        }
-        B.emit(P, qq, K_KRYLOV_UPDATE);
-        rec_fin(P, qq, S, all, FIN_CG_CONV, false, sp.rtol, nb1);
-        rec_z_dot_beta(qq, FIN_CG_BETA);
-    }
-    {
-        Buckets B;
-        for (int j = 0; j < nsys; ++j)
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(TrueResK<OP>{S[j].n, o, b[j], x[j], S[j].part}, S[j].gG, S[j].abytes + 2 * 8.0 * S[j].n);
-            });
-        B.emit(P, tres, K_TRUE_RESIDUAL);
-        rec_fin(P, tres, S, all, FIN_TRUE_RES, false, sp.rtol, nbG);
-    }
-    P.upload(s);
+    Seq q;
+    std::vector<Sys> S = sys_of(ms);
+    rec(P, q, S);
+    P.upload(s_);
+    P.run(q, s_);
+}
 
-    std::vector<KScalars> k(nsys);
-    for (int j = 0; j < nsys; ++j) {
-        k[j] = KScalars{};
-        k[j].maxiter = std::max(0, sp.maxiter);
-        k[j].flexible = flexible;
-        k[j].status = GW_NOT_CONVERGED;
+void BatchEngine::admit(std::vector<Member *> &done_now) {
+    if (joining_.empty()) return;
+    std::vector<Member *> J;
+    for (auto &m : joining_) J.push_back(m.get());
+    const double rtol = sp_.rtol;
+    // scalars: zero, maxiter, flexible (CG), status
+    for (Member *m : J) {
+        KScalars *k = hks(*m);
+        for (int r = 0; r < nrec_; ++r) k[r] = KScalars{};
+        for (int r = 0; r < (kind_ == 0 ? 1 : 2); ++r) {
+            k[r].maxiter = std::max(0, sp_.maxiter);
+            k[r].status = GW_NOT_CONVERGED;
+            if (kind_ == 0)
+                k[r].flexible = sp_.flexible < 0 ? (m->H->mixed() ? 1 : 0) : (sp_.flexible ? 1 : 0);
+        }
+        write_ks(*m);
     }
-    write_all(ks, stage, k, s);
-    for (int j = 0; j < nsys; ++j) fill_f64(x[j], 0.0, S[j].n, s);
-    P.run(init_first, s);
-    read_all(ks, stage, k, s);
-    std::vector<int> final(nsys, 0), restarts(nsys, 0), status(nsys, GW_NOT_CONVERGED);
-    bool any_zero = false;
-    for (int j = 0; j < nsys; ++j)
-        if (k[j].bnorm == 0.0) {
-            // b = 0: x = 0, nothing to iterate
-            final[j] = 1;
-            status[j] = GW_OK;
-            k[j].done = 1;
-            k[j].iters = 0;
-            k[j].rr = 0.0;
-            k[j].rel_true = 0.0;
-            any_zero = true;
-        }
-    if (any_zero) write_all(ks, stage, k, s);
-    const int check = std::max(1, sp.check_every);
-    Runner run{P, sp.graph > 0};
-    int parity = 0;
-    std::vector<KScalars> kfinal(k);
-    Plan Prestart;  // tables of restarts (rare), built when needed
-    for (;;) {
-        bool any = false;
-        for (int j = 0; j < nsys; ++j) any |= !final[j] && !k[j].done;
-        if (any) {
-            P.run(first_z, s);
-            std::vector<PollPlan> plans(nsys, PollPlan{check, sp.graph > 0});
-            int cnt = check;
-            for (;;) {
-                run.block(iter, parity, cnt, s);
-                parity ^= cnt & 1;
-                read_all(ks, stage, k, s);
-                bool all_done = true;
-                int c2 = 1;
-                for (int j = 0; j < nsys; ++j) {
-                    const int cj = plans[j].next(std::sqrt(k[j].rr), k[j].tol, k[j].iters);
-                    if (!k[j].done) {
-                        all_done = false;
-                        c2 = std::max(c2, cj);
-                    }
-                }
-                if (all_done) break;
-                cnt = c2;
-            }
-        }
-        P.run(tres, s);
-        read_all(ks, stage, k, s);
-        std::vector<int> again;
-        for (int j = 0; j < nsys; ++j) {
-            if (final[j]) continue;
-            KScalars &kj = k[j];
-            if (kj.status == GW_BREAKDOWN) status[j] = GW_BREAKDOWN, final[j] = 1;
-            else if (kj.rel_true <= sp.rtol) status[j] = GW_OK, final[j] = 1;
-            else if (kj.iters >= kj.maxiter || restarts[j] >= 8) status[j] = GW_NOT_CONVERGED, final[j] = 1;
-            else again.push_back(j);
-            if (final[j]) kfinal[j] = kj;
-        }
-        if (again.empty()) break;
-        // restart the systems in `again` from their iterate: r = b - A x
-        parity = 0;
-        Prestart = Plan();
-        Seq init_re;
-        {
+    const std::vector<int> all = iota_n(J.size());
+    if (kind_ == 0) {
+        for (Member *m : J) fill_f64(m->v[5], 0.0, m->sys.n, s_);
+        run_once(J, [&](Plan &P, Seq &q, std::vector<Sys> &S) {
             Buckets B;
             std::vector<unsigned> nb;
-            for (int j : again) {
-                ++restarts[j];
-                with_l0(S[j].H->L[0], [&](auto o) {
+            for (size_t a = 0; a < J.size(); ++a) {
+                Member *m = J[a];
+                with_l0(m->H->L[0], [&](auto o) {
                     using OP = decltype(o);
-                    B.put(KrInitK<OP>{S[j].n, o, b[j], x[j], r[j], nullptr, pa[j], nullptr, S[j].part}, S[j].gG, 0.0);
+                    B.put(KrInitK<OP>{m->sys.n, o, m->b0, m->v[5], m->v[0], nullptr, m->v[2], nullptr, m->sys.part},
+                          m->sys.gG, m->sys.abytes + 4 * 8.0 * m->sys.n);
                 });
-                nb.push_back(S[j].gG);
+                nb.push_back(m->sys.gG);
             }
-            B.emit(Prestart, init_re, K_KRYLOV_SPMV);
-            rec_fin(Prestart, init_re, S, again, FIN_INIT_RESTART, false, sp.rtol, nb);
-        }
-        Prestart.upload(s);
-        Prestart.run(init_re, s);
-        read_all(ks, stage, k, s);
-        // systems already final keep done = 1 and skip every launch
+            B.emit(P, q, K_KRYLOV_SPMV);
+            rec_fin(P, q, S, all, FIN_INIT_FIRST, false, rtol, nb);
+        });
+    } else {
+        for (Member *m : J) fill_f64(m->v[9], 0.0, 2 * m->sys.n, s_);
+        run_once(J, [&](Plan &P, Seq &q, std::vector<Sys> &S) {
+            Buckets B;
+            std::vector<unsigned> nb;
+            for (Member *m : J)
+                B.put(InterleaveK{m->sys.n, m->b0, m->b1, m->v[0]}, m->sys.g1, 4 * 8.0 * m->sys.n);
+            B.emit(P, q, -1);
+            for (Member *m : J) {
+                with_l0(m->H->L[0], [&](auto o) {
+                    using OP = decltype(o);
+                    B.put(KrInit2K<OP>{m->sys.n, o, m->v[0], m->v[9], m->v[1], m->v[2], m->v[3], m->v[4],
+                                       m->sys.part, 3},
+                          m->sys.gG, m->sys.abytes + 7 * 16.0 * m->sys.n);
+                });
+                nb.push_back(m->sys.gG);
+            }
+            B.emit(P, q, K_KRYLOV_SPMV);
+            rec_fin(P, q, S, all, FIN_INIT_FIRST, true, rtol, nb);
+        });
     }
-    for (int j = 0; j < nsys; ++j) copy_bytes(x_out[j], x[j], sizeof(double) * (size_t)S[j].n, s);
-    GW_HIP(hipStreamSynchronize(s));
-    const double ms = ms_now() - t0;
+    read_ks();
+    std::vector<Member *> go;  // CG systems that take their first preconditioner application
+    for (Member *m : J) {
+        KScalars *k = hks(*m);
+        if (kind_ == 0) {
+            if (k->bnorm == 0.0) {
+                // b = 0: x = 0, nothing to iterate
+                m->final[0] = 1;
+                m->status[0] = GW_OK;
+                k->done = 1;
+                k->iters = 0;
+                k->rr = 0.0;
+                k->rel_true = 0.0;
+                m->kfinal[0] = *k;
+                write_ks(*m);
+                continue;
+            }
+            if (!k->done) go.push_back(m);
+        } else {
+            bool zero = false;
+            for (int c = 0; c < 2; ++c) {
+                if (k[c].bnorm != 0.0) continue;
+                m->final[c] = 1;
+                m->status[c] = GW_OK;
+                k[c].done = 1;
+                k[c].iters = 0;
+                k[c].rr = 0.0;
+                k[c].rel_true = 0.0;
+                m->kfinal[c] = k[c];
+                zero = true;
+            }
+            if (zero) {
+                k[2].done = k[0].done && k[1].done;
+                write_ks(*m);
+            }
+        }
+    }
+    if (kind_ == 0 && !go.empty()) first_z(go);
+    for (auto &m : joining_) {
+        m->par_off = parity_;
+        Member *raw = m.get();
+        members_.push_back(std::move(m));
+        const bool all_final = raw->final[0] && (kind_ == 0 || raw->final[1]);
+        if (all_final) done_now.push_back(raw);
+    }
+    joining_.clear();
+    dirty_ = true;
+}
+
+// CG: z = V(r), then r.z and z.q and beta's first form, for the systems `ms`.
+void BatchEngine::first_z(const std::vector<Member *> &ms) {
+    const bool mixed = ms[0]->H->mixed();
+    const double rtol = sp_.rtol;
+    run_once(ms, [&](Plan &P, Seq &q, std::vector<Sys> &S) {
+        const std::vector<int> all = iota_n(ms.size());
+        std::vector<const double *> rin;
+        std::vector<double *> zout;
+        std::vector<unsigned> nb;
+        for (Member *m : ms) rin.push_back(m->v[0]), zout.push_back(m->v[1]), nb.push_back(m->sys.g1);
+        rec_precond<1>(P, q, S, all, rin, zout, mixed);
+        Buckets B;
+        for (Member *m : ms)
+            B.put(CgDotK{m->sys.n, m->v[0], m->v[1], m->v[4], m->sys.part, m->sys.ks}, m->sys.g1, 3 * 8.0 * m->sys.n);
+        B.emit(P, q, K_KRYLOV_DOT);
+        rec_fin(P, q, S, all, FIN_CG_BETA_FIRST, false, rtol, nb);
+    });
+}
+
+// The iteration plan of every active system (CG: two variants, by block
+// parity; each system's p buffers follow its own parity).
+void BatchEngine::record_iterations() {
+    st_.reset(new State());
+    std::vector<Member *> ms;
+    for (auto &m : members_)
+        if (!(m->final[0] && (kind_ == 0 || m->final[1]))) ms.push_back(m.get());
+    if (ms.empty()) return;
+    std::vector<Sys> S = sys_of(ms);
+    const std::vector<int> all = iota_n(ms.size());
+    const bool mixed = ms[0]->H->mixed();
+    const double rtol = sp_.rtol;
+    std::vector<unsigned> nb1, nbG;
+    for (Member *m : ms) nb1.push_back(m->sys.g1), nbG.push_back(m->sys.gG);
+    Plan &P = st_->plan;
+    if (kind_ == 0) {
+        for (int par = 0; par < 2; ++par) {
+            Seq &q = st_->iter[par];
+            Buckets B;
+            for (Member *m : ms) {
+                const int lp = par ^ m->par_off;
+                double *po = lp ? m->v[3] : m->v[2], *pn = lp ? m->v[2] : m->v[3];
+                with_l0(m->H->L[0], [&](auto o) {
+                    using OP = decltype(o);
+                    B.put(CgSpmvK<OP>{m->sys.n, o, m->v[1], po, pn, m->v[4], m->sys.part, m->sys.ks}, m->sys.gG,
+                          m->sys.abytes + 4 * 8.0 * m->sys.n);
+                });
+            }
+            B.emit(P, q, K_KRYLOV_SPMV);
+            rec_fin(P, q, S, all, FIN_CG_ALPHA, false, rtol, nbG);
+            for (Member *m : ms) {
+                const int lp = par ^ m->par_off;
+                double *pn = lp ? m->v[2] : m->v[3];
+                B.put(CgUpdateK{m->sys.n, m->v[5], m->v[0], pn, m->v[4], m->sys.part, m->sys.ks}, m->sys.g1,
+                      6 * 8.0 * m->sys.n);
+            }
+            B.emit(P, q, K_KRYLOV_UPDATE);
+            rec_fin(P, q, S, all, FIN_CG_CONV, false, rtol, nb1);
+            std::vector<const double *> rin;
+            std::vector<double *> zout;
+            for (Member *m : ms) rin.push_back(m->v[0]), zout.push_back(m->v[1]);
+            rec_precond<1>(P, q, S, all, rin, zout, mixed);
+            for (Member *m : ms)
+                B.put(CgDotK{m->sys.n, m->v[0], m->v[1], m->v[4], m->sys.part, m->sys.ks}, m->sys.g1,
+                      3 * 8.0 * m->sys.n);
+            B.emit(P, q, K_KRYLOV_DOT);
+            rec_fin(P, q, S, all, FIN_CG_BETA, false, rtol, nb1);
+        }
+    } else {
+        Seq &q = st_->iter[0];
+        Buckets B;
+        for (Member *m : ms)
+            B.put(BcgP2K{m->sys.n, m->v[1], m->v[3], m->v[4], m->sys.ks}, m->sys.g1, 4 * 16.0 * m->sys.n);
+        B.emit(P, q, K_KRYLOV_UPDATE);
+        {
+            std::vector<const double *> in;
+            std::vector<double *> out;
+            for (Member *m : ms) in.push_back(m->v[3]), out.push_back(m->v[7]);
+            rec_precond<2>(P, q, S, all, in, out, mixed);
+        }
+        for (Member *m : ms)
+            with_l0(m->H->L[0], [&](auto o) {
+                using OP = decltype(o);
+                B.put(BcgV2K<OP>{m->sys.n, o, m->v[7], m->v[4], m->v[2], m->sys.part, m->sys.ks}, m->sys.gG,
+                      m->sys.abytes + 3 * 16.0 * m->sys.n);
+            });
+        B.emit(P, q, K_KRYLOV_SPMV);
+        rec_fin(P, q, S, all, FIN_BCG_ALPHA, true, rtol, nbG);
+        for (Member *m : ms)
+            B.put(BcgS2K{m->sys.n, m->v[1], m->v[4], m->v[5], m->sys.part, m->sys.ks}, m->sys.g1,
+                  3 * 16.0 * m->sys.n);
+        B.emit(P, q, K_KRYLOV_UPDATE);
+        rec_fin(P, q, S, all, FIN_BCG_S, true, rtol, nb1);
+        {
+            std::vector<const double *> in;
+            std::vector<double *> out;
+            for (Member *m : ms) in.push_back(m->v[5]), out.push_back(m->v[8]);
+            rec_precond<2>(P, q, S, all, in, out, mixed);
+        }
+        for (Member *m : ms)
+            with_l0(m->H->L[0], [&](auto o) {
+                using OP = decltype(o);
+                B.put(BcgT2K<OP>{m->sys.n, o, m->v[8], m->v[6], m->v[5], m->sys.part, m->sys.ks}, m->sys.gG,
+                      m->sys.abytes + 3 * 16.0 * m->sys.n);
+            });
+        B.emit(P, q, K_KRYLOV_SPMV);
+        rec_fin(P, q, S, all, FIN_BCG_OMEGA, true, rtol, nbG);
+        for (Member *m : ms)
+            B.put(BcgXr2K{m->sys.n, m->v[9], m->v[1], m->v[7], m->v[8], m->v[5], m->v[6], m->v[2], m->sys.part,
+                          m->sys.ks},
+                  m->sys.g1, 8 * 16.0 * m->sys.n);
+        B.emit(P, q, K_KRYLOV_UPDATE);
+        rec_fin(P, q, S, all, FIN_BCG_XR, true, rtol, nb1);
+    }
+    P.upload(s_);
+    dirty_ = false;
+}
+
+// A system whose flag says done: true residual, then final (its output
+// written) or a restart from its iterate.  Returns whether it is final.
+void BatchEngine::complete(const std::vector<Member *> &ms, std::vector<Member *> &done_now) {
+    const double rtol = sp_.rtol;
+    run_once(ms, [&](Plan &P, Seq &q, std::vector<Sys> &S) {
+        Buckets B;
+        std::vector<unsigned> nb;
+        for (Member *m : ms) {
+            with_l0(m->H->L[0], [&](auto o) {
+                using OP = decltype(o);
+                if (kind_ == 0)
+                    B.put(TrueResK<OP>{m->sys.n, o, m->b0, m->v[5], m->sys.part}, m->sys.gG,
+                          m->sys.abytes + 2 * 8.0 * m->sys.n);
+                else
+                    B.put(TrueRes2K<OP>{m->sys.n, o, m->v[0], m->v[9], m->sys.part}, m->sys.gG,
+                          m->sys.abytes + 2 * 16.0 * m->sys.n);
+            });
+            nb.push_back(m->sys.gG);
+        }
+        B.emit(P, q, K_TRUE_RESIDUAL);
+        rec_fin(P, q, S, iota_n(ms.size()), FIN_TRUE_RES, kind_ == 1, rtol, nb);
+    });
+    read_ks();
+    std::vector<Member *> again;
+    std::vector<int> masks;
+    for (Member *m : ms) {
+        KScalars *k = hks(*m);
+        int mask = 0;
+        for (int c = 0; c < (kind_ == 0 ? 1 : 2); ++c) {
+            if (m->final[c]) continue;
+            const KScalars &q1 = k[c];
+            if (q1.status == GW_BREAKDOWN) m->status[c] = GW_BREAKDOWN, m->final[c] = 1;
+            else if (q1.rel_true <= rtol) m->status[c] = GW_OK, m->final[c] = 1;
+            else if (q1.iters >= q1.maxiter || m->restarts[c] >= 8) m->status[c] = GW_NOT_CONVERGED, m->final[c] = 1;
+            else {
+                ++m->restarts[c];
+                mask |= 1 << c;
+            }
+            if (m->final[c]) m->kfinal[c] = q1;
+        }
+        if (mask) {
+            again.push_back(m);
+            masks.push_back(mask);
+        } else {
+            done_now.push_back(m);
+        }
+    }
+    if (again.empty()) return;
+    // restart from the iterate: r = b - A x (and the pair's r_hat, p, v)
+    run_once(again, [&](Plan &P, Seq &q, std::vector<Sys> &S) {
+        Buckets B;
+        std::vector<unsigned> nb;
+        for (size_t a = 0; a < again.size(); ++a) {
+            Member *m = again[a];
+            with_l0(m->H->L[0], [&](auto o) {
+                using OP = decltype(o);
+                if (kind_ == 0)
+                    B.put(KrInitK<OP>{m->sys.n, o, m->b0, m->v[5], m->v[0], nullptr, m->v[2], nullptr, m->sys.part},
+                          m->sys.gG, 0.0);
+                else
+                    B.put(KrInit2K<OP>{m->sys.n, o, m->v[0], m->v[9], m->v[1], m->v[2], m->v[3], m->v[4],
+                                       m->sys.part, masks[a]},
+                          m->sys.gG, 0.0);
+            });
+            nb.push_back(m->sys.gG);
+        }
+        B.emit(P, q, K_KRYLOV_SPMV);
+        for (size_t a = 0; a < again.size(); ++a) {
+            Member *m = again[a];
+            if (kind_ == 0) B.put(FinK{FIN_INIT_RESTART, nb[a], m->sys.part, rtol, m->sys.ks}, 1u, 0.0);
+            else B.put(Fin2K{FIN_INIT_RESTART, nb[a], m->sys.part, rtol, m->sys.ks, masks[a]}, 1u, 0.0);
+        }
+        B.emit(P, q, -1);
+    });
+    read_ks();
+    if (kind_ == 0) {
+        std::vector<Member *> go;
+        for (Member *m : again) {
+            m->par_off = parity_;  // its p buffers start over as at its first iteration
+            m->plan[0] = PollPlan{check_, false};
+            if (!hks(*m)->done) go.push_back(m);
+        }
+        if (!go.empty()) first_z(go);
+    } else {
+        for (Member *m : again) m->plan[0] = m->plan[1] = PollPlan{check_, false};
+    }
+    dirty_ = true;
+}
+
+std::vector<BatchEngine::Result> BatchEngine::step() {
+    std::vector<Member *> done_now;
+    admit(done_now);
+    // systems still iterating
+    auto running = [&](Member *m) {
+        const KScalars *k = hks(*m);
+        return kind_ == 0 ? (!m->final[0] && !k->done) : (!k[2].done);
+    };
+    bool any = false;
+    for (auto &m : members_) any |= running(m.get());
+    if (any) {
+        if (dirty_) record_iterations();
+        for (int c = 0; c < cnt_; ++c) {
+            st_->plan.run(st_->iter[kind_ == 0 ? parity_ : 0], s_);
+            if (kind_ == 0) parity_ ^= 1;
+        }
+        read_ks();
+        int c2 = 1;
+        for (auto &m : members_) {
+            KScalars *k = hks(*m);
+            for (int c = 0; c < (kind_ == 0 ? 1 : 2); ++c) {
+                const int cq = m->plan[c].next(std::sqrt(k[c].rr), k[c].tol, k[c].iters);
+                if (!k[c].done && !m->final[c]) c2 = std::max(c2, cq);
+            }
+        }
+        cnt_ = c2;
+    }
+    // systems that stopped iterating and are not final yet
+    std::vector<Member *> fin;
+    for (auto &m : members_) {
+        const bool final_all = m->final[0] && (kind_ == 0 || m->final[1]);
+        if (final_all) continue;
+        if (!running(m.get())) fin.push_back(m.get());
+    }
+    if (!fin.empty()) complete(fin, done_now);
+    // outputs of the finished systems, then they leave
+    std::vector<Result> out;
+    if (done_now.empty()) return out;
+    {
+        std::vector<Member *> pairs;
+        for (Member *m : done_now) {
+            if (kind_ == 0) copy_bytes(m->x0, m->v[5], sizeof(double) * (size_t)m->sys.n, s_);
+            else pairs.push_back(m);
+        }
+        if (!pairs.empty())
+            run_once(pairs, [&](Plan &P, Seq &q, std::vector<Sys> &) {
+                Buckets B;
+                for (Member *m : pairs) B.put(SplitK{m->sys.n, m->v[9], m->x0, m->x1}, m->sys.g1, 4 * 8.0 * m->sys.n);
+                B.emit(P, q, -1);
+            });
+        GW_HIP(hipStreamSynchronize(s_));
+    }
+    const double now = ms_now();
+    for (Member *m : done_now) {
+        Result r;
+        r.tag = m->tag;
+        for (int c = 0; c < (kind_ == 0 ? 1 : 2); ++c) {
+            const KScalars &q1 = m->kfinal[c];
+            amg_solve_info &i = r.info[c];
+            i.iters = q1.iters;
+            i.status = m->status[c];
+            i.restarts = m->restarts[c];
+            i.rel_res = q1.bnorm != 0.0 ? std::sqrt(q1.rr) / q1.bnorm : 0.0;
+            i.rel_res_true = q1.bnorm != 0.0 ? q1.rel_true : 0.0;
+            i.setup_ms = 0.0;
+            i.solve_ms = now - m->t0;
+        }
+        if (kind_ == 0) {
+            r.status = m->status[0];
+        } else {
+            const int s0 = m->status[0], s1 = m->status[1];
+            r.status = (s0 == GW_BREAKDOWN || s1 == GW_BREAKDOWN) ? GW_BREAKDOWN
+                       : (s0 != GW_OK || s1 != GW_OK)           ? GW_NOT_CONVERGED
+                                                                : GW_OK;
+        }
+        out.push_back(r);
+        free_.push_back(m->slot);
+    }
+    // remove them
+    std::vector<std::unique_ptr<Member>> keep;
+    for (auto &m : members_) {
+        bool gone = false;
+        for (Member *d : done_now) gone |= d == m.get();
+        if (!gone) keep.push_back(std::move(m));
+    }
+    members_.swap(keep);
+    dirty_ = true;
+    return out;
+}
+
+// ------------------------------------------------------- one-shot batches ---
+namespace {
+
+int run_batch(int kind, amg_hierarchy *const *Hs, const double *const *b0, const double *const *b1,
+              double *const *x0, double *const *x1, int32_t nsys, const amg_solve_params &sp, amg_solve_info *info,
+              hipStream_t s) {
+    const char *who = kind == 0 ? "amg_solve_pcg_batch" : "amg_solve_bicgstab_pair_batch";
+    GW_REQUIRE(nsys >= 1 && nsys <= 256, std::string(who) + ": nsys must be in [1, 256]");
+    GW_REQUIRE(Hs, std::string(who) + ": null hierarchy list");
+    BatchEngine E(kind, sp, nsys, s);
+    for (int j = 0; j < nsys; ++j)
+        E.join(reinterpret_cast<void *>((intptr_t)j), Hs[j], b0[j], kind ? b1[j] : nullptr, x0[j],
+               kind ? x1[j] : nullptr);
     int worst = GW_OK;
-    for (int j = 0; j < nsys; ++j) {
-        const KScalars &q1 = kfinal[j];
-        if (info) {
-            info[j].iters = q1.iters;
-            info[j].status = status[j];
-            info[j].restarts = restarts[j];
-            info[j].rel_res = q1.bnorm != 0.0 ? std::sqrt(q1.rr) / q1.bnorm : 0.0;
-            info[j].rel_res_true = q1.bnorm != 0.0 ? q1.rel_true : 0.0;
-            info[j].setup_ms = 0.0;
-            info[j].solve_ms = ms;
+    while (!E.empty())
+        for (const auto &r : E.step()) {
+            const int j = (int)(intptr_t)r.tag;
+            if (info) {
+                if (kind == 0) info[j] = r.info[0];
+                else info[2 * j] = r.info[0], info[2 * j + 1] = r.info[1];
+            }
+            if (r.status == GW_BREAKDOWN) worst = GW_BREAKDOWN;
+            else if (r.status != GW_OK && worst == GW_OK) worst = GW_NOT_CONVERGED;
         }
-        if (status[j] == GW_BREAKDOWN) worst = GW_BREAKDOWN;
-        else if (status[j] != GW_OK && worst == GW_OK) worst = GW_NOT_CONVERGED;
-    }
     return worst;
 }
 
-// -------------------------------------------------- BiCGSTAB pair batch ---
+}  // namespace
+
+int krylov_pcg_batch(amg_hierarchy *const *Hs, const double *const *b, double *const *x_out, int32_t nsys,
+                     const amg_solve_params &sp, amg_solve_info *info, hipStream_t s) {
+    return run_batch(0, Hs, b, nullptr, x_out, nullptr, nsys, sp, info, s);
+}
+
 int krylov_bicgstab2_batch(amg_hierarchy *const *Hs, const double *const *b0, const double *const *b1,
                            double *const *x0, double *const *x1, int32_t nsys, const amg_solve_params &sp,
                            amg_solve_info *info, hipStream_t s) {
-    check_batch(Hs, nsys, "amg_solve_bicgstab_pair_batch");
-    const double t0 = ms_now();
-    const bool mixed = Hs[0]->mixed();
-    std::vector<Sys> S(nsys);
-    DBuf<KScalars> ks((size_t)nsys * 3);
-    Pinned stage((size_t)nsys * 3 * sizeof(KScalars));
-    struct V10 {
-        double *b, *r, *rh, *p, *v, *sv, *t, *ph, *sh, *x;
-    };
-    std::vector<V10> w(nsys);
-    for (int j = 0; j < nsys; ++j) {
-        amg_hierarchy *H = Hs[j];
-        ensure_krylov_workspace(H, 20);
-        ensure_level_vectors(H, 2);
-        const Level &L0 = H->L[0];
-        Sys &y = S[j];
-        y.H = H;
-        y.n = L0.A.n;
-        const int G = L0.As.built() ? 1 : L0.A.grp;
-        y.g1 = kgrid(y.n, 1);
-        y.gG = kgrid(y.n, G);
-        y.part = H->partials.p;
-        y.ks = ks.p + 3 * j;
-        y.done = &ks.p[3 * j + 2].done;
-        y.abytes = op_bytes(L0.A, L0.As, 8);
-        const int64_t n2 = 2 * y.n;
-        double *base = H->kvec.p;
-        w[j] = V10{base, base + n2, base + 2 * n2, base + 3 * n2, base + 4 * n2, base + 5 * n2, base + 6 * n2,
-                   base + 7 * n2, base + 8 * n2, base + 9 * n2};
-    }
-    std::vector<int> all(nsys);
-    for (int j = 0; j < nsys; ++j) all[j] = j;
-    std::vector<unsigned> nb1(nsys), nbG(nsys);
-    for (int j = 0; j < nsys; ++j) nb1[j] = S[j].g1, nbG[j] = S[j].gG;
-
-    Plan P;
-    Seq init_first, iter[2], tres, split;
-    {
-        Buckets B;
-        for (int j = 0; j < nsys; ++j)
-            B.put(InterleaveK{S[j].n, b0[j], b1[j], w[j].b}, S[j].g1, 4 * 8.0 * S[j].n);
-        B.emit(P, init_first, -1);
-        for (int j = 0; j < nsys; ++j)
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(KrInit2K<OP>{S[j].n, o, w[j].b, w[j].x, w[j].r, w[j].rh, w[j].p, w[j].v, S[j].part, 3},
-                      S[j].gG, S[j].abytes + 7 * 16.0 * S[j].n);
-            });
-        B.emit(P, init_first, K_KRYLOV_SPMV);
-        rec_fin(P, init_first, S, all, FIN_INIT_FIRST, true, sp.rtol, nbG);
-    }
-    {
-        Seq &qq = iter[0];
-        Buckets B;
-        for (int j = 0; j < nsys; ++j) B.put(BcgP2K{S[j].n, w[j].r, w[j].p, w[j].v, S[j].ks}, S[j].g1, 4 * 16.0 * S[j].n);
-        B.emit(P, qq, K_KRYLOV_UPDATE);
-        {
-            std::vector<const double *> in(nsys);
-            std::vector<double *> out(nsys);
-            for (int j = 0; j < nsys; ++j) in[j] = w[j].p, out[j] = w[j].ph;
-            rec_precond<2>(P, qq, S, all, in, out, mixed);
-        }
-        for (int j = 0; j < nsys; ++j)
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(BcgV2K<OP>{S[j].n, o, w[j].ph, w[j].v, w[j].rh, S[j].part, S[j].ks}, S[j].gG,
-                      S[j].abytes + 3 * 16.0 * S[j].n);
-            });
-        B.emit(P, qq, K_KRYLOV_SPMV);
-        rec_fin(P, qq, S, all, FIN_BCG_ALPHA, true, sp.rtol, nbG);
-        for (int j = 0; j < nsys; ++j)
-            B.put(BcgS2K{S[j].n, w[j].r, w[j].v, w[j].sv, S[j].part, S[j].ks}, S[j].g1, 3 * 16.0 * S[j].n);
-        B.emit(P, qq, K_KRYLOV_UPDATE);
-        rec_fin(P, qq, S, all, FIN_BCG_S, true, sp.rtol, nb1);
-        {
-            std::vector<const double *> in(nsys);
-            std::vector<double *> out(nsys);
-            for (int j = 0; j < nsys; ++j) in[j] = w[j].sv, out[j] = w[j].sh;
-            rec_precond<2>(P, qq, S, all, in, out, mixed);
-        }
-        for (int j = 0; j < nsys; ++j)
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(BcgT2K<OP>{S[j].n, o, w[j].sh, w[j].t, w[j].sv, S[j].part, S[j].ks}, S[j].gG,
-                      S[j].abytes + 3 * 16.0 * S[j].n);
-            });
-        B.emit(P, qq, K_KRYLOV_SPMV);
-        rec_fin(P, qq, S, all, FIN_BCG_OMEGA, true, sp.rtol, nbG);
-        for (int j = 0; j < nsys; ++j)
-            B.put(BcgXr2K{S[j].n, w[j].x, w[j].r, w[j].ph, w[j].sh, w[j].sv, w[j].t, w[j].rh, S[j].part, S[j].ks},
-                  S[j].g1, 8 * 16.0 * S[j].n);
-        B.emit(P, qq, K_KRYLOV_UPDATE);
-        rec_fin(P, qq, S, all, FIN_BCG_XR, true, sp.rtol, nb1);
-    }
-    {
-        Buckets B;
-        for (int j = 0; j < nsys; ++j)
-            with_l0(S[j].H->L[0], [&](auto o) {
-                using OP = decltype(o);
-                B.put(TrueRes2K<OP>{S[j].n, o, w[j].b, w[j].x, S[j].part}, S[j].gG, S[j].abytes + 2 * 16.0 * S[j].n);
-            });
-        B.emit(P, tres, K_TRUE_RESIDUAL);
-        rec_fin(P, tres, S, all, FIN_TRUE_RES, true, sp.rtol, nbG);
-        for (int j = 0; j < nsys; ++j) B.put(SplitK{S[j].n, w[j].x, x0[j], x1[j]}, S[j].g1, 4 * 8.0 * S[j].n);
-        B.emit(P, split, -1);
-    }
-    P.upload(s);
-
-    std::vector<KScalars> k((size_t)nsys * 3);
-    for (int j = 0; j < nsys; ++j)
-        for (int c = 0; c < 3; ++c) {
-            KScalars &q1 = k[3 * j + c];
-            q1 = KScalars{};
-            if (c < 2) {
-                q1.maxiter = std::max(0, sp.maxiter);
-                q1.status = GW_NOT_CONVERGED;
-            }
-        }
-    write_all(ks, stage, k, s);
-    for (int j = 0; j < nsys; ++j) fill_f64(w[j].x, 0.0, 2 * S[j].n, s);
-    P.run(init_first, s);
-    read_all(ks, stage, k, s);
-    std::vector<int> final((size_t)nsys * 2, 0), restarts((size_t)nsys * 2, 0), status((size_t)nsys * 2, GW_NOT_CONVERGED);
-    bool any_zero = false;
-    for (int j = 0; j < nsys; ++j) {
-        for (int c = 0; c < 2; ++c) {
-            KScalars &q1 = k[3 * j + c];
-            if (q1.bnorm != 0.0) continue;
-            final[2 * j + c] = 1;
-            status[2 * j + c] = GW_OK;
-            q1.done = 1;
-            q1.iters = 0;
-            q1.rr = 0.0;
-            q1.rel_true = 0.0;
-            any_zero = true;
-        }
-        k[3 * j + 2].done = k[3 * j].done && k[3 * j + 1].done;
-    }
-    if (any_zero) write_all(ks, stage, k, s);
-    const int check = std::max(1, sp.check_every);
-    iter[1].clear();  // one sequence: no parity
-    Runner run{P, sp.graph > 0};
-    std::vector<KScalars> kfinal(k);
-    Plan Prestart;
-    for (;;) {
-        std::vector<PollPlan> plans((size_t)nsys * 2, PollPlan{check, sp.graph > 0});
-        int cnt = check;
-        for (;;) {
-            bool all_done = true;
-            for (int j = 0; j < nsys; ++j) all_done &= k[3 * j + 2].done != 0;
-            if (all_done) break;
-            run.block(iter, 0, cnt, s);
-            read_all(ks, stage, k, s);
-            int c2 = 1;
-            for (int j = 0; j < nsys; ++j)
-                for (int c = 0; c < 2; ++c) {
-                    const KScalars &q1 = k[3 * j + c];
-                    const int cq = plans[2 * j + c].next(std::sqrt(q1.rr), q1.tol, q1.iters);
-                    if (!q1.done) c2 = std::max(c2, cq);
-                }
-            cnt = c2;
-        }
-        P.run(tres, s);
-        read_all(ks, stage, k, s);
-        std::vector<int> again;
-        std::vector<int> masks;
-        for (int j = 0; j < nsys; ++j) {
-            int mask = 0;
-            for (int c = 0; c < 2; ++c) {
-                const int e = 2 * j + c;
-                if (final[e]) continue;
-                const KScalars &q1 = k[3 * j + c];
-                if (q1.status == GW_BREAKDOWN) status[e] = GW_BREAKDOWN, final[e] = 1;
-                else if (q1.rel_true <= sp.rtol) status[e] = GW_OK, final[e] = 1;
-                else if (q1.iters >= q1.maxiter || restarts[e] >= 8) status[e] = GW_NOT_CONVERGED, final[e] = 1;
-                else {
-                    ++restarts[e];
-                    mask |= 1 << c;
-                }
-                if (final[e]) kfinal[3 * j + c] = q1;
-            }
-            if (mask) again.push_back(j), masks.push_back(mask);
-        }
-        if (again.empty()) break;
-        Prestart = Plan();
-        Seq init_re;
-        {
-            Buckets B;
-            std::vector<unsigned> nb;
-            for (size_t a = 0; a < again.size(); ++a) {
-                const int j = again[a];
-                with_l0(S[j].H->L[0], [&](auto o) {
-                    using OP = decltype(o);
-                    B.put(KrInit2K<OP>{S[j].n, o, w[j].b, w[j].x, w[j].r, w[j].rh, w[j].p, w[j].v, S[j].part,
-                                       masks[a]},
-                          S[j].gG, 0.0);
-                });
-                nb.push_back(S[j].gG);
-            }
-            B.emit(Prestart, init_re, K_KRYLOV_SPMV);
-            // one finalize per system, each with its own mask
-            for (size_t a = 0; a < again.size(); ++a) {
-                const int j = again[a];
-                B.put(Fin2K{FIN_INIT_RESTART, nb[a], S[j].part, sp.rtol, S[j].ks, masks[a]}, 1u, 0.0);
-            }
-            B.emit(Prestart, init_re, -1);
-        }
-        Prestart.upload(s);
-        Prestart.run(init_re, s);
-        read_all(ks, stage, k, s);
-    }
-    P.run(split, s);
-    GW_HIP(hipStreamSynchronize(s));
-    const double ms = ms_now() - t0;
-    int worst = GW_OK;
-    for (int j = 0; j < nsys; ++j)
-        for (int c = 0; c < 2; ++c) {
-            const int e = 2 * j + c;
-            const KScalars &q1 = kfinal[3 * j + c];
-            if (info) {
-                info[e].iters = q1.iters;
-                info[e].status = status[e];
-                info[e].restarts = restarts[e];
-                info[e].rel_res = q1.bnorm != 0.0 ? std::sqrt(q1.rr) / q1.bnorm : 0.0;
-                info[e].rel_res_true = q1.bnorm != 0.0 ? q1.rel_true : 0.0;
-                info[e].setup_ms = 0.0;
-                info[e].solve_ms = ms;
-            }
-            if (status[e] == GW_BREAKDOWN) worst = GW_BREAKDOWN;
-            else if (status[e] != GW_OK && worst == GW_OK) worst = GW_NOT_CONVERGED;
-        }
-    return worst;
+    return run_batch(1, Hs, b0, b1, x0, x1, nsys, sp, info, s);
 }
 
 }  // namespace gw

@@ -387,8 +387,58 @@ int krylov_pcg(amg_hierarchy *H, const double *b, double *x, const amg_solve_par
 // sides.
 void ensure_krylov_workspace(amg_hierarchy *H, int nvec);
 void ensure_level_vectors(amg_hierarchy *H, int nr);
-// batch.hip: several independent systems in shared launches, each with the
-// iterates of its own solve (info: nsys entries; the pair: 2 nsys).
+// batch.hip: the shared-launch solver.  An engine holds an active set of
+// systems of one kind (0: CG, 1: the BiCGSTAB pair) with the same hierarchy
+// precision, sweep counts and stopping parameters; step() admits the systems
+// that joined, runs one block of iterations of all of them in shared
+// launches, and returns those that finished (each with exactly the result of
+// its own solve).  Vectors stay owned by the caller until their result is
+// returned.
+class BatchEngine {
+   public:
+    struct Result {
+        void *tag;
+        int status;
+        amg_solve_info info[2];
+    };
+    struct Member;
+    struct State;
+    BatchEngine(int kind, const amg_solve_params &sp, int capacity, hipStream_t s);
+    ~BatchEngine();
+    BatchEngine(const BatchEngine &) = delete;
+    BatchEngine &operator=(const BatchEngine &) = delete;
+    bool accepts(const amg_hierarchy *H, const amg_solve_params &sp) const;
+    void join(void *tag, amg_hierarchy *H, const double *b0, const double *b1, double *x0, double *x1);
+    std::vector<Result> step();
+    bool empty() const;
+    int size() const;
+    int kind() const { return kind_; }
+
+   private:
+    int kind_;
+    amg_solve_params sp_;
+    int cap_;
+    hipStream_t s_;
+    int nrec_ = 1, check_ = 4, cnt_ = 4, parity_ = 0;
+    bool dirty_ = true;
+    DBuf<KScalars> ks_;
+    std::unique_ptr<Pinned> stage_;
+    std::vector<int> free_;
+    std::vector<std::unique_ptr<Member>> members_, joining_;
+    std::unique_ptr<State> st_;
+    void read_ks();
+    KScalars *hks(const Member &m);
+    void write_ks(const Member &m);
+    template <class Rec>
+    void run_once(const std::vector<Member *> &ms, Rec &&rec);
+    void admit(std::vector<Member *> &done_now);
+    void first_z(const std::vector<Member *> &ms);
+    void record_iterations();
+    void complete(const std::vector<Member *> &ms, std::vector<Member *> &done_now);
+};
+
+// Several independent systems in shared launches, each with the iterates of
+// its own solve (info: nsys entries; the pair: 2 nsys).
 int krylov_pcg_batch(amg_hierarchy *const *H, const double *const *b, double *const *x, int32_t nsys,
                      const amg_solve_params &sp, amg_solve_info *info, hipStream_t s);
 int krylov_bicgstab2_batch(amg_hierarchy *const *H, const double *const *b0, const double *const *b1,

@@ -11,15 +11,16 @@
 // duration of a request: the travel-time hierarchy serves both right-hand
 // sides.
 //
-// Solves share launches: a slot that reaches a solve (after its setup on
-// its own stream) hands it to the queue's solver thread, which takes every
-// solve of the same kind waiting at that moment (flow CG, or travel-time
-// pairs, with the same precision, sweeps and stopping parameters) and runs
-// them as one batch, one launch per kernel step for all of them
-// (amg_solve_pcg_batch / amg_solve_bicgstab_pair_batch); solves arriving
-// while a batch runs form the next one.  Each system's iterates are those of
-// its solve alone, bit for bit, so a result does not depend on the mix it
-// was served in.  With the setup cache on (queue_set_setup_cache), the flow
+// Solves may share launches (queue_set_batch): a slot that reaches a solve
+// (after its setup on its own stream) then hands it to the queue's solver
+// thread, whose engines (flow CG; travel-time pairs) run the iterations of
+// every solve they hold in shared launches, one launch per kernel step for
+// all of them; a solve joins at the next block of iterations and leaves as
+// soon as it is final.  By default each slot solves on its own stream: with
+// four hardware queues the slots' small kernels already overlap on the
+// device, and the shared launches measured 10-25 % fewer solves/s.  Either
+// way each system's iterates are those of its solve alone, bit for bit, so a
+// result does not depend on the mix it was served in.  With the setup cache on (queue_set_setup_cache), the flow
 // hierarchy outlives its request: a later request with the same conductance
 // field, grid, boundary heads and AMG parameters takes it instead of a new
 // setup, since wells change only the right-hand side (the Discussion's
@@ -188,11 +189,12 @@ struct gw_queue {
     // solves waiting for the solver thread, and its batches
     std::deque<SolveTask *> solves;
     std::condition_variable cv_solve, cv_solved;
-    int max_batch = 16;    // 1: every slot solves on its own stream
+    int max_batch = 1;      // 1: every slot solves on its own stream (measured faster, see DESIGN)
     double window_s = 0.0;  // how long a batch waits for more solves to join
     bool stop_solver = false;
-    std::thread solver;
-    uint64_t n_batches = 0, n_batched = 0;
+    std::vector<std::thread> solvers;  // solver threads, each with its own stream
+    int n_solvers = 0, want_solvers = 1;
+    uint64_t n_batches = 0, n_batched = 0;  // blocks run for two or more solves at once; solves taken
 
     double clock() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void worker();
@@ -416,92 +418,96 @@ int gw_queue::solve(SolveTask &t, hipStream_t s) {
     return t.status;
 }
 
-// The solver thread: takes the oldest waiting solve and every other waiting
-// solve that may share its launches (up to max_batch), runs them as one
-// batch on its own stream, and wakes their slots.
+// A solver thread: one shared-launch engine per kind (flow CG, travel-time
+// pair).  Each round it moves the waiting solves that fit an engine (same
+// parameters as the solves already there, up to max_batch) into it, then
+// runs one block of iterations of every engine that holds solves; a solve
+// leaves as soon as it is final and its slot wakes up, and a solve that
+// arrives meanwhile joins at the next block.  With window_us > 0, an idle
+// solver waits that long for the solves of the other running requests
+// before the first block.
 void gw_queue::solver_loop() {
     hipStream_t s = nullptr;
+    std::unique_ptr<gw::BatchEngine> eng[2];
+    std::vector<SolveTask *> in[2];  // the solves each engine holds
     for (;;) {
-        std::vector<SolveTask *> take;
+        std::vector<SolveTask *> take[2];
+        int cap = 1;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_solve.wait(lk, [&] { return stop_solver || !solves.empty(); });
-            if (solves.empty()) break;  // stop_solver, nothing left
-            const int cap = std::max(1, max_batch);
-            if (window_s > 0.0) {
-                // let solves of other running requests join, up to the window
+            auto busy = [&] { return !in[0].empty() || !in[1].empty(); };
+            cv_solve.wait(lk, [&] { return stop_solver || !solves.empty() || busy(); });
+            if (!busy() && solves.empty()) break;  // stop_solver, nothing left
+            cap = std::max(1, max_batch);
+            if (!busy() && window_s > 0.0) {
                 const auto until = Clock::now() + std::chrono::duration_cast<Clock::duration>(
                                                       std::chrono::duration<double>(window_s));
                 cv_solve.wait_until(lk, until, [&] { return stop_solver || (int)solves.size() >= cap ||
                                                             (int)solves.size() >= running; });
             }
-            SolveTask *first = solves.front();
-            for (auto it = solves.begin(); it != solves.end() && (int)take.size() < cap;) {
-                if (same_batch(**it, *first)) {
-                    take.push_back(*it);
+            for (auto it = solves.begin(); it != solves.end();) {
+                SolveTask *t = *it;
+                const int k = t->kind;
+                const int have = (int)(in[k].size() + take[k].size());
+                bool ok = have < cap;
+                if (ok && have > 0) ok = same_batch(*t, !in[k].empty() ? *in[k][0] : *take[k][0]);
+                if (ok) {
+                    take[k].push_back(t);
                     it = solves.erase(it);
                 } else {
                     ++it;
                 }
             }
-            ++n_batches;
-            n_batched += take.size();
+            n_batched += take[0].size() + take[1].size();
         }
-        const int nsys = (int)take.size();
-        std::vector<amg_solve_info> info((size_t)nsys * 2);
-        std::vector<int> status(nsys, GW_OK);
-        const int st = gw::guarded([&] {
-            if (!s) {
-                GW_HIP(hipSetDevice(device));
-                GW_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-            }
-            std::vector<amg_hierarchy *> H(nsys);
-            std::vector<const double *> b0(nsys), b1(nsys);
-            std::vector<double *> x0(nsys), x1(nsys);
-            for (int j = 0; j < nsys; ++j) {
-                H[j] = take[j]->H;
-                b0[j] = take[j]->b0;
-                b1[j] = take[j]->b1;
-                x0[j] = take[j]->x0;
-                x1[j] = take[j]->x1;
-            }
-            const amg_solve_params &sp = take[0]->sp;
-            if (take[0]->kind == 0) {
-                gw::krylov_pcg_batch(H.data(), b0.data(), x0.data(), nsys, sp, info.data(), s);
-                for (int j = 0; j < nsys; ++j) status[j] = info[j].status;
-            } else {
-                gw::krylov_bicgstab2_batch(H.data(), b0.data(), b1.data(), x0.data(), x1.data(), nsys, sp,
-                                           info.data(), s);
-                for (int j = 0; j < nsys; ++j) {
-                    const int s0 = info[2 * j].status, s1 = info[2 * j + 1].status;
-                    status[j] = (s0 == GW_BREAKDOWN || s1 == GW_BREAKDOWN) ? GW_BREAKDOWN
-                                : (s0 != GW_OK || s1 != GW_OK)           ? GW_NOT_CONVERGED
-                                                                         : GW_OK;
+        for (int k = 0; k < 2; ++k) {
+            if (in[k].empty() && take[k].empty()) continue;
+            std::vector<gw::BatchEngine::Result> res;
+            int active = 0;
+            const int st = gw::guarded([&] {
+                if (!s) {
+                    GW_HIP(hipSetDevice(device));
+                    GW_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
                 }
-            }
-            return GW_OK;
-        });
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (int j = 0; j < nsys; ++j) {
-                SolveTask &t = *take[j];
-                if (st < 0) {
-                    t.status = st;
-                    std::strncpy(t.error, gw_last_error(), sizeof(t.error) - 1);
-                } else {
-                    t.status = status[j];
-                    if (t.kind == 0) {
-                        t.info[0] = info[j];
-                    } else {
-                        t.info[0] = info[2 * j];
-                        t.info[1] = info[2 * j + 1];
+                if (!take[k].empty()) {
+                    if (!eng[k] || eng[k]->empty()) eng[k].reset(new gw::BatchEngine(k, take[k][0]->sp, cap, s));
+                    for (SolveTask *t : take[k]) {
+                        in[k].push_back(t);
+                        eng[k]->join(t, t->H, t->b0, t->b1, t->x0, t->x1);
                     }
                 }
-                t.done = true;
+                active = eng[k]->size();
+                res = eng[k]->step();
+                return GW_OK;
+            });
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                if (st < 0) {
+                    // the engine's solves all fail with the error
+                    for (SolveTask *t : in[k]) {
+                        t->status = st;
+                        std::strncpy(t->error, gw_last_error(), sizeof(t->error) - 1);
+                        t->done = true;
+                    }
+                    in[k].clear();
+                    eng[k].reset();
+                } else {
+                    if (active >= 2) ++n_batches;
+                    for (const auto &r : res) {
+                        SolveTask *t = static_cast<SolveTask *>(r.tag);
+                        t->status = r.status;
+                        t->info[0] = r.info[0];
+                        t->info[1] = r.info[1];
+                        t->done = true;
+                        in[k].erase(std::find(in[k].begin(), in[k].end(), t));
+                    }
+                }
             }
+            if (st < 0 || !res.empty()) cv_solved.notify_all();
         }
-        cv_solved.notify_all();
     }
+    eng[0].reset();
+    eng[1].reset();
     if (s) {
         (void)hipStreamSynchronize(s);
         (void)hipStreamDestroy(s);
@@ -578,7 +584,11 @@ int queue_create(size_t hbm_budget_bytes, int32_t max_slots, gw_queue **q) {
         (void)hipGetLastError();
         Q->device = dev;
         for (int i = 0; i < max_slots; ++i) Q->workers.emplace_back([p = Q.get()] { p->worker(); });
-        Q->solver = std::thread([p = Q.get()] { p->solver_loop(); });
+        {
+            std::lock_guard<std::mutex> lk(Q->mu);
+            for (; Q->n_solvers < Q->want_solvers; ++Q->n_solvers)
+                Q->solvers.emplace_back([p = Q.get()] { p->solver_loop(); });
+        }
         *q = Q.release();
         return GW_OK;
     });
@@ -670,32 +680,37 @@ void queue_destroy(gw_queue *q) {
         q->stop_solver = true;
     }
     q->cv_solve.notify_all();
-    if (q->solver.joinable()) q->solver.join();
+    for (auto &t : q->solvers) t.join();
     for (auto &c : q->cache) amg_free(c.H);
     delete q;
 }
 
-int queue_set_batch(gw_queue *q, int32_t max_batch, double window_us) {
+int queue_set_batch(gw_queue *q, int32_t max_batch, double window_us, int32_t streams) {
     return gw::guarded([&] {
         GW_REQUIRE(q, "queue_set_batch: null queue");
         GW_REQUIRE(max_batch >= 1 && max_batch <= 256, "queue_set_batch: max_batch must be in [1, 256]");
         GW_REQUIRE(window_us >= 0.0 && window_us <= 1e7, "queue_set_batch: window_us must be in [0, 1e7]");
+        GW_REQUIRE(streams >= 1 && streams <= 16, "queue_set_batch: streams must be in [1, 16]");
         {
             std::lock_guard<std::mutex> lk(q->mu);
             q->max_batch = max_batch;
             q->window_s = window_us * 1e-6;
+            q->want_solvers = std::max(q->want_solvers, (int)streams);
+            // more solver threads start now; fewer than running never
+            for (; q->n_solvers < q->want_solvers; ++q->n_solvers)
+                q->solvers.emplace_back([q] { q->solver_loop(); });
         }
         q->cv_solve.notify_all();
         return GW_OK;
     });
 }
 
-int queue_stats(const gw_queue *q, uint64_t *batches, uint64_t *batched_solves) {
+int queue_stats(const gw_queue *q, uint64_t *shared_blocks, uint64_t *solves) {
     return gw::guarded([&] {
         GW_REQUIRE(q, "queue_stats: null queue");
         std::lock_guard<std::mutex> lk(const_cast<gw_queue *>(q)->mu);
-        if (batches) *batches = q->n_batches;
-        if (batched_solves) *batched_solves = q->n_batched;
+        if (shared_blocks) *shared_blocks = q->n_batches;
+        if (solves) *solves = q->n_batched;
         return GW_OK;
     });
 }

@@ -123,6 +123,7 @@ template <int G_, class V>
 struct OpCsr {
     static constexpr int G = G_;
     static constexpr bool kShared = false;  // no block prologue
+    __device__ __host__ static constexpr int lanes() { return G; }
     struct Head {
         int32_t b, e;
         // An empty asm that reads the head: where a kernel returns early,
@@ -150,10 +151,103 @@ struct OpCsr {
     }
 };
 
+// group_row_sum with the lane group a runtime value G (1..64, a power of
+// two): lane l adds entries b+l, b+l+G, ... in order and the group is
+// combined by the same butterfly, with the same number of padding slots as
+// the compile-time form (4 loads a batch for G = 1 or 64, else 8), so every
+// row sum is the compile-time form's bit for bit.
+template <int NR, class V, class F>
+__device__ __forceinline__ VecN<V, NR> group_row_sum_dyn(int32_t b, int32_t e, const int32_t *__restrict__ col,
+                                                         const V *__restrict__ val, int lane, int G, F &&xj) {
+    VecN<V, NR> s;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) s.v[k] = 0;
+    if (b < e) {
+        const int32_t cb = col[b];
+        if (G == 1 || G == 64) {
+            for (int32_t q = b + lane; q < e; q += 4 * G) {
+                V a[4];
+                int32_t c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t p = q + u * G;
+                    const bool in = p < e;
+                    const int32_t pc = in ? p : b;
+                    const V av = val[pc];
+                    const int32_t cv = col[pc];
+                    a[u] = in ? av : V(0);
+                    c[u] = in ? cv : cb;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const VecN<V, NR> xv = xj(c[u]);
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) s.v[k] += a[u] * xv.v[k];
+                }
+            }
+        } else {
+            for (int32_t q = b + lane; q < e; q += 8 * G) {
+                V a[8];
+                int32_t c[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int32_t p = q + u * G;
+                    const bool in = p < e;
+                    const int32_t pc = in ? p : b;
+                    const V av = val[pc];
+                    const int32_t cv = col[pc];
+                    a[u] = in ? av : V(0);
+                    c[u] = in ? cv : cb;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const VecN<V, NR> xv = xj(c[u]);
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) s.v[k] += a[u] * xv.v[k];
+                }
+            }
+        }
+    }
+    for (int o = G / 2; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s.v[k] += __shfl_xor(s.v[k], o, dev::kWave);
+    return s;
+}
+
+// A CSR operator whose lane group is chosen at run time: the systems of a
+// shared launch, whose matrices pick different groups, then take one launch
+// instead of one per group.  Row sums equal OpCsr<g>'s bit for bit.
+template <class V>
+struct OpCsrDyn {
+    static constexpr int G = 0;  // see lanes()
+    static constexpr bool kShared = false;
+    using Head = typename OpCsr<1, V>::Head;
+    const int32_t *rowptr, *col;
+    const V *val;
+    int g;
+    __device__ __host__ int lanes() const { return g; }
+    __device__ __forceinline__ void load(int32_t *) const {}
+    __device__ __forceinline__ Head head(int64_t i) const { return Head{rowptr[i], rowptr[i + 1]}; }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows_at(const Head &h, int64_t, int lane, const int32_t *,
+                                                   F &&xj) const {
+        return group_row_sum_dyn<NR, V>(h.b, h.e, col, val, lane, g, xj);
+    }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows_at<NR>(head(i), i, lane, sd, xj);
+    }
+    template <class F>
+    __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows<1>(i, lane, sd, [&](int32_t j) { return VecN<V, 1>{{(V)xj(j)}}; }).v[0];
+    }
+};
+
 template <class V>
 struct OpSell {
     static constexpr int G = 1;
     static constexpr bool kShared = true;  // the offset dictionary in LDS
+    __device__ __host__ static constexpr int lanes() { return 1; }
     struct Head {
         int32_t off, w;
         __device__ __forceinline__ void keep() const { asm volatile("" ::"v"(off), "v"(w)); }
@@ -223,6 +317,7 @@ template <class B>
 struct OpShift {
     static constexpr int G = B::G;
     static constexpr bool kShared = B::kShared;
+    __device__ __host__ static constexpr int lanes() { return B::lanes(); }
     using Head = typename B::Head;
     B base;
     const double *d;
@@ -294,8 +389,8 @@ __device__ const int32_t kNotDone = 0;
 // in a row.
 #define VROW_PROLOGUE(OP, op, ...)                                                \
     const int64_t gtid = vg_.xcd() * (int64_t)kBlock + threadIdx.x;               \
-    const int64_t row_ = gtid / OP::G;                                            \
-    const int lane = (int)(gtid % OP::G);                                         \
+    const int64_t row_ = gtid / (op).lanes();                                     \
+    const int lane = (int)(gtid % (op).lanes());                                  \
     const bool live_ = row_ < n;                                                  \
     const int32_t stop_ = *(done ? done : &kNotDone);                             \
     const int64_t i = live_ ? row_ : n - 1;                                       \
@@ -530,7 +625,7 @@ __device__ __forceinline__ void kr_init_body(VG vg_, int64_t n, OP op, const dou
                                              double *__restrict__ v, double *partials) {
     OP_PROLOGUE(op)
     double acc[2] = {0.0, 0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         double ax = op.row(i, lane, sd_, [&](int32_t j) { return x[j]; });
         if (lane == 0) {
             double ri = b[i] - ax;
@@ -582,7 +677,7 @@ __device__ __forceinline__ void cg_spmv_body(VG vg_, int64_t n, OP op, const dou
     if (ks->done) return;
     const double beta = ks->beta;
     double acc[1] = {0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         double s = op.row(i, lane, sd_, [&](int32_t j) { return z[j] + beta * p_old[j]; });
         if (lane == 0) {
             double pi = z[i] + beta * p_old[i];
@@ -633,7 +728,7 @@ __device__ __forceinline__ void true_res_body(VG vg_, int64_t n, OP op, const do
                                               const double *__restrict__ x, double *partials) {
     OP_PROLOGUE(op)
     double acc[1] = {0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         double ax = op.row(i, lane, sd_, [&](int32_t j) { return x[j]; });
         if (lane == 0) {
             double ri = b[i] - ax;
@@ -667,7 +762,7 @@ __device__ __forceinline__ void bcg_v_body(VG vg_, int64_t n, OP op, const doubl
     OP_PROLOGUE(op)
     if (ks->done) return;
     double acc[1] = {0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         double vi = op.row(i, lane, sd_, [&](int32_t j) { return ph[j]; });
         if (lane == 0) {
             v[i] = vi;
@@ -700,7 +795,7 @@ __device__ __forceinline__ void bcg_t_body(VG vg_, int64_t n, OP op, const doubl
     OP_PROLOGUE(op)
     if (ks->done) return;
     double acc[2] = {0.0, 0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         double ti = op.row(i, lane, sd_, [&](int32_t j) { return sh[j]; });
         if (lane == 0) {
             t[i] = ti;
@@ -923,7 +1018,7 @@ __device__ __forceinline__ void kr_init2_body(VG vg_, int64_t n, OP op, const do
                                               double *__restrict__ v, double *partials, int mask) {
     OP_PROLOGUE(op)
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         const VecN<double, 2> ax = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(x, j); });
         if (lane == 0) {
 #pragma unroll
@@ -979,7 +1074,7 @@ __device__ __forceinline__ void bcg_v2_body(VG vg_, int64_t n, OP op, const doub
     OP_PROLOGUE(op)
     if (ks[2].done) return;
     double acc[2] = {0.0, 0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         const VecN<double, 2> vi = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(ph, j); });
         if (lane == 0) {
             store_n<double, 2>(v, i, vi);
@@ -1039,7 +1134,7 @@ __device__ __forceinline__ void bcg_t2_body(VG vg_, int64_t n, OP op, const doub
     OP_PROLOGUE(op)
     if (ks[2].done) return;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         const VecN<double, 2> ti = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(sh, j); });
         if (lane == 0) {
             store_n<double, 2>(t, i, ti);
@@ -1112,7 +1207,7 @@ __device__ __forceinline__ void true_res2_body(VG vg_, int64_t n, OP op, const d
                                                const double *__restrict__ x, double *partials) {
     OP_PROLOGUE(op)
     double acc[2] = {0.0, 0.0};
-    GROUP_LOOP(OP::G, i, lane, n) {
+    GROUP_LOOP(op.lanes(), i, lane, n) {
         const VecN<double, 2> ax = op.template rows<2>(i, lane, sd_, [&](int32_t j) { return load_n<double, 2>(x, j); });
         if (lane == 0) {
 #pragma unroll
@@ -1175,12 +1270,11 @@ struct Seg {
     uint32_t blk0, nb;
 };
 
+// `sid` maps each block of the launch to its record (one load, then the
+// record's fields).
 template <class A>
-__global__ void __launch_bounds__(kBlock) k_seg(const Seg<A> *__restrict__ t, int nseg) {
-    int j = 0;
-    for (int k = 1; k < nseg; ++k)
-        if (t[k].blk0 <= blockIdx.x) j = k;
-    const Seg<A> &sg = t[j];
+__global__ void __launch_bounds__(kBlock) k_seg(const Seg<A> *__restrict__ t, const uint16_t *__restrict__ sid) {
+    const Seg<A> &sg = t[sid[blockIdx.x]];
     sg.a.run(VG{(int64_t)blockIdx.x - (int64_t)sg.blk0, (int64_t)sg.nb});
 }
 

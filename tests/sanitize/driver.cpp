@@ -36,8 +36,8 @@ int main() {
     gw_queue *q = nullptr;
     CHECK(queue_create(0, 4, &q) == GW_EINVAL);
     CHECK(queue_create((size_t)8 << 30, 4, &q) == GW_OK && q);
-    CHECK(queue_set_batch(q, 0, 0.0) == GW_EINVAL);
-    CHECK(queue_set_batch(q, 8, 200.0) == GW_OK);
+    CHECK(queue_set_batch(q, 0, 0.0, 1) == GW_EINVAL);
+    CHECK(queue_set_batch(q, 8, 200.0, 3) == GW_OK);
     CHECK(queue_set_setup_cache(q, 65) == GW_EINVAL);
     CHECK(queue_set_setup_cache(q, 2) == GW_OK);
 

@@ -130,9 +130,9 @@ def test_shared_launches_equal_own_streams():
     st = []
     shared = _serve(probs, slots=4, batch=16, window_us=5e5, stats=st)
     own = _serve(probs, slots=4, batch=1)
-    batches, solves = st
-    print(f"  {batches} batches held {solves} solves", flush=True)
-    assert solves == 2 * len(probs) and batches < solves
+    shared_blocks, solves = st
+    print(f"  {solves} solves, {shared_blocks} blocks of iterations shared by two or more", flush=True)
+    assert solves == 2 * len(probs) and shared_blocks > 0
     for (ra, oa), (rb, ob) in zip(shared, own):
         assert ra.status == gw.OK and rb.status == gw.OK, (ra.error, rb.error)
         for k in ("h", "tau", "c"):
@@ -186,12 +186,12 @@ def test_admission_by_budget():
 @needs_lib
 def test_batch_argument_checks_cpu():
     q = gw.Queue(hbm_budget_bytes=1 << 30, max_slots=1)
-    for bad in ((0, 0.0), (257, 0.0), (4, -1.0)):
+    for bad in ((0, 0.0), (257, 0.0), (4, -1.0), (4, 0.0, 0), (4, 0.0, 17)):
         with pytest.raises(gw.GwError) as e:
             q.set_batch(*bad)
         assert e.value.status == gw.EINVAL
     q.set_batch(1)
-    q.set_batch(8, 100.0)
+    q.set_batch(8, 100.0, 4)
     assert q.stats() == (0, 0)
     q.close()
 
