@@ -146,6 +146,11 @@ typedef struct {
     int32_t mis_rounds;   /* MIS-2 rounds                                  */
     double omega_p;       /* prolongator smoothing weight                  */
     size_t bytes;         /* device bytes held for this level              */
+    int32_t slice_rows;   /* rows per slice of the sliced copy the solve
+                             kernels read (64, 32, 16 or 8), 0: none       */
+    int64_t nnz_sliced;   /* entries the sliced copy stores, padding
+                             included (each slice as wide as its longest
+                             row)                                          */
 } amg_level_info;
 
 typedef struct amg_hierarchy amg_hierarchy;

@@ -83,7 +83,7 @@ class StepInfoC(C.Structure):
 class LevelInfoC(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nc", C.c_int32), ("nnz_p", C.c_int64),
                 ("nnz_s", C.c_int64), ("mis_rounds", C.c_int32), ("omega_p", C.c_double),
-                ("bytes", C.c_size_t)]
+                ("bytes", C.c_size_t), ("slice_rows", C.c_int32), ("nnz_sliced", C.c_int64)]
 
 
 class KernelStatC(C.Structure):
@@ -415,6 +415,8 @@ class LevelInfo:
     mis_rounds: int
     omega_p: float
     bytes: int
+    slice_rows: int = 0
+    nnz_sliced: int = 0
 
 
 class Hierarchy:
@@ -442,8 +444,8 @@ class Hierarchy:
         nl, nb = C.c_int32(0), C.c_size_t(0)
         _check(_lib.amg_hierarchy_info(self._h, arr, 32, C.byref(nl), C.byref(nb)))
         k = max(1, nl.value)
-        return ([LevelInfo(a.n, a.nnz, a.nc, a.nnz_p, a.nnz_s, a.mis_rounds, a.omega_p, a.bytes)
-                 for a in arr[:k]], int(nb.value))
+        return ([LevelInfo(a.n, a.nnz, a.nc, a.nnz_p, a.nnz_s, a.mis_rounds, a.omega_p, a.bytes, a.slice_rows,
+                           a.nnz_sliced) for a in arr[:k]], int(nb.value))
 
     @property
     def nlevels(self) -> int:

@@ -188,16 +188,20 @@ struct CsrView {
 };
 inline CsrView view(const Csr &A) { return {A.n, A.ncols, A.nnz, A.rowptr.p, A.col.p, A.val.p}; }
 
-// Sliced ELL copy of an operator for the solve phase: slices of 64 rows (one
-// wave), entries column-major inside a slice so lane l of a wave reads
-// consecutive addresses; short rows are padded with zero values pointing at
-// the row itself.  When the operator has at most 255 distinct offsets
+// Sliced ELL copy of an operator for the solve phase: slices of C rows (C =
+// 64, one wave, or 32, 16 or 8, chosen per operator), entries column-major
+// inside a slice so the lanes of a slice read consecutive addresses; short
+// rows are padded with zero values pointing at the row itself.  Each slice is
+// as wide as its longest row, so operators whose row lengths vary from row to
+// row (the upwind travel-time operator: 1 to 7 entries) take shorter slices,
+// which pad less.  When the operator has at most 255 distinct offsets
 // (col - row), as stencil matrices do, each column is stored as a one-byte
 // index into a small dictionary of offsets; otherwise as an int32 column.
-constexpr int kSellC = 64;
+constexpr int kSellMaxC = 64, kSellMinC = 8;
 constexpr int kSellMaxDict = 255;
 struct Sell {
     int32_t n = 0, nslices = 0;
+    int32_t cshift = 6;          // slice height C = 1 << cshift
     int64_t nnz_padded = 0;
     int32_t ndict = 0;           // 0: int32 columns, else dictionary size
     DBuf<int32_t> soff;          // nslices + 1, entry offset of each slice
@@ -213,13 +217,13 @@ struct Sell {
 };
 
 struct SellView {
-    int32_t n, ndict;
+    int32_t n, ndict, cshift;
     const int32_t *soff;
     const uint8_t *idx;
     const int32_t *col;
     const int32_t *dict;
 };
-inline SellView view(const Sell &S) { return {S.n, S.ndict, S.soff.p, S.idx.p, S.col.p, S.dict.p}; }
+inline SellView view(const Sell &S) { return {S.n, S.ndict, S.cshift, S.soff.p, S.idx.p, S.col.p, S.dict.p}; }
 
 // ------------------------------------------------------------ hierarchy --
 // Level-synchronous schedule of a triangular (more generally acyclic) system

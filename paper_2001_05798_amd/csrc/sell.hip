@@ -1,13 +1,16 @@
 // Sliced ELL layout of the level-0 operator for the solve phase.
 //
-// One slice = 64 consecutive rows = one wave; inside a slice the k-th
-// entries of all 64 rows are stored next to each other, so a wave's load of
-// values or column indices is a single contiguous 512 B (FP64) or 256 B
-// (FP32) run.  A row keeps its CSR entry order; rows shorter than the slice
-// width are padded with a zero value at the row's own column.  Stencil
-// operators have a handful of distinct offsets col - row: those columns are
-// stored as one-byte indices into a sorted offset dictionary (9 B per entry in
-// FP64, 5 B in FP32, instead of 12 / 8 with int32 columns).
+// One slice = C consecutive rows (C = 64, one wave, or 32, 16, 8); inside a
+// slice the k-th entries of all C rows are stored next to each other, so the
+// lanes of a slice load values or column indices from one contiguous run.  A
+// row keeps its CSR entry order; rows shorter than the slice width are padded
+// with a zero value at the row's own column.  C is the largest height whose
+// padded entry count is within 2 % of the count at C = 8: stencil operators
+// (rows of equal length) keep whole-wave slices, the upwind travel-time
+// operator (rows of 1 to 7 entries) takes short ones.  Stencil operators
+// have a handful of distinct offsets col - row: those columns are stored as
+// one-byte indices into a sorted offset dictionary (9 B per entry in FP64, 5
+// B in FP32, instead of 12 / 8 with int32 columns).
 #include <algorithm>
 #include <cstring>
 
@@ -22,11 +25,41 @@ constexpr int kOffsetTable = 4096;  // open-addressing set of offsets (device)
 constexpr int kBlockTable = 512;    // per-block set in LDS
 constexpr int32_t kEmpty = INT32_MIN;
 
-__global__ void k_sell_width(const int32_t *__restrict__ rowptr, int32_t n, int32_t *__restrict__ width) {
+// Padded entry totals at slice heights 8, 16, 32 and 64 (totals[0..3]): a
+// slice is as wide as its longest row.  Grid-stride over whole waves, so the
+// group maxima below always see full waves; the grid is capped, and each
+// block adds its four sums with one integer atomic each.
+__global__ void __launch_bounds__(kBlock) k_sell_pad(const int32_t *__restrict__ rowptr, int32_t n,
+                                                      unsigned long long *__restrict__ totals) {
+    __shared__ unsigned long long sm[kBlock / dev::kWave];
+    const int lane = threadIdx.x & (dev::kWave - 1);
+    unsigned long long t[4] = {0, 0, 0, 0};
+    for (int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; row - lane < n;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        int32_t m = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) m = max(m, __shfl_xor(m, o, dev::kWave));
+        if ((lane & 7) == 0) t[0] += (unsigned long long)m * 8;
+#pragma unroll
+        for (int c = 1; c < 4; ++c) {
+            m = max(m, __shfl_xor(m, 4 << c, dev::kWave));
+            if ((lane & ((8 << c) - 1)) == 0) t[c] += (unsigned long long)m * (8u << c);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const unsigned long long b = dev::block_sum(t[c], sm);
+        if (threadIdx.x == 0 && b) atomicAdd(&totals[c], b);
+    }
+}
+
+// Slice widths (entries per slice, at slice s + 1) at slice height 1 << cshift.
+__global__ void k_sell_width(const int32_t *__restrict__ rowptr, int32_t n, int cshift, int32_t *__restrict__ width) {
     const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int C = 1 << cshift;
     int32_t len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
-    len = dev::wave_max(len);
-    if ((threadIdx.x & (kSellC - 1)) == 0 && row < n) width[row / kSellC + 1] = len * kSellC;
+    for (int o = 1; o < C; o <<= 1) len = max(len, __shfl_xor(len, o, dev::kWave));
+    if ((threadIdx.x & (C - 1)) == 0 && row < n) width[(row >> cshift) + 1] = len << cshift;
 }
 
 __device__ __forceinline__ uint32_t offset_hash(int32_t d) { return ((uint32_t)d * 2654435761u) >> 16; }
@@ -80,12 +113,13 @@ __global__ void __launch_bounds__(kBlock) k_offset_set(const int32_t *__restrict
     }
 }
 
-// One block: the set's entries in ascending order into meta[4 + k] and their
-// count into meta[1] (meta[0] is the overflow flag; a count above
-// kSellMaxDict is reported as such and nothing is written).  The padded entry
-// total is copied next to them so one small read returns everything.
+// One block: the set's entries in ascending order into meta[kMetaDict + k]
+// and their count into meta[1] (meta[0] is the overflow flag; a count above
+// kSellMaxDict is reported as such and nothing is written).  The four padded
+// entry totals are copied next to them so one small read returns everything.
+constexpr int kMetaDict = 10;
 __global__ void __launch_bounds__(1024) k_offset_compact(const int32_t *__restrict__ table, int32_t *meta,
-                                                         const int64_t *__restrict__ total) {
+                                                         const unsigned long long *__restrict__ totals) {
     __shared__ int32_t keys[kOffsetTable];
     __shared__ int32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
@@ -96,16 +130,14 @@ __global__ void __launch_bounds__(1024) k_offset_compact(const int32_t *__restri
     }
     __syncthreads();
     const int m = cnt;
-    if (threadIdx.x == 0) {
-        meta[1] = m;
-        reinterpret_cast<int64_t *>(meta)[1] = *total;
-    }
+    if (threadIdx.x == 0) meta[1] = m;
+    if (threadIdx.x < 4) reinterpret_cast<unsigned long long *>(meta)[1 + threadIdx.x] = totals[threadIdx.x];
     if (m > kSellMaxDict) return;
     for (int t = threadIdx.x; t < m; t += blockDim.x) {
         const int32_t d = keys[t];
         int rank = 0;
         for (int u = 0; u < m; ++u) rank += keys[u] < d;
-        meta[4 + rank] = d;
+        meta[kMetaDict + rank] = d;
     }
 }
 
@@ -120,7 +152,7 @@ __device__ __forceinline__ int32_t dict_index(const int32_t *dict, int32_t ndict
 }
 
 // Thread per row: write the row's entries column-major into its slice.
-__global__ void k_sell_fill(CsrView A, const int32_t *__restrict__ soff, const int32_t *__restrict__ dict,
+__global__ void k_sell_fill(CsrView A, int cshift, const int32_t *__restrict__ soff, const int32_t *__restrict__ dict,
                             int32_t ndict, uint8_t *__restrict__ idx, int32_t *__restrict__ cols,
                             double *__restrict__ val, float *__restrict__ val32) {
     __shared__ int32_t sdict[kSellMaxDict + 1];
@@ -128,13 +160,13 @@ __global__ void k_sell_fill(CsrView A, const int32_t *__restrict__ soff, const i
     __syncthreads();
     const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (row >= A.n) return;
-    const int64_t s = row / kSellC;
-    const int l = (int)(row % kSellC);
-    const int32_t off = soff[s], w = (soff[s + 1] - off) / kSellC;
+    const int64_t s = row >> cshift;
+    const int l = (int)(row & ((1 << cshift) - 1));
+    const int32_t off = soff[s], w = (soff[s + 1] - off) >> cshift;
     const int32_t b = A.rowptr[row], len = A.rowptr[row + 1] - b;
     const int32_t self = ndict ? dict_index(sdict, ndict, 0) : 0;
     for (int32_t k = 0; k < w; ++k) {
-        const int64_t e = off + (int64_t)k * kSellC + l;
+        const int64_t e = off + ((int64_t)k << cshift) + l;
         double v = 0.0;
         int32_t c = (int32_t)row;
         if (k < len) {
@@ -155,45 +187,59 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
     const CsrView A = view(Lv.A);
     Sell &S = Lv.As;
     S = Sell();
-    const int32_t nslices = (A.n + kSellC - 1) / kSellC;
-    // meta: [0] overflow, [1] count, [2..3] padded total (int64), [4..] offsets
-    constexpr int kMeta = 4 + kSellMaxDict;
+    // meta: [0] overflow, [1] count, [2..9] padded totals at C = 8..64
+    // (int64), [kMetaDict..] offsets
+    constexpr int kMeta = kMetaDict + kSellMaxDict;
     static_assert(kMeta * sizeof(int32_t) <= kHostStageBytes, "offset dictionary must fit the pinned stage");
     ProfScope ps(K_SELL_BUILD, 0.0, s);
-    DBuf<int32_t> soff((size_t)nslices + 1);
-    DBuf<int64_t> total(1);
+    DBuf<unsigned long long> totals(4);
     DBuf<int32_t> table(kOffsetTable);
     DBuf<int32_t> meta(kMeta);
-    fill_i32(soff.p, 0, 1, s);
+    fill_i32(reinterpret_cast<int32_t *>(totals.p), 0, 8, s);
     fill_i32(table.p, kEmpty, kOffsetTable, s);
     fill_i32(meta.p, 0, kMeta, s);
-    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.n, soff.p);
-    scan_inclusive_i32(soff.p + 1, nslices, total.p, s);
+    hipLaunchKernelGGL(k_sell_pad, dim3(std::min<unsigned>(blocks_for(A.n), 1024)), dim3(kBlock), 0, s, A.rowptr,
+                       A.n, totals.p);
     hipLaunchKernelGGL(k_offset_set, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.col, A.n, table.p,
                        meta.p);
-    hipLaunchKernelGGL(k_offset_compact, dim3(1), dim3(1024), 0, s, table.p, meta.p, total.p);
+    hipLaunchKernelGGL(k_offset_compact, dim3(1), dim3(1024), 0, s, table.p, meta.p, totals.p);
     GW_HIP(hipGetLastError());
     int32_t *stage = static_cast<int32_t *>(host_stage());
     GW_HIP(hipMemcpyAsync(stage, meta.p, sizeof(int32_t) * kMeta, hipMemcpyDeviceToHost, s));
     GW_HIP(hipStreamSynchronize(s));
     const bool overflow = stage[0] != 0;
     const int32_t count = stage[1];
-    int64_t padded = 0;
-    std::memcpy(&padded, stage + 2, sizeof(int64_t));
+    int64_t pad[4];
+    std::memcpy(pad, stage + 2, sizeof(pad));
+    // the tallest slices whose padding stays within 2 % of the shortest's
+    int cshift = 3;
+    for (int c = 3; c >= 1; --c)
+        if ((double)pad[c] <= 1.02 * (double)pad[0]) {
+            cshift = 3 + c;
+            break;
+        }
+    const int64_t padded = pad[cshift - 3];
     // Rows of very uneven length would pad the copy far beyond the CSR
     // operator: keep the CSR kernels then (also past int32 entry offsets).
-    if (padded >= INT32_MAX || (double)padded > 1.5 * (double)A.nnz + kSellC) return;
+    if (padded >= INT32_MAX || (double)padded > 1.5 * (double)A.nnz + kSellMaxC) return;
     bool use_dict = !overflow && count <= kSellMaxDict && count > 0;
-    if (use_dict) use_dict = std::binary_search(stage + 4, stage + 4 + count, 0);
+    if (use_dict) use_dict = std::binary_search(stage + kMetaDict, stage + kMetaDict + count, 0);
+    const int32_t nslices = (int32_t)(((int64_t)A.n + (1 << cshift) - 1) >> cshift);
+    DBuf<int32_t> soff((size_t)nslices + 1);
+    DBuf<int64_t> total(1);
+    fill_i32(soff.p, 0, 1, s);
+    hipLaunchKernelGGL(k_sell_width, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.n, cshift, soff.p);
+    scan_inclusive_i32(soff.p + 1, nslices, total.p, s);
     S.n = A.n;
     S.nslices = nslices;
+    S.cshift = cshift;
     S.nnz_padded = padded;
     S.soff = std::move(soff);
     const size_t np = (size_t)std::max<int64_t>(padded, 1);
     if (use_dict) {
         S.ndict = count;
         S.dict.alloc((size_t)count);
-        copy_bytes(S.dict.p, meta.p + 4, sizeof(int32_t) * (size_t)count, s);
+        copy_bytes(S.dict.p, meta.p + kMetaDict, sizeof(int32_t) * (size_t)count, s);
         S.idx.alloc(np);
     } else {
         S.ndict = 0;
@@ -201,12 +247,12 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
     }
     S.val.alloc(np);
     if (fp32) S.val32.alloc(np);
-    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, S.soff.p, S.dict.p, S.ndict,
-                       S.idx.p, S.col.p, S.val.p, S.val32.p);
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, cshift, S.soff.p, S.dict.p,
+                       S.ndict, S.idx.p, S.col.p, S.val.p, S.val32.p);
     GW_HIP(hipGetLastError());
-    // the widths (row pointers), the offset set (row pointers and columns),
-    // the fill (the CSR read, the copy written)
-    ps.bytes = 4.0 * (A.n + 1) * 3 + 4.0 * (double)A.nnz + 12.0 * (double)A.nnz +
+    // the padded totals and the widths (row pointers, twice), the offset set
+    // (row pointers and columns), the fill (the CSR read, the copy written)
+    ps.bytes = 4.0 * (A.n + 1) * 4 + 4.0 * (double)A.nnz + 12.0 * (double)A.nnz +
                (double)padded * (8 + (S.ndict ? 1 : 4) + (fp32 ? 4 : 0)) + 4.0 * (nslices + 1);
     ps.cbytes = ps.bytes;
 }

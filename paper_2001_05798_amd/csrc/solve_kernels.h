@@ -258,18 +258,18 @@ struct OpSell {
         for (int t = threadIdx.x; t < S.ndict; t += blockDim.x) sd[t] = S.dict[t];
     }
     __device__ __forceinline__ Head head(int64_t i) const {
-        const int64_t sl = i / kSellC;
+        const int64_t sl = i >> S.cshift;
         const int32_t off = S.soff[sl];
-        return Head{off, (S.soff[sl + 1] - off) / kSellC};
+        return Head{off, (S.soff[sl + 1] - off) >> S.cshift};
     }
-    // Entries k of row i sit at soff[slice] + k*64 + (i mod 64).  Eight
+    // Entries k of row i sit at soff[slice] + k*C + (i mod C).  Eight
     // entries are loaded before their products are summed, so the gathers
     // of x overlap; the sum still runs in entry order.  Slots past the slice
     // width re-read the last entry and are replaced by the padding entry
     // (value 0 at the row's own column) in registers, without branches.
     template <bool DICT, int NR, class F>
     __device__ __forceinline__ VecN<V, NR> row_impl(const Head &h, int64_t i, const int32_t *sd, F &&xj) const {
-        const int l = (int)(i % kSellC);
+        const int l = (int)(i & ((1 << S.cshift) - 1));
         const int32_t off = h.off, w = h.w;
         VecN<V, NR> acc;
 #pragma unroll
@@ -280,7 +280,7 @@ struct OpSell {
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int32_t k = min(k0 + u, w - 1);
-                const int64_t e = off + (int64_t)k * kSellC + l;
+                const int64_t e = off + ((int64_t)k << S.cshift) + l;
                 const V av = val[e];
                 const int32_t cv = DICT ? (int32_t)i + sd[S.idx[e]] : S.col[e];
                 const bool in = k0 + u < w;

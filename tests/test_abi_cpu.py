@@ -113,3 +113,21 @@ def test_amg_params_layout_and_validation():
     prm = Params(0.25, 3, 2.0 / 3.0, 2, 2, 500, 20, 1, 0x5EED, 1)   # ILU0 with the FP32 hierarchy
     assert lib.amg_setup(ctypes.byref(A), ctypes.byref(prm), ctypes.byref(h), None) == -1
     assert b"ILU(0)" in lib.gw_last_error()
+
+
+@pytest.mark.parametrize("struct,cls,field", [
+    ("amg_level_info", "LevelInfoC", "nnz_sliced"),
+    ("amg_solve_params", "SolveParamsC", None),
+    ("amg_solve_info", "SolveInfoC", None),
+    ("gw_kernel_stat", "KernelStatC", "bytes_csr"),
+    ("gw_result", "ResultC", "bytes_used"),
+])
+def test_struct_layouts_match_header(struct, cls, field):
+    # the binding's ctypes records against the header as the C compiler lays
+    # it out: size, and the offset of the last field added
+    import paper_2001_05798_amd as gw
+    c = getattr(gw, cls)
+    last = field or c._fields_[-1][0]
+    size, off = _c_layout(struct, last)
+    assert ctypes.sizeof(c) == size
+    assert getattr(c, last).offset == off

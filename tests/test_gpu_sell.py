@@ -1,0 +1,99 @@
+"""The sliced copy of the level-0 operator: its slice height and stored entry
+count against a count made on the host from the operator's row lengths (each
+slice of C rows as wide as its longest row; C the largest of 64, 32, 16, 8
+whose count is within 2 % of the count at 8), for the 7-point flow operator
+and the upwind travel-time operator (rows of 1 to 7 entries, short slices);
+and the travel-time pair solved on short slices against the oracle's exact
+sweep.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gwinputs as gi
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_05798_amd as gw
+    return gw
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _padded(rowptr, c):
+    lens = np.diff(np.asarray(rowptr, dtype=np.int64))
+    return int(np.pad(lens, (0, (-lens.size) % c)).reshape(-1, c).max(axis=1).sum()) * c
+
+
+def _expected(rowptr):
+    pad = {c: _padded(rowptr, c) for c in (8, 16, 32, 64)}
+    for c in (64, 32, 16):
+        if pad[c] <= 1.02 * pad[8]:
+            return c, pad[c]
+    return 8, pad[8]
+
+
+def _tt_operator(ref, nx, ny, nz, s2, lam, seed):
+    p = gi.heterogeneous_aquifer(nx, ny, nz, s2, lam, seed)
+    fr = ref.solve_flow(p, ref.AmgParams(), rtol=1e-10)
+    qx, qy, qz = ref.darcy_flux(p, fr.h)
+    g = p.grid
+    A, bt, bc, _ = ref.tt_assemble(g, qx, qy, qz, p.phi, (0, g.ny, 0, max(1, g.nz // 2)))
+    return p, fr.h, A, bt, bc
+
+
+@pytest.mark.parametrize("case", [(48, 40, 20, 4.0, 6, 61), (37, 29, 11, 1.0, 3, 62)], ids=["48x40x20", "37x29x11"])
+def test_slice_height_and_padding(gw, ref, case):
+    _say(f"sliced copy {case}")
+    p, _, A, bt, bc = _tt_operator(ref, *case)
+    n = p.grid.n
+    for name, (rowptr, col, val), prm in (
+            ("flow", _flow_csr(ref, p), gw.AmgParams.flow()),
+            ("travel time", (A.rowptr, A.col, A.val), gw.AmgParams.travel_time())):
+        H = gw.amg_setup(n, dev(rowptr), dev(col), dev(val), prm)
+        lv = H.info()[0][0]
+        c, padded = _expected(rowptr)
+        _say(f"  {name}: slice rows {lv.slice_rows} (host {c}), entries {lv.nnz_sliced} (host {padded}), "
+             f"nnz {int(rowptr[-1])}")
+        assert (lv.slice_rows, lv.nnz_sliced) == (c, padded)
+        if name == "travel time":  # short slices pad less than whole-wave ones
+            assert c < 64 and padded < 0.95 * _padded(rowptr, 64)
+
+
+def _flow_csr(ref, p):
+    A, _ = ref.fv_assemble(p)
+    return A.rowptr, A.col, A.val
+
+
+def test_pair_on_short_slices_against_oracle(gw, ref):
+    # the upwind system is acyclic: the oracle's sweep in head order gives
+    # its exact solution
+    _say("travel-time pair on short slices vs the oracle's exact sweep")
+    p, h, A, bt, bc = _tt_operator(ref, 48, 40, 20, 4.0, 6, 61)
+    n = p.grid.n
+    H = gw.amg_setup(n, dev(A.rowptr), dev(A.col), dev(A.val), gw.AmgParams.travel_time())
+    assert H.info()[0][0].slice_rows < 64
+    x0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, (i0, i1) = gw.amg_solve_bicgstab_pair(H, dev(bt), dev(bc), x0, x1, gw.SolveParams(rtol=1e-10))
+    assert st == gw.OK
+    for got, b in ((x0, bt), (x1, bc)):
+        want = ref.tt_sweep(A, b, h)
+        err = np.linalg.norm(got.cpu().numpy() - want) / np.linalg.norm(want)
+        _say(f"  iters {i0.iters}/{i1.iters}, rel err {err:.2e}")
+        assert err <= 1e-8
