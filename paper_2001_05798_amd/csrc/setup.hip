@@ -112,6 +112,182 @@ __global__ void k_tr_sort(const int32_t *__restrict__ trow, const int32_t *__res
     oval[b + rank] = tval[e];
 }
 
+// Transpose by a stable least-significant-digit radix sort of the entries on
+// their column.  The entries enter in row order (row i ascending, columns
+// ascending within a row), so after a stable sort on the column every row
+// of A^T holds its entries in ascending row index: the one CSR of A^T, the
+// same as the count / fill / rank path above, without same-address atomics.
+// A pass handles tiles of kRxTile entries: a histogram of the pass's digit
+// per tile, an exclusive scan of the counts in digit-major order (so the
+// offset of (digit, tile) is where that tile's entries of that digit start),
+// then a scatter in which each entry's place among the tile's entries of its
+// digit is its rank in entry order (ballots over the lanes of the wave
+// holding the same digit, then the counts of the earlier waves).
+constexpr int kRxItems = 16;
+constexpr int kRxTile = kBlock * kRxItems;
+constexpr int kRxWaves = kBlock / dev::kWave;
+// Digits of at most 9 bits: with more buckets a 4096-entry tile leaves runs
+// of about 4 entries per bucket, whose partial-line writes cost more than a
+// third pass (1M-column operator: 88 us a pass at 10 bits).
+constexpr int kRxMaxBits = 9;
+
+// Row of every entry of A (the row order that the sort keeps).
+template <int G>
+__global__ void k_rx_rowid(CsrView A, int32_t *__restrict__ rowid) {
+    const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = gtid / G;
+    const int lane = (int)(gtid % G);
+    if (i >= A.n) return;
+    const int32_t e = A.rowptr[i + 1];
+    for (int32_t p = A.rowptr[i] + lane; p < e; p += G) rowid[p] = (int32_t)i;
+}
+
+// cnt[1 + d * ntiles + t] = entries of tile t whose digit is d.
+__global__ void __launch_bounds__(kBlock) k_rx_hist(const int32_t *__restrict__ key, int64_t nnz, int shift,
+                                                    int bits, int32_t *__restrict__ cnt, int64_t ntiles) {
+    __shared__ int32_t h[1 << kRxMaxBits];
+    const int nd = 1 << bits;
+    for (int d = threadIdx.x; d < nd; d += kBlock) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRxTile;
+    const uint32_t mask = (uint32_t)nd - 1u;
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u) {
+        const int64_t e = base + (int64_t)u * kBlock + threadIdx.x;
+        if (e < nnz) atomicAdd(&h[((uint32_t)key[e] >> shift) & mask], 1);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < nd; d += kBlock) cnt[1 + (int64_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+// One stable pass.  Wave w of the tile takes entries [w*64*kRxItems, ...)
+// of it, 64 consecutive ones at a time, so the entry order is (wave, step,
+// lane).  off[d * ntiles + t] holds the scanned offsets (exclusive).  The
+// tile is first laid out in LDS in its sorted order (slot = the tile's
+// entries of smaller digits, then of the same digit earlier in entry order),
+// and written from there by consecutive threads, so that the stores of a
+// wave cover runs of consecutive addresses.
+__global__ void __launch_bounds__(kBlock) k_rx_scatter(const int32_t *__restrict__ kin,
+                                                       const int32_t *__restrict__ rin,
+                                                       const double *__restrict__ vin, int64_t nnz, int shift,
+                                                       int bits, const int32_t *__restrict__ off, int64_t ntiles,
+                                                       int32_t *__restrict__ kout, int32_t *__restrict__ rout,
+                                                       double *__restrict__ vout) {
+    __shared__ int32_t c[kRxWaves][1 << kRxMaxBits];
+    __shared__ int32_t gofs[1 << kRxMaxBits];
+    __shared__ int32_t wsum[kRxWaves];
+    __shared__ int64_t stage[kRxTile];  // (key, row) pairs, then values
+    const int nd = 1 << bits;
+    const uint32_t mask = (uint32_t)nd - 1u;
+    for (int d = threadIdx.x; d < nd; d += kBlock)
+#pragma unroll
+        for (int w = 0; w < kRxWaves; ++w) c[w][d] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & (dev::kWave - 1), w = threadIdx.x / dev::kWave;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t tile0 = (int64_t)blockIdx.x * kRxTile;
+    const int64_t base = tile0 + (int64_t)w * dev::kWave * kRxItems;
+    const int32_t tcount = (int32_t)min<int64_t>(kRxTile, nnz - tile0);
+    int32_t kk[kRxItems], rr[kRxItems], pos[kRxItems];
+    double vv[kRxItems];
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u) {
+        const int64_t e = base + (int64_t)u * dev::kWave + lane;
+        const bool in = e < nnz;
+        const int64_t es = in ? e : 0;
+        kk[u] = kin[es];
+        rr[u] = rin[es];
+        vv[u] = vin[es];
+        if (!in) kk[u] = -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u) {
+        const bool in = kk[u] >= 0;
+        const uint32_t d = ((uint32_t)kk[u] >> shift) & mask;
+        uint64_t peers = __ballot(in);
+        for (int b = 0; b < bits; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        int32_t before = 0;
+        if (in) before = c[w][d];
+        const int rank = __popcll(peers & lt);
+        // the lowest lane of each digit's peers advances that digit's count
+        // (one writer per digit; every lane has read it above)
+        if (in && rank == 0) c[w][d] = before + __popcll(peers);
+        pos[u] = before + rank;
+    }
+    __syncthreads();
+    // Digit starts within the tile: thread t owns digits [t*dpt, (t+1)*dpt)
+    // (dpt = nd / kBlock, at least 1), sums them, and an exclusive scan over
+    // the threads gives each digit's first slot; c[w][d] becomes that slot
+    // plus the digit's entries in the earlier waves.
+    const int dpt = nd >= kBlock ? nd / kBlock : 1;
+    const int d0 = threadIdx.x * dpt;
+    int32_t mine = 0;
+    if (d0 < nd)
+        for (int d = d0; d < d0 + dpt; ++d)
+#pragma unroll
+            for (int ww = 0; ww < kRxWaves; ++ww) mine += c[ww][d];
+    const int32_t incl = dev::wave_scan_incl(mine);
+    if (lane == dev::kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int32_t start = incl - mine;
+    for (int ww = 0; ww < w; ++ww) start += wsum[ww];
+    if (d0 < nd)
+        for (int d = d0; d < d0 + dpt; ++d) {
+            gofs[d] = off[(int64_t)d * ntiles + blockIdx.x] - start;
+#pragma unroll
+            for (int ww = 0; ww < kRxWaves; ++ww) {
+                const int32_t t = c[ww][d];
+                c[ww][d] = start;
+                start += t;
+            }
+        }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u) {
+        if (kk[u] < 0) continue;
+        const uint32_t d = ((uint32_t)kk[u] >> shift) & mask;
+        pos[u] += c[w][d];
+        stage[pos[u]] = (int64_t)(((uint64_t)(uint32_t)rr[u] << 32) | (uint32_t)kk[u]);
+    }
+    __syncthreads();
+    int32_t dst[kRxItems];
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u) {
+        const int32_t sl = u * kBlock + threadIdx.x;
+        dst[u] = -1;
+        if (sl < tcount) {
+            const uint64_t kr = (uint64_t)stage[sl];
+            const int32_t key = (int32_t)(uint32_t)kr;
+            dst[u] = gofs[((uint32_t)key >> shift) & mask] + sl;
+            kout[dst[u]] = key;
+            rout[dst[u]] = (int32_t)(uint32_t)(kr >> 32);
+        }
+    }
+    __syncthreads();
+    double *sv = reinterpret_cast<double *>(stage);
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u)
+        if (kk[u] >= 0) sv[pos[u]] = vv[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kRxItems; ++u)
+        if (dst[u] >= 0) vout[dst[u]] = sv[u * kBlock + threadIdx.x];
+}
+
+// Row pointers of A^T from the sorted columns: rowptr[J] = first position
+// whose column is >= J (the columns of entries e-1 and e bound the J that
+// entry e starts); the entry past the end closes the trailing rows.
+__global__ void k_rx_rowptr(const int32_t *__restrict__ key, int64_t nnz, int32_t ncols, int32_t *__restrict__ rp) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e > nnz) return;
+    const int32_t prev = e > 0 ? key[e - 1] : -1;
+    const int32_t cur = e < nnz ? key[e] : ncols;
+    for (int32_t J = prev + 1; J <= cur; ++J) rp[J] = (int32_t)e;
+}
+
 // A^T on the pattern of A, when that pattern is symmetric: entry (i, j) of
 // A^T is a_ji, found by binary search in row j of A; no counting, atomic
 // fill or sort.  `miss` is set when some (j, i) is absent (the pattern is not
@@ -1600,9 +1776,72 @@ void launch_csr_check(const CsrView &A, double *diag, int32_t *bad, hipStream_t 
     GW_HIP(hipGetLastError());
 }
 
+// Transposes of at least this many entries, with at least kRxMinPerCol of
+// them per column, take the radix sort; the others the count / fill / rank
+// path (fewer launches, and its atomics are cheap when few entries share a
+// column: 133 us against 236 us for the 1M-row upwind operator, about 4
+// entries a column; the prolongator of the 1M-cell flow hierarchy, 38 a
+// column, 350 us against 144 us).
+constexpr int64_t kRxMinEntries = 1 << 17;
+constexpr int64_t kRxMinPerCol = 6;
+
+static void transpose_radix(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total) {
+    const int64_t nnz = A.nnz;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)A.ncols) ++bits;
+    const int npass = (bits + kRxMaxBits - 1) / kRxMaxBits;
+    const int64_t ntiles = (nnz + kRxTile - 1) / kRxTile;
+    const int nd_max = 1 << ((bits + npass - 1) / npass);
+    DBuf<int32_t> rowid((size_t)nnz), k0((size_t)nnz), r0(npass > 1 ? (size_t)nnz : 0), k1((size_t)nnz),
+        r1(npass > 2 ? (size_t)nnz : 0), cnt((size_t)nd_max * ntiles + 1);
+    DBuf<double> v0(npass > 1 ? (size_t)nnz : 0), v1(npass > 2 ? (size_t)nnz : 0);
+    const int G = lane_group_for(A.n ? (double)nnz / (double)A.n : 0.0);
+    auto rowids = [&](auto gc) {
+        constexpr int GG = decltype(gc)::value;
+        hipLaunchKernelGGL((k_rx_rowid<GG>), dim3(blocks_for((int64_t)A.n * GG)), dim3(kBlock), 0, s, A, rowid.p);
+    };
+    switch (G) {
+        case 1: rowids(std::integral_constant<int, 1>()); break;
+        case 4: rowids(std::integral_constant<int, 4>()); break;
+        case 16: rowids(std::integral_constant<int, 16>()); break;
+        default: rowids(std::integral_constant<int, 64>()); break;
+    }
+    fill_i32(cnt.p, 0, 1, s);
+    const int32_t *kin = A.col, *rin = rowid.p;
+    const double *vin = A.val;
+    int shift = 0;
+    const int32_t *sorted_keys = nullptr;
+    for (int p = 0; p < npass; ++p) {
+        const int b = bits / npass + (p < bits % npass ? 1 : 0);
+        const bool last = p == npass - 1;
+        // outputs: the sets alternate (k0/r0/v0, k1/r1/v1); the last pass
+        // writes rows and values straight into T
+        int32_t *ko = (p % 2 == 0) ? k0.p : k1.p;
+        int32_t *ro = last ? T.col.p : (p % 2 == 0 ? r0.p : r1.p);
+        double *vo = last ? T.val.p : (p % 2 == 0 ? v0.p : v1.p);
+        const int64_t nc = ((int64_t)1 << b) * ntiles;
+        hipLaunchKernelGGL(k_rx_hist, dim3((unsigned)ntiles), dim3(kBlock), 0, s, kin, nnz, shift, b, cnt.p, ntiles);
+        scan_inclusive_i32(cnt.p + 1, nc, scratch_total, s);
+        hipLaunchKernelGGL(k_rx_scatter, dim3((unsigned)ntiles), dim3(kBlock), 0, s, kin, rin, vin, nnz, shift, b,
+                           cnt.p, ntiles, ko, ro, vo);
+        kin = ko;
+        rin = ro;
+        vin = vo;
+        sorted_keys = ko;
+        shift += b;
+    }
+    hipLaunchKernelGGL(k_rx_rowptr, dim3(blocks_for(nnz + 1)), dim3(kBlock), 0, s, sorted_keys, nnz, A.ncols,
+                       T.rowptr.p);
+    GW_HIP(hipGetLastError());
+}
+
 void transpose(const CsrView &A, Csr &T, hipStream_t s, int64_t *scratch_total) {
-    ProfScope ps(K_TRANSPOSE, (double)A.nnz * 36, s);
+    ProfScope ps(K_TRANSPOSE, 24.0 * A.nnz + 4.0 * ((double)A.n + A.ncols + 2), s);
     T.alloc(A.ncols, A.n, A.nnz);
+    if (A.nnz >= kRxMinEntries && A.nnz >= kRxMinPerCol * (int64_t)A.ncols) {
+        transpose_radix(A, T, s, scratch_total);
+        return;
+    }
     fill_i32(T.rowptr.p, 0, (int64_t)A.ncols + 1, s);
     if (A.nnz > 0) {
         unsigned g = std::min<unsigned>(blocks_for(A.nnz, 4), 65536);

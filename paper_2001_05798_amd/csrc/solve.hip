@@ -42,6 +42,12 @@ __global__ void k_smooth(int64_t n, OP op, const V *__restrict__ M, const Bt *__
     smooth_body<OP, V, Bt, Xt, Yt, NR>(VG::here(), n, op, M, b, x, y, done);
 }
 
+template <class OP, class V, class Bt, class Rt, int NR>
+__global__ void k_smooth_res(int64_t n, OP op, const V *__restrict__ M, const Bt *__restrict__ b, V *__restrict__ y,
+                             Rt *__restrict__ r, const int32_t *done) {
+    smooth_res_body<OP, V, Bt, Rt, NR>(VG::here(), n, op, M, b, y, r, done);
+}
+
 template <class OP, class V, class Bt, class Xt, class Rt, int NR>
 __global__ void k_residual(int64_t n, OP op, const Bt *__restrict__ b, const Xt *__restrict__ x,
                            Rt *__restrict__ r, const int32_t *done) {
@@ -180,9 +186,21 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
         if (Lv.ilu) return vcycle_level_ilu<Zt>(H, l, b, out, done, s);
     }
 
+    Level &Nx = H->L[l + 1];
+    V *bc = reinterpret_cast<V *>(Nx.vb.p);
+    const int64_t nc = Lv.nc;
     // pre-smoothing
     if (npre == 0) {
         hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n * NR)), dim3(kBlock), 0, s, x, n * NR, done);
+    } else if (npre == 1) {
+        // the one sweep (x = M b) and the residual in one pass (into t)
+        const double vec = n * (double)vb + nr * n * (double)(sizeof(Bt) + 2 * vb);
+        ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + vec, s, true, cabytes + vec);
+        with_level_op<V>(Lv, [&](auto op) {
+            using OP = decltype(op);
+            GW_LAUNCH_TIMED(ps, (k_smooth_res<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
+                               op, M, b, x, t, done);
+        });
     } else {
         const double vec = n * (double)vb + nr * n * (double)(sizeof(Bt) + vb);
         ProfScope ps(level_kid(K_SMOOTH_FIRST0, l), (npre >= 2 ? abytes : 0.0) + vec, s, true,
@@ -207,11 +225,8 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
         sweep(x, t);
         std::swap(x, t);
     }
-    Level &Nx = H->L[l + 1];
-    V *bc = reinterpret_cast<V *>(Nx.vb.p);
-    const int64_t nc = Lv.nc;
-    // residual and restriction
-    {
+    // residual (formed with the sweep above when npre == 1) and restriction
+    if (npre != 1) {
         const double vec = nr * n * (double)(sizeof(Bt) + 2 * vb);
         ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + vec, s, true, cabytes + vec);
         with_level_op<V>(Lv, [&](auto op) {

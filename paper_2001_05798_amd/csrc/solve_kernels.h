@@ -450,6 +450,38 @@ struct SmoothFirstK {
     __device__ void run(VG vg) const { smooth_first_body<OP, V, Bt, Yt, NR>(vg, n, op, M, b, y, two, done); }
 };
 
+// One pre-smoothing sweep from x = 0 and the residual after it in one pass
+// (one pre-sweep): x1 = M b and r = b - A x1, with x1_j recomputed on the
+// fly as the fused first sweeps do, so that the residual does not wait for
+// the sweep's launch and x1 is not read back.  x1 and r take exactly the
+// values of the sweep kernel followed by the residual kernel.
+template <class OP, class V, class Bt, class Rt, int NR>
+__device__ __forceinline__ void smooth_res_body(VG vg_, int64_t n, OP op, const V *__restrict__ M,
+                                                const Bt *__restrict__ b, V *__restrict__ y, Rt *__restrict__ r,
+                                                const int32_t *done) {
+    VecN<V, NR> bi{};
+    V mi = 0;
+    VROW_PROLOGUE(OP, op, bi = cvt<V>(load_n<Bt, NR>(b, i)); mi = M[i];)
+    const VecN<V, NR> ax = op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) {
+        const VecN<V, NR> bj = cvt<V>(load_n<Bt, NR>(b, j));
+        const V mj = M[j];
+        VecN<V, NR> o;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) o.v[k] = mj * bj.v[k];
+        return o;
+    });
+    if (lane == 0) {
+        VecN<V, NR> x1, o;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            x1.v[k] = mi * bi.v[k];
+            o.v[k] = bi.v[k] - ax.v[k];
+        }
+        store_n<V, NR>(y, i, x1);
+        store_n<Rt, NR>(r, i, cvt<Rt>(o));
+    }
+}
+
 template <class OP, class V, class Bt, class Xt, class Yt, int NR>
 __device__ __forceinline__ void smooth_body(VG vg_, int64_t n, OP op, const V *__restrict__ M,
                                             const Bt *__restrict__ b, const Xt *__restrict__ x, Yt *__restrict__ y,
