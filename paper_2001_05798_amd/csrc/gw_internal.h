@@ -101,6 +101,43 @@ void *host_stage();
 // A second stream of the calling host thread on the current device, for work
 // that overlaps the caller's stream (ordered against it by events).
 hipStream_t side_stream();
+// Work of the calling thread on its side stream, overlapping the work that
+// follows on the caller's stream s.  run(s, f) makes the side stream wait for
+// the work already on s and enqueues f(side) there; join(s) makes s wait for
+// it.  Pool blocks freed while f runs (the side work's temporaries) are held
+// back from the thread's free lists until join, so no kernel enqueued on s
+// in between can receive a block the side stream may still use; the
+// destructor (error paths) synchronizes the side stream before it releases
+// them.  One job at a time per thread.
+struct SideJob {
+    hipStream_t q = nullptr;
+    hipEvent_t start = nullptr, done = nullptr;
+    std::vector<void *> held;
+    bool pending = false;
+    SideJob() = default;
+    SideJob(const SideJob &) = delete;
+    SideJob &operator=(const SideJob &) = delete;
+    template <class F>
+    void run(hipStream_t s, F &&f) {
+        begin(s);
+        struct Restore {
+            SideJob *j;
+            ~Restore() { j->end_defer(); }
+        } r{this};
+        f(q);
+        end_defer();
+        GW_HIP(hipEventRecord(done, q));
+        pending = true;
+    }
+    void join(hipStream_t s);
+    ~SideJob();
+
+  private:
+    void begin(hipStream_t s);
+    void end_defer();
+    std::vector<void *> *prev_ = nullptr;
+    bool deferring_ = false;
+};
 // For a host thread that ends (a serving worker): synchronize and destroy
 // its side streams, free its pinned stage and the pool blocks cached on its
 // free lists.

@@ -104,8 +104,17 @@ void *pool_alloc(size_t bytes) {
     return p;
 }
 
+namespace {
+// Set while a SideJob enqueues its work: blocks freed then are held by it.
+thread_local std::vector<void *> *t_defer = nullptr;
+}  // namespace
+
 void pool_free(void *p) {
     if (!p) return;
+    if (t_defer) {
+        t_defer->push_back(p);
+        return;
+    }
     Pool &P = pool();
     std::lock_guard<std::mutex> g(P.mu);
     auto it = P.live.find(p);
@@ -191,6 +200,41 @@ hipStream_t side_stream() {
     GW_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     streams[dev] = st;
     return st;
+}
+
+void SideJob::begin(hipStream_t s) {
+    GW_REQUIRE(!pending && !deferring_, "side job already running");
+    q = side_stream();
+    if (!start) GW_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    if (!done) GW_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    GW_HIP(hipEventRecord(start, s));
+    GW_HIP(hipStreamWaitEvent(q, start, 0));
+    prev_ = t_defer;
+    t_defer = &held;
+    deferring_ = true;
+}
+
+void SideJob::end_defer() {
+    if (!deferring_) return;
+    t_defer = prev_;
+    deferring_ = false;
+}
+
+void SideJob::join(hipStream_t s) {
+    if (!pending) return;
+    GW_HIP(hipStreamWaitEvent(s, done, 0));
+    pending = false;
+    // every later kernel of s runs after the side work: its blocks may go back
+    for (void *p : held) pool_free(p);
+    held.clear();
+}
+
+SideJob::~SideJob() {
+    end_defer();
+    if (q && (pending || !held.empty())) (void)hipStreamSynchronize(q);
+    for (void *p : held) pool_free(p);
+    if (start) (void)hipEventDestroy(start);
+    if (done) (void)hipEventDestroy(done);
 }
 
 void release_thread_resources() {

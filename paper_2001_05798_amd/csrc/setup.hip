@@ -1879,8 +1879,12 @@ void galerkin(amg_hierarchy *H, int l, int64_t nc, LevelReads &rd, hipStream_t s
     Level &Lv = H->L[l];
     const CsrView A = view(Lv.A);
     const int32_t n = A.n;
-    DBuf<int64_t> total(1);
-    transpose(view(Lv.P), Lv.R, s, total.p);
+    // R = P^T on the side stream, overlapping the symbolic pass of A P
+    SideJob tr;
+    tr.run(s, [&](hipStream_t q) {
+        DBuf<int64_t> total(1);
+        transpose(view(Lv.P), Lv.R, q, total.p);
+    });
     Csr AP;
     const double arow = (double)A.nnz / std::max<int32_t>(n, 1);
     const double pavg = (double)Lv.P.nnz / std::max<int32_t>(n, 1);
@@ -1893,6 +1897,7 @@ void galerkin(amg_hierarchy *H, int l, int64_t nc, LevelReads &rd, hipStream_t s
     const int64_t np = Lv.P.nnz, nr_ = Lv.R.nnz;
     spgemm_symbolic(a_side, p_side, EpiIdentity{}, n, (int32_t)nc, arow, pavg, rd.hblk(1)[0], AP, rd.blk(1), s,
                     rows(n, A.nnz, 4) + rows(n, np, 4));
+    tr.join(s);
     const ARowCsr r_side{Lv.R.rowptr.p, Lv.R.col.p, Lv.R.val.p};
     spgemm_bound(r_side, BCsr{AP.rowptr.p, nullptr, nullptr}, (int32_t)nc, ravg, rd.blk(2), s,
                  rows(nc, nr_, 4) + 4.0 * (n + 1));
