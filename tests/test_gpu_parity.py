@@ -406,6 +406,23 @@ def test_full_size_flow_parity(gw, ref, name, kw):
     assert err <= 1e-8
 
 
+def test_hierarchy_with_three_pass_radix_transpose(gw, ref):
+    # A homogeneous 150^3 cube at the flow settings the benchmark times: the
+    # level-0 prolongator has 303347 columns of about 38 entries each, so
+    # R = P^T takes the radix path with three digit passes (more than 2^18
+    # columns).  Every level, A_1 = R (A P) included, matches bit for bit.
+    _say("hierarchy 150^3 homogeneous: R = P^T by three radix passes")
+    p = gi.homogeneous_slab(150, 150, 150)
+    ap = ref.AmgParams(eps_strong=0.03, npre=1, npost=1)
+    A, b = ref.fv_assemble(p)
+    Hr = ref.Hierarchy(A, ap)
+    l0 = Hr.level(0)
+    assert l0.nc > 1 << 18 and l0.P.nnz >= 6 * l0.nc, (l0.nc, l0.P.nnz)
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap))
+    _compare_hierarchy(gw, ref, Hg, Hr, "150^3")
+
+
 GENERAL_CASES = [
     # thousands of distinct column offsets: sliced ELL with int32 columns
     ("random graph n=3000", lambda: gi.random_graph_spd(3000, 4, 31)),
