@@ -2083,9 +2083,17 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             });
             GW_HIP(hipGetLastError());
         }
-        sym = st.read(miss, s) == 0;
-        H->sym_pattern = sym ? 1 : 0;
+        if (H->sym_pattern == 1) {
+            // a Galerkin product R A P with R = P^T (cancelled entries kept)
+            // has a symmetric pattern when A's is: no read here, the miss
+            // word is checked with the level's next read
+            sym = true;
+        } else {
+            sym = st.read(miss, s) == 0;
+            H->sym_pattern = sym ? 1 : 0;
+        }
     }
+    const bool check_sym = sym && l > 0;
     if (sym) {
         Tv = CsrView{n, n, A.nnz, A.rowptr, A.col, tval_sym.p};
     } else {
@@ -2229,6 +2237,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         rounds += batch;
     }
     Lv.mis_rounds = rounds;
+    if (check_sym && rd.h[2] != 0) fail(GW_EDEVICE, "amg_setup: a Galerkin level lost its symmetric pattern");
     m1.release();
     S.nnz = rd.h64(0);
     Lv.nnz_s = S.nnz;
