@@ -1388,6 +1388,69 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
     for (int32_t i = lane; i < n; i += 64) inv[(int64_t)i * n + c] = x[i];
 }
 
+// The same columns of the inverse for n <= 128, by column-oriented
+// substitutions: lane l holds x_l and x_{l+64}; step j broadcasts the
+// finished x_j with v_readlane (a uniform lane index) and every lane
+// updates its later (forward) or earlier (backward) rows, so a step costs a
+// broadcast and a multiply-subtract instead of a wave-wide sum.  The L and U
+// entries of the next step are loaded one step ahead (staging the factors
+// in LDS first measured slower: 73 against 50 us).  (Each x_i receives
+// its terms in the order j = pos, pos+1, ... rather than as one dot product,
+// so the inverse agrees with the row-oriented one to rounding.)
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+__global__ void __launch_bounds__(64) k_lu_inverse_col(const double *__restrict__ lu, const int32_t *__restrict__ piv,
+                                                       int32_t n, double *__restrict__ inv, const int32_t *status) {
+    const int32_t c = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (c >= n || *status != 0) return;
+    int32_t pos = c;
+    for (int32_t k = 0; k < n; ++k) {
+        const int32_t pk = piv[k];
+        if (pos == k) pos = pk;
+        else if (pos == pk) pos = k;
+    }
+    const int32_t i0 = lane, i1 = lane + 64;
+    double x0 = (i0 == pos) ? 1.0 : 0.0, x1 = (i1 == pos) ? 1.0 : 0.0;
+    // forward: unit lower triangle, x_j final after step j - 1
+    double a0 = 0.0, a1 = 0.0;
+    if (pos < n - 1) {
+        a0 = i0 < n ? lu[(int64_t)i0 * n + pos] : 0.0;
+        a1 = i1 < n ? lu[(int64_t)i1 * n + pos] : 0.0;
+    }
+    for (int32_t j = pos; j < n - 1; ++j) {
+        const double l0 = a0, l1 = a1;
+        if (j + 1 < n - 1) {
+            a0 = i0 < n ? lu[(int64_t)i0 * n + j + 1] : 0.0;
+            a1 = i1 < n ? lu[(int64_t)i1 * n + j + 1] : 0.0;
+        }
+        const double xj = readlane_f64(j < 64 ? x0 : x1, j & 63);
+        if (i0 > j && i0 < n) x0 = x0 - l0 * xj;
+        if (i1 > j && i1 < n) x1 = x1 - l1 * xj;
+    }
+    // backward: upper triangle with its diagonal
+    a0 = i0 < n ? lu[(int64_t)i0 * n + (n - 1)] : 0.0;
+    a1 = i1 < n ? lu[(int64_t)i1 * n + (n - 1)] : 0.0;
+    for (int32_t j = n - 1; j >= 0; --j) {
+        const double u0 = a0, u1 = a1;
+        if (j > 0) {
+            a0 = i0 < n ? lu[(int64_t)i0 * n + j - 1] : 0.0;
+            a1 = i1 < n ? lu[(int64_t)i1 * n + j - 1] : 0.0;
+        }
+        if (i0 == j) x0 = x0 / u0;
+        if (i1 == j) x1 = x1 / u1;
+        const double xj = readlane_f64(j < 64 ? x0 : x1, j & 63);
+        if (i0 < j) x0 = x0 - u0 * xj;
+        if (i1 < j) x1 = x1 - u1 * xj;
+    }
+    if (i0 < n) inv[(int64_t)i0 * n + c] = x0;
+    if (i1 < n) inv[(int64_t)i1 * n + c] = x1;
+}
+
 // ----------------------------------------------------------- Ruge-Stueben --
 // The classical coarsening the paper's figures compare with smoothed
 // aggregation: strength on the size of the negative couplings, a PMIS C/F
@@ -2380,7 +2443,10 @@ void start_coarsest(amg_hierarchy *H, int l, hipStream_t s, CoarseJob &job) {
     {
         // skipped after a zero pivot (the pivots past it were never written)
         ProfScope ps(K_COARSE_LU, (double)n * n * 16, q);
-        hipLaunchKernelGGL(k_lu_inverse, dim3(n), dim3(64), 0, q, H->lu.p, H->piv.p, n, H->inv.p, status);
+        if (n <= 128)
+            hipLaunchKernelGGL(k_lu_inverse_col, dim3(n), dim3(64), 0, q, H->lu.p, H->piv.p, n, H->inv.p, status);
+        else
+            hipLaunchKernelGGL(k_lu_inverse, dim3(n), dim3(64), 0, q, H->lu.p, H->piv.p, n, H->inv.p, status);
         GW_HIP(hipGetLastError());
     }
     GW_HIP(hipEventRecord(job.done, q));
