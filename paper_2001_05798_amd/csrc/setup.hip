@@ -1684,7 +1684,10 @@ int spgemm_group(double avg_a_len) {
 // pass adds what it writes (C's row pointers; its columns and values).
 template <class AR, class BR>
 void spgemm_bound(AR ar, BR br, int32_t nrows, double avg_a_len, int32_t *blk, hipStream_t s, double bytes) {
-    fill_i32(blk, 0, 6, s);  // the bound, and the words the symbolic pass that follows accumulates into
+    // blk (the bound, and the words the symbolic pass accumulates into) was
+    // cleared with the level's read-back block; a repeated call (the
+    // speculative prolongator bound after each batch of MIS-2 rounds) only
+    // raises the maximum, which the later rows' growing aggregates bound
     ProfScope ps(K_SPGEMM, bytes, s);
     // short rows: one lane per row (the row sums are a few loads)
     with_group(avg_a_len > 12.0 ? avg_a_len : 1.0, [&](auto gc) {
