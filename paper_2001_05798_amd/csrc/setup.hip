@@ -586,12 +586,13 @@ __global__ void __launch_bounds__(kBlock) k_strength_sym(CsrView A, const double
 constexpr unsigned kAtomicBlocks = 1024;
 
 __global__ void k_mis_init(const int32_t *__restrict__ srow, int32_t n, uint32_t *__restrict__ state,
-                           int32_t *und) {
+                           uint8_t *__restrict__ done, int32_t *und) {
     __shared__ int32_t sm[kBlock / dev::kWave];
     int32_t c = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const bool kept = srow[i + 1] > srow[i];
         state[i] = kept ? ST_UND : ST_OUT;
+        done[i] = kept ? 0 : 1;
         c += kept;
     }
     c = dev::block_sum(c, sm);
@@ -633,23 +634,34 @@ __device__ __forceinline__ T grp_min(T v) {
          row_ += (int64_t)gridDim.x * blockDim.x / (G))
 
 // m1_i = max(key_i, max_{j in S(i)} key_j) (a maximum: any lane order).
-// Skipped once a previous round left nothing undecided.
+// Skipped once a previous round left nothing undecided.  m1 is read only by
+// undecided nodes, for themselves and their neighbours (S is symmetric), and
+// states never return to UNDECIDED: a node that finds itself and all its
+// neighbours decided is marked done and skipped by later rounds.
 template <int G>
 __global__ void k_mis_m1(const int32_t *__restrict__ srow, const int32_t *__restrict__ scol, int32_t n,
                          const uint32_t *__restrict__ state, uint32_t salt, uint64_t *__restrict__ m1,
-                         const int32_t *prev_und) {
+                         uint8_t *__restrict__ done, const int32_t *prev_und) {
     if (*prev_und == 0) return;
     GRP_ROW(G, n)
-    if (!has_) return;
-    uint64_t m = lane_ == 0 ? mis_key(state[i], salt, i) : 0ull;
+    if (!has_ || done[i]) return;
+    const uint32_t si = state[i];
+    uint64_t m = lane_ == 0 ? mis_key(si, salt, i) : 0ull;
+    int32_t open = si == ST_UND;
     const int32_t e = srow[i + 1];
     for (int32_t p = srow[i] + lane_; p < e; p += G) {
         const int32_t j = scol[p];
-        const uint64_t kj = mis_key(state[j], salt, j);
+        const uint32_t sj = state[j];
+        open |= sj == ST_UND;
+        const uint64_t kj = mis_key(sj, salt, j);
         m = kj > m ? kj : m;
     }
     m = grp_max<G>(m);
-    if (lane_ == 0) m1[i] = m;
+    open = grp_max<G>(open);
+    if (lane_ == 0) {
+        m1[i] = m;
+        if (!open) done[i] = 1;
+    }
 }
 
 // m2_i = max(m1_i, max_j m1_j); UNDECIDED i becomes ROOT if m2_i is its own
@@ -2238,13 +2250,14 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     // back with the round flags: they are final when the rounds have ended.
     DBuf<uint32_t> state(n);
     DBuf<uint64_t> m1(n);
+    DBuf<uint8_t> done(n);
     constexpr int kMaxRounds = kMaxMisRounds, kBatch = 12, kLate = 4;
     int32_t *und = rd.und();
     const uint32_t salt = level_salt(prm.seed, l);
     {
         ProfScope ps(K_MIS2, n * 8.0, s);
         hipLaunchKernelGGL(k_mis_init, dim3(std::min(blocks_for(n), kAtomicBlocks)), dim3(kBlock), 0, s, S.rowptr.p, n,
-                           state.p, und);
+                           state.p, done.p, und);
         GW_HIP(hipGetLastError());
     }
     // lanes per row from A's off-diagonal row length (the graph's own size is
@@ -2269,7 +2282,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
                 constexpr int G = decltype(gc)::value;
                 const dim3 grid(blocks_for((int64_t)n * G));
                 hipLaunchKernelGGL((k_mis_m1<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
-                                   m1.p, und + r);
+                                   m1.p, done.p, und + r);
                 hipLaunchKernelGGL((k_mis_m2<G>), grid, dim3(kBlock), 0, s, S.rowptr.p, S.col.p, n, state.p, salt,
                                    m1.p, und + r, und + r + 1);
             });
@@ -2305,6 +2318,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     Lv.mis_rounds = rounds;
     if (check_sym && rd.h[2] != 0) fail(GW_EDEVICE, "amg_setup: a Galerkin level lost its symmetric pattern");
     m1.release();
+    done.release();
     S.nnz = rd.h64(0);
     Lv.nnz_s = S.nnz;
     T = Csr();
