@@ -70,8 +70,10 @@ void finish(hipStream_t s) {
     if (prof_on()) prof_flush();
 }
 
-// Hierarchy of a device CSR (copied), as amg_setup documents.
-amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream_t s) {
+// Hierarchy of a device CSR (copied), as amg_setup documents.  sym_pattern:
+// -1 probes whether the level-0 pattern is symmetric; 0 takes the general
+// path (A^T formed explicitly), which is correct for any pattern.
+amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream_t s, int sym_pattern = -1) {
     GW_REQUIRE(A && A->rowptr && A->col && A->val, "amg_setup: null matrix");
     GW_REQUIRE(A->n > 0 && A->nnz >= A->n && A->nnz < INT32_MAX, "amg_setup: bad matrix size");
     check_params(prm);
@@ -80,6 +82,7 @@ amg_hierarchy *setup_hierarchy(const gw_csr *A, const amg_params *prm, hipStream
     GW_HIP(hipGetDevice(&dev));
     H->device = dev;
     H->prm = *prm;
+    H->sym_pattern = sym_pattern;
     H->L.resize(33);
     Level &L0 = H->L[0];
     L0.A.alloc(A->n, A->n, A->nnz);
@@ -508,7 +511,9 @@ int tt_solve(const gw_grid *grid, const double *qx, const double *qy, const doub
                              stream);
         if (rc != GW_OK) fail(rc, gw_last_error());
         gw_csr view_{(int32_t)n, nnz, A.rowptr.p, A.col.p, A.val.p};
-        std::unique_ptr<amg_hierarchy> H(setup_hierarchy(&view_, params, s));
+        // an upwind row holds only inflow neighbours, so a_ij and a_ji are
+        // not both stored: no probe for a symmetric pattern
+        std::unique_ptr<amg_hierarchy> H(setup_hierarchy(&view_, params, s, 0));
         A = Csr();
         const double setup_ms = now_ms() - t0;
         GW_REQUIRE(tau != c, "tt_solve: tau and c must be different buffers");

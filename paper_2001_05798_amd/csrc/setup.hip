@@ -421,14 +421,19 @@ __device__ __forceinline__ int32_t grp_scan_incl(int32_t v, int lane) {
 // 0).  A strong entry's place in the column-ordered union is its count of
 // strong predecessors in its own list plus the strong entries of the other
 // list with a smaller column (exclusive prefix counts kept in LDS).  The
-// lumped diagonal is summed in column order, one lane's value after the
-// other.  Rows longer than the LDS lists take the one-lane walk.
+// counting pass stores each entry's outcome in code[] (A's entries at their
+// positions in A, then A^T's at nnz(A) + theirs): the lower-bound index in
+// the other row when the entry is strong, -1 when not; the filling pass
+// places entries from these codes without searching or gathering again.
+// The lumped diagonal is summed in column order, one lane's value after the
+// other.  Rows longer than the LDS lists take the one-lane walk in both
+// passes.
 template <int G, bool FILL>
 __global__ void __launch_bounds__(kBlock) k_strength_grp(CsrView A, CsrView T, const double *__restrict__ diag,
                                                          double eps2, int32_t *__restrict__ cnt,
                                                          const int32_t *__restrict__ srow, int32_t *__restrict__ scol,
                                                          double *__restrict__ sw, uint8_t *__restrict__ strongA,
-                                                         double *__restrict__ dF) {
+                                                         double *__restrict__ dF, int32_t *__restrict__ code) {
     constexpr int CAP = 16 * G;
     __shared__ int32_t pref[FILL ? (kBlock / G) * 2 * (CAP + 1) : 1];
     const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -445,62 +450,69 @@ __global__ void __launch_bounds__(kBlock) k_strength_grp(CsrView A, CsrView T, c
         }
         return;
     }
-    const double di = diag[i];
-    int32_t *PA = pref + (FILL ? (threadIdx.x / G) * 2 * (CAP + 1) : 0);
+    int32_t *codeA = code + pa, *codeT = code + A.nnz + pt;
+    if (!FILL) {
+        const double di = diag[i];
+        int32_t run = 0;
+        for (int32_t c0 = 0; c0 < la; c0 += G) {
+            const int32_t a = c0 + lane;
+            bool st = false;
+            if (a < la) {
+                const int32_t j = A.col[pa + a];
+                const double aij = A.val[pa + a];
+                const int32_t idx = lower_bound_i32(T.col + pt, lt, j);
+                const double aji = (idx < lt && T.col[pt + idx] == j) ? T.val[pt + idx] : 0.0;
+                st = j != i && strong_pair(aij, aji, di, diag[j], eps2);
+                codeA[a] = st ? idx : -1;
+            }
+            run += __shfl(grp_scan_incl<G>(st ? 1 : 0, lane), G - 1, G);
+        }
+        for (int32_t c0 = 0; c0 < lt; c0 += G) {
+            const int32_t u = c0 + lane;
+            bool st = false;
+            if (u < lt) {
+                const int32_t j = T.col[pt + u];
+                const double aji = T.val[pt + u];
+                const int32_t idx = lower_bound_i32(A.col + pa, la, j);
+                const bool only = !(idx < la && A.col[pa + idx] == j);
+                st = only && j != i && strong_pair(0.0, aji, di, diag[j], eps2);
+                codeT[u] = st ? idx : -1;
+            }
+            run += __shfl(grp_scan_incl<G>(st ? 1 : 0, lane), G - 1, G);
+        }
+        if (lane == 0) cnt[i + 1] = run;
+        return;
+    }
+    int32_t *PA = pref + (threadIdx.x / G) * 2 * (CAP + 1);
     int32_t *PT = PA + (CAP + 1);
-    // entry a of A's row: column, a_ij, a_ji, strong
-    auto a_entry = [&](int32_t a, int32_t &j, double &aij, double &aji, int32_t &idx) -> bool {
-        j = A.col[pa + a];
-        aij = A.val[pa + a];
-        idx = lower_bound_i32(T.col + pt, lt, j);
-        aji = (idx < lt && T.col[pt + idx] == j) ? T.val[pt + idx] : 0.0;
-        return j != i && strong_pair(aij, aji, di, diag[j], eps2);
-    };
-    // entry u of A^T's row: column, a_ji, strong and absent from A's row
-    auto t_entry = [&](int32_t u, int32_t &j, double &aji, int32_t &idx) -> bool {
-        j = T.col[pt + u];
-        aji = T.val[pt + u];
-        idx = lower_bound_i32(A.col + pa, la, j);
-        const bool only = !(idx < la && A.col[pa + idx] == j);
-        return only && j != i && strong_pair(0.0, aji, di, diag[j], eps2);
-    };
     int32_t runA = 0, runT = 0;
-    double lump = di;
+    double lump = diag[i];
     for (int32_t c0 = 0; c0 < la; c0 += G) {
         const int32_t a = c0 + lane;
         const bool in = a < la;
-        int32_t j = i, idx = 0;
-        double aij = 0.0, aji = 0.0;
-        const bool st = in && a_entry(a, j, aij, aji, idx);
+        const int32_t j = in ? A.col[pa + a] : i;
+        const double aij = in ? A.val[pa + a] : 0.0;
+        const bool st = in && codeA[a] >= 0;
         const int32_t sc = st ? 1 : 0;
         const int32_t incl = grp_scan_incl<G>(sc, lane);
-        if (FILL) {
-            if (in) {
-                strongA[pa + a] = st ? 1 : 0;
-                PA[a] = runA + incl - sc;
-            }
-            const double weak = (in && j != i && !st) ? aij : 0.0;
-            for (int t = 0; t < G; ++t) {
-                const double w = __shfl(weak, t, G);
-                if (c0 + t < la && w != 0.0) lump = lump + w;
-            }
+        if (in) {
+            strongA[pa + a] = st ? 1 : 0;
+            PA[a] = runA + incl - sc;
+        }
+        const double weak = (in && j != i && !st) ? aij : 0.0;
+        for (int t = 0; t < G; ++t) {
+            const double w = __shfl(weak, t, G);
+            if (c0 + t < la && w != 0.0) lump = lump + w;
         }
         runA += __shfl(incl, G - 1, G);
     }
     for (int32_t c0 = 0; c0 < lt; c0 += G) {
         const int32_t u = c0 + lane;
         const bool in = u < lt;
-        int32_t j = i, idx = 0;
-        double aji = 0.0;
-        const bool st = in && t_entry(u, j, aji, idx);
-        const int32_t sc = st ? 1 : 0;
+        const int32_t sc = (in && codeT[u] >= 0) ? 1 : 0;
         const int32_t incl = grp_scan_incl<G>(sc, lane);
-        if (FILL && in) PT[u] = runT + incl - sc;
+        if (in) PT[u] = runT + incl - sc;
         runT += __shfl(incl, G - 1, G);
-    }
-    if (!FILL) {
-        if (lane == 0) cnt[i + 1] = runA + runT;
-        return;
     }
     if (lane == 0) {
         PA[la] = runA;
@@ -509,21 +521,21 @@ __global__ void __launch_bounds__(kBlock) k_strength_grp(CsrView A, CsrView T, c
     __builtin_amdgcn_wave_barrier();
     const int32_t q0 = srow[i];
     for (int32_t a = lane; a < la; a += G) {
-        int32_t j, idx;
-        double aij, aji;
-        if (!a_entry(a, j, aij, aji, idx)) continue;
+        const int32_t idx = codeA[a];
+        if (idx < 0) continue;
+        const int32_t j = A.col[pa + a];
+        const double aji = (idx < lt && T.col[pt + idx] == j) ? T.val[pt + idx] : 0.0;
         const int32_t pos = PA[a] + PT[idx];
         scol[q0 + pos] = j;
-        const double x = fabs(aij), y = fabs(aji);
+        const double x = fabs(A.val[pa + a]), y = fabs(aji);
         sw[q0 + pos] = x > y ? x : y;
     }
     for (int32_t u = lane; u < lt; u += G) {
-        int32_t j, idx;
-        double aji;
-        if (!t_entry(u, j, aji, idx)) continue;
+        const int32_t idx = codeT[u];
+        if (idx < 0) continue;
         const int32_t pos = PT[u] + PA[idx];
-        scol[q0 + pos] = j;
-        const double y = fabs(aji);
+        scol[q0 + pos] = T.col[pt + u];
+        const double y = fabs(T.val[pt + u]);
         sw[q0 + pos] = 0.0 > y ? 0.0 : y;
     }
     if (lane == 0) dF[i] = lump;
@@ -2184,18 +2196,20 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     S.rowptr.alloc((size_t)n + 1);
     fill_i32(S.rowptr.p, 0, 1, s);
     DBuf<uint8_t> strongA((size_t)std::max<int64_t>(A.nnz, 1));
+    DBuf<int32_t> code;  // per-entry outcomes of the grouped counting pass
     const int Gs = lane_group_for(n ? (double)A.nnz / (double)n : 0.0);
     auto launch_strength = [&](bool fill) {
         auto grp = [&](auto gc) {
             constexpr int GG = decltype(gc)::value;
             const dim3 grid(blocks_for((int64_t)n * GG));
+            if (!fill) code.alloc((size_t)std::max<int64_t>(A.nnz + Tv.nnz, 1));
             if (fill)
                 hipLaunchKernelGGL((k_strength_grp<GG, true>), grid, dim3(kBlock), 0, s, A, Tv, diag.p, eps2,
-                                   (int32_t *)nullptr, S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p);
+                                   (int32_t *)nullptr, S.rowptr.p, S.col.p, sw.p, strongA.p, dF.p, code.p);
             else
                 hipLaunchKernelGGL((k_strength_grp<GG, false>), grid, dim3(kBlock), 0, s, A, Tv, diag.p, eps2,
                                    S.rowptr.p, (const int32_t *)nullptr, (int32_t *)nullptr, (double *)nullptr,
-                                   (uint8_t *)nullptr, (double *)nullptr);
+                                   (uint8_t *)nullptr, (double *)nullptr, code.p);
         };
         if (sym) {
             // A^T lives on A's own pattern: classify in place
@@ -2243,6 +2257,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         launch_strength(true);
         GW_HIP(hipGetLastError());
     }
+    code.release();
 
     // MIS-2 rounds, batched between host reads; a round after the last
     // decision is a no-op.  After each batch the aggregates and the row bound
