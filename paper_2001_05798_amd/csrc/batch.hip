@@ -165,10 +165,13 @@ void with_level_dyn(const Level &Lv, F &&f) {
 // The kernel steps of one V-cycle of every system in `act` from level l down,
 // in the order vcycle_level launches them for one system: b[j] the system's
 // right-hand side at this level (type Bt), out[j] where its result goes
-// (type Zt; null: the level's own buffer).  Returns each system's result.
+// (type Zt; null: the level's own buffer); x1_ready: the restriction into
+// this level also wrote the first sweep (x1 = M b) into the level's x buffer
+// of every system not on its coarsest level.  Returns each system's result.
 template <class V, class Bt, class Zt, int NR>
 std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::vector<int> &act, int l,
-                               const std::vector<const Bt *> &b, const std::vector<Zt *> &out) {
+                               const std::vector<const Bt *> &b, const std::vector<Zt *> &out,
+                               bool x1_ready = false) {
     const int vb = (int)sizeof(V);
     const double nr = NR;
     std::vector<void *> res(act.size(), nullptr);
@@ -198,7 +201,9 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
     }
     const int npre = S[act[fine[0]]].H->prm.npre, npost = S[act[fine[0]]].H->prm.npost;
     // pre-smoothing (npre >= 1: the batch requires it)
+    const int swept = x1_ready ? 1 : (npre >= 2 ? 2 : 1);
     for (int a : fine) {
+        if (x1_ready) break;
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n;
         const double abytes = op_bytes(Lv.A, Lv.As, vb);
@@ -209,7 +214,7 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
                   grid_rows(n, op.lanes()), (npre >= 2 ? abytes : 0.0) + n * (double)vb + nr * n * (double)(sizeof(Bt) + vb));
         });
     }
-    B.emit(P, q, level_kid(K_SMOOTH_FIRST0, l));
+    if (!x1_ready) B.emit(P, q, level_kid(K_SMOOTH_FIRST0, l));
     auto sweep = [&](auto yout_of) {
         for (int a : fine) {
             Level &Lv = S[act[a]].H->L[l];
@@ -225,7 +230,7 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         }
         B.emit(P, q, level_kid(K_SMOOTH0, l));
     };
-    for (int k = 2; k < npre; ++k) {
+    for (int k = swept; k < npre; ++k) {
         sweep([&](int a) { return t[a]; });
         for (int a : fine) std::swap(x[a], t[a]);
     }
@@ -244,11 +249,15 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
     }
     B.emit(P, q, level_kid(K_RESIDUAL0, l));
     for (int a : fine) {
-        Level &Lv = S[act[a]].H->L[l];
+        amg_hierarchy *H = S[act[a]].H;
+        Level &Lv = H->L[l], &Nx = H->L[l + 1];
         const int64_t n = Lv.A.n, nc = Lv.nc;
         const OpCsrDyn<V> op = dyn<V>(Lv.R, LevelOps<V>::rval(Lv));
-        B.put(SpmvK<OpCsrDyn<V>, V, V, V, NR>{nc, op, t[a], bnext[a], S[act[a]].done}, grid_rows(nc, op.lanes()),
-              csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb);
+        const bool x1c = restrict_writes_x1(H, l);
+        B.put(RestrictK<OpCsrDyn<V>, V, NR>{nc, op, t[a], bnext[a], x1c ? LevelOps<V>::mval(Nx) : (const V *)nullptr,
+                                            x1c ? reinterpret_cast<V *>(Nx.vx.p) : (V *)nullptr, S[act[a]].done},
+              grid_rows(nc, op.lanes()),
+              csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb + (x1c ? (nr + 1) * nc * (double)vb : 0.0));
     }
     B.emit(P, q, level_kid(K_RESTRICT0, l));
     // the next level, for the systems that continue
@@ -260,7 +269,8 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         b2.push_back(bnext[a]);
         o2.push_back(nullptr);
     }
-    std::vector<void *> xc = rec_vcycle<V, V, V, NR>(P, q, S, act2, l + 1, b2, o2);
+    // every system that continues past level l+1 has its first sweep there
+    std::vector<void *> xc = rec_vcycle<V, V, V, NR>(P, q, S, act2, l + 1, b2, o2, true);
     for (size_t k = 0; k < fine.size(); ++k) {
         const int a = fine[k];
         Level &Lv = S[act[a]].H->L[l];

@@ -59,6 +59,12 @@ __global__ void k_spmv(int64_t n, OP op, const Xt *__restrict__ x, Yt *__restric
     spmv_body<OP, V, Xt, Yt, NR>(VG::here(), n, op, x, y, done);
 }
 
+template <class OP, class V, int NR>
+__global__ void k_restrict(int64_t n, OP op, const V *__restrict__ t, V *__restrict__ bc, const V *__restrict__ Mc,
+                           V *__restrict__ x1, const int32_t *done) {
+    restrict_body<OP, V, NR>(VG::here(), n, op, t, bc, Mc, x1, done);
+}
+
 template <class OP, class V, class Xt, int NR>
 __global__ void k_prolong(int64_t n, OP op, const Xt *__restrict__ xc, Xt *__restrict__ x, const int32_t *done) {
     prolong_body<OP, V, Xt, NR>(VG::here(), n, op, xc, x, done);
@@ -95,8 +101,12 @@ __global__ void k_convert(const Xt *__restrict__ x, Yt *__restrict__ y, int64_t 
 // right-hand side (type Bt), the result goes to `out` (type Zt) when given,
 // else into one of the level's own buffers, whose address is returned.  V =
 // value type of the hierarchy (also the type of all internal vectors).
+// x1_ready: the restriction that formed b also wrote the first sweep from
+// x = 0 (x1 = M b) into the level's x buffer.
 template <class V, class Bt, class Zt, int NR>
-void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s);
+void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s,
+                   bool x1_ready = false);
+
 
 // A level with the ILU(0) smoother (FP64, one right-hand side): each sweep is
 // x <- x + (LU)^{-1} (b - A x), the first from x = 0 being x = (LU)^{-1} b.
@@ -165,7 +175,8 @@ void *vcycle_level_ilu(amg_hierarchy *H, int l, const double *b, Zt *out, const 
 }
 
 template <class V, class Bt, class Zt, int NR>
-void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s) {
+void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t *done, hipStream_t s,
+                   bool x1_ready) {
     Level &Lv = H->L[l];
     const int64_t n = Lv.A.n;
     const int vb = (int)sizeof(V);
@@ -189,8 +200,11 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
     Level &Nx = H->L[l + 1];
     V *bc = reinterpret_cast<V *>(Nx.vb.p);
     const int64_t nc = Lv.nc;
-    // pre-smoothing
-    if (npre == 0) {
+    // pre-smoothing; sweeps done counts those behind x
+    int swept = 0;
+    if (x1_ready) {
+        swept = 1;  // x1 = M b, written with b by the restriction
+    } else if (npre == 0) {
         hipLaunchKernelGGL((k_zero<V>), dim3(blocks_for(n * NR)), dim3(kBlock), 0, s, x, n * NR, done);
     } else if (npre == 1) {
         // the one sweep (x = M b) and the residual in one pass (into t)
@@ -201,6 +215,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
             GW_LAUNCH_TIMED(ps, (k_smooth_res<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
                                op, M, b, x, t, done);
         });
+        swept = 1;
     } else {
         const double vec = n * (double)vb + nr * n * (double)(sizeof(Bt) + vb);
         ProfScope ps(level_kid(K_SMOOTH_FIRST0, l), (npre >= 2 ? abytes : 0.0) + vec, s, true,
@@ -210,6 +225,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
             GW_LAUNCH_TIMED(ps, (k_smooth_first<OP, V, Bt, V, NR>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n,
                                op, M, b, x, npre >= 2 ? 1 : 0, done);
         });
+        swept = npre >= 2 ? 2 : 1;
     }
     auto sweep = [&](auto *xin, auto *yout) {
         using YT = std::remove_pointer_t<decltype(yout)>;
@@ -221,12 +237,13 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
                                M, b, xin, yout, done);
         });
     };
-    for (int k = 2; k < npre; ++k) {
+    for (int k = swept; k < npre; ++k) {
         sweep(x, t);
         std::swap(x, t);
     }
-    // residual (formed with the sweep above when npre == 1) and restriction
-    if (npre != 1) {
+    // residual (formed with the first sweep when that was the only one and
+    // came from k_smooth_res) and restriction
+    if (!(npre == 1 && !x1_ready)) {
         const double vec = nr * n * (double)(sizeof(Bt) + 2 * vb);
         ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + vec, s, true, cabytes + vec);
         with_level_op<V>(Lv, [&](auto op) {
@@ -235,15 +252,19 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
                                b, x, t, done);
         });
     }
+    const bool x1c = restrict_writes_x1(H, l);
     {
-        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb, s, true);
+        const double x1b = x1c ? nc * (double)vb + nr * nc * (double)vb : 0.0;
+        ProfScope ps(level_kid(K_RESTRICT0, l), csr_bytes(nc, Lv.R.nnz, vb) + nr * (double)(n + nc) * vb + x1b, s,
+                     true);
         with_csr<V>(Lv.R, LevelOps<V>::rval(Lv), [&](auto op) {
             using OP = decltype(op);
-            GW_LAUNCH_TIMED(ps, (k_spmv<OP, V, V, V, NR>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t,
-                               bc, done);
+            GW_LAUNCH_TIMED(ps, (k_restrict<OP, V, NR>), dim3(grid_rows(nc, OP::G)), dim3(kBlock), 0, s, nc, op, t,
+                               bc, x1c ? LevelOps<V>::mval(Nx) : (const V *)nullptr,
+                               x1c ? reinterpret_cast<V *>(Nx.vx.p) : (V *)nullptr, done);
         });
     }
-    V *xc = static_cast<V *>(vcycle_level<V, V, V, NR>(H, l + 1, bc, (V *)nullptr, done, s));
+    V *xc = static_cast<V *>(vcycle_level<V, V, V, NR>(H, l + 1, bc, (V *)nullptr, done, s, x1c));
     {
         ProfScope ps(level_kid(K_PROLONG0, l), csr_bytes(n, Lv.P.nnz, vb) + nr * (double)(2 * n + nc) * vb, s, true);
         with_csr<V>(Lv.P, LevelOps<V>::pval(Lv), [&](auto op) {

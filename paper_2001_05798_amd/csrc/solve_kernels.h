@@ -553,6 +553,38 @@ struct SpmvK {
     __device__ void run(VG vg) const { spmv_body<OP, V, Xt, Yt, NR>(vg, n, op, x, y, done); }
 };
 
+// Restriction b_c = R t; with x1 given, also the first sweep of the next
+// level from x = 0, x1 = M_c b_c (the value that level's fused first sweep
+// would form), so that level starts from a plain sweep or residual.
+template <class OP, class V, int NR>
+__device__ __forceinline__ void restrict_body(VG vg_, int64_t n, OP op, const V *__restrict__ t, V *__restrict__ bc,
+                                              const V *__restrict__ Mc, V *__restrict__ x1, const int32_t *done) {
+    V mi = 0;
+    VROW_PROLOGUE(OP, op, mi = x1 ? Mc[i] : (V)0;)
+    const VecN<V, NR> s =
+        op.template rows_at<NR>(h_, i, lane, sd_, [&](int32_t j) { return load_n<V, NR>(t, j); });
+    if (lane == 0) {
+        store_n<V, NR>(bc, i, s);
+        if (x1) {
+            VecN<V, NR> o;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) o.v[k] = mi * s.v[k];
+            store_n<V, NR>(x1, i, o);
+        }
+    }
+}
+template <class OP, class V, int NR>
+struct RestrictK {
+    int64_t n;
+    OP op;
+    const V *t;
+    V *bc;
+    const V *Mc;
+    V *x1;
+    const int32_t *done;
+    __device__ void run(VG vg) const { restrict_body<OP, V, NR>(vg, n, op, t, bc, Mc, x1, done); }
+};
+
 // x += P x_c
 template <class OP, class V, class Xt, int NR>
 __device__ __forceinline__ void prolong_body(VG vg_, int64_t n, OP op, const Xt *__restrict__ xc,
@@ -1325,6 +1357,13 @@ inline unsigned grid_rows(int64_t n, int G) { return blocks_for(n * G); }
 // Timing class of a V-cycle kernel on level l (ids of level 0, 1 and >= 2
 // are five apart).
 inline int level_kid(int id0, int l) { return id0 + 5 * (l < 2 ? l : 2); }
+
+// Whether the restriction into level l+1 also writes that level's first
+// sweep: it is smoothed (not the coarsest level, not ILU(0)) from x = 0 with
+// at least one pre-sweep.
+inline bool restrict_writes_x1(const amg_hierarchy *H, int l) {
+    return H->prm.npre >= 1 && l + 1 < H->nlev - 1 && !H->L[l + 1].ilu;
+}
 
 template <class V>
 struct LevelOps;
