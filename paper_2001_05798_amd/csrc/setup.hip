@@ -866,8 +866,13 @@ struct BTent {
     }
 };
 
+// Epilogues: row(i) gathers what the output row needs once (before its
+// stores, which the compiler cannot prove apart from the epilogue's
+// arrays), then each entry is formed from that and the sum s.
 struct EpiIdentity {
-    __device__ double operator()(int32_t, int32_t, double s) const { return s; }
+    struct Row {};
+    __device__ Row row(int32_t) const { return {}; }
+    __device__ double operator()(const Row &, int32_t, double s) const { return s; }
 };
 
 // P_iI = [agg(i) == I] - (w / d_i) s_I with d_i = dF_i if positive else a_ii.
@@ -875,11 +880,17 @@ struct EpiSmoothP {
     const int32_t *agg;
     const double *dF, *diag;
     const double *omega;
-    __device__ double operator()(int32_t i, int32_t J, double s) const {
-        double di = dF[i] > 0.0 ? dF[i] : diag[i];
-        double coef = *omega / di;
-        double delta = (agg[i] == J) ? 1.0 : 0.0;
-        return delta - coef * s;
+    struct Row {
+        int32_t agg_i;
+        double coef;
+    };
+    __device__ Row row(int32_t i) const {
+        const double di = dF[i] > 0.0 ? dF[i] : diag[i];
+        return {agg[i], *omega / di};
+    }
+    __device__ double operator()(const Row &r, int32_t J, double s) const {
+        const double delta = (r.agg_i == J) ? 1.0 : 0.0;
+        return delta - r.coef * s;
     }
 };
 
@@ -977,6 +988,9 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
     }
     const int64_t row = dev::xcd_block() * groups + group;  // XCD-contiguous row ranges
     const bool active = row < nrows;
+    // the epilogue's row words, issued now and first needed at the write-out
+    typename EPI::Row er{};
+    if (NUM && active) er = epi.row((int32_t)row);
     for (int32_t s = lane; s < H; s += G) {
         keys[s] = -1;
         if (NUM) vals[s] = 0.0;
@@ -1086,7 +1100,7 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
                 int32_t rank = 0;
                 for (int32_t u = 0; u < m; ++u) rank += stJ[u] < J;
                 ccol[out0 + rank] = J;
-                cval[out0 + rank] = epi(i, J, stV[t]);
+                cval[out0 + rank] = epi(er, J, stV[t]);
             }
         } else {
             for (int32_t s = lane; s < H; s += G) {
@@ -1098,7 +1112,7 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
                     rank += (K2 >= 0 && K2 < J);
                 }
                 ccol[out0 + rank] = J;
-                cval[out0 + rank] = epi(i, J, vals[s]);
+                cval[out0 + rank] = epi(er, J, vals[s]);
             }
         }
     }
