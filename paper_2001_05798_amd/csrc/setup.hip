@@ -1029,7 +1029,20 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
                 continue;
             }
             if (lane < m) {
-                for (int32_t t = 0; t < len; ++t) {
+                int32_t t = 0;
+                for (; t + 1 < len; t += 2) {
+                    int32_t J0, J1;
+                    double b0, b1;
+                    br.get(base, t, J0, b0);
+                    br.get(base, t + 1, J1, b1);
+                    stJ[excl + t] = J0;
+                    stJ[excl + t + 1] = J1;
+                    if (NUM) {
+                        stV[excl + t] = a * b0;
+                        stV[excl + t + 1] = a * b1;
+                    }
+                }
+                if (t < len) {
                     int32_t J;
                     double bv;
                     br.get(base, t, J, bv);
