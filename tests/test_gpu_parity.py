@@ -235,6 +235,29 @@ def test_vcycle_parity(gw, ref, precision):
     assert np.allclose(host(y), ref.spmv(A, x), rtol=1e-13, atol=1e-13 * np.abs(ref.spmv(A, x)).max())
 
 
+@pytest.mark.parametrize("npre,npost", [(0, 1), (1, 1), (1, 2), (2, 1), (3, 2), (2, 0)])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_vcycle_sweep_counts(gw, ref, npre, npost, precision):
+    """The V-cycle against the oracle's for each way a level can start: no
+    pre-sweep (x = 0), one (on the coarse levels the restriction writes x1 =
+    M b and the level forms its residual from it), two or more (a sweep from
+    that x1), with zero to two post-sweeps; three smoothed levels."""
+    _say(f"vcycle sweeps {npre}/{npost} precision={precision}")
+    p = gi.heterogeneous_aquifer(30, 22, 14, 4.0, 4, 6)
+    A, b = ref.fv_assemble(p)
+    ap = ref.AmgParams(n_coarse=40, npre=npre, npost=npost)
+    Hr = ref.Hierarchy(A, ap)
+    assert Hr.nlevels >= 4
+    K, rowptr, col, val, bd = gpu_assemble(gw, p)
+    Hg = gw.amg_setup(p.grid.n, rowptr, col, val, gpu_params(gw, ap, precision))
+    r = gi.random_vector(p.grid.n, 5)
+    z_ref = Hr.vcycle(r)
+    z = torch.zeros(p.grid.n, dtype=torch.float64, device="cuda")
+    gw.amg_vcycle(Hg, dev(r), z)
+    err = np.linalg.norm(host(z) - z_ref) / np.linalg.norm(z_ref)
+    assert err < (1e-12 if precision == 0 else 1e-5), err
+
+
 FLOW_CASES = [
     ("C1 2d 64x64 jacobi", lambda: gi.homogeneous_slab(), dict(smoother=0, npre=1, npost=1)),
     ("3d 40x32x16 s2=4 wells", lambda: gi.heterogeneous_aquifer(40, 32, 16, 4.0, 8, 11), dict()),
