@@ -83,7 +83,8 @@ class StepInfoC(C.Structure):
 class LevelInfoC(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("nc", C.c_int32), ("nnz_p", C.c_int64),
                 ("nnz_s", C.c_int64), ("mis_rounds", C.c_int32), ("omega_p", C.c_double),
-                ("bytes", C.c_size_t), ("slice_rows", C.c_int32), ("nnz_sliced", C.c_int64)]
+                ("bytes", C.c_size_t), ("slice_rows", C.c_int32), ("nnz_sliced", C.c_int64),
+                ("stencil_offsets", C.c_int32)]
 
 
 class KernelStatC(C.Structure):
@@ -417,6 +418,7 @@ class LevelInfo:
     bytes: int
     slice_rows: int = 0
     nnz_sliced: int = 0
+    stencil_offsets: int = 0
 
 
 class Hierarchy:
@@ -445,7 +447,7 @@ class Hierarchy:
         _check(_lib.amg_hierarchy_info(self._h, arr, 32, C.byref(nl), C.byref(nb)))
         k = max(1, nl.value)
         return ([LevelInfo(a.n, a.nnz, a.nc, a.nnz_p, a.nnz_s, a.mis_rounds, a.omega_p, a.bytes, a.slice_rows,
-                           a.nnz_sliced) for a in arr[:k]], int(nb.value))
+                           a.nnz_sliced, a.stencil_offsets) for a in arr[:k]], int(nb.value))
 
     @property
     def nlevels(self) -> int:

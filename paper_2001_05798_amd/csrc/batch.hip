@@ -151,13 +151,15 @@ OpCsrDyn<V> dyn(const Csr &A, const V *val) {
 
 template <class F>
 void with_l0(const Level &L0, F &&f) {
-    if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
+    if (L0.St.built()) f(sten_op<double>(L0.St, L0.St.c.p));
+    else if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
     else f(dyn<double>(L0.A, L0.A.val.p));
 }
 
 template <class V, class F>
 void with_level_dyn(const Level &Lv, F &&f) {
-    if (Lv.As.built() && LevelOps<V>::asval(Lv)) f(OpSell<V>{view(Lv.As), LevelOps<V>::asval(Lv)});
+    if (Lv.St.built() && LevelOps<V>::stval(Lv)) f(sten_op<V>(Lv.St, LevelOps<V>::stval(Lv)));
+    else if (Lv.As.built() && LevelOps<V>::asval(Lv)) f(OpSell<V>{view(Lv.As), LevelOps<V>::asval(Lv)});
     else f(dyn<V>(Lv.A, LevelOps<V>::aval(Lv)));
 }
 
@@ -206,7 +208,7 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         if (x1_ready) break;
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n;
-        const double abytes = op_bytes(Lv.A, Lv.As, vb);
+        const double abytes = op_bytes(Lv, vb);
         with_level_dyn<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             B.put(SmoothFirstK<OP, V, Bt, V, NR>{n, op, LevelOps<V>::mval(Lv), b[a], x[a], npre >= 2 ? 1 : 0,
@@ -219,7 +221,7 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
         for (int a : fine) {
             Level &Lv = S[act[a]].H->L[l];
             const int64_t n = Lv.A.n;
-            const double abytes = op_bytes(Lv.A, Lv.As, vb);
+            const double abytes = op_bytes(Lv, vb);
             auto *yo = yout_of(a);
             using YT = std::remove_pointer_t<decltype(yo)>;
             with_level_dyn<V>(Lv, [&](auto op) {
@@ -240,7 +242,7 @@ std::vector<void *> rec_vcycle(Plan &P, Seq &q, std::vector<Sys> &S, const std::
     for (int a : fine) {
         Level &Lv = S[act[a]].H->L[l];
         const int64_t n = Lv.A.n;
-        const double abytes = op_bytes(Lv.A, Lv.As, vb);
+        const double abytes = op_bytes(Lv, vb);
         with_level_dyn<V>(Lv, [&](auto op) {
             using OP = decltype(op);
             B.put(ResidualK<OP, V, Bt, V, V, NR>{n, op, b[a], x[a], t[a], S[act[a]].done}, grid_rows(n, op.lanes()),
@@ -418,13 +420,13 @@ void BatchEngine::join(void *tag, amg_hierarchy *H, const double *b0, const doub
     Sys &y = m->sys;
     y.H = H;
     y.n = L0.A.n;
-    const int G = L0.As.built() ? 1 : L0.A.grp;
+    const int G = (L0.St.built() || L0.As.built()) ? 1 : L0.A.grp;
     y.g1 = kgrid(y.n, 1);
     y.gG = kgrid(y.n, G);
     y.part = H->partials.p;
     y.ks = ks_.p + (size_t)m->slot * nrec_;
     y.done = kind_ == 0 ? &y.ks->done : &y.ks[2].done;
-    y.abytes = op_bytes(L0.A, L0.As, 8);
+    y.abytes = op_bytes(L0, 8);
     const int64_t len = kind_ == 0 ? y.n : 2 * y.n;
     for (int k = 0; k < (kind_ == 0 ? kCgVecs : 10); ++k) m->v[k] = H->kvec.p + k * len;
     m->plan[0] = m->plan[1] = PollPlan{check_, false};

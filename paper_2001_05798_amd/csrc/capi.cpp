@@ -413,6 +413,7 @@ int amg_hierarchy_info(const amg_hierarchy *H, amg_level_info *out, int32_t max_
             o.bytes = Lv.bytes() + (l == H->nlev - 1 ? H->lu.bytes() + H->inv.bytes() + H->piv.bytes() : 0);
             o.slice_rows = Lv.As.built() ? 1 << Lv.As.cshift : 0;
             o.nnz_sliced = Lv.As.built() ? Lv.As.nnz_padded : 0;
+            o.stencil_offsets = Lv.St.K;
         }
         return GW_OK;
     });

@@ -262,6 +262,23 @@ struct SellView {
 };
 inline SellView view(const Sell &S) { return {S.n, S.ndict, S.cshift, S.soff.p, S.idx.p, S.col.p, S.dict.p}; }
 
+// Symmetric stencil copy of the level-0 operator, taken before the sliced
+// copy: when the column offsets (col - row) are a symmetric set {-d_K ..
+// -d_1, 0, d_1 .. d_K} with K <= kStenMax (the 3-, 5- and 7-point
+// operators) and every a_{i,i-d} equals a_{i-d,i} bit for bit, row i is
+// read from the diagonal and c_k[i] = a_{i,i+d_k} (0 where absent), and its
+// entries left of the diagonal from the mirror rows, c_k[i-d_k]: K+1 values
+// a row, every load coalesced, no column indices.
+constexpr int kStenMax = 3;
+struct Stencil {
+    int32_t n = 0, K = 0;
+    int32_t d[kStenMax] = {};  // positive offsets, ascending
+    DBuf<double> c;             // (K+1) n: the diagonal, then c_1 .. c_K
+    DBuf<float> c32;
+    bool built() const { return K > 0; }
+    size_t bytes() const { return c.bytes() + c32.bytes(); }
+};
+
 // ------------------------------------------------------------ hierarchy --
 // Level-synchronous schedule of a triangular (more generally acyclic) system
 // M x = b: per row its count of off-diagonal dependencies, the rows that
@@ -291,6 +308,7 @@ struct IluData {
 struct Level {
     Csr A;           // operator A_l (level 0: copy of the caller's matrix)
     Sell As;         // sliced ELL copy of A_l used by the solve phase (level 0)
+    Stencil St;      // symmetric stencil copy (level 0), preferred to As
     Csr P, R;        // prolongator n x nc and its transpose (empty on coarsest)
     DBuf<int32_t> agg;
     DBuf<double> M;  // smoother diagonal
@@ -305,7 +323,7 @@ struct Level {
     DBuf<char> vb, vx, vt;
     std::unique_ptr<IluData> ilu;  // ILU(0) smoother (else the diagonal M)
     size_t bytes() const {
-        return A.bytes() + As.bytes() + P.bytes() + R.bytes() + agg.bytes() + M.bytes() + M32.bytes() +
+        return A.bytes() + As.bytes() + St.bytes() + P.bytes() + R.bytes() + agg.bytes() + M.bytes() + M32.bytes() +
                vb.bytes() + vx.bytes() + vt.bytes() + (ilu ? ilu->bytes() : 0);
     }
 };
@@ -331,6 +349,7 @@ struct amg_hierarchy {
     std::vector<gw::Level> L;
     int32_t nd = 0;  // coarsest size
     int sym_pattern = -1;  // level-0 pattern symmetric: -1 not known yet, 0 no, 1 yes
+    int sym_values = -1;   // level-0 values symmetric bit for bit (probed with the pattern)
     gw::DBuf<double> lu, inv;  // row-major LU, column-major inverse
     gw::DBuf<int32_t> piv;
     // Krylov workspace

@@ -12,6 +12,7 @@
 // one-byte indices into a sorted offset dictionary (9 B per entry in FP64, 5
 // B in FP32, instead of 12 / 8 with int32 columns).
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "gw_device.h"
@@ -180,6 +181,121 @@ __global__ void k_sell_fill(CsrView A, int cshift, const int32_t *__restrict__ s
     }
 }
 
+// ---------------------------------------------------- stencil copy ------
+struct StenArgs {
+    int32_t K;
+    int32_t d[kStenMax];  // positive offsets, ascending
+};
+
+// Thread per row: the diagonal and the entries right of it, by offset, into
+// the stencil arrays (0 where the row has no such entry).
+__global__ void k_sten_fill(CsrView A, StenArgs sa, double *__restrict__ c, float *__restrict__ c32) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= A.n) return;
+    const int32_t i = (int32_t)row;
+    double v[kStenMax + 1];
+#pragma unroll
+    for (int k = 0; k <= kStenMax; ++k) v[k] = 0.0;
+    const int32_t e = A.rowptr[i + 1];
+    for (int32_t p = A.rowptr[i]; p < e; ++p) {
+        const int32_t dd = A.col[p] - i;
+        const double a = A.val[p];
+        if (dd == 0) v[0] = a;
+#pragma unroll
+        for (int k = 0; k < kStenMax; ++k)
+            if (k < sa.K && dd == sa.d[k]) v[1 + k] = a;
+    }
+    const int64_t n = A.n;
+#pragma unroll
+    for (int k = 0; k <= kStenMax; ++k) {
+        if (k > sa.K) break;
+        c[k * n + i] = v[k];
+        if (c32) c32[k * n + i] = (float)v[k];
+    }
+}
+
+// Thread per row j: each entry left of the diagonal, a_{j,j-d_k} (0 where
+// absent), against the mirror row's stored c_k[j-d_k], bit for bit; any
+// difference sets *bad (one atomic per block).
+__global__ void __launch_bounds__(kBlock) k_sten_check(CsrView A, StenArgs sa, const double *__restrict__ c,
+                                                       int32_t *bad) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool mis = false;
+    if (row < A.n) {
+        const int32_t j = (int32_t)row;
+        unsigned long long neg[kStenMax];
+#pragma unroll
+        for (int k = 0; k < kStenMax; ++k) neg[k] = 0ull;
+        const int32_t e = A.rowptr[j + 1];
+        for (int32_t p = A.rowptr[j]; p < e; ++p) {
+            const int32_t dd = A.col[p] - j;
+            if (dd >= 0) continue;
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(A.val[p]);
+#pragma unroll
+            for (int k = 0; k < kStenMax; ++k)
+                if (k < sa.K && -dd == sa.d[k]) neg[k] = bits;
+        }
+        const int64_t n = A.n;
+#pragma unroll
+        for (int k = 0; k < kStenMax; ++k) {
+            if (k >= sa.K) break;
+            const int32_t m = j - sa.d[k];
+            const unsigned long long got =
+                m >= 0 ? (unsigned long long)__double_as_longlong(c[(1 + k) * n + m]) : 0ull;
+            mis = mis || got != neg[k];
+        }
+    }
+    if (__syncthreads_or(mis) && threadIdx.x == 0) atomicOr(bad, 1);
+}
+
+// Whether the offsets (ascending, `count` of them) are a symmetric set
+// around 0 with at most kStenMax positive ones; their positive half into sa.
+bool stencil_shape(const int32_t *offsets, int32_t count, StenArgs &sa) {
+    if (count < 3 || count > 2 * kStenMax + 1 || (count & 1) == 0) return false;
+    const int K = count / 2;
+    if (offsets[K] != 0) return false;
+    sa = StenArgs{};
+    sa.K = K;
+    for (int k = 0; k < K; ++k) {
+        sa.d[k] = offsets[K + 1 + k];
+        if (sa.d[k] <= 0 || offsets[K - 1 - k] != -sa.d[k]) return false;
+    }
+    return true;
+}
+
+// The stencil copy of A with the offsets sa when its values are symmetric
+// bit for bit; false (nothing kept) otherwise.  check = false: the values
+// are known to be symmetric (the setup's pattern probe compared every
+// mirror pair), so the copy is filled without the check and its read.
+bool build_stencil(Level &Lv, const StenArgs &sa, bool fp32, bool check, hipStream_t s, double *bytes) {
+    const int K = sa.K;
+    const CsrView A = view(Lv.A);
+    Stencil St;
+    St.n = A.n;
+    St.c.alloc((size_t)(K + 1) * A.n);
+    if (fp32) St.c32.alloc((size_t)(K + 1) * A.n);
+    hipLaunchKernelGGL(k_sten_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, sa, St.c.p, St.c32.p);
+    // the fill reads the CSR arrays and writes the copy
+    *bytes += 4.0 * (A.n + 1) + 12.0 * (double)A.nnz + (double)(K + 1) * A.n * (8 + (fp32 ? 4 : 0));
+    if (check) {
+        DBuf<int32_t> bad(1);
+        fill_i32(bad.p, 0, 1, s);
+        hipLaunchKernelGGL(k_sten_check, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, sa, St.c.p, bad.p);
+        GW_HIP(hipGetLastError());
+        int32_t *stage = static_cast<int32_t *>(host_stage());
+        GW_HIP(hipMemcpyAsync(stage, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        // the check reads the CSR arrays again and K of the copy's arrays
+        *bytes += 4.0 * (A.n + 1) + 12.0 * (double)A.nnz + 8.0 * K * A.n;
+        if (stage[0] != 0) return false;
+    }
+    GW_HIP(hipGetLastError());
+    St.K = K;
+    for (int k = 0; k < kStenMax; ++k) St.d[k] = sa.d[k];
+    Lv.St = std::move(St);
+    return true;
+}
+
 }  // namespace
 
 void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
@@ -195,18 +311,53 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
     DBuf<unsigned long long> totals(4);
     DBuf<int32_t> table(kOffsetTable);
     DBuf<int32_t> meta(kMeta);
+    // the symmetric stencil copy first (level 0; not for an operator known
+    // to be nonsymmetric; GWAMG_STENCIL=0 keeps the sliced copy).  With
+    // values known to be symmetric the offsets are read first and the
+    // sliced copy's slice-height totals only when the stencil is not taken.
+    Lv.St = Stencil();
+    const char *sten_env = std::getenv("GWAMG_STENCIL");
+    const bool sten_try =
+        l == 0 && H->sym_pattern != 0 && H->sym_values != 0 && !(sten_env && std::atoi(sten_env) == 0);
+    const bool sten_known = sten_try && H->sym_values == 1;
     fill_i32(reinterpret_cast<int32_t *>(totals.p), 0, 8, s);
     fill_i32(table.p, kEmpty, kOffsetTable, s);
     fill_i32(meta.p, 0, kMeta, s);
-    hipLaunchKernelGGL(k_sell_pad, dim3(std::min<unsigned>(blocks_for(A.n), 1024)), dim3(kBlock), 0, s, A.rowptr,
-                       A.n, totals.p);
+    auto launch_pad = [&] {
+        hipLaunchKernelGGL(k_sell_pad, dim3(std::min<unsigned>(blocks_for(A.n), 1024)), dim3(kBlock), 0, s,
+                           A.rowptr, A.n, totals.p);
+    };
+    int32_t *stage = static_cast<int32_t *>(host_stage());
+    auto read_meta = [&] {
+        hipLaunchKernelGGL(k_offset_compact, dim3(1), dim3(1024), 0, s, table.p, meta.p, totals.p);
+        GW_HIP(hipGetLastError());
+        GW_HIP(hipMemcpyAsync(stage, meta.p, sizeof(int32_t) * kMeta, hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+    };
+    if (!sten_known) launch_pad();
     hipLaunchKernelGGL(k_offset_set, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.col, A.n, table.p,
                        meta.p);
-    hipLaunchKernelGGL(k_offset_compact, dim3(1), dim3(1024), 0, s, table.p, meta.p, totals.p);
-    GW_HIP(hipGetLastError());
-    int32_t *stage = static_cast<int32_t *>(host_stage());
-    GW_HIP(hipMemcpyAsync(stage, meta.p, sizeof(int32_t) * kMeta, hipMemcpyDeviceToHost, s));
-    GW_HIP(hipStreamSynchronize(s));
+    read_meta();
+    double sb = 4.0 * (A.n + 1) * (sten_known ? 1 : 2) + 4.0 * (double)A.nnz;  // offset set (and padded totals)
+    bool reread = sten_known;  // the totals come later, or the check reused the stage
+    if (sten_try && stage[0] == 0 && stage[1] <= kSellMaxDict) {
+        StenArgs sa;
+        if (stencil_shape(stage + kMetaDict, stage[1], sa)) {
+            reread = true;
+            if (build_stencil(Lv, sa, fp32, !sten_known, s, &sb)) {
+                ps.bytes = sb;
+                ps.cbytes = sb;
+                return;
+            }
+        }
+    }
+    // the sliced copy: its slice-height totals (when not launched yet) and
+    // the offsets again (the stencil's check may have reused the stage)
+    if (sten_known) {
+        launch_pad();
+        sb += 4.0 * (A.n + 1);
+    }
+    if (reread) read_meta();
     const bool overflow = stage[0] != 0;
     const int32_t count = stage[1];
     int64_t pad[4];
@@ -252,7 +403,7 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
     GW_HIP(hipGetLastError());
     // the padded totals and the widths (row pointers, twice), the offset set
     // (row pointers and columns), the fill (the CSR read, the copy written)
-    ps.bytes = 4.0 * (A.n + 1) * 4 + 4.0 * (double)A.nnz + 12.0 * (double)A.nnz +
+    ps.bytes = sb + 4.0 * (A.n + 1) * 2 + 12.0 * (double)A.nnz +
                (double)padded * (8 + (S.ndict ? 1 : 4) + (fp32 ? 4 : 0)) + 4.0 * (nslices + 1);
     ps.cbytes = ps.bytes;
 }

@@ -293,9 +293,12 @@ __global__ void k_rx_rowptr(const int32_t *__restrict__ key, int64_t nnz, int32_
 // fill or sort.  `miss` is set when some (j, i) is absent (the pattern is not
 // symmetric and the result is discarded); one atomic per block at most, on a
 // capped grid.
+// a_ji into tval at the position of a_ij; *miss bit 0: an entry without its
+// mirror (pattern not symmetric), bit 1: a mirror whose value differs bit for
+// bit (values not symmetric).
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_sym_transpose(CsrView A, double *__restrict__ tval, int32_t *miss) {
-    int32_t bad = 0;
+    int32_t bad = 0, vbad = 0;
     const int lane = (int)(threadIdx.x % G);
     for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; row < A.n;
          row += (int64_t)gridDim.x * blockDim.x / G) {
@@ -309,11 +312,17 @@ __global__ void __launch_bounds__(kBlock) k_sym_transpose(CsrView A, double *__r
                 if (A.col[b + mid] < i) lo = mid + 1;
                 else hi = mid;
             }
-            if (lo < len && A.col[b + lo] == i) tval[p] = A.val[b + lo];
-            else bad = 1;
+            if (lo < len && A.col[b + lo] == i) {
+                const double aji = A.val[b + lo];
+                tval[p] = aji;
+                vbad |= __double_as_longlong(aji) != __double_as_longlong(A.val[p]);
+            } else {
+                bad = 1;
+            }
         }
     }
-    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(miss, 1);
+    const int32_t w = (__syncthreads_or(bad) ? 1 : 0) | (__syncthreads_or(vbad) ? 2 : 0);
+    if (w && threadIdx.x == 0) atomicOr(miss, w);
 }
 
 // --------------------------------------------------------------- strength --
@@ -2206,8 +2215,10 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             // word is checked with the level's next read
             sym = true;
         } else {
-            sym = st.read(miss, s) == 0;
+            const int32_t w = st.read(miss, s);
+            sym = (w & 1) == 0;
             H->sym_pattern = sym ? 1 : 0;
+            if (l == 0) H->sym_values = w == 0 ? 1 : 0;
         }
     }
     const bool check_sym = sym && l > 0;
@@ -2358,7 +2369,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         rounds += batch;
     }
     Lv.mis_rounds = rounds;
-    if (check_sym && rd.h[2] != 0) fail(GW_EDEVICE, "amg_setup: a Galerkin level lost its symmetric pattern");
+    if (check_sym && (rd.h[2] & 1) != 0) fail(GW_EDEVICE, "amg_setup: a Galerkin level lost its symmetric pattern");
     m1.release();
     done.release();
     S.nnz = rd.h64(0);

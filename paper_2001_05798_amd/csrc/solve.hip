@@ -118,7 +118,7 @@ void *vcycle_level_ilu(amg_hierarchy *H, int l, const double *b, Zt *out, const 
     double *x = reinterpret_cast<double *>(Lv.vx.p);
     double *t = reinterpret_cast<double *>(Lv.vt.p);
     const int npre = H->prm.npre, npost = H->prm.npost;
-    const double abytes = op_bytes(Lv.A, Lv.As, 8);
+    const double abytes = op_bytes(Lv, 8);
     auto residual = [&](const double *xin, double *r) {
         ProfScope ps(level_kid(K_RESIDUAL0, l), abytes + n * 24.0, s, true);
         with_level_op<double>(Lv, [&](auto op) {
@@ -189,7 +189,7 @@ void *vcycle_level(amg_hierarchy *H, int l, const Bt *b, Zt *out, const int32_t 
         return y;
     }
     const V *M = LevelOps<V>::mval(Lv);
-    const double abytes = op_bytes(Lv.A, Lv.As, vb), cabytes = csr_bytes(n, Lv.A.nnz, vb);
+    const double abytes = op_bytes(Lv, vb), cabytes = csr_bytes(n, Lv.A.nnz, vb);
     V *x = reinterpret_cast<V *>(Lv.vx.p);
     V *t = reinterpret_cast<V *>(Lv.vt.p);
     const int npre = H->prm.npre, npost = H->prm.npost;
@@ -551,23 +551,25 @@ struct Kry {
 
     Kry(amg_hierarchy *H_, hipStream_t s_, double rtol_) : Kry(H_, hier_work(H_), s_, rtol_) {}
     Kry(amg_hierarchy *H_, const KWork &W, hipStream_t s_, double rtol_) : H(H_), L0(H_->L[0]), s(s_), rtol(rtol_) {
-        G = L0.As.built() ? 1 : L0.A.grp;
+        G = (L0.St.built() || L0.As.built()) ? 1 : L0.A.grp;
         n = L0.A.n;
         g1 = kgrid(n, 1);
         gG = kgrid(n, G);
         part = W.part;
         ks = W.ks;
         vec = 8.0 * n;
-        abytes = op_bytes(L0.A, L0.As, 8);
+        abytes = op_bytes(L0, 8);
         cabytes = csr_bytes(n, L0.A.nnz, 8);
     }
     template <bool SHIFT = false, class F>
     void op(F &&f) const {
         if constexpr (SHIFT) {
-            if (L0.As.built()) f(OpShift<OpSell<double>>{OpSell<double>{view(L0.As), L0.As.val.p}, shift});
+            if (L0.St.built()) f(OpShift<OpSten<double>>{sten_op<double>(L0.St, L0.St.c.p), shift});
+            else if (L0.As.built()) f(OpShift<OpSell<double>>{OpSell<double>{view(L0.As), L0.As.val.p}, shift});
             else with_csr<double>(L0.A, L0.A.val.p, [&](auto o) { f(OpShift<decltype(o)>{o, shift}); });
         } else {
-            if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
+            if (L0.St.built()) f(sten_op<double>(L0.St, L0.St.c.p));
+            else if (L0.As.built()) f(OpSell<double>{view(L0.As), L0.As.val.p});
             else with_csr<double>(L0.A, L0.A.val.p, f);
         }
     }
@@ -677,12 +679,13 @@ void vcycle2(amg_hierarchy *H, const double *r, double *z, const int32_t *done, 
 void spmv_level0(amg_hierarchy *H, const double *x, double *y, hipStream_t s) {
     const Level &L0 = H->L[0];
     const int64_t n = L0.A.n;
-    ProfScope ps(K_KRYLOV_SPMV, op_bytes(L0.A, L0.As, 8) + 16.0 * n, s, false, csr_bytes(n, L0.A.nnz, 8) + 16.0 * n);
+    ProfScope ps(K_KRYLOV_SPMV, op_bytes(L0, 8) + 16.0 * n, s, false, csr_bytes(n, L0.A.nnz, 8) + 16.0 * n);
     auto launch = [&](auto o) {
         using OP = decltype(o);
         hipLaunchKernelGGL((k_spmv_f64<OP>), dim3(grid_rows(n, OP::G)), dim3(kBlock), 0, s, n, o, x, y);
     };
-    if (L0.As.built()) launch(OpSell<double>{view(L0.As), L0.As.val.p});
+    if (L0.St.built()) launch(sten_op<double>(L0.St, L0.St.c.p));
+    else if (L0.As.built()) launch(OpSell<double>{view(L0.As), L0.As.val.p});
     else with_csr<double>(L0.A, L0.A.val.p, launch);
     GW_HIP(hipGetLastError());
 }

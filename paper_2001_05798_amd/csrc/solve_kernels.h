@@ -311,6 +311,69 @@ struct OpSell {
     }
 };
 
+// The symmetric stencil copy (Stencil): one lane a row, its 2K+1 terms in
+// column order -- left neighbours i - d_k from the mirror rows' arrays
+// c_k[i - d_k], the diagonal, right neighbours from c_k[i] -- summed as the
+// sliced copy sums the same entries.  Terms of a neighbour outside the
+// matrix, or of k >= K, carry 0 and read x at a clamped index (a finite x
+// adds an exact zero).  No head to load and no dictionary.
+template <class V>
+struct OpSten {
+    static constexpr int G = 1;
+    static constexpr bool kShared = false;
+    __device__ __host__ static constexpr int lanes() { return 1; }
+    struct Head {
+        __device__ __forceinline__ void keep() const {}
+    };
+    int32_t n, K;
+    int32_t d[kStenMax];
+    const V *c;
+    __device__ __forceinline__ void load(int32_t *) const {}
+    __device__ __forceinline__ Head head(int64_t) const { return {}; }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows_at(const Head &, int64_t i, int, const int32_t *, F &&xj) const {
+        constexpr int T = 2 * kStenMax + 1;
+        V a[T];
+        int32_t cj[T];
+        const int32_t ii = (int32_t)i;
+        // slot kStenMax-1-k: left term of d_k; kStenMax: the diagonal;
+        // kStenMax+1+k: right term of d_k
+#pragma unroll
+        for (int k = 0; k < kStenMax; ++k) {
+            const int32_t dk = k < K ? d[k] : 0;
+            const bool lin = k < K && ii >= dk;
+            const bool rin = k < K && ii + dk < n;
+            const int64_t base = (int64_t)(k < K ? 1 + k : 0) * n;
+            const V al = c[base + (lin ? ii - dk : ii)];
+            const V ar = c[base + ii];
+            a[kStenMax - 1 - k] = lin ? al : V(0);
+            cj[kStenMax - 1 - k] = lin ? ii - dk : ii;
+            a[kStenMax + 1 + k] = rin ? ar : V(0);
+            cj[kStenMax + 1 + k] = rin ? ii + dk : ii;
+        }
+        a[kStenMax] = c[ii];
+        cj[kStenMax] = ii;
+        VecN<V, NR> acc;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc.v[k] = 0;
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const VecN<V, NR> xv = xj(cj[u]);
+#pragma unroll
+            for (int k = 0; k < NR; ++k) acc.v[k] += a[u] * xv.v[k];
+        }
+        return acc;
+    }
+    template <int NR, class F>
+    __device__ __forceinline__ VecN<V, NR> rows(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows_at<NR>(head(i), i, lane, sd, xj);
+    }
+    template <class F>
+    __device__ __forceinline__ V row(int64_t i, int lane, const int32_t *sd, F &&xj) const {
+        return rows<1>(i, lane, sd, [&](int32_t j) { return VecN<V, 1>{{(V)xj(j)}}; }).v[0];
+    }
+};
+
 // A + diag(d): the level-0 operator with a diagonal added, for the storage
 // term S/dt of Eq. 2 when the hierarchy of the conductance matrix is kept.
 template <class B>
@@ -1347,9 +1410,14 @@ __global__ void __launch_bounds__(kBlock) k_seg(const Seg<A> *__restrict__ t, co
 // (int32 columns + row pointers for CSR; one-byte offsets or int32 columns,
 // padding included, + slice offsets for sliced ELL).
 inline double csr_bytes(int64_t n, int64_t nnz, int vbytes) { return (double)nnz * (vbytes + 4) + 4.0 * (n + 1); }
-inline double op_bytes(const Csr &A, const Sell &S, int vbytes) {
+// Bytes of one pass over a level's operator in the format the solve
+// kernels read: the stencil copy's K+1 arrays (the mirror rows' reads hit
+// the same arrays), the sliced copy, or the CSR arrays.
+inline double op_bytes(const Level &L, int vbytes) {
+    if (L.St.built()) return (double)(L.St.K + 1) * L.St.n * vbytes;
+    const Sell &S = L.As;
     if (S.built()) return (double)S.nnz_padded * (vbytes + (S.ndict ? 1 : 4)) + 4.0 * (S.nslices + 1);
-    return csr_bytes(A.n, A.nnz, vbytes);
+    return csr_bytes(L.A.n, L.A.nnz, vbytes);
 }
 
 inline unsigned grid_rows(int64_t n, int G) { return blocks_for(n * G); }
@@ -1369,6 +1437,7 @@ template <class V>
 struct LevelOps;
 template <>
 struct LevelOps<double> {
+    static const double *stval(const Level &L) { return L.St.c.p; }
     static const double *aval(const Level &L) { return L.A.val.p; }
     static const double *asval(const Level &L) { return L.As.val.p; }
     static const double *pval(const Level &L) { return L.P.val.p; }
@@ -1377,6 +1446,7 @@ struct LevelOps<double> {
 };
 template <>
 struct LevelOps<float> {
+    static const float *stval(const Level &L) { return L.St.c32.p; }
     static const float *aval(const Level &L) { return L.A.val32.p; }
     static const float *asval(const Level &L) { return L.As.val32.p; }
     static const float *pval(const Level &L) { return L.P.val32.p; }
@@ -1398,10 +1468,19 @@ void with_csr(const Csr &A, const V *val, F &&f) {
     }
 }
 
-// Call f(op) with the level's operator: the sliced ELL copy when built.
+template <class V>
+OpSten<V> sten_op(const Stencil &S, const V *c) {
+    OpSten<V> o{S.n, S.K, {}, c};
+    for (int k = 0; k < kStenMax; ++k) o.d[k] = S.d[k];
+    return o;
+}
+
+// Call f(op) with the level's operator: the stencil copy, else the sliced
+// ELL copy, when built.
 template <class V, class F>
 void with_level_op(const Level &Lv, F &&f) {
-    if (Lv.As.built() && LevelOps<V>::asval(Lv)) f(OpSell<V>{view(Lv.As), LevelOps<V>::asval(Lv)});
+    if (Lv.St.built() && LevelOps<V>::stval(Lv)) f(sten_op<V>(Lv.St, LevelOps<V>::stval(Lv)));
+    else if (Lv.As.built() && LevelOps<V>::asval(Lv)) f(OpSell<V>{view(Lv.As), LevelOps<V>::asval(Lv)});
     else with_csr<V>(Lv.A, LevelOps<V>::aval(Lv), f);
 }
 

@@ -116,7 +116,7 @@ def test_amg_params_layout_and_validation():
 
 
 @pytest.mark.parametrize("struct,cls,field", [
-    ("amg_level_info", "LevelInfoC", "nnz_sliced"),
+    ("amg_level_info", "LevelInfoC", "stencil_offsets"),
     ("amg_solve_params", "SolveParamsC", None),
     ("amg_solve_info", "SolveInfoC", None),
     ("gw_kernel_stat", "KernelStatC", "bytes_csr"),

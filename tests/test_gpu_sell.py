@@ -1,10 +1,13 @@
-"""The sliced copy of the level-0 operator: its slice height and stored entry
-count against a count made on the host from the operator's row lengths (each
-slice of C rows as wide as its longest row; C the largest of 64, 32, 16, 8
-whose count is within 2 % of the count at 8), for the 7-point flow operator
-and the upwind travel-time operator (rows of 1 to 7 entries, short slices);
-and the travel-time pair solved on short slices against the oracle's exact
-sweep.
+"""The level-0 copies the solve kernels read.  The sliced copy: its slice
+height and stored entry count against a count made on the host from the
+operator's row lengths (each slice of C rows as wide as its longest row; C
+the largest of 64, 32, 16, 8 whose count is within 2 % of the count at 8),
+for the 7-point flow operator (stencil copy switched off) and the upwind
+travel-time operator (rows of 1 to 7 entries, short slices); the travel-time
+pair solved on short slices against the oracle's exact sweep.  The symmetric
+stencil copy: taken by the 7- and 5-point flow operators, the same PCG
+iterates bit for bit as on the sliced copy, and not taken when one value
+breaks the symmetry.
 """
 import sys
 
@@ -58,8 +61,9 @@ def _tt_operator(ref, nx, ny, nz, s2, lam, seed):
 
 
 @pytest.mark.parametrize("case", [(48, 40, 20, 4.0, 6, 61), (37, 29, 11, 1.0, 3, 62)], ids=["48x40x20", "37x29x11"])
-def test_slice_height_and_padding(gw, ref, case):
+def test_slice_height_and_padding(gw, ref, case, monkeypatch):
     _say(f"sliced copy {case}")
+    monkeypatch.setenv("GWAMG_STENCIL", "0")
     p, _, A, bt, bc = _tt_operator(ref, *case)
     n = p.grid.n
     for name, (rowptr, col, val), prm in (
@@ -97,3 +101,50 @@ def test_pair_on_short_slices_against_oracle(gw, ref):
         err = np.linalg.norm(got.cpu().numpy() - want) / np.linalg.norm(want)
         _say(f"  iters {i0.iters}/{i1.iters}, rel err {err:.2e}")
         assert err <= 1e-8
+
+
+def _pcg(gw, n, rowptr, col, val, b):
+    H = gw.amg_setup(n, dev(rowptr), dev(col), dev(val), gw.AmgParams.flow())
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    info = gw.amg_solve_pcg(H, dev(b), x, gw.SolveParams(rtol=1e-10))
+    assert info.status == gw.OK
+    return H.info()[0][0], x.cpu().numpy(), info.iters
+
+
+@pytest.mark.parametrize("make,k", [(lambda: gi.heterogeneous_aquifer(37, 29, 11, 1.0, 3, 62), 3),
+                                    (lambda: gi.homogeneous_slab(), 2)], ids=["7-point", "5-point"])
+def test_flow_operator_takes_the_stencil_copy(gw, ref, make, k, monkeypatch):
+    p = make()
+    _say(f"stencil copy {p.grid.nx}x{p.grid.ny}x{p.grid.nz}")
+    A, b = ref.fv_assemble(p)
+    n = p.grid.n
+    lv, x, it = _pcg(gw, n, A.rowptr, A.col, A.val, b)
+    assert (lv.stencil_offsets, lv.slice_rows, lv.nnz_sliced) == (k, 0, 0)
+    monkeypatch.setenv("GWAMG_STENCIL", "0")
+    lv2, x2, it2 = _pcg(gw, n, A.rowptr, A.col, A.val, b)
+    assert lv2.stencil_offsets == 0 and lv2.slice_rows > 0
+    _say(f"  iterations {it} (stencil) / {it2} (sliced)")
+    assert it == it2
+    assert np.array_equal(x.view(np.uint64), x2.view(np.uint64))
+    want = ref.pcg(ref.Hierarchy(A, ref.AmgParams(eps_strong=0.03, npre=1, npost=1)), b, rtol=1e-10)[0]
+    assert np.linalg.norm(x - want) <= 1e-8 * np.linalg.norm(want)
+
+
+def test_asymmetric_values_keep_the_sliced_copy(gw, ref):
+    # found by the setup's pattern probe (AMG preconditioner), or by the
+    # copy's own check of every mirror pair (no preconditioner: no probe)
+    p = gi.heterogeneous_aquifer(37, 29, 11, 1.0, 3, 62)
+    _say("one value off its mirror: sliced copy")
+    A, b = ref.fv_assemble(p)
+    n = p.grid.n
+    val = A.val.copy()
+    # an off-diagonal entry right of the diagonal in the middle row
+    i = n // 2
+    q = next(q for q in range(A.rowptr[i], A.rowptr[i + 1]) if A.col[q] > i)
+    val[q] = np.nextafter(val[q], 0.0)
+    lv, x, it = _pcg(gw, n, A.rowptr, A.col, val, b)
+    assert lv.stencil_offsets == 0 and lv.slice_rows > 0
+    for v, k in ((A.val, 3), (val, 0)):
+        H = gw.amg_setup(n, dev(A.rowptr), dev(A.col), dev(v), gw.AmgParams(smoother=gw.SMOOTHER_NONE))
+        lv = H.info()[0][0]
+        assert lv.stencil_offsets == k and (lv.slice_rows > 0) == (k == 0)
