@@ -151,11 +151,12 @@ typedef struct {
     int64_t nnz_sliced;   /* entries the sliced copy stores, padding
                              included (each slice as wide as its longest
                              row)                                          */
-    int32_t stencil_offsets; /* positive column offsets of the symmetric
-                             stencil copy the solve kernels read instead
-                             of the sliced copy (1-3: the 3-, 5- and
-                             7-point operators with bitwise symmetric
-                             values), 0: none                              */
+    int32_t stencil_offsets; /* positive column offsets of the stencil
+                             copy the solve kernels read instead of the
+                             sliced copy (1-3: 3-, 5- and 7-point
+                             operators), symmetric (values equal to their
+                             mirrors bit for bit) or one-sided (upwind: one
+                             negative value per face), 0: none            */
 } amg_level_info;
 
 typedef struct amg_hierarchy amg_hierarchy;

@@ -269,10 +269,16 @@ inline SellView view(const Sell &S) { return {S.n, S.ndict, S.cshift, S.soff.p, 
 // read from the diagonal and c_k[i] = a_{i,i+d_k} (0 where absent), and its
 // entries left of the diagonal from the mirror rows, c_k[i-d_k]: K+1 values
 // a row, every load coalesced, no column indices.
+// One-sided form, for upwind operators (every off-diagonal strictly
+// negative, and a_{i,i+d} and a_{i+d,i} never both stored): c_k[i] holds the
+// face between rows i and i+d_k, as a_{i,i+d_k} (negative) when row i holds
+// it, as -a_{i+d_k,i} (positive) when row i+d_k does, 0 when neither; row i
+// takes c_k[i] when negative and -c_k[i-d_k] when c_k[i-d_k] is positive.
 constexpr int kStenMax = 3;
 struct Stencil {
     int32_t n = 0, K = 0;
     int32_t d[kStenMax] = {};  // positive offsets, ascending
+    int32_t onesided = 0;       // the one-sided (upwind) form
     DBuf<double> c;             // (K+1) n: the diagonal, then c_1 .. c_K
     DBuf<float> c32;
     bool built() const { return K > 0; }

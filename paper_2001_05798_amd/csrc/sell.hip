@@ -248,6 +248,63 @@ __global__ void __launch_bounds__(kBlock) k_sten_check(CsrView A, StenArgs sa, c
     if (__syncthreads_or(mis) && threadIdx.x == 0) atomicOr(bad, 1);
 }
 
+// One-sided (upwind) form, thread per row i: the diagonal, and for each d_k
+// the face between rows i and i+d_k from row i's entry at +d_k (stored as
+// is) or row i+d_k's entry at -d_k (stored negated).  Sets *bad when an
+// off-diagonal entry of row i is not strictly negative or a face is stored
+// by both rows.
+__global__ void k_sten_onesided(CsrView A, StenArgs sa, double *__restrict__ c, float *__restrict__ c32,
+                                int32_t *bad) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool mis = false;
+    if (row < A.n) {
+        const int32_t i = (int32_t)row;
+        const int64_t n = A.n;
+        double v0 = 0.0, right[kStenMax];
+        bool has[kStenMax];
+#pragma unroll
+        for (int k = 0; k < kStenMax; ++k) {
+            right[k] = 0.0;
+            has[k] = false;
+        }
+        const int32_t e = A.rowptr[i + 1];
+        for (int32_t p = A.rowptr[i]; p < e; ++p) {
+            const int32_t dd = A.col[p] - i;
+            const double a = A.val[p];
+            if (dd == 0) {
+                v0 = a;
+                continue;
+            }
+            mis = mis || !(a < 0.0);
+#pragma unroll
+            for (int k = 0; k < kStenMax; ++k)
+                if (k < sa.K && dd == sa.d[k]) {
+                    right[k] = a;
+                    has[k] = true;
+                }
+        }
+        c[i] = v0;
+        if (c32) c32[i] = (float)v0;
+#pragma unroll
+        for (int k = 0; k < kStenMax; ++k) {
+            if (k >= sa.K) break;
+            double f = has[k] ? right[k] : 0.0;
+            const int32_t j = i + sa.d[k];
+            if (j < A.n) {
+                const int32_t ej = A.rowptr[j + 1];
+                for (int32_t p = A.rowptr[j]; p < ej; ++p) {
+                    if (A.col[p] != i) continue;
+                    mis = mis || has[k];
+                    f = -A.val[p];
+                }
+            }
+            c[(1 + k) * n + i] = f;
+            if (c32) c32[(1 + k) * n + i] = (float)f;
+        }
+    }
+    if (__syncthreads_or(mis) && threadIdx.x == 0) atomicOr(bad, 1);
+}
+
 // Whether the offsets (ascending, `count` of them) are a symmetric set
 // around 0 with at most kStenMax positive ones; their positive half into sa.
 bool stencil_shape(const int32_t *offsets, int32_t count, StenArgs &sa) {
@@ -267,13 +324,33 @@ bool stencil_shape(const int32_t *offsets, int32_t count, StenArgs &sa) {
 // bit for bit; false (nothing kept) otherwise.  check = false: the values
 // are known to be symmetric (the setup's pattern probe compared every
 // mirror pair), so the copy is filled without the check and its read.
-bool build_stencil(Level &Lv, const StenArgs &sa, bool fp32, bool check, hipStream_t s, double *bytes) {
+bool build_stencil(Level &Lv, const StenArgs &sa, bool onesided, bool fp32, bool check, hipStream_t s,
+                   double *bytes) {
     const int K = sa.K;
     const CsrView A = view(Lv.A);
     Stencil St;
     St.n = A.n;
     St.c.alloc((size_t)(K + 1) * A.n);
     if (fp32) St.c32.alloc((size_t)(K + 1) * A.n);
+    if (onesided) {
+        // the fill checks as it goes: the CSR read for row i and its K
+        // neighbours' rows, the copy written
+        DBuf<int32_t> bad(1);
+        fill_i32(bad.p, 0, 1, s);
+        hipLaunchKernelGGL(k_sten_onesided, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, sa, St.c.p, St.c32.p,
+                           bad.p);
+        GW_HIP(hipGetLastError());
+        int32_t *stage = static_cast<int32_t *>(host_stage());
+        GW_HIP(hipMemcpyAsync(stage, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GW_HIP(hipStreamSynchronize(s));
+        *bytes += 4.0 * (A.n + 1) + 12.0 * (double)A.nnz + (double)(K + 1) * A.n * (8 + (fp32 ? 4 : 0));
+        if (stage[0] != 0) return false;
+        St.K = K;
+        St.onesided = 1;
+        for (int k = 0; k < kStenMax; ++k) St.d[k] = sa.d[k];
+        Lv.St = std::move(St);
+        return true;
+    }
     hipLaunchKernelGGL(k_sten_fill, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, sa, St.c.p, St.c32.p);
     // the fill reads the CSR arrays and writes the copy
     *bytes += 4.0 * (A.n + 1) + 12.0 * (double)A.nnz + (double)(K + 1) * A.n * (8 + (fp32 ? 4 : 0));
@@ -311,15 +388,17 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
     DBuf<unsigned long long> totals(4);
     DBuf<int32_t> table(kOffsetTable);
     DBuf<int32_t> meta(kMeta);
-    // the symmetric stencil copy first (level 0; not for an operator known
-    // to be nonsymmetric; GWAMG_STENCIL=0 keeps the sliced copy).  With
-    // values known to be symmetric the offsets are read first and the
-    // sliced copy's slice-height totals only when the stencil is not taken.
+    // a stencil copy first (level 0; GWAMG_STENCIL=0 keeps the sliced copy):
+    // the offsets are read first, and the sliced copy's slice-height totals
+    // are formed only when the stencil is not taken.
     Lv.St = Stencil();
     const char *sten_env = std::getenv("GWAMG_STENCIL");
-    const bool sten_try =
-        l == 0 && H->sym_pattern != 0 && H->sym_values != 0 && !(sten_env && std::atoi(sten_env) == 0);
-    const bool sten_known = sten_try && H->sym_values == 1;
+    const bool sten_on = l == 0 && !(sten_env && std::atoi(sten_env) == 0);
+    // symmetric form unless the pattern or the values are known not to be
+    // symmetric; the one-sided form for a pattern known not to be
+    const bool onesided = H->sym_pattern == 0;
+    const bool sten_try = sten_on && (onesided || H->sym_values != 0);
+    const bool sten_known = sten_try && !onesided && H->sym_values == 1;
     fill_i32(reinterpret_cast<int32_t *>(totals.p), 0, 8, s);
     fill_i32(table.p, kEmpty, kOffsetTable, s);
     fill_i32(meta.p, 0, kMeta, s);
@@ -334,17 +413,16 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
         GW_HIP(hipMemcpyAsync(stage, meta.p, sizeof(int32_t) * kMeta, hipMemcpyDeviceToHost, s));
         GW_HIP(hipStreamSynchronize(s));
     };
-    if (!sten_known) launch_pad();
+    // with a stencil to try, the slice-height totals wait until it is refused
+    if (!sten_try) launch_pad();
     hipLaunchKernelGGL(k_offset_set, dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A.rowptr, A.col, A.n, table.p,
                        meta.p);
     read_meta();
-    double sb = 4.0 * (A.n + 1) * (sten_known ? 1 : 2) + 4.0 * (double)A.nnz;  // offset set (and padded totals)
-    bool reread = sten_known;  // the totals come later, or the check reused the stage
+    double sb = 4.0 * (A.n + 1) * (sten_try ? 1 : 2) + 4.0 * (double)A.nnz;  // offset set (and padded totals)
     if (sten_try && stage[0] == 0 && stage[1] <= kSellMaxDict) {
         StenArgs sa;
         if (stencil_shape(stage + kMetaDict, stage[1], sa)) {
-            reread = true;
-            if (build_stencil(Lv, sa, fp32, !sten_known, s, &sb)) {
+            if (build_stencil(Lv, sa, onesided, fp32, !sten_known, s, &sb)) {
                 ps.bytes = sb;
                 ps.cbytes = sb;
                 return;
@@ -352,12 +430,12 @@ void build_sell(amg_hierarchy *H, int l, bool fp32, hipStream_t s) {
         }
     }
     // the sliced copy: its slice-height totals (when not launched yet) and
-    // the offsets again (the stencil's check may have reused the stage)
-    if (sten_known) {
+    // the words read again with them (a check may have reused the stage)
+    if (sten_try) {
         launch_pad();
         sb += 4.0 * (A.n + 1);
+        read_meta();
     }
-    if (reread) read_meta();
     const bool overflow = stage[0] != 0;
     const int32_t count = stage[1];
     int64_t pad[4];

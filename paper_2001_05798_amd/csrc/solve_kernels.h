@@ -311,12 +311,15 @@ struct OpSell {
     }
 };
 
-// The symmetric stencil copy (Stencil): one lane a row, its 2K+1 terms in
-// column order -- left neighbours i - d_k from the mirror rows' arrays
-// c_k[i - d_k], the diagonal, right neighbours from c_k[i] -- summed as the
-// sliced copy sums the same entries.  Terms of a neighbour outside the
-// matrix, or of k >= K, carry 0 and read x at a clamped index (a finite x
-// adds an exact zero).  No head to load and no dictionary.
+// The stencil copy (Stencil): one lane a row, its 2K+1 terms in column order
+// -- left neighbours i - d_k from the arrays c_k[i - d_k], the diagonal,
+// right neighbours from c_k[i] -- summed as the sliced copy sums the same
+// entries.  Symmetric form: the values as stored; one-sided form: c_k[i]
+// where negative, -c_k[i - d_k] where c_k[i - d_k] is positive (an exact
+// negation back to the stored a_{i,i-d_k}).  Terms of a neighbour outside
+// the matrix, absent from the row, or of k >= K carry 0 and read x at a
+// clamped index (a finite x adds an exact zero).  No head to load and no
+// dictionary.
 template <class V>
 struct OpSten {
     static constexpr int G = 1;
@@ -327,6 +330,7 @@ struct OpSten {
     };
     int32_t n, K;
     int32_t d[kStenMax];
+    int32_t onesided;
     const V *c;
     __device__ __forceinline__ void load(int32_t *) const {}
     __device__ __forceinline__ Head head(int64_t) const { return {}; }
@@ -344,8 +348,10 @@ struct OpSten {
             const bool lin = k < K && ii >= dk;
             const bool rin = k < K && ii + dk < n;
             const int64_t base = (int64_t)(k < K ? 1 + k : 0) * n;
-            const V al = c[base + (lin ? ii - dk : ii)];
-            const V ar = c[base + ii];
+            const V gl = c[base + (lin ? ii - dk : ii)];
+            const V gr = c[base + ii];
+            const V al = onesided ? (gl > V(0) ? -gl : V(0)) : gl;
+            const V ar = onesided ? (gr < V(0) ? gr : V(0)) : gr;
             a[kStenMax - 1 - k] = lin ? al : V(0);
             cj[kStenMax - 1 - k] = lin ? ii - dk : ii;
             a[kStenMax + 1 + k] = rin ? ar : V(0);
@@ -1470,7 +1476,7 @@ void with_csr(const Csr &A, const V *val, F &&f) {
 
 template <class V>
 OpSten<V> sten_op(const Stencil &S, const V *c) {
-    OpSten<V> o{S.n, S.K, {}, c};
+    OpSten<V> o{S.n, S.K, {}, S.onesided, c};
     for (int k = 0; k < kStenMax; ++k) o.d[k] = S.d[k];
     return o;
 }

@@ -7,7 +7,10 @@ travel-time operator (rows of 1 to 7 entries, short slices); the travel-time
 pair solved on short slices against the oracle's exact sweep.  The symmetric
 stencil copy: taken by the 7- and 5-point flow operators, the same PCG
 iterates bit for bit as on the sliced copy, and not taken when one value
-breaks the symmetry.
+breaks the symmetry.  The one-sided stencil copy: taken by the upwind
+travel-time operator, the same pair iterates bit for bit as on the sliced
+copy and the oracle's exact sweep, and not taken when a face is stored by
+both of its rows or an off-diagonal is not negative.
 """
 import sys
 
@@ -84,10 +87,11 @@ def _flow_csr(ref, p):
     return A.rowptr, A.col, A.val
 
 
-def test_pair_on_short_slices_against_oracle(gw, ref):
+def test_pair_on_short_slices_against_oracle(gw, ref, monkeypatch):
     # the upwind system is acyclic: the oracle's sweep in head order gives
     # its exact solution
     _say("travel-time pair on short slices vs the oracle's exact sweep")
+    monkeypatch.setenv("GWAMG_STENCIL", "0")
     p, h, A, bt, bc = _tt_operator(ref, 48, 40, 20, 4.0, 6, 61)
     n = p.grid.n
     H = gw.amg_setup(n, dev(A.rowptr), dev(A.col), dev(A.val), gw.AmgParams.travel_time())
@@ -148,3 +152,58 @@ def test_asymmetric_values_keep_the_sliced_copy(gw, ref):
         H = gw.amg_setup(n, dev(A.rowptr), dev(A.col), dev(v), gw.AmgParams(smoother=gw.SMOOTHER_NONE))
         lv = H.info()[0][0]
         assert lv.stencil_offsets == k and (lv.slice_rows > 0) == (k == 0)
+
+
+def _pair(gw, n, A, bt, bc):
+    H = gw.amg_setup(n, dev(A.rowptr), dev(A.col), dev(A.val), gw.AmgParams.travel_time())
+    x0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, (i0, i1) = gw.amg_solve_bicgstab_pair(H, dev(bt), dev(bc), x0, x1, gw.SolveParams(rtol=1e-10))
+    assert st == gw.OK
+    return H.info()[0][0], x0.cpu().numpy(), x1.cpu().numpy(), (i0.iters, i1.iters)
+
+
+def test_upwind_operator_takes_the_one_sided_copy(gw, ref, monkeypatch):
+    _say("travel-time pair on the one-sided stencil copy")
+    p, h, A, bt, bc = _tt_operator(ref, 48, 40, 20, 4.0, 6, 61)
+    n = p.grid.n
+    lv, x0, x1, it = _pair(gw, n, A, bt, bc)
+    assert (lv.stencil_offsets, lv.slice_rows, lv.nnz_sliced) == (3, 0, 0)
+    monkeypatch.setenv("GWAMG_STENCIL", "0")
+    lv2, y0, y1, it2 = _pair(gw, n, A, bt, bc)
+    assert lv2.stencil_offsets == 0 and lv2.slice_rows > 0
+    _say(f"  iterations {it} (stencil) / {it2} (sliced)")
+    assert it == it2
+    assert np.array_equal(x0.view(np.uint64), y0.view(np.uint64))
+    assert np.array_equal(x1.view(np.uint64), y1.view(np.uint64))
+    for got, b in ((x0, bt), (x1, bc)):
+        want = ref.tt_sweep(A, b, h)
+        assert np.linalg.norm(got - want) <= 1e-8 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("how", ["both rows", "positive"])
+def test_two_sided_face_keeps_the_sliced_copy(gw, ref, how):
+    _say(f"upwind operator with a face {how}: sliced copy")
+    p, h, A, bt, bc = _tt_operator(ref, 30, 22, 14, 4.0, 6, 63)
+    n = p.grid.n
+    rowptr, col, val = A.rowptr.copy(), A.col.copy(), A.val.copy()
+    # a row with an off-diagonal entry
+    i = next(r for r in range(n // 2, n) if rowptr[r + 1] - rowptr[r] > 1)
+    q = next(q for q in range(rowptr[i], rowptr[i + 1]) if col[q] != i)
+    if how == "positive":
+        val[q] = -val[q]
+    else:
+        # store the face's mirror too: insert a_{j,i} into row j
+        j = int(col[q])
+        cols_j = list(col[rowptr[j]:rowptr[j + 1]])
+        assert i not in cols_j
+        pos = rowptr[j] + int(np.searchsorted(cols_j, i))
+        col = np.insert(col, pos, i)
+        val = np.insert(val, pos, val[q] * 0.5)
+        rowptr = rowptr.copy()
+        rowptr[j + 1:] += 1
+    # the setup's pattern probe finds the pattern nonsymmetric, so the
+    # one-sided form is tried and its check refuses it
+    H = gw.amg_setup(n, dev(rowptr), dev(col), dev(val), gw.AmgParams.travel_time())
+    lv = H.info()[0][0]
+    assert lv.stencil_offsets == 0 and lv.slice_rows > 0
