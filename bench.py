@@ -254,6 +254,11 @@ def roofline_entry(s, kernel, traffic):
     if traffic:
         out["counter"] = {"bytes_per_launch": traffic, "achieved": round(gbs(traffic), 1),
                           "frac": round(gbs(traffic) / HBM_PEAK_GBS, 4)}
+    if csr_b > fmt_b:
+        out["bytes_note"] = ("achieved and frac count every operator pass as CSR (the plain formula); the kernels "
+                             "read their own copies (level 0: the stencil copies, four values a row), so the "
+                             "formula counts more bytes than move and its frac can pass 1; format_bytes and "
+                             "counter are the bytes that move")
     return out
 
 
