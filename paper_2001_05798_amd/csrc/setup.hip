@@ -1141,6 +1141,83 @@ __global__ void k_spgemm(AR ar, BR br, int32_t nrows, int hbits, int S, int32_t 
     if (ovf) atomicOr(overflow, 1);
 }
 
+// The same product with one lane per output row, for rows with at most CAP
+// distinct columns (the caller picks CAP from the row bound or the largest
+// row): the row's columns and sums live in registers, each contribution is
+// added to its column's sum in stream order (A entry after A entry, each B
+// row in order), exactly as the hashed kernel adds them, and the row is
+// written in column order by ranking.  NUM = false counts the columns.
+template <int CAP, bool NUM, class AR, class BR, class EPI>
+__global__ void __launch_bounds__(kBlock) k_spgemm_lane(AR ar, BR br, int32_t nrows, int32_t *__restrict__ cnt,
+                                                        const int32_t *__restrict__ crow, int32_t *__restrict__ ccol,
+                                                        double *__restrict__ cval, EPI epi, int32_t *overflow) {
+    const int64_t row = dev::xcd_block() * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= nrows) return;
+    const int32_t i = (int32_t)row;
+    typename EPI::Row er{};
+    if (NUM) er = epi.row(i);
+    int32_t key[CAP];
+    double val[CAP];
+#pragma unroll
+    for (int s = 0; s < CAP; ++s) {
+        key[s] = -1;
+        val[s] = 0.0;
+    }
+    int32_t m = 0;
+    bool ovf = false;
+    const int32_t pend = ar.end(i);
+    for (int32_t p = ar.begin(i); p < pend; ++p) {
+        int32_t k, base, len;
+        double a;
+        if (!ar.get(p, i, k, a)) continue;
+        br.row(k, base, len);
+        for (int32_t t = 0; t < len; ++t) {
+            int32_t J;
+            double bv;
+            br.get(base, t, J, bv);
+            const double c = NUM ? a * bv : 0.0;
+            bool found = false;
+#pragma unroll
+            for (int s = 0; s < CAP; ++s) {
+                if (key[s] == J) {
+                    if (NUM) val[s] = val[s] + c;
+                    found = true;
+                }
+            }
+            if (!found) {
+                if (m < CAP) {
+#pragma unroll
+                    for (int s = 0; s < CAP; ++s) {
+                        if (s == m) {
+                            key[s] = J;
+                            if (NUM) val[s] = val[s] + c;  // 0 + c, as the hashed kernel's first add
+                        }
+                    }
+                    ++m;
+                } else {
+                    ovf = true;
+                }
+            }
+        }
+    }
+    if (!NUM) {
+        cnt[row + 1] = m;
+        if (row == 0) cnt[0] = 0;
+    } else {
+        const int32_t out0 = crow[i];
+#pragma unroll
+        for (int s = 0; s < CAP; ++s) {
+            if (s >= m) break;
+            int32_t rank = 0;
+#pragma unroll
+            for (int u = 0; u < CAP; ++u) rank += (u < m && key[u] < key[s]) ? 1 : 0;
+            ccol[out0 + rank] = key[s];
+            cval[out0 + rank] = epi(er, key[s], val[s]);
+        }
+    }
+    if (ovf) atomicOr(overflow, 1);
+}
+
 // -------------------------------------------------------------- smoother --
 template <int G>
 __global__ void k_smoother_diag(CsrView A, const double *__restrict__ diag, int spai0, double omega,
@@ -1789,12 +1866,44 @@ void spg_launch(const SpgShape &sh, int32_t nrows, bool num, int hbits, K &&kern
     kern(dim3(grid), dim3(groups * G), groups * bytes_group, Sx);
 }
 
+// Rows of at most this many distinct columns, from A-side rows of at most
+// kLaneMaxALen entries on average, take one lane each (k_spgemm_lane): the
+// level-0 products (the prolongator smoothing, at most 7 columns a row, and
+// A P).  The numeric pass keeps the sums in registers too and stops at 16
+// (32 columns and their sums spill); on the Galerkin levels, whose A rows
+// hold ~30 entries, one lane walking them measured slower than the lane
+// groups (prolongator smoothing 68 -> 91 us).
+constexpr int kLaneCapSym = 32, kLaneCapNum = 16;
+constexpr double kLaneMaxALen = 8.0;
+
+template <bool NUM, class AR, class BR, class EPI>
+void launch_spgemm_lane(int32_t cap, AR ar, BR br, EPI epi, int32_t nrows, int32_t *cnt, const int32_t *crow,
+                        int32_t *ccol, double *cval, int32_t *overflow, hipStream_t s) {
+    const dim3 g(blocks_for(std::max<int32_t>(nrows, 1))), b(kBlock);
+    if (cap <= 8)
+        hipLaunchKernelGGL((k_spgemm_lane<8, NUM, AR, BR, EPI>), g, b, 0, s, ar, br, nrows, cnt, crow, ccol, cval,
+                           epi, overflow);
+    else if (cap <= 16)
+        hipLaunchKernelGGL((k_spgemm_lane<16, NUM, AR, BR, EPI>), g, b, 0, s, ar, br, nrows, cnt, crow, ccol, cval,
+                           epi, overflow);
+    else if constexpr (!NUM)
+        hipLaunchKernelGGL((k_spgemm_lane<32, NUM, AR, BR, EPI>), g, b, 0, s, ar, br, nrows, cnt, crow, ccol, cval,
+                           epi, overflow);
+    GW_HIP(hipGetLastError());
+}
+
 template <class AR, class BR, class EPI>
 void spgemm_symbolic(AR ar, BR br, EPI epi, int32_t nrows, int32_t ncols, double avg_a_len, double avg_b_len,
                      int32_t ub, Csr &C, int32_t *blk, hipStream_t s, double in_bytes) {
     const int64_t cap = std::min<int64_t>(ub, ncols);
     const int hb = std::min(pow2_bits_at_least(2 * std::max<int64_t>(cap, 1)), kMaxHashBits);
     C.alloc(nrows, ncols, 0);  // blk[1..5] were cleared by the product's spgemm_bound
+    if (cap <= kLaneCapSym && avg_a_len <= kLaneMaxALen) {
+        ProfScope ps(K_SPGEMM, in_bytes + 4.0 * (nrows + 1), s);
+        launch_spgemm_lane<false>((int32_t)cap, ar, br, epi, nrows, C.rowptr.p, nullptr, nullptr, nullptr, blk + 2, s);
+        scan_inclusive_i32(C.rowptr.p + 1, nrows, reinterpret_cast<int64_t *>(blk + 4), s, blk + 1);
+        return;
+    }
     const SpgShape sh = spg_shape(avg_a_len, avg_b_len);
 #define SPG_SYM(GG)                                                                                           \
     hipLaunchKernelGGL((k_spgemm<GG, false, AR, BR, EPI>), g, b, shm, s, ar, br, nrows, hb, Sx, C.rowptr.p, \
@@ -1827,6 +1936,11 @@ void spgemm_numeric(AR ar, BR br, EPI epi, int32_t nrows, double avg_a_len, doub
     C.nnz = nnz;
     C.col.alloc((size_t)nnz);
     C.val.alloc((size_t)nnz);
+    if (maxd <= kLaneCapNum && avg_a_len <= kLaneMaxALen) {
+        ProfScope ps(K_SPGEMM, in_bytes + 4.0 * (nrows + 1) + 12.0 * (double)nnz, s);
+        launch_spgemm_lane<true>(maxd, ar, br, epi, nrows, nullptr, C.rowptr.p, C.col.p, C.val.p, blk + 2, s);
+        return;
+    }
     // numeric table: at least 1.5 slots per column of the longest row
     const int hbn = std::min(pow2_bits_at_least((int64_t)(1.5 * std::max<int32_t>(maxd, 1))), kMaxHashBits);
     const SpgShape sh = spg_shape(avg_a_len, avg_b_len);
