@@ -1166,36 +1166,50 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_lane(AR ar, BR br, int32_t nr
     int32_t m = 0;
     bool ovf = false;
     const int32_t pend = ar.end(i);
-    for (int32_t p = ar.begin(i); p < pend; ++p) {
-        int32_t k, base, len;
-        double a;
-        if (!ar.get(p, i, k, a)) continue;
-        br.row(k, base, len);
-        for (int32_t t = 0; t < len; ++t) {
-            int32_t J;
-            double bv;
-            br.get(base, t, J, bv);
-            const double c = NUM ? a * bv : 0.0;
-            bool found = false;
+    // A entries and their B-row heads are loaded four at a time (independent
+    // loads in flight), then added in order
+    constexpr int U = 4;
+    for (int32_t p0 = ar.begin(i); p0 < pend; p0 += U) {
+        int32_t kk[U], bb[U], ll[U];
+        double aa[U];
 #pragma unroll
-            for (int s = 0; s < CAP; ++s) {
-                if (key[s] == J) {
-                    if (NUM) val[s] = val[s] + c;
-                    found = true;
-                }
-            }
-            if (!found) {
-                if (m < CAP) {
+        for (int u = 0; u < U; ++u) {
+            kk[u] = 0;
+            aa[u] = 0.0;
+            bb[u] = 0;
+            ll[u] = 0;
+            if (p0 + u < pend && ar.get(p0 + u, i, kk[u], aa[u])) br.row(kk[u], bb[u], ll[u]);
+        }
 #pragma unroll
-                    for (int s = 0; s < CAP; ++s) {
-                        if (s == m) {
-                            key[s] = J;
-                            if (NUM) val[s] = val[s] + c;  // 0 + c, as the hashed kernel's first add
-                        }
+        for (int u = 0; u < U; ++u) {
+            const double a = aa[u];
+            const int32_t base = bb[u], len = ll[u];
+            for (int32_t t = 0; t < len; ++t) {
+                int32_t J;
+                double bv;
+                br.get(base, t, J, bv);
+                const double c = NUM ? a * bv : 0.0;
+                bool found = false;
+#pragma unroll
+                for (int s = 0; s < CAP; ++s) {
+                    if (key[s] == J) {
+                        if (NUM) val[s] = val[s] + c;
+                        found = true;
                     }
-                    ++m;
-                } else {
-                    ovf = true;
+                }
+                if (!found) {
+                    if (m < CAP) {
+#pragma unroll
+                        for (int s = 0; s < CAP; ++s) {
+                            if (s == m) {
+                                key[s] = J;
+                                if (NUM) val[s] = val[s] + c;  // 0 + c, as the hashed kernel's first add
+                            }
+                        }
+                        ++m;
+                    } else {
+                        ovf = true;
+                    }
                 }
             }
         }
