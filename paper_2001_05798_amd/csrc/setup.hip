@@ -2413,8 +2413,12 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
         GW_HIP(hipGetLastError());
     }
     // the graph's size is read later, with the MIS-2 flags: its arrays take
-    // the bound (A's off-diagonal pattern, and that of A^T when not symmetric)
-    scan_inclusive_i32(S.rowptr.p + 1, n, rd.total(0), s);
+    // the bound (A's off-diagonal pattern, and that of A^T when not symmetric).
+    // Its longest row goes to the prolongator product's row bound: a row of
+    // the filtered A (the diagonal and A's strong entries, a subset of the
+    // graph's row) adds at most that many + 1 contributions, one per
+    // aggregate met.
+    scan_inclusive_i32(S.rowptr.p + 1, n, rd.total(0), s, rd.blk(0));
     const int64_t s_cap = std::max<int64_t>(sym ? A.nnz : A.nnz + T.nnz, 1);
     S.col.alloc((size_t)s_cap);
     sw.alloc((size_t)s_cap);
@@ -2426,9 +2430,9 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     code.release();
 
     // MIS-2 rounds, batched between host reads; a round after the last
-    // decision is a no-op.  After each batch the aggregates and the row bound
-    // of the prolongator product are formed from the states reached, and read
-    // back with the round flags: they are final when the rounds have ended.
+    // decision is a no-op.  After each batch the aggregates are formed from
+    // the states reached, and read back with the round flags: they are final
+    // when the rounds have ended.
     DBuf<uint32_t> state(n);
     DBuf<uint64_t> m1(n);
     DBuf<uint8_t> done(n);
@@ -2483,8 +2487,6 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
             });
             GW_HIP(hipGetLastError());
         }
-        // filtered rows: columns and strong flags; tentative P: the aggregate map
-        spgemm_bound(af, bt, n, arow, rd.blk(0), s, 4.0 * (n + 1) + 5.0 * (double)A.nnz + 4.0 * n);
         int32_t flags[kBatch + 1];
         rd.sync(s, und + rounds, sizeof(int32_t) * (batch + 1), flags);
         if (flags[0] == 0) break;  // nothing was undecided before this batch
@@ -2530,7 +2532,7 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     EpiSmoothP ep{Lv.agg.p, dF.p, diag.p, omega.p};
     // P: symbolic pass, then the row bound of A P (it needs only P's row
     // pointers), one read for both
-    spgemm_symbolic(af, bt, ep, n, (int32_t)nc, arow, 1.0, rd.hblk(0)[0], Lv.P, rd.blk(0), s,
+    spgemm_symbolic(af, bt, ep, n, (int32_t)nc, arow, 1.0, rd.hblk(0)[0] + 1, Lv.P, rd.blk(0), s,
                     4.0 * (n + 1) + 5.0 * (double)A.nnz + 4.0 * n);
     spgemm_bound(ARowCsr{A.rowptr, A.col, A.val}, BCsr{Lv.P.rowptr.p, nullptr, nullptr}, n, arow, rd.blk(1), s,
                  4.0 * (n + 1) + 4.0 * (double)A.nnz + 4.0 * (n + 1));
