@@ -102,36 +102,46 @@ __device__ __forceinline__ void sum_partials(const double *partials, unsigned nb
     }
 }
 
-// sum_partials for several values at once (nb >= 1), with every block record this
-// thread reads loaded before any is added (records b = threadIdx.x +
-// u*blockDim.x, u < MAXU, then the rest in a loop), so the loads take one
-// round of latency instead of one per record: tot[k] = the sum of value
-// off[k] of the nb records, added in exactly the order of sum_partials.
-template <int NV, int MAXU = 8>
+// sum_partials for several values at once (nb >= 1), in blocks of BS threads,
+// with every block record this thread reads loaded before any is added
+// (records b = threadIdx.x + u*BS, u < MAXU, then the rest in a loop), so
+// the loads take one round of latency instead of one per record: tot[k] =
+// the sum of value off[k] of the nb records, added in exactly the order of
+// sum_partials.  BS is a constant so that no load of the launch's block size
+// has to finish before the records' loads are issued.
+template <int NV, int BS, int MAXU = 8>
 __device__ __forceinline__ void sum_partials_batched(const double *partials, unsigned nb, int stride,
                                                      const int (&off)[NV], double (&tot)[NV]) {
+    static_assert(BS % kWave == 0 && BS / kWave <= 16, "block of at most 16 waves");
     __shared__ double sm[NV][16];
     double s[NV], t[MAXU][NV];
 #pragma unroll
     for (int u = 0; u < MAXU; ++u) {
-        const unsigned b = threadIdx.x + u * blockDim.x;
+        const unsigned b = threadIdx.x + u * BS;
         const unsigned bb = b < nb ? b : 0;  // nb >= 1; unused, but no branch
 #pragma unroll
         for (int k = 0; k < NV; ++k) t[u][k] = partials[(size_t)bb * stride + off[k]];
     }
+    // Every load above is issued before the first addition waits for one:
+    // memory operations cannot cross these empty statements, and each
+    // addition needs its value out of one.
+#pragma unroll
+    for (int u = 0; u < MAXU; ++u)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) asm volatile("" : "+v"(t[u][k])::"memory");
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = 0.0;
 #pragma unroll
     for (int u = 0; u < MAXU; ++u)
-        if (threadIdx.x + u * blockDim.x < nb)
+        if (threadIdx.x + u * BS < nb)
 #pragma unroll
             for (int k = 0; k < NV; ++k) s[k] += t[u][k];
-    for (unsigned b = threadIdx.x + MAXU * blockDim.x; b < nb; b += blockDim.x)
+    for (unsigned b = threadIdx.x + MAXU * BS; b < nb; b += BS)
 #pragma unroll
         for (int k = 0; k < NV; ++k) s[k] += partials[(size_t)b * stride + off[k]];
     // block sums in block_sum's order, one pair of barriers for all values
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int nw = (blockDim.x + kWave - 1) / kWave;
+    constexpr int nw = BS / kWave;
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = wave_sum(s[k]);
     if (lane == 0)

@@ -1354,13 +1354,107 @@ __global__ void __launch_bounds__(1024) k_dense_lu(double *__restrict__ a, int32
 constexpr int kLuLdsSmall = 88;  // up to 88 x 88 (61952 B): 256 threads, more: 512 (measured
                                  // 18 % faster than 1024 at n = 109, 14 % at n = 141)
 
+// The same factorization for a matrix held in LDS, with two barriers a step
+// instead of five: the pivot search of column k+1 runs inside step k's
+// trailing update (lane 0 of each wave sees the new column k+1 entries of
+// its rows, in increasing row order, and keeps the first largest with its
+// signed value), and every thread then picks the pivot from the per-wave
+// records itself; the row swap and the scaling of column k share one phase,
+// thread 0 taking the two column-k entries that both would touch.  Every
+// entry gets the same operations in the same order as in lu_in_place, and
+// the pivot is the same row, so the factors and pivots are identical.
+template <int NW>
+__device__ __forceinline__ void lu_lds_two_barrier(double *a, int32_t n, int32_t *__restrict__ piv,
+                                                   int32_t *status) {
+    // n <= 143 (the matrix fits in LDS), so 32-bit indices
+    __shared__ double sv[NW], sval[NW];
+    __shared__ int32_t si[NW];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // column 0's search: lane 0 of wave w scans rows w, w + NW, ...
+    if (lane == 0) {
+        double best = -1.0, bv = 0.0;
+        int32_t bi = n;
+        for (int32_t i = w; i < n; i += NW) {
+            const double v = a[i * n];
+            if (fabs(v) > best) { best = fabs(v); bi = i; bv = v; }
+        }
+        sv[w] = best, si[w] = bi, sval[w] = bv;
+    }
+    __syncthreads();
+    for (int32_t k = 0; k < n; ++k) {
+        // the per-wave records, all read before they are compared
+        double rv[NW], rs[NW];
+        int32_t ri[NW];
+#pragma unroll
+        for (int q = 0; q < NW; ++q) rv[q] = sv[q], rs[q] = sval[q], ri[q] = si[q];
+        double b = rv[0], pv = rs[0];
+        int32_t p = ri[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q)
+            if (rv[q] > b || (rv[q] == b && ri[q] < p)) { b = rv[q]; p = ri[q]; pv = rs[q]; }
+        if (tid == 0) piv[k] = p;
+        if (!(b > 0.0)) {
+            if (tid == 0) *status = GW_SINGULAR;
+            return;
+        }
+        // swap rows k and p outside column k; column k: a_kk = pivot, the
+        // old a_kk moves to row p and is scaled there, the rest are scaled
+        if (tid == 0) {
+            const double t = a[k * n + k];
+            a[k * n + k] = pv;
+            if (p != k) a[p * n + k] = t / pv;
+        }
+        if (p != k)
+            for (int32_t j = tid; j < n; j += NW * 64)
+                if (j != k) {
+                    const double t = a[k * n + j];
+                    a[k * n + j] = a[p * n + j];
+                    a[p * n + j] = t;
+                }
+        for (int32_t i = k + 1 + tid; i < n; i += NW * 64)
+            if (i != p) a[i * n + k] = a[i * n + k] / pv;
+        __syncthreads();
+        // trailing update (a wave takes four rows at a time, lanes along the
+        // row) with the search of column k+1 on lane 0 (j = k+1)
+        double best = -1.0, bv = 0.0;
+        int32_t bi = n;
+        for (int32_t i0 = k + 1 + w; i0 < n; i0 += 4 * NW) {
+            double lik[4];
+            int32_t row[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                row[u] = min(i0 + u * NW, n - 1) * n;
+                lik[u] = a[row[u] + k];
+            }
+            for (int32_t j = k + 1 + lane; j < n; j += 64) {
+                const double akj = a[k * n + j];
+                double aij[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) aij[u] = a[row[u] + j];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t i = i0 + u * NW;
+                    if (i < n) {
+                        const double v = aij[u] - lik[u] * akj;
+                        a[row[u] + j] = v;
+                        if (j == k + 1 && fabs(v) > best) { best = fabs(v); bi = i; bv = v; }
+                    }
+                }
+            }
+        }
+        if (lane == 0) sv[w] = best, si[w] = bi, sval[w] = bv;
+        __syncthreads();
+    }
+}
+
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_dense_lu_lds(double *__restrict__ a, int32_t n,
                                                          int32_t *__restrict__ piv, int32_t *status) {
+    static_assert(BLOCK % 64 == 0 && BLOCK <= 1024, "whole waves, at most 16");
     extern __shared__ double lu_sm[];
     for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) lu_sm[e] = a[e];
     __syncthreads();
-    lu_in_place(lu_sm, n, piv, status);
+    lu_lds_two_barrier<BLOCK / 64>(lu_sm, n, piv, status);
     __syncthreads();
     for (int32_t e = threadIdx.x; e < n * n; e += blockDim.x) a[e] = lu_sm[e];
 }

@@ -969,7 +969,7 @@ enum FinOp : int {
 };
 
 // The scalar step that follows reduction `op`, from the reduced values.
-__device__ void fin_apply(int op, const double (&tot)[2], double rtol, KScalars *ks) {
+__device__ __forceinline__ void fin_apply(int op, const double (&tot)[2], double rtol, KScalars *ks) {
     switch (op) {
         case FIN_INIT_FIRST:
         case FIN_INIT_RESTART:
@@ -1070,21 +1070,26 @@ __host__ __device__ constexpr int fin_nv(int op) {
             op == FIN_BCG_OMEGA || op == FIN_BCG_XR) ? 2 : 1;
 }
 
-// The partials are loaded before the skip test reads the scalars, so both
-// latencies overlap.  One block.
+// The scalars are read into registers before the records are summed, so
+// their load overlaps the records' instead of following the block's two
+// barriers; thread 0 writes them back when the step changes them.  One block.
 __device__ __forceinline__ void finalize_body(int op, unsigned nb, const double *partials, double rtol,
                                               KScalars *ks) {
+    KScalars k = *ks;
     double tot[2] = {0.0, 0.0};
     if (fin_nv(op) == 2) {
         const int off[2] = {0, 1};
-        dev::sum_partials_batched<2>(partials, nb, 2, off, tot);
+        dev::sum_partials_batched<2, kKBlock>(partials, nb, 2, off, tot);
     } else {
         const int off[1] = {0};
         double t1[1];
-        dev::sum_partials_batched<1>(partials, nb, 1, off, t1);
+        dev::sum_partials_batched<1, kKBlock>(partials, nb, 1, off, t1);
         tot[0] = t1[0];
     }
-    if (threadIdx.x == 0 && !fin_skip(op, ks)) fin_apply(op, tot, rtol, ks);
+    if (threadIdx.x == 0 && !fin_skip(op, &k)) {
+        fin_apply(op, tot, rtol, &k);
+        *ks = k;
+    }
 }
 struct FinK {
     int op;
@@ -1103,24 +1108,28 @@ __device__ __forceinline__ void finalize2_body(int op, unsigned nb, const double
                                                KScalars *ks, int mask) {
     // both systems' sums in one pass over the records (each added in the
     // order of a one-system finalize)
+    KScalars k[2] = {ks[0], ks[1]};  // read before the sums, as in finalize_body
     double tot[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     if (fin_nv(op) == 2) {
         const int off[4] = {0, 1, 2, 3};
         double t[4];
-        dev::sum_partials_batched<4>(partials, nb, 4, off, t);
+        dev::sum_partials_batched<4, kKBlock>(partials, nb, 4, off, t);
         tot[0][0] = t[0], tot[0][1] = t[1], tot[1][0] = t[2], tot[1][1] = t[3];
     } else {
         const int off[2] = {0, 1};
         double t[2];
-        dev::sum_partials_batched<2>(partials, nb, 2, off, t);
+        dev::sum_partials_batched<2, kKBlock>(partials, nb, 2, off, t);
         tot[0][0] = t[0], tot[1][0] = t[1];
     }
-    if (threadIdx.x == 0)
-        for (int r = 0; r < 2; ++r)
-            if ((mask >> r & 1) && !fin_skip(op, ks + r)) fin_apply(op, tot[r], rtol, ks + r);
     if (threadIdx.x == 0) {
-        ks[2].done = ks[0].done && ks[1].done;
-        ks[2].pending_x = ks[0].pending_x || ks[1].pending_x;
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            if ((mask >> r & 1) && !fin_skip(op, &k[r])) {
+                fin_apply(op, tot[r], rtol, &k[r]);
+                ks[r] = k[r];
+            }
+        ks[2].done = k[0].done && k[1].done;
+        ks[2].pending_x = k[0].pending_x || k[1].pending_x;
     }
 }
 struct Fin2K {

@@ -151,7 +151,7 @@ HIER_CASES = [
     ("2d 64x64 jacobi", lambda: gi.homogeneous_slab(), dict(smoother=0, npre=1, npost=1)),
     ("3d 24x20x12 s2=4", lambda: gi.heterogeneous_aquifer(24, 20, 12, 4.0, 4, 5), dict()),
     ("3d 37x23x11 s2=1 ragged", lambda: gi.heterogeneous_aquifer(37, 23, 11, 1.0, 3, 8), dict(n_coarse=40)),
-    # coarsest levels of 109 and 141 rows (LU in LDS with 1024 threads, the
+    # coarsest levels of 109 and 141 rows (LU in LDS with 512 threads, the
     # second at the 160 KB limit) and of 412 rows (LU in global memory)
     ("3d 30x22x14 coarsest 109", lambda: gi.heterogeneous_aquifer(30, 22, 14, 4.0, 4, 5), dict()),
     ("3d 36x30x12 coarsest 141", lambda: gi.heterogeneous_aquifer(36, 30, 12, 4.0, 4, 5), dict()),
@@ -610,6 +610,33 @@ def test_setup_reports_zero_pivot_in_coarsest_lu(gw, ref):
     Hg = gw.amg_setup(2, dev(rp), dev(cl), dev(B.val))
     lu = torch.zeros(4, dtype=torch.float64, device="cuda")
     piv = torch.zeros(2, dtype=torch.int32, device="cuda")
+    gw.amg_coarse_export(Hg, lu, piv)
+    assert np.array_equal(host(piv), piv_ref)
+    assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64))
+
+
+@pytest.mark.parametrize("n", [60, 120])
+def test_coarsest_lu_with_row_interchanges(gw, ref, n):
+    # A dense nonsymmetric matrix that is its own coarsest level, with
+    # off-diagonal entries up to eight times the diagonal, so partial
+    # pivoting interchanges rows at most steps (the flow hierarchies'
+    # coarsest matrices rarely need one).  n = 60 and 120 take the two LDS
+    # forms of the factorization (256 and 512 threads); factors and pivots
+    # bit for bit.
+    _say(f"coarsest LU with row interchanges, n={n}")
+    rng = np.random.default_rng(1000 + n)
+    M = rng.uniform(-4.0, 4.0, (n, n))
+    np.fill_diagonal(M, rng.uniform(0.5, 1.0, n))
+    rp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    cl = np.tile(np.arange(n, dtype=np.int32), n)
+    A = ref.Csr(rowptr=rp, col=cl, val=M.reshape(-1).copy())
+    Hr = ref.Hierarchy(A, ref.AmgParams())
+    assert Hr.nlevels == 1
+    lu_ref, piv_ref = Hr.coarse_lu()
+    assert np.count_nonzero(piv_ref != np.arange(n)) > n // 2
+    Hg = gw.amg_setup(n, dev(rp), dev(cl), dev(A.val))
+    lu = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    piv = torch.zeros(n, dtype=torch.int32, device="cuda")
     gw.amg_coarse_export(Hg, lu, piv)
     assert np.array_equal(host(piv), piv_ref)
     assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64))
