@@ -1638,8 +1638,10 @@ __global__ void __launch_bounds__(64) k_lu_inverse(const double *__restrict__ lu
 // finished x_j with v_readlane (a uniform lane index) and every lane
 // updates its later (forward) or earlier (backward) rows, so a step costs a
 // broadcast and a multiply-subtract instead of a wave-wide sum.  The L and U
-// entries of the next step are loaded one step ahead (staging the factors
-// in LDS first measured slower: 73 against 50 us).  (Each x_i receives
+// entries of the next kInvAhead steps are loaded while the current ones run,
+// so the chain of steps waits for memory once per kInvAhead steps (one step
+// ahead, with the pivots read one by one: 42 us for n = 118; staging the
+// factors in LDS first measured slower still, 73 against 50 us).  (Each x_i receives
 // its terms in the order j = pos, pos+1, ... rather than as one dot product,
 // so the inverse agrees with the row-oriented one to rounding.)
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
@@ -1648,49 +1650,80 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
+constexpr int kInvAhead = 16;  // substitution steps whose factor entries are loaded ahead
+
 __global__ void __launch_bounds__(64) k_lu_inverse_col(const double *__restrict__ lu, const int32_t *__restrict__ piv,
                                                        int32_t n, double *__restrict__ inv, const int32_t *status) {
+    constexpr int D = kInvAhead;
     const int32_t c = blockIdx.x;
     const int lane = threadIdx.x;
-    if (c >= n || *status != 0) return;
+    if (c >= n) return;
+    // the pivots, two a lane (after a zero pivot the later ones were never
+    // written: loaded, but not used)
+    const int32_t p0 = lane < n ? piv[lane] : lane, p1 = lane + 64 < n ? piv[lane + 64] : lane + 64;
+    if (*status != 0) return;
     int32_t pos = c;
     for (int32_t k = 0; k < n; ++k) {
-        const int32_t pk = piv[k];
+        const int32_t pk = __builtin_amdgcn_readlane(k < 64 ? p0 : p1, k & 63);
         if (pos == k) pos = pk;
         else if (pos == pk) pos = k;
     }
     const int32_t i0 = lane, i1 = lane + 64;
+    // rows past n read row n-1 and columns past the ends the last one: in
+    // bounds, never used
+    const int32_t r0 = min(i0, n - 1) * n, r1 = min(i1, n - 1) * n;
     double x0 = (i0 == pos) ? 1.0 : 0.0, x1 = (i1 == pos) ? 1.0 : 0.0;
-    // forward: unit lower triangle, x_j final after step j - 1
-    double a0 = 0.0, a1 = 0.0;
-    if (pos < n - 1) {
-        a0 = i0 < n ? lu[(int64_t)i0 * n + pos] : 0.0;
-        a1 = i1 < n ? lu[(int64_t)i1 * n + pos] : 0.0;
+    double c0[D], c1[D], f0[D], f1[D];
+    // forward: unit lower triangle, x_j final after step j - 1; the entries
+    // of the next D steps are loaded while these D run
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        const int32_t j = min(pos + u, n - 1);
+        c0[u] = lu[r0 + j], c1[u] = lu[r1 + j];
     }
-    for (int32_t j = pos; j < n - 1; ++j) {
-        const double l0 = a0, l1 = a1;
-        if (j + 1 < n - 1) {
-            a0 = i0 < n ? lu[(int64_t)i0 * n + j + 1] : 0.0;
-            a1 = i1 < n ? lu[(int64_t)i1 * n + j + 1] : 0.0;
+    for (int32_t jb = pos; jb < n - 1; jb += D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int32_t j = min(jb + D + u, n - 1);
+            f0[u] = lu[r0 + j], f1[u] = lu[r1 + j];
         }
-        const double xj = readlane_f64(j < 64 ? x0 : x1, j & 63);
-        if (i0 > j && i0 < n) x0 = x0 - l0 * xj;
-        if (i1 > j && i1 < n) x1 = x1 - l1 * xj;
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int32_t j = jb + u;
+            if (j < n - 1) {
+                const double xj = readlane_f64(j < 64 ? x0 : x1, j & 63);
+                if (i0 > j && i0 < n) x0 = x0 - c0[u] * xj;
+                if (i1 > j && i1 < n) x1 = x1 - c1[u] * xj;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < D; ++u) c0[u] = f0[u], c1[u] = f1[u];
     }
-    // backward: upper triangle with its diagonal
-    a0 = i0 < n ? lu[(int64_t)i0 * n + (n - 1)] : 0.0;
-    a1 = i1 < n ? lu[(int64_t)i1 * n + (n - 1)] : 0.0;
-    for (int32_t j = n - 1; j >= 0; --j) {
-        const double u0 = a0, u1 = a1;
-        if (j > 0) {
-            a0 = i0 < n ? lu[(int64_t)i0 * n + j - 1] : 0.0;
-            a1 = i1 < n ? lu[(int64_t)i1 * n + j - 1] : 0.0;
+    // backward: upper triangle with its diagonal, j = n-1 down to 0
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        const int32_t j = max(n - 1 - u, 0);
+        c0[u] = lu[r0 + j], c1[u] = lu[r1 + j];
+    }
+    for (int32_t jb = n - 1; jb >= 0; jb -= D) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int32_t j = max(jb - D - u, 0);
+            f0[u] = lu[r0 + j], f1[u] = lu[r1 + j];
         }
-        if (i0 == j) x0 = x0 / u0;
-        if (i1 == j) x1 = x1 / u1;
-        const double xj = readlane_f64(j < 64 ? x0 : x1, j & 63);
-        if (i0 < j) x0 = x0 - u0 * xj;
-        if (i1 < j) x1 = x1 - u1 * xj;
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            const int32_t j = jb - u;
+            if (j >= 0) {
+                if (i0 == j) x0 = x0 / c0[u];
+                if (i1 == j) x1 = x1 / c1[u];
+                const double xj = readlane_f64(j < 64 ? x0 : x1, j & 63);
+                if (i0 < j) x0 = x0 - c0[u] * xj;
+                if (i1 < j) x1 = x1 - c1[u] * xj;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < D; ++u) c0[u] = f0[u], c1[u] = f1[u];
     }
     if (i0 < n) inv[(int64_t)i0 * n + c] = x0;
     if (i1 < n) inv[(int64_t)i1 * n + c] = x1;
