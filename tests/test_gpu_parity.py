@@ -615,14 +615,15 @@ def test_setup_reports_zero_pivot_in_coarsest_lu(gw, ref):
     assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64))
 
 
-@pytest.mark.parametrize("n", [60, 120])
+@pytest.mark.parametrize("n", [60, 120, 128, 130])
 def test_coarsest_lu_with_row_interchanges(gw, ref, n):
     # A dense nonsymmetric matrix that is its own coarsest level, with
     # off-diagonal entries up to eight times the diagonal, so partial
     # pivoting interchanges rows at most steps (the flow hierarchies'
     # coarsest matrices rarely need one).  n = 60 and 120 take the two LDS
-    # forms of the factorization (256 and 512 threads); factors and pivots
-    # bit for bit.
+    # forms of the factorization (256 and 512 threads), 128 the largest
+    # inverse by column-oriented substitutions and 130 the row-oriented one;
+    # factors and pivots bit for bit.
     _say(f"coarsest LU with row interchanges, n={n}")
     rng = np.random.default_rng(1000 + n)
     M = rng.uniform(-4.0, 4.0, (n, n))
@@ -637,9 +638,14 @@ def test_coarsest_lu_with_row_interchanges(gw, ref, n):
     Hg = gw.amg_setup(n, dev(rp), dev(cl), dev(A.val))
     lu = torch.zeros(n * n, dtype=torch.float64, device="cuda")
     piv = torch.zeros(n, dtype=torch.int32, device="cuda")
-    gw.amg_coarse_export(Hg, lu, piv)
+    inv = torch.zeros(n * n, dtype=torch.float64, device="cuda")
+    gw.amg_coarse_export(Hg, lu, piv, inv)
     assert np.array_equal(host(piv), piv_ref)
     assert np.array_equal(host(lu).view(np.uint64), lu_ref.reshape(-1).view(np.uint64))
+    # the inverse undoes the interchanges (each column starts from the
+    # permuted unit vector): A^-1 A = I
+    Ainv = host(inv).reshape(n, n)
+    assert np.abs(Ainv @ M - np.eye(n)).max() < 1e-10 * np.linalg.cond(M)
 
 
 def test_breakdown_when_rhat_v_vanishes(gw, ref):
