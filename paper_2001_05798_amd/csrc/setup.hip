@@ -1267,11 +1267,16 @@ __global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, in
 }
 
 // ------------------------------------------------------------- coarse LU --
+// One wave a row: the lanes clear the dense row, then write its entries
+// (a row's columns are distinct, so the scattered writes never collide).
 __global__ void k_csr_to_dense(CsrView A, double *__restrict__ a) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / dev::kWave;
+    const int lane = threadIdx.x & (dev::kWave - 1);
     if (i >= A.n) return;
-    for (int32_t c = 0; c < A.n; ++c) a[i * A.n + c] = 0.0;
-    for (int32_t p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) a[i * A.n + A.col[p]] = A.val[p];
+    double *row = a + i * A.n;
+    for (int32_t c = lane; c < A.n; c += dev::kWave) row[c] = 0.0;
+    __threadfence_block();  // the zeros land before any entry overwrites one
+    for (int32_t p = A.rowptr[i] + lane; p < A.rowptr[i + 1]; p += dev::kWave) row[A.col[p]] = A.val[p];
 }
 
 // Right-looking LU with partial pivoting in one workgroup (LAPACK getrf
@@ -2736,7 +2741,8 @@ void start_coarsest(amg_hierarchy *H, int l, hipStream_t s, CoarseJob &job) {
     int32_t *status = job.status.p;
     {
         ProfScope ps(K_COARSE_LU, (double)n * n * 24, q);
-        hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for(n)), dim3(kBlock), 0, q, view(Lv.A), H->lu.p);
+        hipLaunchKernelGGL(k_csr_to_dense, dim3(blocks_for((int64_t)n * dev::kWave)), dim3(kBlock), 0, q, view(Lv.A),
+                           H->lu.p);
         const size_t lds = (size_t)n * n * sizeof(double);
         if (n <= kLuLdsSmall) {
             hipLaunchKernelGGL(k_dense_lu_lds<256>, dim3(1), dim3(256), lds, q, H->lu.p, n, H->piv.p, status);
