@@ -793,19 +793,56 @@ __device__ __forceinline__ double grp_ordered_sum(int32_t b, int32_t e, int lane
     return s;
 }
 
-template <int G>
-__global__ void k_rho(CsrView A, const double *__restrict__ diag, unsigned long long *rho_bits) {
+// One thread a row, in row order within the block, so the block's entries
+// are one contiguous range: up to kRhoStage of them are first copied to LDS
+// with coalesced loads (|a_ij|), then each thread adds its row's from LDS;
+// a longer range loads each row's entries B at a time, all B before any is
+// added.  Either way the row is summed one entry after another from s = 0
+// in column order (the sum grp_ordered_sum forms).
+constexpr int kRhoStage = 16 * kBlock;
+
+template <int B>
+__global__ void __launch_bounds__(kBlock) k_rho(CsrView A, const double *__restrict__ diag,
+                                                unsigned long long *rho_bits) {
+    __shared__ double st[kRhoStage];
+    const int64_t r0 = dev::xcd_block() * (int64_t)kBlock;
+    const int64_t i = r0 + threadIdx.x;
+    const int64_t rl = min(r0 + kBlock, (int64_t)A.n);  // one past the block's last row
+    const int32_t base = A.rowptr[r0], top = A.rowptr[rl];
+    const bool staged = top - base <= kRhoStage;  // the same in every thread
+    if (staged) {
+        for (int32_t p = base + threadIdx.x; p < top; p += kBlock) st[p - base] = fabs(A.val[p]);
+        __syncthreads();
+    }
     double r = 0.0;
-    GRP_LOOP(G, A.n) {
-        const int32_t i = (int32_t)row_;
-        const double s = grp_ordered_sum<G>(A.rowptr[i], A.rowptr[i + 1], lane_,
-                                            [&](int32_t p) { return fabs(A.val[p]); });
-        const double ri = s / diag[i];
+    if (i < A.n) {
+        const int32_t b = A.rowptr[i], e = A.rowptr[i + 1];
+        const double d = diag[i];
+        double s = 0.0;
+        if (staged) {
+            for (int32_t p = b; p < e; ++p) s = s + st[p - base];
+        } else {
+            for (int32_t c0 = b; c0 < e; c0 += B) {
+                double v[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) v[u] = fabs(A.val[min(c0 + u, e - 1)]);
+#pragma unroll
+                for (int u = 0; u < B; ++u)
+                    if (c0 + u < e) s = s + v[u];
+            }
+        }
+        const double ri = s / d;
         r = ri > r ? ri : r;
     }
     __shared__ double sm[kBlock / dev::kWave];
     r = dev::block_max(r, sm);
-    if (threadIdx.x == 0) atomicMax(rho_bits, (unsigned long long)__double_as_longlong(r));
+    // a block whose maximum does not pass the value already there skips the
+    // atomic (the maximum only grows, so none is lost), so thousands of
+    // blocks do not queue on the one address
+    if (threadIdx.x == 0) {
+        const unsigned long long rb = (unsigned long long)__double_as_longlong(r);
+        if (rb > __hip_atomic_load(rho_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(rho_bits, rb);
+    }
 }
 
 __global__ void k_omega(const unsigned long long *rho_bits, double *omega) {
@@ -2653,11 +2690,10 @@ void build_level(amg_hierarchy *H, int l, hipStream_t s, bool *is_coarsest) {
     omega.alloc(1);
     {
         ProfScope ps(K_SETUP_MISC, (double)A.nnz * 8 + n * 8.0, s);
-        with_group(mean_row(A.nnz, n), [&](auto gc) {
-            constexpr int G = decltype(gc)::value;
-            hipLaunchKernelGGL((k_rho<G>), dim3(std::min(blocks_for((int64_t)n * G), kAtomicBlocks)), dim3(kBlock), 0,
-                               s, A, diag.p, rho_bits);
-        });
+        if (mean_row(A.nnz, n) <= 8.0)
+            hipLaunchKernelGGL((k_rho<8>), dim3(blocks_for(n)), dim3(kBlock), 0, s, A, diag.p, rho_bits);
+        else
+            hipLaunchKernelGGL((k_rho<16>), dim3(blocks_for(n)), dim3(kBlock), 0, s, A, diag.p, rho_bits);
         hipLaunchKernelGGL(k_omega, dim3(1), dim3(64), 0, s, rho_bits, omega.p);
         GW_HIP(hipGetLastError());
     }
