@@ -1270,19 +1270,46 @@ __global__ void __launch_bounds__(kBlock) k_spgemm_lane(AR ar, BR br, int32_t nr
 }
 
 // -------------------------------------------------------------- smoother --
-template <int G>
-__global__ void k_smoother_diag(CsrView A, const double *__restrict__ diag, int spai0, double omega,
-                                double *__restrict__ M) {
-    GRP_ROW(G, A.n)
-    if (!has_) return;
-    const double aii = diag[i];
-    if (spai0) {
-        const double s = grp_ordered_sum<G>(A.rowptr[i], A.rowptr[i + 1], lane_,
-                                            [&](int32_t p) { return A.val[p] * A.val[p]; });
-        if (lane_ == 0) M[i] = aii / s;
-    } else if (lane_ == 0) {
-        M[i] = omega / aii;
+// SPAI0: M_i = a_ii / sum_j a_ij^2, the squares added in column order from
+// 0, one thread a row as in k_rho (the block's squares staged in LDS when
+// they fit, else loaded B at a time); damped Jacobi: M_i = omega / a_ii.
+template <int B>
+__global__ void __launch_bounds__(kBlock) k_smoother_diag(CsrView A, const double *__restrict__ diag, int spai0,
+                                                          double omega, double *__restrict__ M) {
+    __shared__ double st[kRhoStage];
+    const int64_t r0 = dev::xcd_block() * (int64_t)kBlock;
+    const int64_t i = r0 + threadIdx.x;
+    if (!spai0) {  // the same in every thread
+        if (i < A.n) M[i] = omega / diag[i];
+        return;
     }
+    const int64_t rl = min(r0 + kBlock, (int64_t)A.n);
+    const int32_t base = A.rowptr[r0], top = A.rowptr[rl];
+    const bool staged = top - base <= kRhoStage;  // the same in every thread
+    if (staged) {
+        for (int32_t p = base + threadIdx.x; p < top; p += kBlock) st[p - base] = A.val[p] * A.val[p];
+        __syncthreads();
+    }
+    if (i >= A.n) return;
+    const int32_t b = A.rowptr[i], e = A.rowptr[i + 1];
+    const double aii = diag[i];
+    double s = 0.0;
+    if (staged) {
+        for (int32_t p = b; p < e; ++p) s = s + st[p - base];
+    } else {
+        for (int32_t c0 = b; c0 < e; c0 += B) {
+            double v[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const double a = A.val[min(c0 + u, e - 1)];
+                v[u] = a * a;
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (c0 + u < e) s = s + v[u];
+        }
+    }
+    M[i] = aii / s;
 }
 
 // Diagonal of each row (0 when absent).
@@ -2719,11 +2746,13 @@ void make_smoother(amg_hierarchy *H, int l, hipStream_t s) {
     csr_diag(A, diag.p, s);
     Lv.M.alloc(A.n);
     ProfScope ps(K_SETUP_MISC, (double)A.nnz * 12 + A.n * 16.0, s);
-    with_group(mean_row(A.nnz, A.n), [&](auto gc) {
-        constexpr int G = decltype(gc)::value;
-        hipLaunchKernelGGL((k_smoother_diag<G>), dim3(blocks_for((int64_t)A.n * G)), dim3(kBlock), 0, s, A, diag.p,
-                           H->prm.smoother == GW_SMOOTHER_SPAI0 ? 1 : 0, H->prm.omega, Lv.M.p);
-    });
+    const int spai0 = H->prm.smoother == GW_SMOOTHER_SPAI0 ? 1 : 0;
+    if (mean_row(A.nnz, A.n) <= 8.0)
+        hipLaunchKernelGGL((k_smoother_diag<8>), dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag.p, spai0,
+                           H->prm.omega, Lv.M.p);
+    else
+        hipLaunchKernelGGL((k_smoother_diag<16>), dim3(blocks_for(A.n)), dim3(kBlock), 0, s, A, diag.p, spai0,
+                           H->prm.omega, Lv.M.p);
     GW_HIP(hipGetLastError());
 }
 
